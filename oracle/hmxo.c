@@ -1,0 +1,660 @@
+/*
+ * hmxo.c -- CPU oracle (TEST INFRASTRUCTURE ONLY) for the H-matrix path of
+ * Zaspel, "Algorithmic patterns for H-matrices on many-core processors".
+ *
+ * Plain, slow, FP64 code written from the paper's definitions.  Only the
+ * tests, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it.  Nothing here is shared with the HIP library.
+ *
+ * Build:  gcc -O2 -std=c11 -fopenmp -ffp-contract=off -fPIC -shared
+ * (no FMA contraction: the ordering and the partition must come out of the
+ * exact IEEE operation sequence written below).
+ */
+#include "hmxo.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int hmxo_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Kernel functions (eq. (2) matrix entries; Section 6.2 model problem with a
+ * length scale, and two exactly-low-rank test kernels).                     */
+/* ------------------------------------------------------------------------ */
+double hmxo_kernel(int kind, double p0, const double* x, const double* y, int d)
+{
+    double r2 = 0.0, dot = 0.0;
+    for (int k = 0; k < d; ++k) {
+        double t = x[k] - y[k];
+        r2 += t * t;
+        dot += x[k] * y[k];
+    }
+    switch (kind) {
+    case HMXO_GAUSSIAN:
+        return exp(-r2 / p0);
+    case HMXO_MATERN32: {
+        double s = sqrt(3.0) * sqrt(r2) / p0;
+        return (1.0 + s) * exp(-s);
+    }
+    case HMXO_CONST:
+        return 1.0;
+    case HMXO_LOWRANK:
+        return (1.0 + dot) * (1.0 + dot);
+    default:
+        return NAN;
+    }
+}
+
+/* entry (i, j) of the Morton-ordered matrix, coordinates from the d x n SoA */
+static double entry(const double* soa, int64_t n, int d, int kind, double p0, int64_t i,
+                    int64_t j)
+{
+    double x[3], y[3];
+    for (int k = 0; k < d; ++k) {
+        x[k] = soa[(int64_t)k * n + i];
+        y[k] = soa[(int64_t)k * n + j];
+    }
+    return hmxo_kernel(kind, p0, x, y, d);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Z-order (Section 4.4, Algorithm 6)                                        */
+/* ------------------------------------------------------------------------ */
+int hmxo_global_box(const double* pts, int64_t n, int32_t d, double* lo, double* hi)
+{
+    if (n < 1 || d < 1 || d > 3) return -1;
+    for (int k = 0; k < d; ++k) {
+        lo[k] = pts[k];
+        hi[k] = pts[k];
+    }
+    for (int64_t i = 1; i < n; ++i)
+        for (int k = 0; k < d; ++k) {
+            double v = pts[i * d + k];
+            if (v < lo[k]) lo[k] = v;
+            if (v > hi[k]) hi[k] = v;
+        }
+    return 0;
+}
+
+/* bits per dimension of the fixed-point representation */
+static int morton_bits(int d)
+{
+    int b = 64 / d;
+    return b < 32 ? b : 32;
+}
+
+int hmxo_morton(const double* pts, int64_t n, int32_t d, const double* lo, const double* hi,
+                uint64_t* codes)
+{
+    if (n < 0 || d < 1 || d > 3) return -1;
+    const int B = morton_bits(d);
+    const double scale = ldexp(1.0, B);           /* 2^B, exact */
+    const uint64_t qmax = (B == 64) ? ~0ull : ((1ull << B) - 1ull);
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t q[3] = {0, 0, 0};
+        for (int k = 0; k < d; ++k) {
+            if (hi[k] == lo[k]) {
+                q[k] = 0;
+                continue;
+            }
+            /* fixed-point representation relative to the global box */
+            double t = (pts[i * d + k] - lo[k]) / (hi[k] - lo[k]);
+            double f = floor(t * scale);
+            uint64_t v = (f >= (double)qmax) ? qmax : (uint64_t)f;
+            q[k] = v;
+        }
+        /* interleave: bit b of dimension k lands at position b*d + (d-1-k) */
+        uint64_t code = 0;
+        for (int b = 0; b < B; ++b)
+            for (int k = 0; k < d; ++k)
+                if ((q[k] >> b) & 1ull) code |= 1ull << (b * d + (d - 1 - k));
+        codes[i] = code;
+    }
+    return 0;
+}
+
+typedef struct {
+    uint64_t code;
+    int32_t idx;
+} code_idx;
+
+static int cmp_code_idx(const void* a, const void* b)
+{
+    const code_idx* x = (const code_idx*)a;
+    const code_idx* y = (const code_idx*)b;
+    if (x->code < y->code) return -1;
+    if (x->code > y->code) return 1;
+    return (x->idx > y->idx) - (x->idx < y->idx); /* stable: original order on ties */
+}
+
+int hmxo_sort(const uint64_t* codes, int64_t n, int32_t* perm)
+{
+    if (n < 0) return -1;
+    code_idx* a = (code_idx*)malloc(sizeof(code_idx) * (size_t)(n > 0 ? n : 1));
+    if (!a) return -2;
+    for (int64_t i = 0; i < n; ++i) {
+        a[i].code = codes[i];
+        a[i].idx = (int32_t)i;
+    }
+    qsort(a, (size_t)n, sizeof(code_idx), cmp_code_idx);
+    for (int64_t i = 0; i < n; ++i) perm[i] = a[i].idx;
+    free(a);
+    return 0;
+}
+
+int hmxo_ordered_coords(const double* pts, int64_t n, int32_t d, const int32_t* perm, double* soa)
+{
+    for (int k = 0; k < d; ++k)
+        for (int64_t i = 0; i < n; ++i) soa[(int64_t)k * n + i] = pts[(int64_t)perm[i] * d + k];
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cluster tree (Section 2.1, (C1)-(C4); split in halves of the Morton order) */
+/* ------------------------------------------------------------------------ */
+int64_t hmxo_cluster_tree(int64_t n, int32_t leaf, int64_t cap, int32_t* lo, int32_t* hi,
+                          int32_t* depth, int64_t* child0)
+{
+    if (n < 1 || leaf < 1) return -1;
+    /* count first: breadth-first expansion of [0, n) */
+    int64_t count = 0;
+    {
+        int64_t qcap = 16, qn = 1, qh = 0;
+        int64_t* qlo = (int64_t*)malloc(sizeof(int64_t) * qcap);
+        int64_t* qhi = (int64_t*)malloc(sizeof(int64_t) * qcap);
+        qlo[0] = 0;
+        qhi[0] = n;
+        while (qh < qn) {
+            int64_t a = qlo[qh], b = qhi[qh];
+            ++qh;
+            ++count;
+            if (b - a > leaf) {
+                if (qn + 2 > qcap) {
+                    qcap *= 2;
+                    qlo = (int64_t*)realloc(qlo, sizeof(int64_t) * qcap);
+                    qhi = (int64_t*)realloc(qhi, sizeof(int64_t) * qcap);
+                }
+                int64_t mid = a + (b - a) / 2;
+                qlo[qn] = a;
+                qhi[qn] = mid;
+                ++qn;
+                qlo[qn] = mid;
+                qhi[qn] = b;
+                ++qn;
+            }
+        }
+        free(qlo);
+        free(qhi);
+    }
+    if (cap < count) return count;
+    /* fill in breadth-first order; children of node k appended at the tail */
+    int64_t tail = 1;
+    lo[0] = 0;
+    hi[0] = (int32_t)n;
+    depth[0] = 0;
+    for (int64_t k = 0; k < count; ++k) {
+        int64_t a = lo[k], b = hi[k];
+        if (b - a > leaf) {
+            int64_t mid = a + (b - a) / 2; /* the first half is the floor half */
+            child0[k] = tail;
+            lo[tail] = (int32_t)a;
+            hi[tail] = (int32_t)mid;
+            depth[tail] = depth[k] + 1;
+            lo[tail + 1] = (int32_t)mid;
+            hi[tail + 1] = (int32_t)b;
+            depth[tail + 1] = depth[k] + 1;
+            tail += 2;
+        } else {
+            child0[k] = -1;
+        }
+    }
+    return count;
+}
+
+int hmxo_boxes(const double* soa, int64_t n, int32_t d, int64_t nnodes, const int32_t* lo,
+               const int32_t* hi, double* bmin, double* bmax)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t c = 0; c < nnodes; ++c) {
+        for (int k = 0; k < d; ++k) {
+            double mn = soa[(int64_t)k * n + lo[c]], mx = mn;
+            for (int64_t i = lo[c] + 1; i < hi[c]; ++i) {
+                double v = soa[(int64_t)k * n + i];
+                if (v < mn) mn = v;
+                if (v > mx) mx = v;
+            }
+            bmin[c * d + k] = mn;
+            bmax[c * d + k] = mx;
+        }
+    }
+    return 0;
+}
+
+/* eq. (3): min(diam Q_t, diam Q_s) <= eta dist(Q_t, Q_s), squared on both
+ * sides (diam, dist >= 0), summed in dimension order. */
+int hmxo_admissible(const double* amin, const double* amax, const double* bmin,
+                    const double* bmax, int32_t d, double eta)
+{
+    double dt = 0.0, ds = 0.0, dist2 = 0.0;
+    for (int k = 0; k < d; ++k) {
+        double w = amax[k] - amin[k];
+        dt += w * w;
+    }
+    for (int k = 0; k < d; ++k) {
+        double w = bmax[k] - bmin[k];
+        ds += w * w;
+    }
+    for (int k = 0; k < d; ++k) {
+        double g1 = amin[k] - bmax[k];
+        double g2 = bmin[k] - amax[k];
+        if (g1 < 0.0) g1 = 0.0;
+        if (g2 < 0.0) g2 = 0.0;
+        double s = g1 * g1 + g2 * g2;
+        dist2 += s;
+    }
+    double dmin = dt < ds ? dt : ds;
+    return dmin <= (eta * eta) * dist2;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Block cluster tree (Algorithm 1) traversed level by level (Algorithm 4)   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t nn;
+    int32_t *lo, *hi, *depth;
+    int64_t* child0;
+    double *bmin, *bmax;
+} ctree;
+
+static int ctree_make(ctree* t, const double* soa, int64_t n, int32_t d, int32_t leaf)
+{
+    int64_t cnt = hmxo_cluster_tree(n, leaf, 0, NULL, NULL, NULL, NULL);
+    if (cnt < 1) return -1;
+    t->nn = cnt;
+    t->lo = (int32_t*)malloc(sizeof(int32_t) * cnt);
+    t->hi = (int32_t*)malloc(sizeof(int32_t) * cnt);
+    t->depth = (int32_t*)malloc(sizeof(int32_t) * cnt);
+    t->child0 = (int64_t*)malloc(sizeof(int64_t) * cnt);
+    t->bmin = (double*)malloc(sizeof(double) * cnt * d);
+    t->bmax = (double*)malloc(sizeof(double) * cnt * d);
+    if (!t->lo || !t->hi || !t->depth || !t->child0 || !t->bmin || !t->bmax) return -2;
+    hmxo_cluster_tree(n, leaf, cnt, t->lo, t->hi, t->depth, t->child0);
+    hmxo_boxes(soa, n, d, cnt, t->lo, t->hi, t->bmin, t->bmax);
+    return 0;
+}
+
+static void ctree_free(ctree* t)
+{
+    free(t->lo);
+    free(t->hi);
+    free(t->depth);
+    free(t->child0);
+    free(t->bmin);
+    free(t->bmax);
+}
+
+typedef struct {
+    int64_t n, cap;
+    int64_t* a; /* pairs of cluster-node ids */
+} pairlist;
+
+static void pl_push(pairlist* p, int64_t t, int64_t s)
+{
+    if (p->n + 1 > p->cap) {
+        p->cap = p->cap ? 2 * p->cap : 64;
+        p->a = (int64_t*)realloc(p->a, sizeof(int64_t) * 2 * p->cap);
+    }
+    p->a[2 * p->n] = t;
+    p->a[2 * p->n + 1] = s;
+    p->n++;
+}
+
+/* leaves with levels, as pairs of node ids */
+typedef struct {
+    pairlist adm, dense;
+    int64_t *adm_level, *dense_level;
+    int64_t level_sizes[64];
+    int32_t nlev;
+} partition;
+
+static void part_free(partition* P)
+{
+    free(P->adm.a);
+    free(P->dense.a);
+    free(P->adm_level);
+    free(P->dense_level);
+}
+
+static int part_make(partition* P, const ctree* T, int32_t d, int32_t leaf, double eta)
+{
+    memset(P, 0, sizeof(*P));
+    pairlist cur = {0, 0, NULL}, nxt = {0, 0, NULL};
+    int64_t acap = 0, dcap = 0;
+    pl_push(&cur, 0, 0); /* level 0 holds I x I */
+    int lev = 0;
+    while (cur.n > 0) {
+        if (lev >= 64) return -3;
+        P->level_sizes[lev] = cur.n;
+        nxt.n = 0;
+        for (int64_t q = 0; q < cur.n; ++q) {
+            int64_t t = cur.a[2 * q], s = cur.a[2 * q + 1];
+            int64_t mt = T->hi[t] - T->lo[t], ms = T->hi[s] - T->lo[s];
+            if (hmxo_admissible(T->bmin + t * d, T->bmax + t * d, T->bmin + s * d,
+                                T->bmax + s * d, d, eta)) {
+                pl_push(&P->adm, t, s);
+                if (P->adm.n > acap) {
+                    acap = P->adm.cap;
+                    P->adm_level = (int64_t*)realloc(P->adm_level, sizeof(int64_t) * acap);
+                }
+                P->adm_level[P->adm.n - 1] = lev;
+            } else if (mt > leaf && ms > leaf) {
+                /* children in the loop order of Algorithm 1: tau' outer, sigma' inner */
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b) pl_push(&nxt, T->child0[t] + a, T->child0[s] + b);
+            } else {
+                pl_push(&P->dense, t, s);
+                if (P->dense.n > dcap) {
+                    dcap = P->dense.cap;
+                    P->dense_level =
+                        (int64_t*)realloc(P->dense_level, sizeof(int64_t) * dcap);
+                }
+                P->dense_level[P->dense.n - 1] = lev;
+            }
+        }
+        pairlist tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+        ++lev;
+    }
+    P->nlev = lev;
+    free(cur.a);
+    free(nxt.a);
+    return 0;
+}
+
+int hmxo_partition(const double* soa, int64_t n, int32_t d, int32_t leaf, double eta,
+                   int64_t cap_adm, int32_t* adm, int64_t* n_adm, int64_t cap_dense,
+                   int32_t* dense, int64_t* n_dense, int64_t* level_sizes, int32_t* n_levels)
+{
+    if (n < 1 || d < 1 || d > 3 || leaf < 1 || !(eta >= 0.0)) return -1;
+    ctree T;
+    if (ctree_make(&T, soa, n, d, leaf)) return -2;
+    partition P;
+    if (part_make(&P, &T, d, leaf, eta)) {
+        ctree_free(&T);
+        return -3;
+    }
+    *n_adm = P.adm.n;
+    *n_dense = P.dense.n;
+    *n_levels = P.nlev;
+    for (int l = 0; l < P.nlev; ++l) level_sizes[l] = P.level_sizes[l];
+    int rc = 0;
+    if (P.adm.n > cap_adm || P.dense.n > cap_dense) rc = 1;
+    if (rc == 0) {
+        for (int64_t q = 0; q < P.adm.n; ++q) {
+            int64_t t = P.adm.a[2 * q], s = P.adm.a[2 * q + 1];
+            int32_t* o = adm + 5 * q;
+            o[0] = T.lo[t];
+            o[1] = T.hi[t];
+            o[2] = T.lo[s];
+            o[3] = T.hi[s];
+            o[4] = (int32_t)P.adm_level[q];
+        }
+        for (int64_t q = 0; q < P.dense.n; ++q) {
+            int64_t t = P.dense.a[2 * q], s = P.dense.a[2 * q + 1];
+            int32_t* o = dense + 5 * q;
+            o[0] = T.lo[t];
+            o[1] = T.hi[t];
+            o[2] = T.lo[s];
+            o[3] = T.hi[s];
+            o[4] = (int32_t)P.dense_level[q];
+        }
+    }
+    part_free(&P);
+    ctree_free(&T);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adaptive cross approximation (Algorithm 2), column-first with partial    */
+/* pivoting.  Column pivots: the first column, then the largest entry of the */
+/* last row residual among unused columns; a column whose residual has no   */
+/* entry above eps0 adds no rank and the lowest unused column is tried next. */
+/* ------------------------------------------------------------------------ */
+int hmxo_aca(const double* soa, int64_t n, int32_t d, int32_t kind, double p0, int64_t tlo,
+             int64_t thi, int64_t slo, int64_t shi, int32_t kmax, double eps, double aca_eta,
+             double eps0, int32_t fixed, int32_t r_start, double* U, double* V, int32_t* rank,
+             int32_t* steps)
+{
+    const int64_t m = thi - tlo, nc = shi - slo;
+    if (m < 1 || nc < 1 || kmax < 1) return -1;
+    int64_t R = kmax;
+    if (m < R) R = m;
+    if (nc < R) R = nc;
+    char* used_r = (char*)calloc((size_t)m, 1);
+    char* used_c = (char*)calloc((size_t)nc, 1);
+    double* uh = (double*)malloc(sizeof(double) * m);
+    if (!used_r || !used_c || !uh) return -2;
+    const double tol = eps * (1.0 - aca_eta) / (1.0 + eps);
+    int64_t r = 0, ncols_used = 0, j = 0;
+    int32_t nsteps = 0;
+    double S2 = 0.0;
+    int one_shot = r_start > 0;
+    int64_t target = one_shot ? (r_start < R ? r_start : R) : R;
+    for (;;) {
+        if (r >= target) {
+            /* one-shot target reached: judge the last term, continue if it fails */
+            if (!one_shot || r >= R) break;
+            one_shot = 0;
+            target = R;
+            /* the test on the last computed term was not yet applied */
+            double nu2 = 0.0, nv2 = 0.0;
+            for (int64_t i = 0; i < m; ++i) nu2 += U[(r - 1) * m + i] * U[(r - 1) * m + i];
+            for (int64_t q = 0; q < nc; ++q) nv2 += V[(r - 1) * nc + q] * V[(r - 1) * nc + q];
+            if (sqrt(nu2 * nv2) <= tol * sqrt(S2)) break;
+            continue;
+        }
+        /* residual column u^ = A[:, j] - sum_l u_l (v_l)_j */
+        for (int64_t i = 0; i < m; ++i) {
+            double a = entry(soa, n, d, kind, p0, tlo + i, slo + j);
+            for (int64_t l = 0; l < r; ++l) a -= U[l * m + i] * V[l * nc + j];
+            uh[i] = a;
+        }
+        used_c[j] = 1;
+        ++ncols_used;
+        ++nsteps;
+        /* row pivot: largest |u^_i| over unused rows, lowest index on ties */
+        int64_t ip = -1;
+        double best = -1.0;
+        for (int64_t i = 0; i < m; ++i)
+            if (!used_r[i] && fabs(uh[i]) > best) {
+                best = fabs(uh[i]);
+                ip = i;
+            }
+        if (ip < 0 || best <= eps0) {
+            if (ncols_used >= nc) break;
+            int64_t q = 0;
+            while (used_c[q]) ++q;
+            j = q;
+            continue;
+        }
+        const double piv = uh[ip];
+        for (int64_t i = 0; i < m; ++i) U[r * m + i] = uh[i] / piv;
+        /* residual row v = A[i_r, :]^T - sum_l (u_l)_{i_r} v_l */
+        for (int64_t q = 0; q < nc; ++q) {
+            double a = entry(soa, n, d, kind, p0, tlo + ip, slo + q);
+            for (int64_t l = 0; l < r; ++l) a -= U[l * m + ip] * V[l * nc + q];
+            V[r * nc + q] = a;
+        }
+        used_r[ip] = 1;
+        /* ||S_r||_F^2 = ||S_{r-1}||_F^2 + 2 sum_l (u_r.u_l)(v_r.v_l) + |u_r|^2 |v_r|^2 */
+        double nu2 = 0.0, nv2 = 0.0, cross = 0.0;
+        for (int64_t i = 0; i < m; ++i) nu2 += U[r * m + i] * U[r * m + i];
+        for (int64_t q = 0; q < nc; ++q) nv2 += V[r * nc + q] * V[r * nc + q];
+        for (int64_t l = 0; l < r; ++l) {
+            double du = 0.0, dv = 0.0;
+            for (int64_t i = 0; i < m; ++i) du += U[r * m + i] * U[l * m + i];
+            for (int64_t q = 0; q < nc; ++q) dv += V[r * nc + q] * V[l * nc + q];
+            cross += du * dv;
+        }
+        S2 += 2.0 * cross + nu2 * nv2;
+        ++r;
+        if (!fixed && !one_shot && sqrt(nu2 * nv2) <= tol * sqrt(S2)) break;
+        /* next column pivot: largest |(v_r)_j| over unused columns */
+        int64_t jp = -1;
+        double bc = -1.0;
+        for (int64_t q = 0; q < nc; ++q)
+            if (!used_c[q] && fabs(V[(r - 1) * nc + q]) > bc) {
+                bc = fabs(V[(r - 1) * nc + q]);
+                jp = q;
+            }
+        if (jp < 0) break;
+        j = jp;
+    }
+    *rank = (int32_t)r;
+    if (steps) *steps = nsteps;
+    free(used_r);
+    free(used_c);
+    free(uh);
+    return 0;
+}
+
+int hmxo_dense_block(const double* soa, int64_t n, int32_t d, int32_t kind, double p0,
+                     int64_t tlo, int64_t thi, int64_t slo, int64_t shi, double* A)
+{
+    const int64_t m = thi - tlo, nc = shi - slo;
+    for (int64_t q = 0; q < nc; ++q)
+        for (int64_t i = 0; i < m; ++i)
+            A[q * m + i] = entry(soa, n, d, kind, p0, tlo + i, slo + q);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* H-matrix-vector product (Algorithm 3, flat over the leaf lists)           */
+/* ------------------------------------------------------------------------ */
+int hmxo_hmvp(const double* pts, int64_t n, int32_t d, int32_t kind, double p0, int32_t leaf,
+              double eta, int32_t kmax, double eps, double aca_eta, double eps0, int32_t fixed,
+              double sigma2, double alpha, double beta, const double* x, double* z,
+              int64_t ranks_cap, int32_t* ranks, double* stats)
+{
+    if (n < 1 || d < 1 || d > 3 || leaf < 1 || !(eta >= 0.0) || kmax < 1) return -1;
+    double lo[3], hi[3];
+    hmxo_global_box(pts, n, d, lo, hi);
+    uint64_t* codes = (uint64_t*)malloc(sizeof(uint64_t) * n);
+    int32_t* perm = (int32_t*)malloc(sizeof(int32_t) * n);
+    double* soa = (double*)malloc(sizeof(double) * n * d);
+    double* xm = (double*)malloc(sizeof(double) * n);
+    double* zm = (double*)calloc((size_t)n, sizeof(double));
+    if (!codes || !perm || !soa || !xm || !zm) return -2;
+    hmxo_morton(pts, n, d, lo, hi, codes);
+    hmxo_sort(codes, n, perm);
+    hmxo_ordered_coords(pts, n, d, perm, soa);
+    for (int64_t k = 0; k < n; ++k) xm[k] = x[perm[k]];
+
+    ctree T;
+    if (ctree_make(&T, soa, n, d, leaf)) return -2;
+    partition P;
+    if (part_make(&P, &T, d, leaf, eta)) return -3;
+
+    double sum_rank = 0.0, dense_entries = 0.0, factor_entries = 0.0;
+    int nthr = hmxo_num_threads();
+    double* zpriv = (double*)calloc((size_t)nthr * (size_t)n, sizeof(double));
+    if (!zpriv) return -2;
+
+#pragma omp parallel reduction(+ : sum_rank, dense_entries, factor_entries)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double* zt = zpriv + (int64_t)tid * n;
+        /* admissible leaves: z|tau += U (V^T x|sigma) */
+#pragma omp for schedule(dynamic, 1) nowait
+        for (int64_t q = 0; q < P.adm.n; ++q) {
+            int64_t t = P.adm.a[2 * q], s = P.adm.a[2 * q + 1];
+            int64_t tlo = T.lo[t], thi = T.hi[t], slo = T.lo[s], shi = T.hi[s];
+            int64_t m = thi - tlo, nc = shi - slo;
+            int64_t R = kmax;
+            double* U = (double*)malloc(sizeof(double) * m * R);
+            double* V = (double*)malloc(sizeof(double) * nc * R);
+            int32_t rk = 0;
+            hmxo_aca(soa, n, d, kind, p0, tlo, thi, slo, shi, kmax, eps, aca_eta, eps0, fixed, 0,
+                     U, V, &rk, NULL);
+            if (ranks && q < ranks_cap) ranks[q] = rk;
+            for (int64_t l = 0; l < rk; ++l) {
+                double tl = 0.0;
+                for (int64_t jj = 0; jj < nc; ++jj) tl += V[l * nc + jj] * xm[slo + jj];
+                for (int64_t i = 0; i < m; ++i) zt[tlo + i] += U[l * m + i] * tl;
+            }
+            sum_rank += rk;
+            factor_entries += (double)rk * (double)(m + nc);
+            free(U);
+            free(V);
+        }
+        /* dense leaves: z|tau += A|tau x sigma x|sigma */
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t q = 0; q < P.dense.n; ++q) {
+            int64_t t = P.dense.a[2 * q], s = P.dense.a[2 * q + 1];
+            int64_t tlo = T.lo[t], thi = T.hi[t], slo = T.lo[s], shi = T.hi[s];
+            for (int64_t i = tlo; i < thi; ++i) {
+                double acc = 0.0;
+                for (int64_t jj = slo; jj < shi; ++jj)
+                    acc += entry(soa, n, d, kind, p0, i, jj) * xm[jj];
+                zt[i] += acc;
+            }
+            dense_entries += (double)(thi - tlo) * (double)(shi - slo);
+        }
+    }
+    for (int th = 0; th < nthr; ++th)
+        for (int64_t k = 0; k < n; ++k) zm[k] += zpriv[(int64_t)th * n + k];
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t p = perm[k];
+        double hz = zm[k] + sigma2 * xm[k];
+        z[p] = alpha * hz + (beta != 0.0 ? beta * z[p] : 0.0);
+    }
+    if (stats) {
+        stats[0] = (double)P.adm.n;
+        stats[1] = (double)P.dense.n;
+        stats[2] = sum_rank;
+        stats[3] = dense_entries;
+        stats[4] = factor_entries;
+        stats[5] = (double)P.nlev;
+        stats[6] = 0.0;
+        stats[7] = 0.0;
+    }
+    free(zpriv);
+    part_free(&P);
+    ctree_free(&T);
+    free(codes);
+    free(perm);
+    free(soa);
+    free(xm);
+    free(zm);
+    return 0;
+}
+
+int hmxo_dense_matvec(const double* pts, int64_t n, int32_t d, int32_t kind, double p0,
+                      double sigma2, const double* x, const int64_t* rows, int64_t nrows,
+                      double* z)
+{
+    int64_t cnt = rows ? nrows : n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < cnt; ++q) {
+        int64_t i = rows ? rows[q] : q;
+        double acc = 0.0;
+        for (int64_t j = 0; j < n; ++j) acc += hmxo_kernel(kind, p0, pts + i * d, pts + j * d, d) * x[j];
+        z[q] = acc + sigma2 * x[i];
+    }
+    return 0;
+}

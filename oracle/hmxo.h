@@ -1,0 +1,97 @@
+/*
+ * hmxo.h -- CPU oracle for the H-matrix construction and H-matrix-vector
+ * product of Zaspel, "Algorithmic patterns for H-matrices on many-core
+ * processors" (arXiv:1708.09707).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, plain, FP64 reference
+ * that the HIP path is checked against.  Only the tests, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it.  It shares no code, no
+ * header and no constant with the HIP library.
+ *
+ * All pointers are host pointers.  Points are row-major (n x d) doubles;
+ * "soa" arrays are the Morton-ordered coordinates stored dimension-major
+ * (d x n).  Functions return 0 on success and a negative value on bad
+ * arguments.
+ */
+#ifndef HMXO_H
+#define HMXO_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* kernel kinds; p0 is the kernel parameter */
+#define HMXO_GAUSSIAN 0   /* exp(-r^2 / p0)                                */
+#define HMXO_MATERN32 1   /* (1 + sqrt(3) r / p0) exp(-sqrt(3) r / p0)      */
+#define HMXO_CONST    3   /* 1 (rank-one matrix)                            */
+#define HMXO_LOWRANK  4   /* (1 + x.y)^2 (rank <= 1 + d + d(d+1)/2)         */
+
+double hmxo_kernel(int kind, double p0, const double* x, const double* y, int d);
+
+/* Section 4.4 (Z-order curve) and Algorithm 6 */
+int hmxo_global_box(const double* pts, int64_t n, int32_t d, double* lo, double* hi);
+int hmxo_morton(const double* pts, int64_t n, int32_t d, const double* lo, const double* hi,
+                uint64_t* codes);
+int hmxo_sort(const uint64_t* codes, int64_t n, int32_t* perm);
+int hmxo_ordered_coords(const double* pts, int64_t n, int32_t d, const int32_t* perm, double* soa);
+
+/* Section 2.1 (cluster tree, cardinality-based clustering on the Z-order).
+ * Nodes in breadth-first order; child0[k] = -1 for a leaf, else the two
+ * children are child0[k] and child0[k]+1.  Returns the node count, or the
+ * required count if cap is too small (arrays untouched). */
+int64_t hmxo_cluster_tree(int64_t n, int32_t leaf, int64_t cap, int32_t* lo, int32_t* hi,
+                          int32_t* depth, int64_t* child0);
+/* Section 2.2: a = min, b = max over the node's points; boxes are d-major per node */
+int hmxo_boxes(const double* soa, int64_t n, int32_t d, int64_t nnodes, const int32_t* lo,
+               const int32_t* hi, double* bmin, double* bmax);
+/* eq. (3) in the squared form (no square roots) */
+int hmxo_admissible(const double* amin, const double* amax, const double* bmin,
+                    const double* bmax, int32_t d, double eta);
+
+/* Algorithm 1, done level by level as in Algorithm 4.  Leaves are written as
+ * (tlo, thi, slo, shi, level) records (5 int32 each) in canonical order
+ * (level, position in level).  level_sizes[l] = |V(l)|.  Returns 0, or 1 if a
+ * capacity was too small (counts are still reported). */
+int hmxo_partition(const double* soa, int64_t n, int32_t d, int32_t leaf, double eta,
+                   int64_t cap_adm, int32_t* adm, int64_t* n_adm,
+                   int64_t cap_dense, int32_t* dense, int64_t* n_dense,
+                   int64_t* level_sizes, int32_t* n_levels);
+
+/* Algorithm 2 on the block tau x sigma = [tlo,thi) x [slo,shi) of the
+ * Morton-ordered matrix.  U is m x kmax and V is n x kmax, column-major.
+ * fixed != 0 skips the stopping test (fixed rank).  r_start > 0 selects the
+ * one-shot form: exactly min(r_start, R) steps, then the stopping test on the
+ * last term; if it fails, continue adaptively.  *steps gets the number of
+ * columns evaluated (including skipped ones). */
+int hmxo_aca(const double* soa, int64_t n, int32_t d, int32_t kind, double p0,
+             int64_t tlo, int64_t thi, int64_t slo, int64_t shi, int32_t kmax,
+             double eps, double aca_eta, double eps0, int32_t fixed, int32_t r_start,
+             double* U, double* V, int32_t* rank, int32_t* steps);
+
+/* Algorithm 3 in flat form (no-storage mode: every block is built, applied and
+ * discarded):  z = alpha * (H x + sigma2 x) + beta * z, vectors in the
+ * original point order.  ranks (optional, cap n_adm) gets the ACA ranks in
+ * canonical admissible order.  stats (optional, 8 doubles):
+ * [n_adm, n_dense, sum rank, dense entries, factor entries, levels, 0, 0]. */
+int hmxo_hmvp(const double* pts, int64_t n, int32_t d, int32_t kind, double p0,
+              int32_t leaf, double eta, int32_t kmax, double eps, double aca_eta,
+              double eps0, int32_t fixed, double sigma2, double alpha, double beta,
+              const double* x, double* z, int64_t ranks_cap, int32_t* ranks, double* stats);
+
+/* brute-force dense product z_i = sum_j phi(y_i, y_j) x_j (+ sigma2 x_i) for
+ * the listed rows (rows == NULL: all rows; then z has n entries, else nrows). */
+int hmxo_dense_matvec(const double* pts, int64_t n, int32_t d, int32_t kind, double p0,
+                      double sigma2, const double* x, const int64_t* rows, int64_t nrows,
+                      double* z);
+
+/* dense block A|tau x sigma of the Morton-ordered matrix, column-major m x n */
+int hmxo_dense_block(const double* soa, int64_t n, int32_t d, int32_t kind, double p0,
+                     int64_t tlo, int64_t thi, int64_t slo, int64_t shi, double* A);
+
+int hmxo_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
