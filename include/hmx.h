@@ -1,0 +1,180 @@
+/*
+ * hmx.h -- C ABI of the MI355X (gfx950) H-matrix library.
+ *
+ * The library builds an H-matrix approximation of the kernel matrix
+ *     A_ij = phi(y_i, y_j),  i, j = 1..N                     (paper eq. (2))
+ * for points y_i in R^d (d = 1, 2, 3) and applies it to vectors:
+ *     z := alpha (A + sigma2 I) x + beta z                    (Section 2.5,
+ *                                                              Algorithm 3;
+ *                                                              shift from the
+ *                                                              GPR / kernel
+ *                                                              ridge setting
+ *                                                              of Section 1)
+ * following Zaspel, "Algorithmic patterns for H-matrices on many-core
+ * processors" (arXiv:1708.09707):
+ *   - Z-order (Morton) ordering of the points                 Section 4.4, Alg. 6
+ *   - cardinality-based cluster tree on that order            Section 2.1
+ *   - block cluster tree traversal, level by level, with the
+ *     bounding-box admissibility condition                    Alg. 1, Alg. 4, eq. (3)
+ *   - batched adaptive cross approximation (ACA) of the
+ *     admissible blocks                                       Alg. 2, Section 5.4.1
+ *   - batched H-matrix-vector product (dense near field plus
+ *     U (V^T x) far field)                                    Alg. 3, Section 5.4
+ *
+ * Conventions (every function):
+ *   - Pointers documented as "device" must be HIP device allocations on the
+ *     current device; "host" pointers are ordinary host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All device work is enqueued on it.
+ *   - Functions return an hmx_status and never abort; on error the message of
+ *     hmx_last_error() (thread-local) says what failed.  A failed build
+ *     produces no handle and leaks no device memory.
+ *   - One handle must not be used from two threads at once; distinct handles
+ *     may be.
+ *   - Limits: 1 <= N < 2^31, d in {1,2,3}, 1 <= max_rank <= 128.
+ */
+#ifndef HMX_H
+#define HMX_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hmx_hmatrix_s* hmx_hmatrix; /* opaque; owns all device memory it allocates */
+
+typedef enum {
+    HMX_OK = 0,
+    HMX_ERR_INVALID_ARG = 1,
+    HMX_ERR_OOM = 2,
+    HMX_ERR_DEVICE = 3,
+    HMX_ERR_NOT_CONVERGED = 4,
+    HMX_ERR_UNSUPPORTED = 5
+} hmx_status;
+
+typedef enum { HMX_F64 = 0, HMX_F32 = 1, HMX_BF16 = 2 } hmx_dtype;
+
+/* Kernel functions phi(x, y) with r = |x - y| (Euclidean).
+ *  HMX_GAUSSIAN  : exp(-r^2 / p0)                    (Section 6.2 with a length
+ *                                                     scale, p0 = l^2 > 0)
+ *  HMX_MATERN32  : (1 + sqrt(3) r / p0) exp(-sqrt(3) r / p0), p0 = l > 0
+ *  HMX_TEST_CONST: 1 (rank-one matrix; test kernel)
+ *  HMX_TEST_LOWRANK: (1 + x.y)^2 (rank <= 1 + d + d(d+1)/2; test kernel) */
+typedef enum {
+    HMX_GAUSSIAN = 0,
+    HMX_MATERN32 = 1,
+    HMX_TEST_CONST = 3,
+    HMX_TEST_LOWRANK = 4
+} hmx_kernel_kind;
+
+typedef struct {
+    hmx_kernel_kind kind;
+    double p0;
+    double p1; /* reserved, 0 */
+} hmx_kernel;
+
+/* ACA rank control.
+ *  HMX_RANK_ADAPTIVE: Algorithm 2 with its stopping criterion, at most max_rank.
+ *  HMX_RANK_FIXED   : exactly min(max_rank, m, n) rank-one steps, no stopping
+ *                     test (the fixed-k mode of the paper's experiments). */
+typedef enum { HMX_RANK_ADAPTIVE = 0, HMX_RANK_FIXED = 2 } hmx_rank_mode;
+
+typedef struct {
+    int32_t leaf_size;       /* C_leaf >= 1: clusters with more points split (Section 2.1) */
+    double eta;              /* admissibility parameter eta >= 0 (eq. (3)) */
+    double aca_eps;          /* ACA relative accuracy epsilon >= 0 (Algorithm 2) */
+    double aca_eta;          /* the (1 - eta) factor of Algorithm 2's stopping test,
+                                in [0, 1); default 0 (see the stopping test) */
+    double aca_eps0;         /* a residual column whose largest entry is <= eps0
+                                adds no rank (Section 2.4); < 0 selects the
+                                default 1e-14 (F64) or 1e-7 (F32) */
+    int32_t max_rank;        /* k_max, 1..128 */
+    double sigma2;           /* diagonal shift sigma^2 >= 0 of (A + sigma^2 I) */
+    hmx_dtype compute_dtype; /* HMX_F64 or HMX_F32: kernel evaluation, factor and
+                                near-field storage, matvec accumulation */
+    hmx_rank_mode rank_mode;
+    int32_t reserved[8];
+} hmx_params;
+
+/* Statistics of a built H-matrix (host struct). */
+typedef struct {
+    int64_t n;
+    int32_t d;
+    int32_t levels;           /* block-tree levels |V(l)| > 0 */
+    int64_t n_adm, n_dense;   /* admissible / dense leaves */
+    int64_t n_tiles;          /* leaf clusters (row tiles of the matvec) */
+    int64_t sum_rank;         /* sum of ACA ranks */
+    int32_t max_rank_used;
+    int32_t reserved0;
+    int64_t factor_entries;   /* sum_adm rank * (|tau| + |sigma|) */
+    int64_t near_entries;     /* sum_dense |tau| * |sigma| */
+    int64_t aca_columns;      /* ACA residual columns evaluated (incl. skipped) */
+    double matvec_bytes;      /* algorithmic HBM bytes of one matvec (beta = 0) */
+    double phase_ms[8];       /* build phases: order, tree, traversal, aca,
+                                 compaction, near field, matvec plan, total */
+    int64_t device_bytes;     /* device memory held by the handle */
+    int64_t level_sizes[64];  /* |V(l)| per level */
+} hmx_stats;
+
+/* Fill *p with the defaults: leaf 256, eta 1.5, eps 1e-5, aca_eta 0,
+ * eps0 default, max_rank 64, sigma2 0, F32, adaptive. */
+hmx_status hmx_params_default(hmx_params* p);
+
+/* Build the H-matrix of phi over the points.
+ *   points : device, n x d row-major, pts_dtype F64 or F32 (F32 values are
+ *            promoted exactly to F64 for ordering and boxes).  Read only; the
+ *            handle keeps its own Morton-ordered copy, so points may be freed
+ *            after the call.
+ *   kernel, params : host structs (see above).
+ *   out    : host; receives the handle on HMX_OK, NULL otherwise.
+ * Host-blocking: synchronises `stream` once per block-tree level and at pool
+ * sizing; every step runs in device kernels. */
+hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t d,
+                     const hmx_kernel* kernel, const hmx_params* params, void* stream,
+                     hmx_hmatrix* out);
+
+/* z := alpha (H + sigma2 I) x + beta z in the ORIGINAL point order
+ * (Algorithm 3; x is permuted to Morton order and z back, Section 5.1).
+ *   x, z : device vectors of n entries in vec_dtype, which must equal the
+ *          handle's compute dtype.  x and z must not overlap.
+ * Fully asynchronous on `stream`; allocates nothing. */
+hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype, double alpha,
+                      double beta, void* stream);
+
+/* Copy the ordering and the partition to host memory (any pointer may be
+ * NULL to skip it):
+ *   codes : n Morton codes in the ORIGINAL point order
+ *   perm  : n int32; perm[k] = original index of the k-th point in Morton order
+ *   adm, dense : 5 int32 per leaf (tlo, thi, slo, shi, level) in canonical
+ *           order (level, position in level); index ranges are half-open in
+ *           the Morton order.  *n_adm / *n_dense receive the counts and give
+ *           the capacities on input (in leaves); too small -> INVALID_ARG.
+ * Synchronises `stream`. */
+hmx_status hmx_get_partition(hmx_hmatrix h, uint64_t* codes, int32_t* perm, int32_t* adm,
+                             int64_t* n_adm, int32_t* dense, int64_t* n_dense, void* stream);
+
+/* Cluster-tree leaf boxes / any node box: copies the global box (2*d doubles:
+ * lo then hi) and, if nodes != NULL, the boxes of the leaf clusters in Morton
+ * order (n_tiles x (lo[d], hi[d], first, last+1) as doubles).  Synchronises. */
+hmx_status hmx_get_boxes(hmx_hmatrix h, double* global_box, double* leaf_boxes, void* stream);
+
+/* ACA ranks of the admissible leaves in canonical order (n_adm int32), and
+ * optionally the factors of one admissible leaf converted to double:
+ * U (m x rank, column-major), V (n x rank).  Synchronises. */
+hmx_status hmx_get_ranks(hmx_hmatrix h, int32_t* ranks, void* stream);
+hmx_status hmx_get_factors(hmx_hmatrix h, int64_t leaf, double* U, double* V, int32_t* rank,
+                           void* stream);
+
+hmx_status hmx_get_stats(hmx_hmatrix h, hmx_stats* s);
+
+/* Free every device buffer of the handle (synchronises the device). */
+hmx_status hmx_destroy(hmx_hmatrix h);
+
+const char* hmx_status_string(hmx_status s);
+const char* hmx_last_error(void); /* thread-local message of the last failure */
+
+#ifdef __cplusplus
+}
+#endif
+#endif

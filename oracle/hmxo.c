@@ -428,10 +428,45 @@ int hmxo_partition(const double* soa, int64_t n, int32_t d, int32_t leaf, double
 
 /* ------------------------------------------------------------------------ */
 /* Adaptive cross approximation (Algorithm 2), column-first with partial    */
-/* pivoting.  Column pivots: the first column, then the largest entry of the */
-/* last row residual among unused columns; a column whose residual has no   */
-/* entry above eps0 adds no rank and the lowest unused column is tried next. */
+/* pivoting.  Column pivots (left to the implementation by the paper): the  */
+/* first column is the sigma point nearest to the centre of tau's bounding  */
+/* box; later ones the largest entry of the last row residual among unused  */
+/* columns.  A column whose residual has no entry above eps0 adds no rank;  */
+/* the lowest unused column is tried next, and after kmax such failed       */
+/* columns the block stops.                                                 */
 /* ------------------------------------------------------------------------ */
+
+/* the sigma column whose point is nearest (squared distance, dimension
+ * order, FP64) to the centre 0.5 (a + b) of tau's bounding box; lowest
+ * index on ties */
+static int64_t first_column(const double* soa, int64_t n, int d, int64_t tlo, int64_t thi,
+                            int64_t slo, int64_t shi)
+{
+    double c[3];
+    for (int k = 0; k < d; ++k) {
+        double a = soa[(int64_t)k * n + tlo], b = a;
+        for (int64_t i = tlo + 1; i < thi; ++i) {
+            double v = soa[(int64_t)k * n + i];
+            if (v < a) a = v;
+            if (v > b) b = v;
+        }
+        c[k] = 0.5 * (a + b);
+    }
+    int64_t best = 0;
+    double bd = INFINITY;
+    for (int64_t q = slo; q < shi; ++q) {
+        double s = 0.0;
+        for (int k = 0; k < d; ++k) {
+            double t = soa[(int64_t)k * n + q] - c[k];
+            s += t * t;
+        }
+        if (s < bd) {
+            bd = s;
+            best = q - slo;
+        }
+    }
+    return best;
+}
 int hmxo_aca(const double* soa, int64_t n, int32_t d, int32_t kind, double p0, int64_t tlo,
              int64_t thi, int64_t slo, int64_t shi, int32_t kmax, double eps, double aca_eta,
              double eps0, int32_t fixed, int32_t r_start, double* U, double* V, int32_t* rank,
@@ -447,7 +482,8 @@ int hmxo_aca(const double* soa, int64_t n, int32_t d, int32_t kind, double p0, i
     double* uh = (double*)malloc(sizeof(double) * m);
     if (!used_r || !used_c || !uh) return -2;
     const double tol = eps * (1.0 - aca_eta) / (1.0 + eps);
-    int64_t r = 0, ncols_used = 0, j = 0;
+    int64_t r = 0, ncols_used = 0, nfailed = 0;
+    int64_t j = first_column(soa, n, d, tlo, thi, slo, shi);
     int32_t nsteps = 0;
     double S2 = 0.0;
     int one_shot = r_start > 0;
@@ -483,7 +519,8 @@ int hmxo_aca(const double* soa, int64_t n, int32_t d, int32_t kind, double p0, i
                 ip = i;
             }
         if (ip < 0 || best <= eps0) {
-            if (ncols_used >= nc) break;
+            ++nfailed;
+            if (ncols_used >= nc || nfailed >= kmax) break;
             int64_t q = 0;
             while (used_c[q]) ++q;
             j = q;

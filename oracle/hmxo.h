@@ -59,8 +59,10 @@ int hmxo_partition(const double* soa, int64_t n, int32_t d, int32_t leaf, double
                    int64_t* level_sizes, int32_t* n_levels);
 
 /* Algorithm 2 on the block tau x sigma = [tlo,thi) x [slo,shi) of the
- * Morton-ordered matrix.  U is m x kmax and V is n x kmax, column-major.
- * fixed != 0 skips the stopping test (fixed rank).  r_start > 0 selects the
+ * Morton-ordered matrix.  First column: the sigma point nearest to the centre
+ * of tau's bounding box; a column without a residual entry above eps0 adds no
+ * rank, the lowest unused column follows, and kmax such columns end the block.
+ * U is m x kmax and V is n x kmax, column-major.  fixed != 0 skips the stopping test (fixed rank).  r_start > 0 selects the
  * one-shot form: exactly min(r_start, R) steps, then the stopping test on the
  * last term; if it fails, continue adaptively.  *steps gets the number of
  * columns evaluated (including skipped ones). */

@@ -1,0 +1,796 @@
+// C ABI and host orchestration of the H-matrix build and matvec.
+// Every step of the path runs in the device kernels of k_*.hip; this file
+// sizes buffers, launches, and reads back the few counters that size the
+// next step (one per block-tree level, as in Algorithm 4, and one per pool).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hmx_internal.h"
+
+using namespace hmx;
+
+namespace {
+
+thread_local std::string g_err;
+
+void set_err(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+// owning device buffer
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T* as() const {
+        return (T*)p;
+    }
+};
+
+struct Fail {
+    hmx_status s;
+};
+
+void check(hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+        set_err("%s: %s", what, hipGetErrorString(e));
+        throw Fail{e == hipErrorOutOfMemory ? HMX_ERR_OOM : HMX_ERR_DEVICE};
+    }
+}
+
+void alloc(DevBuf& b, size_t bytes, const char* what) {
+    b.release();
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        set_err("device allocation of %zu bytes for %s failed: %s", bytes, what,
+                hipGetErrorString(e));
+        throw Fail{HMX_ERR_OOM};
+    }
+    b.bytes = bytes;
+}
+
+template <typename T>
+T read_scalar(const T* dev, hipStream_t st) {
+    T v;
+    check(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, st), "readback");
+    check(hipStreamSynchronize(st), "stream synchronize");
+    return v;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct hmx_hmatrix_s {
+    int64_t n = 0;
+    int d = 0;
+    hmx_kernel kern{};
+    hmx_params prm{};
+    int f64 = 0;
+    size_t esz = 4;  // bytes per stored entry
+    double box[6] = {0, 0, 0, 0, 0, 0};
+    int L = 0;
+    int64_t nslots = 0;
+    int64_t n_adm = 0, n_dense = 0, ntiles = 0, npieces = 0, sum_rank = 0;
+    int max_tile = 0;
+    int64_t factor_entries = 0, near_entries = 0;
+    DevBuf codes, perm, soa64, soa32, node_lo, node_hi, bmin, bmax;
+    DevBuf adm, adm_level, dense, dense_level;
+    DevBuf tile_of_point, tile_lo;
+    DevBuf rank, steps, uoff, voff, toff, U, V, near_off, near;
+    DevBuf pieces, tile_ptr, vecpool;
+    hmx_stats stats{};
+
+    int64_t device_bytes() const {
+        const DevBuf* all[] = {&codes,   &perm,      &soa64,         &soa32,   &node_lo, &node_hi,
+                               &bmin,    &bmax,      &adm,           &adm_level, &dense,
+                               &dense_level, &tile_of_point, &tile_lo, &rank,   &steps,
+                               &uoff,    &voff,      &toff,          &U,       &V,
+                               &near_off, &near,     &pieces,        &tile_ptr, &vecpool};
+        int64_t s = 0;
+        for (auto* b : all) s += (int64_t)b->bytes;
+        return s;
+    }
+};
+
+namespace {
+
+// grow a device buffer to at least `bytes`, keeping the first `keep` bytes
+void grow(DevBuf& b, size_t bytes, size_t keep, hipStream_t st, const char* what) {
+    if (b.p && b.bytes >= bytes) return;
+    size_t nb = std::max(bytes, b.bytes * 2);
+    DevBuf nbuf;
+    alloc(nbuf, nb, what);
+    if (keep) check(hipMemcpyAsync(nbuf.p, b.p, keep, hipMemcpyDeviceToDevice, st), "grow copy");
+    check(hipStreamSynchronize(st), "grow sync");
+    std::swap(b.p, nbuf.p);
+    std::swap(b.bytes, nbuf.bytes);
+}
+
+int max_depth(int64_t n, int leaf) {
+    int L = 0;
+    int64_t s = n;  // largest cluster at depth L is ceil(n / 2^L)
+    while (s > leaf) {
+        s = (s + 1) / 2;
+        ++L;
+    }
+    return L;
+}
+
+void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) {
+    using clk = std::chrono::steady_clock;
+    const auto t_all = clk::now();
+    const int64_t n = h->n;
+    const int d = h->d;
+    const int leaf = h->prm.leaf_size;
+    const double eta = h->prm.eta;
+    const int f64 = h->f64;
+    const size_t esz = h->esz;
+    hmx_stats& S = h->stats;
+    auto t0 = clk::now();
+
+    // ---- 1. global box, Morton codes, stable sort, ordered coordinates ----
+    {
+        const int nparts = global_box_parts(n);
+        DevBuf partial, boxd;
+        alloc(partial, (size_t)nparts * 6 * sizeof(double), "box partials");
+        alloc(boxd, 6 * sizeof(double), "box");
+        check(launch_global_box(pts, pts_f64, n, d, partial.as<double>(), nparts,
+                                boxd.as<double>(), st),
+              "global box");
+        double hb[6];
+        check(hipMemcpyAsync(hb, boxd.p, 2 * d * sizeof(double), hipMemcpyDeviceToHost, st),
+              "box readback");
+        check(hipStreamSynchronize(st), "box sync");
+        for (int k = 0; k < 2 * d; ++k)
+            if (!std::isfinite(hb[k])) {
+                set_err("points contain NaN or infinite coordinates");
+                throw Fail{HMX_ERR_INVALID_ARG};
+            }
+        for (int k = 0; k < 2 * d; ++k) h->box[k] = hb[k];
+
+        alloc(h->codes, n * 8, "morton codes");
+        alloc(h->perm, n * 4, "permutation");
+        check(launch_morton(pts, pts_f64, n, d, boxd.as<double>(), h->codes.as<uint64_t>(),
+                            h->perm.as<uint32_t>(), st),
+              "morton");
+        DevBuf scratch;
+        alloc(scratch, radix_sort_scratch_bytes(n), "sort scratch");
+        const int bits = d == 3 ? 63 : 64;
+        check(radix_sort_pairs(h->codes.as<uint64_t>(), h->perm.as<uint32_t>(), n, bits,
+                               scratch.p, st),
+              "radix sort");
+        alloc(h->soa64, (size_t)n * d * 8, "coords f64");
+        if (!f64) alloc(h->soa32, (size_t)n * d * 4, "coords f32");
+        check(launch_gather_coords(pts, pts_f64, n, d, h->perm.as<uint32_t>(),
+                                   h->soa64.as<double>(), f64 ? nullptr : h->soa32.as<float>(), st),
+              "gather coords");
+        check(hipStreamSynchronize(st), "order sync");
+    }
+    S.phase_ms[0] = ms_since(t0);
+    t0 = clk::now();
+
+    // ---- 2. cluster tree, boxes, leaf tiles ----
+    h->L = max_depth(n, leaf);
+    if (h->L > 29) {
+        set_err("cluster tree too deep (%d levels); raise leaf_size", h->L);
+        throw Fail{HMX_ERR_UNSUPPORTED};
+    }
+    h->nslots = (2ll << h->L) - 1;
+    alloc(h->node_lo, h->nslots * 4, "node lo");
+    alloc(h->node_hi, h->nslots * 4, "node hi");
+    for (int l = 0; l <= h->L; ++l)
+        check(launch_tree_level(l, n, leaf, h->node_lo.as<int32_t>(), h->node_hi.as<int32_t>(), st),
+              "tree level");
+    alloc(h->bmin, (size_t)h->nslots * d * 8, "box min");
+    alloc(h->bmax, (size_t)h->nslots * d * 8, "box max");
+    for (int l = h->L; l >= 0; --l)
+        check(launch_box_level(l, d, leaf, h->node_lo.as<int32_t>(), h->node_hi.as<int32_t>(),
+                               h->soa64.as<double>(), n, h->bmin.as<double>(),
+                               h->bmax.as<double>(), st),
+              "box level");
+    {
+        alloc(h->tile_of_point, n * 4, "tile of point");
+        check(hipMemsetAsync(h->tile_of_point.p, 0, n * 4, st), "memset");
+        check(launch_mark_leaves(h->L, leaf, h->node_lo.as<int32_t>(), h->node_hi.as<int32_t>(),
+                                 h->nslots, h->tile_of_point.as<int32_t>(), st),
+              "mark leaves");
+        DevBuf scratch, cnt;
+        alloc(scratch, tile_scan_scratch_bytes(n), "tile scan");
+        alloc(cnt, 8, "tile count");
+        // upper bound on tiles for tile_lo: number of slots
+        alloc(h->tile_lo, (size_t)(std::min<int64_t>(h->nslots, n) + 1) * 4, "tile lo");
+        check(launch_iota_scan_tiles(h->tile_of_point.as<int32_t>(), n, h->tile_lo.as<int32_t>(),
+                                     cnt.as<int64_t>(), scratch.p, st),
+              "tile scan");
+        h->ntiles = read_scalar(cnt.as<int64_t>(), st);
+    }
+    {
+        // largest leaf cluster = largest tile
+        int64_t s = n;
+        while (s > leaf) s = (s + 1) / 2;
+        h->max_tile = (int)s;
+    }
+    S.phase_ms[1] = ms_since(t0);
+    t0 = clk::now();
+
+    // ---- 3. block cluster tree traversal (Algorithm 4 applied to Algorithm 1) ----
+    int64_t big_adm = n;
+    {
+        DevBuf cur, nxt, scratch, totals;
+        alloc(cur, 8, "level 0");
+        const int2 root = make_int2(0, 0);
+        check(hipMemcpyAsync(cur.p, &root, sizeof root, hipMemcpyHostToDevice, st), "root");
+        alloc(totals, 8 * sizeof(int64_t), "totals");
+        int64_t ncur = 1;
+        int level = 0;
+        int64_t cap_adm = 0, cap_dense = 0;
+        int min_adm_level = -1;
+        while (ncur > 0) {
+            if (level >= 64) {
+                set_err("block tree deeper than 64 levels");
+                throw Fail{HMX_ERR_UNSUPPORTED};
+            }
+            S.level_sizes[level] = ncur;
+            const int64_t nblk = traverse_blocks(ncur);
+            if (!scratch.p || scratch.bytes < traverse_scratch_bytes(ncur))
+                alloc(scratch, traverse_scratch_bytes(ncur), "traverse scratch");
+            int64_t* bc = scratch.as<int64_t>();
+            check(launch_traverse_count(cur.as<int2>(), ncur, h->node_lo.as<int32_t>(),
+                                        h->node_hi.as<int32_t>(), h->bmin.as<double>(),
+                                        h->bmax.as<double>(), d, leaf, eta, bc, st),
+                  "traverse count");
+            check(launch_traverse_scan(bc, nblk, totals.as<int64_t>(), st), "traverse scan");
+            int64_t tot[3];
+            check(hipMemcpyAsync(tot, totals.p, 3 * 8, hipMemcpyDeviceToHost, st), "totals");
+            check(hipStreamSynchronize(st), "level sync");
+            if (tot[0] > 0 && min_adm_level < 0) min_adm_level = level;
+            if (h->n_adm + tot[0] > cap_adm) {
+                int64_t nc = std::max<int64_t>(2 * cap_adm, h->n_adm + tot[0]);
+                grow(h->adm, nc * sizeof(int4), h->n_adm * sizeof(int4), st, "adm leaves");
+                grow(h->adm_level, nc * 4, h->n_adm * 4, st, "adm levels");
+                cap_adm = nc;
+            }
+            if (h->n_dense + tot[2] > cap_dense) {
+                int64_t nc = std::max<int64_t>(2 * cap_dense, h->n_dense + tot[2]);
+                grow(h->dense, nc * sizeof(int4), h->n_dense * sizeof(int4), st, "dense leaves");
+                grow(h->dense_level, nc * 4, h->n_dense * 4, st, "dense levels");
+                cap_dense = nc;
+            }
+            const int64_t nnext = 4 * tot[1];
+            alloc(nxt, nnext * sizeof(int2), "next level");
+            check(launch_traverse_write(cur.as<int2>(), ncur, h->node_lo.as<int32_t>(),
+                                        h->node_hi.as<int32_t>(), h->bmin.as<double>(),
+                                        h->bmax.as<double>(), d, leaf, eta, bc, level,
+                                        nxt.as<int2>(), h->adm.as<int4>(),
+                                        h->adm_level.as<int32_t>(), h->n_adm, h->dense.as<int4>(),
+                                        h->dense_level.as<int32_t>(), h->n_dense, st),
+                  "traverse write");
+            h->n_adm += tot[0];
+            h->n_dense += tot[2];
+            std::swap(cur.p, nxt.p);
+            std::swap(cur.bytes, nxt.bytes);
+            ncur = nnext;
+            ++level;
+        }
+        check(hipStreamSynchronize(st), "traverse sync");
+        S.levels = level;
+        // largest admissible block side: clusters at the first admissible level
+        for (int l = 0; l < std::max(min_adm_level, 0); ++l) big_adm = (big_adm + 1) / 2;
+    }
+    S.phase_ms[2] = ms_since(t0);
+    t0 = clk::now();
+
+    const int kmax = h->prm.max_rank;
+    DevBuf tmp_a, tmp_b, scan_scr, total;
+    alloc(total, 8, "total");
+    const int64_t nmax = std::max<int64_t>(std::max<int64_t>(h->n_adm, h->n_dense), 1);
+    alloc(scan_scr, scan_scratch_bytes(nmax + 1) + 64, "scan scratch");
+    auto scan = [&](int64_t* data, int64_t cnt) -> int64_t {
+        check(exclusive_scan_i64(data, cnt, total.as<int64_t>(), scan_scr.p, st), "scan");
+        return read_scalar(total.as<int64_t>(), st);
+    };
+
+    // ---- 4. batched ACA of the admissible leaves ----
+    alloc(h->rank, std::max<int64_t>(h->n_adm, 1) * 4, "ranks");
+    alloc(h->steps, std::max<int64_t>(h->n_adm, 1) * 4, "steps");
+    alloc(h->uoff, (h->n_adm + 1) * 8, "U offsets");
+    alloc(h->voff, (h->n_adm + 1) * 8, "V offsets");
+    if (h->n_adm > 0) {
+        DevBuf cu, cv, Ucap, Vcap;
+        alloc(cu, (h->n_adm + 1) * 8, "U capacity offsets");
+        alloc(cv, (h->n_adm + 1) * 8, "V capacity offsets");
+        check(launch_extent(h->adm.as<int4>(), h->n_adm, 0, kmax, nullptr, nullptr,
+                            cu.as<int64_t>(), st),
+              "extent");
+        check(launch_extent(h->adm.as<int4>(), h->n_adm, 1, kmax, nullptr, nullptr,
+                            cv.as<int64_t>(), st),
+              "extent");
+        const int64_t ucap = scan(cu.as<int64_t>(), h->n_adm);
+        const int64_t vcap = scan(cv.as<int64_t>(), h->n_adm);
+        alloc(Ucap, ucap * esz, "U capacity pool");
+        alloc(Vcap, vcap * esz, "V capacity pool");
+        const int64_t big = big_adm;
+        const int words = (int)(2 * ((big + 31) / 32));
+        if ((size_t)words * 4 > 64 * 1024) {
+            set_err("admissible block of %lld rows exceeds the ACA bitmask capacity",
+                    (long long)big);
+            throw Fail{HMX_ERR_UNSUPPORTED};
+        }
+        AcaArgs a{};
+        a.soa = f64 ? h->soa64.p : h->soa32.p;
+        a.soa64 = h->soa64.as<double>();
+        a.n = n;
+        a.d = d;
+        a.kern = KernelFn{(int)h->kern.kind, h->kern.p0};
+        a.blocks = h->adm.as<int4>();
+        a.nblocks = h->n_adm;
+        a.uoff = cu.as<int64_t>();
+        a.voff = cv.as<int64_t>();
+        a.kmax = kmax;
+        a.eps = h->prm.aca_eps;
+        a.aca_eta = h->prm.aca_eta;
+        a.eps0 = h->prm.aca_eps0 >= 0 ? h->prm.aca_eps0 : (f64 ? 1e-14 : 1e-7);
+        a.fixed = h->prm.rank_mode == HMX_RANK_FIXED;
+        a.U = Ucap.p;
+        a.V = Vcap.p;
+        a.rank = h->rank.as<int32_t>();
+        a.steps = h->steps.as<int32_t>();
+        a.lds_words = std::max(words, 2);
+        check(launch_aca(a, f64, st), "aca");
+        check(hipStreamSynchronize(st), "aca sync");
+        S.phase_ms[3] = ms_since(t0);
+        t0 = clk::now();
+        // exact-size pools
+        check(launch_extent(h->adm.as<int4>(), h->n_adm, 3, 0, h->rank.as<int32_t>(), nullptr,
+                            h->uoff.as<int64_t>(), st),
+              "extent");
+        check(launch_extent(h->adm.as<int4>(), h->n_adm, 4, 0, h->rank.as<int32_t>(), nullptr,
+                            h->voff.as<int64_t>(), st),
+              "extent");
+        const int64_t ue = scan(h->uoff.as<int64_t>(), h->n_adm);
+        const int64_t ve = scan(h->voff.as<int64_t>(), h->n_adm);
+        alloc(h->U, ue * esz, "U pool");
+        alloc(h->V, ve * esz, "V pool");
+        check(launch_compact_factors(h->adm.as<int4>(), h->n_adm, h->rank.as<int32_t>(),
+                                     cu.as<int64_t>(), cv.as<int64_t>(), h->uoff.as<int64_t>(),
+                                     h->voff.as<int64_t>(), Ucap.p, Vcap.p, h->U.p, h->V.p, f64,
+                                     st),
+              "compact");
+        check(hipStreamSynchronize(st), "compact sync");
+        h->factor_entries = ue + ve;
+        S.phase_ms[4] = ms_since(t0);
+    } else {
+        alloc(h->U, 16, "U pool");
+        alloc(h->V, 16, "V pool");
+    }
+    t0 = clk::now();
+    // t offsets
+    alloc(h->toff, (h->n_adm + 1) * 8, "t offsets");
+    if (h->n_adm > 0) {
+        check(launch_extent(h->adm.as<int4>(), h->n_adm, 5, 0, h->rank.as<int32_t>(), nullptr,
+                            h->toff.as<int64_t>(), st),
+              "extent");
+        h->sum_rank = scan(h->toff.as<int64_t>(), h->n_adm);
+    }
+    alloc(h->vecpool, (size_t)(n + h->sum_rank) * esz, "vector pool");
+
+    // ---- 5. near field (dense leaves, stored) ----
+    alloc(h->near_off, (h->n_dense + 1) * 8, "near offsets");
+    if (h->n_dense > 0) {
+        check(launch_extent(h->dense.as<int4>(), h->n_dense, 2, 0, nullptr, nullptr,
+                            h->near_off.as<int64_t>(), st),
+              "extent");
+        h->near_entries = scan(h->near_off.as<int64_t>(), h->n_dense);
+        alloc(h->near, h->near_entries * esz, "near-field pool");
+        check(launch_near_assemble(f64 ? h->soa64.p : h->soa32.p, n, d,
+                                   KernelFn{(int)h->kern.kind, h->kern.p0}, h->dense.as<int4>(),
+                                   h->n_dense, h->near_off.as<int64_t>(), h->near.p, f64, st),
+              "near field");
+        check(hipStreamSynchronize(st), "near sync");
+    } else {
+        alloc(h->near, 16, "near-field pool");
+    }
+    S.phase_ms[5] = ms_since(t0);
+    t0 = clk::now();
+
+    // ---- 6. matvec plan: pieces grouped by row tile ----
+    {
+        const int64_t nb = h->n_adm + h->n_dense;
+        DevBuf cnt, pieces_unsorted, keys, vals, sscr;
+        alloc(cnt, (nb + 1) * 8, "piece counts");
+        check(launch_extent(h->adm.as<int4>(), h->n_adm, 6, 0, h->rank.as<int32_t>(),
+                            h->tile_of_point.as<int32_t>(), cnt.as<int64_t>(), st),
+              "extent");
+        check(launch_extent(h->dense.as<int4>(), h->n_dense, 6, 0, nullptr,
+                            h->tile_of_point.as<int32_t>(), cnt.as<int64_t>() + h->n_adm, st),
+              "extent");
+        DevBuf big_scr;
+        alloc(big_scr, scan_scratch_bytes(nb + 1) + 64, "piece scan");
+        check(exclusive_scan_i64(cnt.as<int64_t>(), nb, total.as<int64_t>(), big_scr.p, st),
+              "piece scan");
+        h->npieces = read_scalar(total.as<int64_t>(), st);
+        alloc(pieces_unsorted, h->npieces * sizeof(Piece), "pieces");
+        alloc(keys, h->npieces * 8, "piece keys");
+        alloc(vals, h->npieces * 4, "piece vals");
+        check(launch_piece_fill(h->adm.as<int4>(), h->n_adm, h->rank.as<int32_t>(),
+                                h->tile_of_point.as<int32_t>(), h->tile_lo.as<int32_t>(),
+                                cnt.as<int64_t>(), h->uoff.as<int64_t>(), h->toff.as<int64_t>(),
+                                n, 1, 0, pieces_unsorted.as<Piece>(), keys.as<uint64_t>(),
+                                vals.as<uint32_t>(), st),
+              "piece fill");
+        check(launch_piece_fill(h->dense.as<int4>(), h->n_dense, nullptr,
+                                h->tile_of_point.as<int32_t>(), h->tile_lo.as<int32_t>(),
+                                cnt.as<int64_t>() + h->n_adm, h->near_off.as<int64_t>(), nullptr,
+                                0, 0, 0, pieces_unsorted.as<Piece>(), keys.as<uint64_t>(),
+                                vals.as<uint32_t>(), st),
+              "piece fill");
+        int bits = 1;
+        while ((1ll << bits) <= h->ntiles) ++bits;
+        alloc(sscr, radix_sort_scratch_bytes(h->npieces), "piece sort");
+        check(radix_sort_pairs(keys.as<uint64_t>(), vals.as<uint32_t>(), h->npieces, bits, sscr.p,
+                               st),
+              "piece sort");
+        alloc(h->pieces, h->npieces * sizeof(Piece), "sorted pieces");
+        check(launch_piece_gather(pieces_unsorted.as<Piece>(), vals.as<uint32_t>(), h->npieces,
+                                  h->pieces.as<Piece>(), st),
+              "piece gather");
+        alloc(h->tile_ptr, (h->ntiles + 1) * 8, "tile ptr");
+        check(launch_tile_offsets(keys.as<uint64_t>(), h->npieces, h->ntiles,
+                                  h->tile_ptr.as<int64_t>(), st),
+              "tile ptr");
+        check(hipStreamSynchronize(st), "plan sync");
+    }
+    S.phase_ms[6] = ms_since(t0);
+
+    // ---- stats ----
+    S.n = n;
+    S.d = d;
+    S.n_adm = h->n_adm;
+    S.n_dense = h->n_dense;
+    S.n_tiles = h->ntiles;
+    S.sum_rank = h->sum_rank;
+    S.factor_entries = h->factor_entries;
+    S.near_entries = h->near_entries;
+    S.phase_ms[7] = ms_since(t_all);
+    // algorithmic bytes of one matvec with beta = 0: stored data once, the
+    // vectors x and z once, perm for gather and scatter, t written and read
+    S.matvec_bytes = (double)(h->near_entries + h->factor_entries) * esz +
+                     (double)n * (2.0 * esz + 8.0) + (double)h->sum_rank * 2.0 * esz;
+    S.device_bytes = h->device_bytes();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hmx_status_string(hmx_status s) {
+    switch (s) {
+        case HMX_OK: return "ok";
+        case HMX_ERR_INVALID_ARG: return "invalid argument";
+        case HMX_ERR_OOM: return "out of device memory";
+        case HMX_ERR_DEVICE: return "device error";
+        case HMX_ERR_NOT_CONVERGED: return "not converged";
+        case HMX_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* hmx_last_error(void) { return g_err.c_str(); }
+
+hmx_status hmx_params_default(hmx_params* p) {
+    if (!p) {
+        set_err("params is NULL");
+        return HMX_ERR_INVALID_ARG;
+    }
+    memset(p, 0, sizeof *p);
+    p->leaf_size = 256;
+    p->eta = 1.5;
+    p->aca_eps = 1e-5;
+    p->aca_eta = 0.0;
+    p->aca_eps0 = -1.0;
+    p->max_rank = 64;
+    p->sigma2 = 0.0;
+    p->compute_dtype = HMX_F32;
+    p->rank_mode = HMX_RANK_ADAPTIVE;
+    return HMX_OK;
+}
+
+hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t d,
+                     const hmx_kernel* kernel, const hmx_params* params, void* stream,
+                     hmx_hmatrix* out) {
+    if (out) *out = nullptr;
+    if (!out || !points || !kernel || !params) {
+        set_err("NULL argument");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (n < 1 || n >= (1ll << 31)) {
+        set_err("n = %lld out of range [1, 2^31)", (long long)n);
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (d < 1 || d > 3) {
+        set_err("d = %d not in {1,2,3}", d);
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (pts_dtype != HMX_F64 && pts_dtype != HMX_F32) {
+        set_err("points must be F64 or F32");
+        return HMX_ERR_INVALID_ARG;
+    }
+    const hmx_params& p = *params;
+    if (p.leaf_size < 1 || !(p.eta >= 0) || !std::isfinite(p.eta) || !(p.aca_eps >= 0) ||
+        !(p.aca_eta >= 0 && p.aca_eta < 1) || p.max_rank < 1 || p.max_rank > kMaxRankCap ||
+        !(p.sigma2 >= 0) || !std::isfinite(p.sigma2)) {
+        set_err("invalid params (leaf %d, eta %g, eps %g, aca_eta %g, max_rank %d, sigma2 %g)",
+                p.leaf_size, p.eta, p.aca_eps, p.aca_eta, p.max_rank, p.sigma2);
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (p.compute_dtype != HMX_F64 && p.compute_dtype != HMX_F32) {
+        set_err("compute_dtype must be F64 or F32");
+        return HMX_ERR_UNSUPPORTED;
+    }
+    if (p.rank_mode != HMX_RANK_ADAPTIVE && p.rank_mode != HMX_RANK_FIXED) {
+        set_err("unsupported rank mode %d", (int)p.rank_mode);
+        return HMX_ERR_UNSUPPORTED;
+    }
+    if (kernel->kind != HMX_GAUSSIAN && kernel->kind != HMX_MATERN32 &&
+        kernel->kind != HMX_TEST_CONST && kernel->kind != HMX_TEST_LOWRANK) {
+        set_err("unknown kernel kind %d", (int)kernel->kind);
+        return HMX_ERR_INVALID_ARG;
+    }
+    if ((kernel->kind == HMX_GAUSSIAN || kernel->kind == HMX_MATERN32) &&
+        !(kernel->p0 > 0 && std::isfinite(kernel->p0))) {
+        set_err("kernel parameter p0 must be positive and finite");
+        return HMX_ERR_INVALID_ARG;
+    }
+    hmx_hmatrix_s* h = new (std::nothrow) hmx_hmatrix_s();
+    if (!h) {
+        set_err("host allocation failed");
+        return HMX_ERR_OOM;
+    }
+    h->n = n;
+    h->d = d;
+    h->kern = *kernel;
+    h->prm = p;
+    h->f64 = p.compute_dtype == HMX_F64;
+    h->esz = h->f64 ? 8 : 4;
+    try {
+        build_impl(h, points, pts_dtype == HMX_F64, (hipStream_t)stream);
+    } catch (const Fail& f) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        (void)hipGetLastError();
+        delete h;
+        return f.s;
+    } catch (const std::bad_alloc&) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        delete h;
+        set_err("host allocation failed");
+        return HMX_ERR_OOM;
+    }
+    *out = h;
+    return HMX_OK;
+}
+
+hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype, double alpha,
+                      double beta, void* stream) {
+    if (!h || !x || !z) {
+        set_err("NULL argument");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if ((vec_dtype == HMX_F64) != (h->f64 == 1) || vec_dtype == HMX_BF16) {
+        set_err("vector dtype must equal the compute dtype");
+        return HMX_ERR_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int f64 = h->f64;
+    hipError_t e = launch_gather_x(x, h->perm.as<int32_t>(), h->n, h->vecpool.p, f64, st);
+    if (e == hipSuccess)
+        e = launch_far_phase1(h->adm.as<int4>(), h->n_adm, h->rank.as<int32_t>(),
+                              h->voff.as<int64_t>(), h->toff.as<int64_t>(), h->V.p, h->vecpool.p,
+                              h->n, f64, st);
+    if (e == hipSuccess)
+        e = launch_rowtile(h->ntiles, h->tile_lo.as<int32_t>(), h->tile_ptr.as<int64_t>(),
+                           h->pieces.as<Piece>(), h->near.p, h->U.p, h->vecpool.p,
+                           h->perm.as<int32_t>(), h->n, alpha, beta, h->prm.sigma2, z,
+                           h->max_tile, f64, st);
+    if (e != hipSuccess) {
+        set_err("matvec launch: %s", hipGetErrorString(e));
+        return HMX_ERR_DEVICE;
+    }
+    return HMX_OK;
+}
+
+hmx_status hmx_get_partition(hmx_hmatrix h, uint64_t* codes, int32_t* perm, int32_t* adm,
+                             int64_t* n_adm, int32_t* dense, int64_t* n_dense, void* stream) {
+    if (!h) {
+        set_err("NULL handle");
+        return HMX_ERR_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        if ((adm && (!n_adm || *n_adm < h->n_adm)) || (dense && (!n_dense || *n_dense < h->n_dense))) {
+            if (n_adm) *n_adm = h->n_adm;
+            if (n_dense) *n_dense = h->n_dense;
+            set_err("partition capacity too small");
+            return HMX_ERR_INVALID_ARG;
+        }
+        if (n_adm) *n_adm = h->n_adm;
+        if (n_dense) *n_dense = h->n_dense;
+        std::vector<uint32_t> pm(h->n);
+        check(hipMemcpyAsync(pm.data(), h->perm.p, h->n * 4, hipMemcpyDeviceToHost, st), "perm");
+        std::vector<uint64_t> sc;
+        if (codes) {
+            sc.resize(h->n);
+            check(hipMemcpyAsync(sc.data(), h->codes.p, h->n * 8, hipMemcpyDeviceToHost, st),
+                  "codes");
+        }
+        std::vector<int4> a(h->n_adm), dn(h->n_dense);
+        std::vector<int32_t> al(h->n_adm), dl(h->n_dense);
+        if (adm && h->n_adm) {
+            check(hipMemcpyAsync(a.data(), h->adm.p, h->n_adm * 16, hipMemcpyDeviceToHost, st), "adm");
+            check(hipMemcpyAsync(al.data(), h->adm_level.p, h->n_adm * 4, hipMemcpyDeviceToHost, st),
+                  "adm level");
+        }
+        if (dense && h->n_dense) {
+            check(hipMemcpyAsync(dn.data(), h->dense.p, h->n_dense * 16, hipMemcpyDeviceToHost, st),
+                  "dense");
+            check(hipMemcpyAsync(dl.data(), h->dense_level.p, h->n_dense * 4, hipMemcpyDeviceToHost,
+                                 st),
+                  "dense level");
+        }
+        check(hipStreamSynchronize(st), "sync");
+        if (perm)
+            for (int64_t k = 0; k < h->n; ++k) perm[k] = (int32_t)pm[k];
+        if (codes)
+            for (int64_t k = 0; k < h->n; ++k) codes[pm[k]] = sc[k];
+        if (adm)
+            for (int64_t q = 0; q < h->n_adm; ++q) {
+                int32_t* o = adm + 5 * q;
+                o[0] = a[q].x; o[1] = a[q].y; o[2] = a[q].z; o[3] = a[q].w; o[4] = al[q];
+            }
+        if (dense)
+            for (int64_t q = 0; q < h->n_dense; ++q) {
+                int32_t* o = dense + 5 * q;
+                o[0] = dn[q].x; o[1] = dn[q].y; o[2] = dn[q].z; o[3] = dn[q].w; o[4] = dl[q];
+            }
+    } catch (const Fail& f) {
+        return f.s;
+    }
+    return HMX_OK;
+}
+
+hmx_status hmx_get_boxes(hmx_hmatrix h, double* global_box, double* leaf_boxes, void* stream) {
+    if (!h) {
+        set_err("NULL handle");
+        return HMX_ERR_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        if (global_box)
+            for (int k = 0; k < 2 * h->d; ++k) global_box[k] = h->box[k];
+        if (leaf_boxes) {
+            const int d = h->d;
+            std::vector<int32_t> lo(h->nslots), hi(h->nslots);
+            std::vector<double> bmn(h->nslots * d), bmx(h->nslots * d);
+            check(hipMemcpyAsync(lo.data(), h->node_lo.p, h->nslots * 4, hipMemcpyDeviceToHost, st), "lo");
+            check(hipMemcpyAsync(hi.data(), h->node_hi.p, h->nslots * 4, hipMemcpyDeviceToHost, st), "hi");
+            check(hipMemcpyAsync(bmn.data(), h->bmin.p, h->nslots * d * 8, hipMemcpyDeviceToHost, st), "bmin");
+            check(hipMemcpyAsync(bmx.data(), h->bmax.p, h->nslots * d * 8, hipMemcpyDeviceToHost, st), "bmax");
+            check(hipStreamSynchronize(st), "sync");
+            // leaf clusters in Morton order (sorted by lo)
+            std::vector<std::pair<int32_t, int64_t>> leaves;
+            for (int64_t id = 0; id < h->nslots; ++id)
+                if (lo[id] >= 0 && hi[id] - lo[id] <= h->prm.leaf_size) leaves.push_back({lo[id], id});
+            std::sort(leaves.begin(), leaves.end());
+            const int w = 2 * d + 2;
+            for (size_t t = 0; t < leaves.size(); ++t) {
+                const int64_t id = leaves[t].second;
+                for (int k = 0; k < d; ++k) {
+                    leaf_boxes[t * w + k] = bmn[id * d + k];
+                    leaf_boxes[t * w + d + k] = bmx[id * d + k];
+                }
+                leaf_boxes[t * w + 2 * d] = lo[id];
+                leaf_boxes[t * w + 2 * d + 1] = hi[id];
+            }
+        }
+    } catch (const Fail& f) {
+        return f.s;
+    }
+    return HMX_OK;
+}
+
+hmx_status hmx_get_ranks(hmx_hmatrix h, int32_t* ranks, void* stream) {
+    if (!h || !ranks) {
+        set_err("NULL argument");
+        return HMX_ERR_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        if (h->n_adm) {
+            check(hipMemcpyAsync(ranks, h->rank.p, h->n_adm * 4, hipMemcpyDeviceToHost, st), "ranks");
+            check(hipStreamSynchronize(st), "sync");
+        }
+    } catch (const Fail& f) {
+        return f.s;
+    }
+    return HMX_OK;
+}
+
+hmx_status hmx_get_factors(hmx_hmatrix h, int64_t leaf, double* U, double* V, int32_t* rank,
+                           void* stream) {
+    if (!h || leaf < 0 || leaf >= h->n_adm || !U || !V || !rank) {
+        set_err("invalid argument to hmx_get_factors");
+        return HMX_ERR_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        int4 bl;
+        int32_t r;
+        int64_t uo, vo;
+        check(hipMemcpyAsync(&bl, h->adm.as<int4>() + leaf, 16, hipMemcpyDeviceToHost, st), "blk");
+        check(hipMemcpyAsync(&r, h->rank.as<int32_t>() + leaf, 4, hipMemcpyDeviceToHost, st), "r");
+        check(hipMemcpyAsync(&uo, h->uoff.as<int64_t>() + leaf, 8, hipMemcpyDeviceToHost, st), "uo");
+        check(hipMemcpyAsync(&vo, h->voff.as<int64_t>() + leaf, 8, hipMemcpyDeviceToHost, st), "vo");
+        check(hipStreamSynchronize(st), "sync");
+        const int64_t m = bl.y - bl.x, nc = bl.w - bl.z;
+        *rank = r;
+        if (h->f64) {
+            check(hipMemcpyAsync(U, h->U.as<double>() + uo, r * m * 8, hipMemcpyDeviceToHost, st), "U");
+            check(hipMemcpyAsync(V, h->V.as<double>() + vo, r * nc * 8, hipMemcpyDeviceToHost, st), "V");
+            check(hipStreamSynchronize(st), "sync");
+        } else {
+            std::vector<float> u(r * m), v(r * nc);
+            check(hipMemcpyAsync(u.data(), h->U.as<float>() + uo, r * m * 4, hipMemcpyDeviceToHost, st), "U");
+            check(hipMemcpyAsync(v.data(), h->V.as<float>() + vo, r * nc * 4, hipMemcpyDeviceToHost, st), "V");
+            check(hipStreamSynchronize(st), "sync");
+            for (int64_t e = 0; e < r * m; ++e) U[e] = u[e];
+            for (int64_t e = 0; e < r * nc; ++e) V[e] = v[e];
+        }
+    } catch (const Fail& f) {
+        return f.s;
+    }
+    return HMX_OK;
+}
+
+hmx_status hmx_get_stats(hmx_hmatrix h, hmx_stats* s) {
+    if (!h || !s) {
+        set_err("NULL argument");
+        return HMX_ERR_INVALID_ARG;
+    }
+    *s = h->stats;
+    return HMX_OK;
+}
+
+hmx_status hmx_destroy(hmx_hmatrix h) {
+    if (!h) return HMX_OK;
+    (void)hipDeviceSynchronize();
+    delete h;
+    return HMX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,205 @@
+// Internal declarations shared by the HIP translation units of libhmx.
+// Device helpers (kernel functions, reductions) and the host-side launchers
+// each .hip file exports to the orchestration in hmx_api.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/hmx.h"
+
+namespace hmx {
+
+constexpr int kMaxRankCap = 128;  // largest supported k_max
+constexpr int kWave = 64;         // CDNA wavefront width
+
+struct KernelFn {
+    int kind;
+    double p0;
+};
+
+// ---------------------------------------------------------------------------
+// kernel functions phi(x, y) (matrix entries of eq. (2)); T = float or double
+// ---------------------------------------------------------------------------
+template <typename T>
+struct KernelEval {
+    int kind;
+    T inv_p0;   // 1 / p0
+    T s3_inv;   // sqrt(3) / p0 (Matern-3/2)
+    __host__ __device__ KernelEval() {}
+    __host__ KernelEval(const KernelFn& k)
+        : kind(k.kind), inv_p0((T)(1.0 / k.p0)), s3_inv((T)(1.7320508075688772 / k.p0)) {}
+};
+
+__device__ __forceinline__ float kexp(float a) { return __expf(a); }
+__device__ __forceinline__ double kexp(double a) { return exp(a); }
+__device__ __forceinline__ float ksqrt(float a) { return __fsqrt_rn(a); }
+__device__ __forceinline__ double ksqrt(double a) { return sqrt(a); }
+
+// phi for points x (d coords) and y (d coords)
+template <typename T>
+__device__ __forceinline__ T phi(const KernelEval<T>& K, const T* x, const T* y, int d) {
+    T r2 = 0, dot = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        if (k < d) {
+            T t = x[k] - y[k];
+            r2 += t * t;
+            dot += x[k] * y[k];
+        }
+    switch (K.kind) {
+        case HMX_GAUSSIAN:
+            return kexp(-r2 * K.inv_p0);
+        case HMX_MATERN32: {
+            T s = ksqrt(r2) * K.s3_inv;
+            return ((T)1 + s) * kexp(-s);
+        }
+        case HMX_TEST_CONST:
+            return (T)1;
+        default: {  // HMX_TEST_LOWRANK
+            T u = (T)1 + dot;
+            return u * u;
+        }
+    }
+}
+
+// load point i of a d x n SoA array
+template <typename T>
+__device__ __forceinline__ void load_pt(const T* __restrict__ soa, int64_t n, int d, int64_t i,
+                                        T* p) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) p[k] = (k < d) ? soa[(int64_t)k * n + i] : (T)0;
+}
+
+// ---------------------------------------------------------------------------
+// wave / block reductions (wave64)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers (host side); every launcher enqueues on `st` and returns
+// hipSuccess or the launch error
+// ---------------------------------------------------------------------------
+// ordering (k_order.hip)
+hipError_t launch_global_box(const void* pts, int pts_f64, int64_t n, int d, double* partial,
+                             int nparts, double* box /*2d: lo then hi*/, hipStream_t st);
+int global_box_parts(int64_t n);
+hipError_t launch_morton(const void* pts, int pts_f64, int64_t n, int d, const double* box,
+                         uint64_t* codes, uint32_t* idx, hipStream_t st);
+// stable LSD radix sort of (key, value) pairs on the low `bits` key bits;
+// scratch from radix_sort_scratch_bytes; results end in keys/vals
+size_t radix_sort_scratch_bytes(int64_t n);
+hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int bits, void* scratch,
+                            hipStream_t st);
+hipError_t launch_gather_coords(const void* pts, int pts_f64, int64_t n, int d,
+                                const uint32_t* perm, double* soa64, float* soa32,
+                                hipStream_t st);
+
+// scans (k_tree.hip): exclusive scan of n int64 values in place; total to *total_dev
+size_t scan_scratch_bytes(int64_t n);
+hipError_t exclusive_scan_i64(int64_t* data, int64_t n, int64_t* total_dev, void* scratch,
+                              hipStream_t st);
+
+// cluster tree and traversal (k_tree.hip)
+hipError_t launch_tree_level(int level, int64_t n, int leaf, int32_t* node_lo, int32_t* node_hi,
+                             hipStream_t st);
+hipError_t launch_box_level(int level, int d, int leaf, const int32_t* node_lo,
+                            const int32_t* node_hi, const double* soa, int64_t n, double* bmin,
+                            double* bmax, hipStream_t st);
+// traversal of one block-tree level: classify (t, s) pairs, write children of
+// split nodes to next (4 per split node) and leaves to adm/dense (as
+// int4 ranges + level) at the given bases; counts_dev[0..2] = (#adm, #split,
+// #dense) of this level.  Two phases: count, then write.
+size_t traverse_scratch_bytes(int64_t max_nodes);
+int64_t traverse_blocks(int64_t nodes);
+hipError_t launch_traverse_count(const int2* cur, int64_t ncur, const int32_t* node_lo,
+                                 const int32_t* node_hi, const double* bmin, const double* bmax,
+                                 int d, int leaf, double eta, int64_t* block_counts,
+                                 hipStream_t st);
+hipError_t launch_traverse_scan(int64_t* block_counts, int64_t nblk, int64_t* totals,
+                                hipStream_t st);
+hipError_t launch_traverse_write(const int2* cur, int64_t ncur, const int32_t* node_lo,
+                                 const int32_t* node_hi, const double* bmin, const double* bmax,
+                                 int d, int leaf, double eta, const int64_t* block_offsets,
+                                 int level, int2* next, int4* adm, int32_t* adm_level,
+                                 int64_t adm_base, int4* dense, int32_t* dense_level,
+                                 int64_t dense_base, hipStream_t st);
+
+// leaf tiles (k_tree.hip): tile_of_point via leaf-start flags and a scan
+hipError_t launch_mark_leaves(int L, int leaf, const int32_t* node_lo, const int32_t* node_hi,
+                              int64_t nslots, int32_t* flags, hipStream_t st);
+hipError_t launch_iota_scan_tiles(int32_t* flags_to_tile, int64_t n, int32_t* tile_lo,
+                                  int64_t* ntiles_dev, void* scratch, hipStream_t st);
+size_t tile_scan_scratch_bytes(int64_t n);
+
+// ACA (k_aca.hip)
+struct AcaArgs {
+    const void* soa;      // d x n compute-type coords
+    const double* soa64;  // d x n FP64 coords (first-column choice)
+    int64_t n;
+    int d;
+    KernelFn kern;
+    const int4* blocks;
+    int64_t nblocks;
+    const int64_t* uoff;  // per block, capacity offsets (entries)
+    const int64_t* voff;
+    int kmax;
+    double eps, aca_eta, eps0;
+    int fixed;
+    void* U;
+    void* V;
+    int32_t* rank;
+    int32_t* steps;
+    int lds_words;  // used-row + used-col bitmask words reserved per workgroup
+};
+hipError_t launch_aca(const AcaArgs& a, int f64, hipStream_t st);
+
+// near field and matvec (k_mvp.hip)
+hipError_t launch_near_assemble(const void* soa, int64_t n, int d, KernelFn kern,
+                                const int4* blocks, int64_t nblocks, const int64_t* off,
+                                void* A, int f64, hipStream_t st);
+hipError_t launch_compact_factors(const int4* blocks, int64_t nblocks, const int32_t* rank,
+                                  const int64_t* cap_uoff, const int64_t* cap_voff,
+                                  const int64_t* uoff, const int64_t* voff, const void* Ucap,
+                                  const void* Vcap, void* U, void* V, int f64, hipStream_t st);
+
+struct Piece {
+    int64_t a_off;  // element offset of the piece's first row in its pool
+    int64_t v_off;  // element offset of the vector segment in the vector pool
+    int32_t ld;     // column stride (rows of the whole block)
+    int32_t ncols;
+    int32_t pool;   // 0 = near-field pool, 1 = U pool
+    int32_t pad;
+};
+// per-block sizes: mode 0: m * mult, 1: n * mult, 2: m * n, 3: r * m, 4: r * n,
+// 5: r, 6: row tiles covered by tau (0 for an admissible leaf of rank 0)
+hipError_t launch_extent(const int4* blocks, int64_t nb, int mode, int64_t mult,
+                         const int32_t* rank, const int32_t* tile_of_point, int64_t* out,
+                         hipStream_t st);
+hipError_t launch_piece_fill(const int4* blocks, int64_t nblocks, const int32_t* rank,
+                             const int32_t* tile_of_point, const int32_t* tile_lo,
+                             const int64_t* piece_off, const int64_t* data_off,
+                             const int64_t* vec_off_blk, int64_t vec_base, int pool,
+                             int64_t piece_base, Piece* pieces, uint64_t* keys, uint32_t* vals,
+                             hipStream_t st);
+hipError_t launch_piece_gather(const Piece* src, const uint32_t* order, int64_t npieces,
+                               Piece* dst, hipStream_t st);
+hipError_t launch_tile_offsets(const uint64_t* sorted_tile, int64_t npieces, int64_t ntiles,
+                               int64_t* tile_ptr, hipStream_t st);
+hipError_t launch_gather_x(const void* x, const int32_t* perm, int64_t n, void* xm, int f64,
+                           hipStream_t st);
+hipError_t launch_far_phase1(const int4* adm, int64_t nadm, const int32_t* rank,
+                             const int64_t* voff, const int64_t* toff, const void* V,
+                             void* vecpool, int64_t n, int f64, hipStream_t st);
+hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t* tile_ptr,
+                          const Piece* pieces, const void* near, const void* U,
+                          const void* vecpool, const int32_t* perm, int64_t n, double alpha,
+                          double beta, double sigma2, void* z, int max_tile, int f64,
+                          hipStream_t st);
+
+}  // namespace hmx

@@ -1,0 +1,408 @@
+// Batched adaptive cross approximation (Algorithm 2, Section 5.4.1).
+//
+// One workgroup (4 waves) per admissible block, each running its own rank
+// loop, so blocks stop independently (no global "voting" bounded by the
+// slowest block).  Per step r:
+//   1. residual column  u^ = A[:, j] - sum_{l<r} u_l (v_l)_j   (rows over threads)
+//   2. row pivot        i  = argmax over unused rows |u^_i| (lowest index on ties)
+//      a column whose largest residual entry is <= eps0 adds no rank; the
+//      lowest unused column is tried next, and kmax such columns end the block
+//   3. u_r = u^ / u^_i,  v_r = A[i, :]^T - sum_{l<r} (u_l)_i v_l  (cols over threads)
+//   4. |S_r|_F^2 += 2 sum_{l<r} (u_r.u_l)(v_r.v_l) + |u_r|^2 |v_r|^2   in FP64
+//   5. stop if |u_r| |v_r| <= eps (1 - aca_eta) / (1 + eps) |S_r|_F
+//   6. next column pivot j = argmax over unused columns |(v_r)_j|
+// The first column is the sigma point nearest (FP64, no contraction) to the
+// centre of tau's bounding box, so the first cross runs through the block's
+// largest entries.
+// Used rows/columns are bitmasks in LDS.  U (m x kmax) and V (n x kmax) are
+// column-major in a capacity pool; column r of U doubles as the scratch for
+// the residual column.  All reductions have a fixed tree, so the result is
+// bit-reproducible from run to run.
+#include <climits>
+
+#include "hmx_internal.h"
+
+namespace hmx {
+
+namespace {
+
+constexpr int kAcaThreads = 256;
+constexpr int kAcaWaves = kAcaThreads / kWave;
+
+template <typename T>
+struct Arg {
+    T best;  // |value|; -1 = none
+    int idx;
+    T val;   // signed value
+};
+
+template <typename T>
+__device__ __forceinline__ void arg_combine(Arg<T>& a, const Arg<T>& b) {
+    if (b.best > a.best || (b.best == a.best && b.idx < a.idx)) a = b;
+}
+
+template <typename T>
+__device__ __forceinline__ Arg<T> wave_argmax(Arg<T> a) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        Arg<T> b;
+        b.best = __shfl_xor(a.best, o, 64);
+        b.idx = __shfl_xor(a.idx, o, 64);
+        b.val = __shfl_xor(a.val, o, 64);
+        arg_combine(a, b);
+    }
+    return a;
+}
+
+template <typename T>
+struct AcaShared {
+    T vec[kMaxRankCap];      // broadcast row of V (step 1) / row of U (step 3)
+    T abest[kAcaWaves];
+    T aval[kAcaWaves];
+    int aidx[kAcaWaves];
+    double dsum[3][kAcaWaves];
+    int imin[kAcaWaves];
+    double dkey[kAcaWaves];
+    int dkidx[kAcaWaves];
+};
+
+template <typename T>
+__device__ Arg<T> block_argmax(Arg<T> a, AcaShared<T>& sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    a = wave_argmax(a);
+    if (lane == 0) {
+        sh.abest[w] = a.best;
+        sh.aidx[w] = a.idx;
+        sh.aval[w] = a.val;
+    }
+    __syncthreads();
+    Arg<T> r{sh.abest[0], sh.aidx[0], sh.aval[0]};
+    for (int q = 1; q < kAcaWaves; ++q) {
+        Arg<T> b{sh.abest[q], sh.aidx[q], sh.aval[q]};
+        arg_combine(r, b);
+    }
+    __syncthreads();
+    return r;
+}
+
+// sums of three doubles across the workgroup, same tree on every thread
+template <typename T>
+__device__ void block_sum3(double& a, double& b, double& c, AcaShared<T>& sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    if (lane == 0) {
+        sh.dsum[0][w] = a;
+        sh.dsum[1][w] = b;
+        sh.dsum[2][w] = c;
+    }
+    __syncthreads();
+    a = sh.dsum[0][0];
+    b = sh.dsum[1][0];
+    c = sh.dsum[2][0];
+    for (int q = 1; q < kAcaWaves; ++q) {
+        a += sh.dsum[0][q];
+        b += sh.dsum[1][q];
+        c += sh.dsum[2][q];
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ int block_min_int(int v, AcaShared<T>& sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        int u = __shfl_xor(v, o, 64);
+        v = u < v ? u : v;
+    }
+    if (lane == 0) sh.imin[w] = v;
+    __syncthreads();
+    int r = sh.imin[0];
+    for (int q = 1; q < kAcaWaves; ++q) r = sh.imin[q] < r ? sh.imin[q] : r;
+    __syncthreads();
+    return r;
+}
+
+// min (op = 0) or max (op = 1) of a double across the workgroup
+template <typename T>
+__device__ double block_minmax(double v, int op, AcaShared<T>& sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double u = __shfl_xor(v, o, 64);
+        v = op ? (u > v ? u : v) : (u < v ? u : v);
+    }
+    if (lane == 0) sh.dkey[w] = v;
+    __syncthreads();
+    double r = sh.dkey[0];
+    for (int q = 1; q < kAcaWaves; ++q) r = op ? (sh.dkey[q] > r ? sh.dkey[q] : r)
+                                               : (sh.dkey[q] < r ? sh.dkey[q] : r);
+    __syncthreads();
+    return r;
+}
+
+// index of the smallest key (lowest index on ties)
+template <typename T>
+__device__ int block_argmin_f64(double key, int idx, AcaShared<T>& sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double k2 = __shfl_xor(key, o, 64);
+        const int i2 = __shfl_xor(idx, o, 64);
+        if (k2 < key || (k2 == key && i2 < idx)) {
+            key = k2;
+            idx = i2;
+        }
+    }
+    if (lane == 0) {
+        sh.dkey[w] = key;
+        sh.dkidx[w] = idx;
+    }
+    __syncthreads();
+    double bk = sh.dkey[0];
+    int bi = sh.dkidx[0];
+    for (int q = 1; q < kAcaWaves; ++q)
+        if (sh.dkey[q] < bk || (sh.dkey[q] == bk && sh.dkidx[q] < bi)) {
+            bk = sh.dkey[q];
+            bi = sh.dkidx[q];
+        }
+    __syncthreads();
+    return bi;
+}
+
+// first column: the sigma point nearest to the centre 0.5 (a + b) of tau's
+// bounding box, squared distance summed in dimension order, all in FP64
+// without contraction
+template <typename T>
+__device__ int first_column(const double* __restrict__ soa64, int64_t n, int d, int4 bl,
+                            AcaShared<T>& sh) {
+    const int m = bl.y - bl.x, nc = bl.w - bl.z;
+    double c[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < d; ++k) {
+        double mn = INFINITY, mx = -INFINITY;
+        for (int i = threadIdx.x; i < m; i += kAcaThreads) {
+            const double v = soa64[(int64_t)k * n + bl.x + i];
+            mn = v < mn ? v : mn;
+            mx = v > mx ? v : mx;
+        }
+        mn = block_minmax(mn, 0, sh);
+        mx = block_minmax(mx, 1, sh);
+        c[k] = __dmul_rn(0.5, __dadd_rn(mn, mx));
+    }
+    double best = INFINITY;
+    int bi = INT_MAX;
+    for (int q = threadIdx.x; q < nc; q += kAcaThreads) {
+        double s = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const double t = __dsub_rn(soa64[(int64_t)k * n + bl.z + q], c[k]);
+            s = __dadd_rn(s, __dmul_rn(t, t));
+        }
+        if (s < best) {
+            best = s;
+            bi = q;
+        }
+    }
+    return block_argmin_f64(best, bi, sh);
+}
+
+__device__ __forceinline__ bool bit_get(const uint32_t* m, int i) {
+    return (m[i >> 5] >> (i & 31)) & 1u;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kAcaThreads) void aca_kernel(
+    const T* __restrict__ soa, const double* __restrict__ soa64, int64_t n, int d, KernelEval<T> K,
+    const int4* __restrict__ blocks, int64_t nblocks, const int64_t* __restrict__ uoff,
+    const int64_t* __restrict__ voff, int kmax, double eps, double aca_eta, T eps0, int fixed,
+    T* __restrict__ Upool, T* __restrict__ Vpool, int32_t* __restrict__ rank_out,
+    int32_t* __restrict__ steps_out) {
+    extern __shared__ uint32_t smask[];
+    __shared__ AcaShared<T> sh;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const double tol = eps * (1.0 - aca_eta) / (1.0 + eps);
+
+    for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
+        const int4 bl = blocks[b];
+        const int m = bl.y - bl.x, nc = bl.w - bl.z;
+        int R = kmax;
+        R = m < R ? m : R;
+        R = nc < R ? nc : R;
+        T* __restrict__ U = Upool + uoff[b];
+        T* __restrict__ V = Vpool + voff[b];
+        const int mw = (m + 31) >> 5, nw = (nc + 31) >> 5;
+        uint32_t* rmask = smask;
+        uint32_t* cmask = smask + mw;
+        for (int q = tid; q < mw + nw; q += kAcaThreads) smask[q] = 0u;
+        __syncthreads();
+
+        int r = 0, ncols_used = 0, nfailed = 0, steps = 0;
+        int j = first_column(soa64, n, d, bl, sh);
+        double S2 = 0.0;
+        while (r < R) {
+            // ---- step 1: residual column j into U[:, r] ----
+            if (tid < r) sh.vec[tid] = V[(int64_t)tid * nc + j];
+            if (tid == 0) cmask[j >> 5] |= 1u << (j & 31);
+            __syncthreads();
+            ++ncols_used;
+            ++steps;
+            T yj[3];
+            load_pt(soa, n, d, (int64_t)bl.z + j, yj);
+            Arg<T> am{(T)-1, INT_MAX, (T)0};
+            for (int i = tid; i < m; i += kAcaThreads) {
+                T xi[3];
+                load_pt(soa, n, d, (int64_t)bl.x + i, xi);
+                T a = phi(K, xi, yj, d);
+                for (int l = 0; l < r; ++l) a -= U[(int64_t)l * m + i] * sh.vec[l];
+                U[(int64_t)r * m + i] = a;
+                const T aa = a < (T)0 ? -a : a;
+                if (!bit_get(rmask, i) && aa > am.best) {
+                    am.best = aa;
+                    am.idx = i;
+                    am.val = a;
+                }
+            }
+            am = block_argmax(am, sh);
+            if (am.idx == INT_MAX || am.best <= eps0) {
+                // no usable pivot in this column: try the lowest unused column
+                ++nfailed;
+                if (ncols_used >= nc || nfailed >= kmax) break;
+                int cand = INT_MAX;
+                for (int q = tid; q < nw; q += kAcaThreads) {
+                    const uint32_t word = cmask[q];
+                    if (word != 0xffffffffu) {
+                        const int c = (q << 5) + __ffs(~word) - 1;
+                        if (c < nc && c < cand) cand = c;
+                    }
+                }
+                cand = block_min_int(cand, sh);
+                if (cand == INT_MAX) break;
+                j = cand;
+                continue;
+            }
+            const int ip = am.idx;
+            const T piv = am.val;
+            // ---- step 3a: normalise u_r ----
+            double nu2 = 0.0;
+            for (int i = tid; i < m; i += kAcaThreads) {
+                const T u = U[(int64_t)r * m + i] / piv;
+                U[(int64_t)r * m + i] = u;
+                nu2 += (double)u * (double)u;
+            }
+            if (tid < r) sh.vec[tid] = U[(int64_t)tid * m + ip];
+            if (tid == 0) rmask[ip >> 5] |= 1u << (ip & 31);
+            __syncthreads();
+            // ---- step 3b: residual row i_r into V[:, r] ----
+            T xp[3];
+            load_pt(soa, n, d, (int64_t)bl.x + ip, xp);
+            double nv2 = 0.0;
+            Arg<T> cm{(T)-1, INT_MAX, (T)0};
+            for (int q = tid; q < nc; q += kAcaThreads) {
+                T yq[3];
+                load_pt(soa, n, d, (int64_t)bl.z + q, yq);
+                T a = phi(K, xp, yq, d);
+                for (int l = 0; l < r; ++l) a -= sh.vec[l] * V[(int64_t)l * nc + q];
+                V[(int64_t)r * nc + q] = a;
+                nv2 += (double)a * (double)a;
+                const T aa = a < (T)0 ? -a : a;
+                if (!bit_get(cmask, q) && aa > cm.best) {
+                    cm.best = aa;
+                    cm.idx = q;
+                    cm.val = a;
+                }
+            }
+            __syncthreads();
+            // ---- step 4: cross terms (u_r.u_l)(v_r.v_l), one wave per l ----
+            double cross = 0.0;
+            for (int l = w; l < r; l += kAcaWaves) {
+                double du = 0.0, dv = 0.0;
+                for (int i = lane; i < m; i += kWave)
+                    du += (double)U[(int64_t)r * m + i] * (double)U[(int64_t)l * m + i];
+                for (int q = lane; q < nc; q += kWave)
+                    dv += (double)V[(int64_t)r * nc + q] * (double)V[(int64_t)l * nc + q];
+                du = wave_sum(du);
+                dv = wave_sum(dv);
+                if (lane == 0) cross += du * dv;
+            }
+            block_sum3(nu2, nv2, cross, sh);
+            cm = block_argmax(cm, sh);
+            ++r;
+            S2 += 2.0 * cross + nu2 * nv2;
+            // ---- step 5: stopping criterion ----
+            if (!fixed && sqrt(nu2 * nv2) <= tol * sqrt(S2)) break;
+            // ---- step 6: next column pivot ----
+            if (cm.idx == INT_MAX) break;
+            j = cm.idx;
+        }
+        if (tid == 0) {
+            rank_out[b] = r;
+            if (steps_out) steps_out[b] = steps;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void compact_kernel(const int4* __restrict__ blocks,
+                                                      int64_t nblocks,
+                                                      const int32_t* __restrict__ rank,
+                                                      const int64_t* __restrict__ cu,
+                                                      const int64_t* __restrict__ cv,
+                                                      const int64_t* __restrict__ eu,
+                                                      const int64_t* __restrict__ ev,
+                                                      const T* __restrict__ Ucap,
+                                                      const T* __restrict__ Vcap,
+                                                      T* __restrict__ U, T* __restrict__ V) {
+    for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
+        const int4 bl = blocks[b];
+        const int64_t m = bl.y - bl.x, nc = bl.w - bl.z, r = rank[b];
+        const T* su = Ucap + cu[b];
+        const T* sv = Vcap + cv[b];
+        T* du = U + eu[b];
+        T* dv = V + ev[b];
+        for (int64_t e = threadIdx.x; e < r * m; e += blockDim.x) du[e] = su[e];
+        for (int64_t e = threadIdx.x; e < r * nc; e += blockDim.x) dv[e] = sv[e];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_aca(const AcaArgs& a, int f64, hipStream_t st) {
+    if (a.nblocks == 0) return hipSuccess;
+    const unsigned grid = (unsigned)(a.nblocks < 0x7fffffff ? a.nblocks : 0x7fffffff);
+    const size_t lds = (size_t)a.lds_words * sizeof(uint32_t);
+    if (f64) {
+        KernelEval<double> K(a.kern);
+        hipLaunchKernelGGL(aca_kernel<double>, dim3(grid), dim3(kAcaThreads), lds, st,
+                           (const double*)a.soa, a.soa64, a.n, a.d, K, a.blocks, a.nblocks, a.uoff, a.voff,
+                           a.kmax, a.eps, a.aca_eta, (double)a.eps0, a.fixed, (double*)a.U,
+                           (double*)a.V, a.rank, a.steps);
+    } else {
+        KernelEval<float> K(a.kern);
+        hipLaunchKernelGGL(aca_kernel<float>, dim3(grid), dim3(kAcaThreads), lds, st,
+                           (const float*)a.soa, a.soa64, a.n, a.d, K, a.blocks, a.nblocks, a.uoff, a.voff,
+                           a.kmax, a.eps, a.aca_eta, (float)a.eps0, a.fixed, (float*)a.U,
+                           (float*)a.V, a.rank, a.steps);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_factors(const int4* blocks, int64_t nblocks, const int32_t* rank,
+                                  const int64_t* cap_uoff, const int64_t* cap_voff,
+                                  const int64_t* uoff, const int64_t* voff, const void* Ucap,
+                                  const void* Vcap, void* U, void* V, int f64, hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    const unsigned grid = (unsigned)(nblocks < 65536 * 16 ? nblocks : 65536 * 16);
+    if (f64)
+        hipLaunchKernelGGL(compact_kernel<double>, dim3(grid), dim3(256), 0, st, blocks, nblocks,
+                           rank, cap_uoff, cap_voff, uoff, voff, (const double*)Ucap,
+                           (const double*)Vcap, (double*)U, (double*)V);
+    else
+        hipLaunchKernelGGL(compact_kernel<float>, dim3(grid), dim3(256), 0, st, blocks, nblocks,
+                           rank, cap_uoff, cap_voff, uoff, voff, (const float*)Ucap,
+                           (const float*)Vcap, (float*)U, (float*)V);
+    return hipGetLastError();
+}
+
+}  // namespace hmx

@@ -1,0 +1,254 @@
+"""Python binding of the libhmx C ABI (``include/hmx.h``).
+
+Argument marshalling only: every step of the build and the matvec runs in the
+HIP kernels of ``libhmx.so``.  PyTorch supplies device memory (tensors) and
+streams.  The functions carry the C names; ``HMatrix`` is a small owner of a
+handle.  There is no CPU fallback: if the library is missing this module
+raises on import of the library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhmx.so")
+
+HMX_OK, HMX_ERR_INVALID_ARG, HMX_ERR_OOM, HMX_ERR_DEVICE, HMX_ERR_NOT_CONVERGED, \
+    HMX_ERR_UNSUPPORTED = range(6)
+HMX_F64, HMX_F32, HMX_BF16 = 0, 1, 2
+HMX_GAUSSIAN, HMX_MATERN32, HMX_TEST_CONST, HMX_TEST_LOWRANK = 0, 1, 3, 4
+HMX_RANK_ADAPTIVE, HMX_RANK_FIXED = 0, 2
+KERNELS = {"gaussian": HMX_GAUSSIAN, "matern32": HMX_MATERN32, "const": HMX_TEST_CONST,
+           "lowrank": HMX_TEST_LOWRANK}
+DTYPES = {"f64": HMX_F64, "f32": HMX_F32, "bf16": HMX_BF16}
+
+# every symbol declared in include/hmx.h
+EXPORTS = ["hmx_params_default", "hmx_build", "hmx_matvec", "hmx_get_partition",
+           "hmx_get_boxes", "hmx_get_ranks", "hmx_get_factors", "hmx_get_stats",
+           "hmx_destroy", "hmx_status_string", "hmx_last_error"]
+
+
+class hmx_kernel(C.Structure):
+    _fields_ = [("kind", C.c_int), ("p0", C.c_double), ("p1", C.c_double)]
+
+
+class hmx_params(C.Structure):
+    _fields_ = [("leaf_size", C.c_int32), ("eta", C.c_double), ("aca_eps", C.c_double),
+                ("aca_eta", C.c_double), ("aca_eps0", C.c_double), ("max_rank", C.c_int32),
+                ("sigma2", C.c_double), ("compute_dtype", C.c_int), ("rank_mode", C.c_int),
+                ("reserved", C.c_int32 * 8)]
+
+
+class hmx_stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("d", C.c_int32), ("levels", C.c_int32),
+                ("n_adm", C.c_int64), ("n_dense", C.c_int64), ("n_tiles", C.c_int64),
+                ("sum_rank", C.c_int64), ("max_rank_used", C.c_int32),
+                ("reserved0", C.c_int32), ("factor_entries", C.c_int64),
+                ("near_entries", C.c_int64), ("aca_columns", C.c_int64),
+                ("matvec_bytes", C.c_double), ("phase_ms", C.c_double * 8),
+                ("device_bytes", C.c_int64), ("level_sizes", C.c_int64 * 64)]
+
+
+class HmxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("hmx status %d (%s): %s" % (status, _status_name(status), msg))
+        self.status = status
+
+
+def _status_name(s):
+    return ["ok", "invalid argument", "out of device memory", "device error",
+            "not converged", "unsupported"][s] if 0 <= s < 6 else "unknown"
+
+
+_lib = None
+
+
+def lib():
+    """Load libhmx.so (import torch first so both share one HIP runtime)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libhmx.so is not built (%s); run __graft_entry__.build()"
+                               % LIB_PATH)
+        try:
+            import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.hmx_params_default.argtypes = [C.POINTER(hmx_params)]
+        L.hmx_build.argtypes = [P, C.c_int, i64, i32, C.POINTER(hmx_kernel),
+                                C.POINTER(hmx_params), P, C.POINTER(P)]
+        L.hmx_matvec.argtypes = [P, P, P, C.c_int, f64, f64, P]
+        L.hmx_get_partition.argtypes = [P, P, P, P, C.POINTER(i64), P, C.POINTER(i64), P]
+        L.hmx_get_boxes.argtypes = [P, P, P, P]
+        L.hmx_get_ranks.argtypes = [P, P, P]
+        L.hmx_get_factors.argtypes = [P, i64, P, P, C.POINTER(i32), P]
+        L.hmx_get_stats.argtypes = [P, C.POINTER(hmx_stats)]
+        L.hmx_destroy.argtypes = [P]
+        L.hmx_status_string.restype = C.c_char_p
+        L.hmx_status_string.argtypes = [C.c_int]
+        L.hmx_last_error.restype = C.c_char_p
+        L.hmx_last_error.argtypes = []
+        for name in EXPORTS:
+            getattr(L, name).restype = getattr(L, name).restype if name in (
+                "hmx_status_string", "hmx_last_error") else C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != HMX_OK:
+        raise HmxError(status, lib().hmx_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _dtype_of(t):
+    import torch
+    if t.dtype == torch.float64:
+        return HMX_F64
+    if t.dtype == torch.float32:
+        return HMX_F32
+    if t.dtype == torch.bfloat16:
+        return HMX_BF16
+    raise TypeError("unsupported dtype %s" % t.dtype)
+
+
+def hmx_params_default(**overrides) -> hmx_params:
+    p = hmx_params()
+    _check(lib().hmx_params_default(C.byref(p)))
+    for k, v in overrides.items():
+        if k == "compute_dtype" and isinstance(v, str):
+            v = DTYPES[v]
+        setattr(p, k, v)
+    return p
+
+
+def make_kernel(kind, p0=1.0) -> hmx_kernel:
+    return hmx_kernel(KERNELS[kind] if isinstance(kind, str) else int(kind), float(p0), 0.0)
+
+
+def hmx_build(points, kernel: hmx_kernel, params: hmx_params, stream=None):
+    """points: contiguous CUDA tensor (n, d) float64/float32.  Returns a handle."""
+    if not points.is_cuda or not points.is_contiguous() or points.dim() != 2:
+        raise ValueError("points must be a contiguous (n, d) device tensor")
+    h = C.c_void_p()
+    _check(lib().hmx_build(C.c_void_p(points.data_ptr()), _dtype_of(points), points.shape[0],
+                           points.shape[1], C.byref(kernel), C.byref(params), _stream(stream),
+                           C.byref(h)))
+    return h
+
+
+def hmx_matvec(h, x, z, alpha=1.0, beta=0.0, stream=None):
+    if not (x.is_cuda and z.is_cuda and x.is_contiguous() and z.is_contiguous()):
+        raise ValueError("x and z must be contiguous device tensors")
+    _check(lib().hmx_matvec(h, C.c_void_p(x.data_ptr()), C.c_void_p(z.data_ptr()), _dtype_of(x),
+                            float(alpha), float(beta), _stream(stream)))
+
+
+def hmx_get_stats(h) -> hmx_stats:
+    s = hmx_stats()
+    _check(lib().hmx_get_stats(h, C.byref(s)))
+    return s
+
+
+def hmx_get_partition(h, stream=None):
+    s = hmx_get_stats(h)
+    n = s.n
+    codes = np.empty(n, np.uint64)
+    perm = np.empty(n, np.int32)
+    na, nd = C.c_int64(s.n_adm), C.c_int64(s.n_dense)
+    adm = np.empty((max(s.n_adm, 1), 5), np.int32)
+    den = np.empty((max(s.n_dense, 1), 5), np.int32)
+    _check(lib().hmx_get_partition(h, codes.ctypes.data_as(C.c_void_p),
+                                   perm.ctypes.data_as(C.c_void_p), adm.ctypes.data_as(C.c_void_p),
+                                   C.byref(na), den.ctypes.data_as(C.c_void_p), C.byref(nd),
+                                   _stream(stream)))
+    return dict(codes=codes, perm=perm, adm=adm[: na.value].copy(), dense=den[: nd.value].copy(),
+                level_sizes=np.array(s.level_sizes[: s.levels], np.int64))
+
+
+def hmx_get_boxes(h, stream=None):
+    s = hmx_get_stats(h)
+    d = s.d
+    gb = np.empty(2 * d)
+    lb = np.empty((s.n_tiles, 2 * d + 2))
+    _check(lib().hmx_get_boxes(h, gb.ctypes.data_as(C.c_void_p), lb.ctypes.data_as(C.c_void_p),
+                               _stream(stream)))
+    return gb[:d].copy(), gb[d:].copy(), lb
+
+
+def hmx_get_ranks(h, stream=None):
+    s = hmx_get_stats(h)
+    r = np.zeros(max(s.n_adm, 1), np.int32)
+    _check(lib().hmx_get_ranks(h, r.ctypes.data_as(C.c_void_p), _stream(stream)))
+    return r[: s.n_adm].copy()
+
+
+def hmx_get_factors(h, leaf: int, m: int, n: int, kmax: int, stream=None):
+    U = np.zeros(m * kmax)
+    V = np.zeros(n * kmax)
+    r = C.c_int32(0)
+    _check(lib().hmx_get_factors(h, int(leaf), U.ctypes.data_as(C.c_void_p),
+                                 V.ctypes.data_as(C.c_void_p), C.byref(r), _stream(stream)))
+    k = r.value
+    return U[: k * m].reshape(k, m).T.copy(), V[: k * n].reshape(k, n).T.copy(), k
+
+
+def hmx_destroy(h):
+    if h:
+        _check(lib().hmx_destroy(h))
+
+
+class HMatrix:
+    """Owner of an hmx handle built from device points."""
+
+    def __init__(self, points, kernel="gaussian", p0=1.0, stream=None, **params):
+        self.params = hmx_params_default(**params)
+        self.kernel = make_kernel(kernel, p0)
+        self.n, self.d = int(points.shape[0]), int(points.shape[1])
+        self.h = hmx_build(points, self.kernel, self.params, stream)
+
+    def matvec(self, x, z=None, alpha=1.0, beta=0.0, stream=None):
+        import torch
+        if z is None:
+            z = torch.empty_like(x)
+        hmx_matvec(self.h, x, z, alpha, beta, stream)
+        return z
+
+    def stats(self):
+        return hmx_get_stats(self.h)
+
+    def partition(self):
+        return hmx_get_partition(self.h)
+
+    def ranks(self):
+        return hmx_get_ranks(self.h)
+
+    def close(self):
+        if self.h:
+            hmx_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

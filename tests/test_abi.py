@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol
+include/hmx.h declares, the ctypes structs match the C layout, and argument
+validation happens before any device work.  CPU only (no compute calls)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hmx.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(hmx_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1708_09707_amd import hmx
+    L = hmx.lib()
+    names = _declared()
+    assert len(names) >= 10
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert sorted(hmx.EXPORTS) == names
+
+
+def test_struct_layout_matches_c(tmp_path):
+    from paper_1708_09707_amd import hmx
+    prog = tmp_path / "layout.c"
+    prog.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "hmx.h"
+int main(void) {
+  printf("%zu %zu %zu\\n", sizeof(hmx_params), sizeof(hmx_stats), sizeof(hmx_kernel));
+  printf("%zu %zu %zu %zu\\n", offsetof(hmx_params, max_rank), offsetof(hmx_params, sigma2),
+         offsetof(hmx_params, rank_mode), offsetof(hmx_params, reserved));
+  printf("%zu %zu %zu\\n", offsetof(hmx_stats, matvec_bytes), offsetof(hmx_stats, device_bytes),
+         offsetof(hmx_stats, level_sizes));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(prog),
+                           "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split()
+    want = [C.sizeof(hmx.hmx_params), C.sizeof(hmx.hmx_stats), C.sizeof(hmx.hmx_kernel),
+            hmx.hmx_params.max_rank.offset, hmx.hmx_params.sigma2.offset,
+            hmx.hmx_params.rank_mode.offset, hmx.hmx_params.reserved.offset,
+            hmx.hmx_stats.matvec_bytes.offset, hmx.hmx_stats.device_bytes.offset,
+            hmx.hmx_stats.level_sizes.offset]
+    assert [int(v) for v in out] == want
+
+
+def test_defaults_and_status_strings():
+    from paper_1708_09707_amd import hmx
+    p = hmx.hmx_params_default()
+    assert (p.leaf_size, p.eta, p.aca_eps, p.max_rank, p.compute_dtype) == (256, 1.5, 1e-5, 64,
+                                                                          hmx.HMX_F32)
+    L = hmx.lib()
+    assert L.hmx_status_string(0) == b"ok"
+    assert L.hmx_status_string(2) == b"out of device memory"
+
+
+def test_validation_before_device_work():
+    """Invalid arguments are rejected on the host, without touching a device."""
+    from paper_1708_09707_amd import hmx
+    L = hmx.lib()
+    h = C.c_void_p()
+    K = hmx.make_kernel("gaussian", 0.1)
+    P = hmx.hmx_params_default()
+    dummy = C.c_void_p(1)  # never dereferenced: validation fails first
+    assert L.hmx_build(None, 0, 10, 2, C.byref(K), C.byref(P), None, C.byref(h)) == 1
+    assert L.hmx_build(dummy, 0, 0, 2, C.byref(K), C.byref(P), None, C.byref(h)) == 1
+    assert L.hmx_build(dummy, 0, 10, 4, C.byref(K), C.byref(P), None, C.byref(h)) == 1
+    assert L.hmx_build(dummy, 2, 10, 2, C.byref(K), C.byref(P), None, C.byref(h)) == 1
+    for field, val in [("leaf_size", 0), ("eta", -1.0), ("max_rank", 0), ("max_rank", 200),
+                       ("aca_eta", 1.5), ("sigma2", float("nan"))]:
+        Q = hmx.hmx_params_default(**{field: val})
+        assert L.hmx_build(dummy, 0, 10, 2, C.byref(K), C.byref(Q), None, C.byref(h)) == 1, field
+        assert b"invalid params" in L.hmx_last_error()
+    Q = hmx.hmx_params_default(compute_dtype=hmx.HMX_BF16)
+    assert L.hmx_build(dummy, 0, 10, 2, C.byref(K), C.byref(Q), None, C.byref(h)) == 5
+    K0 = hmx.make_kernel("gaussian", 0.0)
+    assert L.hmx_build(dummy, 0, 10, 2, C.byref(K0), C.byref(P), None, C.byref(h)) == 1
+    assert not h.value
+    assert L.hmx_matvec(None, dummy, dummy, 1, 1.0, 0.0, None) == 1
+    assert L.hmx_destroy(None) == 0

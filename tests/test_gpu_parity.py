@@ -1,0 +1,268 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Ordering, boxes and the block partition must match bit for bit; the matvec
+must match the FP64 dense product within the stated tolerance
+e_rel <= 10 eps_ACA + 4 u_storage (u = 2^-53 for F64, 2^-24 for F32), and
+the oracle's H-matrix-vector product within the same bound.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def H():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1708_09707_amd import hmx
+    hmx.lib()
+    return hmx
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _tol(eps, dtype):
+    return 10 * eps + 4 * (2.0 ** -53 if dtype == "f64" else 2.0 ** -24)
+
+
+def _build(H, pts, kernel="gaussian", p0=0.1, dtype="f64", pts_dtype=np.float64, **kw):
+    print("build: n=%d d=%d kernel=%s p0=%g dtype=%s %s" % (pts.shape[0], pts.shape[1], kernel,
+                                                           p0, dtype, kw), flush=True)
+    return H.HMatrix(_dev(pts.astype(pts_dtype)), kernel, p0, compute_dtype=dtype, **kw)
+
+
+CASES = [
+    # n, d, leaf, eta, pts dtype
+    (4096, 2, 64, 1.5, np.float64),
+    (5000, 3, 50, 1.5, np.float64),
+    (12345, 2, 100, 2.0, np.float32),
+    (3001, 1, 16, 1.0, np.float64),
+    (20000, 3, 128, 1.5, np.float32),
+    (1, 2, 8, 1.5, np.float64),
+    (2, 3, 1, 1.5, np.float64),
+    (300, 2, 300, 1.5, np.float64),
+    (777, 2, 7, 0.0, np.float64),
+]
+
+
+@pytest.mark.parametrize("n,d,leaf,eta,pdt", CASES)
+def test_ordering_and_partition_bit_exact(H, orc, n, d, leaf, eta, pdt):
+    pts = synth.uniform_points(n, d, 1000 + n + d, dtype=pdt)
+    hm = _build(H, pts, dtype="f64", pts_dtype=pdt, leaf_size=leaf, eta=eta)
+    part = hm.partition()
+    p64 = pts.astype(np.float64)
+    codes, perm, soa = orc.order(p64)
+    assert np.array_equal(part["codes"], codes)
+    assert np.array_equal(part["perm"], perm)
+    lo, hi, lb = H.hmx_get_boxes(hm.h)
+    olo, ohi = orc.global_box(p64)
+    assert np.array_equal(lo, olo) and np.array_equal(hi, ohi)
+    # leaf-cluster boxes against the oracle's brute-force boxes
+    clo, chi, _, ch = orc.cluster_tree(n, leaf)
+    leaves = np.where(ch < 0)[0]
+    order = np.argsort(clo[leaves])
+    bmin, bmax = orc.boxes(soa, clo[leaves][order], chi[leaves][order])
+    assert lb.shape[0] == len(leaves)
+    assert np.array_equal(lb[:, 2 * d], clo[leaves][order])
+    assert np.array_equal(lb[:, :d], bmin) and np.array_equal(lb[:, d:2 * d], bmax)
+    adm, den, ls = orc.partition(soa, leaf, eta)
+    assert np.array_equal(part["adm"], adm)
+    assert np.array_equal(part["dense"], den)
+    assert np.array_equal(part["level_sizes"], ls)
+    hm.close()
+
+
+def test_identical_points_single_rank_one_block(H, orc):
+    pts = np.full((1000, 2), 0.25)
+    hm = _build(H, pts, leaf_size=16, eta=1.5, aca_eps=1e-8)
+    part = hm.partition()
+    assert np.array_equal(part["perm"], np.arange(1000))
+    assert part["adm"].tolist() == [[0, 1000, 0, 1000, 0]] and len(part["dense"]) == 0
+    assert hm.ranks().tolist() == [1]
+    x = synth.normal_vector(1000, 3)
+    z = hm.matvec(_dev(x)).cpu().numpy()
+    assert np.allclose(z, x.sum(), rtol=1e-12, atol=1e-11)
+    hm.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_small_workload_matvec(H, orc, dtype):
+    """N=4096 uniform in [0,1]^2, Gaussian p0=0.1, leaf 64, eta 1.5, eps 1e-6,
+    kmax 32: against the FP64 dense product and the oracle's H-MVP."""
+    pts = synth.uniform_points(4096, 2, 11)
+    x = synth.normal_vector(4096, 12)
+    eps = 1e-6
+    hm = _build(H, pts, "gaussian", 0.1, dtype, leaf_size=64, eta=1.5, aca_eps=eps, max_rank=32)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    z = hm.matvec(_dev(x).to(tdt)).double().cpu().numpy()
+    zd = orc.dense_matvec(pts, x, "gaussian", 0.1)
+    err = np.linalg.norm(z - zd) / np.linalg.norm(zd)
+    zo, ranks_o, st = orc.hmvp(pts, x, "gaussian", 0.1, 64, 1.5, 32, eps, want_ranks=True)
+    err_o = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    print("rel err vs dense %.3e, vs oracle %.3e" % (err, err_o))
+    tol = _tol(eps, dtype) if dtype == "f64" else 1e-5
+    assert err <= tol and err_o <= tol
+    ranks = hm.ranks()
+    s = hm.stats()
+    assert s.n_adm == st["n_adm"] and s.n_dense == st["n_dense"]
+    if dtype == "f64":
+        # same arithmetic up to summation order: ranks agree almost everywhere
+        assert np.mean(ranks == ranks_o) >= 0.95
+        assert np.abs(ranks.astype(int) - ranks_o).max() <= 2
+    assert s.near_entries == st["dense_entries"]
+    hm.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_aca_block_errors(H, orc, dtype):
+    pts = synth.uniform_points(6000, 3, 21)
+    eps = 1e-5 if dtype == "f32" else 1e-8
+    hm = _build(H, pts, "gaussian", 0.05, dtype, leaf_size=64, eta=1.5, aca_eps=eps, max_rank=64)
+    part = hm.partition()
+    _, _, soa = orc.order(pts)
+    rng = np.random.default_rng(3)
+    adm = part["adm"]
+    picks = rng.choice(len(adm), 25, replace=False)
+    for q in picks:
+        b = adm[q]
+        m, n = b[1] - b[0], b[3] - b[2]
+        U, V, r = H.hmx_get_factors(hm.h, int(q), m, n, 64)
+        A = orc.dense_block(soa, "gaussian", 0.05, *b[:4])
+        err = np.linalg.norm(A - U @ V.T) / np.linalg.norm(A)
+        assert err <= 10 * eps + 1e-5 * (dtype == "f32"), (q, r, err)
+        s = np.linalg.svd(A, compute_uv=False)
+        assert r >= 1 and np.linalg.norm(A - U @ V.T) >= np.sqrt((s[r:] ** 2).sum()) * (1 - 1e-6) - 1e-12
+    hm.close()
+
+
+def test_special_cases_reduce_to_dense(H, orc):
+    pts = synth.uniform_points(3000, 2, 5)
+    x = synth.normal_vector(3000, 6)
+    zd = orc.dense_matvec(pts, x, "matern32", 0.2)
+    # eta = 0: no admissible block, the H-matrix is the dense matrix
+    hm = _build(H, pts, "matern32", 0.2, "f64", leaf_size=40, eta=0.0)
+    assert hm.stats().n_adm == 0
+    z = hm.matvec(_dev(x)).cpu().numpy()
+    assert np.linalg.norm(z - zd) <= 1e-13 * np.linalg.norm(zd)
+    hm.close()
+    # leaf >= n: a single dense block
+    hm = _build(H, pts, "matern32", 0.2, "f64", leaf_size=3000, eta=1.5)
+    z = hm.matvec(_dev(x)).cpu().numpy()
+    assert np.linalg.norm(z - zd) <= 1e-13 * np.linalg.norm(zd)
+    hm.close()
+    # k_max >= every admissible block side and eps = 0: ACA is exact
+    pts, x = pts[:1000].copy(), x[:1000].copy()
+    zd = orc.dense_matvec(pts, x, "matern32", 0.2)
+    hm = _build(H, pts, "matern32", 0.2, "f64", leaf_size=16, eta=1.5, aca_eps=0.0,
+                aca_eps0=0.0, max_rank=128)
+    adm = hm.partition()["adm"]
+    assert len(adm) > 0 and (adm[:, 1] - adm[:, 0]).max() <= 128
+    z = hm.matvec(_dev(x)).cpu().numpy()
+    assert np.linalg.norm(z - zd) <= 1e-10 * np.linalg.norm(zd)
+    hm.close()
+
+
+def test_const_and_lowrank_kernels(H, orc):
+    pts = synth.uniform_points(5000, 3, 7)
+    x = synth.normal_vector(5000, 8)
+    hm = _build(H, pts, "const", 1.0, "f64", leaf_size=64, eta=1.5, aca_eps=1e-8, max_rank=8)
+    assert np.all(hm.ranks() == 1)
+    z = hm.matvec(_dev(x)).cpu().numpy()
+    assert np.allclose(z, x.sum(), rtol=0, atol=1e-10)
+    hm.close()
+    hm = _build(H, pts, "lowrank", 1.0, "f64", leaf_size=64, eta=1.5, aca_eps=0.0,
+                aca_eps0=1e-9, max_rank=32)
+    assert hm.ranks().max() <= 10
+    z = hm.matvec(_dev(x)).cpu().numpy()
+    zd = orc.dense_matvec(pts, x, "lowrank", 1.0)
+    assert np.linalg.norm(z - zd) <= 1e-11 * np.linalg.norm(zd)
+    hm.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_alpha_beta_sigma(H, orc, dtype):
+    pts = synth.uniform_points(2500, 2, 9)
+    x = synth.normal_vector(2500, 10)
+    z0 = synth.normal_vector(2500, 11)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    hm = _build(H, pts, "gaussian", 0.05, dtype, leaf_size=32, eta=1.5, aca_eps=1e-7,
+                sigma2=0.3)
+    base = hm.matvec(_dev(x).to(tdt)).double().cpu().numpy()
+    z = _dev(z0).to(tdt)
+    hm.matvec(_dev(x).to(tdt), z, alpha=2.0, beta=-0.5)
+    z = z.double().cpu().numpy()
+    rt = 1e-12 if dtype == "f64" else 1e-5
+    assert np.allclose(z, 2.0 * base - 0.5 * z0, rtol=rt, atol=rt * np.abs(base).max())
+    zo, _, _ = orc.hmvp(pts, x, "gaussian", 0.05, 32, 1.5, 64, 1e-7, sigma2=0.3)
+    assert np.linalg.norm(base - zo) <= _tol(1e-7, dtype) * 10 * np.linalg.norm(zo)
+    hm.close()
+
+
+def test_determinism(H):
+    pts = synth.uniform_points(30000, 2, 13)
+    x = _dev(synth.normal_vector(30000, 14)).float()
+    outs = []
+    for _ in range(2):
+        hm = _build(H, pts, "gaussian", 0.01, "f32", leaf_size=128, eta=1.5, aca_eps=1e-5)
+        p = hm.partition()
+        outs.append((p["adm"], p["dense"], hm.ranks(), hm.matvec(x).cpu().numpy()))
+        hm.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
+def test_invalid_arguments(H):
+    pts = _dev(synth.uniform_points(100, 2, 1))
+    K = H.make_kernel("gaussian", 0.1)
+    bad = [dict(leaf_size=0), dict(eta=-1.0), dict(aca_eps=-1.0), dict(max_rank=0),
+           dict(max_rank=129), dict(aca_eta=1.0), dict(sigma2=-1.0)]
+    for kw in bad:
+        with pytest.raises(H.HmxError) as e:
+            H.hmx_build(pts, K, H.hmx_params_default(**kw))
+        assert e.value.status == H.HMX_ERR_INVALID_ARG
+    nanpts = synth.uniform_points(100, 2, 1)
+    nanpts[17, 1] = np.nan
+    with pytest.raises(H.HmxError) as e:
+        H.hmx_build(_dev(nanpts), K, H.hmx_params_default())
+    assert e.value.status == H.HMX_ERR_INVALID_ARG
+    with pytest.raises(H.HmxError):
+        H.hmx_build(pts, H.make_kernel("gaussian", 0.0), H.hmx_params_default())
+    with pytest.raises(H.HmxError):
+        H.hmx_build(_dev(synth.uniform_points(10, 4, 1)), K, H.hmx_params_default())
+    # vector dtype must match the compute dtype
+    hm = H.HMatrix(pts, "gaussian", 0.1, compute_dtype="f32", leaf_size=16)
+    with pytest.raises(H.HmxError):
+        hm.matvec(torch.zeros(100, dtype=torch.float64, device="cuda:0"))
+    hm.close()
+
+
+def test_full_size_partition_and_sampled_rows(H, orc):
+    """N = 2^20 uniform points in [0,1]^2, Gaussian p0 = 0.01, leaf 256,
+    eta 1.5, eps 1e-5, kmax 64, FP32: the launch configuration of the
+    benchmark.  Partition bit for bit; matvec on 256 sampled rows against the
+    FP64 dense product."""
+    n = 1 << 20
+    pts = synth.uniform_points(n, 2, 21, dtype=np.float32)
+    x = synth.normal_vector(n, 2200, dtype=np.float32)
+    hm = _build(H, pts, "gaussian", 0.01, "f32", pts_dtype=np.float32, leaf_size=256, eta=1.5,
+                aca_eps=1e-5, max_rank=64)
+    z = hm.matvec(_dev(x)).double().cpu().numpy()
+    part = hm.partition()
+    p64 = pts.astype(np.float64)
+    codes, perm, soa = orc.order(p64)
+    assert np.array_equal(part["codes"], codes) and np.array_equal(part["perm"], perm)
+    adm, den, ls = orc.partition(soa, 256, 1.5)
+    assert np.array_equal(part["adm"], adm) and np.array_equal(part["dense"], den)
+    rows = synth.sample_rows(n, 256, 77)
+    zr = orc.dense_matvec(p64, x.astype(np.float64), "gaussian", 0.01, rows=rows)
+    err = np.linalg.norm(z[rows] - zr) / np.linalg.norm(zr)
+    print("sampled-row rel err %.3e" % err)
+    assert err <= 1e-4
+    hm.close()

@@ -47,8 +47,8 @@ def test_aca_const_kernel_rank_one(orc):
     assert r == 1
     A = orc.dense_block(soa, "const", 1.0, *b[:4])
     assert np.abs(A - U @ V.T).max() <= 1e-14
-    # the eps0 guard rejects every further column: all columns were tried
-    assert steps == b[3] - b[2]
+    # the eps0 guard rejects every further column; kmax failed columns end it
+    assert steps == 1 + 16
 
 
 @pytest.mark.parametrize("d,maxrank", [(2, 6), (3, 10)])
@@ -100,8 +100,11 @@ def test_aca_pivot_structure(orc):
         assert np.all(U[i, l + 1:] == 0.0) or np.abs(U[i, l + 1:]).max() < 1e-12
     R = A - U @ V.T
     assert np.abs(R[piv_rows, :]).max() <= 1e-12 * np.abs(A).max()
-    # the first column pivot is column 0
-    assert np.abs(R[:, 0]).max() <= 1e-12 * np.abs(A).max()
+    # the first column pivot is the sigma point nearest to tau's box centre
+    c = 0.5 * (soa[:, b[0]:b[1]].min(1) + soa[:, b[0]:b[1]].max(1))
+    j1 = int(np.argmin(((soa[:, b[2]:b[3]] - c[:, None]) ** 2).sum(0)))
+    assert np.abs(R[:, j1]).max() <= 1e-12 * np.abs(A).max()
+    assert np.abs(U[:, 0] * V[j1, 0] - A[:, j1]).max() <= 1e-12 * np.abs(A).max()
 
 
 def test_aca_fixed_and_one_shot(orc):
