@@ -87,8 +87,9 @@ typedef struct {
     double aca_eta;          /* the (1 - eta) factor of Algorithm 2's stopping test,
                                 in [0, 1); default 0 (see the stopping test) */
     double aca_eps0;         /* a residual column whose largest entry is <= eps0
-                                adds no rank (Section 2.4); < 0 selects the
-                                default 1e-14 (F64) or 1e-7 (F32) */
+                                times the column's own largest |entry| adds no
+                                rank (Section 2.4); < 0 selects the default
+                                1e-14 (F64) or 1e-7 (F32) */
     int32_t max_rank;        /* k_max, 1..128 */
     double sigma2;           /* diagonal shift sigma^2 >= 0 of (A + sigma^2 I) */
     hmx_dtype compute_dtype; /* HMX_F64 or HMX_F32: kernel evaluation, factor and
@@ -106,8 +107,10 @@ typedef struct {
     int64_t n_tiles;          /* leaf clusters (row tiles of the matvec) */
     int64_t sum_rank;         /* sum of ACA ranks */
     int32_t max_rank_used;
-    int32_t reserved0;
+    int32_t entry_bytes;      /* bytes per stored factor / near-field entry */
     int64_t factor_entries;   /* sum_adm rank * (|tau| + |sigma|) */
+    int64_t u_entries;        /* sum_adm rank * |tau|   (U pool) */
+    int64_t v_entries;        /* sum_adm rank * |sigma| (V pool) */
     int64_t near_entries;     /* sum_dense |tau| * |sigma| */
     int64_t aca_columns;      /* ACA residual columns evaluated (incl. skipped) */
     double matvec_bytes;      /* algorithmic HBM bytes of one matvec (beta = 0) */
@@ -167,6 +170,17 @@ hmx_status hmx_get_factors(hmx_hmatrix h, int64_t leaf, double* U, double* V, in
                            void* stream);
 
 hmx_status hmx_get_stats(hmx_hmatrix h, hmx_stats* s);
+
+/* Per-phase matvec timing with HIP events (tracing).  After
+ * hmx_profile_begin(h, max_calls) every hmx_matvec on h records events on its
+ * stream around its three phases (gather of x, far-field phase 1, row tiles)
+ * for the first max_calls calls.  hmx_profile_end synchronises on the last
+ * recorded event, writes the summed milliseconds of each phase to ms[0..2]
+ * (host) and the number of recorded calls to *calls, and releases the
+ * events.  begin allocates the events (host-side HIP objects, no device
+ * memory); matvec itself still allocates nothing. */
+hmx_status hmx_profile_begin(hmx_hmatrix h, int32_t max_calls);
+hmx_status hmx_profile_end(hmx_hmatrix h, double* ms, int32_t* calls);
 
 /* Free every device buffer of the handle (synchronises the device). */
 hmx_status hmx_destroy(hmx_hmatrix h);

@@ -63,6 +63,8 @@ def lib():
                                 f64, f64, P, P, i64, P, P]
         L.hmxo_dense_matvec.argtypes = [P, i64, i32, i32, f64, f64, P, P, i64, P]
         L.hmxo_dense_block.argtypes = [P, i64, i32, i32, f64, i64, i64, i64, i64, P]
+        L.hmxo_hmvp_rows.argtypes = [P, i64, i32, i32, f64, i32, f64, i32, f64, f64, f64, i32,
+                                     i64, i64, P, P, P, P]
         L.hmxo_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -246,3 +248,22 @@ def dense_matvec(pts, x, kind, p0, sigma2=0.0, rows=None):
         lib().hmxo_dense_matvec(_p(pts), n, d, kind_of(kind), float(p0), float(sigma2), _p(x),
                                 _p(rows), rows.shape[0], _p(z))
     return z
+
+
+def hmvp_rows(pts, x, kind, p0, leaf, eta, kmax, eps, row_lo, row_hi, aca_eta=0.0, eps0=1e-14,
+              fixed=False):
+    """Stored-mode H x on Morton-order rows [row_lo, row_hi).  Returns
+    (z_rows in Morton order, perm, dict of times / stored entries)."""
+    pts = _f64(pts)
+    n, d = pts.shape
+    x = _f64(x)
+    z = np.zeros(row_hi - row_lo)
+    perm = np.empty(n, np.int32)
+    t = np.zeros(5)
+    rc = lib().hmxo_hmvp_rows(_p(pts), n, d, kind_of(kind), float(p0), int(leaf), float(eta),
+                              int(kmax), float(eps), float(aca_eta), float(eps0), int(bool(fixed)),
+                              int(row_lo), int(row_hi), _p(x), _p(z), _p(perm), _p(t))
+    if rc != 0:
+        raise ValueError("hmxo_hmvp_rows failed: %d" % rc)
+    return z, perm, dict(partition_s=t[0], build_s=t[1], apply_s=t[2], entries=t[3],
+                         blocks=int(t[4]))

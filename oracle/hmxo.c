@@ -431,9 +431,10 @@ int hmxo_partition(const double* soa, int64_t n, int32_t d, int32_t leaf, double
 /* pivoting.  Column pivots (left to the implementation by the paper): the  */
 /* first column is the sigma point nearest to the centre of tau's bounding  */
 /* box; later ones the largest entry of the last row residual among unused  */
-/* columns.  A column whose residual has no entry above eps0 adds no rank;  */
-/* the lowest unused column is tried next, and after kmax such failed       */
-/* columns the block stops.                                                 */
+/* columns.  A column whose residual has no entry (over unused rows) above */
+/* eps0 times the largest |entry| of the column itself adds no rank (the   */
+/* residual is zero or rounding noise); the lowest unused column is tried  */
+/* next, and after kmax such failed columns the block stops.               */
 /* ------------------------------------------------------------------------ */
 
 /* the sigma column whose point is nearest (squared distance, dimension
@@ -502,8 +503,10 @@ int hmxo_aca(const double* soa, int64_t n, int32_t d, int32_t kind, double p0, i
             continue;
         }
         /* residual column u^ = A[:, j] - sum_l u_l (v_l)_j */
+        double colmax = 0.0;
         for (int64_t i = 0; i < m; ++i) {
             double a = entry(soa, n, d, kind, p0, tlo + i, slo + j);
+            if (fabs(a) > colmax) colmax = fabs(a);
             for (int64_t l = 0; l < r; ++l) a -= U[l * m + i] * V[l * nc + j];
             uh[i] = a;
         }
@@ -518,7 +521,7 @@ int hmxo_aca(const double* soa, int64_t n, int32_t d, int32_t kind, double p0, i
                 best = fabs(uh[i]);
                 ip = i;
             }
-        if (ip < 0 || best <= eps0) {
+        if (ip < 0 || best <= eps0 * colmax) {
             ++nfailed;
             if (ncols_used >= nc || nfailed >= kmax) break;
             int64_t q = 0;
@@ -693,5 +696,159 @@ int hmxo_dense_matvec(const double* pts, int64_t n, int32_t d, int32_t kind, dou
         for (int64_t j = 0; j < n; ++j) acc += hmxo_kernel(kind, p0, pts + i * d, pts + j * d, d) * x[j];
         z[q] = acc + sigma2 * x[i];
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Stored-mode H-matrix-vector product restricted to the Morton-order rows  */
+/* [row_lo, row_hi): every leaf whose tau meets the range is built (ACA or  */
+/* dense entries) and stored, then applied.  z receives (H x)_k for the     */
+/* rows in Morton order.  times: [order+partition s, build s, apply s,      */
+/* stored entries, blocks].  Used as a bounded CPU sample of a workload.    */
+/* ------------------------------------------------------------------------ */
+#include <time.h>
+
+static double now_s(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+typedef struct {
+    int64_t tlo, thi, slo, shi, r0, r1; /* block and the rows of it kept */
+    int32_t adm, rank;
+    double *U, *V, *A;
+} stored_block;
+
+int hmxo_hmvp_rows(const double* pts, int64_t n, int32_t d, int32_t kind, double p0,
+                   int32_t leaf, double eta, int32_t kmax, double eps, double aca_eta,
+                   double eps0, int32_t fixed, int64_t row_lo, int64_t row_hi, const double* x,
+                   double* z, int32_t* perm_out, double* times)
+{
+    if (n < 1 || d < 1 || d > 3 || leaf < 1 || row_lo < 0 || row_hi > n || row_lo >= row_hi)
+        return -1;
+    double t0 = now_s();
+    double lo[3], hi[3];
+    hmxo_global_box(pts, n, d, lo, hi);
+    uint64_t* codes = (uint64_t*)malloc(sizeof(uint64_t) * n);
+    int32_t* perm = (int32_t*)malloc(sizeof(int32_t) * n);
+    double* soa = (double*)malloc(sizeof(double) * n * d);
+    double* xm = (double*)malloc(sizeof(double) * n);
+    if (!codes || !perm || !soa || !xm) return -2;
+    hmxo_morton(pts, n, d, lo, hi, codes);
+    hmxo_sort(codes, n, perm);
+    hmxo_ordered_coords(pts, n, d, perm, soa);
+    for (int64_t k = 0; k < n; ++k) xm[k] = x[perm[k]];
+    if (perm_out)
+        for (int64_t k = 0; k < n; ++k) perm_out[k] = perm[k];
+    ctree T;
+    if (ctree_make(&T, soa, n, d, leaf)) return -2;
+    partition P;
+    if (part_make(&P, &T, d, leaf, eta)) return -3;
+    /* blocks meeting the rows */
+    int64_t nb = 0;
+    stored_block* B = (stored_block*)malloc(sizeof(stored_block) * (P.adm.n + P.dense.n + 1));
+    for (int pass = 0; pass < 2; ++pass) {
+        pairlist* L = pass == 0 ? &P.adm : &P.dense;
+        for (int64_t q = 0; q < L->n; ++q) {
+            int64_t t = L->a[2 * q], s = L->a[2 * q + 1];
+            int64_t a = T.lo[t], b = T.hi[t];
+            if (b <= row_lo || a >= row_hi) continue;
+            stored_block* sb = &B[nb++];
+            sb->tlo = a;
+            sb->thi = b;
+            sb->slo = T.lo[s];
+            sb->shi = T.hi[s];
+            sb->r0 = a > row_lo ? a : row_lo;
+            sb->r1 = b < row_hi ? b : row_hi;
+            sb->adm = pass == 0;
+            sb->rank = 0;
+            sb->U = sb->V = sb->A = NULL;
+        }
+    }
+    double t1 = now_s();
+    double entries = 0.0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : entries)
+    for (int64_t q = 0; q < nb; ++q) {
+        stored_block* sb = &B[q];
+        int64_t m = sb->thi - sb->tlo, nc = sb->shi - sb->slo, mr = sb->r1 - sb->r0;
+        if (sb->adm) {
+            double* U = (double*)malloc(sizeof(double) * m * kmax);
+            double* V = (double*)malloc(sizeof(double) * nc * kmax);
+            int32_t rk = 0;
+            hmxo_aca(soa, n, d, kind, p0, sb->tlo, sb->thi, sb->slo, sb->shi, kmax, eps, aca_eta,
+                     eps0, fixed, 0, U, V, &rk, NULL);
+            /* keep the rows of U in the range */
+            sb->U = (double*)malloc(sizeof(double) * (mr * rk + 1));
+            for (int64_t l = 0; l < rk; ++l)
+                for (int64_t i = 0; i < mr; ++i) sb->U[l * mr + i] = U[l * m + (sb->r0 - sb->tlo) + i];
+            sb->V = V;
+            sb->rank = rk;
+            free(U);
+            entries += (double)rk * (double)(mr + nc);
+        } else {
+            sb->A = (double*)malloc(sizeof(double) * mr * nc);
+            for (int64_t jj = 0; jj < nc; ++jj)
+                for (int64_t i = 0; i < mr; ++i)
+                    sb->A[jj * mr + i] = entry(soa, n, d, kind, p0, sb->r0 + i, sb->slo + jj);
+            entries += (double)mr * (double)nc;
+        }
+    }
+    double t2 = now_s();
+    const int64_t nr = row_hi - row_lo;
+    int nthr = hmxo_num_threads();
+    double* zp = (double*)calloc((size_t)nthr * (size_t)nr, sizeof(double));
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double* zt = zp + (int64_t)tid * nr;
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t q = 0; q < nb; ++q) {
+            stored_block* sb = &B[q];
+            int64_t nc = sb->shi - sb->slo, mr = sb->r1 - sb->r0, off = sb->r0 - row_lo;
+            if (sb->adm) {
+                for (int64_t l = 0; l < sb->rank; ++l) {
+                    double tl = 0.0;
+                    for (int64_t jj = 0; jj < nc; ++jj) tl += sb->V[l * nc + jj] * xm[sb->slo + jj];
+                    for (int64_t i = 0; i < mr; ++i) zt[off + i] += sb->U[l * mr + i] * tl;
+                }
+            } else {
+                for (int64_t jj = 0; jj < nc; ++jj) {
+                    double xv = xm[sb->slo + jj];
+                    for (int64_t i = 0; i < mr; ++i) zt[off + i] += sb->A[jj * mr + i] * xv;
+                }
+            }
+        }
+    }
+    for (int64_t i = 0; i < nr; ++i) {
+        double acc = 0.0;
+        for (int th = 0; th < nthr; ++th) acc += zp[(int64_t)th * nr + i];
+        z[i] = acc;
+    }
+    double t3 = now_s();
+    if (times) {
+        times[0] = t1 - t0;
+        times[1] = t2 - t1;
+        times[2] = t3 - t2;
+        times[3] = entries;
+        times[4] = (double)nb;
+    }
+    for (int64_t q = 0; q < nb; ++q) {
+        free(B[q].U);
+        free(B[q].V);
+        free(B[q].A);
+    }
+    free(B);
+    free(zp);
+    part_free(&P);
+    ctree_free(&T);
+    free(codes);
+    free(perm);
+    free(soa);
+    free(xm);
     return 0;
 }

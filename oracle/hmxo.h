@@ -60,8 +60,9 @@ int hmxo_partition(const double* soa, int64_t n, int32_t d, int32_t leaf, double
 
 /* Algorithm 2 on the block tau x sigma = [tlo,thi) x [slo,shi) of the
  * Morton-ordered matrix.  First column: the sigma point nearest to the centre
- * of tau's bounding box; a column without a residual entry above eps0 adds no
- * rank, the lowest unused column follows, and kmax such columns end the block.
+ * of tau's bounding box; a column without a residual entry above eps0 times
+ * the column's own largest |entry| adds no rank, the lowest unused column
+ * follows, and kmax such columns end the block.
  * U is m x kmax and V is n x kmax, column-major.  fixed != 0 skips the stopping test (fixed rank).  r_start > 0 selects the
  * one-shot form: exactly min(r_start, R) steps, then the stopping test on the
  * last term; if it fails, continue adaptively.  *steps gets the number of
@@ -80,6 +81,16 @@ int hmxo_hmvp(const double* pts, int64_t n, int32_t d, int32_t kind, double p0,
               int32_t leaf, double eta, int32_t kmax, double eps, double aca_eta,
               double eps0, int32_t fixed, double sigma2, double alpha, double beta,
               const double* x, double* z, int64_t ranks_cap, int32_t* ranks, double* stats);
+
+/* Stored-mode product restricted to the Morton-order rows [row_lo, row_hi):
+ * the leaves whose tau meets the range are built (ACA / dense entries),
+ * stored and applied; z gets (H x) for those rows in Morton order (no shift).
+ * perm_out (optional, n) gets the permutation.  times (5 doubles): order +
+ * partition seconds, build seconds, apply seconds, stored entries, blocks. */
+int hmxo_hmvp_rows(const double* pts, int64_t n, int32_t d, int32_t kind, double p0,
+                   int32_t leaf, double eta, int32_t kmax, double eps, double aca_eta,
+                   double eps0, int32_t fixed, int64_t row_lo, int64_t row_hi, const double* x,
+                   double* z, int32_t* perm_out, double* times);
 
 /* brute-force dense product z_i = sum_j phi(y_i, y_j) x_j (+ sigma2 x_i) for
  * the listed rows (rows == NULL: all rows; then z has n entries, else nrows). */

@@ -106,6 +106,16 @@ struct hmx_hmatrix_s {
     DevBuf rank, steps, uoff, voff, toff, U, V, near_off, near;
     DevBuf pieces, tile_ptr, vecpool;
     hmx_stats stats{};
+    // matvec phase tracing (hmx_profile_begin / end)
+    std::vector<hipEvent_t> prof_events;
+    int32_t prof_max = 0, prof_calls = 0;
+
+    void prof_release() {
+        for (auto e : prof_events) (void)hipEventDestroy(e);
+        prof_events.clear();
+        prof_max = prof_calls = 0;
+    }
+    ~hmx_hmatrix_s() { prof_release(); }
 
     int64_t device_bytes() const {
         const DevBuf* all[] = {&codes,   &perm,      &soa64,         &soa32,   &node_lo, &node_hi,
@@ -385,6 +395,21 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
               "compact");
         check(hipStreamSynchronize(st), "compact sync");
         h->factor_entries = ue + ve;
+        S.u_entries = ue;
+        S.v_entries = ve;
+        // rank statistics (host copy of the per-block ranks and column counts)
+        std::vector<int32_t> rk(h->n_adm), stp(h->n_adm);
+        check(hipMemcpyAsync(rk.data(), h->rank.p, h->n_adm * 4, hipMemcpyDeviceToHost, st), "ranks");
+        check(hipMemcpyAsync(stp.data(), h->steps.p, h->n_adm * 4, hipMemcpyDeviceToHost, st), "steps");
+        check(hipStreamSynchronize(st), "stats sync");
+        int32_t mr = 0;
+        int64_t cols = 0;
+        for (int64_t b = 0; b < h->n_adm; ++b) {
+            mr = std::max(mr, rk[b]);
+            cols += stp[b];
+        }
+        S.max_rank_used = mr;
+        S.aca_columns = cols;
         S.phase_ms[4] = ms_since(t0);
     } else {
         alloc(h->U, 16, "U pool");
@@ -478,6 +503,7 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
     S.sum_rank = h->sum_rank;
     S.factor_entries = h->factor_entries;
     S.near_entries = h->near_entries;
+    S.entry_bytes = (int32_t)esz;
     S.phase_ms[7] = ms_since(t_all);
     // algorithmic bytes of one matvec with beta = 0: stored data once, the
     // vectors x and z once, perm for gather and scatter, t written and read
@@ -608,16 +634,22 @@ hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype
     }
     hipStream_t st = (hipStream_t)stream;
     const int f64 = h->f64;
-    hipError_t e = launch_gather_x(x, h->perm.as<int32_t>(), h->n, h->vecpool.p, f64, st);
+    hipEvent_t* ev = nullptr;
+    if (h->prof_calls < h->prof_max) ev = &h->prof_events[4 * h->prof_calls++];
+    hipError_t e = ev ? hipEventRecord(ev[0], st) : hipSuccess;
+    if (e == hipSuccess) e = launch_gather_x(x, h->perm.as<int32_t>(), h->n, h->vecpool.p, f64, st);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
     if (e == hipSuccess)
         e = launch_far_phase1(h->adm.as<int4>(), h->n_adm, h->rank.as<int32_t>(),
                               h->voff.as<int64_t>(), h->toff.as<int64_t>(), h->V.p, h->vecpool.p,
                               h->n, f64, st);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
     if (e == hipSuccess)
         e = launch_rowtile(h->ntiles, h->tile_lo.as<int32_t>(), h->tile_ptr.as<int64_t>(),
                            h->pieces.as<Piece>(), h->near.p, h->U.p, h->vecpool.p,
                            h->perm.as<int32_t>(), h->n, alpha, beta, h->prm.sigma2, z,
                            h->max_tile, f64, st);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
     if (e != hipSuccess) {
         set_err("matvec launch: %s", hipGetErrorString(e));
         return HMX_ERR_DEVICE;
@@ -784,6 +816,52 @@ hmx_status hmx_get_stats(hmx_hmatrix h, hmx_stats* s) {
     }
     *s = h->stats;
     return HMX_OK;
+}
+
+hmx_status hmx_profile_begin(hmx_hmatrix h, int32_t max_calls) {
+    if (!h || max_calls < 0 || max_calls > (1 << 20)) {
+        set_err("invalid argument to hmx_profile_begin");
+        return HMX_ERR_INVALID_ARG;
+    }
+    h->prof_release();
+    h->prof_events.resize((size_t)4 * max_calls, nullptr);
+    for (auto& e : h->prof_events) {
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) {
+            e = nullptr;
+            h->prof_release();
+            set_err("hipEventCreate: %s", hipGetErrorString(r));
+            return HMX_ERR_DEVICE;
+        }
+    }
+    h->prof_max = max_calls;
+    h->prof_calls = 0;
+    return HMX_OK;
+}
+
+hmx_status hmx_profile_end(hmx_hmatrix h, double* ms, int32_t* calls) {
+    if (!h || !ms || !calls) {
+        set_err("invalid argument to hmx_profile_end");
+        return HMX_ERR_INVALID_ARG;
+    }
+    ms[0] = ms[1] = ms[2] = 0.0;
+    *calls = h->prof_calls;
+    hmx_status s = HMX_OK;
+    if (h->prof_calls > 0) {
+        hipError_t r = hipEventSynchronize(h->prof_events[4 * h->prof_calls - 1]);
+        for (int32_t c = 0; c < h->prof_calls && r == hipSuccess; ++c)
+            for (int p = 0; p < 3 && r == hipSuccess; ++p) {
+                float t = 0.f;
+                r = hipEventElapsedTime(&t, h->prof_events[4 * c + p], h->prof_events[4 * c + p + 1]);
+                ms[p] += t;
+            }
+        if (r != hipSuccess) {
+            set_err("event timing: %s", hipGetErrorString(r));
+            s = HMX_ERR_DEVICE;
+        }
+    }
+    h->prof_release();
+    return s;
 }
 
 hmx_status hmx_destroy(hmx_hmatrix h) {

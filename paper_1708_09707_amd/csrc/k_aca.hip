@@ -5,7 +5,8 @@
 // slowest block).  Per step r:
 //   1. residual column  u^ = A[:, j] - sum_{l<r} u_l (v_l)_j   (rows over threads)
 //   2. row pivot        i  = argmax over unused rows |u^_i| (lowest index on ties)
-//      a column whose largest residual entry is <= eps0 adds no rank; the
+//      a column whose largest residual entry is <= eps0 times the column's own
+//      largest |entry| adds no rank (zero or rounding-noise residual); the
 //      lowest unused column is tried next, and kmax such columns end the block
 //   3. u_r = u^ / u^_i,  v_r = A[i, :]^T - sum_{l<r} (u_l)_i v_l  (cols over threads)
 //   4. |S_r|_F^2 += 2 sum_{l<r} (u_r.u_l)(v_r.v_l) + |u_r|^2 |v_r|^2   in FP64
@@ -250,10 +251,13 @@ __global__ __launch_bounds__(kAcaThreads) void aca_kernel(
             T yj[3];
             load_pt(soa, n, d, (int64_t)bl.z + j, yj);
             Arg<T> am{(T)-1, INT_MAX, (T)0};
+            double colmax = 0.0;
             for (int i = tid; i < m; i += kAcaThreads) {
                 T xi[3];
                 load_pt(soa, n, d, (int64_t)bl.x + i, xi);
                 T a = phi(K, xi, yj, d);
+                const double aa0 = a < (T)0 ? -(double)a : (double)a;
+                colmax = aa0 > colmax ? aa0 : colmax;
                 for (int l = 0; l < r; ++l) a -= U[(int64_t)l * m + i] * sh.vec[l];
                 U[(int64_t)r * m + i] = a;
                 const T aa = a < (T)0 ? -a : a;
@@ -264,7 +268,8 @@ __global__ __launch_bounds__(kAcaThreads) void aca_kernel(
                 }
             }
             am = block_argmax(am, sh);
-            if (am.idx == INT_MAX || am.best <= eps0) {
+            colmax = block_minmax(colmax, 1, sh);
+            if (am.idx == INT_MAX || (double)am.best <= (double)eps0 * colmax) {
                 // no usable pivot in this column: try the lowest unused column
                 ++nfailed;
                 if (ncols_used >= nc || nfailed >= kmax) break;

@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
                     if (row < mt) {
                         const int64_t i = (int64_t)t0 + rb + row;
                         const int32_t pi = perm[i];
-                        T out = alpha * (acc[k] + sigma2 * vec[i]);
+                        T out = alpha * (sigma2 != (T)0 ? acc[k] + sigma2 * vec[i] : acc[k]);
                         if (beta != (T)0) out += beta * z[pi];
                         z[pi] = out;
                     }

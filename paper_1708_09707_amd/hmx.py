@@ -28,7 +28,8 @@ DTYPES = {"f64": HMX_F64, "f32": HMX_F32, "bf16": HMX_BF16}
 # every symbol declared in include/hmx.h
 EXPORTS = ["hmx_params_default", "hmx_build", "hmx_matvec", "hmx_get_partition",
            "hmx_get_boxes", "hmx_get_ranks", "hmx_get_factors", "hmx_get_stats",
-           "hmx_destroy", "hmx_status_string", "hmx_last_error"]
+           "hmx_profile_begin", "hmx_profile_end", "hmx_destroy", "hmx_status_string",
+           "hmx_last_error"]
 
 
 class hmx_kernel(C.Structure):
@@ -46,7 +47,8 @@ class hmx_stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("d", C.c_int32), ("levels", C.c_int32),
                 ("n_adm", C.c_int64), ("n_dense", C.c_int64), ("n_tiles", C.c_int64),
                 ("sum_rank", C.c_int64), ("max_rank_used", C.c_int32),
-                ("reserved0", C.c_int32), ("factor_entries", C.c_int64),
+                ("entry_bytes", C.c_int32), ("factor_entries", C.c_int64),
+                ("u_entries", C.c_int64), ("v_entries", C.c_int64),
                 ("near_entries", C.c_int64), ("aca_columns", C.c_int64),
                 ("matvec_bytes", C.c_double), ("phase_ms", C.c_double * 8),
                 ("device_bytes", C.c_int64), ("level_sizes", C.c_int64 * 64)]
@@ -89,6 +91,8 @@ def lib():
         L.hmx_get_factors.argtypes = [P, i64, P, P, C.POINTER(i32), P]
         L.hmx_get_stats.argtypes = [P, C.POINTER(hmx_stats)]
         L.hmx_destroy.argtypes = [P]
+        L.hmx_profile_begin.argtypes = [P, i32]
+        L.hmx_profile_end.argtypes = [P, P, C.POINTER(i32)]
         L.hmx_status_string.restype = C.c_char_p
         L.hmx_status_string.argtypes = [C.c_int]
         L.hmx_last_error.restype = C.c_char_p
@@ -204,6 +208,18 @@ def hmx_get_factors(h, leaf: int, m: int, n: int, kmax: int, stream=None):
                                  V.ctypes.data_as(C.c_void_p), C.byref(r), _stream(stream)))
     k = r.value
     return U[: k * m].reshape(k, m).T.copy(), V[: k * n].reshape(k, n).T.copy(), k
+
+
+def hmx_profile_begin(h, max_calls: int):
+    _check(lib().hmx_profile_begin(h, int(max_calls)))
+
+
+def hmx_profile_end(h):
+    """Returns (summed ms per phase [gather, phase1, rowtile], calls)."""
+    ms = np.zeros(3)
+    calls = C.c_int32(0)
+    _check(lib().hmx_profile_end(h, ms.ctypes.data_as(C.c_void_p), C.byref(calls)))
+    return ms, calls.value
 
 
 def hmx_destroy(h):

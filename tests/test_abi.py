@@ -38,8 +38,8 @@ int main(void) {
   printf("%zu %zu %zu\\n", sizeof(hmx_params), sizeof(hmx_stats), sizeof(hmx_kernel));
   printf("%zu %zu %zu %zu\\n", offsetof(hmx_params, max_rank), offsetof(hmx_params, sigma2),
          offsetof(hmx_params, rank_mode), offsetof(hmx_params, reserved));
-  printf("%zu %zu %zu\\n", offsetof(hmx_stats, matvec_bytes), offsetof(hmx_stats, device_bytes),
-         offsetof(hmx_stats, level_sizes));
+  printf("%zu %zu %zu %zu\\n", offsetof(hmx_stats, matvec_bytes), offsetof(hmx_stats, device_bytes),
+         offsetof(hmx_stats, level_sizes), offsetof(hmx_stats, v_entries));
   return 0;
 }
 """)
@@ -51,7 +51,7 @@ int main(void) {
             hmx.hmx_params.max_rank.offset, hmx.hmx_params.sigma2.offset,
             hmx.hmx_params.rank_mode.offset, hmx.hmx_params.reserved.offset,
             hmx.hmx_stats.matvec_bytes.offset, hmx.hmx_stats.device_bytes.offset,
-            hmx.hmx_stats.level_sizes.offset]
+            hmx.hmx_stats.level_sizes.offset, hmx.hmx_stats.v_entries.offset]
     assert [int(v) for v in out] == want
 
 
