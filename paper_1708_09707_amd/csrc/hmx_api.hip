@@ -104,7 +104,7 @@ struct hmx_hmatrix_s {
     DevBuf adm, adm_level, dense, dense_level;
     DevBuf tile_of_point, tile_lo;
     DevBuf rank, steps, uoff, voff, toff, U, V, near_off, near;
-    DevBuf pieces, tile_ptr, vecpool;
+    DevBuf pieces, tile_ptr, vecpool, col_block;
     hmx_stats stats{};
     // matvec phase tracing (hmx_profile_begin / end)
     std::vector<hipEvent_t> prof_events;
@@ -122,7 +122,8 @@ struct hmx_hmatrix_s {
                                &bmin,    &bmax,      &adm,           &adm_level, &dense,
                                &dense_level, &tile_of_point, &tile_lo, &rank,   &steps,
                                &uoff,    &voff,      &toff,          &U,       &V,
-                               &near_off, &near,     &pieces,        &tile_ptr, &vecpool};
+                               &near_off, &near,     &pieces,        &tile_ptr, &vecpool,
+                               &col_block};
         int64_t s = 0;
         for (auto* b : all) s += (int64_t)b->bytes;
         return s;
@@ -425,6 +426,10 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
         h->sum_rank = scan(h->toff.as<int64_t>(), h->n_adm);
     }
     alloc(h->vecpool, (size_t)(n + h->sum_rank) * esz, "vector pool");
+    alloc(h->col_block, (size_t)std::max<int64_t>(h->sum_rank, 1) * 4, "column map");
+    check(launch_col_block(h->rank.as<int32_t>(), h->toff.as<int64_t>(), h->n_adm,
+                           h->col_block.as<int32_t>(), st),
+          "column map");
 
     // ---- 5. near field (dense leaves, stored) ----
     alloc(h->near_off, (h->n_dense + 1) * 8, "near offsets");
@@ -640,9 +645,9 @@ hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype
     if (e == hipSuccess) e = launch_gather_x(x, h->perm.as<int32_t>(), h->n, h->vecpool.p, f64, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
     if (e == hipSuccess)
-        e = launch_far_phase1(h->adm.as<int4>(), h->n_adm, h->rank.as<int32_t>(),
-                              h->voff.as<int64_t>(), h->toff.as<int64_t>(), h->V.p, h->vecpool.p,
-                              h->n, f64, st);
+        e = launch_far_phase1(h->adm.as<int4>(), h->col_block.as<int32_t>(),
+                              h->voff.as<int64_t>(), h->toff.as<int64_t>(), h->sum_rank, h->V.p,
+                              h->vecpool.p, h->n, f64, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
     if (e == hipSuccess)
         e = launch_rowtile(h->ntiles, h->tile_lo.as<int32_t>(), h->tile_ptr.as<int64_t>(),

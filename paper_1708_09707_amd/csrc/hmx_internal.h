@@ -193,8 +193,10 @@ hipError_t launch_tile_offsets(const uint64_t* sorted_tile, int64_t npieces, int
                                int64_t* tile_ptr, hipStream_t st);
 hipError_t launch_gather_x(const void* x, const int32_t* perm, int64_t n, void* xm, int f64,
                            hipStream_t st);
-hipError_t launch_far_phase1(const int4* adm, int64_t nadm, const int32_t* rank,
-                             const int64_t* voff, const int64_t* toff, const void* V,
+hipError_t launch_col_block(const int32_t* rank, const int64_t* toff, int64_t nadm,
+                            int32_t* col_block, hipStream_t st);
+hipError_t launch_far_phase1(const int4* adm, const int32_t* col_block, const int64_t* voff,
+                             const int64_t* toff, int64_t ncols_total, const void* V,
                              void* vecpool, int64_t n, int f64, hipStream_t st);
 hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t* tile_ptr,
                           const Piece* pieces, const void* near, const void* U,

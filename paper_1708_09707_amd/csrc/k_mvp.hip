@@ -136,94 +136,189 @@ __global__ void gather_x_kernel(const T* __restrict__ x, const int32_t* __restri
     if (i < n) xm[i] = x[perm[i]];
 }
 
-// phase 1: t_b[l] = sum_j V_b[j, l] x[slo + j], one wave per column l
+// 16-byte vector of T: 4 floats or 2 doubles
 template <typename T>
-__global__ __launch_bounds__(256) void far_phase1_kernel(const int4* __restrict__ adm,
-                                                         int64_t nadm,
-                                                         const int32_t* __restrict__ rank,
-                                                         const int64_t* __restrict__ voff,
-                                                         const int64_t* __restrict__ toff,
-                                                         const T* __restrict__ V,
-                                                         T* __restrict__ vec, int64_t n) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int64_t b = blockIdx.x; b < nadm; b += gridDim.x) {
-        const int4 bl = adm[b];
-        const int nc = bl.w - bl.z, r = rank[b];
-        const T* __restrict__ Vb = V + voff[b];
-        const T* __restrict__ xs = vec + bl.z;
-        for (int l = w; l < r; l += 4) {
-            const T* __restrict__ col = Vb + (int64_t)l * nc;
-            T acc = 0;
-            for (int j = lane; j < nc; j += 64) acc += col[j] * xs[j];
-            acc = wave_sum(acc);
-            if (lane == 0) vec[n + toff[b] + l] = acc;
-        }
-    }
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using type = float4;
+    static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+    using type = double2;
+    static constexpr int n = 2;
+};
+
+template <typename V, typename T>
+__device__ __forceinline__ T vget(const V& v, int e);
+template <>
+__device__ __forceinline__ float vget<float4, float>(const float4& v, int e) {
+    return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
+}
+template <>
+__device__ __forceinline__ double vget<double2, double>(const double2& v, int e) {
+    return e == 0 ? v.x : v.y;
 }
 
-// phase 2: one workgroup per row tile; G column groups of GS threads, each
-// thread owns up to kMaxRpt rows of the tile
-constexpr int kTileThreads = 256;
-constexpr int kMaxRpt = 8;
-
+// phase 1: t_b[l] = sum_j V_b[j, l] x[slo + j]; one wave per column of the
+// flattened list of all factor columns (col_block maps a column to its leaf)
 template <typename T>
+__global__ __launch_bounds__(256) void far_phase1_kernel(
+    const int4* __restrict__ adm, const int32_t* __restrict__ col_block,
+    const int64_t* __restrict__ voff, const int64_t* __restrict__ toff, const T* __restrict__ V,
+    T* __restrict__ vec, int64_t n, int64_t ncols_total) {
+    using V16 = typename Vec16<T>::type;
+    constexpr int VEC = Vec16<T>::n;
+    const int lane = threadIdx.x & 63;
+    const int64_t k = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    if (k >= ncols_total) return;
+    const int b = col_block[k];
+    const int4 bl = adm[b];
+    const int nc = bl.w - bl.z;
+    const int l = (int)(k - toff[b]);
+    const int64_t cofs = voff[b] + (int64_t)l * nc;
+    const T* __restrict__ col = V + cofs;
+    const T* __restrict__ xs = vec + bl.z;
+    T acc = 0;
+    if (((cofs | (int64_t)bl.z | (int64_t)nc) % VEC) == 0) {
+        const V16* __restrict__ c16 = (const V16*)col;
+        const V16* __restrict__ x16 = (const V16*)xs;
+        const int nv = nc / VEC;
+        int j = lane;
+        for (; j + 64 < nv; j += 128) {
+            const V16 a0 = c16[j], a1 = c16[j + 64];
+            const V16 x0 = x16[j], x1 = x16[j + 64];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+                acc += vget<V16, T>(a0, e) * vget<V16, T>(x0, e) +
+                       vget<V16, T>(a1, e) * vget<V16, T>(x1, e);
+        }
+        for (; j < nv; j += 64) {
+            const V16 a0 = c16[j], x0 = x16[j];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc += vget<V16, T>(a0, e) * vget<V16, T>(x0, e);
+        }
+    } else {
+        for (int j = lane; j < nc; j += 64) acc += col[j] * xs[j];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) vec[n + k] = acc;
+}
+
+// column -> admissible leaf map for the flattened factor columns
+__global__ void col_block_kernel(const int32_t* __restrict__ rank, const int64_t* __restrict__ toff,
+                                 int64_t nadm, int32_t* __restrict__ col_block) {
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= nadm) return;
+    const int64_t o = toff[b];
+    for (int l = 0; l < rank[b]; ++l) col_block[o + l] = (int32_t)b;
+}
+
+// phase 2: one workgroup per row tile.  The 4 waves split into G = 4 * (64/L)
+// column groups of L lanes; lane q of a group owns RV vectors of VEC rows
+// (vector v*L + q), so a group covers L*RV*VEC rows with 16-byte loads when
+// the piece is aligned (scalar loads otherwise).  Groups take interleaved
+// columns of every piece; their partial rows are summed in LDS in a fixed
+// order and the tile is scattered to the original order.
+constexpr int kTileThreads = 256;
+
+template <typename T, int RV>
 __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
     int64_t ntiles, const int32_t* __restrict__ tile_lo, const int64_t* __restrict__ tile_ptr,
     const Piece* __restrict__ pieces, const T* __restrict__ near, const T* __restrict__ U,
-    const T* __restrict__ vec, const int32_t* __restrict__ perm, int64_t n, T alpha, T beta,
-    T sigma2, T* __restrict__ z, int G, int GS) {
-    __shared__ T red[kTileThreads * kMaxRpt];
-    const int tid = threadIdx.x;
-    const int g = tid / GS, rr = tid - g * GS;
-    const int chunk = GS * kMaxRpt;  // rows handled per pass over the pieces
+    const T* __restrict__ vec, const int32_t* __restrict__ perm, T alpha, T beta, T sigma2,
+    T* __restrict__ z, int L) {
+    using V16 = typename Vec16<T>::type;
+    constexpr int VEC = Vec16<T>::n;
+    extern __shared__ unsigned char red_raw[];
+    T* red = (T*)red_raw;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int S = 64 / L;
+    const int G = 4 * S;
+    const int g = w * S + lane / L;
+    const int q = lane % L;
+    const int rpg = L * RV * VEC;  // rows per group pass
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int32_t t0 = tile_lo[t];
-        const int mt_all = tile_lo[t + 1] - t0;
+        const int mt = tile_lo[t + 1] - t0;
         const int64_t p0 = tile_ptr[t], p1 = tile_ptr[t + 1];
-        for (int rb = 0; rb < mt_all; rb += chunk) {
-            const int mt = (mt_all - rb) < chunk ? (mt_all - rb) : chunk;
-            T acc[kMaxRpt];
+        for (int rb = 0; rb < mt; rb += rpg) {
+            const int mc = (mt - rb) < rpg ? (mt - rb) : rpg;
+            T acc[RV][VEC];
 #pragma unroll
-            for (int k = 0; k < kMaxRpt; ++k) acc[k] = 0;
+            for (int v = 0; v < RV; ++v)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc[v][e] = 0;
             for (int64_t p = p0; p < p1; ++p) {
                 const Piece pc = pieces[p];
-                const T* __restrict__ base = (pc.pool ? U : near) + pc.a_off + rb;
-                const T* __restrict__ v = vec + pc.v_off;
-                for (int c = g; c < pc.ncols; c += G) {
-                    const T wv = v[c];
-                    const T* __restrict__ col = base + (int64_t)c * pc.ld;
+                const int64_t aoff = pc.a_off + rb;
+                const T* __restrict__ base = (pc.pool ? U : near) + aoff;
+                const T* __restrict__ wv = vec + pc.v_off;
+                const int ld = pc.ld, ncols = pc.ncols;
+                if (((aoff | (int64_t)ld | (int64_t)mt) % VEC) == 0) {
+                    int c = g;
+                    for (; c + 3 * G < ncols; c += 4 * G) {
+                        const T w0 = wv[c], w1 = wv[c + G], w2 = wv[c + 2 * G], w3 = wv[c + 3 * G];
+                        const V16* c0 = (const V16*)(base + (int64_t)c * ld);
+                        const V16* c1 = (const V16*)(base + (int64_t)(c + G) * ld);
+                        const V16* c2 = (const V16*)(base + (int64_t)(c + 2 * G) * ld);
+                        const V16* c3 = (const V16*)(base + (int64_t)(c + 3 * G) * ld);
 #pragma unroll
-                    for (int k = 0; k < kMaxRpt; ++k) {
-                        const int row = rr + GS * k;
-                        if (row < mt) acc[k] += col[row] * wv;
+                        for (int v = 0; v < RV; ++v) {
+                            const int vi = v * L + q;
+                            if (vi * VEC < mc) {
+                                const V16 a0 = c0[vi], a1 = c1[vi], a2 = c2[vi], a3 = c3[vi];
+#pragma unroll
+                                for (int e = 0; e < VEC; ++e)
+                                    acc[v][e] += vget<V16, T>(a0, e) * w0 + vget<V16, T>(a1, e) * w1 +
+                                                 vget<V16, T>(a2, e) * w2 + vget<V16, T>(a3, e) * w3;
+                            }
+                        }
+                    }
+                    for (; c < ncols; c += G) {
+                        const T w0 = wv[c];
+                        const V16* c0 = (const V16*)(base + (int64_t)c * ld);
+#pragma unroll
+                        for (int v = 0; v < RV; ++v) {
+                            const int vi = v * L + q;
+                            if (vi * VEC < mc) {
+                                const V16 a0 = c0[vi];
+#pragma unroll
+                                for (int e = 0; e < VEC; ++e) acc[v][e] += vget<V16, T>(a0, e) * w0;
+                            }
+                        }
+                    }
+                } else {
+                    for (int c = g; c < ncols; c += G) {
+                        const T w0 = wv[c];
+                        const T* __restrict__ col = base + (int64_t)c * ld;
+#pragma unroll
+                        for (int v = 0; v < RV; ++v)
+#pragma unroll
+                            for (int e = 0; e < VEC; ++e) {
+                                const int row = (v * L + q) * VEC + e;
+                                if (row < mc) acc[v][e] += col[row] * w0;
+                            }
                     }
                 }
             }
-            if (G > 1) {
+            // sum the G partial row sets in a fixed order
 #pragma unroll
-                for (int k = 0; k < kMaxRpt; ++k) red[(g * kMaxRpt + k) * GS + rr] = acc[k];
-                __syncthreads();
-                if (g == 0) {
-                    for (int q = 1; q < G; ++q)
+            for (int v = 0; v < RV; ++v)
 #pragma unroll
-                        for (int k = 0; k < kMaxRpt; ++k)
-                            acc[k] += red[(q * kMaxRpt + k) * GS + rr];
-                }
-                __syncthreads();
+                for (int e = 0; e < VEC; ++e) red[g * rpg + (v * L + q) * VEC + e] = acc[v][e];
+            __syncthreads();
+            for (int row = tid; row < mc; row += kTileThreads) {
+                T sum = red[row];
+                for (int gg = 1; gg < G; ++gg) sum += red[gg * rpg + row];
+                const int64_t i = (int64_t)t0 + rb + row;
+                const int32_t pi = perm[i];
+                T out = alpha * (sigma2 != (T)0 ? sum + sigma2 * vec[i] : sum);
+                if (beta != (T)0) out += beta * z[pi];
+                z[pi] = out;
             }
-            if (g == 0) {
-#pragma unroll
-                for (int k = 0; k < kMaxRpt; ++k) {
-                    const int row = rr + GS * k;
-                    if (row < mt) {
-                        const int64_t i = (int64_t)t0 + rb + row;
-                        const int32_t pi = perm[i];
-                        T out = alpha * (sigma2 != (T)0 ? acc[k] + sigma2 * vec[i] : acc[k]);
-                        if (beta != (T)0) out += beta * z[pi];
-                        z[pi] = out;
-                    }
-                }
-            }
+            __syncthreads();
         }
     }
 }
@@ -294,17 +389,55 @@ hipError_t launch_gather_x(const void* x, const int32_t* perm, int64_t n, void* 
     return hipGetLastError();
 }
 
-hipError_t launch_far_phase1(const int4* adm, int64_t nadm, const int32_t* rank,
-                             const int64_t* voff, const int64_t* toff, const void* V,
-                             void* vecpool, int64_t n, int f64, hipStream_t st) {
+hipError_t launch_col_block(const int32_t* rank, const int64_t* toff, int64_t nadm,
+                            int32_t* col_block, hipStream_t st) {
     if (nadm == 0) return hipSuccess;
-    const unsigned grid = grid_cap(nadm, 1 << 20);
+    hipLaunchKernelGGL(col_block_kernel, dim3((unsigned)((nadm + 255) / 256)), dim3(256), 0, st,
+                       rank, toff, nadm, col_block);
+    return hipGetLastError();
+}
+
+hipError_t launch_far_phase1(const int4* adm, const int32_t* col_block, const int64_t* voff,
+                             const int64_t* toff, int64_t ncols_total, const void* V,
+                             void* vecpool, int64_t n, int f64, hipStream_t st) {
+    if (ncols_total == 0) return hipSuccess;
+    const int64_t nblk = (ncols_total + 3) / 4;  // 4 waves (columns) per workgroup
+    if (nblk > 0x7fffffffll) return hipErrorInvalidValue;
     if (f64)
-        hipLaunchKernelGGL(far_phase1_kernel<double>, dim3(grid), dim3(256), 0, st, adm, nadm,
-                           rank, voff, toff, (const double*)V, (double*)vecpool, n);
+        hipLaunchKernelGGL(far_phase1_kernel<double>, dim3((unsigned)nblk), dim3(256), 0, st, adm,
+                           col_block, voff, toff, (const double*)V, (double*)vecpool, n,
+                           ncols_total);
     else
-        hipLaunchKernelGGL(far_phase1_kernel<float>, dim3(grid), dim3(256), 0, st, adm, nadm,
-                           rank, voff, toff, (const float*)V, (float*)vecpool, n);
+        hipLaunchKernelGGL(far_phase1_kernel<float>, dim3((unsigned)nblk), dim3(256), 0, st, adm,
+                           col_block, voff, toff, (const float*)V, (float*)vecpool, n,
+                           ncols_total);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t rowtile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_t* tile_ptr,
+                                   const Piece* pieces, const void* near, const void* U,
+                                   const void* vecpool, const int32_t* perm, double alpha,
+                                   double beta, double sigma2, void* z, int max_tile,
+                                   hipStream_t st) {
+    constexpr int VEC = Vec16<T>::n;
+    const int need = (max_tile + VEC - 1) / VEC;  // vectors per tile column
+    int L = 8, RV = 1;
+    while (L < need && L < 64) L *= 2;
+    while (L * RV < need && RV < 8) RV *= 2;
+    const size_t lds = (size_t)(4 * (64 / L)) * L * RV * VEC * sizeof(T);
+    const unsigned grid = grid_cap(ntiles, 1 << 20);
+#define HMX_ROWTILE(RVV)                                                                          \
+    hipLaunchKernelGGL((rowtile_kernel<T, RVV>), dim3(grid), dim3(kTileThreads), lds, st, ntiles, \
+                       tile_lo, tile_ptr, pieces, (const T*)near, (const T*)U, (const T*)vecpool, \
+                       perm, (T)alpha, (T)beta, (T)sigma2, (T*)z, L)
+    switch (RV) {
+        case 1: HMX_ROWTILE(1); break;
+        case 2: HMX_ROWTILE(2); break;
+        case 4: HMX_ROWTILE(4); break;
+        default: HMX_ROWTILE(8); break;
+    }
+#undef HMX_ROWTILE
     return hipGetLastError();
 }
 
@@ -313,25 +446,13 @@ hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t*
                           const void* vecpool, const int32_t* perm, int64_t n, double alpha,
                           double beta, double sigma2, void* z, int max_tile, int f64,
                           hipStream_t st) {
+    (void)n;
     if (ntiles == 0) return hipSuccess;
-    // rows per group: the smallest power of two >= max_tile / kMaxRpt, at least 64
-    // group size: the smallest power of two >= the largest tile (64..256);
-    // tiles above GS * kMaxRpt rows are processed in several row passes
-    int GS = 64;
-    while (GS < max_tile && GS < kTileThreads) GS *= 2;
-    const int G = kTileThreads / GS;
-    const unsigned grid = grid_cap(ntiles, 1 << 20);
     if (f64)
-        hipLaunchKernelGGL(rowtile_kernel<double>, dim3(grid), dim3(kTileThreads), 0, st, ntiles,
-                           tile_lo, tile_ptr, pieces, (const double*)near, (const double*)U,
-                           (const double*)vecpool, perm, n, alpha, beta, sigma2, (double*)z, G,
-                           GS);
-    else
-        hipLaunchKernelGGL(rowtile_kernel<float>, dim3(grid), dim3(kTileThreads), 0, st, ntiles,
-                           tile_lo, tile_ptr, pieces, (const float*)near, (const float*)U,
-                           (const float*)vecpool, perm, n, (float)alpha, (float)beta,
-                           (float)sigma2, (float*)z, G, GS);
-    return hipGetLastError();
+        return rowtile_dispatch<double>(ntiles, tile_lo, tile_ptr, pieces, near, U, vecpool, perm,
+                                        alpha, beta, sigma2, z, max_tile, st);
+    return rowtile_dispatch<float>(ntiles, tile_lo, tile_ptr, pieces, near, U, vecpool, perm,
+                                   alpha, beta, sigma2, z, max_tile, st);
 }
 
 }  // namespace hmx
