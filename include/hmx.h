@@ -182,8 +182,14 @@ hmx_status hmx_get_stats(hmx_hmatrix h, hmx_stats* s);
 hmx_status hmx_profile_begin(hmx_hmatrix h, int32_t max_calls);
 hmx_status hmx_profile_end(hmx_hmatrix h, double* ms, int32_t* calls);
 
-/* Free every device buffer of the handle (synchronises the device). */
+/* Release every device buffer of the handle (synchronises the device).  The
+ * buffers return to the library's device-block cache, which later builds
+ * reuse; hmx_trim gives the cached blocks back to the driver. */
 hmx_status hmx_destroy(hmx_hmatrix h);
+
+/* Free the library's cached device blocks (synchronises the device);
+ * *released_bytes (optional, host) receives the bytes returned. */
+hmx_status hmx_trim(int64_t* released_bytes);
 
 const char* hmx_status_string(hmx_status s);
 const char* hmx_last_error(void); /* thread-local message of the last failure */

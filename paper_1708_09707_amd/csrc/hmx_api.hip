@@ -8,6 +8,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -29,7 +31,74 @@ void set_err(const char* fmt, ...) {
     g_err = buf;
 }
 
-// owning device buffer
+struct Fail {
+    hmx_status s;
+};
+
+// Process-wide cache of device blocks.  Builds allocate and release the same
+// large pools again and again (capacity scratch, factor and near-field
+// pools); returning them to the driver and mapping them anew each time costs
+// seconds on a busy device, so released blocks are kept per device and
+// reused best-fit (a block is reused for requests of 3/4 of its size or
+// more).  A failed device allocation flushes the cache and retries once.
+// Blocks enter the cache only after the work using them has completed (the
+// build synchronises its stream before releasing scratch, destroy
+// synchronises the device).
+struct DeviceCache {
+    std::mutex mu;
+    std::multimap<size_t, std::pair<int, void*>> blocks;  // size -> (device, ptr)
+    size_t cached = 0;
+};
+DeviceCache& cache() {
+    static DeviceCache* c = new DeviceCache();  // never destroyed: process lifetime
+    return *c;
+}
+
+size_t cache_round(size_t bytes) {
+    const size_t g = bytes >= ((size_t)64 << 20) ? ((size_t)2 << 20) : 256;
+    return (bytes + g - 1) / g * g;
+}
+
+// *bytes: requested size in, size of the block handed out on return
+hipError_t cache_alloc(void** p, size_t* bytes) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    DeviceCache& c = cache();
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        for (auto it = c.blocks.lower_bound(*bytes); it != c.blocks.end(); ++it) {
+            if (it->first / 4 * 3 > *bytes) break;
+            if (it->second.first != dev) continue;
+            *p = it->second.second;
+            *bytes = it->first;
+            c.cached -= it->first;
+            c.blocks.erase(it);
+            return hipSuccess;
+        }
+    }
+    hipError_t e = hipMalloc(p, *bytes);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        std::lock_guard<std::mutex> lk(c.mu);
+        (void)hipDeviceSynchronize();
+        for (auto& b : c.blocks) (void)hipFree(b.second.second);
+        c.blocks.clear();
+        c.cached = 0;
+        e = hipMalloc(p, *bytes);
+    }
+    return e;
+}
+
+void cache_free(void* p, size_t bytes) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    DeviceCache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.blocks.insert({bytes, {dev, p}});
+    c.cached += bytes;
+}
+
+// owning device buffer (allocated through the cache)
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
@@ -38,7 +107,7 @@ struct DevBuf {
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) cache_free(p, bytes);
         p = nullptr;
         bytes = 0;
     }
@@ -48,13 +117,11 @@ struct DevBuf {
     }
 };
 
-struct Fail {
-    hmx_status s;
-};
-
 void check(hipError_t e, const char* what) {
     if (e != hipSuccess) {
         set_err("%s: %s", what, hipGetErrorString(e));
+        // unwinding returns buffers to the cache: wait for in-flight work first
+        (void)hipDeviceSynchronize();
         throw Fail{e == hipErrorOutOfMemory ? HMX_ERR_OOM : HMX_ERR_DEVICE};
     }
 }
@@ -62,9 +129,11 @@ void check(hipError_t e, const char* what) {
 void alloc(DevBuf& b, size_t bytes, const char* what) {
     b.release();
     if (bytes == 0) bytes = 16;
-    hipError_t e = hipMalloc(&b.p, bytes);
+    bytes = cache_round(bytes);
+    hipError_t e = cache_alloc(&b.p, &bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
+        (void)hipDeviceSynchronize();  // in-flight work may still use released blocks
         b.p = nullptr;
         set_err("device allocation of %zu bytes for %s failed: %s", bytes, what,
                 hipGetErrorString(e));
@@ -79,6 +148,31 @@ T read_scalar(const T* dev, hipStream_t st) {
     check(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, st), "readback");
     check(hipStreamSynchronize(st), "stream synchronize");
     return v;
+}
+
+// device -> pageable host copy through a pinned staging buffer (large
+// readbacks never ask the runtime to pin caller memory)
+void d2h(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return;
+    const size_t chunk = std::min<size_t>(bytes, (size_t)32 << 20);
+    void* stage = nullptr;
+    hipError_t e = hipHostMalloc(&stage, chunk, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        set_err("pinned staging allocation failed: %s", hipGetErrorString(e));
+        throw Fail{HMX_ERR_OOM};
+    }
+    hipError_t r = hipSuccess;
+    for (size_t off = 0; off < bytes && r == hipSuccess; off += chunk) {
+        const size_t nb = std::min(chunk, bytes - off);
+        r = hipMemcpyAsync(stage, (const char*)src + off, nb, hipMemcpyDeviceToHost, st);
+        if (r == hipSuccess) r = hipStreamSynchronize(st);
+        if (r == hipSuccess) memcpy((char*)dst + off, stage, nb);
+    }
+    (void)hipHostFree(stage);
+    if (r != hipSuccess) {
+        set_err("device to host copy: %s", hipGetErrorString(r));
+        throw Fail{HMX_ERR_DEVICE};
+    }
 }
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -398,19 +492,17 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
         h->factor_entries = ue + ve;
         S.u_entries = ue;
         S.v_entries = ve;
-        // rank statistics (host copy of the per-block ranks and column counts)
-        std::vector<int32_t> rk(h->n_adm), stp(h->n_adm);
-        check(hipMemcpyAsync(rk.data(), h->rank.p, h->n_adm * 4, hipMemcpyDeviceToHost, st), "ranks");
-        check(hipMemcpyAsync(stp.data(), h->steps.p, h->n_adm * 4, hipMemcpyDeviceToHost, st), "steps");
+        // rank statistics, reduced on the device
+        DevBuf red;
+        alloc(red, 4 * sizeof(unsigned long long), "stats");
+        unsigned long long* rd = red.as<unsigned long long>();
+        check(launch_int_stats(h->rank.as<int32_t>(), h->n_adm, rd, st), "rank stats");
+        check(launch_int_stats(h->steps.as<int32_t>(), h->n_adm, rd + 2, st), "step stats");
+        unsigned long long hv[4];
+        check(hipMemcpyAsync(hv, rd, sizeof hv, hipMemcpyDeviceToHost, st), "stats readback");
         check(hipStreamSynchronize(st), "stats sync");
-        int32_t mr = 0;
-        int64_t cols = 0;
-        for (int64_t b = 0; b < h->n_adm; ++b) {
-            mr = std::max(mr, rk[b]);
-            cols += stp[b];
-        }
-        S.max_rank_used = mr;
-        S.aca_columns = cols;
+        S.max_rank_used = (int32_t)hv[0];
+        S.aca_columns = (int64_t)hv[3];
         S.phase_ms[4] = ms_since(t0);
     } else {
         alloc(h->U, 16, "U pool");
@@ -679,26 +771,21 @@ hmx_status hmx_get_partition(hmx_hmatrix h, uint64_t* codes, int32_t* perm, int3
         if (n_adm) *n_adm = h->n_adm;
         if (n_dense) *n_dense = h->n_dense;
         std::vector<uint32_t> pm(h->n);
-        check(hipMemcpyAsync(pm.data(), h->perm.p, h->n * 4, hipMemcpyDeviceToHost, st), "perm");
+        d2h(pm.data(), h->perm.p, h->n * 4, st);
         std::vector<uint64_t> sc;
         if (codes) {
             sc.resize(h->n);
-            check(hipMemcpyAsync(sc.data(), h->codes.p, h->n * 8, hipMemcpyDeviceToHost, st),
-                  "codes");
+            d2h(sc.data(), h->codes.p, h->n * 8, st);
         }
         std::vector<int4> a(h->n_adm), dn(h->n_dense);
         std::vector<int32_t> al(h->n_adm), dl(h->n_dense);
         if (adm && h->n_adm) {
-            check(hipMemcpyAsync(a.data(), h->adm.p, h->n_adm * 16, hipMemcpyDeviceToHost, st), "adm");
-            check(hipMemcpyAsync(al.data(), h->adm_level.p, h->n_adm * 4, hipMemcpyDeviceToHost, st),
-                  "adm level");
+            d2h(a.data(), h->adm.p, h->n_adm * 16, st);
+            d2h(al.data(), h->adm_level.p, h->n_adm * 4, st);
         }
         if (dense && h->n_dense) {
-            check(hipMemcpyAsync(dn.data(), h->dense.p, h->n_dense * 16, hipMemcpyDeviceToHost, st),
-                  "dense");
-            check(hipMemcpyAsync(dl.data(), h->dense_level.p, h->n_dense * 4, hipMemcpyDeviceToHost,
-                                 st),
-                  "dense level");
+            d2h(dn.data(), h->dense.p, h->n_dense * 16, st);
+            d2h(dl.data(), h->dense_level.p, h->n_dense * 4, st);
         }
         check(hipStreamSynchronize(st), "sync");
         if (perm)
@@ -734,10 +821,10 @@ hmx_status hmx_get_boxes(hmx_hmatrix h, double* global_box, double* leaf_boxes, 
             const int d = h->d;
             std::vector<int32_t> lo(h->nslots), hi(h->nslots);
             std::vector<double> bmn(h->nslots * d), bmx(h->nslots * d);
-            check(hipMemcpyAsync(lo.data(), h->node_lo.p, h->nslots * 4, hipMemcpyDeviceToHost, st), "lo");
-            check(hipMemcpyAsync(hi.data(), h->node_hi.p, h->nslots * 4, hipMemcpyDeviceToHost, st), "hi");
-            check(hipMemcpyAsync(bmn.data(), h->bmin.p, h->nslots * d * 8, hipMemcpyDeviceToHost, st), "bmin");
-            check(hipMemcpyAsync(bmx.data(), h->bmax.p, h->nslots * d * 8, hipMemcpyDeviceToHost, st), "bmax");
+            d2h(lo.data(), h->node_lo.p, h->nslots * 4, st);
+            d2h(hi.data(), h->node_hi.p, h->nslots * 4, st);
+            d2h(bmn.data(), h->bmin.p, h->nslots * d * 8, st);
+            d2h(bmx.data(), h->bmax.p, h->nslots * d * 8, st);
             check(hipStreamSynchronize(st), "sync");
             // leaf clusters in Morton order (sorted by lo)
             std::vector<std::pair<int32_t, int64_t>> leaves;
@@ -769,8 +856,7 @@ hmx_status hmx_get_ranks(hmx_hmatrix h, int32_t* ranks, void* stream) {
     hipStream_t st = (hipStream_t)stream;
     try {
         if (h->n_adm) {
-            check(hipMemcpyAsync(ranks, h->rank.p, h->n_adm * 4, hipMemcpyDeviceToHost, st), "ranks");
-            check(hipStreamSynchronize(st), "sync");
+            d2h(ranks, h->rank.p, h->n_adm * 4, st);
         }
     } catch (const Fail& f) {
         return f.s;
@@ -797,14 +883,12 @@ hmx_status hmx_get_factors(hmx_hmatrix h, int64_t leaf, double* U, double* V, in
         const int64_t m = bl.y - bl.x, nc = bl.w - bl.z;
         *rank = r;
         if (h->f64) {
-            check(hipMemcpyAsync(U, h->U.as<double>() + uo, r * m * 8, hipMemcpyDeviceToHost, st), "U");
-            check(hipMemcpyAsync(V, h->V.as<double>() + vo, r * nc * 8, hipMemcpyDeviceToHost, st), "V");
-            check(hipStreamSynchronize(st), "sync");
+            d2h(U, h->U.as<double>() + uo, r * m * 8, st);
+            d2h(V, h->V.as<double>() + vo, r * nc * 8, st);
         } else {
             std::vector<float> u(r * m), v(r * nc);
-            check(hipMemcpyAsync(u.data(), h->U.as<float>() + uo, r * m * 4, hipMemcpyDeviceToHost, st), "U");
-            check(hipMemcpyAsync(v.data(), h->V.as<float>() + vo, r * nc * 4, hipMemcpyDeviceToHost, st), "V");
-            check(hipStreamSynchronize(st), "sync");
+            d2h(u.data(), h->U.as<float>() + uo, r * m * 4, st);
+            d2h(v.data(), h->V.as<float>() + vo, r * nc * 4, st);
             for (int64_t e = 0; e < r * m; ++e) U[e] = u[e];
             for (int64_t e = 0; e < r * nc; ++e) V[e] = v[e];
         }
@@ -873,6 +957,21 @@ hmx_status hmx_destroy(hmx_hmatrix h) {
     if (!h) return HMX_OK;
     (void)hipDeviceSynchronize();
     delete h;
+    return HMX_OK;
+}
+
+hmx_status hmx_trim(int64_t* released_bytes) {
+    DeviceCache& c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    (void)hipDeviceSynchronize();
+    int64_t tot = 0;
+    for (auto& b : c.blocks) {
+        (void)hipFree(b.second.second);
+        tot += (int64_t)b.first;
+    }
+    c.blocks.clear();
+    c.cached = 0;
+    if (released_bytes) *released_bytes = tot;
     return HMX_OK;
 }
 

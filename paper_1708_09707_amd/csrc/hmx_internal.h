@@ -193,6 +193,9 @@ hipError_t launch_tile_offsets(const uint64_t* sorted_tile, int64_t npieces, int
                                int64_t* tile_ptr, hipStream_t st);
 hipError_t launch_gather_x(const void* x, const int32_t* perm, int64_t n, void* xm, int f64,
                            hipStream_t st);
+// out[0] = max and out[1] = sum of n non-negative int32 values (device)
+hipError_t launch_int_stats(const int32_t* a, int64_t n, unsigned long long* out,
+                            hipStream_t st);
 hipError_t launch_col_block(const int32_t* rank, const int64_t* toff, int64_t nadm,
                             int32_t* col_block, hipStream_t st);
 hipError_t launch_far_phase1(const int4* adm, const int32_t* col_block, const int64_t* voff,

@@ -206,6 +206,25 @@ __global__ __launch_bounds__(256) void far_phase1_kernel(
     if (lane == 0) vec[n + k] = acc;
 }
 
+// out[0] = max, out[1] = sum of n int32 values (integer atomics: order-free)
+__global__ void int_stats_kernel(const int32_t* __restrict__ a, int64_t n,
+                                 unsigned long long* __restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int32_t v = i < n ? a[i] : 0;
+    int32_t mx = v;
+    int64_t sm = v;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int32_t u = __shfl_xor(mx, o, 64);
+        mx = u > mx ? u : mx;
+        sm += __shfl_xor(sm, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&out[0], (unsigned long long)mx);
+        atomicAdd(&out[1], (unsigned long long)sm);
+    }
+}
+
 // column -> admissible leaf map for the flattened factor columns
 __global__ void col_block_kernel(const int32_t* __restrict__ rank, const int64_t* __restrict__ toff,
                                  int64_t nadm, int32_t* __restrict__ col_block) {
@@ -386,6 +405,15 @@ hipError_t launch_gather_x(const void* x, const int32_t* perm, int64_t n, void* 
     else
         hipLaunchKernelGGL(gather_x_kernel<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                            st, (const float*)x, perm, n, (float*)xm);
+    return hipGetLastError();
+}
+
+hipError_t launch_int_stats(const int32_t* a, int64_t n, unsigned long long* out,
+                            hipStream_t st) {
+    hipError_t e = hipMemsetAsync(out, 0, 2 * sizeof(unsigned long long), st);
+    if (e != hipSuccess || n == 0) return e;
+    hipLaunchKernelGGL(int_stats_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a,
+                       n, out);
     return hipGetLastError();
 }
 

@@ -28,8 +28,8 @@ DTYPES = {"f64": HMX_F64, "f32": HMX_F32, "bf16": HMX_BF16}
 # every symbol declared in include/hmx.h
 EXPORTS = ["hmx_params_default", "hmx_build", "hmx_matvec", "hmx_get_partition",
            "hmx_get_boxes", "hmx_get_ranks", "hmx_get_factors", "hmx_get_stats",
-           "hmx_profile_begin", "hmx_profile_end", "hmx_destroy", "hmx_status_string",
-           "hmx_last_error"]
+           "hmx_profile_begin", "hmx_profile_end", "hmx_destroy", "hmx_trim",
+           "hmx_status_string", "hmx_last_error"]
 
 
 class hmx_kernel(C.Structure):
@@ -91,6 +91,7 @@ def lib():
         L.hmx_get_factors.argtypes = [P, i64, P, P, C.POINTER(i32), P]
         L.hmx_get_stats.argtypes = [P, C.POINTER(hmx_stats)]
         L.hmx_destroy.argtypes = [P]
+        L.hmx_trim.argtypes = [C.POINTER(i64)]
         L.hmx_profile_begin.argtypes = [P, i32]
         L.hmx_profile_end.argtypes = [P, P, C.POINTER(i32)]
         L.hmx_status_string.restype = C.c_char_p
@@ -225,6 +226,13 @@ def hmx_profile_end(h):
 def hmx_destroy(h):
     if h:
         _check(lib().hmx_destroy(h))
+
+
+def hmx_trim() -> int:
+    """Return the library's cached device blocks to the driver; bytes freed."""
+    r = C.c_int64(0)
+    _check(lib().hmx_trim(C.byref(r)))
+    return r.value
 
 
 class HMatrix:
