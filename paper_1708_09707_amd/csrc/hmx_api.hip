@@ -197,8 +197,9 @@ struct hmx_hmatrix_s {
     DevBuf codes, perm, soa64, soa32, node_lo, node_hi, bmin, bmax;
     DevBuf adm, adm_level, dense, dense_level;
     DevBuf tile_of_point, tile_lo;
-    DevBuf rank, steps, uoff, voff, toff, U, V, near_off, near;
-    DevBuf pieces, tile_ptr, vecpool, col_block;
+    DevBuf rank, steps, voff, toff, V;
+    DevBuf pieces, pool, widx, tile_col, tile_doff, vecpool, col_block;
+    int64_t pool_entries = 0, ncols_total = 0;
     hmx_stats stats{};
     // matvec phase tracing (hmx_profile_begin / end)
     std::vector<hipEvent_t> prof_events;
@@ -212,11 +213,11 @@ struct hmx_hmatrix_s {
     ~hmx_hmatrix_s() { prof_release(); }
 
     int64_t device_bytes() const {
-        const DevBuf* all[] = {&codes,   &perm,      &soa64,         &soa32,   &node_lo, &node_hi,
-                               &bmin,    &bmax,      &adm,           &adm_level, &dense,
-                               &dense_level, &tile_of_point, &tile_lo, &rank,   &steps,
-                               &uoff,    &voff,      &toff,          &U,       &V,
-                               &near_off, &near,     &pieces,        &tile_ptr, &vecpool,
+        const DevBuf* all[] = {&codes,     &perm,          &soa64,   &soa32,     &node_lo,
+                               &node_hi,   &bmin,          &bmax,    &adm,       &adm_level,
+                               &dense,     &dense_level,   &tile_of_point, &tile_lo, &rank,
+                               &steps,     &voff,          &toff,    &V,         &pieces,
+                               &pool,      &widx,          &tile_col, &tile_doff, &vecpool,
                                &col_block};
         int64_t s = 0;
         for (auto* b : all) s += (int64_t)b->bytes;
@@ -413,24 +414,23 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
     t0 = clk::now();
 
     const int kmax = h->prm.max_rank;
-    DevBuf tmp_a, tmp_b, scan_scr, total;
+    DevBuf scan_scr, total;
     alloc(total, 8, "total");
-    const int64_t nmax = std::max<int64_t>(std::max<int64_t>(h->n_adm, h->n_dense), 1);
-    alloc(scan_scr, scan_scratch_bytes(nmax + 1) + 64, "scan scratch");
     auto scan = [&](int64_t* data, int64_t cnt) -> int64_t {
+        const size_t need = scan_scratch_bytes(cnt + 1) + 64;
+        if (!scan_scr.p || scan_scr.bytes < need) alloc(scan_scr, need, "scan scratch");
         check(exclusive_scan_i64(data, cnt, total.as<int64_t>(), scan_scr.p, st), "scan");
         return read_scalar(total.as<int64_t>(), st);
     };
 
-    // ---- 4. batched ACA of the admissible leaves ----
+    // ---- 4. batched ACA of the admissible leaves (capacity pools) ----
     alloc(h->rank, std::max<int64_t>(h->n_adm, 1) * 4, "ranks");
     alloc(h->steps, std::max<int64_t>(h->n_adm, 1) * 4, "steps");
-    alloc(h->uoff, (h->n_adm + 1) * 8, "U offsets");
     alloc(h->voff, (h->n_adm + 1) * 8, "V offsets");
+    DevBuf cu, cv, Ucap, Vcap;
+    alloc(cu, (h->n_adm + 1) * 8, "U capacity offsets");
+    alloc(cv, (h->n_adm + 1) * 8, "V capacity offsets");
     if (h->n_adm > 0) {
-        DevBuf cu, cv, Ucap, Vcap;
-        alloc(cu, (h->n_adm + 1) * 8, "U capacity offsets");
-        alloc(cv, (h->n_adm + 1) * 8, "V capacity offsets");
         check(launch_extent(h->adm.as<int4>(), h->n_adm, 0, kmax, nullptr, nullptr,
                             cu.as<int64_t>(), st),
               "extent");
@@ -472,26 +472,24 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
         check(hipStreamSynchronize(st), "aca sync");
         S.phase_ms[3] = ms_since(t0);
         t0 = clk::now();
-        // exact-size pools
+        // V pool (exact ranks), U entry count
+        DevBuf ue_cnt;
+        alloc(ue_cnt, (h->n_adm + 1) * 8, "U entries");
         check(launch_extent(h->adm.as<int4>(), h->n_adm, 3, 0, h->rank.as<int32_t>(), nullptr,
-                            h->uoff.as<int64_t>(), st),
+                            ue_cnt.as<int64_t>(), st),
               "extent");
+        S.u_entries = scan(ue_cnt.as<int64_t>(), h->n_adm);
         check(launch_extent(h->adm.as<int4>(), h->n_adm, 4, 0, h->rank.as<int32_t>(), nullptr,
                             h->voff.as<int64_t>(), st),
               "extent");
-        const int64_t ue = scan(h->uoff.as<int64_t>(), h->n_adm);
-        const int64_t ve = scan(h->voff.as<int64_t>(), h->n_adm);
-        alloc(h->U, ue * esz, "U pool");
-        alloc(h->V, ve * esz, "V pool");
-        check(launch_compact_factors(h->adm.as<int4>(), h->n_adm, h->rank.as<int32_t>(),
-                                     cu.as<int64_t>(), cv.as<int64_t>(), h->uoff.as<int64_t>(),
-                                     h->voff.as<int64_t>(), Ucap.p, Vcap.p, h->U.p, h->V.p, f64,
-                                     st),
-              "compact");
+        S.v_entries = scan(h->voff.as<int64_t>(), h->n_adm);
+        alloc(h->V, S.v_entries * esz, "V pool");
+        check(launch_compact_v(h->adm.as<int4>(), h->n_adm, h->rank.as<int32_t>(),
+                               cv.as<int64_t>(), h->voff.as<int64_t>(), Vcap.p, h->V.p, f64, st),
+              "compact V");
         check(hipStreamSynchronize(st), "compact sync");
-        h->factor_entries = ue + ve;
-        S.u_entries = ue;
-        S.v_entries = ve;
+        Vcap.release();
+        h->factor_entries = S.u_entries + S.v_entries;
         // rank statistics, reduced on the device
         DevBuf red;
         alloc(red, 4 * sizeof(unsigned long long), "stats");
@@ -503,13 +501,10 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
         check(hipStreamSynchronize(st), "stats sync");
         S.max_rank_used = (int32_t)hv[0];
         S.aca_columns = (int64_t)hv[3];
-        S.phase_ms[4] = ms_since(t0);
     } else {
-        alloc(h->U, 16, "U pool");
         alloc(h->V, 16, "V pool");
     }
-    t0 = clk::now();
-    // t offsets
+    // t offsets, vector pool, column -> leaf map of phase 1
     alloc(h->toff, (h->n_adm + 1) * 8, "t offsets");
     if (h->n_adm > 0) {
         check(launch_extent(h->adm.as<int4>(), h->n_adm, 5, 0, h->rank.as<int32_t>(), nullptr,
@@ -522,30 +517,14 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
     check(launch_col_block(h->rank.as<int32_t>(), h->toff.as<int64_t>(), h->n_adm,
                            h->col_block.as<int32_t>(), st),
           "column map");
-
-    // ---- 5. near field (dense leaves, stored) ----
-    alloc(h->near_off, (h->n_dense + 1) * 8, "near offsets");
-    if (h->n_dense > 0) {
-        check(launch_extent(h->dense.as<int4>(), h->n_dense, 2, 0, nullptr, nullptr,
-                            h->near_off.as<int64_t>(), st),
-              "extent");
-        h->near_entries = scan(h->near_off.as<int64_t>(), h->n_dense);
-        alloc(h->near, h->near_entries * esz, "near-field pool");
-        check(launch_near_assemble(f64 ? h->soa64.p : h->soa32.p, n, d,
-                                   KernelFn{(int)h->kern.kind, h->kern.p0}, h->dense.as<int4>(),
-                                   h->n_dense, h->near_off.as<int64_t>(), h->near.p, f64, st),
-              "near field");
-        check(hipStreamSynchronize(st), "near sync");
-    } else {
-        alloc(h->near, 16, "near-field pool");
-    }
-    S.phase_ms[5] = ms_since(t0);
+    S.phase_ms[4] = ms_since(t0);
     t0 = clk::now();
 
-    // ---- 6. matvec plan: pieces grouped by row tile ----
+    // ---- 5. tile-major matrix pool: pieces (leaf block x row tile) sorted by
+    //         tile, then filled with near-field entries and U rows ----
     {
         const int64_t nb = h->n_adm + h->n_dense;
-        DevBuf cnt, pieces_unsorted, keys, vals, sscr;
+        DevBuf cnt, unsorted, keys, vals, sscr, psize, pcols;
         alloc(cnt, (nb + 1) * 8, "piece counts");
         check(launch_extent(h->adm.as<int4>(), h->n_adm, 6, 0, h->rank.as<int32_t>(),
                             h->tile_of_point.as<int32_t>(), cnt.as<int64_t>(), st),
@@ -553,25 +532,19 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
         check(launch_extent(h->dense.as<int4>(), h->n_dense, 6, 0, nullptr,
                             h->tile_of_point.as<int32_t>(), cnt.as<int64_t>() + h->n_adm, st),
               "extent");
-        DevBuf big_scr;
-        alloc(big_scr, scan_scratch_bytes(nb + 1) + 64, "piece scan");
-        check(exclusive_scan_i64(cnt.as<int64_t>(), nb, total.as<int64_t>(), big_scr.p, st),
-              "piece scan");
-        h->npieces = read_scalar(total.as<int64_t>(), st);
-        alloc(pieces_unsorted, h->npieces * sizeof(Piece), "pieces");
+        h->npieces = scan(cnt.as<int64_t>(), nb);
+        alloc(unsorted, h->npieces * sizeof(Piece), "pieces");
         alloc(keys, h->npieces * 8, "piece keys");
         alloc(vals, h->npieces * 4, "piece vals");
         check(launch_piece_fill(h->adm.as<int4>(), h->n_adm, h->rank.as<int32_t>(),
                                 h->tile_of_point.as<int32_t>(), h->tile_lo.as<int32_t>(),
-                                cnt.as<int64_t>(), h->uoff.as<int64_t>(), h->toff.as<int64_t>(),
-                                n, 1, 0, pieces_unsorted.as<Piece>(), keys.as<uint64_t>(),
-                                vals.as<uint32_t>(), st),
+                                cnt.as<int64_t>(), h->toff.as<int64_t>(), n, 0,
+                                unsorted.as<Piece>(), keys.as<uint64_t>(), vals.as<uint32_t>(), st),
               "piece fill");
         check(launch_piece_fill(h->dense.as<int4>(), h->n_dense, nullptr,
                                 h->tile_of_point.as<int32_t>(), h->tile_lo.as<int32_t>(),
-                                cnt.as<int64_t>() + h->n_adm, h->near_off.as<int64_t>(), nullptr,
-                                0, 0, 0, pieces_unsorted.as<Piece>(), keys.as<uint64_t>(),
-                                vals.as<uint32_t>(), st),
+                                cnt.as<int64_t>() + h->n_adm, nullptr, 0, 0, unsorted.as<Piece>(),
+                                keys.as<uint64_t>(), vals.as<uint32_t>(), st),
               "piece fill");
         int bits = 1;
         while ((1ll << bits) <= h->ntiles) ++bits;
@@ -580,16 +553,49 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
                                st),
               "piece sort");
         alloc(h->pieces, h->npieces * sizeof(Piece), "sorted pieces");
-        check(launch_piece_gather(pieces_unsorted.as<Piece>(), vals.as<uint32_t>(), h->npieces,
-                                  h->pieces.as<Piece>(), st),
+        alloc(psize, (h->npieces + 1) * 8, "piece sizes");
+        alloc(pcols, (h->npieces + 1) * 8, "piece columns");
+        check(launch_piece_gather(unsorted.as<Piece>(), vals.as<uint32_t>(), h->npieces,
+                                  h->pieces.as<Piece>(), psize.as<int64_t>(), pcols.as<int64_t>(),
+                                  h->tile_lo.as<int32_t>(), (int)esz, st),
               "piece gather");
-        alloc(h->tile_ptr, (h->ntiles + 1) * 8, "tile ptr");
-        check(launch_tile_offsets(keys.as<uint64_t>(), h->npieces, h->ntiles,
-                                  h->tile_ptr.as<int64_t>(), st),
+        h->pool_entries = scan(psize.as<int64_t>(), h->npieces);
+        h->ncols_total = scan(pcols.as<int64_t>(), h->npieces);
+        alloc(h->widx, (size_t)std::max<int64_t>(h->ncols_total, 1) * 8, "column weights");
+        check(launch_piece_layout(h->pieces.as<Piece>(), h->npieces, psize.as<int64_t>(),
+                                  pcols.as<int64_t>(), h->widx.as<int64_t>(), st),
+              "piece layout");
+        DevBuf tptr;
+        alloc(tptr, (h->ntiles + 1) * 8, "tile ptr");
+        check(launch_tile_offsets(keys.as<uint64_t>(), h->npieces, h->ntiles, tptr.as<int64_t>(),
+                                  st),
               "tile ptr");
-        check(hipStreamSynchronize(st), "plan sync");
+        alloc(h->tile_col, (h->ntiles + 1) * 8, "tile columns");
+        alloc(h->tile_doff, (h->ntiles + 1) * 8, "tile data offsets");
+        check(launch_tile_meta(tptr.as<int64_t>(), h->ntiles, h->npieces, psize.as<int64_t>(),
+                               pcols.as<int64_t>(), h->ncols_total, h->pool_entries,
+                               h->tile_col.as<int64_t>(), h->tile_doff.as<int64_t>(), st),
+              "tile meta");
+        alloc(h->pool, (size_t)std::max<int64_t>(h->pool_entries, 1) * esz, "matrix pool");
+        check(launch_piece_data(h->pieces.as<Piece>(), h->npieces, h->tile_lo.as<int32_t>(),
+                                h->adm.as<int4>(), h->dense.as<int4>(), cu.as<int64_t>(), Ucap.p,
+                                f64 ? h->soa64.p : h->soa32.p, n, d,
+                                KernelFn{(int)h->kern.kind, h->kern.p0}, h->pool.p, f64, st),
+              "piece data");
+        check(hipStreamSynchronize(st), "pool sync");
     }
-    S.phase_ms[6] = ms_since(t0);
+    Ucap.release();
+    // near-field entry count (algorithmic, unpadded)
+    if (h->n_dense > 0) {
+        DevBuf ne;
+        alloc(ne, (h->n_dense + 1) * 8, "near entries");
+        check(launch_extent(h->dense.as<int4>(), h->n_dense, 2, 0, nullptr, nullptr,
+                            ne.as<int64_t>(), st),
+              "extent");
+        h->near_entries = scan(ne.as<int64_t>(), h->n_dense);
+    }
+    S.phase_ms[5] = ms_since(t0);
+    S.phase_ms[6] = 0.0;
 
     // ---- stats ----
     S.n = n;
@@ -742,9 +748,9 @@ hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype
                               h->vecpool.p, h->n, f64, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
     if (e == hipSuccess)
-        e = launch_rowtile(h->ntiles, h->tile_lo.as<int32_t>(), h->tile_ptr.as<int64_t>(),
-                           h->pieces.as<Piece>(), h->near.p, h->U.p, h->vecpool.p,
-                           h->perm.as<int32_t>(), h->n, alpha, beta, h->prm.sigma2, z,
+        e = launch_rowtile(h->ntiles, h->tile_lo.as<int32_t>(), h->tile_col.as<int64_t>(),
+                           h->tile_doff.as<int64_t>(), h->widx.as<int64_t>(), h->pool.p,
+                           h->vecpool.p, h->perm.as<int32_t>(), alpha, beta, h->prm.sigma2, z,
                            h->max_tile, f64, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
     if (e != hipSuccess) {
@@ -874,23 +880,38 @@ hmx_status hmx_get_factors(hmx_hmatrix h, int64_t leaf, double* U, double* V, in
     try {
         int4 bl;
         int32_t r;
-        int64_t uo, vo;
+        int64_t vo;
         check(hipMemcpyAsync(&bl, h->adm.as<int4>() + leaf, 16, hipMemcpyDeviceToHost, st), "blk");
         check(hipMemcpyAsync(&r, h->rank.as<int32_t>() + leaf, 4, hipMemcpyDeviceToHost, st), "r");
-        check(hipMemcpyAsync(&uo, h->uoff.as<int64_t>() + leaf, 8, hipMemcpyDeviceToHost, st), "uo");
         check(hipMemcpyAsync(&vo, h->voff.as<int64_t>() + leaf, 8, hipMemcpyDeviceToHost, st), "vo");
         check(hipStreamSynchronize(st), "sync");
         const int64_t m = bl.y - bl.x, nc = bl.w - bl.z;
+        const size_t esz = h->esz;
         *rank = r;
-        if (h->f64) {
-            d2h(U, h->U.as<double>() + uo, r * m * 8, st);
-            d2h(V, h->V.as<double>() + vo, r * nc * 8, st);
-        } else {
-            std::vector<float> u(r * m), v(r * nc);
-            d2h(u.data(), h->U.as<float>() + uo, r * m * 4, st);
-            d2h(v.data(), h->V.as<float>() + vo, r * nc * 4, st);
-            for (int64_t e = 0; e < r * m; ++e) U[e] = u[e];
-            for (int64_t e = 0; e < r * nc; ++e) V[e] = v[e];
+        auto to_double = [&](const std::vector<char>& raw, size_t cnt, double* out) {
+            for (size_t e = 0; e < cnt; ++e)
+                out[e] = esz == 8 ? ((const double*)raw.data())[e] : ((const float*)raw.data())[e];
+        };
+        // V: one column-major region
+        std::vector<char> raw((size_t)r * nc * esz + 1);
+        d2h(raw.data(), (const char*)h->V.p + vo * esz, (size_t)r * nc * esz, st);
+        to_double(raw, (size_t)r * nc, V);
+        // U: the factor pieces of this leaf, one per row tile, in the tile-major pool
+        std::vector<Piece> pcs(h->npieces);
+        d2h(pcs.data(), h->pieces.p, h->npieces * sizeof(Piece), st);
+        std::vector<int32_t> tlo(h->ntiles + 1);
+        d2h(tlo.data(), h->tile_lo.p, (h->ntiles + 1) * 4, st);
+        for (const Piece& pc : pcs) {
+            if (pc.blk != (int32_t)leaf) continue;
+            const int mt = tlo[pc.tile + 1] - tlo[pc.tile];
+            const int vecn = 16 / (int)esz;
+            const int ld = (mt + vecn - 1) / vecn * vecn;
+            std::vector<char> col((size_t)ld * r * esz + 1);
+            d2h(col.data(), (const char*)h->pool.p + pc.d_off * esz, (size_t)ld * r * esz, st);
+            std::vector<double> cd((size_t)ld * r);
+            to_double(col, (size_t)ld * r, cd.data());
+            for (int l = 0; l < r; ++l)
+                for (int i = 0; i < mt; ++i) U[(int64_t)l * m + pc.row0 + i] = cd[(size_t)l * ld + i];
         }
     } catch (const Fail& f) {
         return f.s;

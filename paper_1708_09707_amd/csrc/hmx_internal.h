@@ -160,21 +160,15 @@ struct AcaArgs {
 hipError_t launch_aca(const AcaArgs& a, int f64, hipStream_t st);
 
 // near field and matvec (k_mvp.hip)
-hipError_t launch_near_assemble(const void* soa, int64_t n, int d, KernelFn kern,
-                                const int4* blocks, int64_t nblocks, const int64_t* off,
-                                void* A, int f64, hipStream_t st);
-hipError_t launch_compact_factors(const int4* blocks, int64_t nblocks, const int32_t* rank,
-                                  const int64_t* cap_uoff, const int64_t* cap_voff,
-                                  const int64_t* uoff, const int64_t* voff, const void* Ucap,
-                                  const void* Vcap, void* U, void* V, int f64, hipStream_t st);
-
+// A piece is the part of one leaf block inside one row tile (leaf cluster);
+// the matrix pool stores the pieces of each tile contiguously (tile-major).
 struct Piece {
-    int64_t a_off;  // element offset of the piece's first row in its pool
-    int64_t v_off;  // element offset of the vector segment in the vector pool
-    int32_t ld;     // column stride (rows of the whole block)
+    int64_t d_off;  // element offset of the piece in the matrix pool
+    int64_t v_off;  // element offset of its weights in the vector pool
+    int32_t blk;    // admissible leaf b >= 0 (factor piece), or -(dense leaf + 1)
+    int32_t tile;
     int32_t ncols;
-    int32_t pool;   // 0 = near-field pool, 1 = U pool
-    int32_t pad;
+    int32_t row0;   // first row of the tile inside the block's tau
 };
 // per-block sizes: mode 0: m * mult, 1: n * mult, 2: m * n, 3: r * m, 4: r * n,
 // 5: r, 6: row tiles covered by tau (0 for an admissible leaf of rank 0)
@@ -183,14 +177,27 @@ hipError_t launch_extent(const int4* blocks, int64_t nb, int mode, int64_t mult,
                          hipStream_t st);
 hipError_t launch_piece_fill(const int4* blocks, int64_t nblocks, const int32_t* rank,
                              const int32_t* tile_of_point, const int32_t* tile_lo,
-                             const int64_t* piece_off, const int64_t* data_off,
-                             const int64_t* vec_off_blk, int64_t vec_base, int pool,
+                             const int64_t* piece_off, const int64_t* toff, int64_t vec_base,
                              int64_t piece_base, Piece* pieces, uint64_t* keys, uint32_t* vals,
                              hipStream_t st);
 hipError_t launch_piece_gather(const Piece* src, const uint32_t* order, int64_t npieces,
-                               Piece* dst, hipStream_t st);
+                               Piece* dst, int64_t* size, int64_t* cols, const int32_t* tile_lo,
+                               int esz, hipStream_t st);
+hipError_t launch_piece_layout(Piece* pieces, int64_t np, const int64_t* doff,
+                               const int64_t* coff, int64_t* widx, hipStream_t st);
 hipError_t launch_tile_offsets(const uint64_t* sorted_tile, int64_t npieces, int64_t ntiles,
                                int64_t* tile_ptr, hipStream_t st);
+hipError_t launch_tile_meta(const int64_t* tile_ptr, int64_t ntiles, int64_t np,
+                            const int64_t* doff, const int64_t* coff, int64_t total_cols,
+                            int64_t total_data, int64_t* tile_col, int64_t* tile_doff,
+                            hipStream_t st);
+hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* tile_lo,
+                             const int4* adm, const int4* dense, const int64_t* ucap_off,
+                             const void* Ucap, const void* soa, int64_t n, int d, KernelFn kern,
+                             void* pool, int f64, hipStream_t st);
+hipError_t launch_compact_v(const int4* blocks, int64_t nblocks, const int32_t* rank,
+                            const int64_t* cap_voff, const int64_t* voff, const void* Vcap,
+                            void* V, int f64, hipStream_t st);
 hipError_t launch_gather_x(const void* x, const int32_t* perm, int64_t n, void* xm, int f64,
                            hipStream_t st);
 // out[0] = max and out[1] = sum of n non-negative int32 values (device)
@@ -201,10 +208,9 @@ hipError_t launch_col_block(const int32_t* rank, const int64_t* toff, int64_t na
 hipError_t launch_far_phase1(const int4* adm, const int32_t* col_block, const int64_t* voff,
                              const int64_t* toff, int64_t ncols_total, const void* V,
                              void* vecpool, int64_t n, int f64, hipStream_t st);
-hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t* tile_ptr,
-                          const Piece* pieces, const void* near, const void* U,
-                          const void* vecpool, const int32_t* perm, int64_t n, double alpha,
-                          double beta, double sigma2, void* z, int max_tile, int f64,
-                          hipStream_t st);
+hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t* tile_col,
+                          const int64_t* tile_doff, const int64_t* widx, const void* pool,
+                          const void* vecpool, const int32_t* perm, double alpha, double beta,
+                          double sigma2, void* z, int max_tile, int f64, hipStream_t st);
 
 }  // namespace hmx

@@ -348,29 +348,6 @@ __global__ __launch_bounds__(kAcaThreads) void aca_kernel(
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void compact_kernel(const int4* __restrict__ blocks,
-                                                      int64_t nblocks,
-                                                      const int32_t* __restrict__ rank,
-                                                      const int64_t* __restrict__ cu,
-                                                      const int64_t* __restrict__ cv,
-                                                      const int64_t* __restrict__ eu,
-                                                      const int64_t* __restrict__ ev,
-                                                      const T* __restrict__ Ucap,
-                                                      const T* __restrict__ Vcap,
-                                                      T* __restrict__ U, T* __restrict__ V) {
-    for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
-        const int4 bl = blocks[b];
-        const int64_t m = bl.y - bl.x, nc = bl.w - bl.z, r = rank[b];
-        const T* su = Ucap + cu[b];
-        const T* sv = Vcap + cv[b];
-        T* du = U + eu[b];
-        T* dv = V + ev[b];
-        for (int64_t e = threadIdx.x; e < r * m; e += blockDim.x) du[e] = su[e];
-        for (int64_t e = threadIdx.x; e < r * nc; e += blockDim.x) dv[e] = sv[e];
-    }
-}
-
 }  // namespace
 
 hipError_t launch_aca(const AcaArgs& a, int f64, hipStream_t st) {
@@ -390,23 +367,6 @@ hipError_t launch_aca(const AcaArgs& a, int f64, hipStream_t st) {
                            a.kmax, a.eps, a.aca_eta, (float)a.eps0, a.fixed, (float*)a.U,
                            (float*)a.V, a.rank, a.steps);
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_compact_factors(const int4* blocks, int64_t nblocks, const int32_t* rank,
-                                  const int64_t* cap_uoff, const int64_t* cap_voff,
-                                  const int64_t* uoff, const int64_t* voff, const void* Ucap,
-                                  const void* Vcap, void* U, void* V, int f64, hipStream_t st) {
-    if (nblocks == 0) return hipSuccess;
-    const unsigned grid = (unsigned)(nblocks < 65536 * 16 ? nblocks : 65536 * 16);
-    if (f64)
-        hipLaunchKernelGGL(compact_kernel<double>, dim3(grid), dim3(256), 0, st, blocks, nblocks,
-                           rank, cap_uoff, cap_voff, uoff, voff, (const double*)Ucap,
-                           (const double*)Vcap, (double*)U, (double*)V);
-    else
-        hipLaunchKernelGGL(compact_kernel<float>, dim3(grid), dim3(256), 0, st, blocks, nblocks,
-                           rank, cap_uoff, cap_voff, uoff, voff, (const float*)Ucap,
-                           (const float*)Vcap, (float*)U, (float*)V);
     return hipGetLastError();
 }
 

@@ -1,54 +1,34 @@
 // Near-field assembly and the batched H-matrix-vector product (Algorithm 3
 // in flat form, Section 5.4).
 //
-// Storage (all column-major, one contiguous region per block):
-//   near pool : A|tau x sigma for every dense leaf (m x n)
-//   U pool    : U (m x r) for every admissible leaf, V pool: V (n x r)
-//   vector pool: [ x in Morton order (n) | t_b = V_b^T x|sigma (sum r) ]
-// Matvec = gather x -> phase 1 (t_b for every admissible leaf) -> phase 2
-// (one workgroup per leaf cluster of rows: z|tile = sum of its pieces, where
-// a piece is the tile's rows of a dense block times x|sigma or of U_b times
-// t_b) -> scatter to the original order with alpha, beta, sigma2.
-// Every z row is written by exactly one workgroup and every sum has a fixed
-// order, so the product is deterministic.
+// Storage.  The rows of the matrix are cut into row tiles, the leaf clusters
+// of the cluster tree.  A piece is the part of one leaf block that falls in
+// one tile: the tile's rows of a dense block A|tau x sigma (ncols = |sigma|,
+// weights x|sigma), or the tile's rows of the factor U of an admissible block
+// (ncols = rank, weights t_b = V_b^T x|sigma).  All pieces of a tile are
+// stored one after another, column-major with the tile's leading dimension
+// ld_t = (tile rows rounded up to 16 bytes), so a tile is one contiguous
+// ld_t x C_t matrix in the matrix pool and column k of it is multiplied by
+// vec[widx[k]].  Padding rows hold zeros.
+//   vector pool: [ x in Morton order (n) | t_b for every admissible leaf ]
+//   V pool     : V_b (n_b x r_b) column-major per admissible leaf.
+// Matvec = gather x -> phase 1 (all t_b) -> phase 2 (one workgroup per tile,
+// streaming its contiguous region) -> scatter to the original order with
+// alpha, beta, sigma2.  Each z row is written by one workgroup and every sum
+// has a fixed order, so the product is deterministic.
 #include "hmx_internal.h"
 
 namespace hmx {
 
 namespace {
 
-// ---------------------------------------------------------------------------
-// near field: A[q m + i] = phi(y_{tlo+i}, y_{slo+q})
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void near_kernel(const T* __restrict__ soa, int64_t n, int d,
-                                                   KernelEval<T> K,
-                                                   const int4* __restrict__ blocks,
-                                                   int64_t nblocks,
-                                                   const int64_t* __restrict__ off,
-                                                   T* __restrict__ A) {
-    for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
-        const int4 bl = blocks[b];
-        const int m = bl.y - bl.x, nc = bl.w - bl.z;
-        T* __restrict__ out = A + off[b];
-        const int64_t tot = (int64_t)m * nc;
-        int i = threadIdx.x, q = 0;
-        while (i >= m) {
-            i -= m;
-            ++q;
-        }
-        for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
-            T x[3], y[3];
-            load_pt(soa, n, d, (int64_t)bl.x + i, x);
-            load_pt(soa, n, d, (int64_t)bl.z + q, y);
-            out[e] = phi(K, x, y, d);
-            i += blockDim.x;
-            while (i >= m) {
-                i -= m;
-                ++q;
-            }
-        }
-    }
+unsigned grid_cap(int64_t nb, int64_t cap) { return (unsigned)(nb < cap ? nb : cap); }
+
+// elements per 16-byte vector for an entry size, and the padded tile height
+__device__ __host__ __forceinline__ int vec_elems(int esz) { return 16 / esz; }
+__device__ __host__ __forceinline__ int tile_ld(int rows, int esz) {
+    const int v = vec_elems(esz);
+    return (rows + v - 1) / v * v;
 }
 
 // per-block sizes: mode 0: m * mult, 1: n * mult, 2: m * n, 3: r * m, 4: r * n,
@@ -70,47 +50,70 @@ __global__ void extent_kernel(const int4* __restrict__ blocks, int64_t nb, int m
         case 4: v = (int64_t)rank[b] * nc; break;
         case 5: v = rank[b]; break;
         default:
-            v = (rank && rank[b] == 0) ? 0
-                                       : (int64_t)(tile_of_point[bl.y - 1] - tile_of_point[bl.x] + 1);
+            v = (rank && rank[b] == 0)
+                    ? 0
+                    : (int64_t)(tile_of_point[bl.y - 1] - tile_of_point[bl.x] + 1);
     }
     out[b] = v;
 }
 
+// one piece per (leaf block, tile of its rows); key = tile for the stable sort
 __global__ void piece_fill_kernel(const int4* __restrict__ blocks, int64_t nb,
                                   const int32_t* __restrict__ rank,
                                   const int32_t* __restrict__ tile_of_point,
                                   const int32_t* __restrict__ tile_lo,
                                   const int64_t* __restrict__ piece_off,
-                                  const int64_t* __restrict__ data_off,
-                                  const int64_t* __restrict__ vec_off_blk, int64_t vec_base,
-                                  int pool, int64_t piece_base, Piece* __restrict__ pieces,
+                                  const int64_t* __restrict__ toff, int64_t vec_base,
+                                  int64_t piece_base, Piece* __restrict__ pieces,
                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (b >= nb) return;
     const int4 bl = blocks[b];
     const int r = rank ? rank[b] : 0;
     if (rank && r == 0) return;
-    const int m = bl.y - bl.x;
     const int t0 = tile_of_point[bl.x], t1 = tile_of_point[bl.y - 1];
     int64_t p = piece_base + piece_off[b];
     for (int t = t0; t <= t1; ++t, ++p) {
         Piece pc;
-        pc.a_off = data_off[b] + (tile_lo[t] - bl.x);
-        pc.v_off = rank ? vec_base + vec_off_blk[b] : (int64_t)bl.z;
-        pc.ld = m;
+        pc.d_off = 0;
+        pc.v_off = rank ? vec_base + toff[b] : (int64_t)bl.z;
+        pc.blk = rank ? (int32_t)b : -(int32_t)b - 1;
+        pc.tile = t;
         pc.ncols = rank ? r : (bl.w - bl.z);
-        pc.pool = pool;
-        pc.pad = 0;
+        pc.row0 = tile_lo[t] - bl.x;
         pieces[p] = pc;
         keys[p] = (uint64_t)t;
         vals[p] = (uint32_t)p;
     }
 }
 
-__global__ void piece_gather_kernel(const Piece* __restrict__ src, const uint32_t* __restrict__ order,
-                                    int64_t np, Piece* __restrict__ dst) {
+// sorted order -> pieces; also each piece's data size and column count
+__global__ void piece_gather_kernel(const Piece* __restrict__ src,
+                                    const uint32_t* __restrict__ order, int64_t np,
+                                    Piece* __restrict__ dst, int64_t* __restrict__ size,
+                                    int64_t* __restrict__ cols, const int32_t* __restrict__ tile_lo,
+                                    int esz) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < np) dst[i] = src[order[i]];
+    if (i >= np) return;
+    const Piece pc = src[order[i]];
+    dst[i] = pc;
+    const int mt = tile_lo[pc.tile + 1] - tile_lo[pc.tile];
+    size[i] = (int64_t)tile_ld(mt, esz) * pc.ncols;
+    cols[i] = pc.ncols;
+}
+
+// after the scans: piece data offsets, and the weight index of every column
+__global__ void piece_layout_kernel(Piece* __restrict__ pieces, int64_t np,
+                                    const int64_t* __restrict__ doff,
+                                    const int64_t* __restrict__ coff,
+                                    int64_t* __restrict__ widx) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    Piece pc = pieces[i];
+    pc.d_off = doff[i];
+    pieces[i] = pc;
+    const int64_t c0 = coff[i];
+    for (int c = 0; c < pc.ncols; ++c) widx[c0 + c] = pc.v_off + c;
 }
 
 // tile_ptr[t] = number of pieces with tile < t (lower bound in the sorted keys)
@@ -127,6 +130,67 @@ __global__ void tile_ptr_kernel(const uint64_t* __restrict__ keys, int64_t np, i
             hi = mid;
     }
     ptr[t] = lo;
+}
+
+// per tile: first column and data offset (from its first piece)
+__global__ void tile_meta_kernel(const int64_t* __restrict__ tile_ptr, int64_t ntiles,
+                                 int64_t np, const int64_t* __restrict__ doff,
+                                 const int64_t* __restrict__ coff, int64_t total_cols,
+                                 int64_t total_data, int64_t* __restrict__ tile_col,
+                                 int64_t* __restrict__ tile_doff) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t > ntiles) return;
+    const int64_t p = tile_ptr[t];
+    tile_col[t] = p < np ? coff[p] : total_cols;
+    tile_doff[t] = p < np ? doff[p] : total_data;
+}
+
+// Fill the matrix pool piece by piece: dense pieces evaluate phi (the near
+// field, Section 5.4.2), factor pieces copy the tile's rows of U_b from the
+// ACA capacity pool.  Padding rows are zero.
+template <typename T>
+__global__ __launch_bounds__(256) void piece_data_kernel(
+    const Piece* __restrict__ pieces, int64_t np, const int32_t* __restrict__ tile_lo,
+    const int4* __restrict__ adm, const int4* __restrict__ dense,
+    const int64_t* __restrict__ ucap_off, const T* __restrict__ Ucap, const T* __restrict__ soa,
+    int64_t n, int d, KernelEval<T> K, T* __restrict__ pool) {
+    constexpr int esz = sizeof(T);
+    for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
+        const Piece pc = pieces[p];
+        const int32_t r0 = tile_lo[pc.tile];
+        const int mt = tile_lo[pc.tile + 1] - r0;
+        const int ld = tile_ld(mt, esz);
+        T* __restrict__ out = pool + pc.d_off;
+        const int64_t tot = (int64_t)ld * pc.ncols;
+        const bool is_factor = pc.blk >= 0;
+        const int4 bl = is_factor ? adm[pc.blk] : dense[-pc.blk - 1];
+        const int m = bl.y - bl.x;
+        const T* __restrict__ src = is_factor ? Ucap + ucap_off[pc.blk] + pc.row0 : nullptr;
+        int i = threadIdx.x, c = 0;
+        while (i >= ld) {
+            i -= ld;
+            ++c;
+        }
+        for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+            T v = (T)0;
+            if (i < mt) {
+                if (is_factor) {
+                    v = src[(int64_t)c * m + i];
+                } else {
+                    T x[3], y[3];
+                    load_pt(soa, n, d, (int64_t)r0 + i, x);
+                    load_pt(soa, n, d, (int64_t)bl.z + c, y);
+                    v = phi(K, x, y, d);
+                }
+            }
+            out[e] = v;
+            i += blockDim.x;
+            while (i >= ld) {
+                i -= ld;
+                ++c;
+            }
+        }
+    }
 }
 
 template <typename T>
@@ -161,8 +225,55 @@ __device__ __forceinline__ double vget<double2, double>(const double2& v, int e)
     return e == 0 ? v.x : v.y;
 }
 
+// out[0] = max, out[1] = sum of n int32 values (integer atomics: order-free)
+__global__ void int_stats_kernel(const int32_t* __restrict__ a, int64_t n,
+                                 unsigned long long* __restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int32_t v = i < n ? a[i] : 0;
+    int32_t mx = v;
+    int64_t sm = v;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int32_t u = __shfl_xor(mx, o, 64);
+        mx = u > mx ? u : mx;
+        sm += __shfl_xor(sm, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&out[0], (unsigned long long)mx);
+        atomicAdd(&out[1], (unsigned long long)sm);
+    }
+}
+
+// V compaction: the first r_b columns of each V_b from the capacity pool
+template <typename T>
+__global__ __launch_bounds__(256) void compact_v_kernel(const int4* __restrict__ blocks,
+                                                        int64_t nblocks,
+                                                        const int32_t* __restrict__ rank,
+                                                        const int64_t* __restrict__ cv,
+                                                        const int64_t* __restrict__ ev,
+                                                        const T* __restrict__ Vcap,
+                                                        T* __restrict__ V) {
+    for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
+        const int4 bl = blocks[b];
+        const int64_t nc = bl.w - bl.z, r = rank[b];
+        const T* sv = Vcap + cv[b];
+        T* dv = V + ev[b];
+        for (int64_t e = threadIdx.x; e < r * nc; e += blockDim.x) dv[e] = sv[e];
+    }
+}
+
+// column -> admissible leaf map for the flattened factor columns
+__global__ void col_block_kernel(const int32_t* __restrict__ rank,
+                                 const int64_t* __restrict__ toff, int64_t nadm,
+                                 int32_t* __restrict__ col_block) {
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= nadm) return;
+    const int64_t o = toff[b];
+    for (int l = 0; l < rank[b]; ++l) col_block[o + l] = (int32_t)b;
+}
+
 // phase 1: t_b[l] = sum_j V_b[j, l] x[slo + j]; one wave per column of the
-// flattened list of all factor columns (col_block maps a column to its leaf)
+// flattened list of all factor columns
 template <typename T>
 __global__ __launch_bounds__(256) void far_phase1_kernel(
     const int4* __restrict__ adm, const int32_t* __restrict__ col_block,
@@ -206,119 +317,75 @@ __global__ __launch_bounds__(256) void far_phase1_kernel(
     if (lane == 0) vec[n + k] = acc;
 }
 
-// out[0] = max, out[1] = sum of n int32 values (integer atomics: order-free)
-__global__ void int_stats_kernel(const int32_t* __restrict__ a, int64_t n,
-                                 unsigned long long* __restrict__ out) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int32_t v = i < n ? a[i] : 0;
-    int32_t mx = v;
-    int64_t sm = v;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const int32_t u = __shfl_xor(mx, o, 64);
-        mx = u > mx ? u : mx;
-        sm += __shfl_xor(sm, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        atomicMax(&out[0], (unsigned long long)mx);
-        atomicAdd(&out[1], (unsigned long long)sm);
-    }
-}
-
-// column -> admissible leaf map for the flattened factor columns
-__global__ void col_block_kernel(const int32_t* __restrict__ rank, const int64_t* __restrict__ toff,
-                                 int64_t nadm, int32_t* __restrict__ col_block) {
-    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (b >= nadm) return;
-    const int64_t o = toff[b];
-    for (int l = 0; l < rank[b]; ++l) col_block[o + l] = (int32_t)b;
-}
-
-// phase 2: one workgroup per row tile.  The 4 waves split into G = 4 * (64/L)
-// column groups of L lanes; lane q of a group owns RV vectors of VEC rows
-// (vector v*L + q), so a group covers L*RV*VEC rows with 16-byte loads when
-// the piece is aligned (scalar loads otherwise).  Groups take interleaved
-// columns of every piece; their partial rows are summed in LDS in a fixed
-// order and the tile is scattered to the original order.
+// phase 2: one workgroup per row tile.  The tile is a contiguous ld x C
+// column-major matrix; column k is weighted by vec[widx[k]].  The 4 waves
+// split into G = 4 * (64 / L) column groups of L lanes; lane q of a group
+// owns RV 16-byte vectors of rows (vector v * L + q).  Groups take
+// interleaved columns (4 in flight per lane); their partial rows are summed
+// in LDS in a fixed order and the tile is scattered to the original order.
 constexpr int kTileThreads = 256;
 
-template <typename T, int RV>
+template <typename T, int L, int RV>
 __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
-    int64_t ntiles, const int32_t* __restrict__ tile_lo, const int64_t* __restrict__ tile_ptr,
-    const Piece* __restrict__ pieces, const T* __restrict__ near, const T* __restrict__ U,
-    const T* __restrict__ vec, const int32_t* __restrict__ perm, T alpha, T beta, T sigma2,
-    T* __restrict__ z, int L) {
+    int64_t ntiles, const int32_t* __restrict__ tile_lo, const int64_t* __restrict__ tile_col,
+    const int64_t* __restrict__ tile_doff, const int64_t* __restrict__ widx,
+    const T* __restrict__ pool, const T* __restrict__ vec, const int32_t* __restrict__ perm,
+    T alpha, T beta, T sigma2, T* __restrict__ z) {
     using V16 = typename Vec16<T>::type;
     constexpr int VEC = Vec16<T>::n;
-    extern __shared__ unsigned char red_raw[];
-    T* red = (T*)red_raw;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int S = 64 / L;
-    const int G = 4 * S;
-    const int g = w * S + lane / L;
+    constexpr int S = 64 / L;
+    constexpr int G = 4 * S;
+    constexpr int RPG = L * RV * VEC;  // rows per pass
+    __shared__ T red[G * RPG];
+    const int tid = threadIdx.x, lane = tid & 63;
+    // the group index is wave-uniform when a group is a whole wave
+    const int g = (S == 1) ? __builtin_amdgcn_readfirstlane(tid >> 6) : (tid >> 6) * S + lane / L;
     const int q = lane % L;
-    const int rpg = L * RV * VEC;  // rows per group pass
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int32_t t0 = tile_lo[t];
-        const int mt = tile_lo[t + 1] - t0;
-        const int64_t p0 = tile_ptr[t], p1 = tile_ptr[t + 1];
-        for (int rb = 0; rb < mt; rb += rpg) {
-            const int mc = (mt - rb) < rpg ? (mt - rb) : rpg;
+        const int32_t r0 = tile_lo[t];
+        const int mt = tile_lo[t + 1] - r0;
+        const int ld = (mt + VEC - 1) / VEC * VEC;
+        const int64_t k0 = tile_col[t], nk = tile_col[t + 1] - k0;
+        const T* __restrict__ base0 = pool + tile_doff[t];
+        const int64_t* __restrict__ wi = widx + k0;
+        for (int rb = 0; rb < ld; rb += RPG) {
+            const int nvec = ((ld - rb) < RPG ? (ld - rb) : RPG) / VEC;  // vectors in this pass
+            const T* __restrict__ base = base0 + rb;
             T acc[RV][VEC];
 #pragma unroll
             for (int v = 0; v < RV; ++v)
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) acc[v][e] = 0;
-            for (int64_t p = p0; p < p1; ++p) {
-                const Piece pc = pieces[p];
-                const int64_t aoff = pc.a_off + rb;
-                const T* __restrict__ base = (pc.pool ? U : near) + aoff;
-                const T* __restrict__ wv = vec + pc.v_off;
-                const int ld = pc.ld, ncols = pc.ncols;
-                if (((aoff | (int64_t)ld | (int64_t)mt) % VEC) == 0) {
-                    int c = g;
-                    for (; c + 3 * G < ncols; c += 4 * G) {
-                        const T w0 = wv[c], w1 = wv[c + G], w2 = wv[c + 2 * G], w3 = wv[c + 3 * G];
-                        const V16* c0 = (const V16*)(base + (int64_t)c * ld);
-                        const V16* c1 = (const V16*)(base + (int64_t)(c + G) * ld);
-                        const V16* c2 = (const V16*)(base + (int64_t)(c + 2 * G) * ld);
-                        const V16* c3 = (const V16*)(base + (int64_t)(c + 3 * G) * ld);
+            int64_t c = g;
+            for (; c + 3 * G < nk; c += 4 * G) {
+                const T w0 = vec[wi[c]], w1 = vec[wi[c + G]], w2 = vec[wi[c + 2 * G]],
+                        w3 = vec[wi[c + 3 * G]];
+                const V16* c0 = (const V16*)(base + c * ld);
+                const V16* c1 = (const V16*)(base + (c + G) * ld);
+                const V16* c2 = (const V16*)(base + (c + 2 * G) * ld);
+                const V16* c3 = (const V16*)(base + (c + 3 * G) * ld);
 #pragma unroll
-                        for (int v = 0; v < RV; ++v) {
-                            const int vi = v * L + q;
-                            if (vi * VEC < mc) {
-                                const V16 a0 = c0[vi], a1 = c1[vi], a2 = c2[vi], a3 = c3[vi];
+                for (int v = 0; v < RV; ++v) {
+                    const int vi = v * L + q;
+                    if (vi < nvec) {
+                        const V16 a0 = c0[vi], a1 = c1[vi], a2 = c2[vi], a3 = c3[vi];
 #pragma unroll
-                                for (int e = 0; e < VEC; ++e)
-                                    acc[v][e] += vget<V16, T>(a0, e) * w0 + vget<V16, T>(a1, e) * w1 +
-                                                 vget<V16, T>(a2, e) * w2 + vget<V16, T>(a3, e) * w3;
-                            }
-                        }
+                        for (int e = 0; e < VEC; ++e)
+                            acc[v][e] += vget<V16, T>(a0, e) * w0 + vget<V16, T>(a1, e) * w1 +
+                                         vget<V16, T>(a2, e) * w2 + vget<V16, T>(a3, e) * w3;
                     }
-                    for (; c < ncols; c += G) {
-                        const T w0 = wv[c];
-                        const V16* c0 = (const V16*)(base + (int64_t)c * ld);
+                }
+            }
+            for (; c < nk; c += G) {
+                const T w0 = vec[wi[c]];
+                const V16* c0 = (const V16*)(base + c * ld);
 #pragma unroll
-                        for (int v = 0; v < RV; ++v) {
-                            const int vi = v * L + q;
-                            if (vi * VEC < mc) {
-                                const V16 a0 = c0[vi];
+                for (int v = 0; v < RV; ++v) {
+                    const int vi = v * L + q;
+                    if (vi < nvec) {
+                        const V16 a0 = c0[vi];
 #pragma unroll
-                                for (int e = 0; e < VEC; ++e) acc[v][e] += vget<V16, T>(a0, e) * w0;
-                            }
-                        }
-                    }
-                } else {
-                    for (int c = g; c < ncols; c += G) {
-                        const T w0 = wv[c];
-                        const T* __restrict__ col = base + (int64_t)c * ld;
-#pragma unroll
-                        for (int v = 0; v < RV; ++v)
-#pragma unroll
-                            for (int e = 0; e < VEC; ++e) {
-                                const int row = (v * L + q) * VEC + e;
-                                if (row < mc) acc[v][e] += col[row] * w0;
-                            }
+                        for (int e = 0; e < VEC; ++e) acc[v][e] += vget<V16, T>(a0, e) * w0;
                     }
                 }
             }
@@ -326,12 +393,14 @@ __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
 #pragma unroll
             for (int v = 0; v < RV; ++v)
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) red[g * rpg + (v * L + q) * VEC + e] = acc[v][e];
+                for (int e = 0; e < VEC; ++e) red[g * RPG + (v * L + q) * VEC + e] = acc[v][e];
             __syncthreads();
+            const int mc = (mt - rb) < RPG ? (mt - rb) : RPG;  // real rows of this pass
             for (int row = tid; row < mc; row += kTileThreads) {
                 T sum = red[row];
-                for (int gg = 1; gg < G; ++gg) sum += red[gg * rpg + row];
-                const int64_t i = (int64_t)t0 + rb + row;
+#pragma unroll
+                for (int gg = 1; gg < G; ++gg) sum += red[gg * RPG + row];
+                const int64_t i = (int64_t)r0 + rb + row;
                 const int32_t pi = perm[i];
                 T out = alpha * (sigma2 != (T)0 ? sum + sigma2 * vec[i] : sum);
                 if (beta != (T)0) out += beta * z[pi];
@@ -342,23 +411,36 @@ __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
     }
 }
 
-unsigned grid_cap(int64_t nb, int64_t cap) { return (unsigned)(nb < cap ? nb : cap); }
-
-}  // namespace
-
-hipError_t launch_near_assemble(const void* soa, int64_t n, int d, KernelFn kern,
-                                const int4* blocks, int64_t nblocks, const int64_t* off, void* A,
-                                int f64, hipStream_t st) {
-    if (nblocks == 0) return hipSuccess;
-    const unsigned grid = grid_cap(nblocks, 1 << 20);
-    if (f64)
-        hipLaunchKernelGGL(near_kernel<double>, dim3(grid), dim3(256), 0, st, (const double*)soa,
-                           n, d, KernelEval<double>(kern), blocks, nblocks, off, (double*)A);
+template <typename T>
+hipError_t rowtile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_t* tile_col,
+                            const int64_t* tile_doff, const int64_t* widx, const void* pool,
+                            const void* vecpool, const int32_t* perm, double alpha, double beta,
+                            double sigma2, void* z, int max_tile, hipStream_t st) {
+    constexpr int VEC = Vec16<T>::n;
+    const int need = (max_tile + VEC - 1) / VEC;  // vectors per tile column
+    int L = 16, RV = 1;
+    while (L < need && L < 64) L *= 2;
+    while (L * RV < need && RV < 4) RV *= 2;
+    const unsigned grid = grid_cap(ntiles, 1 << 20);
+#define HMX_RT(LL, RR)                                                                       \
+    hipLaunchKernelGGL((rowtile_kernel<T, LL, RR>), dim3(grid), dim3(kTileThreads), 0, st, \
+                       ntiles, tile_lo, tile_col, tile_doff, widx, (const T*)pool,          \
+                       (const T*)vecpool, perm, (T)alpha, (T)beta, (T)sigma2, (T*)z)
+    if (L == 16)
+        HMX_RT(16, 1);
+    else if (L == 32)
+        HMX_RT(32, 1);
+    else if (RV == 1)
+        HMX_RT(64, 1);
+    else if (RV == 2)
+        HMX_RT(64, 2);
     else
-        hipLaunchKernelGGL(near_kernel<float>, dim3(grid), dim3(256), 0, st, (const float*)soa, n,
-                           d, KernelEval<float>(kern), blocks, nblocks, off, (float*)A);
+        HMX_RT(64, 4);
+#undef HMX_RT
     return hipGetLastError();
 }
+
+}  // namespace
 
 hipError_t launch_extent(const int4* blocks, int64_t nb, int mode, int64_t mult,
                          const int32_t* rank, const int32_t* tile_of_point, int64_t* out,
@@ -371,22 +453,30 @@ hipError_t launch_extent(const int4* blocks, int64_t nb, int mode, int64_t mult,
 
 hipError_t launch_piece_fill(const int4* blocks, int64_t nblocks, const int32_t* rank,
                              const int32_t* tile_of_point, const int32_t* tile_lo,
-                             const int64_t* piece_off, const int64_t* data_off,
-                             const int64_t* vec_off_blk, int64_t vec_base, int pool,
+                             const int64_t* piece_off, const int64_t* toff, int64_t vec_base,
                              int64_t piece_base, Piece* pieces, uint64_t* keys, uint32_t* vals,
                              hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
     hipLaunchKernelGGL(piece_fill_kernel, dim3((unsigned)((nblocks + 255) / 256)), dim3(256), 0,
-                       st, blocks, nblocks, rank, tile_of_point, tile_lo, piece_off, data_off,
-                       vec_off_blk, vec_base, pool, piece_base, pieces, keys, vals);
+                       st, blocks, nblocks, rank, tile_of_point, tile_lo, piece_off, toff,
+                       vec_base, piece_base, pieces, keys, vals);
     return hipGetLastError();
 }
 
 hipError_t launch_piece_gather(const Piece* src, const uint32_t* order, int64_t npieces,
-                               Piece* dst, hipStream_t st) {
+                               Piece* dst, int64_t* size, int64_t* cols, const int32_t* tile_lo,
+                               int esz, hipStream_t st) {
     if (npieces == 0) return hipSuccess;
     hipLaunchKernelGGL(piece_gather_kernel, dim3((unsigned)((npieces + 255) / 256)), dim3(256), 0,
-                       st, src, order, npieces, dst);
+                       st, src, order, npieces, dst, size, cols, tile_lo, esz);
+    return hipGetLastError();
+}
+
+hipError_t launch_piece_layout(Piece* pieces, int64_t np, const int64_t* doff,
+                               const int64_t* coff, int64_t* widx, hipStream_t st) {
+    if (np == 0) return hipSuccess;
+    hipLaunchKernelGGL(piece_layout_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st,
+                       pieces, np, doff, coff, widx);
     return hipGetLastError();
 }
 
@@ -394,6 +484,47 @@ hipError_t launch_tile_offsets(const uint64_t* sorted_tile, int64_t npieces, int
                                int64_t* tile_ptr, hipStream_t st) {
     hipLaunchKernelGGL(tile_ptr_kernel, dim3((unsigned)((ntiles + 1 + 255) / 256)), dim3(256), 0,
                        st, sorted_tile, npieces, ntiles, tile_ptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_meta(const int64_t* tile_ptr, int64_t ntiles, int64_t np,
+                            const int64_t* doff, const int64_t* coff, int64_t total_cols,
+                            int64_t total_data, int64_t* tile_col, int64_t* tile_doff,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(tile_meta_kernel, dim3((unsigned)((ntiles + 1 + 255) / 256)), dim3(256), 0,
+                       st, tile_ptr, ntiles, np, doff, coff, total_cols, total_data, tile_col,
+                       tile_doff);
+    return hipGetLastError();
+}
+
+hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* tile_lo,
+                             const int4* adm, const int4* dense, const int64_t* ucap_off,
+                             const void* Ucap, const void* soa, int64_t n, int d, KernelFn kern,
+                             void* pool, int f64, hipStream_t st) {
+    if (np == 0) return hipSuccess;
+    const unsigned grid = grid_cap(np, 1 << 20);
+    if (f64)
+        hipLaunchKernelGGL(piece_data_kernel<double>, dim3(grid), dim3(256), 0, st, pieces, np,
+                           tile_lo, adm, dense, ucap_off, (const double*)Ucap,
+                           (const double*)soa, n, d, KernelEval<double>(kern), (double*)pool);
+    else
+        hipLaunchKernelGGL(piece_data_kernel<float>, dim3(grid), dim3(256), 0, st, pieces, np,
+                           tile_lo, adm, dense, ucap_off, (const float*)Ucap, (const float*)soa,
+                           n, d, KernelEval<float>(kern), (float*)pool);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_v(const int4* blocks, int64_t nblocks, const int32_t* rank,
+                            const int64_t* cap_voff, const int64_t* voff, const void* Vcap,
+                            void* V, int f64, hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    const unsigned grid = grid_cap(nblocks, 1 << 20);
+    if (f64)
+        hipLaunchKernelGGL(compact_v_kernel<double>, dim3(grid), dim3(256), 0, st, blocks,
+                           nblocks, rank, cap_voff, voff, (const double*)Vcap, (double*)V);
+    else
+        hipLaunchKernelGGL(compact_v_kernel<float>, dim3(grid), dim3(256), 0, st, blocks, nblocks,
+                           rank, cap_voff, voff, (const float*)Vcap, (float*)V);
     return hipGetLastError();
 }
 
@@ -442,45 +573,16 @@ hipError_t launch_far_phase1(const int4* adm, const int32_t* col_block, const in
     return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t rowtile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_t* tile_ptr,
-                                   const Piece* pieces, const void* near, const void* U,
-                                   const void* vecpool, const int32_t* perm, double alpha,
-                                   double beta, double sigma2, void* z, int max_tile,
-                                   hipStream_t st) {
-    constexpr int VEC = Vec16<T>::n;
-    const int need = (max_tile + VEC - 1) / VEC;  // vectors per tile column
-    int L = 8, RV = 1;
-    while (L < need && L < 64) L *= 2;
-    while (L * RV < need && RV < 8) RV *= 2;
-    const size_t lds = (size_t)(4 * (64 / L)) * L * RV * VEC * sizeof(T);
-    const unsigned grid = grid_cap(ntiles, 1 << 20);
-#define HMX_ROWTILE(RVV)                                                                          \
-    hipLaunchKernelGGL((rowtile_kernel<T, RVV>), dim3(grid), dim3(kTileThreads), lds, st, ntiles, \
-                       tile_lo, tile_ptr, pieces, (const T*)near, (const T*)U, (const T*)vecpool, \
-                       perm, (T)alpha, (T)beta, (T)sigma2, (T*)z, L)
-    switch (RV) {
-        case 1: HMX_ROWTILE(1); break;
-        case 2: HMX_ROWTILE(2); break;
-        case 4: HMX_ROWTILE(4); break;
-        default: HMX_ROWTILE(8); break;
-    }
-#undef HMX_ROWTILE
-    return hipGetLastError();
-}
-
-hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t* tile_ptr,
-                          const Piece* pieces, const void* near, const void* U,
-                          const void* vecpool, const int32_t* perm, int64_t n, double alpha,
-                          double beta, double sigma2, void* z, int max_tile, int f64,
-                          hipStream_t st) {
-    (void)n;
+hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t* tile_col,
+                          const int64_t* tile_doff, const int64_t* widx, const void* pool,
+                          const void* vecpool, const int32_t* perm, double alpha, double beta,
+                          double sigma2, void* z, int max_tile, int f64, hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
     if (f64)
-        return rowtile_dispatch<double>(ntiles, tile_lo, tile_ptr, pieces, near, U, vecpool, perm,
-                                        alpha, beta, sigma2, z, max_tile, st);
-    return rowtile_dispatch<float>(ntiles, tile_lo, tile_ptr, pieces, near, U, vecpool, perm,
-                                   alpha, beta, sigma2, z, max_tile, st);
+        return rowtile_dispatch<double>(ntiles, tile_lo, tile_col, tile_doff, widx, pool, vecpool,
+                                        perm, alpha, beta, sigma2, z, max_tile, st);
+    return rowtile_dispatch<float>(ntiles, tile_lo, tile_col, tile_doff, widx, pool, vecpool,
+                                   perm, alpha, beta, sigma2, z, max_tile, st);
 }
 
 }  // namespace hmx
