@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--matvecs", type=int, default=None)
     ap.add_argument("--workload", default="gauss2d_n1m_f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -205,6 +207,17 @@ def main():
                      "traffic": traffic, "algorithmic_bytes_per_launch": rt_bytes,
                      "avg_launch_ms": rt_ms},
     }
+    if args.calibrate_copy > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
+        # the scale between the counters and bytes moved
+        nel = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = nel * 4
+        del src, dst
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle on a row sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, pts, xs, z_first, part_perm)

@@ -200,29 +200,26 @@ __global__ void gather_x_kernel(const T* __restrict__ x, const int32_t* __restri
     if (i < n) xm[i] = x[perm[i]];
 }
 
-// 16-byte vector of T: 4 floats or 2 doubles
+// 16-byte vector of T: 4 floats or 2 doubles (clang extended vectors, which
+// the non-temporal load builtin accepts)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 template <typename T>
 struct Vec16;
 template <>
 struct Vec16<float> {
-    using type = float4;
+    using type = f32x4;
     static constexpr int n = 4;
 };
 template <>
 struct Vec16<double> {
-    using type = double2;
+    using type = f64x2;
     static constexpr int n = 2;
 };
 
 template <typename V, typename T>
-__device__ __forceinline__ T vget(const V& v, int e);
-template <>
-__device__ __forceinline__ float vget<float4, float>(const float4& v, int e) {
-    return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
-}
-template <>
-__device__ __forceinline__ double vget<double2, double>(const double2& v, int e) {
-    return e == 0 ? v.x : v.y;
+__device__ __forceinline__ T vget(const V& v, int e) {
+    return v[e];
 }
 
 // out[0] = max, out[1] = sum of n int32 values (integer atomics: order-free)
@@ -318,12 +315,22 @@ __global__ __launch_bounds__(256) void far_phase1_kernel(
 }
 
 // phase 2: one workgroup per row tile.  The tile is a contiguous ld x C
-// column-major matrix; column k is weighted by vec[widx[k]].  The 4 waves
-// split into G = 4 * (64 / L) column groups of L lanes; lane q of a group
-// owns RV 16-byte vectors of rows (vector v * L + q).  Groups take
-// interleaved columns (4 in flight per lane); their partial rows are summed
-// in LDS in a fixed order and the tile is scattered to the original order.
+// column-major matrix; column k is weighted by vec[widx[k]].  Weights are
+// gathered into LDS a chunk of kChunk columns at a time, so the streaming
+// loads never wait on an index lookup.  The 4 waves split into
+// G = 4 * (64 / L) column groups of L lanes; lane q of a group owns RV
+// 16-byte vectors of rows (vector v * L + q).  Groups take interleaved
+// columns, kUnroll in flight per lane, with non-temporal loads (every matrix
+// byte is read once per product); the G partial row sets are summed in LDS
+// in a fixed order and the tile is scattered to the original order.
 constexpr int kTileThreads = 256;
+constexpr int kChunk = 1024;
+constexpr int kUnroll = 8;
+
+template <typename V>
+__device__ __forceinline__ V nt_load(const V* p) {
+    return __builtin_nontemporal_load(p);
+}
 
 template <typename T, int L, int RV>
 __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
@@ -337,6 +344,7 @@ __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
     constexpr int G = 4 * S;
     constexpr int RPG = L * RV * VEC;  // rows per pass
     __shared__ T red[G * RPG];
+    __shared__ T sw[kChunk];
     const int tid = threadIdx.x, lane = tid & 63;
     // the group index is wave-uniform when a group is a whole wave
     const int g = (S == 1) ? __builtin_amdgcn_readfirstlane(tid >> 6) : (tid >> 6) * S + lane / L;
@@ -350,44 +358,53 @@ __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
         const int64_t* __restrict__ wi = widx + k0;
         for (int rb = 0; rb < ld; rb += RPG) {
             const int nvec = ((ld - rb) < RPG ? (ld - rb) : RPG) / VEC;  // vectors in this pass
-            const T* __restrict__ base = base0 + rb;
             T acc[RV][VEC];
 #pragma unroll
             for (int v = 0; v < RV; ++v)
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) acc[v][e] = 0;
-            int64_t c = g;
-            for (; c + 3 * G < nk; c += 4 * G) {
-                const T w0 = vec[wi[c]], w1 = vec[wi[c + G]], w2 = vec[wi[c + 2 * G]],
-                        w3 = vec[wi[c + 3 * G]];
-                const V16* c0 = (const V16*)(base + c * ld);
-                const V16* c1 = (const V16*)(base + (c + G) * ld);
-                const V16* c2 = (const V16*)(base + (c + 2 * G) * ld);
-                const V16* c3 = (const V16*)(base + (c + 3 * G) * ld);
+            for (int64_t kc = 0; kc < nk; kc += kChunk) {
+                const int cnt = (nk - kc) < kChunk ? (int)(nk - kc) : kChunk;
+                for (int j = tid; j < cnt; j += kTileThreads) sw[j] = vec[wi[kc + j]];
+                __syncthreads();
+                const T* __restrict__ base = base0 + rb + kc * ld;
+                int c = g;
+                for (; c + (kUnroll - 1) * G < cnt; c += kUnroll * G) {
+                    T w[kUnroll];
+                    const V16* cp[kUnroll];
 #pragma unroll
-                for (int v = 0; v < RV; ++v) {
-                    const int vi = v * L + q;
-                    if (vi < nvec) {
-                        const V16 a0 = c0[vi], a1 = c1[vi], a2 = c2[vi], a3 = c3[vi];
+                    for (int u = 0; u < kUnroll; ++u) {
+                        w[u] = sw[c + u * G];
+                        cp[u] = (const V16*)(base + (int64_t)(c + u * G) * ld);
+                    }
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e)
-                            acc[v][e] += vget<V16, T>(a0, e) * w0 + vget<V16, T>(a1, e) * w1 +
-                                         vget<V16, T>(a2, e) * w2 + vget<V16, T>(a3, e) * w3;
+                    for (int v = 0; v < RV; ++v) {
+                        const int vi = v * L + q;
+                        if (vi < nvec) {
+                            V16 a[kUnroll];
+#pragma unroll
+                            for (int u = 0; u < kUnroll; ++u) a[u] = nt_load(cp[u] + vi);
+#pragma unroll
+                            for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+                                for (int e = 0; e < VEC; ++e) acc[v][e] += vget<V16, T>(a[u], e) * w[u];
+                        }
                     }
                 }
-            }
-            for (; c < nk; c += G) {
-                const T w0 = vec[wi[c]];
-                const V16* c0 = (const V16*)(base + c * ld);
+                for (; c < cnt; c += G) {
+                    const T w0 = sw[c];
+                    const V16* c0 = (const V16*)(base + (int64_t)c * ld);
 #pragma unroll
-                for (int v = 0; v < RV; ++v) {
-                    const int vi = v * L + q;
-                    if (vi < nvec) {
-                        const V16 a0 = c0[vi];
+                    for (int v = 0; v < RV; ++v) {
+                        const int vi = v * L + q;
+                        if (vi < nvec) {
+                            const V16 a0 = nt_load(c0 + vi);
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) acc[v][e] += vget<V16, T>(a0, e) * w0;
+                            for (int e = 0; e < VEC; ++e) acc[v][e] += vget<V16, T>(a0, e) * w0;
+                        }
                     }
                 }
+                __syncthreads();
             }
             // sum the G partial row sets in a fixed order
 #pragma unroll
