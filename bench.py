@@ -131,7 +131,8 @@ def main():
     z_d = torch.empty(n, dtype=tdt, device=dev)
     kern = H.make_kernel(wl["kernel"], wl["p0"])
     prm = H.hmx_params_default(leaf_size=wl["leaf"], eta=wl["eta"], aca_eps=wl["eps"],
-                               max_rank=wl["kmax"], compute_dtype=wl["dtype"])
+                               max_rank=wl["kmax"], compute_dtype=wl["dtype"],
+                               storage_dtype=wl.get("storage", wl["dtype"]))
     stream = torch.cuda.current_stream()
 
     def one_step(timed):
@@ -188,11 +189,14 @@ def main():
     out = {
         "metric": METRIC, "value": gbs, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": step_ms, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": wl["dtype"], "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": wl.get("storage", wl["dtype"]),
+        "data": "synthetic",
         "config": {"workload": "%s: plain method, N=%d points uniform in [0,1]^%d, %s kernel "
-                               "p0=%g, leaf %d, eta %g, ACA eps %g, max rank %d, %d matvecs per "
-                               "step" % (args.workload, n, d, wl["kernel"], wl["p0"], wl["leaf"],
-                                         wl["eta"], wl["eps"], wl["kmax"], M),
+                               "p0=%g, leaf %d, eta %g, ACA eps %g, max rank %d, %s arithmetic, "
+                               "%s storage, %d matvecs per step" % (
+                                   args.workload, n, d, wl["kernel"], wl["p0"], wl["leaf"],
+                                   wl["eta"], wl["eps"], wl["kmax"], wl["dtype"],
+                                   wl.get("storage", wl["dtype"]), M),
                    "n": n, "d": d, "matvecs_per_step": M},
         "build_s": build_s, "matvec_ms": mv_ms,
         "build_phase_ms": list(recs[-1]["stats"].phase_ms),

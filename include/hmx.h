@@ -92,8 +92,12 @@ typedef struct {
                                 1e-14 (F64) or 1e-7 (F32) */
     int32_t max_rank;        /* k_max, 1..128 */
     double sigma2;           /* diagonal shift sigma^2 >= 0 of (A + sigma^2 I) */
-    hmx_dtype compute_dtype; /* HMX_F64 or HMX_F32: kernel evaluation, factor and
-                                near-field storage, matvec accumulation */
+    hmx_dtype compute_dtype; /* HMX_F64 or HMX_F32: kernel evaluation, ACA and
+                                matvec accumulation (the ACA norm estimate is
+                                always FP64) */
+    hmx_dtype storage_dtype; /* stored near field, U and V: HMX_F64 (requires
+                                F64 compute), HMX_F32 or HMX_BF16 (require F32
+                                compute; BF16 rounds to nearest even) */
     hmx_rank_mode rank_mode;
     int32_t reserved[8];
 } hmx_params;
@@ -107,7 +111,7 @@ typedef struct {
     int64_t n_tiles;          /* leaf clusters (row tiles of the matvec) */
     int64_t sum_rank;         /* sum of ACA ranks */
     int32_t max_rank_used;
-    int32_t entry_bytes;      /* bytes per stored factor / near-field entry */
+    int32_t entry_bytes;      /* bytes per stored factor / near-field entry (storage dtype) */
     int64_t factor_entries;   /* sum_adm rank * (|tau| + |sigma|) */
     int64_t u_entries;        /* sum_adm rank * |tau|   (U pool) */
     int64_t v_entries;        /* sum_adm rank * |sigma| (V pool) */
@@ -121,7 +125,7 @@ typedef struct {
 } hmx_stats;
 
 /* Fill *p with the defaults: leaf 256, eta 1.5, eps 1e-5, aca_eta 0,
- * eps0 default, max_rank 64, sigma2 0, F32, adaptive. */
+ * eps0 default, max_rank 64, sigma2 0, F32 compute and storage, adaptive. */
 hmx_status hmx_params_default(hmx_params* p);
 
 /* Build the H-matrix of phi over the points.
@@ -140,7 +144,8 @@ hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t
 /* z := alpha (H + sigma2 I) x + beta z in the ORIGINAL point order
  * (Algorithm 3; x is permuted to Morton order and z back, Section 5.1).
  *   x, z : device vectors of n entries in vec_dtype, which must equal the
- *          handle's compute dtype.  x and z must not overlap.
+ *          handle's compute dtype (F32 for BF16 storage).  x and z must not
+ *          overlap.
  * Fully asynchronous on `stream`; allocates nothing. */
 hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype, double alpha,
                       double beta, void* stream);

@@ -187,7 +187,9 @@ struct hmx_hmatrix_s {
     hmx_kernel kern{};
     hmx_params prm{};
     int f64 = 0;
-    size_t esz = 4;  // bytes per stored entry
+    size_t esz = 4;  // bytes per compute-type value (vectors, ACA scratch)
+    int smode = 1;   // storage mode: 0 F64, 1 F32, 2 BF16
+    size_t ssz = 4;  // bytes per stored near-field / factor entry
     double box[6] = {0, 0, 0, 0, 0, 0};
     int L = 0;
     int64_t nslots = 0;
@@ -258,6 +260,8 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
     const double eta = h->prm.eta;
     const int f64 = h->f64;
     const size_t esz = h->esz;
+    const size_t ssz = h->ssz;
+    const int smode = h->smode;
     hmx_stats& S = h->stats;
     auto t0 = clk::now();
 
@@ -483,9 +487,9 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
                             h->voff.as<int64_t>(), st),
               "extent");
         S.v_entries = scan(h->voff.as<int64_t>(), h->n_adm);
-        alloc(h->V, S.v_entries * esz, "V pool");
+        alloc(h->V, S.v_entries * ssz, "V pool");
         check(launch_compact_v(h->adm.as<int4>(), h->n_adm, h->rank.as<int32_t>(),
-                               cv.as<int64_t>(), h->voff.as<int64_t>(), Vcap.p, h->V.p, f64, st),
+                               cv.as<int64_t>(), h->voff.as<int64_t>(), Vcap.p, h->V.p, smode, st),
               "compact V");
         check(hipStreamSynchronize(st), "compact sync");
         Vcap.release();
@@ -557,7 +561,7 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
         alloc(pcols, (h->npieces + 1) * 8, "piece columns");
         check(launch_piece_gather(unsorted.as<Piece>(), vals.as<uint32_t>(), h->npieces,
                                   h->pieces.as<Piece>(), psize.as<int64_t>(), pcols.as<int64_t>(),
-                                  h->tile_lo.as<int32_t>(), (int)esz, st),
+                                  h->tile_lo.as<int32_t>(), (int)ssz, st),
               "piece gather");
         h->pool_entries = scan(psize.as<int64_t>(), h->npieces);
         h->ncols_total = scan(pcols.as<int64_t>(), h->npieces);
@@ -576,11 +580,11 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
                                pcols.as<int64_t>(), h->ncols_total, h->pool_entries,
                                h->tile_col.as<int64_t>(), h->tile_doff.as<int64_t>(), st),
               "tile meta");
-        alloc(h->pool, (size_t)std::max<int64_t>(h->pool_entries, 1) * esz, "matrix pool");
+        alloc(h->pool, (size_t)std::max<int64_t>(h->pool_entries, 1) * ssz, "matrix pool");
         check(launch_piece_data(h->pieces.as<Piece>(), h->npieces, h->tile_lo.as<int32_t>(),
                                 h->adm.as<int4>(), h->dense.as<int4>(), cu.as<int64_t>(), Ucap.p,
                                 f64 ? h->soa64.p : h->soa32.p, n, d,
-                                KernelFn{(int)h->kern.kind, h->kern.p0}, h->pool.p, f64, st),
+                                KernelFn{(int)h->kern.kind, h->kern.p0}, h->pool.p, smode, st),
               "piece data");
         check(hipStreamSynchronize(st), "pool sync");
     }
@@ -606,11 +610,11 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
     S.sum_rank = h->sum_rank;
     S.factor_entries = h->factor_entries;
     S.near_entries = h->near_entries;
-    S.entry_bytes = (int32_t)esz;
+    S.entry_bytes = (int32_t)ssz;
     S.phase_ms[7] = ms_since(t_all);
     // algorithmic bytes of one matvec with beta = 0: stored data once, the
     // vectors x and z once, perm for gather and scatter, t written and read
-    S.matvec_bytes = (double)(h->near_entries + h->factor_entries) * esz +
+    S.matvec_bytes = (double)(h->near_entries + h->factor_entries) * ssz +
                      (double)n * (2.0 * esz + 8.0) + (double)h->sum_rank * 2.0 * esz;
     S.device_bytes = h->device_bytes();
 }
@@ -647,6 +651,7 @@ hmx_status hmx_params_default(hmx_params* p) {
     p->max_rank = 64;
     p->sigma2 = 0.0;
     p->compute_dtype = HMX_F32;
+    p->storage_dtype = HMX_F32;
     p->rank_mode = HMX_RANK_ADAPTIVE;
     return HMX_OK;
 }
@@ -683,6 +688,11 @@ hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t
         set_err("compute_dtype must be F64 or F32");
         return HMX_ERR_UNSUPPORTED;
     }
+    if ((p.compute_dtype == HMX_F64) != (p.storage_dtype == HMX_F64) ||
+        (p.storage_dtype != HMX_F64 && p.storage_dtype != HMX_F32 && p.storage_dtype != HMX_BF16)) {
+        set_err("storage_dtype must be F64 with F64 compute, F32 or BF16 with F32 compute");
+        return HMX_ERR_UNSUPPORTED;
+    }
     if (p.rank_mode != HMX_RANK_ADAPTIVE && p.rank_mode != HMX_RANK_FIXED) {
         set_err("unsupported rank mode %d", (int)p.rank_mode);
         return HMX_ERR_UNSUPPORTED;
@@ -708,6 +718,8 @@ hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t
     h->prm = p;
     h->f64 = p.compute_dtype == HMX_F64;
     h->esz = h->f64 ? 8 : 4;
+    h->smode = p.storage_dtype == HMX_F64 ? 0 : (p.storage_dtype == HMX_F32 ? 1 : 2);
+    h->ssz = h->smode == 0 ? 8 : (h->smode == 1 ? 4 : 2);
     try {
         build_impl(h, points, pts_dtype == HMX_F64, (hipStream_t)stream);
     } catch (const Fail& f) {
@@ -745,13 +757,13 @@ hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype
     if (e == hipSuccess)
         e = launch_far_phase1(h->adm.as<int4>(), h->col_block.as<int32_t>(),
                               h->voff.as<int64_t>(), h->toff.as<int64_t>(), h->sum_rank, h->V.p,
-                              h->vecpool.p, h->n, f64, st);
+                              h->vecpool.p, h->n, h->smode, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
     if (e == hipSuccess)
         e = launch_rowtile(h->ntiles, h->tile_lo.as<int32_t>(), h->tile_col.as<int64_t>(),
                            h->tile_doff.as<int64_t>(), h->widx.as<int64_t>(), h->pool.p,
                            h->vecpool.p, h->perm.as<int32_t>(), alpha, beta, h->prm.sigma2, z,
-                           h->max_tile, f64, st);
+                           h->max_tile, h->smode, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
     if (e != hipSuccess) {
         set_err("matvec launch: %s", hipGetErrorString(e));
@@ -886,11 +898,21 @@ hmx_status hmx_get_factors(hmx_hmatrix h, int64_t leaf, double* U, double* V, in
         check(hipMemcpyAsync(&vo, h->voff.as<int64_t>() + leaf, 8, hipMemcpyDeviceToHost, st), "vo");
         check(hipStreamSynchronize(st), "sync");
         const int64_t m = bl.y - bl.x, nc = bl.w - bl.z;
-        const size_t esz = h->esz;
+        const size_t esz = h->ssz;  // stored entry size
         *rank = r;
         auto to_double = [&](const std::vector<char>& raw, size_t cnt, double* out) {
-            for (size_t e = 0; e < cnt; ++e)
-                out[e] = esz == 8 ? ((const double*)raw.data())[e] : ((const float*)raw.data())[e];
+            for (size_t e = 0; e < cnt; ++e) {
+                if (esz == 8) {
+                    out[e] = ((const double*)raw.data())[e];
+                } else if (esz == 4) {
+                    out[e] = ((const float*)raw.data())[e];
+                } else {
+                    uint32_t u = (uint32_t)((const uint16_t*)raw.data())[e] << 16;
+                    float f;
+                    memcpy(&f, &u, 4);
+                    out[e] = f;
+                }
+            }
         };
         // V: one column-major region
         std::vector<char> raw((size_t)r * nc * esz + 1);

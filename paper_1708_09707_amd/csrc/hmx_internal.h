@@ -194,10 +194,11 @@ hipError_t launch_tile_meta(const int64_t* tile_ptr, int64_t ntiles, int64_t np,
 hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* tile_lo,
                              const int4* adm, const int4* dense, const int64_t* ucap_off,
                              const void* Ucap, const void* soa, int64_t n, int d, KernelFn kern,
-                             void* pool, int f64, hipStream_t st);
+                             void* pool, int smode, hipStream_t st);
+// smode: storage mode 0 = F64, 1 = F32, 2 = BF16 storage with F32 arithmetic
 hipError_t launch_compact_v(const int4* blocks, int64_t nblocks, const int32_t* rank,
                             const int64_t* cap_voff, const int64_t* voff, const void* Vcap,
-                            void* V, int f64, hipStream_t st);
+                            void* V, int smode, hipStream_t st);
 hipError_t launch_gather_x(const void* x, const int32_t* perm, int64_t n, void* xm, int f64,
                            hipStream_t st);
 // out[0] = max and out[1] = sum of n non-negative int32 values (device)
@@ -207,10 +208,10 @@ hipError_t launch_col_block(const int32_t* rank, const int64_t* toff, int64_t na
                             int32_t* col_block, hipStream_t st);
 hipError_t launch_far_phase1(const int4* adm, const int32_t* col_block, const int64_t* voff,
                              const int64_t* toff, int64_t ncols_total, const void* V,
-                             void* vecpool, int64_t n, int f64, hipStream_t st);
+                             void* vecpool, int64_t n, int smode, hipStream_t st);
 hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t* tile_col,
                           const int64_t* tile_doff, const int64_t* widx, const void* pool,
                           const void* vecpool, const int32_t* perm, double alpha, double beta,
-                          double sigma2, void* z, int max_tile, int f64, hipStream_t st);
+                          double sigma2, void* z, int max_tile, int smode, hipStream_t st);
 
 }  // namespace hmx

@@ -31,6 +31,72 @@ __device__ __host__ __forceinline__ int tile_ld(int rows, int esz) {
     return (rows + v - 1) / v * v;
 }
 
+// ---------------------------------------------------------------------------
+// storage types: the pools hold S (double, float or bfloat16 bits), the
+// arithmetic runs in T (double or float).  bfloat16 = the upper 16 bits of an
+// IEEE float; conversion rounds to nearest, ties to even.
+// ---------------------------------------------------------------------------
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <typename S, typename T>
+struct Store;
+template <>
+struct Store<double, double> {
+    static __device__ __forceinline__ double put(double v) { return v; }
+};
+template <>
+struct Store<float, float> {
+    static __device__ __forceinline__ float put(float v) { return v; }
+};
+template <>
+struct Store<uint16_t, float> {
+    static __device__ __forceinline__ uint16_t put(float v) { return f32_to_bf16(v); }
+};
+
+// decode one 16-byte vector of S into 16 / sizeof(S) values of T
+template <typename S, typename T>
+struct Dec;
+template <>
+struct Dec<float, float> {
+    static constexpr int n = 4;
+    static __device__ __forceinline__ void get(const u32x4& r, float* o) {
+        o[0] = __uint_as_float(r[0]);
+        o[1] = __uint_as_float(r[1]);
+        o[2] = __uint_as_float(r[2]);
+        o[3] = __uint_as_float(r[3]);
+    }
+};
+template <>
+struct Dec<double, double> {
+    static constexpr int n = 2;
+    static __device__ __forceinline__ void get(const u32x4& r, double* o) {
+        o[0] = __hiloint2double((int)r[1], (int)r[0]);
+        o[1] = __hiloint2double((int)r[3], (int)r[2]);
+    }
+};
+template <>
+struct Dec<uint16_t, float> {
+    static constexpr int n = 8;
+    static __device__ __forceinline__ void get(const u32x4& r, float* o) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            o[2 * k] = __uint_as_float(r[k] << 16);
+            o[2 * k + 1] = __uint_as_float(r[k] & 0xffff0000u);
+        }
+    }
+};
+
+__device__ __forceinline__ u32x4 nt_load(const u32x4* p) { return __builtin_nontemporal_load(p); }
+
 // per-block sizes: mode 0: m * mult, 1: n * mult, 2: m * n, 3: r * m, 4: r * n,
 // 5: r, 6: number of row tiles covered (0 if rank == 0 for an admissible list)
 __global__ void extent_kernel(const int4* __restrict__ blocks, int64_t nb, int mode, int64_t mult,
@@ -148,19 +214,19 @@ __global__ void tile_meta_kernel(const int64_t* __restrict__ tile_ptr, int64_t n
 // Fill the matrix pool piece by piece: dense pieces evaluate phi (the near
 // field, Section 5.4.2), factor pieces copy the tile's rows of U_b from the
 // ACA capacity pool.  Padding rows are zero.
-template <typename T>
+template <typename S, typename T>
 __global__ __launch_bounds__(256) void piece_data_kernel(
     const Piece* __restrict__ pieces, int64_t np, const int32_t* __restrict__ tile_lo,
     const int4* __restrict__ adm, const int4* __restrict__ dense,
     const int64_t* __restrict__ ucap_off, const T* __restrict__ Ucap, const T* __restrict__ soa,
-    int64_t n, int d, KernelEval<T> K, T* __restrict__ pool) {
-    constexpr int esz = sizeof(T);
+    int64_t n, int d, KernelEval<T> K, S* __restrict__ pool) {
+    constexpr int ssz = sizeof(S);
     for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
         const Piece pc = pieces[p];
         const int32_t r0 = tile_lo[pc.tile];
         const int mt = tile_lo[pc.tile + 1] - r0;
-        const int ld = tile_ld(mt, esz);
-        T* __restrict__ out = pool + pc.d_off;
+        const int ld = tile_ld(mt, ssz);
+        S* __restrict__ out = pool + pc.d_off;
         const int64_t tot = (int64_t)ld * pc.ncols;
         const bool is_factor = pc.blk >= 0;
         const int4 bl = is_factor ? adm[pc.blk] : dense[-pc.blk - 1];
@@ -183,7 +249,7 @@ __global__ __launch_bounds__(256) void piece_data_kernel(
                     v = phi(K, x, y, d);
                 }
             }
-            out[e] = v;
+            out[e] = Store<S, T>::put(v);
             i += blockDim.x;
             while (i >= ld) {
                 i -= ld;
@@ -198,28 +264,6 @@ __global__ void gather_x_kernel(const T* __restrict__ x, const int32_t* __restri
                                 int64_t n, T* __restrict__ xm) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) xm[i] = x[perm[i]];
-}
-
-// 16-byte vector of T: 4 floats or 2 doubles (clang extended vectors, which
-// the non-temporal load builtin accepts)
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-template <typename T>
-struct Vec16;
-template <>
-struct Vec16<float> {
-    using type = f32x4;
-    static constexpr int n = 4;
-};
-template <>
-struct Vec16<double> {
-    using type = f64x2;
-    static constexpr int n = 2;
-};
-
-template <typename V, typename T>
-__device__ __forceinline__ T vget(const V& v, int e) {
-    return v[e];
 }
 
 // out[0] = max, out[1] = sum of n int32 values (integer atomics: order-free)
@@ -242,20 +286,20 @@ __global__ void int_stats_kernel(const int32_t* __restrict__ a, int64_t n,
 }
 
 // V compaction: the first r_b columns of each V_b from the capacity pool
-template <typename T>
+template <typename S, typename T>
 __global__ __launch_bounds__(256) void compact_v_kernel(const int4* __restrict__ blocks,
                                                         int64_t nblocks,
                                                         const int32_t* __restrict__ rank,
                                                         const int64_t* __restrict__ cv,
                                                         const int64_t* __restrict__ ev,
                                                         const T* __restrict__ Vcap,
-                                                        T* __restrict__ V) {
+                                                        S* __restrict__ V) {
     for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
         const int4 bl = blocks[b];
         const int64_t nc = bl.w - bl.z, r = rank[b];
         const T* sv = Vcap + cv[b];
-        T* dv = V + ev[b];
-        for (int64_t e = threadIdx.x; e < r * nc; e += blockDim.x) dv[e] = sv[e];
+        S* dv = V + ev[b];
+        for (int64_t e = threadIdx.x; e < r * nc; e += blockDim.x) dv[e] = Store<S, T>::put(sv[e]);
     }
 }
 
@@ -272,12 +316,29 @@ __global__ void col_block_kernel(const int32_t* __restrict__ rank,
 // phase 1: t_b[l] = sum_j V_b[j, l] x[slo + j]; one wave per column of the
 // flattened list of all factor columns
 template <typename T>
+__device__ __forceinline__ void load_x16(const T* p, T* o);
+template <>
+__device__ __forceinline__ void load_x16<float>(const float* p, float* o) {
+    const f32x4 v = *(const f32x4*)p;
+    o[0] = v[0];
+    o[1] = v[1];
+    o[2] = v[2];
+    o[3] = v[3];
+}
+template <>
+__device__ __forceinline__ void load_x16<double>(const double* p, double* o) {
+    const f64x2 v = *(const f64x2*)p;
+    o[0] = v[0];
+    o[1] = v[1];
+}
+
+template <typename S, typename T>
 __global__ __launch_bounds__(256) void far_phase1_kernel(
     const int4* __restrict__ adm, const int32_t* __restrict__ col_block,
-    const int64_t* __restrict__ voff, const int64_t* __restrict__ toff, const T* __restrict__ V,
+    const int64_t* __restrict__ voff, const int64_t* __restrict__ toff, const S* __restrict__ V,
     T* __restrict__ vec, int64_t n, int64_t ncols_total) {
-    using V16 = typename Vec16<T>::type;
-    constexpr int VEC = Vec16<T>::n;
+    constexpr int VS = Dec<S, T>::n;  // values per 16-byte load of V
+    constexpr int VT = 16 / sizeof(T);
     const int lane = threadIdx.x & 63;
     const int64_t k = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     if (k >= ncols_total) return;
@@ -286,29 +347,29 @@ __global__ __launch_bounds__(256) void far_phase1_kernel(
     const int nc = bl.w - bl.z;
     const int l = (int)(k - toff[b]);
     const int64_t cofs = voff[b] + (int64_t)l * nc;
-    const T* __restrict__ col = V + cofs;
+    const S* __restrict__ col = V + cofs;
     const T* __restrict__ xs = vec + bl.z;
     T acc = 0;
-    if (((cofs | (int64_t)bl.z | (int64_t)nc) % VEC) == 0) {
-        const V16* __restrict__ c16 = (const V16*)col;
-        const V16* __restrict__ x16 = (const V16*)xs;
-        const int nv = nc / VEC;
-        int j = lane;
-        for (; j + 64 < nv; j += 128) {
-            const V16 a0 = c16[j], a1 = c16[j + 64];
-            const V16 x0 = x16[j], x1 = x16[j + 64];
+    if ((cofs % VS) == 0 && (nc % VS) == 0 && ((int64_t)bl.z % VT) == 0) {
+        const u32x4* __restrict__ c16 = (const u32x4*)col;
+        const int nv = nc / VS;
+        for (int j = lane; j < nv; j += 64) {
+            T a[VS], xv[VS];
+            Dec<S, T>::get(nt_load(c16 + j), a);
 #pragma unroll
-            for (int e = 0; e < VEC; ++e)
-                acc += vget<V16, T>(a0, e) * vget<V16, T>(x0, e) +
-                       vget<V16, T>(a1, e) * vget<V16, T>(x1, e);
-        }
-        for (; j < nv; j += 64) {
-            const V16 a0 = c16[j], x0 = x16[j];
+            for (int u = 0; u < VS / VT; ++u) load_x16<T>(xs + (int64_t)j * VS + u * VT, xv + u * VT);
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) acc += vget<V16, T>(a0, e) * vget<V16, T>(x0, e);
+            for (int e = 0; e < VS; ++e) acc += a[e] * xv[e];
         }
     } else {
-        for (int j = lane; j < nc; j += 64) acc += col[j] * xs[j];
+        for (int j = lane; j < nc; j += 64) {
+            T a;
+            if constexpr (sizeof(S) == 2)
+                a = __uint_as_float((uint32_t)(*(const uint16_t*)(col + j)) << 16);
+            else
+                a = (T)col[j];
+            acc += a * xs[j];
+        }
     }
     acc = wave_sum(acc);
     if (lane == 0) vec[n + k] = acc;
@@ -327,34 +388,28 @@ constexpr int kTileThreads = 256;
 constexpr int kChunk = 1024;
 constexpr int kUnroll = 8;
 
-template <typename V>
-__device__ __forceinline__ V nt_load(const V* p) {
-    return __builtin_nontemporal_load(p);
-}
-
-template <typename T, int L, int RV>
+template <typename S, typename T, int L, int RV>
 __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
     int64_t ntiles, const int32_t* __restrict__ tile_lo, const int64_t* __restrict__ tile_col,
     const int64_t* __restrict__ tile_doff, const int64_t* __restrict__ widx,
-    const T* __restrict__ pool, const T* __restrict__ vec, const int32_t* __restrict__ perm,
+    const S* __restrict__ pool, const T* __restrict__ vec, const int32_t* __restrict__ perm,
     T alpha, T beta, T sigma2, T* __restrict__ z) {
-    using V16 = typename Vec16<T>::type;
-    constexpr int VEC = Vec16<T>::n;
-    constexpr int S = 64 / L;
-    constexpr int G = 4 * S;
+    constexpr int VEC = Dec<S, T>::n;  // rows per 16-byte vector
+    constexpr int SUB = 64 / L;
+    constexpr int G = 4 * SUB;
     constexpr int RPG = L * RV * VEC;  // rows per pass
     __shared__ T red[G * RPG];
     __shared__ T sw[kChunk];
     const int tid = threadIdx.x, lane = tid & 63;
     // the group index is wave-uniform when a group is a whole wave
-    const int g = (S == 1) ? __builtin_amdgcn_readfirstlane(tid >> 6) : (tid >> 6) * S + lane / L;
+    const int g = (SUB == 1) ? __builtin_amdgcn_readfirstlane(tid >> 6) : (tid >> 6) * SUB + lane / L;
     const int q = lane % L;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int32_t r0 = tile_lo[t];
         const int mt = tile_lo[t + 1] - r0;
         const int ld = (mt + VEC - 1) / VEC * VEC;
         const int64_t k0 = tile_col[t], nk = tile_col[t + 1] - k0;
-        const T* __restrict__ base0 = pool + tile_doff[t];
+        const S* __restrict__ base0 = pool + tile_doff[t];
         const int64_t* __restrict__ wi = widx + k0;
         for (int rb = 0; rb < ld; rb += RPG) {
             const int nvec = ((ld - rb) < RPG ? (ld - rb) : RPG) / VEC;  // vectors in this pass
@@ -367,40 +422,44 @@ __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
                 const int cnt = (nk - kc) < kChunk ? (int)(nk - kc) : kChunk;
                 for (int j = tid; j < cnt; j += kTileThreads) sw[j] = vec[wi[kc + j]];
                 __syncthreads();
-                const T* __restrict__ base = base0 + rb + kc * ld;
+                const S* __restrict__ base = base0 + rb + kc * ld;
                 int c = g;
                 for (; c + (kUnroll - 1) * G < cnt; c += kUnroll * G) {
                     T w[kUnroll];
-                    const V16* cp[kUnroll];
+                    const u32x4* cp[kUnroll];
 #pragma unroll
                     for (int u = 0; u < kUnroll; ++u) {
                         w[u] = sw[c + u * G];
-                        cp[u] = (const V16*)(base + (int64_t)(c + u * G) * ld);
+                        cp[u] = (const u32x4*)(base + (int64_t)(c + u * G) * ld);
                     }
 #pragma unroll
                     for (int v = 0; v < RV; ++v) {
                         const int vi = v * L + q;
                         if (vi < nvec) {
-                            V16 a[kUnroll];
+                            u32x4 raw[kUnroll];
 #pragma unroll
-                            for (int u = 0; u < kUnroll; ++u) a[u] = nt_load(cp[u] + vi);
+                            for (int u = 0; u < kUnroll; ++u) raw[u] = nt_load(cp[u] + vi);
 #pragma unroll
-                            for (int u = 0; u < kUnroll; ++u)
+                            for (int u = 0; u < kUnroll; ++u) {
+                                T a[VEC];
+                                Dec<S, T>::get(raw[u], a);
 #pragma unroll
-                                for (int e = 0; e < VEC; ++e) acc[v][e] += vget<V16, T>(a[u], e) * w[u];
+                                for (int e = 0; e < VEC; ++e) acc[v][e] += a[e] * w[u];
+                            }
                         }
                     }
                 }
                 for (; c < cnt; c += G) {
                     const T w0 = sw[c];
-                    const V16* c0 = (const V16*)(base + (int64_t)c * ld);
+                    const u32x4* c0 = (const u32x4*)(base + (int64_t)c * ld);
 #pragma unroll
                     for (int v = 0; v < RV; ++v) {
                         const int vi = v * L + q;
                         if (vi < nvec) {
-                            const V16 a0 = nt_load(c0 + vi);
+                            T a[VEC];
+                            Dec<S, T>::get(nt_load(c0 + vi), a);
 #pragma unroll
-                            for (int e = 0; e < VEC; ++e) acc[v][e] += vget<V16, T>(a0, e) * w0;
+                            for (int e = 0; e < VEC; ++e) acc[v][e] += a[e] * w0;
                         }
                     }
                 }
@@ -428,20 +487,20 @@ __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
     }
 }
 
-template <typename T>
+template <typename S, typename T>
 hipError_t rowtile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_t* tile_col,
                             const int64_t* tile_doff, const int64_t* widx, const void* pool,
                             const void* vecpool, const int32_t* perm, double alpha, double beta,
                             double sigma2, void* z, int max_tile, hipStream_t st) {
-    constexpr int VEC = Vec16<T>::n;
+    constexpr int VEC = Dec<S, T>::n;
     const int need = (max_tile + VEC - 1) / VEC;  // vectors per tile column
     int L = 16, RV = 1;
     while (L < need && L < 64) L *= 2;
     while (L * RV < need && RV < 4) RV *= 2;
     const unsigned grid = grid_cap(ntiles, 1 << 20);
-#define HMX_RT(LL, RR)                                                                       \
-    hipLaunchKernelGGL((rowtile_kernel<T, LL, RR>), dim3(grid), dim3(kTileThreads), 0, st, \
-                       ntiles, tile_lo, tile_col, tile_doff, widx, (const T*)pool,          \
+#define HMX_RT(LL, RR)                                                                          \
+    hipLaunchKernelGGL((rowtile_kernel<S, T, LL, RR>), dim3(grid), dim3(kTileThreads), 0, st, \
+                       ntiles, tile_lo, tile_col, tile_doff, widx, (const S*)pool,             \
                        (const T*)vecpool, perm, (T)alpha, (T)beta, (T)sigma2, (T*)z)
     if (L == 16)
         HMX_RT(16, 1);
@@ -514,34 +573,44 @@ hipError_t launch_tile_meta(const int64_t* tile_ptr, int64_t ntiles, int64_t np,
     return hipGetLastError();
 }
 
+// storage modes: 0 = F64/F64, 1 = F32/F32, 2 = BF16 storage with F32 arithmetic
 hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* tile_lo,
                              const int4* adm, const int4* dense, const int64_t* ucap_off,
                              const void* Ucap, const void* soa, int64_t n, int d, KernelFn kern,
-                             void* pool, int f64, hipStream_t st) {
+                             void* pool, int smode, hipStream_t st) {
     if (np == 0) return hipSuccess;
     const unsigned grid = grid_cap(np, 1 << 20);
-    if (f64)
-        hipLaunchKernelGGL(piece_data_kernel<double>, dim3(grid), dim3(256), 0, st, pieces, np,
-                           tile_lo, adm, dense, ucap_off, (const double*)Ucap,
+    if (smode == 0)
+        hipLaunchKernelGGL((piece_data_kernel<double, double>), dim3(grid), dim3(256), 0, st,
+                           pieces, np, tile_lo, adm, dense, ucap_off, (const double*)Ucap,
                            (const double*)soa, n, d, KernelEval<double>(kern), (double*)pool);
+    else if (smode == 1)
+        hipLaunchKernelGGL((piece_data_kernel<float, float>), dim3(grid), dim3(256), 0, st,
+                           pieces, np, tile_lo, adm, dense, ucap_off, (const float*)Ucap,
+                           (const float*)soa, n, d, KernelEval<float>(kern), (float*)pool);
     else
-        hipLaunchKernelGGL(piece_data_kernel<float>, dim3(grid), dim3(256), 0, st, pieces, np,
-                           tile_lo, adm, dense, ucap_off, (const float*)Ucap, (const float*)soa,
-                           n, d, KernelEval<float>(kern), (float*)pool);
+        hipLaunchKernelGGL((piece_data_kernel<uint16_t, float>), dim3(grid), dim3(256), 0, st,
+                           pieces, np, tile_lo, adm, dense, ucap_off, (const float*)Ucap,
+                           (const float*)soa, n, d, KernelEval<float>(kern), (uint16_t*)pool);
     return hipGetLastError();
 }
 
 hipError_t launch_compact_v(const int4* blocks, int64_t nblocks, const int32_t* rank,
                             const int64_t* cap_voff, const int64_t* voff, const void* Vcap,
-                            void* V, int f64, hipStream_t st) {
+                            void* V, int smode, hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
     const unsigned grid = grid_cap(nblocks, 1 << 20);
-    if (f64)
-        hipLaunchKernelGGL(compact_v_kernel<double>, dim3(grid), dim3(256), 0, st, blocks,
-                           nblocks, rank, cap_voff, voff, (const double*)Vcap, (double*)V);
+    if (smode == 0)
+        hipLaunchKernelGGL((compact_v_kernel<double, double>), dim3(grid), dim3(256), 0, st,
+                           blocks, nblocks, rank, cap_voff, voff, (const double*)Vcap,
+                           (double*)V);
+    else if (smode == 1)
+        hipLaunchKernelGGL((compact_v_kernel<float, float>), dim3(grid), dim3(256), 0, st,
+                           blocks, nblocks, rank, cap_voff, voff, (const float*)Vcap, (float*)V);
     else
-        hipLaunchKernelGGL(compact_v_kernel<float>, dim3(grid), dim3(256), 0, st, blocks, nblocks,
-                           rank, cap_voff, voff, (const float*)Vcap, (float*)V);
+        hipLaunchKernelGGL((compact_v_kernel<uint16_t, float>), dim3(grid), dim3(256), 0, st,
+                           blocks, nblocks, rank, cap_voff, voff, (const float*)Vcap,
+                           (uint16_t*)V);
     return hipGetLastError();
 }
 
@@ -575,31 +644,39 @@ hipError_t launch_col_block(const int32_t* rank, const int64_t* toff, int64_t na
 
 hipError_t launch_far_phase1(const int4* adm, const int32_t* col_block, const int64_t* voff,
                              const int64_t* toff, int64_t ncols_total, const void* V,
-                             void* vecpool, int64_t n, int f64, hipStream_t st) {
+                             void* vecpool, int64_t n, int smode, hipStream_t st) {
     if (ncols_total == 0) return hipSuccess;
     const int64_t nblk = (ncols_total + 3) / 4;  // 4 waves (columns) per workgroup
     if (nblk > 0x7fffffffll) return hipErrorInvalidValue;
-    if (f64)
-        hipLaunchKernelGGL(far_phase1_kernel<double>, dim3((unsigned)nblk), dim3(256), 0, st, adm,
-                           col_block, voff, toff, (const double*)V, (double*)vecpool, n,
+    if (smode == 0)
+        hipLaunchKernelGGL((far_phase1_kernel<double, double>), dim3((unsigned)nblk), dim3(256),
+                           0, st, adm, col_block, voff, toff, (const double*)V, (double*)vecpool,
+                           n, ncols_total);
+    else if (smode == 1)
+        hipLaunchKernelGGL((far_phase1_kernel<float, float>), dim3((unsigned)nblk), dim3(256), 0,
+                           st, adm, col_block, voff, toff, (const float*)V, (float*)vecpool, n,
                            ncols_total);
     else
-        hipLaunchKernelGGL(far_phase1_kernel<float>, dim3((unsigned)nblk), dim3(256), 0, st, adm,
-                           col_block, voff, toff, (const float*)V, (float*)vecpool, n,
-                           ncols_total);
+        hipLaunchKernelGGL((far_phase1_kernel<uint16_t, float>), dim3((unsigned)nblk), dim3(256),
+                           0, st, adm, col_block, voff, toff, (const uint16_t*)V,
+                           (float*)vecpool, n, ncols_total);
     return hipGetLastError();
 }
 
 hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t* tile_col,
                           const int64_t* tile_doff, const int64_t* widx, const void* pool,
                           const void* vecpool, const int32_t* perm, double alpha, double beta,
-                          double sigma2, void* z, int max_tile, int f64, hipStream_t st) {
+                          double sigma2, void* z, int max_tile, int smode, hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
-    if (f64)
-        return rowtile_dispatch<double>(ntiles, tile_lo, tile_col, tile_doff, widx, pool, vecpool,
-                                        perm, alpha, beta, sigma2, z, max_tile, st);
-    return rowtile_dispatch<float>(ntiles, tile_lo, tile_col, tile_doff, widx, pool, vecpool,
-                                   perm, alpha, beta, sigma2, z, max_tile, st);
+    if (smode == 0)
+        return rowtile_dispatch<double, double>(ntiles, tile_lo, tile_col, tile_doff, widx, pool,
+                                                vecpool, perm, alpha, beta, sigma2, z, max_tile,
+                                                st);
+    if (smode == 1)
+        return rowtile_dispatch<float, float>(ntiles, tile_lo, tile_col, tile_doff, widx, pool,
+                                              vecpool, perm, alpha, beta, sigma2, z, max_tile, st);
+    return rowtile_dispatch<uint16_t, float>(ntiles, tile_lo, tile_col, tile_doff, widx, pool,
+                                             vecpool, perm, alpha, beta, sigma2, z, max_tile, st);
 }
 
 }  // namespace hmx

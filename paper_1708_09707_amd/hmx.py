@@ -39,7 +39,8 @@ class hmx_kernel(C.Structure):
 class hmx_params(C.Structure):
     _fields_ = [("leaf_size", C.c_int32), ("eta", C.c_double), ("aca_eps", C.c_double),
                 ("aca_eta", C.c_double), ("aca_eps0", C.c_double), ("max_rank", C.c_int32),
-                ("sigma2", C.c_double), ("compute_dtype", C.c_int), ("rank_mode", C.c_int),
+                ("sigma2", C.c_double), ("compute_dtype", C.c_int), ("storage_dtype", C.c_int),
+                ("rank_mode", C.c_int),
                 ("reserved", C.c_int32 * 8)]
 
 
@@ -134,9 +135,11 @@ def hmx_params_default(**overrides) -> hmx_params:
     p = hmx_params()
     _check(lib().hmx_params_default(C.byref(p)))
     for k, v in overrides.items():
-        if k == "compute_dtype" and isinstance(v, str):
+        if k in ("compute_dtype", "storage_dtype") and isinstance(v, str):
             v = DTYPES[v]
         setattr(p, k, v)
+    if "compute_dtype" in overrides and "storage_dtype" not in overrides:
+        p.storage_dtype = p.compute_dtype  # store in the compute precision unless asked
     return p
 
 

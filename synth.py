@@ -90,4 +90,8 @@ WORKLOADS = {
     "gauss2d_n1m_f32": dict(n=1 << 20, d=2, dist="uniform", pts_seed=21, x_seed=2200,
                             kernel="gaussian", p0=0.01, leaf=256, eta=1.5, eps=1e-5,
                             kmax=64, dtype="f32", n_matvec=100),
+    # the same with BF16 storage of the near field and the factors
+    "gauss2d_n1m_bf16": dict(n=1 << 20, d=2, dist="uniform", pts_seed=21, x_seed=2200,
+                             kernel="gaussian", p0=0.01, leaf=256, eta=1.5, eps=1e-5,
+                             kmax=64, dtype="f32", storage="bf16", n_matvec=100),
 }

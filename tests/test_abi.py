@@ -36,8 +36,9 @@ def test_struct_layout_matches_c(tmp_path):
 #include "hmx.h"
 int main(void) {
   printf("%zu %zu %zu\\n", sizeof(hmx_params), sizeof(hmx_stats), sizeof(hmx_kernel));
-  printf("%zu %zu %zu %zu\\n", offsetof(hmx_params, max_rank), offsetof(hmx_params, sigma2),
-         offsetof(hmx_params, rank_mode), offsetof(hmx_params, reserved));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(hmx_params, max_rank), offsetof(hmx_params, sigma2),
+         offsetof(hmx_params, rank_mode), offsetof(hmx_params, reserved),
+         offsetof(hmx_params, storage_dtype));
   printf("%zu %zu %zu %zu\\n", offsetof(hmx_stats, matvec_bytes), offsetof(hmx_stats, device_bytes),
          offsetof(hmx_stats, level_sizes), offsetof(hmx_stats, v_entries));
   return 0;
@@ -50,6 +51,7 @@ int main(void) {
     want = [C.sizeof(hmx.hmx_params), C.sizeof(hmx.hmx_stats), C.sizeof(hmx.hmx_kernel),
             hmx.hmx_params.max_rank.offset, hmx.hmx_params.sigma2.offset,
             hmx.hmx_params.rank_mode.offset, hmx.hmx_params.reserved.offset,
+            hmx.hmx_params.storage_dtype.offset,
             hmx.hmx_stats.matvec_bytes.offset, hmx.hmx_stats.device_bytes.offset,
             hmx.hmx_stats.level_sizes.offset, hmx.hmx_stats.v_entries.offset]
     assert [int(v) for v in out] == want
@@ -83,6 +85,10 @@ def test_validation_before_device_work():
         assert L.hmx_build(dummy, 0, 10, 2, C.byref(K), C.byref(Q), None, C.byref(h)) == 1, field
         assert b"invalid params" in L.hmx_last_error()
     Q = hmx.hmx_params_default(compute_dtype=hmx.HMX_BF16)
+    assert L.hmx_build(dummy, 0, 10, 2, C.byref(K), C.byref(Q), None, C.byref(h)) == 5
+    Q = hmx.hmx_params_default(compute_dtype="f64", storage_dtype="bf16")
+    assert L.hmx_build(dummy, 0, 10, 2, C.byref(K), C.byref(Q), None, C.byref(h)) == 5
+    Q = hmx.hmx_params_default(compute_dtype="f32", storage_dtype="f64")
     assert L.hmx_build(dummy, 0, 10, 2, C.byref(K), C.byref(Q), None, C.byref(h)) == 5
     K0 = hmx.make_kernel("gaussian", 0.0)
     assert L.hmx_build(dummy, 0, 10, 2, C.byref(K0), C.byref(P), None, C.byref(h)) == 1

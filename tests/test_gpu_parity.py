@@ -266,3 +266,56 @@ def test_full_size_partition_and_sampled_rows(H, orc):
     print("sampled-row rel err %.3e" % err)
     assert err <= 1e-4
     hm.close()
+
+
+def _bf16_rne(a):
+    """float32 -> bfloat16 (round to nearest, ties to even) -> float32, numpy."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32)
+
+
+def test_bf16_storage_is_rounded_f32(H, orc):
+    """BF16 storage rounds exactly the FP32 factors of the same ACA (round to
+    nearest even), and the product meets the BF16 tolerance."""
+    pts = synth.uniform_points(4096, 2, 11)
+    x = synth.normal_vector(4096, 12)
+    eps = 1e-6
+    kw = dict(leaf_size=64, eta=1.5, aca_eps=eps, max_rank=32)
+    h32 = _build(H, pts, "gaussian", 0.1, "f32", **kw)
+    h16 = H.HMatrix(_dev(pts), "gaussian", 0.1, compute_dtype="f32", storage_dtype="bf16", **kw)
+    assert np.array_equal(h32.ranks(), h16.ranks())
+    adm = h32.partition()["adm"]
+    for q in [0, 7, len(adm) // 2, len(adm) - 1]:
+        b = adm[q]
+        m, n = b[1] - b[0], b[3] - b[2]
+        U32, V32, r = H.hmx_get_factors(h32.h, int(q), m, n, 32)
+        U16, V16, r2 = H.hmx_get_factors(h16.h, int(q), m, n, 32)
+        assert r == r2
+        assert np.array_equal(U16, _bf16_rne(U32).astype(np.float64))
+        assert np.array_equal(V16, _bf16_rne(V32).astype(np.float64))
+    xd = _dev(x).float()
+    z16 = h16.matvec(xd).double().cpu().numpy()
+    zd = orc.dense_matvec(pts, x, "gaussian", 0.1)
+    err = np.linalg.norm(z16 - zd) / np.linalg.norm(zd)
+    print("bf16 rel err %.3e" % err)
+    assert err <= 10 * eps + 4 * 2.0 ** -9
+    st = h16.stats()
+    assert st.entry_bytes == 2
+    h32.close()
+    h16.close()
+
+
+def test_bf16_ragged_tiles(H, orc):
+    """Tiles whose height is not a multiple of 8 (BF16 vectors) use the padded
+    tile layout; the product still meets the BF16 tolerance."""
+    pts = synth.uniform_points(5003, 3, 17)
+    x = synth.normal_vector(5003, 18)
+    hm = H.HMatrix(_dev(pts), "matern32", 0.3, compute_dtype="f32", storage_dtype="bf16",
+                   leaf_size=37, eta=1.5, aca_eps=1e-5, max_rank=48)
+    z = hm.matvec(_dev(x).float()).double().cpu().numpy()
+    zd = orc.dense_matvec(pts, x, "matern32", 0.3)
+    err = np.linalg.norm(z - zd) / np.linalg.norm(zd)
+    print("bf16 ragged rel err %.3e" % err)
+    assert err <= 1e-4 + 4 * 2.0 ** -9
+    hm.close()
