@@ -99,7 +99,11 @@ typedef struct {
                                 F64 compute), HMX_F32 or HMX_BF16 (require F32
                                 compute; BF16 rounds to nearest even) */
     hmx_rank_mode rank_mode;
-    int32_t reserved[8];
+    int32_t aca_chunk_mb;    /* ACA scratch budget per chunk of admissible blocks,
+                                MiB; 0 selects 8192.  Blocks are approximated in
+                                chunks whose k_max-column scratch fits the budget,
+                                then compacted to their exact ranks */
+    int32_t reserved[7];
 } hmx_params;
 
 /* Statistics of a built H-matrix (host struct). */
@@ -117,6 +121,7 @@ typedef struct {
     int64_t v_entries;        /* sum_adm rank * |sigma| (V pool) */
     int64_t near_entries;     /* sum_dense |tau| * |sigma| */
     int64_t aca_columns;      /* ACA residual columns evaluated (incl. skipped) */
+    int64_t aca_chunks;       /* chunks the admissible leaves were approximated in */
     double matvec_bytes;      /* algorithmic HBM bytes of one matvec (beta = 0) */
     double phase_ms[8];       /* build phases: order, tree, traversal, aca,
                                  compaction, near field, matvec plan, total */

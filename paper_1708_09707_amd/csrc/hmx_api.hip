@@ -418,33 +418,43 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
     t0 = clk::now();
 
     const int kmax = h->prm.max_rank;
-    DevBuf scan_scr, total;
-    alloc(total, 8, "total");
+    DevBuf scan_scr;
+    // exclusive scan of data[0..cnt) in place; the total is also stored in
+    // data[cnt] (every offset array has cnt + 1 entries) and returned
     auto scan = [&](int64_t* data, int64_t cnt) -> int64_t {
         const size_t need = scan_scratch_bytes(cnt + 1) + 64;
         if (!scan_scr.p || scan_scr.bytes < need) alloc(scan_scr, need, "scan scratch");
-        check(exclusive_scan_i64(data, cnt, total.as<int64_t>(), scan_scr.p, st), "scan");
-        return read_scalar(total.as<int64_t>(), st);
+        check(exclusive_scan_i64(data, cnt, data + cnt, scan_scr.p, st), "scan");
+        return read_scalar(data + cnt, st);
     };
 
-    // ---- 4. batched ACA of the admissible leaves (capacity pools) ----
+    // ---- 4. batched ACA of the admissible leaves, in chunks ----
+    // Each chunk of consecutive admissible leaves gets k_max-column scratch
+    // for U and V within the budget; after its ACA the factors are compacted
+    // to their exact ranks (U in the compute type as the source of the
+    // tile-major pool, V in the storage type).
     alloc(h->rank, std::max<int64_t>(h->n_adm, 1) * 4, "ranks");
     alloc(h->steps, std::max<int64_t>(h->n_adm, 1) * 4, "steps");
     alloc(h->voff, (h->n_adm + 1) * 8, "V offsets");
-    DevBuf cu, cv, Ucap, Vcap;
-    alloc(cu, (h->n_adm + 1) * 8, "U capacity offsets");
-    alloc(cv, (h->n_adm + 1) * 8, "V capacity offsets");
+    DevBuf cu, cv, cc, Ucap, Vcap, Uex, uoff_ex;
+    alloc(uoff_ex, (h->n_adm + 1) * 8, "U offsets");
+    int nchunks = 0;
     if (h->n_adm > 0) {
+        alloc(cu, (h->n_adm + 1) * 8, "U capacity offsets");
+        alloc(cv, (h->n_adm + 1) * 8, "V capacity offsets");
+        alloc(cc, (h->n_adm + 1) * 8, "capacity offsets");
         check(launch_extent(h->adm.as<int4>(), h->n_adm, 0, kmax, nullptr, nullptr,
                             cu.as<int64_t>(), st),
               "extent");
         check(launch_extent(h->adm.as<int4>(), h->n_adm, 1, kmax, nullptr, nullptr,
                             cv.as<int64_t>(), st),
               "extent");
-        const int64_t ucap = scan(cu.as<int64_t>(), h->n_adm);
-        const int64_t vcap = scan(cv.as<int64_t>(), h->n_adm);
-        alloc(Ucap, ucap * esz, "U capacity pool");
-        alloc(Vcap, vcap * esz, "V capacity pool");
+        check(launch_extent(h->adm.as<int4>(), h->n_adm, 7, kmax, nullptr, nullptr,
+                            cc.as<int64_t>(), st),
+              "extent");
+        scan(cu.as<int64_t>(), h->n_adm);
+        scan(cv.as<int64_t>(), h->n_adm);
+        const int64_t ctot = scan(cc.as<int64_t>(), h->n_adm);
         const int64_t big = big_adm;
         const int words = (int)(2 * ((big + 31) / 32));
         if ((size_t)words * 4 > 64 * 1024) {
@@ -452,16 +462,40 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
                     (long long)big);
             throw Fail{HMX_ERR_UNSUPPORTED};
         }
+        // chunking: each chunk's capacity is at most step + one block
+        const int64_t budget_mb = h->prm.aca_chunk_mb > 0 ? h->prm.aca_chunk_mb : 8192;
+        const int64_t budget = std::max<int64_t>(budget_mb * ((int64_t)1 << 20) / (int64_t)esz, 1);
+        nchunks = (int)std::min<int64_t>((ctot + budget - 1) / budget, 1 << 20);
+        nchunks = std::max(nchunks, 1);
+        const int64_t step = (ctot + nchunks - 1) / nchunks;
+        DevBuf bnd;
+        alloc(bnd, (size_t)(nchunks + 1) * 8, "chunk bounds");
+        check(launch_chunk_bounds(cc.as<int64_t>(), h->n_adm, step, nchunks, bnd.as<int64_t>(),
+                                  st),
+              "chunk bounds");
+        std::vector<int64_t> hb(nchunks + 1), hcu(nchunks + 1), hcv(nchunks + 1);
+        d2h(hb.data(), bnd.p, (nchunks + 1) * 8, st);
+        // capacity offsets at the boundaries (cu, cv have n_adm + 1 valid entries)
+        int64_t max_u = 0, max_v = 0;
+        for (int k = 0; k <= nchunks; ++k) {
+            check(hipMemcpyAsync(&hcu[k], cu.as<int64_t>() + hb[k], 8, hipMemcpyDeviceToHost, st),
+                  "cu");
+            check(hipMemcpyAsync(&hcv[k], cv.as<int64_t>() + hb[k], 8, hipMemcpyDeviceToHost, st),
+                  "cv");
+        }
+        check(hipStreamSynchronize(st), "bounds sync");
+        for (int k = 0; k < nchunks; ++k) {
+            max_u = std::max(max_u, hcu[k + 1] - hcu[k]);
+            max_v = std::max(max_v, hcv[k + 1] - hcv[k]);
+        }
+        alloc(Ucap, (size_t)std::max<int64_t>(max_u, 1) * esz, "U chunk scratch");
+        alloc(Vcap, (size_t)std::max<int64_t>(max_v, 1) * esz, "V chunk scratch");
         AcaArgs a{};
         a.soa = f64 ? h->soa64.p : h->soa32.p;
         a.soa64 = h->soa64.as<double>();
         a.n = n;
         a.d = d;
         a.kern = KernelFn{(int)h->kern.kind, h->kern.p0};
-        a.blocks = h->adm.as<int4>();
-        a.nblocks = h->n_adm;
-        a.uoff = cu.as<int64_t>();
-        a.voff = cv.as<int64_t>();
         a.kmax = kmax;
         a.eps = h->prm.aca_eps;
         a.aca_eta = h->prm.aca_eta;
@@ -469,31 +503,50 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
         a.fixed = h->prm.rank_mode == HMX_RANK_FIXED;
         a.U = Ucap.p;
         a.V = Vcap.p;
-        a.rank = h->rank.as<int32_t>();
-        a.steps = h->steps.as<int32_t>();
         a.lds_words = std::max(words, 2);
-        check(launch_aca(a, f64, st), "aca");
-        check(hipStreamSynchronize(st), "aca sync");
-        S.phase_ms[3] = ms_since(t0);
-        t0 = clk::now();
-        // V pool (exact ranks), U entry count
-        DevBuf ue_cnt;
-        alloc(ue_cnt, (h->n_adm + 1) * 8, "U entries");
-        check(launch_extent(h->adm.as<int4>(), h->n_adm, 3, 0, h->rank.as<int32_t>(), nullptr,
-                            ue_cnt.as<int64_t>(), st),
-              "extent");
-        S.u_entries = scan(ue_cnt.as<int64_t>(), h->n_adm);
-        check(launch_extent(h->adm.as<int4>(), h->n_adm, 4, 0, h->rank.as<int32_t>(), nullptr,
-                            h->voff.as<int64_t>(), st),
-              "extent");
-        S.v_entries = scan(h->voff.as<int64_t>(), h->n_adm);
-        alloc(h->V, S.v_entries * ssz, "V pool");
-        check(launch_compact_v(h->adm.as<int4>(), h->n_adm, h->rank.as<int32_t>(),
-                               cv.as<int64_t>(), h->voff.as<int64_t>(), Vcap.p, h->V.p, smode, st),
-              "compact V");
-        check(hipStreamSynchronize(st), "compact sync");
+        double aca_ms = 0.0;
+        int64_t utot = 0, vtot = 0;
+        for (int k = 0; k < nchunks; ++k) {
+            const int64_t b0 = hb[k], nbk = hb[k + 1] - hb[k];
+            if (nbk == 0) continue;
+            const auto ta = clk::now();
+            a.blocks = h->adm.as<int4>() + b0;
+            a.nblocks = nbk;
+            a.uoff = cu.as<int64_t>() + b0;
+            a.voff = cv.as<int64_t>() + b0;
+            a.ubase = hcu[k];
+            a.vbase = hcv[k];
+            a.rank = h->rank.as<int32_t>() + b0;
+            a.steps = h->steps.as<int32_t>() + b0;
+            check(launch_aca(a, f64, st), "aca");
+            check(hipStreamSynchronize(st), "aca sync");
+            aca_ms += ms_since(ta);
+            // exact offsets of this chunk's blocks: chunk-local scan plus the running totals
+            int64_t* ue = uoff_ex.as<int64_t>() + b0;
+            int64_t* ve = h->voff.as<int64_t>() + b0;
+            check(launch_extent(a.blocks, nbk, 3, 0, a.rank, nullptr, ue, st), "extent");
+            check(launch_extent(a.blocks, nbk, 4, 0, a.rank, nullptr, ve, st), "extent");
+            const int64_t uk = scan(ue, nbk), vk = scan(ve, nbk);
+            check(launch_add_const(ue, nbk, utot, st), "offsets");
+            check(launch_add_const(ve, nbk, vtot, st), "offsets");
+            grow(Uex, (size_t)(utot + uk) * esz, (size_t)utot * esz, st, "U pool");
+            grow(h->V, (size_t)(vtot + vk) * ssz, (size_t)vtot * ssz, st, "V pool");
+            check(launch_compact_u(a.blocks, nbk, a.rank, a.uoff, a.ubase, ue, Ucap.p, Uex.p, f64,
+                                   st),
+                  "compact U");
+            check(launch_compact_v(a.blocks, nbk, a.rank, a.voff, a.vbase, ve, Vcap.p, h->V.p,
+                                   smode, st),
+                  "compact V");
+            check(hipStreamSynchronize(st), "compact sync");
+            utot += uk;
+            vtot += vk;
+        }
+        Ucap.release();
         Vcap.release();
-        h->factor_entries = S.u_entries + S.v_entries;
+        S.u_entries = utot;
+        S.v_entries = vtot;
+        h->factor_entries = utot + vtot;
+        S.phase_ms[3] = aca_ms;
         // rank statistics, reduced on the device
         DevBuf red;
         alloc(red, 4 * sizeof(unsigned long long), "stats");
@@ -505,9 +558,12 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
         check(hipStreamSynchronize(st), "stats sync");
         S.max_rank_used = (int32_t)hv[0];
         S.aca_columns = (int64_t)hv[3];
-    } else {
-        alloc(h->V, 16, "V pool");
     }
+    if (!h->V.p) alloc(h->V, 16, "V pool");
+    if (!Uex.p) alloc(Uex, 16, "U pool");
+    S.aca_chunks = nchunks;
+    S.phase_ms[4] = ms_since(t0) - S.phase_ms[3];
+    t0 = clk::now();
     // t offsets, vector pool, column -> leaf map of phase 1
     alloc(h->toff, (h->n_adm + 1) * 8, "t offsets");
     if (h->n_adm > 0) {
@@ -521,7 +577,7 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
     check(launch_col_block(h->rank.as<int32_t>(), h->toff.as<int64_t>(), h->n_adm,
                            h->col_block.as<int32_t>(), st),
           "column map");
-    S.phase_ms[4] = ms_since(t0);
+    S.phase_ms[4] += ms_since(t0);
     t0 = clk::now();
 
     // ---- 5. tile-major matrix pool: pieces (leaf block x row tile) sorted by
@@ -582,13 +638,13 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
               "tile meta");
         alloc(h->pool, (size_t)std::max<int64_t>(h->pool_entries, 1) * ssz, "matrix pool");
         check(launch_piece_data(h->pieces.as<Piece>(), h->npieces, h->tile_lo.as<int32_t>(),
-                                h->adm.as<int4>(), h->dense.as<int4>(), cu.as<int64_t>(), Ucap.p,
+                                h->adm.as<int4>(), h->dense.as<int4>(), uoff_ex.as<int64_t>(), Uex.p,
                                 f64 ? h->soa64.p : h->soa32.p, n, d,
                                 KernelFn{(int)h->kern.kind, h->kern.p0}, h->pool.p, smode, st),
               "piece data");
         check(hipStreamSynchronize(st), "pool sync");
     }
-    Ucap.release();
+    Uex.release();
     // near-field entry count (algorithmic, unpadded)
     if (h->n_dense > 0) {
         DevBuf ne;

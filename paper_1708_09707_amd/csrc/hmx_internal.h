@@ -148,6 +148,7 @@ struct AcaArgs {
     int64_t nblocks;
     const int64_t* uoff;  // per block, capacity offsets (entries)
     const int64_t* voff;
+    int64_t ubase, vbase; // subtracted from uoff / voff (offset of the chunk's first block)
     int kmax;
     double eps, aca_eta, eps0;
     int fixed;
@@ -171,7 +172,8 @@ struct Piece {
     int32_t row0;   // first row of the tile inside the block's tau
 };
 // per-block sizes: mode 0: m * mult, 1: n * mult, 2: m * n, 3: r * m, 4: r * n,
-// 5: r, 6: row tiles covered by tau (0 for an admissible leaf of rank 0)
+// 5: r, 6: row tiles covered by tau (0 for an admissible leaf of rank 0),
+// 7: (m + n) * mult
 hipError_t launch_extent(const int4* blocks, int64_t nb, int mode, int64_t mult,
                          const int32_t* rank, const int32_t* tile_of_point, int64_t* out,
                          hipStream_t st);
@@ -197,10 +199,19 @@ hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* til
                              void* pool, int smode, hipStream_t st);
 // smode: storage mode 0 = F64, 1 = F32, 2 = BF16 storage with F32 arithmetic
 hipError_t launch_compact_v(const int4* blocks, int64_t nblocks, const int32_t* rank,
-                            const int64_t* cap_voff, const int64_t* voff, const void* Vcap,
-                            void* V, int smode, hipStream_t st);
+                            const int64_t* cap_voff, int64_t cap_base, const int64_t* voff,
+                            const void* Vcap, void* V, int smode, hipStream_t st);
 hipError_t launch_gather_x(const void* x, const int32_t* perm, int64_t n, void* xm, int f64,
                            hipStream_t st);
+// data[i] += c for i < n
+hipError_t launch_add_const(int64_t* data, int64_t n, int64_t c, hipStream_t st);
+// U compaction into the exact per-block pool (compute type)
+hipError_t launch_compact_u(const int4* blocks, int64_t nblocks, const int32_t* rank,
+                            const int64_t* cap_uoff, int64_t cap_base, const int64_t* uoff,
+                            const void* Ucap, void* U, int f64, hipStream_t st);
+// chunk boundaries: bnd[k] = first block whose capacity offset is >= k * step
+hipError_t launch_chunk_bounds(const int64_t* cap_off, int64_t nb, int64_t step, int nchunks,
+                               int64_t* bnd, hipStream_t st);
 // out[0] = max and out[1] = sum of n non-negative int32 values (device)
 hipError_t launch_int_stats(const int32_t* a, int64_t n, unsigned long long* out,
                             hipStream_t st);

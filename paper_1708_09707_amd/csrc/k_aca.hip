@@ -216,7 +216,8 @@ template <typename T>
 __global__ __launch_bounds__(kAcaThreads) void aca_kernel(
     const T* __restrict__ soa, const double* __restrict__ soa64, int64_t n, int d, KernelEval<T> K,
     const int4* __restrict__ blocks, int64_t nblocks, const int64_t* __restrict__ uoff,
-    const int64_t* __restrict__ voff, int kmax, double eps, double aca_eta, T eps0, int fixed,
+    const int64_t* __restrict__ voff, int64_t ubase, int64_t vbase, int kmax, double eps,
+    double aca_eta, T eps0, int fixed,
     T* __restrict__ Upool, T* __restrict__ Vpool, int32_t* __restrict__ rank_out,
     int32_t* __restrict__ steps_out) {
     extern __shared__ uint32_t smask[];
@@ -230,8 +231,8 @@ __global__ __launch_bounds__(kAcaThreads) void aca_kernel(
         int R = kmax;
         R = m < R ? m : R;
         R = nc < R ? nc : R;
-        T* __restrict__ U = Upool + uoff[b];
-        T* __restrict__ V = Vpool + voff[b];
+        T* __restrict__ U = Upool + (uoff[b] - ubase);
+        T* __restrict__ V = Vpool + (voff[b] - vbase);
         const int mw = (m + 31) >> 5, nw = (nc + 31) >> 5;
         uint32_t* rmask = smask;
         uint32_t* cmask = smask + mw;
@@ -358,13 +359,13 @@ hipError_t launch_aca(const AcaArgs& a, int f64, hipStream_t st) {
         KernelEval<double> K(a.kern);
         hipLaunchKernelGGL(aca_kernel<double>, dim3(grid), dim3(kAcaThreads), lds, st,
                            (const double*)a.soa, a.soa64, a.n, a.d, K, a.blocks, a.nblocks, a.uoff, a.voff,
-                           a.kmax, a.eps, a.aca_eta, (double)a.eps0, a.fixed, (double*)a.U,
+                           a.ubase, a.vbase, a.kmax, a.eps, a.aca_eta, (double)a.eps0, a.fixed, (double*)a.U,
                            (double*)a.V, a.rank, a.steps);
     } else {
         KernelEval<float> K(a.kern);
         hipLaunchKernelGGL(aca_kernel<float>, dim3(grid), dim3(kAcaThreads), lds, st,
                            (const float*)a.soa, a.soa64, a.n, a.d, K, a.blocks, a.nblocks, a.uoff, a.voff,
-                           a.kmax, a.eps, a.aca_eta, (float)a.eps0, a.fixed, (float*)a.U,
+                           a.ubase, a.vbase, a.kmax, a.eps, a.aca_eta, (float)a.eps0, a.fixed, (float*)a.U,
                            (float*)a.V, a.rank, a.steps);
     }
     return hipGetLastError();

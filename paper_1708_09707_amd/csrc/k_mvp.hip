@@ -115,6 +115,7 @@ __global__ void extent_kernel(const int4* __restrict__ blocks, int64_t nb, int m
         case 3: v = (int64_t)rank[b] * m; break;
         case 4: v = (int64_t)rank[b] * nc; break;
         case 5: v = rank[b]; break;
+        case 7: v = (m + nc) * mult; break;
         default:
             v = (rank && rank[b] == 0)
                     ? 0
@@ -291,16 +292,63 @@ __global__ __launch_bounds__(256) void compact_v_kernel(const int4* __restrict__
                                                         int64_t nblocks,
                                                         const int32_t* __restrict__ rank,
                                                         const int64_t* __restrict__ cv,
+                                                        int64_t cbase,
                                                         const int64_t* __restrict__ ev,
                                                         const T* __restrict__ Vcap,
                                                         S* __restrict__ V) {
     for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
         const int4 bl = blocks[b];
         const int64_t nc = bl.w - bl.z, r = rank[b];
-        const T* sv = Vcap + cv[b];
+        const T* sv = Vcap + (cv[b] - cbase);
         S* dv = V + ev[b];
         for (int64_t e = threadIdx.x; e < r * nc; e += blockDim.x) dv[e] = Store<S, T>::put(sv[e]);
     }
+}
+
+// U compaction into the exact per-block pool (compute type, source of the
+// tile-major matrix pool)
+template <typename T>
+__global__ __launch_bounds__(256) void compact_u_kernel(const int4* __restrict__ blocks,
+                                                        int64_t nblocks,
+                                                        const int32_t* __restrict__ rank,
+                                                        const int64_t* __restrict__ cu,
+                                                        int64_t cbase,
+                                                        const int64_t* __restrict__ eu,
+                                                        const T* __restrict__ Ucap,
+                                                        T* __restrict__ U) {
+    for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
+        const int4 bl = blocks[b];
+        const int64_t m = bl.y - bl.x, r = rank[b];
+        const T* su = Ucap + (cu[b] - cbase);
+        T* du = U + eu[b];
+        for (int64_t e = threadIdx.x; e < r * m; e += blockDim.x) du[e] = su[e];
+    }
+}
+
+__global__ void add_const_kernel(int64_t* __restrict__ a, int64_t n, int64_t c) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) a[i] += c;
+}
+
+// bnd[k] = lower bound of k * step in the non-decreasing cap_off[0..nb]
+__global__ void chunk_bounds_kernel(const int64_t* __restrict__ cap_off, int64_t nb, int64_t step,
+                                    int nchunks, int64_t* __restrict__ bnd) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > nchunks) return;
+    if (k == nchunks) {
+        bnd[k] = nb;
+        return;
+    }
+    const int64_t target = (int64_t)k * step;
+    int64_t lo = 0, hi = nb;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (cap_off[mid] < target)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    bnd[k] = lo;
 }
 
 // column -> admissible leaf map for the flattened factor columns
@@ -596,21 +644,50 @@ hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* til
 }
 
 hipError_t launch_compact_v(const int4* blocks, int64_t nblocks, const int32_t* rank,
-                            const int64_t* cap_voff, const int64_t* voff, const void* Vcap,
-                            void* V, int smode, hipStream_t st) {
+                            const int64_t* cap_voff, int64_t cap_base, const int64_t* voff,
+                            const void* Vcap, void* V, int smode, hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
     const unsigned grid = grid_cap(nblocks, 1 << 20);
     if (smode == 0)
         hipLaunchKernelGGL((compact_v_kernel<double, double>), dim3(grid), dim3(256), 0, st,
-                           blocks, nblocks, rank, cap_voff, voff, (const double*)Vcap,
+                           blocks, nblocks, rank, cap_voff, cap_base, voff, (const double*)Vcap,
                            (double*)V);
     else if (smode == 1)
         hipLaunchKernelGGL((compact_v_kernel<float, float>), dim3(grid), dim3(256), 0, st,
-                           blocks, nblocks, rank, cap_voff, voff, (const float*)Vcap, (float*)V);
+                           blocks, nblocks, rank, cap_voff, cap_base, voff, (const float*)Vcap,
+                           (float*)V);
     else
         hipLaunchKernelGGL((compact_v_kernel<uint16_t, float>), dim3(grid), dim3(256), 0, st,
-                           blocks, nblocks, rank, cap_voff, voff, (const float*)Vcap,
+                           blocks, nblocks, rank, cap_voff, cap_base, voff, (const float*)Vcap,
                            (uint16_t*)V);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_u(const int4* blocks, int64_t nblocks, const int32_t* rank,
+                            const int64_t* cap_uoff, int64_t cap_base, const int64_t* uoff,
+                            const void* Ucap, void* U, int f64, hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    const unsigned grid = grid_cap(nblocks, 1 << 20);
+    if (f64)
+        hipLaunchKernelGGL(compact_u_kernel<double>, dim3(grid), dim3(256), 0, st, blocks, nblocks,
+                           rank, cap_uoff, cap_base, uoff, (const double*)Ucap, (double*)U);
+    else
+        hipLaunchKernelGGL(compact_u_kernel<float>, dim3(grid), dim3(256), 0, st, blocks, nblocks,
+                           rank, cap_uoff, cap_base, uoff, (const float*)Ucap, (float*)U);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_const(int64_t* data, int64_t n, int64_t c, hipStream_t st) {
+    if (n <= 0 || c == 0) return hipSuccess;
+    hipLaunchKernelGGL(add_const_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, data,
+                       n, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_bounds(const int64_t* cap_off, int64_t nb, int64_t step, int nchunks,
+                               int64_t* bnd, hipStream_t st) {
+    hipLaunchKernelGGL(chunk_bounds_kernel, dim3((unsigned)((nchunks + 1 + 255) / 256)), dim3(256),
+                       0, st, cap_off, nb, step, nchunks, bnd);
     return hipGetLastError();
 }
 

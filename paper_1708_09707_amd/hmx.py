@@ -40,8 +40,8 @@ class hmx_params(C.Structure):
     _fields_ = [("leaf_size", C.c_int32), ("eta", C.c_double), ("aca_eps", C.c_double),
                 ("aca_eta", C.c_double), ("aca_eps0", C.c_double), ("max_rank", C.c_int32),
                 ("sigma2", C.c_double), ("compute_dtype", C.c_int), ("storage_dtype", C.c_int),
-                ("rank_mode", C.c_int),
-                ("reserved", C.c_int32 * 8)]
+                ("rank_mode", C.c_int), ("aca_chunk_mb", C.c_int32),
+                ("reserved", C.c_int32 * 7)]
 
 
 class hmx_stats(C.Structure):
@@ -51,6 +51,7 @@ class hmx_stats(C.Structure):
                 ("entry_bytes", C.c_int32), ("factor_entries", C.c_int64),
                 ("u_entries", C.c_int64), ("v_entries", C.c_int64),
                 ("near_entries", C.c_int64), ("aca_columns", C.c_int64),
+                ("aca_chunks", C.c_int64),
                 ("matvec_bytes", C.c_double), ("phase_ms", C.c_double * 8),
                 ("device_bytes", C.c_int64), ("level_sizes", C.c_int64 * 64)]
 

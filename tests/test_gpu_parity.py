@@ -218,6 +218,24 @@ def test_determinism(H):
         assert np.array_equal(a, b)
 
 
+def test_aca_chunking_is_invisible(H):
+    """Approximating the admissible leaves in many small chunks gives the same
+    ranks, factors and product bits as one chunk."""
+    pts = synth.uniform_points(40000, 3, 23)
+    x = _dev(synth.normal_vector(40000, 24)).float()
+    outs = []
+    for mb in [0, 1]:
+        hm = _build(H, pts, "gaussian", 0.02, "f32", leaf_size=64, eta=1.5, aca_eps=1e-5,
+                    aca_chunk_mb=mb)
+        st = hm.stats()
+        print("chunks", st.aca_chunks)
+        outs.append((st.aca_chunks, hm.ranks(), hm.matvec(x).cpu().numpy()))
+        hm.close()
+    assert outs[0][0] == 1 and outs[1][0] > 10
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[0][2], outs[1][2])
+
+
 def test_invalid_arguments(H):
     pts = _dev(synth.uniform_points(100, 2, 1))
     K = H.make_kernel("gaussian", 0.1)
