@@ -155,6 +155,22 @@ hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t
 hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype, double alpha,
                       double beta, void* stream);
 
+/* Conjugate gradients for (H + sigma2 I) c = b, the kernel ridge regression
+ * / Gaussian process system of Section 1, with H this handle's H-matrix and
+ * sigma2 from its params (textbook CG; inner products accumulated in FP64).
+ *   b, x : device vectors of n entries, original point order, compute dtype.
+ *          x is overwritten; the iteration starts from x = 0.
+ *   stops when the recurrence residual |r| / |b| <= rel_tol, after max_iter
+ *   iterations, or on breakdown (p.(H + sigma2 I)p <= 0: the shifted
+ *   H-matrix is not positive definite to working precision).
+ *   iters, rel_res (recurrence), true_rel_res (|b - (H + sigma2 I) x| / |b|,
+ *   one extra product at the end): host, optional.
+ * Returns HMX_ERR_NOT_CONVERGED when rel_tol was not reached (x holds the
+ * last iterate).  Host-blocking (one readback per iteration); allocates
+ * three work vectors. */
+hmx_status hmx_cg_solve(hmx_hmatrix h, const void* b, void* x, double rel_tol, int32_t max_iter,
+                        void* stream, int32_t* iters, double* rel_res, double* true_rel_res);
+
 /* Copy the ordering and the partition to host memory (any pointer may be
  * NULL to skip it):
  *   codes : n Morton codes in the ORIGINAL point order

@@ -65,6 +65,7 @@ def lib():
         L.hmxo_dense_block.argtypes = [P, i64, i32, i32, f64, i64, i64, i64, i64, P]
         L.hmxo_hmvp_rows.argtypes = [P, i64, i32, i32, f64, i32, f64, i32, f64, f64, f64, i32,
                                      i64, i64, P, P, P, P]
+        L.hmxo_cg_dense.argtypes = [P, i64, i32, i32, f64, f64, P, P, f64, i32, P, P]
         L.hmxo_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -267,3 +268,15 @@ def hmvp_rows(pts, x, kind, p0, leaf, eta, kmax, eps, row_lo, row_hi, aca_eta=0.
         raise ValueError("hmxo_hmvp_rows failed: %d" % rc)
     return z, perm, dict(partition_s=t[0], build_s=t[1], apply_s=t[2], entries=t[3],
                          blocks=int(t[4]))
+
+
+def cg_dense(pts, b, kind, p0, sigma2, tol=1e-10, max_iter=10000):
+    """CG on the dense (A + sigma2 I) x = b.  Returns (x, rc, iters, rel_res)."""
+    pts = _f64(pts)
+    n, d = pts.shape
+    b = _f64(b)
+    x = np.zeros(n)
+    it, res = C.c_int32(0), C.c_double(0)
+    rc = lib().hmxo_cg_dense(_p(pts), n, d, kind_of(kind), float(p0), float(sigma2), _p(b),
+                             _p(x), float(tol), int(max_iter), C.byref(it), C.byref(res))
+    return x, rc, it.value, res.value

@@ -852,3 +852,62 @@ int hmxo_hmvp_rows(const double* pts, int64_t n, int32_t d, int32_t kind, double
     free(xm);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Conjugate gradients (Hestenes-Stiefel) on the dense system               */
+/* (A + sigma2 I) x = b with the brute-force product: the reference for the */
+/* kernel ridge regression solve.  x starts at 0; stops when |r|/|b| <= tol */
+/* (recurrence residual).  Returns 0 converged, 1 not converged, 2 breakdown */
+/* ------------------------------------------------------------------------ */
+int hmxo_cg_dense(const double* pts, int64_t n, int32_t d, int32_t kind, double p0,
+                  double sigma2, const double* b, double* x, double tol, int32_t max_iter,
+                  int32_t* iters, double* rel_res)
+{
+    double* r = (double*)malloc(sizeof(double) * n);
+    double* p = (double*)malloc(sizeof(double) * n);
+    double* q = (double*)malloc(sizeof(double) * n);
+    if (!r || !p || !q) return -2;
+    double bb = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        x[i] = 0.0;
+        r[i] = b[i];
+        p[i] = b[i];
+        bb += b[i] * b[i];
+    }
+    double rr = bb;
+    int rc = 1;
+    int32_t it = 0;
+    double res = bb > 0.0 ? 1.0 : 0.0;
+    if (bb == 0.0) rc = 0;
+    while (rc == 1 && it < max_iter) {
+        hmxo_dense_matvec(pts, n, d, kind, p0, sigma2, p, NULL, 0, q);
+        double pq = 0.0;
+        for (int64_t i = 0; i < n; ++i) pq += p[i] * q[i];
+        ++it;
+        if (!(pq > 0.0)) {
+            rc = 2;
+            break;
+        }
+        const double alpha = rr / pq;
+        double rr2 = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] += alpha * p[i];
+            r[i] -= alpha * q[i];
+            rr2 += r[i] * r[i];
+        }
+        res = sqrt(rr2 / bb);
+        if (res <= tol) {
+            rc = 0;
+            break;
+        }
+        const double beta = rr2 / rr;
+        for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
+        rr = rr2;
+    }
+    if (iters) *iters = it;
+    if (rel_res) *rel_res = res;
+    free(r);
+    free(p);
+    free(q);
+    return rc;
+}

@@ -98,6 +98,13 @@ int hmxo_dense_matvec(const double* pts, int64_t n, int32_t d, int32_t kind, dou
                       double sigma2, const double* x, const int64_t* rows, int64_t nrows,
                       double* z);
 
+/* Conjugate gradients on the dense system (A + sigma2 I) x = b, x from 0,
+ * stopping at |r| / |b| <= tol.  Returns 0 converged, 1 not converged,
+ * 2 breakdown (p.Ap <= 0). */
+int hmxo_cg_dense(const double* pts, int64_t n, int32_t d, int32_t kind, double p0,
+                  double sigma2, const double* b, double* x, double tol, int32_t max_iter,
+                  int32_t* iters, double* rel_res);
+
 /* dense block A|tau x sigma of the Morton-ordered matrix, column-major m x n */
 int hmxo_dense_block(const double* soa, int64_t n, int32_t d, int32_t kind, double p0,
                      int64_t tlo, int64_t thi, int64_t slo, int64_t shi, double* A);

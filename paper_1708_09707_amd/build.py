@@ -25,7 +25,7 @@ COMMON = [
 ]
 # exact IEEE sequences required (ordering and partition are compared bit for bit)
 NO_CONTRACT = {"k_order.hip", "k_tree.hip"}
-SOURCES = ["k_order.hip", "k_tree.hip", "k_aca.hip", "k_mvp.hip", "hmx_api.hip"]
+SOURCES = ["k_order.hip", "k_tree.hip", "k_aca.hip", "k_mvp.hip", "k_blas.hip", "hmx_api.hip"]
 
 
 def hipcc() -> str:

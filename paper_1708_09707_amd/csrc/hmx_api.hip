@@ -828,6 +828,86 @@ hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype
     return HMX_OK;
 }
 
+hmx_status hmx_cg_solve(hmx_hmatrix h, const void* b, void* x, double rel_tol, int32_t max_iter,
+                        void* stream, int32_t* iters, double* rel_res, double* true_rel_res) {
+    if (!h || !b || !x || !(rel_tol >= 0) || max_iter < 0) {
+        set_err("invalid argument to hmx_cg_solve");
+        return HMX_ERR_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int f64 = h->f64;
+    const int64_t n = h->n;
+    const hmx_dtype vdt = f64 ? HMX_F64 : HMX_F32;
+    int32_t it = 0;
+    double rr = 0.0, bb = 0.0, res = 0.0;
+    hmx_status status = HMX_OK;
+    try {
+        DevBuf r, p, q, scal, partial;
+        alloc(r, (size_t)n * h->esz, "cg r");
+        alloc(p, (size_t)n * h->esz, "cg p");
+        alloc(q, (size_t)n * h->esz, "cg q");
+        alloc(scal, 8 * sizeof(double), "cg scalars");
+        alloc(partial, cg_scratch_bytes(), "cg partials");
+        double* sc = scal.as<double>();
+        double* pa = partial.as<double>();
+        check(launch_fill_zero(x, n, f64, st), "cg init");
+        check(launch_copy(r.p, b, n, f64, st), "cg init");
+        check(launch_copy(p.p, b, n, f64, st), "cg init");
+        check(launch_dot(b, b, n, f64, pa, sc + 3, st), "cg dot");
+        check(launch_copy(sc, sc + 3, 1, 1, st), "cg init");  // r.r = b.b
+        check(hipMemcpyAsync(&bb, sc + 3, 8, hipMemcpyDeviceToHost, st), "cg readback");
+        check(hipStreamSynchronize(st), "cg sync");
+        rr = bb;
+        if (bb == 0.0) {
+            if (iters) *iters = 0;
+            if (rel_res) *rel_res = 0.0;
+            if (true_rel_res) *true_rel_res = 0.0;
+            return HMX_OK;
+        }
+        res = 1.0;
+        status = HMX_ERR_NOT_CONVERGED;
+        while (it < max_iter) {
+            hmx_status s = hmx_matvec(h, p.p, q.p, vdt, 1.0, 0.0, stream);
+            if (s != HMX_OK) return s;
+            check(launch_dot(p.p, q.p, n, f64, pa, sc + 1, st), "cg dot");
+            check(launch_cg_update(x, r.p, p.p, q.p, sc, n, f64, pa, sc + 2, st), "cg update");
+            double two[2];
+            check(hipMemcpyAsync(two, sc + 1, 16, hipMemcpyDeviceToHost, st), "cg readback");
+            check(hipStreamSynchronize(st), "cg sync");
+            ++it;
+            if (!(two[0] > 0.0)) {
+                set_err("CG breakdown at iteration %d: p.Ap = %g", it, two[0]);
+                break;  // x holds a damaged last update; report not converged
+            }
+            rr = two[1];
+            res = sqrt(rr / bb);
+            if (res <= rel_tol) {
+                status = HMX_OK;
+                break;
+            }
+            check(launch_cg_direction(p.p, r.p, sc, n, f64, st), "cg direction");
+            check(launch_copy(sc, sc + 2, 1, 1, st), "cg shift");
+        }
+        if (status != HMX_OK && it >= max_iter) set_err("CG did not converge in %d iterations", it);
+        if (true_rel_res) {
+            // r = b - (H + sigma2 I) x
+            hmx_status s = hmx_matvec(h, x, q.p, vdt, 1.0, 0.0, stream);
+            if (s != HMX_OK) return s;
+            check(launch_sub(r.p, b, q.p, n, f64, st), "cg residual");
+            check(launch_dot(r.p, r.p, n, f64, pa, sc + 4, st), "cg residual");
+            double d2 = 0.0;
+            check(hipMemcpyAsync(&d2, sc + 4, 8, hipMemcpyDeviceToHost, st), "cg readback");
+            check(hipStreamSynchronize(st), "cg sync");
+            *true_rel_res = sqrt(d2 / bb);
+        }
+    } catch (const Fail& f) {
+        return f.s;
+    }
+    if (iters) *iters = it;
+    if (rel_res) *rel_res = res;
+    return status;
+}
+
 hmx_status hmx_get_partition(hmx_hmatrix h, uint64_t* codes, int32_t* perm, int32_t* adm,
                              int64_t* n_adm, int32_t* dense, int64_t* n_dense, void* stream) {
     if (!h) {

@@ -225,4 +225,19 @@ hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t*
                           const void* vecpool, const int32_t* perm, double alpha, double beta,
                           double sigma2, void* z, int max_tile, int smode, hipStream_t st);
 
+// conjugate gradients (k_blas.hip): FP64-accumulated inner products
+size_t cg_scratch_bytes();
+hipError_t launch_dot(const void* a, const void* b, int64_t n, int f64, double* partial,
+                      double* out, hipStream_t st);
+// x += alpha p, r -= alpha q with alpha = scal[0] / scal[1]; *out = r.r
+hipError_t launch_cg_update(void* x, void* r, const void* p, const void* q, const double* scal,
+                            int64_t n, int f64, double* partial, double* out, hipStream_t st);
+// p = r + (scal[2] / scal[0]) p
+hipError_t launch_cg_direction(void* p, const void* r, const double* scal, int64_t n, int f64,
+                               hipStream_t st);
+hipError_t launch_copy(void* dst, const void* src, int64_t n, int f64, hipStream_t st);
+hipError_t launch_fill_zero(void* dst, int64_t n, int f64, hipStream_t st);
+hipError_t launch_sub(void* out, const void* a, const void* b, int64_t n, int f64,
+                      hipStream_t st);
+
 }  // namespace hmx

@@ -26,7 +26,7 @@ KERNELS = {"gaussian": HMX_GAUSSIAN, "matern32": HMX_MATERN32, "const": HMX_TEST
 DTYPES = {"f64": HMX_F64, "f32": HMX_F32, "bf16": HMX_BF16}
 
 # every symbol declared in include/hmx.h
-EXPORTS = ["hmx_params_default", "hmx_build", "hmx_matvec", "hmx_get_partition",
+EXPORTS = ["hmx_params_default", "hmx_build", "hmx_matvec", "hmx_cg_solve", "hmx_get_partition",
            "hmx_get_boxes", "hmx_get_ranks", "hmx_get_factors", "hmx_get_stats",
            "hmx_profile_begin", "hmx_profile_end", "hmx_destroy", "hmx_trim",
            "hmx_status_string", "hmx_last_error"]
@@ -87,6 +87,8 @@ def lib():
         L.hmx_build.argtypes = [P, C.c_int, i64, i32, C.POINTER(hmx_kernel),
                                 C.POINTER(hmx_params), P, C.POINTER(P)]
         L.hmx_matvec.argtypes = [P, P, P, C.c_int, f64, f64, P]
+        L.hmx_cg_solve.argtypes = [P, P, P, f64, i32, P, C.POINTER(i32), C.POINTER(f64),
+                                   C.POINTER(f64)]
         L.hmx_get_partition.argtypes = [P, P, P, P, C.POINTER(i64), P, C.POINTER(i64), P]
         L.hmx_get_boxes.argtypes = [P, P, P, P]
         L.hmx_get_ranks.argtypes = [P, P, P]
@@ -164,6 +166,19 @@ def hmx_matvec(h, x, z, alpha=1.0, beta=0.0, stream=None):
         raise ValueError("x and z must be contiguous device tensors")
     _check(lib().hmx_matvec(h, C.c_void_p(x.data_ptr()), C.c_void_p(z.data_ptr()), _dtype_of(x),
                             float(alpha), float(beta), _stream(stream)))
+
+
+def hmx_cg_solve(h, b, x, rel_tol=1e-6, max_iter=1000, stream=None, raise_on_fail=True):
+    """Solve (H + sigma2 I) x = b by CG.  Returns (status, iters, rel_res, true_rel_res)."""
+    if not (b.is_cuda and x.is_cuda and b.is_contiguous() and x.is_contiguous()):
+        raise ValueError("b and x must be contiguous device tensors")
+    it, rr, tr = C.c_int32(0), C.c_double(0), C.c_double(0)
+    s = lib().hmx_cg_solve(h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                           float(rel_tol), int(max_iter), _stream(stream), C.byref(it),
+                           C.byref(rr), C.byref(tr))
+    if s not in (HMX_OK, HMX_ERR_NOT_CONVERGED) or (raise_on_fail and s != HMX_OK):
+        _check(s)
+    return s, it.value, rr.value, tr.value
 
 
 def hmx_get_stats(h) -> hmx_stats:

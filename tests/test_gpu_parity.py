@@ -337,3 +337,59 @@ def test_bf16_ragged_tiles(H, orc):
     print("bf16 ragged rel err %.3e" % err)
     assert err <= 1e-4 + 4 * 2.0 ** -9
     hm.close()
+
+
+def test_cg_krr_f64_against_dense(H, orc):
+    """Kernel ridge regression: CG on (H + sigma2 I) c = y with GMM points in
+    [0,1]^3, Matern-3/2 (l = 0.1), sigma2 = 1e-2.  With a fine H-matrix the
+    solution matches the oracle's dense CG within cond * (e_H + tol)."""
+    n = 3000
+    pts = synth.gmm_points(n, 3, 31, ncomp=16)
+    y = synth.krr_target(pts, 32)
+    hm = _build(H, pts, "matern32", 0.1, "f64", leaf_size=64, eta=1.5, aca_eps=1e-9,
+                max_rank=96, sigma2=1e-2)
+    c = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+    s, it, res, tres = H.hmx_cg_solve(hm.h, _dev(y), c, rel_tol=1e-9, max_iter=2000)
+    print("cg f64: iters %d rel res %.3e true %.3e" % (it, res, tres))
+    assert s == H.HMX_OK and res <= 1e-9 and tres <= 1e-7
+    c_ref, rc, it_ref, _ = orc.cg_dense(pts, y, "matern32", 0.1, 1e-2, tol=1e-12)
+    assert rc == 0
+    err = np.linalg.norm(c.cpu().numpy() - c_ref) / np.linalg.norm(c_ref)
+    print("cg f64: |c - c_dense| / |c_dense| = %.3e (dense CG %d iters)" % (err, it_ref))
+    assert err <= 1e-4
+    hm.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_cg_krr_mixed_precision(H, orc, storage):
+    """The same system with F32 arithmetic and F32 / BF16 storage, FP64 inner
+    products: the recurrence reaches the tolerance and the true residual of
+    the computed solution against the FP64 dense system is small."""
+    n = 3000
+    pts = synth.gmm_points(n, 3, 31, ncomp=16)
+    y = synth.krr_target(pts, 32)
+    hm = H.HMatrix(_dev(pts), "matern32", 0.1, compute_dtype="f32", storage_dtype=storage,
+                   leaf_size=64, eta=1.5, aca_eps=1e-5, max_rank=64, sigma2=1e-2)
+    c = torch.zeros(n, dtype=torch.float32, device="cuda:0")
+    s, it, res, tres = H.hmx_cg_solve(hm.h, _dev(y).float(), c, rel_tol=1e-5, max_iter=3000,
+                                      raise_on_fail=False)
+    cc = c.double().cpu().numpy()
+    r_dense = orc.dense_matvec(pts, cc, "matern32", 0.1, sigma2=1e-2) - y
+    dres = np.linalg.norm(r_dense) / np.linalg.norm(y)
+    print("cg %s: status %d iters %d rel res %.3e true %.3e dense-system residual %.3e" % (
+        storage, s, it, res, tres, dres))
+    assert s == H.HMX_OK and res <= 1e-5
+    assert dres <= (2e-3 if storage == "bf16" else 1e-4)
+    hm.close()
+
+
+def test_cg_edge_cases(H):
+    pts = synth.uniform_points(500, 2, 3)
+    hm = _build(H, pts, "gaussian", 0.05, "f64", leaf_size=32, sigma2=0.1)
+    y = _dev(synth.normal_vector(500, 4))
+    c = torch.zeros(500, dtype=torch.float64, device="cuda:0")
+    s, it, res, _ = H.hmx_cg_solve(hm.h, y, c, rel_tol=1e-12, max_iter=1, raise_on_fail=False)
+    assert s == H.HMX_ERR_NOT_CONVERGED and it == 1
+    s, it, res, tres = H.hmx_cg_solve(hm.h, torch.zeros_like(y), c, rel_tol=1e-8)
+    assert s == H.HMX_OK and it == 0 and not c.abs().max().item()
+    hm.close()

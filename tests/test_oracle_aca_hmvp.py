@@ -214,3 +214,23 @@ def test_aca_stops_at_first_rank_meeting_the_criterion(orc):
             assert (lhs <= rhs) == (l == r), (q, l, r, lhs, rhs)
         checked += 1
     assert checked >= 5
+
+
+def test_cg_dense_matches_cholesky(orc):
+    """The oracle's CG on (A + sigma2 I) c = y (kernel ridge regression) agrees
+    with a dense Cholesky solve; it stops at the requested recurrence residual
+    and its true residual is of the same size."""
+    from scipy.linalg import cho_factor, cho_solve
+    pts = synth.gmm_points(600, 3, 31, ncomp=8)
+    y = synth.krr_target(pts, 32)
+    A = _dense(pts, "matern32", 0.1) + 1e-2 * np.eye(600)
+    c_ref = cho_solve(cho_factor(A), y)
+    c, rc, it, res = orc.cg_dense(pts, y, "matern32", 0.1, 1e-2, tol=1e-10)
+    assert rc == 0 and res <= 1e-10 and it < 600
+    assert np.linalg.norm(c - c_ref) <= 1e-6 * np.linalg.norm(c_ref)
+    assert np.linalg.norm(A @ c - y) <= 1e-9 * np.linalg.norm(y)
+    # max_iter = 1: not converged, one iteration; b = 0: converged at once
+    _, rc1, it1, _ = orc.cg_dense(pts, y, "matern32", 0.1, 1e-2, tol=1e-10, max_iter=1)
+    assert rc1 == 1 and it1 == 1
+    x0, rc0, it0, _ = orc.cg_dense(pts, np.zeros(600), "matern32", 0.1, 1e-2)
+    assert rc0 == 0 and it0 == 0 and not x0.any()
