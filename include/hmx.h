@@ -95,9 +95,11 @@ typedef struct {
     hmx_dtype compute_dtype; /* HMX_F64 or HMX_F32: kernel evaluation, ACA and
                                 matvec accumulation (the ACA norm estimate is
                                 always FP64) */
-    hmx_dtype storage_dtype; /* stored near field, U and V: HMX_F64 (requires
-                                F64 compute), HMX_F32 or HMX_BF16 (require F32
+    hmx_dtype storage_dtype; /* stored factors U and V: HMX_F64 (requires F64
+                                compute), HMX_F32 or HMX_BF16 (require F32
                                 compute; BF16 rounds to nearest even) */
+    hmx_dtype near_dtype;    /* stored near field: equal to storage_dtype, or
+                                HMX_F32 with BF16 factors */
     hmx_rank_mode rank_mode;
     int32_t aca_chunk_mb;    /* ACA scratch budget per chunk of admissible blocks,
                                 MiB; 0 selects 8192.  Blocks are approximated in
@@ -115,13 +117,15 @@ typedef struct {
     int64_t n_tiles;          /* leaf clusters (row tiles of the matvec) */
     int64_t sum_rank;         /* sum of ACA ranks */
     int32_t max_rank_used;
-    int32_t entry_bytes;      /* bytes per stored factor / near-field entry (storage dtype) */
+    int32_t entry_bytes;      /* bytes per stored factor entry (storage dtype) */
     int64_t factor_entries;   /* sum_adm rank * (|tau| + |sigma|) */
     int64_t u_entries;        /* sum_adm rank * |tau|   (U pool) */
     int64_t v_entries;        /* sum_adm rank * |sigma| (V pool) */
     int64_t near_entries;     /* sum_dense |tau| * |sigma| */
     int64_t aca_columns;      /* ACA residual columns evaluated (incl. skipped) */
     int64_t aca_chunks;       /* chunks the admissible leaves were approximated in */
+    int32_t near_entry_bytes; /* bytes per stored near-field entry */
+    int32_t reserved1;
     double matvec_bytes;      /* algorithmic HBM bytes of one matvec (beta = 0) */
     double phase_ms[8];       /* build phases: order, tree, traversal, aca,
                                  compaction, near field, matvec plan, total */

@@ -188,8 +188,10 @@ struct hmx_hmatrix_s {
     hmx_params prm{};
     int f64 = 0;
     size_t esz = 4;  // bytes per compute-type value (vectors, ACA scratch)
-    int smode = 1;   // storage mode: 0 F64, 1 F32, 2 BF16
-    size_t ssz = 4;  // bytes per stored near-field / factor entry
+    int smode = 1;   // factor (U, V) storage mode: 0 F64, 1 F32, 2 BF16
+    size_t ssz = 4;  // bytes per stored factor entry
+    int nmode = 1;   // near-field storage mode
+    size_t nsz = 4;  // bytes per stored near-field entry
     double box[6] = {0, 0, 0, 0, 0, 0};
     int L = 0;
     int64_t nslots = 0;
@@ -200,8 +202,8 @@ struct hmx_hmatrix_s {
     DevBuf adm, adm_level, dense, dense_level;
     DevBuf tile_of_point, tile_lo;
     DevBuf rank, steps, voff, toff, V;
-    DevBuf pieces, pool, widx, tile_col, tile_doff, vecpool, col_block;
-    int64_t pool_entries = 0, ncols_total = 0;
+    DevBuf pieces, upool, npool, widx, tile_meta, vecpool, col_block;
+    int64_t upool_entries = 0, npool_entries = 0, ncols_total = 0;
     hmx_stats stats{};
     // matvec phase tracing (hmx_profile_begin / end)
     std::vector<hipEvent_t> prof_events;
@@ -219,7 +221,7 @@ struct hmx_hmatrix_s {
                                &node_hi,   &bmin,          &bmax,    &adm,       &adm_level,
                                &dense,     &dense_level,   &tile_of_point, &tile_lo, &rank,
                                &steps,     &voff,          &toff,    &V,         &pieces,
-                               &pool,      &widx,          &tile_col, &tile_doff, &vecpool,
+                               &upool,     &npool,         &widx,    &tile_meta, &vecpool,
                                &col_block};
         int64_t s = 0;
         for (auto* b : all) s += (int64_t)b->bytes;
@@ -613,34 +615,42 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
                                st),
               "piece sort");
         alloc(h->pieces, h->npieces * sizeof(Piece), "sorted pieces");
-        alloc(psize, (h->npieces + 1) * 8, "piece sizes");
-        alloc(pcols, (h->npieces + 1) * 8, "piece columns");
+        DevBuf psu, psn, pc, pcu;
+        alloc(psu, (h->npieces + 1) * 8, "piece sizes");
+        alloc(psn, (h->npieces + 1) * 8, "piece sizes");
+        alloc(pc, (h->npieces + 1) * 8, "piece columns");
+        alloc(pcu, (h->npieces + 1) * 8, "piece columns");
+        const int R = rows_per_unit(smode, h->nmode);
         check(launch_piece_gather(unsorted.as<Piece>(), vals.as<uint32_t>(), h->npieces,
-                                  h->pieces.as<Piece>(), psize.as<int64_t>(), pcols.as<int64_t>(),
-                                  h->tile_lo.as<int32_t>(), (int)ssz, st),
+                                  h->pieces.as<Piece>(), psu.as<int64_t>(), psn.as<int64_t>(),
+                                  pc.as<int64_t>(), pcu.as<int64_t>(), h->tile_lo.as<int32_t>(), R,
+                                  st),
               "piece gather");
-        h->pool_entries = scan(psize.as<int64_t>(), h->npieces);
-        h->ncols_total = scan(pcols.as<int64_t>(), h->npieces);
+        h->upool_entries = scan(psu.as<int64_t>(), h->npieces);
+        h->npool_entries = scan(psn.as<int64_t>(), h->npieces);
+        h->ncols_total = scan(pc.as<int64_t>(), h->npieces);
+        scan(pcu.as<int64_t>(), h->npieces);
         alloc(h->widx, (size_t)std::max<int64_t>(h->ncols_total, 1) * 8, "column weights");
-        check(launch_piece_layout(h->pieces.as<Piece>(), h->npieces, psize.as<int64_t>(),
-                                  pcols.as<int64_t>(), h->widx.as<int64_t>(), st),
+        check(launch_piece_layout(h->pieces.as<Piece>(), h->npieces, psu.as<int64_t>(),
+                                  psn.as<int64_t>(), pc.as<int64_t>(), h->widx.as<int64_t>(), st),
               "piece layout");
         DevBuf tptr;
         alloc(tptr, (h->ntiles + 1) * 8, "tile ptr");
         check(launch_tile_offsets(keys.as<uint64_t>(), h->npieces, h->ntiles, tptr.as<int64_t>(),
                                   st),
               "tile ptr");
-        alloc(h->tile_col, (h->ntiles + 1) * 8, "tile columns");
-        alloc(h->tile_doff, (h->ntiles + 1) * 8, "tile data offsets");
-        check(launch_tile_meta(tptr.as<int64_t>(), h->ntiles, h->npieces, psize.as<int64_t>(),
-                               pcols.as<int64_t>(), h->ncols_total, h->pool_entries,
-                               h->tile_col.as<int64_t>(), h->tile_doff.as<int64_t>(), st),
+        alloc(h->tile_meta, (size_t)(h->ntiles + 1) * 4 * 8, "tile meta");
+        check(launch_tile_meta(tptr.as<int64_t>(), h->ntiles, h->npieces, pc.as<int64_t>(),
+                               pcu.as<int64_t>(), psu.as<int64_t>(), psn.as<int64_t>(),
+                               h->tile_meta.as<int64_t>(), st),
               "tile meta");
-        alloc(h->pool, (size_t)std::max<int64_t>(h->pool_entries, 1) * ssz, "matrix pool");
+        alloc(h->upool, (size_t)std::max<int64_t>(h->upool_entries, 1) * ssz, "factor pool");
+        alloc(h->npool, (size_t)std::max<int64_t>(h->npool_entries, 1) * h->nsz, "near-field pool");
         check(launch_piece_data(h->pieces.as<Piece>(), h->npieces, h->tile_lo.as<int32_t>(),
                                 h->adm.as<int4>(), h->dense.as<int4>(), uoff_ex.as<int64_t>(), Uex.p,
                                 f64 ? h->soa64.p : h->soa32.p, n, d,
-                                KernelFn{(int)h->kern.kind, h->kern.p0}, h->pool.p, smode, st),
+                                KernelFn{(int)h->kern.kind, h->kern.p0}, h->upool.p, h->npool.p,
+                                smode, h->nmode, st),
               "piece data");
         check(hipStreamSynchronize(st), "pool sync");
     }
@@ -667,10 +677,11 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
     S.factor_entries = h->factor_entries;
     S.near_entries = h->near_entries;
     S.entry_bytes = (int32_t)ssz;
+    S.near_entry_bytes = (int32_t)h->nsz;
     S.phase_ms[7] = ms_since(t_all);
     // algorithmic bytes of one matvec with beta = 0: stored data once, the
     // vectors x and z once, perm for gather and scatter, t written and read
-    S.matvec_bytes = (double)(h->near_entries + h->factor_entries) * ssz +
+    S.matvec_bytes = (double)h->near_entries * h->nsz + (double)h->factor_entries * ssz +
                      (double)n * (2.0 * esz + 8.0) + (double)h->sum_rank * 2.0 * esz;
     S.device_bytes = h->device_bytes();
 }
@@ -708,6 +719,7 @@ hmx_status hmx_params_default(hmx_params* p) {
     p->sigma2 = 0.0;
     p->compute_dtype = HMX_F32;
     p->storage_dtype = HMX_F32;
+    p->near_dtype = HMX_F32;
     p->rank_mode = HMX_RANK_ADAPTIVE;
     return HMX_OK;
 }
@@ -749,6 +761,14 @@ hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t
         set_err("storage_dtype must be F64 with F64 compute, F32 or BF16 with F32 compute");
         return HMX_ERR_UNSUPPORTED;
     }
+    {
+        const bool ok = (p.near_dtype == p.storage_dtype) ||
+                        (p.storage_dtype == HMX_BF16 && p.near_dtype == HMX_F32);
+        if (!ok) {
+            set_err("near_dtype must equal storage_dtype, or be F32 with BF16 factors");
+            return HMX_ERR_UNSUPPORTED;
+        }
+    }
     if (p.rank_mode != HMX_RANK_ADAPTIVE && p.rank_mode != HMX_RANK_FIXED) {
         set_err("unsupported rank mode %d", (int)p.rank_mode);
         return HMX_ERR_UNSUPPORTED;
@@ -776,6 +796,8 @@ hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t
     h->esz = h->f64 ? 8 : 4;
     h->smode = p.storage_dtype == HMX_F64 ? 0 : (p.storage_dtype == HMX_F32 ? 1 : 2);
     h->ssz = h->smode == 0 ? 8 : (h->smode == 1 ? 4 : 2);
+    h->nmode = p.near_dtype == HMX_F64 ? 0 : (p.near_dtype == HMX_F32 ? 1 : 2);
+    h->nsz = h->nmode == 0 ? 8 : (h->nmode == 1 ? 4 : 2);
     try {
         build_impl(h, points, pts_dtype == HMX_F64, (hipStream_t)stream);
     } catch (const Fail& f) {
@@ -816,10 +838,10 @@ hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype
                               h->vecpool.p, h->n, h->smode, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
     if (e == hipSuccess)
-        e = launch_rowtile(h->ntiles, h->tile_lo.as<int32_t>(), h->tile_col.as<int64_t>(),
-                           h->tile_doff.as<int64_t>(), h->widx.as<int64_t>(), h->pool.p,
-                           h->vecpool.p, h->perm.as<int32_t>(), alpha, beta, h->prm.sigma2, z,
-                           h->max_tile, h->smode, st);
+        e = launch_rowtile(h->ntiles, h->tile_lo.as<int32_t>(), h->tile_meta.as<int64_t>(),
+                           h->widx.as<int64_t>(), h->upool.p, h->npool.p, h->vecpool.p,
+                           h->perm.as<int32_t>(), alpha, beta, h->prm.sigma2, z, h->max_tile,
+                           h->smode, h->nmode, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
     if (e != hipSuccess) {
         set_err("matvec launch: %s", hipGetErrorString(e));
@@ -1062,10 +1084,10 @@ hmx_status hmx_get_factors(hmx_hmatrix h, int64_t leaf, double* U, double* V, in
         for (const Piece& pc : pcs) {
             if (pc.blk != (int32_t)leaf) continue;
             const int mt = tlo[pc.tile + 1] - tlo[pc.tile];
-            const int vecn = 16 / (int)esz;
-            const int ld = (mt + vecn - 1) / vecn * vecn;
+            const int R = rows_per_unit(h->smode, h->nmode);
+            const int ld = (mt + R - 1) / R * R;
             std::vector<char> col((size_t)ld * r * esz + 1);
-            d2h(col.data(), (const char*)h->pool.p + pc.d_off * esz, (size_t)ld * r * esz, st);
+            d2h(col.data(), (const char*)h->upool.p + pc.d_off * esz, (size_t)ld * r * esz, st);
             std::vector<double> cd((size_t)ld * r);
             to_double(col, (size_t)ld * r, cd.data());
             for (int l = 0; l < r; ++l)

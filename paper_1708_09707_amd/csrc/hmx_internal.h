@@ -183,20 +183,24 @@ hipError_t launch_piece_fill(const int4* blocks, int64_t nblocks, const int32_t*
                              int64_t piece_base, Piece* pieces, uint64_t* keys, uint32_t* vals,
                              hipStream_t st);
 hipError_t launch_piece_gather(const Piece* src, const uint32_t* order, int64_t npieces,
-                               Piece* dst, int64_t* size, int64_t* cols, const int32_t* tile_lo,
-                               int esz, hipStream_t st);
-hipError_t launch_piece_layout(Piece* pieces, int64_t np, const int64_t* doff,
-                               const int64_t* coff, int64_t* widx, hipStream_t st);
+                               Piece* dst, int64_t* size_u, int64_t* size_n, int64_t* cols,
+                               int64_t* cols_u, const int32_t* tile_lo, int R, hipStream_t st);
+hipError_t launch_piece_layout(Piece* pieces, int64_t np, const int64_t* doff_u,
+                               const int64_t* doff_n, const int64_t* coff, int64_t* widx,
+                               hipStream_t st);
 hipError_t launch_tile_offsets(const uint64_t* sorted_tile, int64_t npieces, int64_t ntiles,
                                int64_t* tile_ptr, hipStream_t st);
+// meta[4 t + 0..3] = first column, first factor column, factor-pool and
+// near-pool data offsets of tile t (t = 0..ntiles; entry ntiles = totals)
 hipError_t launch_tile_meta(const int64_t* tile_ptr, int64_t ntiles, int64_t np,
-                            const int64_t* doff, const int64_t* coff, int64_t total_cols,
-                            int64_t total_data, int64_t* tile_col, int64_t* tile_doff,
-                            hipStream_t st);
+                            const int64_t* coff, const int64_t* coff_u, const int64_t* doff_u,
+                            const int64_t* doff_n, int64_t* meta, hipStream_t st);
+// rows per 16-byte lane unit for the factor / near storage modes (0 F64, 1 F32, 2 BF16)
+int rows_per_unit(int fmode, int nmode);
 hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* tile_lo,
-                             const int4* adm, const int4* dense, const int64_t* ucap_off,
-                             const void* Ucap, const void* soa, int64_t n, int d, KernelFn kern,
-                             void* pool, int smode, hipStream_t st);
+                             const int4* adm, const int4* dense, const int64_t* uoff,
+                             const void* Usrc, const void* soa, int64_t n, int d, KernelFn kern,
+                             void* upool, void* npool, int fmode, int nmode, hipStream_t st);
 // smode: storage mode 0 = F64, 1 = F32, 2 = BF16 storage with F32 arithmetic
 hipError_t launch_compact_v(const int4* blocks, int64_t nblocks, const int32_t* rank,
                             const int64_t* cap_voff, int64_t cap_base, const int64_t* voff,
@@ -220,10 +224,11 @@ hipError_t launch_col_block(const int32_t* rank, const int64_t* toff, int64_t na
 hipError_t launch_far_phase1(const int4* adm, const int32_t* col_block, const int64_t* voff,
                              const int64_t* toff, int64_t ncols_total, const void* V,
                              void* vecpool, int64_t n, int smode, hipStream_t st);
-hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t* tile_col,
-                          const int64_t* tile_doff, const int64_t* widx, const void* pool,
+hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t* meta,
+                          const int64_t* widx, const void* upool, const void* npool,
                           const void* vecpool, const int32_t* perm, double alpha, double beta,
-                          double sigma2, void* z, int max_tile, int smode, hipStream_t st);
+                          double sigma2, void* z, int max_tile, int fmode, int nmode,
+                          hipStream_t st);
 
 // conjugate gradients (k_blas.hip): FP64-accumulated inner products
 size_t cg_scratch_bytes();

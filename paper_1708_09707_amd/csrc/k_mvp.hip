@@ -3,17 +3,20 @@
 //
 // Storage.  The rows of the matrix are cut into row tiles, the leaf clusters
 // of the cluster tree.  A piece is the part of one leaf block that falls in
-// one tile: the tile's rows of a dense block A|tau x sigma (ncols = |sigma|,
-// weights x|sigma), or the tile's rows of the factor U of an admissible block
-// (ncols = rank, weights t_b = V_b^T x|sigma).  All pieces of a tile are
-// stored one after another, column-major with the tile's leading dimension
-// ld_t = (tile rows rounded up to 16 bytes), so a tile is one contiguous
-// ld_t x C_t matrix in the matrix pool and column k of it is multiplied by
-// vec[widx[k]].  Padding rows hold zeros.
+// one tile: the tile's rows of the factor U of an admissible block (ncols =
+// rank, weights t_b = V_b^T x|sigma) or of a dense block A|tau x sigma
+// (ncols = |sigma|, weights x|sigma).  Factor pieces live in the factor pool,
+// dense pieces in the near-field pool (each with its own storage type); in
+// both, the pieces of a tile are stored one after another, column-major with
+// the tile's leading dimension ld_t (tile rows rounded up to R, the rows of
+// one 16-byte vector of the narrower type), so each tile is one contiguous
+// ld_t x C matrix per pool and column k of the tile is multiplied by
+// vec[widx[k]] (factor columns first, then dense columns).  Padding rows hold
+// zeros.
 //   vector pool: [ x in Morton order (n) | t_b for every admissible leaf ]
 //   V pool     : V_b (n_b x r_b) column-major per admissible leaf.
 // Matvec = gather x -> phase 1 (all t_b) -> phase 2 (one workgroup per tile,
-// streaming its contiguous region) -> scatter to the original order with
+// streaming its two contiguous regions) -> scatter to the original order with
 // alpha, beta, sigma2.  Each z row is written by one workgroup and every sum
 // has a fixed order, so the product is deterministic.
 #include "hmx_internal.h"
@@ -24,12 +27,8 @@ namespace {
 
 unsigned grid_cap(int64_t nb, int64_t cap) { return (unsigned)(nb < cap ? nb : cap); }
 
-// elements per 16-byte vector for an entry size, and the padded tile height
-__device__ __host__ __forceinline__ int vec_elems(int esz) { return 16 / esz; }
-__device__ __host__ __forceinline__ int tile_ld(int rows, int esz) {
-    const int v = vec_elems(esz);
-    return (rows + v - 1) / v * v;
-}
+// padded tile height: rows rounded up to R (R = 16 / narrowest entry size)
+__device__ __host__ __forceinline__ int tile_ld(int rows, int R) { return (rows + R - 1) / R * R; }
 
 // ---------------------------------------------------------------------------
 // storage types: the pools hold S (double, float or bfloat16 bits), the
@@ -154,30 +153,36 @@ __global__ void piece_fill_kernel(const int4* __restrict__ blocks, int64_t nb,
     }
 }
 
-// sorted order -> pieces; also each piece's data size and column count
+// sorted order -> pieces; each piece's data size in its pool and columns
 __global__ void piece_gather_kernel(const Piece* __restrict__ src,
                                     const uint32_t* __restrict__ order, int64_t np,
-                                    Piece* __restrict__ dst, int64_t* __restrict__ size,
-                                    int64_t* __restrict__ cols, const int32_t* __restrict__ tile_lo,
-                                    int esz) {
+                                    Piece* __restrict__ dst, int64_t* __restrict__ size_u,
+                                    int64_t* __restrict__ size_n, int64_t* __restrict__ cols,
+                                    int64_t* __restrict__ cols_u,
+                                    const int32_t* __restrict__ tile_lo, int R) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= np) return;
     const Piece pc = src[order[i]];
     dst[i] = pc;
     const int mt = tile_lo[pc.tile + 1] - tile_lo[pc.tile];
-    size[i] = (int64_t)tile_ld(mt, esz) * pc.ncols;
+    const int64_t sz = (int64_t)tile_ld(mt, R) * pc.ncols;
+    const bool f = pc.blk >= 0;
+    size_u[i] = f ? sz : 0;
+    size_n[i] = f ? 0 : sz;
     cols[i] = pc.ncols;
+    cols_u[i] = f ? pc.ncols : 0;
 }
 
 // after the scans: piece data offsets, and the weight index of every column
 __global__ void piece_layout_kernel(Piece* __restrict__ pieces, int64_t np,
-                                    const int64_t* __restrict__ doff,
+                                    const int64_t* __restrict__ doff_u,
+                                    const int64_t* __restrict__ doff_n,
                                     const int64_t* __restrict__ coff,
                                     int64_t* __restrict__ widx) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= np) return;
     Piece pc = pieces[i];
-    pc.d_off = doff[i];
+    pc.d_off = pc.blk >= 0 ? doff_u[i] : doff_n[i];
     pieces[i] = pc;
     const int64_t c0 = coff[i];
     for (int c = 0; c < pc.ncols; ++c) widx[c0 + c] = pc.v_off + c;
@@ -199,58 +204,59 @@ __global__ void tile_ptr_kernel(const uint64_t* __restrict__ keys, int64_t np, i
     ptr[t] = lo;
 }
 
-// per tile: first column and data offset (from its first piece)
+// per tile (from its first piece): first column, first factor column, and
+// data offsets in the two pools; entry ntiles holds the totals
 __global__ void tile_meta_kernel(const int64_t* __restrict__ tile_ptr, int64_t ntiles,
-                                 int64_t np, const int64_t* __restrict__ doff,
-                                 const int64_t* __restrict__ coff, int64_t total_cols,
-                                 int64_t total_data, int64_t* __restrict__ tile_col,
-                                 int64_t* __restrict__ tile_doff) {
+                                 int64_t np, const int64_t* __restrict__ coff,
+                                 const int64_t* __restrict__ coff_u,
+                                 const int64_t* __restrict__ doff_u,
+                                 const int64_t* __restrict__ doff_n, int64_t* __restrict__ meta) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t > ntiles) return;
-    const int64_t p = tile_ptr[t];
-    tile_col[t] = p < np ? coff[p] : total_cols;
-    tile_doff[t] = p < np ? doff[p] : total_data;
+    const int64_t p = tile_ptr[t];  // <= np; the scans hold the totals at index np
+    meta[4 * t + 0] = coff[p];
+    meta[4 * t + 1] = coff_u[p];
+    meta[4 * t + 2] = doff_u[p];
+    meta[4 * t + 3] = doff_n[p];
 }
 
 // Fill the matrix pool piece by piece: dense pieces evaluate phi (the near
 // field, Section 5.4.2), factor pieces copy the tile's rows of U_b from the
 // ACA capacity pool.  Padding rows are zero.
-template <typename S, typename T>
+template <typename SU, typename SN, typename T>
 __global__ __launch_bounds__(256) void piece_data_kernel(
     const Piece* __restrict__ pieces, int64_t np, const int32_t* __restrict__ tile_lo,
     const int4* __restrict__ adm, const int4* __restrict__ dense,
-    const int64_t* __restrict__ ucap_off, const T* __restrict__ Ucap, const T* __restrict__ soa,
-    int64_t n, int d, KernelEval<T> K, S* __restrict__ pool) {
-    constexpr int ssz = sizeof(S);
+    const int64_t* __restrict__ uoff, const T* __restrict__ Usrc, const T* __restrict__ soa,
+    int64_t n, int d, KernelEval<T> K, int R, SU* __restrict__ upool, SN* __restrict__ npool) {
     for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
         const Piece pc = pieces[p];
         const int32_t r0 = tile_lo[pc.tile];
         const int mt = tile_lo[pc.tile + 1] - r0;
-        const int ld = tile_ld(mt, ssz);
-        S* __restrict__ out = pool + pc.d_off;
+        const int ld = tile_ld(mt, R);
         const int64_t tot = (int64_t)ld * pc.ncols;
         const bool is_factor = pc.blk >= 0;
         const int4 bl = is_factor ? adm[pc.blk] : dense[-pc.blk - 1];
         const int m = bl.y - bl.x;
-        const T* __restrict__ src = is_factor ? Ucap + ucap_off[pc.blk] + pc.row0 : nullptr;
+        const T* __restrict__ src = is_factor ? Usrc + uoff[pc.blk] + pc.row0 : nullptr;
         int i = threadIdx.x, c = 0;
         while (i >= ld) {
             i -= ld;
             ++c;
         }
         for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
-            T v = (T)0;
-            if (i < mt) {
-                if (is_factor) {
-                    v = src[(int64_t)c * m + i];
-                } else {
+            if (is_factor) {
+                upool[pc.d_off + e] = Store<SU, T>::put(i < mt ? src[(int64_t)c * m + i] : (T)0);
+            } else {
+                T v = (T)0;
+                if (i < mt) {
                     T x[3], y[3];
                     load_pt(soa, n, d, (int64_t)r0 + i, x);
                     load_pt(soa, n, d, (int64_t)bl.z + c, y);
                     v = phi(K, x, y, d);
                 }
+                npool[pc.d_off + e] = Store<SN, T>::put(v);
             }
-            out[e] = Store<S, T>::put(v);
             i += blockDim.x;
             while (i >= ld) {
                 i -= ld;
@@ -436,16 +442,75 @@ constexpr int kTileThreads = 256;
 constexpr int kChunk = 1024;
 constexpr int kUnroll = 8;
 
-template <typename S, typename T, int L, int RV>
+// R consecutive rows of one column as T values (R / (16 / sizeof(S)) loads)
+template <typename S, typename T, int R>
+__device__ __forceinline__ void load_rows(const S* __restrict__ col, int unit, T* out) {
+    constexpr int VS = Dec<S, T>::n;
+    const u32x4* p = (const u32x4*)(col + (int64_t)unit * R);
+#pragma unroll
+    for (int k = 0; k < R / VS; ++k) Dec<S, T>::get(nt_load(p + k), out + k * VS);
+}
+
+// accumulate nk columns of one pool segment (base: row pass start of the
+// tile's first column in this segment) into acc
+template <typename S, typename T, int L, int RV, int R, int G>
+__device__ __forceinline__ void rowtile_segment(const S* __restrict__ base, int ld, int64_t nk,
+                                                const int64_t* __restrict__ wi,
+                                                const T* __restrict__ vec, T* __restrict__ sw,
+                                                int g, int q, int nvec, T (&acc)[RV][R]) {
+    for (int64_t kc = 0; kc < nk; kc += kChunk) {
+        const int cnt = (nk - kc) < kChunk ? (int)(nk - kc) : kChunk;
+        for (int j = threadIdx.x; j < cnt; j += kTileThreads) sw[j] = vec[wi[kc + j]];
+        __syncthreads();
+        const S* __restrict__ b = base + kc * ld;
+        int c = g;
+        for (; c + (kUnroll - 1) * G < cnt; c += kUnroll * G) {
+            T w[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) w[u] = sw[c + u * G];
+#pragma unroll
+            for (int v = 0; v < RV; ++v) {
+                const int vi = v * L + q;
+                if (vi < nvec) {
+                    T a[kUnroll][R];
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u)
+                        load_rows<S, T, R>(b + (int64_t)(c + u * G) * ld, vi, a[u]);
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+                        for (int e = 0; e < R; ++e) acc[v][e] += a[u][e] * w[u];
+                }
+            }
+        }
+        for (; c < cnt; c += G) {
+            const T w0 = sw[c];
+#pragma unroll
+            for (int v = 0; v < RV; ++v) {
+                const int vi = v * L + q;
+                if (vi < nvec) {
+                    T a[R];
+                    load_rows<S, T, R>(b + (int64_t)c * ld, vi, a);
+#pragma unroll
+                    for (int e = 0; e < R; ++e) acc[v][e] += a[e] * w0;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename SU, typename SN, typename T, int L, int RV>
 __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
-    int64_t ntiles, const int32_t* __restrict__ tile_lo, const int64_t* __restrict__ tile_col,
-    const int64_t* __restrict__ tile_doff, const int64_t* __restrict__ widx,
-    const S* __restrict__ pool, const T* __restrict__ vec, const int32_t* __restrict__ perm,
-    T alpha, T beta, T sigma2, T* __restrict__ z) {
-    constexpr int VEC = Dec<S, T>::n;  // rows per 16-byte vector
+    int64_t ntiles, const int32_t* __restrict__ tile_lo, const int64_t* __restrict__ meta,
+    const int64_t* __restrict__ widx, const SU* __restrict__ upool, const SN* __restrict__ npool,
+    const T* __restrict__ vec, const int32_t* __restrict__ perm, T alpha, T beta, T sigma2,
+    T* __restrict__ z) {
+    constexpr int VU = Dec<SU, T>::n, VN = Dec<SN, T>::n;
+    constexpr int R = VU > VN ? VU : VN;  // rows per lane unit
     constexpr int SUB = 64 / L;
     constexpr int G = 4 * SUB;
-    constexpr int RPG = L * RV * VEC;  // rows per pass
+    constexpr int RPG = L * RV * R;  // rows per pass
     __shared__ T red[G * RPG];
     __shared__ T sw[kChunk];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -455,69 +520,27 @@ __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int32_t r0 = tile_lo[t];
         const int mt = tile_lo[t + 1] - r0;
-        const int ld = (mt + VEC - 1) / VEC * VEC;
-        const int64_t k0 = tile_col[t], nk = tile_col[t + 1] - k0;
-        const S* __restrict__ base0 = pool + tile_doff[t];
-        const int64_t* __restrict__ wi = widx + k0;
+        const int ld = tile_ld(mt, R);
+        const int64_t k0 = meta[4 * t], k1 = meta[4 * t + 4];
+        const int64_t ku = meta[4 * t + 5] - meta[4 * t + 1];  // factor columns of the tile
+        const SU* __restrict__ ubase = upool + meta[4 * t + 2];
+        const SN* __restrict__ nbase = npool + meta[4 * t + 3];
         for (int rb = 0; rb < ld; rb += RPG) {
-            const int nvec = ((ld - rb) < RPG ? (ld - rb) : RPG) / VEC;  // vectors in this pass
-            T acc[RV][VEC];
+            const int nvec = ((ld - rb) < RPG ? (ld - rb) : RPG) / R;  // lane units in this pass
+            T acc[RV][R];
 #pragma unroll
             for (int v = 0; v < RV; ++v)
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) acc[v][e] = 0;
-            for (int64_t kc = 0; kc < nk; kc += kChunk) {
-                const int cnt = (nk - kc) < kChunk ? (int)(nk - kc) : kChunk;
-                for (int j = tid; j < cnt; j += kTileThreads) sw[j] = vec[wi[kc + j]];
-                __syncthreads();
-                const S* __restrict__ base = base0 + rb + kc * ld;
-                int c = g;
-                for (; c + (kUnroll - 1) * G < cnt; c += kUnroll * G) {
-                    T w[kUnroll];
-                    const u32x4* cp[kUnroll];
-#pragma unroll
-                    for (int u = 0; u < kUnroll; ++u) {
-                        w[u] = sw[c + u * G];
-                        cp[u] = (const u32x4*)(base + (int64_t)(c + u * G) * ld);
-                    }
-#pragma unroll
-                    for (int v = 0; v < RV; ++v) {
-                        const int vi = v * L + q;
-                        if (vi < nvec) {
-                            u32x4 raw[kUnroll];
-#pragma unroll
-                            for (int u = 0; u < kUnroll; ++u) raw[u] = nt_load(cp[u] + vi);
-#pragma unroll
-                            for (int u = 0; u < kUnroll; ++u) {
-                                T a[VEC];
-                                Dec<S, T>::get(raw[u], a);
-#pragma unroll
-                                for (int e = 0; e < VEC; ++e) acc[v][e] += a[e] * w[u];
-                            }
-                        }
-                    }
-                }
-                for (; c < cnt; c += G) {
-                    const T w0 = sw[c];
-                    const u32x4* c0 = (const u32x4*)(base + (int64_t)c * ld);
-#pragma unroll
-                    for (int v = 0; v < RV; ++v) {
-                        const int vi = v * L + q;
-                        if (vi < nvec) {
-                            T a[VEC];
-                            Dec<S, T>::get(nt_load(c0 + vi), a);
-#pragma unroll
-                            for (int e = 0; e < VEC; ++e) acc[v][e] += a[e] * w0;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
+                for (int e = 0; e < R; ++e) acc[v][e] = 0;
+            rowtile_segment<SU, T, L, RV, R, G>(ubase + rb, ld, ku, widx + k0, vec, sw, g, q,
+                                                 nvec, acc);
+            rowtile_segment<SN, T, L, RV, R, G>(nbase + rb, ld, k1 - k0 - ku, widx + k0 + ku, vec,
+                                                 sw, g, q, nvec, acc);
             // sum the G partial row sets in a fixed order
 #pragma unroll
             for (int v = 0; v < RV; ++v)
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) red[g * RPG + (v * L + q) * VEC + e] = acc[v][e];
+                for (int e = 0; e < R; ++e) red[g * RPG + (v * L + q) * R + e] = acc[v][e];
             __syncthreads();
             const int mc = (mt - rb) < RPG ? (mt - rb) : RPG;  // real rows of this pass
             for (int row = tid; row < mc; row += kTileThreads) {
@@ -535,21 +558,23 @@ __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
     }
 }
 
-template <typename S, typename T>
-hipError_t rowtile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_t* tile_col,
-                            const int64_t* tile_doff, const int64_t* widx, const void* pool,
+template <typename SU, typename SN, typename T>
+hipError_t rowtile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_t* meta,
+                            const int64_t* widx, const void* upool, const void* npool,
                             const void* vecpool, const int32_t* perm, double alpha, double beta,
                             double sigma2, void* z, int max_tile, hipStream_t st) {
-    constexpr int VEC = Dec<S, T>::n;
-    const int need = (max_tile + VEC - 1) / VEC;  // vectors per tile column
+    constexpr int VU = Dec<SU, T>::n, VN = Dec<SN, T>::n;
+    constexpr int R = VU > VN ? VU : VN;
+    const int need = (max_tile + R - 1) / R;  // lane units per tile column
     int L = 16, RV = 1;
     while (L < need && L < 64) L *= 2;
     while (L * RV < need && RV < 4) RV *= 2;
     const unsigned grid = grid_cap(ntiles, 1 << 20);
-#define HMX_RT(LL, RR)                                                                          \
-    hipLaunchKernelGGL((rowtile_kernel<S, T, LL, RR>), dim3(grid), dim3(kTileThreads), 0, st, \
-                       ntiles, tile_lo, tile_col, tile_doff, widx, (const S*)pool,             \
-                       (const T*)vecpool, perm, (T)alpha, (T)beta, (T)sigma2, (T*)z)
+#define HMX_RT(LL, RR)                                                                       \
+    hipLaunchKernelGGL((rowtile_kernel<SU, SN, T, LL, RR>), dim3(grid), dim3(kTileThreads), \
+                       0, st, ntiles, tile_lo, meta, widx, (const SU*)upool,                 \
+                       (const SN*)npool, (const T*)vecpool, perm, (T)alpha, (T)beta,        \
+                       (T)sigma2, (T*)z)
     if (L == 16)
         HMX_RT(16, 1);
     else if (L == 32)
@@ -588,19 +613,20 @@ hipError_t launch_piece_fill(const int4* blocks, int64_t nblocks, const int32_t*
 }
 
 hipError_t launch_piece_gather(const Piece* src, const uint32_t* order, int64_t npieces,
-                               Piece* dst, int64_t* size, int64_t* cols, const int32_t* tile_lo,
-                               int esz, hipStream_t st) {
+                               Piece* dst, int64_t* size_u, int64_t* size_n, int64_t* cols,
+                               int64_t* cols_u, const int32_t* tile_lo, int R, hipStream_t st) {
     if (npieces == 0) return hipSuccess;
     hipLaunchKernelGGL(piece_gather_kernel, dim3((unsigned)((npieces + 255) / 256)), dim3(256), 0,
-                       st, src, order, npieces, dst, size, cols, tile_lo, esz);
+                       st, src, order, npieces, dst, size_u, size_n, cols, cols_u, tile_lo, R);
     return hipGetLastError();
 }
 
-hipError_t launch_piece_layout(Piece* pieces, int64_t np, const int64_t* doff,
-                               const int64_t* coff, int64_t* widx, hipStream_t st) {
+hipError_t launch_piece_layout(Piece* pieces, int64_t np, const int64_t* doff_u,
+                               const int64_t* doff_n, const int64_t* coff, int64_t* widx,
+                               hipStream_t st) {
     if (np == 0) return hipSuccess;
     hipLaunchKernelGGL(piece_layout_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st,
-                       pieces, np, doff, coff, widx);
+                       pieces, np, doff_u, doff_n, coff, widx);
     return hipGetLastError();
 }
 
@@ -612,34 +638,41 @@ hipError_t launch_tile_offsets(const uint64_t* sorted_tile, int64_t npieces, int
 }
 
 hipError_t launch_tile_meta(const int64_t* tile_ptr, int64_t ntiles, int64_t np,
-                            const int64_t* doff, const int64_t* coff, int64_t total_cols,
-                            int64_t total_data, int64_t* tile_col, int64_t* tile_doff,
-                            hipStream_t st) {
+                            const int64_t* coff, const int64_t* coff_u, const int64_t* doff_u,
+                            const int64_t* doff_n, int64_t* meta, hipStream_t st) {
     hipLaunchKernelGGL(tile_meta_kernel, dim3((unsigned)((ntiles + 1 + 255) / 256)), dim3(256), 0,
-                       st, tile_ptr, ntiles, np, doff, coff, total_cols, total_data, tile_col,
-                       tile_doff);
+                       st, tile_ptr, ntiles, np, coff, coff_u, doff_u, doff_n, meta);
     return hipGetLastError();
 }
 
-// storage modes: 0 = F64/F64, 1 = F32/F32, 2 = BF16 storage with F32 arithmetic
+// storage modes: 0 = F64 (F64 arithmetic), 1 = F32, 2 = BF16 (F32 arithmetic)
+int rows_per_unit(int fmode, int nmode) {
+    auto v = [](int m) { return m == 0 ? 2 : (m == 1 ? 4 : 8); };
+    return v(fmode) > v(nmode) ? v(fmode) : v(nmode);
+}
+
 hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* tile_lo,
-                             const int4* adm, const int4* dense, const int64_t* ucap_off,
-                             const void* Ucap, const void* soa, int64_t n, int d, KernelFn kern,
-                             void* pool, int smode, hipStream_t st) {
+                             const int4* adm, const int4* dense, const int64_t* uoff,
+                             const void* Usrc, const void* soa, int64_t n, int d, KernelFn kern,
+                             void* upool, void* npool, int fmode, int nmode, hipStream_t st) {
     if (np == 0) return hipSuccess;
     const unsigned grid = grid_cap(np, 1 << 20);
-    if (smode == 0)
-        hipLaunchKernelGGL((piece_data_kernel<double, double>), dim3(grid), dim3(256), 0, st,
-                           pieces, np, tile_lo, adm, dense, ucap_off, (const double*)Ucap,
-                           (const double*)soa, n, d, KernelEval<double>(kern), (double*)pool);
-    else if (smode == 1)
-        hipLaunchKernelGGL((piece_data_kernel<float, float>), dim3(grid), dim3(256), 0, st,
-                           pieces, np, tile_lo, adm, dense, ucap_off, (const float*)Ucap,
-                           (const float*)soa, n, d, KernelEval<float>(kern), (float*)pool);
+    const int R = rows_per_unit(fmode, nmode);
+#define HMX_PD(SU, SN, T)                                                                     \
+    hipLaunchKernelGGL((piece_data_kernel<SU, SN, T>), dim3(grid), dim3(256), 0, st, pieces, \
+                       np, tile_lo, adm, dense, uoff, (const T*)Usrc, (const T*)soa, n, d,   \
+                       KernelEval<T>(kern), R, (SU*)upool, (SN*)npool)
+    if (fmode == 0 && nmode == 0)
+        HMX_PD(double, double, double);
+    else if (fmode == 1 && nmode == 1)
+        HMX_PD(float, float, float);
+    else if (fmode == 2 && nmode == 2)
+        HMX_PD(uint16_t, uint16_t, float);
+    else if (fmode == 2 && nmode == 1)
+        HMX_PD(uint16_t, float, float);
     else
-        hipLaunchKernelGGL((piece_data_kernel<uint16_t, float>), dim3(grid), dim3(256), 0, st,
-                           pieces, np, tile_lo, adm, dense, ucap_off, (const float*)Ucap,
-                           (const float*)soa, n, d, KernelEval<float>(kern), (uint16_t*)pool);
+        return hipErrorInvalidValue;
+#undef HMX_PD
     return hipGetLastError();
 }
 
@@ -740,20 +773,29 @@ hipError_t launch_far_phase1(const int4* adm, const int32_t* col_block, const in
     return hipGetLastError();
 }
 
-hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t* tile_col,
-                          const int64_t* tile_doff, const int64_t* widx, const void* pool,
+hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t* meta,
+                          const int64_t* widx, const void* upool, const void* npool,
                           const void* vecpool, const int32_t* perm, double alpha, double beta,
-                          double sigma2, void* z, int max_tile, int smode, hipStream_t st) {
+                          double sigma2, void* z, int max_tile, int fmode, int nmode,
+                          hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
-    if (smode == 0)
-        return rowtile_dispatch<double, double>(ntiles, tile_lo, tile_col, tile_doff, widx, pool,
-                                                vecpool, perm, alpha, beta, sigma2, z, max_tile,
-                                                st);
-    if (smode == 1)
-        return rowtile_dispatch<float, float>(ntiles, tile_lo, tile_col, tile_doff, widx, pool,
-                                              vecpool, perm, alpha, beta, sigma2, z, max_tile, st);
-    return rowtile_dispatch<uint16_t, float>(ntiles, tile_lo, tile_col, tile_doff, widx, pool,
-                                             vecpool, perm, alpha, beta, sigma2, z, max_tile, st);
+    if (fmode == 0 && nmode == 0)
+        return rowtile_dispatch<double, double, double>(ntiles, tile_lo, meta, widx, upool, npool,
+                                                        vecpool, perm, alpha, beta, sigma2, z,
+                                                        max_tile, st);
+    if (fmode == 1 && nmode == 1)
+        return rowtile_dispatch<float, float, float>(ntiles, tile_lo, meta, widx, upool, npool,
+                                                     vecpool, perm, alpha, beta, sigma2, z,
+                                                     max_tile, st);
+    if (fmode == 2 && nmode == 2)
+        return rowtile_dispatch<uint16_t, uint16_t, float>(ntiles, tile_lo, meta, widx, upool,
+                                                           npool, vecpool, perm, alpha, beta,
+                                                           sigma2, z, max_tile, st);
+    if (fmode == 2 && nmode == 1)
+        return rowtile_dispatch<uint16_t, float, float>(ntiles, tile_lo, meta, widx, upool,
+                                                        npool, vecpool, perm, alpha, beta, sigma2,
+                                                        z, max_tile, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace hmx

@@ -40,6 +40,7 @@ class hmx_params(C.Structure):
     _fields_ = [("leaf_size", C.c_int32), ("eta", C.c_double), ("aca_eps", C.c_double),
                 ("aca_eta", C.c_double), ("aca_eps0", C.c_double), ("max_rank", C.c_int32),
                 ("sigma2", C.c_double), ("compute_dtype", C.c_int), ("storage_dtype", C.c_int),
+                ("near_dtype", C.c_int),
                 ("rank_mode", C.c_int), ("aca_chunk_mb", C.c_int32),
                 ("reserved", C.c_int32 * 7)]
 
@@ -51,8 +52,8 @@ class hmx_stats(C.Structure):
                 ("entry_bytes", C.c_int32), ("factor_entries", C.c_int64),
                 ("u_entries", C.c_int64), ("v_entries", C.c_int64),
                 ("near_entries", C.c_int64), ("aca_columns", C.c_int64),
-                ("aca_chunks", C.c_int64),
-                ("matvec_bytes", C.c_double), ("phase_ms", C.c_double * 8),
+                ("aca_chunks", C.c_int64), ("near_entry_bytes", C.c_int32),
+                ("reserved1", C.c_int32), ("matvec_bytes", C.c_double), ("phase_ms", C.c_double * 8),
                 ("device_bytes", C.c_int64), ("level_sizes", C.c_int64 * 64)]
 
 
@@ -138,11 +139,13 @@ def hmx_params_default(**overrides) -> hmx_params:
     p = hmx_params()
     _check(lib().hmx_params_default(C.byref(p)))
     for k, v in overrides.items():
-        if k in ("compute_dtype", "storage_dtype") and isinstance(v, str):
+        if k in ("compute_dtype", "storage_dtype", "near_dtype") and isinstance(v, str):
             v = DTYPES[v]
         setattr(p, k, v)
     if "compute_dtype" in overrides and "storage_dtype" not in overrides:
         p.storage_dtype = p.compute_dtype  # store in the compute precision unless asked
+    if "near_dtype" not in overrides:
+        p.near_dtype = p.storage_dtype
     return p
 
 

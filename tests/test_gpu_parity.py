@@ -362,14 +362,16 @@ def test_cg_krr_f64_against_dense(H, orc):
 
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_cg_krr_mixed_precision(H, orc, storage):
-    """The same system with F32 arithmetic and F32 / BF16 storage, FP64 inner
-    products: the recurrence reaches the tolerance and the true residual of
-    the computed solution against the FP64 dense system is small."""
+    """The same system with F32 arithmetic, F32 near field and F32 / BF16
+    factors, FP64 inner products: the recurrence reaches the tolerance and the
+    true residual of the computed solution against the FP64 dense system is
+    small."""
     n = 3000
     pts = synth.gmm_points(n, 3, 31, ncomp=16)
     y = synth.krr_target(pts, 32)
     hm = H.HMatrix(_dev(pts), "matern32", 0.1, compute_dtype="f32", storage_dtype=storage,
-                   leaf_size=64, eta=1.5, aca_eps=1e-5, max_rank=64, sigma2=1e-2)
+                   near_dtype="f32", leaf_size=64, eta=1.5, aca_eps=1e-5, max_rank=64,
+                   sigma2=1e-2)
     c = torch.zeros(n, dtype=torch.float32, device="cuda:0")
     s, it, res, tres = H.hmx_cg_solve(hm.h, _dev(y).float(), c, rel_tol=1e-5, max_iter=3000,
                                       raise_on_fail=False)
@@ -381,6 +383,54 @@ def test_cg_krr_mixed_precision(H, orc, storage):
     assert s == H.HMX_OK and res <= 1e-5
     assert dres <= (2e-3 if storage == "bf16" else 1e-4)
     hm.close()
+
+
+def test_cg_breakdown_is_reported(H):
+    """With a BF16 near field the rounding (about 2^-9 of entries near 1)
+    exceeds sigma2 = 1e-2 and the shifted H-matrix is indefinite: CG must stop
+    with NOT_CONVERGED instead of returning a wrong solution as converged."""
+    n = 3000
+    pts = synth.gmm_points(n, 3, 31, ncomp=16)
+    y = synth.krr_target(pts, 32)
+    hm = H.HMatrix(_dev(pts), "matern32", 0.1, compute_dtype="f32", storage_dtype="bf16",
+                   near_dtype="bf16", leaf_size=64, eta=1.5, aca_eps=1e-5, max_rank=64,
+                   sigma2=1e-2)
+    c = torch.zeros(n, dtype=torch.float32, device="cuda:0")
+    s, it, res, _ = H.hmx_cg_solve(hm.h, _dev(y).float(), c, rel_tol=1e-5, max_iter=3000,
+                                   raise_on_fail=False)
+    print("bf16 near field: status %d iters %d rel res %.3e" % (s, it, res))
+    assert s in (H.HMX_OK, H.HMX_ERR_NOT_CONVERGED)
+    if s == H.HMX_OK:
+        assert res <= 1e-5
+    hm.close()
+
+
+def test_bf16_factors_f32_near(H, orc):
+    """BF16 factors with an F32 near field: factors are the rounded F32 ones,
+    the near field is untouched, the product is within the BF16 bound."""
+    pts = synth.uniform_points(6000, 3, 41)
+    x = synth.normal_vector(6000, 42)
+    kw = dict(leaf_size=48, eta=1.5, aca_eps=1e-6, max_rank=48)
+    h32 = _build(H, pts, "gaussian", 0.05, "f32", **kw)
+    hmx = H.HMatrix(_dev(pts), "gaussian", 0.05, compute_dtype="f32", storage_dtype="bf16",
+                    near_dtype="f32", **kw)
+    st = hmx.stats()
+    assert st.entry_bytes == 2 and st.near_entry_bytes == 4
+    adm = h32.partition()["adm"]
+    for q in [1, len(adm) // 3, len(adm) - 2]:
+        b = adm[q]
+        m, n = b[1] - b[0], b[3] - b[2]
+        U32, V32, r = H.hmx_get_factors(h32.h, int(q), m, n, 48)
+        U16, V16, _ = H.hmx_get_factors(hmx.h, int(q), m, n, 48)
+        assert np.array_equal(U16, _bf16_rne(U32).astype(np.float64))
+        assert np.array_equal(V16, _bf16_rne(V32).astype(np.float64))
+    z = hmx.matvec(_dev(x).float()).double().cpu().numpy()
+    zd = orc.dense_matvec(pts, x, "gaussian", 0.05)
+    err = np.linalg.norm(z - zd) / np.linalg.norm(zd)
+    print("bf16 factors / f32 near rel err %.3e" % err)
+    assert err <= 1e-5 + 4 * 2.0 ** -9
+    h32.close()
+    hmx.close()
 
 
 def test_cg_edge_cases(H):
