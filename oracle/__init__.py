@@ -66,6 +66,11 @@ def lib():
         L.hmxo_hmvp_rows.argtypes = [P, i64, i32, i32, f64, i32, f64, i32, f64, f64, f64, i32,
                                      i64, i64, P, P, P, P]
         L.hmxo_cg_dense.argtypes = [P, i64, i32, i32, f64, f64, P, P, f64, i32, P, P]
+        L.hmxo_mlp_nparams.restype = C.c_int
+        L.hmxo_mlp_forward.argtypes = [P, P, i64, P]
+        L.hmxo_mlp_loss_grad.argtypes = [P, P, P, i64, f64, P, P]
+        L.hmxo_mlp_adam.argtypes = [P, P, P, P, i64, i64, f64, f64, f64, f64]
+        L.hmxo_features.argtypes = [P, P, P, P, i32, i64, i64, f64, P]
         L.hmxo_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -280,3 +285,37 @@ def cg_dense(pts, b, kind, p0, sigma2, tol=1e-10, max_iter=10000):
     rc = lib().hmxo_cg_dense(_p(pts), n, d, kind_of(kind), float(p0), float(sigma2), _p(b),
                              _p(x), float(tol), int(max_iter), C.byref(it), C.byref(res))
     return x, rc, it.value, res.value
+
+
+def mlp_nparams():
+    return lib().hmxo_mlp_nparams()
+
+
+def mlp_forward(w, X):
+    w, X = _f64(w), _f64(X)
+    out = np.empty(X.shape[0])
+    lib().hmxo_mlp_forward(_p(w), _p(X), X.shape[0], _p(out))
+    return out
+
+
+def mlp_loss_grad(w, X, y, q=0.9):
+    w, X, y = _f64(w), _f64(X), _f64(y)
+    g = np.empty(w.shape[0])
+    loss = C.c_double(0)
+    lib().hmxo_mlp_loss_grad(_p(w), _p(X), _p(y), X.shape[0], float(q), C.byref(loss), _p(g))
+    return loss.value, g
+
+
+def mlp_adam(w, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In place on float64 arrays w, m, v."""
+    g = _f64(g)
+    lib().hmxo_mlp_adam(_p(w), _p(m), _p(v), _p(g), w.shape[0], int(t), float(lr), float(b1),
+                        float(b2), float(eps))
+
+
+def features(ta, tb, sa, sb, m, n, ell):
+    ta, tb, sa, sb = map(_f64, (ta, tb, sa, sb))
+    f = np.empty(8)
+    lib().hmxo_features(_p(ta), _p(tb), _p(sa), _p(sb), ta.shape[0], int(m), int(n), float(ell),
+                        _p(f))
+    return f

@@ -911,3 +911,161 @@ int hmxo_cg_dense(const double* pts, int64_t n, int32_t d, int32_t kind, double 
     free(q);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Rank predictor: an MLP 8 -> 64 -> 64 -> 64 -> 1 with ReLU, trained on     */
+/* (block features, ACA rank) pairs with the pinball (quantile) loss and    */
+/* Adam.  Parameters are packed as W1 (64x8, row-major), b1, W2 (64x64),    */
+/* b2, W3 (64x64), b3, W4 (1x64), b4.                                       */
+/* ------------------------------------------------------------------------ */
+#define MLP_IN 8
+#define MLP_H 64
+#define MLP_NPARAM (MLP_H * MLP_IN + MLP_H + 2 * (MLP_H * MLP_H + MLP_H) + MLP_H + 1)
+
+int hmxo_mlp_nparams(void) { return MLP_NPARAM; }
+
+typedef struct {
+    const double *W1, *b1, *W2, *b2, *W3, *b3, *W4, *b4;
+} mlp_view;
+
+static mlp_view mlp_unpack(const double* w)
+{
+    mlp_view v;
+    v.W1 = w;
+    v.b1 = v.W1 + MLP_H * MLP_IN;
+    v.W2 = v.b1 + MLP_H;
+    v.b2 = v.W2 + MLP_H * MLP_H;
+    v.W3 = v.b2 + MLP_H;
+    v.b3 = v.W3 + MLP_H * MLP_H;
+    v.W4 = v.b3 + MLP_H;
+    v.b4 = v.W4 + MLP_H;
+    return v;
+}
+
+/* one sample: pre-activations z1..z3, activations a1..a3 (64 each), output */
+static double mlp_sample(const mlp_view* p, const double* x, double* z1, double* a1, double* z2,
+                         double* a2, double* z3, double* a3)
+{
+    for (int i = 0; i < MLP_H; ++i) {
+        double s = p->b1[i];
+        for (int k = 0; k < MLP_IN; ++k) s += p->W1[i * MLP_IN + k] * x[k];
+        z1[i] = s;
+        a1[i] = s > 0.0 ? s : 0.0;
+    }
+    for (int i = 0; i < MLP_H; ++i) {
+        double s = p->b2[i];
+        for (int k = 0; k < MLP_H; ++k) s += p->W2[i * MLP_H + k] * a1[k];
+        z2[i] = s;
+        a2[i] = s > 0.0 ? s : 0.0;
+    }
+    for (int i = 0; i < MLP_H; ++i) {
+        double s = p->b3[i];
+        for (int k = 0; k < MLP_H; ++k) s += p->W3[i * MLP_H + k] * a2[k];
+        z3[i] = s;
+        a3[i] = s > 0.0 ? s : 0.0;
+    }
+    double o = p->b4[0];
+    for (int k = 0; k < MLP_H; ++k) o += p->W4[k] * a3[k];
+    return o;
+}
+
+int hmxo_mlp_forward(const double* w, const double* X, int64_t B, double* out)
+{
+    mlp_view p = mlp_unpack(w);
+    double z1[MLP_H], a1[MLP_H], z2[MLP_H], a2[MLP_H], z3[MLP_H], a3[MLP_H];
+    for (int64_t b = 0; b < B; ++b) out[b] = mlp_sample(&p, X + b * MLP_IN, z1, a1, z2, a2, z3, a3);
+    return 0;
+}
+
+/* pinball loss rho_q(u) = u (q - [u < 0]) with u = y - prediction, averaged
+ * over the batch; grad (packed like the parameters) by back-propagation.
+ * At u = 0 the subgradient q is used. */
+int hmxo_mlp_loss_grad(const double* w, const double* X, const double* y, int64_t B, double q,
+                       double* loss, double* grad)
+{
+    mlp_view p = mlp_unpack(w);
+    memset(grad, 0, sizeof(double) * MLP_NPARAM);
+    double *gW1 = grad, *gb1 = gW1 + MLP_H * MLP_IN, *gW2 = gb1 + MLP_H, *gb2 = gW2 + MLP_H * MLP_H;
+    double *gW3 = gb2 + MLP_H, *gb3 = gW3 + MLP_H * MLP_H, *gW4 = gb3 + MLP_H, *gb4 = gW4 + MLP_H;
+    double L = 0.0;
+    double z1[MLP_H], a1[MLP_H], z2[MLP_H], a2[MLP_H], z3[MLP_H], a3[MLP_H];
+    double d3[MLP_H], d2[MLP_H], d1[MLP_H];
+    for (int64_t b = 0; b < B; ++b) {
+        const double* x = X + b * MLP_IN;
+        const double o = mlp_sample(&p, x, z1, a1, z2, a2, z3, a3);
+        const double u = y[b] - o;
+        const double ind = u < 0.0 ? 1.0 : 0.0;
+        L += u * (q - ind);
+        const double dout = -(q - ind) / (double)B; /* dL/d prediction */
+        gb4[0] += dout;
+        for (int k = 0; k < MLP_H; ++k) {
+            gW4[k] += dout * a3[k];
+            d3[k] = z3[k] > 0.0 ? dout * p.W4[k] : 0.0;
+        }
+        for (int i = 0; i < MLP_H; ++i) {
+            gb3[i] += d3[i];
+            for (int k = 0; k < MLP_H; ++k) gW3[i * MLP_H + k] += d3[i] * a2[k];
+        }
+        for (int k = 0; k < MLP_H; ++k) {
+            double s = 0.0;
+            for (int i = 0; i < MLP_H; ++i) s += p.W3[i * MLP_H + k] * d3[i];
+            d2[k] = z2[k] > 0.0 ? s : 0.0;
+        }
+        for (int i = 0; i < MLP_H; ++i) {
+            gb2[i] += d2[i];
+            for (int k = 0; k < MLP_H; ++k) gW2[i * MLP_H + k] += d2[i] * a1[k];
+        }
+        for (int k = 0; k < MLP_H; ++k) {
+            double s = 0.0;
+            for (int i = 0; i < MLP_H; ++i) s += p.W2[i * MLP_H + k] * d2[i];
+            d1[k] = z1[k] > 0.0 ? s : 0.0;
+        }
+        for (int i = 0; i < MLP_H; ++i) {
+            gb1[i] += d1[i];
+            for (int k = 0; k < MLP_IN; ++k) gW1[i * MLP_IN + k] += d1[i] * x[k];
+        }
+    }
+    *loss = L / (double)B;
+    return 0;
+}
+
+/* Adam (Kingma & Ba): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * w -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps), t >= 1 */
+int hmxo_mlp_adam(double* w, double* m, double* v, const double* g, int64_t n, int64_t t,
+                  double lr, double b1, double b2, double eps)
+{
+    const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+    for (int64_t i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        w[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+    return 0;
+}
+
+/* Geometric features of a block tau x sigma (boxes a..b, sizes m, n):
+ * [log2 m, log2 n, diam_tau / l, diam_sigma / l, dist / l,
+ *  min(diam) / max(dist, 1e-12), d, log10 l^2] with l the kernel length. */
+int hmxo_features(const double* ta, const double* tb, const double* sa, const double* sb, int32_t d,
+                  int64_t m, int64_t n, double ell, double* f)
+{
+    double dt = 0.0, ds = 0.0, dist2 = 0.0;
+    for (int k = 0; k < d; ++k) {
+        dt += (tb[k] - ta[k]) * (tb[k] - ta[k]);
+        ds += (sb[k] - sa[k]) * (sb[k] - sa[k]);
+        double g1 = ta[k] - sb[k], g2 = sa[k] - tb[k];
+        if (g1 < 0.0) g1 = 0.0;
+        if (g2 < 0.0) g2 = 0.0;
+        dist2 += g1 * g1 + g2 * g2;
+    }
+    const double Dt = sqrt(dt), Ds = sqrt(ds), dist = sqrt(dist2);
+    f[0] = log2((double)m);
+    f[1] = log2((double)n);
+    f[2] = Dt / ell;
+    f[3] = Ds / ell;
+    f[4] = dist / ell;
+    f[5] = (Dt < Ds ? Dt : Ds) / (dist > 1e-12 ? dist : 1e-12);
+    f[6] = (double)d;
+    f[7] = log10(ell * ell);
+    return 0;
+}

@@ -109,6 +109,20 @@ int hmxo_cg_dense(const double* pts, int64_t n, int32_t d, int32_t kind, double 
 int hmxo_dense_block(const double* soa, int64_t n, int32_t d, int32_t kind, double p0,
                      int64_t tlo, int64_t thi, int64_t slo, int64_t shi, double* A);
 
+/* Rank predictor MLP 8 -> 64 -> 64 -> 64 -> 1 (ReLU), parameters packed as
+ * W1 (64x8 row-major), b1, W2 (64x64), b2, W3 (64x64), b3, W4 (1x64), b4. */
+int hmxo_mlp_nparams(void);
+int hmxo_mlp_forward(const double* w, const double* X, int64_t B, double* out);
+/* pinball loss (quantile q) averaged over the batch and its gradient */
+int hmxo_mlp_loss_grad(const double* w, const double* X, const double* y, int64_t B, double q,
+                       double* loss, double* grad);
+/* one Adam step (t >= 1) on n parameters */
+int hmxo_mlp_adam(double* w, double* m, double* v, const double* g, int64_t n, int64_t t,
+                  double lr, double b1, double b2, double eps);
+/* the 8 block features from the two cluster boxes */
+int hmxo_features(const double* ta, const double* tb, const double* sa, const double* sb, int32_t d,
+                  int64_t m, int64_t n, double ell, double* f);
+
 int hmxo_num_threads(void);
 
 #ifdef __cplusplus
