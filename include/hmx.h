@@ -76,9 +76,40 @@ typedef struct {
 
 /* ACA rank control.
  *  HMX_RANK_ADAPTIVE: Algorithm 2 with its stopping criterion, at most max_rank.
+ *  HMX_RANK_LEARNED : a rank predictor (hmx_mlp, below) sizes every
+ *                     admissible block before the ACA, so that one batched
+ *                     pass replaces k_max-sized scratch: each block gets
+ *                     storage for r^ = clamp(ceil(pred) + 1, 1,
+ *                     min(max_rank, m, n)) columns.
+ *                     Sizing form (learned_one_shot = 0): Algorithm 2 with
+ *                     its stopping test every step; a block that fills its
+ *                     r^ columns unfinished is approximated again with
+ *                     max_rank storage.  The ranks and factors are those of
+ *                     HMX_RANK_ADAPTIVE (bit for bit); the prediction only
+ *                     sizes memory.
+ *                     One-shot form (learned_one_shot = 1): exactly r^ steps
+ *                     without the test, which then judges the last term; a
+ *                     failing block is approximated again with max_rank
+ *                     storage (the same r^ steps, then adaptive).  Either
+ *                     way Algorithm 2's test judges every block.
  *  HMX_RANK_FIXED   : exactly min(max_rank, m, n) rank-one steps, no stopping
  *                     test (the fixed-k mode of the paper's experiments). */
-typedef enum { HMX_RANK_ADAPTIVE = 0, HMX_RANK_FIXED = 2 } hmx_rank_mode;
+typedef enum { HMX_RANK_ADAPTIVE = 0, HMX_RANK_LEARNED = 1, HMX_RANK_FIXED = 2 } hmx_rank_mode;
+
+/* Rank predictor: an MLP 8 -> 64 -> 64 -> 64 -> 1 with ReLU on the hidden
+ * layers, FP32, on the features of an admissible block tau x sigma
+ *   [log2 |tau|, log2 |sigma|, diam(tau) / l, diam(sigma) / l, dist / l,
+ *    min(diam(tau), diam(sigma)) / max(dist, 1e-12), d, log10 l^2]
+ * (bounding-box diameters and distance of eq. (3); l the kernel's length
+ * scale: sqrt(p0) for the Gaussian, p0 for Matern-3/2, 1 for the test
+ * kernels), standardised per feature as (f - mean) * scale.  Parameters are
+ * packed W1 (64 x 8, row-major), b1, W2 (64 x 64), b2, W3 (64 x 64), b3,
+ * W4 (1 x 64), b4: HMX_MLP_NPARAMS floats.  Trained with the pinball
+ * (quantile) loss rho_q(y - pred) = (y - pred)(q - [y < pred]) averaged over
+ * the batch, and Adam. */
+#define HMX_MLP_NPARAMS 8961
+#define HMX_MLP_FEATURES 8
+typedef struct hmx_mlp_s* hmx_mlp; /* opaque; owns its device parameters */
 
 typedef struct {
     int32_t leaf_size;       /* C_leaf >= 1: clusters with more points split (Section 2.1) */
@@ -105,7 +136,14 @@ typedef struct {
                                 MiB; 0 selects 8192.  Blocks are approximated in
                                 chunks whose k_max-column scratch fits the budget,
                                 then compacted to their exact ranks */
-    int32_t reserved[7];
+    int32_t aca_only;        /* 1: stop after the ACA (no matrix pool).  The
+                                handle then serves partition, ranks, features
+                                and stats; hmx_matvec returns UNSUPPORTED.
+                                Used to collect predictor training data */
+    hmx_mlp mlp;             /* predictor for HMX_RANK_LEARNED (borrowed; must
+                                outlive hmx_build only), else NULL */
+    int32_t learned_one_shot; /* HMX_RANK_LEARNED form: 0 sizing, 1 one-shot */
+    int32_t reserved[3];
 } hmx_params;
 
 /* Statistics of a built H-matrix (host struct). */
@@ -131,6 +169,11 @@ typedef struct {
                                  compaction, near field, matvec plan, total */
     int64_t device_bytes;     /* device memory held by the handle */
     int64_t level_sizes[64];  /* |V(l)| per level */
+    int64_t aca_fallback;     /* HMX_RANK_LEARNED: blocks left unfinished by
+                                 their target and approximated again */
+    int64_t aca_capacity;     /* entries of ACA storage reserved: sum over the
+                                 blocks of (target or max_rank) * (m + n) */
+    double predict_ms;        /* HMX_RANK_LEARNED: rank prediction time */
 } hmx_stats;
 
 /* Fill *p with the defaults: leaf 256, eta 1.5, eps 1e-5, aca_eta 0,
@@ -211,6 +254,59 @@ hmx_status hmx_get_stats(hmx_hmatrix h, hmx_stats* s);
  * memory); matvec itself still allocates nothing. */
 hmx_status hmx_profile_begin(hmx_hmatrix h, int32_t max_calls);
 hmx_status hmx_profile_end(hmx_hmatrix h, double* ms, int32_t* calls);
+
+/* ---- rank predictor (HMX_RANK_LEARNED) ---- */
+
+/* Create a predictor.  params: host, HMX_MLP_NPARAMS floats (the initial
+ * weights; NULL = all zero).  Standardisation starts as the identity
+ * (mean 0, scale 1) and the Adam state at zero. */
+hmx_status hmx_mlp_create(const float* params, hmx_mlp* out);
+hmx_status hmx_mlp_destroy(hmx_mlp m);
+
+/* Host copies of the parameters and the standardisation (8 floats each);
+ * any pointer may be NULL.  set resets the Adam state (moments and step). */
+hmx_status hmx_mlp_set_params(hmx_mlp m, const float* params, const float* mean,
+                              const float* scale);
+hmx_status hmx_mlp_get_params(hmx_mlp m, float* params, float* mean, float* scale);
+
+/* Set the standardisation from n training samples X (device, n x 8 FP32):
+ * mean = sample mean, scale = 1 / population standard deviation (1 where it
+ * is below 1e-6), both accumulated in FP64. */
+hmx_status hmx_mlp_fit_normalization(hmx_mlp m, const float* X, int64_t n, void* stream);
+
+/* out[b] = MLP(standardised X[b]) for B samples (device X: B x 8, out: B).
+ * Asynchronous; allocates activation memory of B * 193 floats. */
+hmx_status hmx_mlp_forward(hmx_mlp m, const float* X, int64_t B, float* out, void* stream);
+
+/* Gradient of the mean pinball loss with quantile q in (0, 1) over a batch:
+ * X (device, B x 8), y (device, B targets), grad (device, HMX_MLP_NPARAMS,
+ * packed like the parameters), loss (host double, optional; synchronises
+ * when given).  At y == pred the subgradient q is used. */
+hmx_status hmx_mlp_loss_grad(hmx_mlp m, const float* X, const float* y, int64_t B, double q,
+                             float* grad, double* loss, void* stream);
+
+/* One Adam step with the given gradient (device): t += 1, then
+ * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * w -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */
+hmx_status hmx_mlp_adam(hmx_mlp m, const float* grad, double lr, double beta1, double beta2,
+                        double eps, void* stream);
+
+/* Mini-batch training: for s = 0..steps-1 the batch is the samples
+ * batch_idx[s * B .. s * B + B) (device int64 indices into X, y, drawn by
+ * the caller; values outside [0, n) are clamped), forward, backward, Adam (beta 0.9 / 0.999, eps 1e-8).
+ * X (device n x 8), y (device n).  losses (device double, steps entries,
+ * optional) receives each batch's loss before its update.  Asynchronous. */
+hmx_status hmx_mlp_train(hmx_mlp m, const float* X, const float* y, int64_t n,
+                         const int64_t* batch_idx, int64_t B, int32_t steps, double q, double lr,
+                         double* losses, void* stream);
+
+/* Training pairs of a built handle (any rank mode, including aca_only):
+ * the features of every admissible leaf in canonical order (device, n_adm x
+ * 8 FP32) and, if ranks != NULL, its ACA rank as float (device, n_adm).
+ * *n_adm (host) gives the capacity in leaves and receives the count; a too
+ * small capacity returns INVALID_ARG.  Asynchronous. */
+hmx_status hmx_block_features(hmx_hmatrix h, float* features, float* ranks, int64_t* n_adm,
+                              void* stream);
 
 /* Release every device buffer of the handle (synchronises the device).  The
  * buffers return to the library's device-block cache, which later builds

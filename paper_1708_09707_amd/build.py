@@ -25,7 +25,8 @@ COMMON = [
 ]
 # exact IEEE sequences required (ordering and partition are compared bit for bit)
 NO_CONTRACT = {"k_order.hip", "k_tree.hip"}
-SOURCES = ["k_order.hip", "k_tree.hip", "k_aca.hip", "k_mvp.hip", "k_blas.hip", "hmx_api.hip"]
+SOURCES = ["k_order.hip", "k_tree.hip", "k_aca.hip", "k_mvp.hip", "k_blas.hip", "k_mlp.hip",
+           "hmx_api.hip"]
 
 
 def hipcc() -> str:
@@ -56,7 +57,7 @@ def build(verbose: bool = True) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Wl,-z,defs", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))

@@ -181,6 +181,14 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 
 }  // namespace
 
+// rank predictor: FP32 parameters, standardisation and Adam state on the
+// device, plus work buffers grown on demand
+struct hmx_mlp_s {
+    DevBuf w, m, v, mean, scale;
+    int64_t t = 0;  // Adam steps taken
+    DevBuf act, scratch, grad, Xb, yb, loss;
+};
+
 struct hmx_hmatrix_s {
     int64_t n = 0;
     int d = 0;
@@ -199,7 +207,7 @@ struct hmx_hmatrix_s {
     int max_tile = 0;
     int64_t factor_entries = 0, near_entries = 0;
     DevBuf codes, perm, soa64, soa32, node_lo, node_hi, bmin, bmax;
-    DevBuf adm, adm_level, dense, dense_level;
+    DevBuf adm, adm_level, adm_ids, dense, dense_level;
     DevBuf tile_of_point, tile_lo;
     DevBuf rank, steps, voff, toff, V;
     DevBuf pieces, upool, npool, widx, tile_meta, vecpool, col_block;
@@ -219,6 +227,7 @@ struct hmx_hmatrix_s {
     int64_t device_bytes() const {
         const DevBuf* all[] = {&codes,     &perm,          &soa64,   &soa32,     &node_lo,
                                &node_hi,   &bmin,          &bmax,    &adm,       &adm_level,
+                               &adm_ids,
                                &dense,     &dense_level,   &tile_of_point, &tile_lo, &rank,
                                &steps,     &voff,          &toff,    &V,         &pieces,
                                &upool,     &npool,         &widx,    &tile_meta, &vecpool,
@@ -230,6 +239,38 @@ struct hmx_hmatrix_s {
 };
 
 namespace {
+
+// counts, sizes and the matvec's algorithmic bytes into the handle's stats
+void finish_stats(hmx_hmatrix_s* h, std::chrono::steady_clock::time_point t_all) {
+    hmx_stats& S = h->stats;
+    const size_t esz = h->esz, ssz = h->ssz;
+    const int64_t n = h->n;
+    S.n = n;
+    S.d = h->d;
+    S.n_adm = h->n_adm;
+    S.n_dense = h->n_dense;
+    S.n_tiles = h->ntiles;
+    if (!h->prm.aca_only) S.sum_rank = h->sum_rank;
+    S.factor_entries = h->factor_entries;
+    S.near_entries = h->near_entries;
+    S.entry_bytes = (int32_t)ssz;
+    S.near_entry_bytes = (int32_t)h->nsz;
+    S.phase_ms[7] = ms_since(t_all);
+    // algorithmic bytes of one matvec with beta = 0: stored data once, the
+    // vectors x and z once, perm for gather and scatter, t written and read
+    S.matvec_bytes = h->prm.aca_only
+                         ? 0.0
+                         : (double)h->near_entries * h->nsz + (double)h->factor_entries * ssz +
+                               (double)n * (2.0 * esz + 8.0) + (double)S.sum_rank * 2.0 * esz;
+    S.device_bytes = h->device_bytes();
+}
+
+// length scale l of the predictor's features
+double kernel_length(const hmx_kernel& k) {
+    if (k.kind == HMX_GAUSSIAN) return std::sqrt(k.p0);
+    if (k.kind == HMX_MATERN32) return k.p0;
+    return 1.0;
+}
 
 // grow a device buffer to at least `bytes`, keeping the first `keep` bytes
 void grow(DevBuf& b, size_t bytes, size_t keep, hipStream_t st, const char* what) {
@@ -387,6 +428,7 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
                 int64_t nc = std::max<int64_t>(2 * cap_adm, h->n_adm + tot[0]);
                 grow(h->adm, nc * sizeof(int4), h->n_adm * sizeof(int4), st, "adm leaves");
                 grow(h->adm_level, nc * 4, h->n_adm * 4, st, "adm levels");
+                grow(h->adm_ids, nc * sizeof(int2), h->n_adm * sizeof(int2), st, "adm node ids");
                 cap_adm = nc;
             }
             if (h->n_dense + tot[2] > cap_dense) {
@@ -401,7 +443,8 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
                                         h->node_hi.as<int32_t>(), h->bmin.as<double>(),
                                         h->bmax.as<double>(), d, leaf, eta, bc, level,
                                         nxt.as<int2>(), h->adm.as<int4>(),
-                                        h->adm_level.as<int32_t>(), h->n_adm, h->dense.as<int4>(),
+                                        h->adm_level.as<int32_t>(), h->adm_ids.as<int2>(),
+                                        h->n_adm, h->dense.as<int4>(),
                                         h->dense_level.as<int32_t>(), h->n_dense, st),
                   "traverse write");
             h->n_adm += tot[0];
@@ -431,32 +474,23 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
     };
 
     // ---- 4. batched ACA of the admissible leaves, in chunks ----
-    // Each chunk of consecutive admissible leaves gets k_max-column scratch
-    // for U and V within the budget; after its ACA the factors are compacted
-    // to their exact ranks (U in the compute type as the source of the
-    // tile-major pool, V in the storage type).
+    // A pass approximates a list of blocks in chunks: every block gets
+    // scratch for its column capacity (k_max, or the predicted target in the
+    // learned one-shot pass) within the chunk budget; after the chunk's ACA
+    // the factors are compacted to their exact ranks (U in the compute type
+    // as the source of the tile-major pool, V in the storage type) and
+    // appended to the pools.
     alloc(h->rank, std::max<int64_t>(h->n_adm, 1) * 4, "ranks");
     alloc(h->steps, std::max<int64_t>(h->n_adm, 1) * 4, "steps");
     alloc(h->voff, (h->n_adm + 1) * 8, "V offsets");
-    DevBuf cu, cv, cc, Ucap, Vcap, Uex, uoff_ex;
+    DevBuf Uex, uoff_ex;
     alloc(uoff_ex, (h->n_adm + 1) * 8, "U offsets");
     int nchunks = 0;
+    double aca_ms = 0.0;
+    int64_t utot = 0, vtot = 0;
+    const bool learned = h->prm.rank_mode == HMX_RANK_LEARNED;
+    const bool aca_only = h->prm.aca_only != 0;
     if (h->n_adm > 0) {
-        alloc(cu, (h->n_adm + 1) * 8, "U capacity offsets");
-        alloc(cv, (h->n_adm + 1) * 8, "V capacity offsets");
-        alloc(cc, (h->n_adm + 1) * 8, "capacity offsets");
-        check(launch_extent(h->adm.as<int4>(), h->n_adm, 0, kmax, nullptr, nullptr,
-                            cu.as<int64_t>(), st),
-              "extent");
-        check(launch_extent(h->adm.as<int4>(), h->n_adm, 1, kmax, nullptr, nullptr,
-                            cv.as<int64_t>(), st),
-              "extent");
-        check(launch_extent(h->adm.as<int4>(), h->n_adm, 7, kmax, nullptr, nullptr,
-                            cc.as<int64_t>(), st),
-              "extent");
-        scan(cu.as<int64_t>(), h->n_adm);
-        scan(cv.as<int64_t>(), h->n_adm);
-        const int64_t ctot = scan(cc.as<int64_t>(), h->n_adm);
         const int64_t big = big_adm;
         const int words = (int)(2 * ((big + 31) / 32));
         if ((size_t)words * 4 > 64 * 1024) {
@@ -464,34 +498,8 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
                     (long long)big);
             throw Fail{HMX_ERR_UNSUPPORTED};
         }
-        // chunking: each chunk's capacity is at most step + one block
         const int64_t budget_mb = h->prm.aca_chunk_mb > 0 ? h->prm.aca_chunk_mb : 8192;
         const int64_t budget = std::max<int64_t>(budget_mb * ((int64_t)1 << 20) / (int64_t)esz, 1);
-        nchunks = (int)std::min<int64_t>((ctot + budget - 1) / budget, 1 << 20);
-        nchunks = std::max(nchunks, 1);
-        const int64_t step = (ctot + nchunks - 1) / nchunks;
-        DevBuf bnd;
-        alloc(bnd, (size_t)(nchunks + 1) * 8, "chunk bounds");
-        check(launch_chunk_bounds(cc.as<int64_t>(), h->n_adm, step, nchunks, bnd.as<int64_t>(),
-                                  st),
-              "chunk bounds");
-        std::vector<int64_t> hb(nchunks + 1), hcu(nchunks + 1), hcv(nchunks + 1);
-        d2h(hb.data(), bnd.p, (nchunks + 1) * 8, st);
-        // capacity offsets at the boundaries (cu, cv have n_adm + 1 valid entries)
-        int64_t max_u = 0, max_v = 0;
-        for (int k = 0; k <= nchunks; ++k) {
-            check(hipMemcpyAsync(&hcu[k], cu.as<int64_t>() + hb[k], 8, hipMemcpyDeviceToHost, st),
-                  "cu");
-            check(hipMemcpyAsync(&hcv[k], cv.as<int64_t>() + hb[k], 8, hipMemcpyDeviceToHost, st),
-                  "cv");
-        }
-        check(hipStreamSynchronize(st), "bounds sync");
-        for (int k = 0; k < nchunks; ++k) {
-            max_u = std::max(max_u, hcu[k + 1] - hcu[k]);
-            max_v = std::max(max_v, hcv[k + 1] - hcv[k]);
-        }
-        alloc(Ucap, (size_t)std::max<int64_t>(max_u, 1) * esz, "U chunk scratch");
-        alloc(Vcap, (size_t)std::max<int64_t>(max_v, 1) * esz, "V chunk scratch");
         AcaArgs a{};
         a.soa = f64 ? h->soa64.p : h->soa32.p;
         a.soa64 = h->soa64.as<double>();
@@ -503,48 +511,164 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
         a.aca_eta = h->prm.aca_eta;
         a.eps0 = h->prm.aca_eps0 >= 0 ? h->prm.aca_eps0 : (f64 ? 1e-14 : 1e-7);
         a.fixed = h->prm.rank_mode == HMX_RANK_FIXED;
-        a.U = Ucap.p;
-        a.V = Vcap.p;
         a.lds_words = std::max(words, 2);
-        double aca_ms = 0.0;
-        int64_t utot = 0, vtot = 0;
-        for (int k = 0; k < nchunks; ++k) {
-            const int64_t b0 = hb[k], nbk = hb[k + 1] - hb[k];
-            if (nbk == 0) continue;
-            const auto ta = clk::now();
-            a.blocks = h->adm.as<int4>() + b0;
-            a.nblocks = nbk;
-            a.uoff = cu.as<int64_t>() + b0;
-            a.voff = cv.as<int64_t>() + b0;
-            a.ubase = hcu[k];
-            a.vbase = hcv[k];
-            a.rank = h->rank.as<int32_t>() + b0;
-            a.steps = h->steps.as<int32_t>() + b0;
-            check(launch_aca(a, f64, st), "aca");
-            check(hipStreamSynchronize(st), "aca sync");
-            aca_ms += ms_since(ta);
-            // exact offsets of this chunk's blocks: chunk-local scan plus the running totals
-            int64_t* ue = uoff_ex.as<int64_t>() + b0;
-            int64_t* ve = h->voff.as<int64_t>() + b0;
-            check(launch_extent(a.blocks, nbk, 3, 0, a.rank, nullptr, ue, st), "extent");
-            check(launch_extent(a.blocks, nbk, 4, 0, a.rank, nullptr, ve, st), "extent");
-            const int64_t uk = scan(ue, nbk), vk = scan(ve, nbk);
-            check(launch_add_const(ue, nbk, utot, st), "offsets");
-            check(launch_add_const(ve, nbk, vtot, st), "offsets");
-            grow(Uex, (size_t)(utot + uk) * esz, (size_t)utot * esz, st, "U pool");
-            grow(h->V, (size_t)(vtot + vk) * ssz, (size_t)vtot * ssz, st, "V pool");
-            check(launch_compact_u(a.blocks, nbk, a.rank, a.uoff, a.ubase, ue, Ucap.p, Uex.p, f64,
-                                   st),
-                  "compact U");
-            check(launch_compact_v(a.blocks, nbk, a.rank, a.voff, a.vbase, ve, Vcap.p, h->V.p,
-                                   smode, st),
-                  "compact V");
-            check(hipStreamSynchronize(st), "compact sync");
-            utot += uk;
-            vtot += vk;
+
+        // one pass over blocks[0..nb): cap = per-block column capacity (null:
+        // k_max), rt = one-shot targets (null: adaptive); exact offsets of the
+        // blocks' factors in the pools go to ue_all / ve_all
+        auto pass = [&](const int4* blocks, int64_t nb, const int32_t* cap, const int32_t* rt,
+                        int one_shot, int cap_only, int32_t* rank, int32_t* steps,
+                        int64_t* ue_all, int64_t* ve_all) {
+            DevBuf cu, cv, cc, Ucap, Vcap;
+            alloc(cu, (nb + 1) * 8, "U capacity offsets");
+            alloc(cv, (nb + 1) * 8, "V capacity offsets");
+            alloc(cc, (nb + 1) * 8, "capacity offsets");
+            check(launch_extent(blocks, nb, cap ? 3 : 0, kmax, cap, nullptr, cu.as<int64_t>(), st),
+                  "extent");
+            check(launch_extent(blocks, nb, cap ? 4 : 1, kmax, cap, nullptr, cv.as<int64_t>(), st),
+                  "extent");
+            check(launch_extent(blocks, nb, cap ? 8 : 7, kmax, cap, nullptr, cc.as<int64_t>(), st),
+                  "extent");
+            scan(cu.as<int64_t>(), nb);
+            scan(cv.as<int64_t>(), nb);
+            const int64_t ctot = scan(cc.as<int64_t>(), nb);
+            S.aca_capacity += ctot;
+            // each chunk's capacity is at most step + one block
+            int nch = (int)std::min<int64_t>((ctot + budget - 1) / budget, 1 << 20);
+            nch = std::max(nch, 1);
+            const int64_t step = (ctot + nch - 1) / nch;
+            DevBuf bnd;
+            alloc(bnd, (size_t)(nch + 1) * 8, "chunk bounds");
+            check(launch_chunk_bounds(cc.as<int64_t>(), nb, step, nch, bnd.as<int64_t>(), st),
+                  "chunk bounds");
+            std::vector<int64_t> hb(nch + 1), hcu(nch + 1), hcv(nch + 1);
+            d2h(hb.data(), bnd.p, (nch + 1) * 8, st);
+            int64_t max_u = 0, max_v = 0;
+            for (int k = 0; k <= nch; ++k) {
+                check(hipMemcpyAsync(&hcu[k], cu.as<int64_t>() + hb[k], 8, hipMemcpyDeviceToHost,
+                                     st),
+                      "cu");
+                check(hipMemcpyAsync(&hcv[k], cv.as<int64_t>() + hb[k], 8, hipMemcpyDeviceToHost,
+                                     st),
+                      "cv");
+            }
+            check(hipStreamSynchronize(st), "bounds sync");
+            for (int k = 0; k < nch; ++k) {
+                max_u = std::max(max_u, hcu[k + 1] - hcu[k]);
+                max_v = std::max(max_v, hcv[k + 1] - hcv[k]);
+            }
+            alloc(Ucap, (size_t)std::max<int64_t>(max_u, 1) * esz, "U chunk scratch");
+            alloc(Vcap, (size_t)std::max<int64_t>(max_v, 1) * esz, "V chunk scratch");
+            a.U = Ucap.p;
+            a.V = Vcap.p;
+            a.one_shot = one_shot;
+            a.cap_only = cap_only;
+            for (int k = 0; k < nch; ++k) {
+                const int64_t b0 = hb[k], nbk = hb[k + 1] - hb[k];
+                if (nbk == 0) continue;
+                ++nchunks;
+                const auto ta = clk::now();
+                a.blocks = blocks + b0;
+                a.nblocks = nbk;
+                a.uoff = cu.as<int64_t>() + b0;
+                a.voff = cv.as<int64_t>() + b0;
+                a.ubase = hcu[k];
+                a.vbase = hcv[k];
+                a.rtarget = rt ? rt + b0 : nullptr;
+                a.rank = rank + b0;
+                a.steps = steps + b0;
+                check(launch_aca(a, f64, st), "aca");
+                check(hipStreamSynchronize(st), "aca sync");
+                aca_ms += ms_since(ta);
+                if (aca_only) continue;
+                // exact offsets of this chunk's blocks: chunk-local scan plus the
+                // running totals
+                int64_t* ue = ue_all + b0;
+                int64_t* ve = ve_all + b0;
+                check(launch_extent(a.blocks, nbk, 3, 0, a.rank, nullptr, ue, st), "extent");
+                check(launch_extent(a.blocks, nbk, 4, 0, a.rank, nullptr, ve, st), "extent");
+                const int64_t uk = scan(ue, nbk), vk = scan(ve, nbk);
+                check(launch_add_const(ue, nbk, utot, st), "offsets");
+                check(launch_add_const(ve, nbk, vtot, st), "offsets");
+                grow(Uex, (size_t)(utot + uk) * esz, (size_t)utot * esz, st, "U pool");
+                grow(h->V, (size_t)(vtot + vk) * ssz, (size_t)vtot * ssz, st, "V pool");
+                check(launch_compact_u(a.blocks, nbk, a.rank, a.uoff, a.ubase, ue, Ucap.p, Uex.p,
+                                       f64, st),
+                      "compact U");
+                check(launch_compact_v(a.blocks, nbk, a.rank, a.voff, a.vbase, ve, Vcap.p,
+                                       h->V.p, smode, st),
+                      "compact V");
+                check(hipStreamSynchronize(st), "compact sync");
+                utot += uk;
+                vtot += vk;
+            }
+        };
+
+        if (!learned) {
+            pass(h->adm.as<int4>(), h->n_adm, nullptr, nullptr, 0, 0, h->rank.as<int32_t>(),
+                 h->steps.as<int32_t>(), uoff_ex.as<int64_t>(), h->voff.as<int64_t>());
+        } else {
+            // learned sizing: predicted targets, a pass with storage of that
+            // size, then the blocks left unfinished again with k_max columns
+            // (sizing form: plain adaptive; one-shot form: the same target
+            // steps, the test, then adaptive)
+            const int one_shot = h->prm.learned_one_shot;
+            DevBuf rt;
+            alloc(rt, h->n_adm * 4, "rank targets");
+            const auto tp = clk::now();
+            const double ell = kernel_length(h->kern);
+            const hmx_mlp_s* mp = h->prm.mlp;
+            check(launch_rank_predict(h->adm.as<int4>(), h->adm_ids.as<int2>(), h->n_adm,
+                                      h->bmin.as<double>(), h->bmax.as<double>(), d, ell,
+                                      mp->w.as<float>(), mp->mean.as<float>(),
+                                      mp->scale.as<float>(), kmax, nullptr, rt.as<int32_t>(), st),
+                  "rank prediction");
+            check(hipStreamSynchronize(st), "prediction sync");
+            S.predict_ms = ms_since(tp);
+            pass(h->adm.as<int4>(), h->n_adm, rt.as<int32_t>(), rt.as<int32_t>(), one_shot, 1,
+                 h->rank.as<int32_t>(), h->steps.as<int32_t>(), uoff_ex.as<int64_t>(),
+                 h->voff.as<int64_t>());
+            DevBuf flag;
+            alloc(flag, (h->n_adm + 1) * 8, "fallback flags");
+            check(launch_fail_flags(h->rank.as<int32_t>(), h->n_adm, flag.as<int64_t>(), st),
+                  "fallback flags");
+            const int64_t nfb = scan(flag.as<int64_t>(), h->n_adm);
+            S.aca_fallback = nfb;
+            if (nfb > 0) {
+                DevBuf list, bfb, rtfb, rkfb, stfb, uefb, vefb;
+                alloc(list, nfb * 4, "fallback list");
+                alloc(bfb, nfb * sizeof(int4), "fallback blocks");
+                alloc(rtfb, nfb * 4, "fallback targets");
+                alloc(rkfb, nfb * 4, "fallback ranks");
+                alloc(stfb, nfb * 4, "fallback steps");
+                alloc(uefb, (nfb + 1) * 8, "fallback U offsets");
+                alloc(vefb, (nfb + 1) * 8, "fallback V offsets");
+                check(launch_gather_failed(h->rank.as<int32_t>(), flag.as<int64_t>(), h->n_adm,
+                                           h->adm.as<int4>(), rt.as<int32_t>(),
+                                           list.as<int32_t>(), bfb.as<int4>(),
+                                           rtfb.as<int32_t>(), st),
+                      "fallback gather");
+                pass(bfb.as<int4>(), nfb, nullptr, one_shot ? rtfb.as<int32_t>() : nullptr,
+                     one_shot, 0, rkfb.as<int32_t>(), stfb.as<int32_t>(), uefb.as<int64_t>(),
+                     vefb.as<int64_t>());
+                const int32_t* li = list.as<int32_t>();
+                check(launch_scatter_i32(li, nfb, rkfb.as<int32_t>(), h->rank.as<int32_t>(), 0,
+                                         st),
+                      "fallback ranks");
+                check(launch_scatter_i32(li, nfb, stfb.as<int32_t>(), h->steps.as<int32_t>(), 1,
+                                         st),
+                      "fallback steps");
+                if (!aca_only) {
+                    check(launch_scatter_i64(li, nfb, uefb.as<int64_t>(), uoff_ex.as<int64_t>(),
+                                             st),
+                          "fallback offsets");
+                    check(launch_scatter_i64(li, nfb, vefb.as<int64_t>(), h->voff.as<int64_t>(),
+                                             st),
+                          "fallback offsets");
+                }
+                check(hipStreamSynchronize(st), "fallback sync");
+            }
         }
-        Ucap.release();
-        Vcap.release();
         S.u_entries = utot;
         S.v_entries = vtot;
         h->factor_entries = utot + vtot;
@@ -559,12 +683,18 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
         check(hipMemcpyAsync(hv, rd, sizeof hv, hipMemcpyDeviceToHost, st), "stats readback");
         check(hipStreamSynchronize(st), "stats sync");
         S.max_rank_used = (int32_t)hv[0];
+        S.sum_rank = (int64_t)hv[1];
         S.aca_columns = (int64_t)hv[3];
     }
     if (!h->V.p) alloc(h->V, 16, "V pool");
     if (!Uex.p) alloc(Uex, 16, "U pool");
     S.aca_chunks = nchunks;
-    S.phase_ms[4] = ms_since(t0) - S.phase_ms[3];
+    S.phase_ms[4] = ms_since(t0) - S.phase_ms[3] - S.predict_ms;
+    if (aca_only) {
+        Uex.release();
+        finish_stats(h, t_all);
+        return;
+    }
     t0 = clk::now();
     // t offsets, vector pool, column -> leaf map of phase 1
     alloc(h->toff, (h->n_adm + 1) * 8, "t offsets");
@@ -667,23 +797,7 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
     S.phase_ms[5] = ms_since(t0);
     S.phase_ms[6] = 0.0;
 
-    // ---- stats ----
-    S.n = n;
-    S.d = d;
-    S.n_adm = h->n_adm;
-    S.n_dense = h->n_dense;
-    S.n_tiles = h->ntiles;
-    S.sum_rank = h->sum_rank;
-    S.factor_entries = h->factor_entries;
-    S.near_entries = h->near_entries;
-    S.entry_bytes = (int32_t)ssz;
-    S.near_entry_bytes = (int32_t)h->nsz;
-    S.phase_ms[7] = ms_since(t_all);
-    // algorithmic bytes of one matvec with beta = 0: stored data once, the
-    // vectors x and z once, perm for gather and scatter, t written and read
-    S.matvec_bytes = (double)h->near_entries * h->nsz + (double)h->factor_entries * ssz +
-                     (double)n * (2.0 * esz + 8.0) + (double)h->sum_rank * 2.0 * esz;
-    S.device_bytes = h->device_bytes();
+    finish_stats(h, t_all);
 }
 
 }  // namespace
@@ -769,9 +883,22 @@ hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t
             return HMX_ERR_UNSUPPORTED;
         }
     }
-    if (p.rank_mode != HMX_RANK_ADAPTIVE && p.rank_mode != HMX_RANK_FIXED) {
+    if (p.rank_mode != HMX_RANK_ADAPTIVE && p.rank_mode != HMX_RANK_FIXED &&
+        p.rank_mode != HMX_RANK_LEARNED) {
         set_err("unsupported rank mode %d", (int)p.rank_mode);
         return HMX_ERR_UNSUPPORTED;
+    }
+    if (p.rank_mode == HMX_RANK_LEARNED && !p.mlp) {
+        set_err("HMX_RANK_LEARNED needs a rank predictor (params.mlp)");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (p.aca_only != 0 && p.aca_only != 1) {
+        set_err("aca_only must be 0 or 1");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (p.learned_one_shot != 0 && p.learned_one_shot != 1) {
+        set_err("learned_one_shot must be 0 or 1");
+        return HMX_ERR_INVALID_ARG;
     }
     if (kernel->kind != HMX_GAUSSIAN && kernel->kind != HMX_MATERN32 &&
         kernel->kind != HMX_TEST_CONST && kernel->kind != HMX_TEST_LOWRANK) {
@@ -825,6 +952,10 @@ hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype
         set_err("vector dtype must equal the compute dtype");
         return HMX_ERR_INVALID_ARG;
     }
+    if (h->prm.aca_only) {
+        set_err("handle was built with aca_only: no matrix to apply");
+        return HMX_ERR_UNSUPPORTED;
+    }
     hipStream_t st = (hipStream_t)stream;
     const int f64 = h->f64;
     hipEvent_t* ev = nullptr;
@@ -855,6 +986,10 @@ hmx_status hmx_cg_solve(hmx_hmatrix h, const void* b, void* x, double rel_tol, i
     if (!h || !b || !x || !(rel_tol >= 0) || max_iter < 0) {
         set_err("invalid argument to hmx_cg_solve");
         return HMX_ERR_INVALID_ARG;
+    }
+    if (h->prm.aca_only) {
+        set_err("handle was built with aca_only: no matrix to apply");
+        return HMX_ERR_UNSUPPORTED;
     }
     hipStream_t st = (hipStream_t)stream;
     const int f64 = h->f64;
@@ -1046,6 +1181,10 @@ hmx_status hmx_get_factors(hmx_hmatrix h, int64_t leaf, double* U, double* V, in
         set_err("invalid argument to hmx_get_factors");
         return HMX_ERR_INVALID_ARG;
     }
+    if (h->prm.aca_only) {
+        set_err("handle was built with aca_only: factors were not kept");
+        return HMX_ERR_UNSUPPORTED;
+    }
     hipStream_t st = (hipStream_t)stream;
     try {
         int4 bl;
@@ -1152,6 +1291,237 @@ hmx_status hmx_profile_end(hmx_hmatrix h, double* ms, int32_t* calls) {
     }
     h->prof_release();
     return s;
+}
+
+// ---------------------------------------------------------------------------
+// rank predictor
+// ---------------------------------------------------------------------------
+
+extern "C++" {
+namespace {
+const int64_t kP = HMX_MLP_NPARAMS;
+
+template <typename F>
+hmx_status guarded(F&& f) {
+    try {
+        f();
+    } catch (const Fail& e) {
+        return e.s;
+    } catch (const std::bad_alloc&) {
+        set_err("host allocation failed");
+        return HMX_ERR_OOM;
+    }
+    return HMX_OK;
+}
+
+// grow a work buffer without keeping its contents (the stream is synchronised
+// first: the old block may still be in use by queued work)
+void ensure(DevBuf& b, size_t bytes, hipStream_t st, const char* what) {
+    if (b.p && b.bytes >= bytes) return;
+    check(hipStreamSynchronize(st), "work buffer sync");
+    alloc(b, bytes, what);
+}
+}  // namespace
+}  // extern "C++"
+
+hmx_status hmx_mlp_create(const float* params, hmx_mlp* out) {
+    if (out) *out = nullptr;
+    if (!out) {
+        set_err("NULL argument");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (mlp_nparams() != kP) {
+        set_err("parameter count mismatch");
+        return HMX_ERR_DEVICE;
+    }
+    hmx_mlp_s* m = new (std::nothrow) hmx_mlp_s();
+    if (!m) {
+        set_err("host allocation failed");
+        return HMX_ERR_OOM;
+    }
+    hmx_status s = guarded([&] {
+        alloc(m->w, kP * 4, "mlp weights");
+        alloc(m->m, kP * 4, "adam m");
+        alloc(m->v, kP * 4, "adam v");
+        alloc(m->mean, 8 * 4, "mlp mean");
+        alloc(m->scale, 8 * 4, "mlp scale");
+        std::vector<float> w(kP, 0.f), mu(8, 0.f), sc(8, 1.f);
+        if (params) memcpy(w.data(), params, kP * 4);
+        check(hipMemcpy(m->w.p, w.data(), kP * 4, hipMemcpyHostToDevice), "weights");
+        check(hipMemset(m->m.p, 0, kP * 4), "adam m");
+        check(hipMemset(m->v.p, 0, kP * 4), "adam v");
+        check(hipMemcpy(m->mean.p, mu.data(), 32, hipMemcpyHostToDevice), "mean");
+        check(hipMemcpy(m->scale.p, sc.data(), 32, hipMemcpyHostToDevice), "scale");
+    });
+    if (s != HMX_OK) {
+        delete m;
+        return s;
+    }
+    *out = m;
+    return HMX_OK;
+}
+
+hmx_status hmx_mlp_destroy(hmx_mlp m) {
+    if (!m) return HMX_OK;
+    (void)hipDeviceSynchronize();
+    delete m;
+    return HMX_OK;
+}
+
+hmx_status hmx_mlp_set_params(hmx_mlp m, const float* params, const float* mean,
+                              const float* scale) {
+    if (!m) {
+        set_err("NULL predictor");
+        return HMX_ERR_INVALID_ARG;
+    }
+    return guarded([&] {
+        check(hipDeviceSynchronize(), "sync");
+        if (params) check(hipMemcpy(m->w.p, params, kP * 4, hipMemcpyHostToDevice), "weights");
+        if (mean) check(hipMemcpy(m->mean.p, mean, 32, hipMemcpyHostToDevice), "mean");
+        if (scale) check(hipMemcpy(m->scale.p, scale, 32, hipMemcpyHostToDevice), "scale");
+        check(hipMemset(m->m.p, 0, kP * 4), "adam m");
+        check(hipMemset(m->v.p, 0, kP * 4), "adam v");
+        m->t = 0;
+    });
+}
+
+hmx_status hmx_mlp_get_params(hmx_mlp m, float* params, float* mean, float* scale) {
+    if (!m) {
+        set_err("NULL predictor");
+        return HMX_ERR_INVALID_ARG;
+    }
+    return guarded([&] {
+        check(hipDeviceSynchronize(), "sync");
+        if (params) check(hipMemcpy(params, m->w.p, kP * 4, hipMemcpyDeviceToHost), "weights");
+        if (mean) check(hipMemcpy(mean, m->mean.p, 32, hipMemcpyDeviceToHost), "mean");
+        if (scale) check(hipMemcpy(scale, m->scale.p, 32, hipMemcpyDeviceToHost), "scale");
+    });
+}
+
+hmx_status hmx_mlp_fit_normalization(hmx_mlp m, const float* X, int64_t n, void* stream) {
+    if (!m || !X || n < 1) {
+        set_err("invalid argument to hmx_mlp_fit_normalization");
+        return HMX_ERR_INVALID_ARG;
+    }
+    return guarded([&] {
+        check(mlp_norm(X, n, m->mean.as<float>(), m->scale.as<float>(), (hipStream_t)stream),
+              "normalization");
+    });
+}
+
+hmx_status hmx_mlp_forward(hmx_mlp m, const float* X, int64_t B, float* out, void* stream) {
+    if (!m || B < 0 || (B > 0 && (!X || !out))) {
+        set_err("invalid argument to hmx_mlp_forward");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (B == 0) return HMX_OK;
+    hipStream_t st = (hipStream_t)stream;
+    return guarded([&] {
+        ensure(m->act, (size_t)B * 193 * 4, st, "activations");
+        check(mlp_forward(m->w.as<float>(), m->mean.as<float>(), m->scale.as<float>(), X, B,
+                          m->act.as<float>(), st),
+              "mlp forward");
+        check(hipMemcpyAsync(out, m->act.as<float>() + (size_t)B * 192, (size_t)B * 4,
+                             hipMemcpyDeviceToDevice, st),
+              "output copy");
+    });
+}
+
+extern "C++" {
+namespace {
+// forward + backward on a device batch; loss_dev optional
+void mlp_step_grad(hmx_mlp_s* m, const float* X, const float* y, int64_t B, double q,
+                   float* grad, double* loss_dev, hipStream_t st) {
+    ensure(m->act, (size_t)B * 193 * 4, st, "activations");
+    ensure(m->scratch, mlp_grad_scratch_floats(B) * 4, st, "gradient scratch");
+    check(mlp_forward(m->w.as<float>(), m->mean.as<float>(), m->scale.as<float>(), X, B,
+                      m->act.as<float>(), st),
+          "mlp forward");
+    check(mlp_backward(m->w.as<float>(), m->mean.as<float>(), m->scale.as<float>(), X, y, B,
+                       (float)q, m->act.as<float>(), grad, m->scratch.as<float>(), loss_dev, st),
+          "mlp backward");
+}
+}  // namespace
+}  // extern "C++"
+
+hmx_status hmx_mlp_loss_grad(hmx_mlp m, const float* X, const float* y, int64_t B, double q,
+                             float* grad, double* loss, void* stream) {
+    if (!m || !X || !y || !grad || B < 1 || !(q > 0 && q < 1)) {
+        set_err("invalid argument to hmx_mlp_loss_grad");
+        return HMX_ERR_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    return guarded([&] {
+        ensure(m->loss, 8, st, "loss");
+        mlp_step_grad(m, X, y, B, q, grad, loss ? m->loss.as<double>() : nullptr, st);
+        if (loss) *loss = read_scalar(m->loss.as<double>(), st);
+    });
+}
+
+hmx_status hmx_mlp_adam(hmx_mlp m, const float* grad, double lr, double beta1, double beta2,
+                        double eps, void* stream) {
+    if (!m || !grad || !(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) ||
+        !(eps > 0)) {
+        set_err("invalid argument to hmx_mlp_adam");
+        return HMX_ERR_INVALID_ARG;
+    }
+    return guarded([&] {
+        m->t += 1;
+        check(mlp_adam(m->w.as<float>(), m->m.as<float>(), m->v.as<float>(), grad, m->t,
+                       (float)lr, (float)beta1, (float)beta2, (float)eps, (hipStream_t)stream),
+              "adam");
+    });
+}
+
+hmx_status hmx_mlp_train(hmx_mlp m, const float* X, const float* y, int64_t n,
+                         const int64_t* batch_idx, int64_t B, int32_t steps, double q, double lr,
+                         double* losses, void* stream) {
+    if (!m || !X || !y || n < 1 || !batch_idx || B < 1 || steps < 0 || !(q > 0 && q < 1) ||
+        !(lr >= 0)) {
+        set_err("invalid argument to hmx_mlp_train");
+        return HMX_ERR_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    return guarded([&] {
+        ensure(m->Xb, (size_t)B * 8 * 4, st, "batch features");
+        ensure(m->yb, (size_t)B * 4, st, "batch targets");
+        ensure(m->grad, (size_t)kP * 4, st, "gradient");
+        ensure(m->act, (size_t)B * 193 * 4, st, "activations");
+        ensure(m->scratch, mlp_grad_scratch_floats(B) * 4, st, "gradient scratch");
+        for (int32_t s = 0; s < steps; ++s) {
+            check(mlp_gather_batch(X, y, n, batch_idx + (int64_t)s * B, B, m->Xb.as<float>(),
+                                   m->yb.as<float>(), st),
+                  "batch gather");
+            mlp_step_grad(m, m->Xb.as<float>(), m->yb.as<float>(), B, q, m->grad.as<float>(),
+                          losses ? losses + s : nullptr, st);
+            m->t += 1;
+            check(mlp_adam(m->w.as<float>(), m->m.as<float>(), m->v.as<float>(),
+                           m->grad.as<float>(), m->t, (float)lr, 0.9f, 0.999f, 1e-8f, st),
+                  "adam");
+        }
+    });
+}
+
+hmx_status hmx_block_features(hmx_hmatrix h, float* features, float* ranks, int64_t* n_adm,
+                              void* stream) {
+    if (!h || !n_adm || (h->n_adm > 0 && !features)) {
+        set_err("invalid argument to hmx_block_features");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (*n_adm < h->n_adm) {
+        set_err("capacity %lld below %lld admissible leaves", (long long)*n_adm,
+                (long long)h->n_adm);
+        *n_adm = h->n_adm;
+        return HMX_ERR_INVALID_ARG;
+    }
+    *n_adm = h->n_adm;
+    return guarded([&] {
+        check(launch_features(h->adm.as<int4>(), h->adm_ids.as<int2>(), h->n_adm,
+                              h->bmin.as<double>(), h->bmax.as<double>(), h->d,
+                              kernel_length(h->kern), h->rank.as<int32_t>(), features, ranks,
+                              (hipStream_t)stream),
+              "features");
+    });
 }
 
 hmx_status hmx_destroy(hmx_hmatrix h) {

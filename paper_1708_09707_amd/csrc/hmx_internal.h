@@ -127,8 +127,8 @@ hipError_t launch_traverse_write(const int2* cur, int64_t ncur, const int32_t* n
                                  const int32_t* node_hi, const double* bmin, const double* bmax,
                                  int d, int leaf, double eta, const int64_t* block_offsets,
                                  int level, int2* next, int4* adm, int32_t* adm_level,
-                                 int64_t adm_base, int4* dense, int32_t* dense_level,
-                                 int64_t dense_base, hipStream_t st);
+                                 int2* adm_ids, int64_t adm_base, int4* dense,
+                                 int32_t* dense_level, int64_t dense_base, hipStream_t st);
 
 // leaf tiles (k_tree.hip): tile_of_point via leaf-start flags and a scan
 hipError_t launch_mark_leaves(int L, int leaf, const int32_t* node_lo, const int32_t* node_hi,
@@ -152,6 +152,9 @@ struct AcaArgs {
     int kmax;
     double eps, aca_eta, eps0;
     int fixed;
+    const int32_t* rtarget;  // per-block target ranks, or null (adaptive)
+    int one_shot;            // targets are run without the test, then judged by it
+    int cap_only;            // storage holds only the target: unfinished blocks get rank -1
     void* U;
     void* V;
     int32_t* rank;
@@ -173,7 +176,7 @@ struct Piece {
 };
 // per-block sizes: mode 0: m * mult, 1: n * mult, 2: m * n, 3: r * m, 4: r * n,
 // 5: r, 6: row tiles covered by tau (0 for an admissible leaf of rank 0),
-// 7: (m + n) * mult
+// 7: (m + n) * mult, 8: (m + n) * r; negative ranks count as 0 in 3, 4, 5
 hipError_t launch_extent(const int4* blocks, int64_t nb, int mode, int64_t mult,
                          const int32_t* rank, const int32_t* tile_of_point, int64_t* out,
                          hipStream_t st);
@@ -244,5 +247,39 @@ hipError_t launch_copy(void* dst, const void* src, int64_t n, int f64, hipStream
 hipError_t launch_fill_zero(void* dst, int64_t n, int f64, hipStream_t st);
 hipError_t launch_sub(void* out, const void* a, const void* b, int64_t n, int f64,
                       hipStream_t st);
+
+
+// learned rank sizing (k_mlp.hip): MLP 8 -> 64 -> 64 -> 64 -> 1 (ReLU), FP32
+int64_t mlp_nparams();
+size_t mlp_grad_scratch_floats(int64_t B);
+// act: B * (3 * 64 + 1) floats (hidden activations, then the outputs)
+hipError_t mlp_forward(const float* w, const float* mean, const float* scale, const float* X,
+                       int64_t B, float* act, hipStream_t st);
+hipError_t mlp_backward(const float* w, const float* mean, const float* scale, const float* X,
+                        const float* y, int64_t B, float q, const float* act, float* grad,
+                        float* scratch, double* loss, hipStream_t st);
+hipError_t mlp_adam(float* w, float* m, float* v, const float* g, int64_t t, float lr, float b1,
+                    float b2, float eps, hipStream_t st);
+hipError_t mlp_norm(const float* X, int64_t n, float* mean, float* scale, hipStream_t st);
+hipError_t mlp_gather_batch(const float* X, const float* y, int64_t n, const int64_t* idx,
+                            int64_t B, float* Xb, float* yb, hipStream_t st);
+hipError_t launch_features(const int4* blocks, const int2* ids, int64_t nb, const double* bmin,
+                           const double* bmax, int d, double ell, const int32_t* rank, float* F,
+                           float* y, hipStream_t st);
+hipError_t launch_rank_predict(const int4* blocks, const int2* ids, int64_t nb, const double* bmin,
+                               const double* bmax, int d, double ell, const float* w,
+                               const float* mean, const float* scale, int kmax, float* pred,
+                               int32_t* target, hipStream_t st);
+// fallback lists: flag[b] = rank[b] < 0 (int64, scanned by the caller into
+// positions pos), then the flagged blocks gathered in order
+hipError_t launch_fail_flags(const int32_t* rank, int64_t nb, int64_t* flag, hipStream_t st);
+hipError_t launch_gather_failed(const int32_t* rank, const int64_t* pos, int64_t nb,
+                                const int4* blocks, const int32_t* rt, int32_t* list,
+                                int4* blocks_out, int32_t* rt_out, hipStream_t st);
+// dst[list[i]] = src[i] (i32 / i64), or += for add != 0 (i32)
+hipError_t launch_scatter_i32(const int32_t* list, int64_t nl, const int32_t* src, int32_t* dst,
+                              int add, hipStream_t st);
+hipError_t launch_scatter_i64(const int32_t* list, int64_t nl, const int64_t* src, int64_t* dst,
+                              hipStream_t st);
 
 }  // namespace hmx

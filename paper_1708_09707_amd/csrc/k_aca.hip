@@ -12,6 +12,12 @@
 //   4. |S_r|_F^2 += 2 sum_{l<r} (u_r.u_l)(v_r.v_l) + |u_r|^2 |v_r|^2   in FP64
 //   5. stop if |u_r| |v_r| <= eps (1 - aca_eta) / (1 + eps) |S_r|_F
 //   6. next column pivot j = argmax over unused columns |(v_r)_j|
+// Learned rank sizing gives every block a predicted target: storage for that
+// many columns with the test in 5 applied every step (sizing form), or
+// exactly that many steps with the test applied to the last term only
+// (one-shot form).  A block that reaches its target unfinished continues
+// adaptively (the fallback), or, when its storage holds only the target,
+// reports rank -1 to be approximated again with k_max columns.
 // The first column is the sigma point nearest (FP64, no contraction) to the
 // centre of tau's bounding box, so the first cross runs through the block's
 // largest entries.
@@ -217,7 +223,8 @@ __global__ __launch_bounds__(kAcaThreads) void aca_kernel(
     const T* __restrict__ soa, const double* __restrict__ soa64, int64_t n, int d, KernelEval<T> K,
     const int4* __restrict__ blocks, int64_t nblocks, const int64_t* __restrict__ uoff,
     const int64_t* __restrict__ voff, int64_t ubase, int64_t vbase, int kmax, double eps,
-    double aca_eta, T eps0, int fixed,
+    double aca_eta, T eps0, int fixed, const int32_t* __restrict__ rtarget, int one_shot_mode,
+    int cap_only,
     T* __restrict__ Upool, T* __restrict__ Vpool, int32_t* __restrict__ rank_out,
     int32_t* __restrict__ steps_out) {
     extern __shared__ uint32_t smask[];
@@ -239,10 +246,35 @@ __global__ __launch_bounds__(kAcaThreads) void aca_kernel(
         for (int q = tid; q < mw + nw; q += kAcaThreads) smask[q] = 0u;
         __syncthreads();
 
+        // rtarget[b] > 0 bounds the block's columns to a predicted target.
+        // Sizing form (one_shot_mode = 0): the stopping test runs every step
+        // as in the adaptive method.  One-shot form: the target is reached
+        // without the test, which then judges the last term.  A block that
+        // reaches its target unfinished either continues adaptively (storage
+        // for k_max columns) or, with cap_only (storage for the target only),
+        // ends with rank -1 to be approximated again with k_max columns.
+        const bool sized = rtarget && rtarget[b] > 0;
+        bool one_shot = sized && one_shot_mode;
+        int target = sized ? (rtarget[b] < R ? rtarget[b] : R) : R;
+        bool refused = false;
+        double last_p = 0.0;  // |u_r|^2 |v_r|^2 of the last term
+
         int r = 0, ncols_used = 0, nfailed = 0, steps = 0;
         int j = first_column(soa64, n, d, bl, sh);
         double S2 = 0.0;
-        while (r < R) {
+        for (;;) {
+            if (r >= target) {
+                if (r >= R) break;
+                if (one_shot) {
+                    one_shot = false;
+                    if (sqrt(last_p) <= tol * sqrt(S2)) break;
+                }
+                if (cap_only) {
+                    refused = true;
+                    break;
+                }
+                target = R;
+            }
             // ---- step 1: residual column j into U[:, r] ----
             if (tid < r) sh.vec[tid] = V[(int64_t)tid * nc + j];
             if (tid == 0) cmask[j >> 5] |= 1u << (j & 31);
@@ -335,14 +367,15 @@ __global__ __launch_bounds__(kAcaThreads) void aca_kernel(
             cm = block_argmax(cm, sh);
             ++r;
             S2 += 2.0 * cross + nu2 * nv2;
+            last_p = nu2 * nv2;
             // ---- step 5: stopping criterion ----
-            if (!fixed && sqrt(nu2 * nv2) <= tol * sqrt(S2)) break;
+            if (!fixed && !one_shot && sqrt(last_p) <= tol * sqrt(S2)) break;
             // ---- step 6: next column pivot ----
             if (cm.idx == INT_MAX) break;
             j = cm.idx;
         }
         if (tid == 0) {
-            rank_out[b] = r;
+            rank_out[b] = refused ? -1 : r;
             if (steps_out) steps_out[b] = steps;
         }
         __syncthreads();
@@ -359,13 +392,13 @@ hipError_t launch_aca(const AcaArgs& a, int f64, hipStream_t st) {
         KernelEval<double> K(a.kern);
         hipLaunchKernelGGL(aca_kernel<double>, dim3(grid), dim3(kAcaThreads), lds, st,
                            (const double*)a.soa, a.soa64, a.n, a.d, K, a.blocks, a.nblocks, a.uoff, a.voff,
-                           a.ubase, a.vbase, a.kmax, a.eps, a.aca_eta, (double)a.eps0, a.fixed, (double*)a.U,
+                           a.ubase, a.vbase, a.kmax, a.eps, a.aca_eta, (double)a.eps0, a.fixed, a.rtarget, a.one_shot, a.cap_only, (double*)a.U,
                            (double*)a.V, a.rank, a.steps);
     } else {
         KernelEval<float> K(a.kern);
         hipLaunchKernelGGL(aca_kernel<float>, dim3(grid), dim3(kAcaThreads), lds, st,
                            (const float*)a.soa, a.soa64, a.n, a.d, K, a.blocks, a.nblocks, a.uoff, a.voff,
-                           a.ubase, a.vbase, a.kmax, a.eps, a.aca_eta, (float)a.eps0, a.fixed, (float*)a.U,
+                           a.ubase, a.vbase, a.kmax, a.eps, a.aca_eta, (float)a.eps0, a.fixed, a.rtarget, a.one_shot, a.cap_only, (float*)a.U,
                            (float*)a.V, a.rank, a.steps);
     }
     return hipGetLastError();

@@ -111,10 +111,12 @@ __global__ void extent_kernel(const int4* __restrict__ blocks, int64_t nb, int m
         case 0: v = m * mult; break;
         case 1: v = nc * mult; break;
         case 2: v = m * nc; break;
-        case 3: v = (int64_t)rank[b] * m; break;
-        case 4: v = (int64_t)rank[b] * nc; break;
-        case 5: v = rank[b]; break;
+        // ranks < 0 (blocks waiting for a fallback approximation) count as 0
+        case 3: v = rank[b] > 0 ? (int64_t)rank[b] * m : 0; break;
+        case 4: v = rank[b] > 0 ? (int64_t)rank[b] * nc : 0; break;
+        case 5: v = rank[b] > 0 ? rank[b] : 0; break;
         case 7: v = (m + nc) * mult; break;
+        case 8: v = (m + nc) * (int64_t)rank[b]; break;
         default:
             v = (rank && rank[b] == 0)
                     ? 0

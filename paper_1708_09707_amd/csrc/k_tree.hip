@@ -284,8 +284,9 @@ __global__ __launch_bounds__(kTravThreads) void traverse_write_kernel(
     const int32_t* __restrict__ hi, const double* __restrict__ bmin,
     const double* __restrict__ bmax, int d, int leaf, double eta,
     const int64_t* __restrict__ block_off, int level, int2* __restrict__ next,
-    int4* __restrict__ adm, int32_t* __restrict__ adm_level, int64_t adm_base,
-    int4* __restrict__ dense, int32_t* __restrict__ dense_level, int64_t dense_base) {
+    int4* __restrict__ adm, int32_t* __restrict__ adm_level, int2* __restrict__ adm_ids,
+    int64_t adm_base, int4* __restrict__ dense, int32_t* __restrict__ dense_level,
+    int64_t dense_base) {
     __shared__ int64_t sh[kScanThreads / 64 + 1];
     const int64_t nblk = gridDim.x;
     const int64_t base = blockIdx.x * (int64_t)kTravTile + threadIdx.x * (int64_t)kTravItems;
@@ -321,6 +322,7 @@ __global__ __launch_bounds__(kTravThreads) void traverse_write_kernel(
             if (cls[k] == 0) {
                 adm[adm_base + off[0]] = r;
                 adm_level[adm_base + off[0]] = level;
+                adm_ids[adm_base + off[0]] = ts[k];
                 off[0]++;
             } else {
                 dense[dense_base + off[2]] = r;
@@ -420,12 +422,12 @@ hipError_t launch_traverse_write(const int2* cur, int64_t ncur, const int32_t* n
                                  const int32_t* node_hi, const double* bmin, const double* bmax,
                                  int d, int leaf, double eta, const int64_t* block_offsets,
                                  int level, int2* next, int4* adm, int32_t* adm_level,
-                                 int64_t adm_base, int4* dense, int32_t* dense_level,
-                                 int64_t dense_base, hipStream_t st) {
+                                 int2* adm_ids, int64_t adm_base, int4* dense,
+                                 int32_t* dense_level, int64_t dense_base, hipStream_t st) {
     const int64_t nb = traverse_blocks(ncur);
     hipLaunchKernelGGL(traverse_write_kernel, dim3((unsigned)nb), dim3(kTravThreads), 0, st, cur,
                        ncur, node_lo, node_hi, bmin, bmax, d, leaf, eta, block_offsets, level,
-                       next, adm, adm_level, adm_base, dense, dense_level, dense_base);
+                       next, adm, adm_level, adm_ids, adm_base, dense, dense_level, dense_base);
     return hipGetLastError();
 }
 

@@ -20,7 +20,9 @@ HMX_OK, HMX_ERR_INVALID_ARG, HMX_ERR_OOM, HMX_ERR_DEVICE, HMX_ERR_NOT_CONVERGED,
     HMX_ERR_UNSUPPORTED = range(6)
 HMX_F64, HMX_F32, HMX_BF16 = 0, 1, 2
 HMX_GAUSSIAN, HMX_MATERN32, HMX_TEST_CONST, HMX_TEST_LOWRANK = 0, 1, 3, 4
-HMX_RANK_ADAPTIVE, HMX_RANK_FIXED = 0, 2
+HMX_RANK_ADAPTIVE, HMX_RANK_LEARNED, HMX_RANK_FIXED = 0, 1, 2
+HMX_MLP_NPARAMS, HMX_MLP_FEATURES = 8961, 8
+RANK_MODES = {"adaptive": HMX_RANK_ADAPTIVE, "learned": HMX_RANK_LEARNED, "fixed": HMX_RANK_FIXED}
 KERNELS = {"gaussian": HMX_GAUSSIAN, "matern32": HMX_MATERN32, "const": HMX_TEST_CONST,
            "lowrank": HMX_TEST_LOWRANK}
 DTYPES = {"f64": HMX_F64, "f32": HMX_F32, "bf16": HMX_BF16}
@@ -29,7 +31,10 @@ DTYPES = {"f64": HMX_F64, "f32": HMX_F32, "bf16": HMX_BF16}
 EXPORTS = ["hmx_params_default", "hmx_build", "hmx_matvec", "hmx_cg_solve", "hmx_get_partition",
            "hmx_get_boxes", "hmx_get_ranks", "hmx_get_factors", "hmx_get_stats",
            "hmx_profile_begin", "hmx_profile_end", "hmx_destroy", "hmx_trim",
-           "hmx_status_string", "hmx_last_error"]
+           "hmx_status_string", "hmx_last_error", "hmx_mlp_create", "hmx_mlp_destroy",
+           "hmx_mlp_set_params", "hmx_mlp_get_params", "hmx_mlp_fit_normalization",
+           "hmx_mlp_forward", "hmx_mlp_loss_grad", "hmx_mlp_adam", "hmx_mlp_train",
+           "hmx_block_features"]
 
 
 class hmx_kernel(C.Structure):
@@ -42,7 +47,8 @@ class hmx_params(C.Structure):
                 ("sigma2", C.c_double), ("compute_dtype", C.c_int), ("storage_dtype", C.c_int),
                 ("near_dtype", C.c_int),
                 ("rank_mode", C.c_int), ("aca_chunk_mb", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("aca_only", C.c_int32), ("mlp", C.c_void_p),
+                ("learned_one_shot", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class hmx_stats(C.Structure):
@@ -54,7 +60,9 @@ class hmx_stats(C.Structure):
                 ("near_entries", C.c_int64), ("aca_columns", C.c_int64),
                 ("aca_chunks", C.c_int64), ("near_entry_bytes", C.c_int32),
                 ("reserved1", C.c_int32), ("matvec_bytes", C.c_double), ("phase_ms", C.c_double * 8),
-                ("device_bytes", C.c_int64), ("level_sizes", C.c_int64 * 64)]
+                ("device_bytes", C.c_int64), ("level_sizes", C.c_int64 * 64),
+                ("aca_fallback", C.c_int64), ("aca_capacity", C.c_int64),
+                ("predict_ms", C.c_double)]
 
 
 class HmxError(RuntimeError):
@@ -99,6 +107,16 @@ def lib():
         L.hmx_trim.argtypes = [C.POINTER(i64)]
         L.hmx_profile_begin.argtypes = [P, i32]
         L.hmx_profile_end.argtypes = [P, P, C.POINTER(i32)]
+        L.hmx_mlp_create.argtypes = [P, C.POINTER(P)]
+        L.hmx_mlp_destroy.argtypes = [P]
+        L.hmx_mlp_set_params.argtypes = [P, P, P, P]
+        L.hmx_mlp_get_params.argtypes = [P, P, P, P]
+        L.hmx_mlp_fit_normalization.argtypes = [P, P, i64, P]
+        L.hmx_mlp_forward.argtypes = [P, P, i64, P, P]
+        L.hmx_mlp_loss_grad.argtypes = [P, P, P, i64, f64, P, C.POINTER(f64), P]
+        L.hmx_mlp_adam.argtypes = [P, P, f64, f64, f64, f64, P]
+        L.hmx_mlp_train.argtypes = [P, P, P, i64, P, i64, i32, f64, f64, P, P]
+        L.hmx_block_features.argtypes = [P, P, P, C.POINTER(i64), P]
         L.hmx_status_string.restype = C.c_char_p
         L.hmx_status_string.argtypes = [C.c_int]
         L.hmx_last_error.restype = C.c_char_p
@@ -141,6 +159,10 @@ def hmx_params_default(**overrides) -> hmx_params:
     for k, v in overrides.items():
         if k in ("compute_dtype", "storage_dtype", "near_dtype") and isinstance(v, str):
             v = DTYPES[v]
+        if k == "rank_mode" and isinstance(v, str):
+            v = RANK_MODES[v]
+        if k == "mlp":
+            v = v.handle if isinstance(v, RankMLP) else v
         setattr(p, k, v)
     if "compute_dtype" in overrides and "storage_dtype" not in overrides:
         p.storage_dtype = p.compute_dtype  # store in the compute precision unless asked
@@ -255,6 +277,151 @@ def hmx_trim() -> int:
     r = C.c_int64(0)
     _check(lib().hmx_trim(C.byref(r)))
     return r.value
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _np_f32(a, n):
+    a = np.ascontiguousarray(a, dtype=np.float32).reshape(-1)
+    if a.shape[0] != n:
+        raise ValueError("expected %d values, got %d" % (n, a.shape[0]))
+    return a
+
+
+def hmx_mlp_create(params=None):
+    h = C.c_void_p()
+    w = None if params is None else _np_f32(params, HMX_MLP_NPARAMS)
+    _check(lib().hmx_mlp_create(None if w is None else w.ctypes.data_as(C.c_void_p), C.byref(h)))
+    return h
+
+
+def hmx_mlp_destroy(h):
+    if h:
+        _check(lib().hmx_mlp_destroy(h))
+
+
+def hmx_mlp_set_params(h, params=None, mean=None, scale=None):
+    w = None if params is None else _np_f32(params, HMX_MLP_NPARAMS)
+    mu = None if mean is None else _np_f32(mean, HMX_MLP_FEATURES)
+    sc = None if scale is None else _np_f32(scale, HMX_MLP_FEATURES)
+    _check(lib().hmx_mlp_set_params(h, *[None if a is None else a.ctypes.data_as(C.c_void_p)
+                                         for a in (w, mu, sc)]))
+
+
+def hmx_mlp_get_params(h):
+    w = np.empty(HMX_MLP_NPARAMS, np.float32)
+    mu = np.empty(HMX_MLP_FEATURES, np.float32)
+    sc = np.empty(HMX_MLP_FEATURES, np.float32)
+    _check(lib().hmx_mlp_get_params(h, *[a.ctypes.data_as(C.c_void_p) for a in (w, mu, sc)]))
+    return w, mu, sc
+
+
+def _dev_f32(t, cols=None):
+    import torch
+    if not (t.is_cuda and t.is_contiguous() and t.dtype == torch.float32):
+        raise ValueError("expected a contiguous float32 device tensor")
+    if cols is not None and (t.dim() != 2 or t.shape[1] != cols):
+        raise ValueError("expected shape (B, %d)" % cols)
+    return t
+
+
+def hmx_mlp_fit_normalization(h, X, stream=None):
+    _dev_f32(X, HMX_MLP_FEATURES)
+    _check(lib().hmx_mlp_fit_normalization(h, _ptr(X), X.shape[0], _stream(stream)))
+
+
+def hmx_mlp_forward(h, X, out=None, stream=None):
+    import torch
+    _dev_f32(X, HMX_MLP_FEATURES)
+    if out is None:
+        out = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _check(lib().hmx_mlp_forward(h, _ptr(X), X.shape[0], _ptr(out), _stream(stream)))
+    return out
+
+
+def hmx_mlp_loss_grad(h, X, y, q=0.9, grad=None, stream=None):
+    """Returns (loss, grad tensor)."""
+    import torch
+    _dev_f32(X, HMX_MLP_FEATURES)
+    _dev_f32(y)
+    if grad is None:
+        grad = torch.empty(HMX_MLP_NPARAMS, dtype=torch.float32, device=X.device)
+    loss = C.c_double(0)
+    _check(lib().hmx_mlp_loss_grad(h, _ptr(X), _ptr(y), X.shape[0], float(q), _ptr(grad),
+                                   C.byref(loss), _stream(stream)))
+    return loss.value, grad
+
+
+def hmx_mlp_adam(h, grad, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _dev_f32(grad)
+    _check(lib().hmx_mlp_adam(h, _ptr(grad), float(lr), float(beta1), float(beta2), float(eps),
+                              _stream(stream)))
+
+
+def hmx_mlp_train(h, X, y, batch_idx, batch, steps, q=0.9, lr=1e-3, losses=None, stream=None):
+    import torch
+    _dev_f32(X, HMX_MLP_FEATURES)
+    _dev_f32(y)
+    if not (batch_idx.is_cuda and batch_idx.dtype == torch.int64 and batch_idx.is_contiguous()):
+        raise ValueError("batch_idx must be a contiguous int64 device tensor")
+    if batch_idx.numel() < int(batch) * int(steps):
+        raise ValueError("batch_idx holds fewer than batch * steps indices")
+    if losses is not None and (losses.dtype != torch.float64 or losses.numel() < steps):
+        raise ValueError("losses must be a float64 device tensor of >= steps entries")
+    _check(lib().hmx_mlp_train(h, _ptr(X), _ptr(y), X.shape[0], _ptr(batch_idx), int(batch),
+                               int(steps), float(q), float(lr), _ptr(losses), _stream(stream)))
+
+
+def hmx_block_features(h, with_ranks=True, stream=None):
+    """(features (n_adm, 8) float32, ranks (n_adm,) float32 or None) as device tensors."""
+    import torch
+    s = hmx_get_stats(h)
+    na = C.c_int64(s.n_adm)
+    F = torch.empty((max(s.n_adm, 1), HMX_MLP_FEATURES), dtype=torch.float32, device="cuda")
+    y = torch.empty(max(s.n_adm, 1), dtype=torch.float32, device="cuda") if with_ranks else None
+    _check(lib().hmx_block_features(h, _ptr(F), _ptr(y), C.byref(na), _stream(stream)))
+    return F[: na.value], (y[: na.value] if y is not None else None)
+
+
+class RankMLP:
+    """Owner of an hmx_mlp rank predictor."""
+
+    def __init__(self, params=None):
+        self.handle = hmx_mlp_create(params)
+
+    def set_params(self, params=None, mean=None, scale=None):
+        hmx_mlp_set_params(self.handle, params, mean, scale)
+
+    def get_params(self):
+        return hmx_mlp_get_params(self.handle)
+
+    def fit_normalization(self, X, stream=None):
+        hmx_mlp_fit_normalization(self.handle, X, stream)
+
+    def forward(self, X, stream=None):
+        return hmx_mlp_forward(self.handle, X, stream=stream)
+
+    def loss_grad(self, X, y, q=0.9, stream=None):
+        return hmx_mlp_loss_grad(self.handle, X, y, q, stream=stream)
+
+    def adam(self, grad, lr=1e-3, stream=None):
+        hmx_mlp_adam(self.handle, grad, lr, stream=stream)
+
+    def train(self, X, y, batch_idx, batch, steps, q=0.9, lr=1e-3, losses=None, stream=None):
+        hmx_mlp_train(self.handle, X, y, batch_idx, batch, steps, q, lr, losses, stream)
+
+    def close(self):
+        if self.handle:
+            hmx_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class HMatrix:

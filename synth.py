@@ -80,6 +80,31 @@ def sample_rows(n: int, k: int, seed: int) -> np.ndarray:
     return np.sort(g.choice(int(n), size=k, replace=False)).astype(np.int64)
 
 
+# Rank-predictor layer sizes (input, three hidden layers, output) and the
+# packing order of its parameters: W1, b1, W2, b2, W3, b3, W4, b4.
+MLP_LAYERS = (8, 64, 64, 64, 1)
+
+
+def mlp_init_params(seed: int) -> np.ndarray:
+    """Initial predictor weights: W ~ N(0, 2 / fan_in) (He), biases 0, float32."""
+    g = rng(seed)
+    parts = []
+    for fan_in, fan_out in zip(MLP_LAYERS[:-1], MLP_LAYERS[1:]):
+        parts.append(g.standard_normal(fan_out * fan_in) * np.sqrt(2.0 / fan_in))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def batch_indices(n: int, batch: int, steps: int, seed: int) -> np.ndarray:
+    """steps x batch sample indices, each step an independent draw without
+    replacement from [0, n) (with replacement when batch > n), int64."""
+    g = rng(seed)
+    out = np.empty((int(steps), int(batch)), np.int64)
+    for s in range(int(steps)):
+        out[s] = g.choice(int(n), size=int(batch), replace=int(batch) > int(n))
+    return out.reshape(-1)
+
+
 # Workload recipes (sizes, kernels, seeds).  Plain data, no arithmetic.
 WORKLOADS = {
     # small plain FP64 case, checked against the dense product
