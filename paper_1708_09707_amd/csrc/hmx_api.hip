@@ -491,6 +491,16 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
     const bool learned = h->prm.rank_mode == HMX_RANK_LEARNED;
     const bool aca_only = h->prm.aca_only != 0;
     if (h->n_adm > 0) {
+        // size classes by tree level: clusters at level l hold at most s_l
+        // points (s_0 = n, s_{l+1} = ceil(s_l / 2)); levels whose clusters can
+        // exceed kBigRows points form the 512-thread class
+        constexpr int64_t kBigRows = 4096;
+        int lvl_split = 0;
+        int64_t s_split = n;
+        while (s_split >= kBigRows) {
+            s_split = (s_split + 1) / 2;
+            ++lvl_split;
+        }
         const int64_t big = big_adm;
         const int words = (int)(2 * ((big + 31) / 32));
         if ((size_t)words * 4 > 64 * 1024) {
@@ -498,6 +508,7 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
                     (long long)big);
             throw Fail{HMX_ERR_UNSUPPORTED};
         }
+        const int small_words = (int)(2 * ((std::min(s_split, big) + 31) / 32));
         const int64_t budget_mb = h->prm.aca_chunk_mb > 0 ? h->prm.aca_chunk_mb : 8192;
         const int64_t budget = std::max<int64_t>(budget_mb * ((int64_t)1 << 20) / (int64_t)esz, 1);
         AcaArgs a{};
@@ -511,14 +522,20 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
         a.aca_eta = h->prm.aca_eta;
         a.eps0 = h->prm.aca_eps0 >= 0 ? h->prm.aca_eps0 : (f64 ? 1e-14 : 1e-7);
         a.fixed = h->prm.rank_mode == HMX_RANK_FIXED;
-        a.lds_words = std::max(words, 2);
+        a.big_words = std::max(words, 2);
+        a.small_words = std::max(small_words, 2);
+        DevBuf split;
+        alloc(split, 8, "class split");
 
         // one pass over blocks[0..nb): cap = per-block column capacity (null:
         // k_max), rt = one-shot targets (null: adaptive); exact offsets of the
         // blocks' factors in the pools go to ue_all / ve_all
-        auto pass = [&](const int4* blocks, int64_t nb, const int32_t* cap, const int32_t* rt,
-                        int one_shot, int cap_only, int32_t* rank, int32_t* steps,
-                        int64_t* ue_all, int64_t* ve_all) {
+        auto pass = [&](const int4* blocks, const int32_t* levels, int64_t nb, const int32_t* cap,
+                        const int32_t* rt, int one_shot, int cap_only, int32_t* rank,
+                        int32_t* steps, int64_t* ue_all, int64_t* ve_all) {
+            check(launch_level_split(levels, nb, lvl_split, split.as<int64_t>(), st),
+                  "class split");
+            const int64_t nbig_all = read_scalar(split.as<int64_t>(), st);
             DevBuf cu, cv, cc, Ucap, Vcap;
             alloc(cu, (nb + 1) * 8, "U capacity offsets");
             alloc(cv, (nb + 1) * 8, "V capacity offsets");
@@ -575,6 +592,7 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
                 a.ubase = hcu[k];
                 a.vbase = hcv[k];
                 a.rtarget = rt ? rt + b0 : nullptr;
+                a.nbig = std::max<int64_t>(0, std::min(nbig_all - b0, nbk));
                 a.rank = rank + b0;
                 a.steps = steps + b0;
                 check(launch_aca(a, f64, st), "aca");
@@ -605,8 +623,9 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
         };
 
         if (!learned) {
-            pass(h->adm.as<int4>(), h->n_adm, nullptr, nullptr, 0, 0, h->rank.as<int32_t>(),
-                 h->steps.as<int32_t>(), uoff_ex.as<int64_t>(), h->voff.as<int64_t>());
+            pass(h->adm.as<int4>(), h->adm_level.as<int32_t>(), h->n_adm, nullptr, nullptr, 0, 0,
+                 h->rank.as<int32_t>(), h->steps.as<int32_t>(), uoff_ex.as<int64_t>(),
+                 h->voff.as<int64_t>());
         } else {
             // learned sizing: predicted targets, a pass with storage of that
             // size, then the blocks left unfinished again with k_max columns
@@ -625,9 +644,9 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
                   "rank prediction");
             check(hipStreamSynchronize(st), "prediction sync");
             S.predict_ms = ms_since(tp);
-            pass(h->adm.as<int4>(), h->n_adm, rt.as<int32_t>(), rt.as<int32_t>(), one_shot, 1,
-                 h->rank.as<int32_t>(), h->steps.as<int32_t>(), uoff_ex.as<int64_t>(),
-                 h->voff.as<int64_t>());
+            pass(h->adm.as<int4>(), h->adm_level.as<int32_t>(), h->n_adm, rt.as<int32_t>(),
+                 rt.as<int32_t>(), one_shot, 1, h->rank.as<int32_t>(), h->steps.as<int32_t>(),
+                 uoff_ex.as<int64_t>(), h->voff.as<int64_t>());
             DevBuf flag;
             alloc(flag, (h->n_adm + 1) * 8, "fallback flags");
             check(launch_fail_flags(h->rank.as<int32_t>(), h->n_adm, flag.as<int64_t>(), st),
@@ -635,22 +654,23 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
             const int64_t nfb = scan(flag.as<int64_t>(), h->n_adm);
             S.aca_fallback = nfb;
             if (nfb > 0) {
-                DevBuf list, bfb, rtfb, rkfb, stfb, uefb, vefb;
+                DevBuf list, bfb, lvfb, rtfb, rkfb, stfb, uefb, vefb;
                 alloc(list, nfb * 4, "fallback list");
                 alloc(bfb, nfb * sizeof(int4), "fallback blocks");
+                alloc(lvfb, nfb * 4, "fallback levels");
                 alloc(rtfb, nfb * 4, "fallback targets");
                 alloc(rkfb, nfb * 4, "fallback ranks");
                 alloc(stfb, nfb * 4, "fallback steps");
                 alloc(uefb, (nfb + 1) * 8, "fallback U offsets");
                 alloc(vefb, (nfb + 1) * 8, "fallback V offsets");
                 check(launch_gather_failed(h->rank.as<int32_t>(), flag.as<int64_t>(), h->n_adm,
-                                           h->adm.as<int4>(), rt.as<int32_t>(),
-                                           list.as<int32_t>(), bfb.as<int4>(),
-                                           rtfb.as<int32_t>(), st),
+                                           h->adm.as<int4>(), h->adm_level.as<int32_t>(),
+                                           rt.as<int32_t>(), list.as<int32_t>(), bfb.as<int4>(),
+                                           lvfb.as<int32_t>(), rtfb.as<int32_t>(), st),
                       "fallback gather");
-                pass(bfb.as<int4>(), nfb, nullptr, one_shot ? rtfb.as<int32_t>() : nullptr,
-                     one_shot, 0, rkfb.as<int32_t>(), stfb.as<int32_t>(), uefb.as<int64_t>(),
-                     vefb.as<int64_t>());
+                pass(bfb.as<int4>(), lvfb.as<int32_t>(), nfb, nullptr,
+                     one_shot ? rtfb.as<int32_t>() : nullptr, one_shot, 0, rkfb.as<int32_t>(),
+                     stfb.as<int32_t>(), uefb.as<int64_t>(), vefb.as<int64_t>());
                 const int32_t* li = list.as<int32_t>();
                 check(launch_scatter_i32(li, nfb, rkfb.as<int32_t>(), h->rank.as<int32_t>(), 0,
                                          st),

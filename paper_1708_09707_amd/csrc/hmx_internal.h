@@ -159,9 +159,16 @@ struct AcaArgs {
     void* V;
     int32_t* rank;
     int32_t* steps;
-    int lds_words;  // used-row + used-col bitmask words reserved per workgroup
+    // size classes: blocks [0, nbig) (upper tree levels) run in 512-thread
+    // workgroups, the rest in 256-thread ones; each class reserves the
+    // used-row + used-col bitmask words of its largest block
+    int64_t nbig;
+    int big_words, small_words;
 };
 hipError_t launch_aca(const AcaArgs& a, int f64, hipStream_t st);
+// *out = first index with level[index] >= lvl in the non-decreasing level[0..nb)
+hipError_t launch_level_split(const int32_t* level, int64_t nb, int lvl, int64_t* out,
+                              hipStream_t st);
 
 // near field and matvec (k_mvp.hip)
 // A piece is the part of one leaf block inside one row tile (leaf cluster);
@@ -274,8 +281,9 @@ hipError_t launch_rank_predict(const int4* blocks, const int2* ids, int64_t nb, 
 // positions pos), then the flagged blocks gathered in order
 hipError_t launch_fail_flags(const int32_t* rank, int64_t nb, int64_t* flag, hipStream_t st);
 hipError_t launch_gather_failed(const int32_t* rank, const int64_t* pos, int64_t nb,
-                                const int4* blocks, const int32_t* rt, int32_t* list,
-                                int4* blocks_out, int32_t* rt_out, hipStream_t st);
+                                const int4* blocks, const int32_t* level, const int32_t* rt,
+                                int32_t* list, int4* blocks_out, int32_t* level_out,
+                                int32_t* rt_out, hipStream_t st);
 // dst[list[i]] = src[i] (i32 / i64), or += for add != 0 (i32)
 hipError_t launch_scatter_i32(const int32_t* list, int64_t nl, const int32_t* src, int32_t* dst,
                               int add, hipStream_t st);

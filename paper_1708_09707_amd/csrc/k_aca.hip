@@ -1,8 +1,10 @@
 // Batched adaptive cross approximation (Algorithm 2, Section 5.4.1).
 //
-// One workgroup (4 waves) per admissible block, each running its own rank
-// loop, so blocks stop independently (no global "voting" bounded by the
-// slowest block).  Per step r:
+// One workgroup per admissible block, each running its own rank loop, so
+// blocks stop independently (no global "voting" bounded by the slowest
+// block).  Blocks of the upper tree levels (many rows) get 512-thread
+// workgroups, the rest 256; the canonical leaf order is level order, so the
+// large class is a prefix of every block list.  Per step r:
 //   1. residual column  u^ = A[:, j] - sum_{l<r} u_l (v_l)_j   (rows over threads)
 //   2. row pivot        i  = argmax over unused rows |u^_i| (lowest index on ties)
 //      a column whose largest residual entry is <= eps0 times the column's own
@@ -12,6 +14,9 @@
 //   4. |S_r|_F^2 += 2 sum_{l<r} (u_r.u_l)(v_r.v_l) + |u_r|^2 |v_r|^2   in FP64
 //   5. stop if |u_r| |v_r| <= eps (1 - aca_eta) / (1 + eps) |S_r|_F
 //   6. next column pivot j = argmax over unused columns |(v_r)_j|
+// The inner products of step 4 are computed by the whole workgroup, eight
+// previous columns per pass, in FP64; the U products ride along with the
+// normalisation of u_r.
 // Learned rank sizing gives every block a predicted target: storage for that
 // many columns with the test in 5 applied every step (sizing form), or
 // exactly that many steps with the test applied to the last term only
@@ -21,7 +26,7 @@
 // The first column is the sigma point nearest (FP64, no contraction) to the
 // centre of tau's bounding box, so the first cross runs through the block's
 // largest entries.
-// Used rows/columns are bitmasks in LDS.  U (m x kmax) and V (n x kmax) are
+// Used rows/columns are bitmasks in LDS.  U (m x cap) and V (n x cap) are
 // column-major in a capacity pool; column r of U doubles as the scratch for
 // the residual column.  All reductions have a fixed tree, so the result is
 // bit-reproducible from run to run.
@@ -33,8 +38,13 @@ namespace hmx {
 
 namespace {
 
-constexpr int kAcaThreads = 256;
-constexpr int kAcaWaves = kAcaThreads / kWave;
+constexpr int kDotCols = 8;     // previous columns per inner-product pass
+constexpr int kBigThreads = 512;  // workgroup size of the upper-level class
+
+template <int NT>
+constexpr int dot_cols() {
+    return kDotCols;
+}
 
 template <typename T>
 struct Arg {
@@ -61,20 +71,23 @@ __device__ __forceinline__ Arg<T> wave_argmax(Arg<T> a) {
     return a;
 }
 
-template <typename T>
+template <typename T, int NW>
 struct AcaShared {
-    T vec[kMaxRankCap];      // broadcast row of V (step 1) / row of U (step 3)
-    T abest[kAcaWaves];
-    T aval[kAcaWaves];
-    int aidx[kAcaWaves];
-    double dsum[3][kAcaWaves];
-    int imin[kAcaWaves];
-    double dkey[kAcaWaves];
-    int dkidx[kAcaWaves];
+    T vec[kMaxRankCap];         // broadcast row of V (step 1) / row of U (step 3)
+    double gu[kMaxRankCap];     // u_r . u_l
+    double gv[kMaxRankCap];     // v_r . v_l
+    double part[NW][kDotCols];  // per-wave partial inner products
+    T abest[NW];
+    T aval[NW];
+    int aidx[NW];
+    double dsum[2][NW];
+    int imin[NW];
+    double dkey[NW];
+    int dkidx[NW];
 };
 
-template <typename T>
-__device__ Arg<T> block_argmax(Arg<T> a, AcaShared<T>& sh) {
+template <typename T, int NW>
+__device__ Arg<T> block_argmax(Arg<T> a, AcaShared<T, NW>& sh) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     a = wave_argmax(a);
     if (lane == 0) {
@@ -84,7 +97,7 @@ __device__ Arg<T> block_argmax(Arg<T> a, AcaShared<T>& sh) {
     }
     __syncthreads();
     Arg<T> r{sh.abest[0], sh.aidx[0], sh.aval[0]};
-    for (int q = 1; q < kAcaWaves; ++q) {
+    for (int q = 1; q < NW; ++q) {
         Arg<T> b{sh.abest[q], sh.aidx[q], sh.aval[q]};
         arg_combine(r, b);
     }
@@ -92,32 +105,21 @@ __device__ Arg<T> block_argmax(Arg<T> a, AcaShared<T>& sh) {
     return r;
 }
 
-// sums of three doubles across the workgroup, same tree on every thread
-template <typename T>
-__device__ void block_sum3(double& a, double& b, double& c, AcaShared<T>& sh) {
+// sum of a double across the workgroup, same tree on every thread
+template <typename T, int NW>
+__device__ double block_sum(double a, AcaShared<T, NW>& sh, int slot) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     a = wave_sum(a);
-    b = wave_sum(b);
-    c = wave_sum(c);
-    if (lane == 0) {
-        sh.dsum[0][w] = a;
-        sh.dsum[1][w] = b;
-        sh.dsum[2][w] = c;
-    }
+    if (lane == 0) sh.dsum[slot][w] = a;
     __syncthreads();
-    a = sh.dsum[0][0];
-    b = sh.dsum[1][0];
-    c = sh.dsum[2][0];
-    for (int q = 1; q < kAcaWaves; ++q) {
-        a += sh.dsum[0][q];
-        b += sh.dsum[1][q];
-        c += sh.dsum[2][q];
-    }
+    double s = sh.dsum[slot][0];
+    for (int q = 1; q < NW; ++q) s += sh.dsum[slot][q];
     __syncthreads();
+    return s;
 }
 
-template <typename T>
-__device__ int block_min_int(int v, AcaShared<T>& sh) {
+template <typename T, int NW>
+__device__ int block_min_int(int v, AcaShared<T, NW>& sh) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -127,14 +129,14 @@ __device__ int block_min_int(int v, AcaShared<T>& sh) {
     if (lane == 0) sh.imin[w] = v;
     __syncthreads();
     int r = sh.imin[0];
-    for (int q = 1; q < kAcaWaves; ++q) r = sh.imin[q] < r ? sh.imin[q] : r;
+    for (int q = 1; q < NW; ++q) r = sh.imin[q] < r ? sh.imin[q] : r;
     __syncthreads();
     return r;
 }
 
 // min (op = 0) or max (op = 1) of a double across the workgroup
-template <typename T>
-__device__ double block_minmax(double v, int op, AcaShared<T>& sh) {
+template <typename T, int NW>
+__device__ double block_minmax(double v, int op, AcaShared<T, NW>& sh) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -144,15 +146,15 @@ __device__ double block_minmax(double v, int op, AcaShared<T>& sh) {
     if (lane == 0) sh.dkey[w] = v;
     __syncthreads();
     double r = sh.dkey[0];
-    for (int q = 1; q < kAcaWaves; ++q) r = op ? (sh.dkey[q] > r ? sh.dkey[q] : r)
-                                               : (sh.dkey[q] < r ? sh.dkey[q] : r);
+    for (int q = 1; q < NW; ++q) r = op ? (sh.dkey[q] > r ? sh.dkey[q] : r)
+                                        : (sh.dkey[q] < r ? sh.dkey[q] : r);
     __syncthreads();
     return r;
 }
 
 // index of the smallest key (lowest index on ties)
-template <typename T>
-__device__ int block_argmin_f64(double key, int idx, AcaShared<T>& sh) {
+template <typename T, int NW>
+__device__ int block_argmin_f64(double key, int idx, AcaShared<T, NW>& sh) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -170,7 +172,7 @@ __device__ int block_argmin_f64(double key, int idx, AcaShared<T>& sh) {
     __syncthreads();
     double bk = sh.dkey[0];
     int bi = sh.dkidx[0];
-    for (int q = 1; q < kAcaWaves; ++q)
+    for (int q = 1; q < NW; ++q)
         if (sh.dkey[q] < bk || (sh.dkey[q] == bk && sh.dkidx[q] < bi)) {
             bk = sh.dkey[q];
             bi = sh.dkidx[q];
@@ -179,17 +181,36 @@ __device__ int block_argmin_f64(double key, int idx, AcaShared<T>& sh) {
     return bi;
 }
 
+// reduce acc[0..DC) across the workgroup into out[0..nk) (fixed tree)
+template <int DC, typename T, int NW>
+__device__ void block_sum_cols(double* acc, int nk, double* out, AcaShared<T, NW>& sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < DC; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < DC; ++k) sh.part[w][k] = acc[k];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nk) {
+        double s = sh.part[0][threadIdx.x];
+        for (int q = 1; q < NW; ++q) s += sh.part[q][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
 // first column: the sigma point nearest to the centre 0.5 (a + b) of tau's
 // bounding box, squared distance summed in dimension order, all in FP64
 // without contraction
-template <typename T>
+template <typename T, int NT>
 __device__ int first_column(const double* __restrict__ soa64, int64_t n, int d, int4 bl,
-                            AcaShared<T>& sh) {
+                            AcaShared<T, NT / kWave>& sh) {
     const int m = bl.y - bl.x, nc = bl.w - bl.z;
     double c[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < d; ++k) {
         double mn = INFINITY, mx = -INFINITY;
-        for (int i = threadIdx.x; i < m; i += kAcaThreads) {
+        for (int i = threadIdx.x; i < m; i += NT) {
             const double v = soa64[(int64_t)k * n + bl.x + i];
             mn = v < mn ? v : mn;
             mx = v > mx ? v : mx;
@@ -200,7 +221,7 @@ __device__ int first_column(const double* __restrict__ soa64, int64_t n, int d, 
     }
     double best = INFINITY;
     int bi = INT_MAX;
-    for (int q = threadIdx.x; q < nc; q += kAcaThreads) {
+    for (int q = threadIdx.x; q < nc; q += NT) {
         double s = 0.0;
         for (int k = 0; k < d; ++k) {
             const double t = __dsub_rn(soa64[(int64_t)k * n + bl.z + q], c[k]);
@@ -218,18 +239,19 @@ __device__ __forceinline__ bool bit_get(const uint32_t* m, int i) {
     return (m[i >> 5] >> (i & 31)) & 1u;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kAcaThreads) void aca_kernel(
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void aca_kernel(
     const T* __restrict__ soa, const double* __restrict__ soa64, int64_t n, int d, KernelEval<T> K,
     const int4* __restrict__ blocks, int64_t nblocks, const int64_t* __restrict__ uoff,
     const int64_t* __restrict__ voff, int64_t ubase, int64_t vbase, int kmax, double eps,
     double aca_eta, T eps0, int fixed, const int32_t* __restrict__ rtarget, int one_shot_mode,
-    int cap_only,
-    T* __restrict__ Upool, T* __restrict__ Vpool, int32_t* __restrict__ rank_out,
-    int32_t* __restrict__ steps_out) {
+    int cap_only, int lds_words, T* __restrict__ Upool, T* __restrict__ Vpool,
+    int32_t* __restrict__ rank_out, int32_t* __restrict__ steps_out) {
+    constexpr int NW = NT / kWave;
+    constexpr int DC = dot_cols<NT>();
     extern __shared__ uint32_t smask[];
-    __shared__ AcaShared<T> sh;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    __shared__ AcaShared<T, NW> sh;
+    const int tid = threadIdx.x;
     const double tol = eps * (1.0 - aca_eta) / (1.0 + eps);
 
     for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
@@ -241,9 +263,16 @@ __global__ __launch_bounds__(kAcaThreads) void aca_kernel(
         T* __restrict__ U = Upool + (uoff[b] - ubase);
         T* __restrict__ V = Vpool + (voff[b] - vbase);
         const int mw = (m + 31) >> 5, nw = (nc + 31) >> 5;
+        if (mw + nw > lds_words) {  // outside this launch's size class (never by construction)
+            if (tid == 0) {
+                rank_out[b] = 0;
+                if (steps_out) steps_out[b] = 0;
+            }
+            continue;
+        }
         uint32_t* rmask = smask;
         uint32_t* cmask = smask + mw;
-        for (int q = tid; q < mw + nw; q += kAcaThreads) smask[q] = 0u;
+        for (int q = tid; q < mw + nw; q += NT) smask[q] = 0u;
         __syncthreads();
 
         // rtarget[b] > 0 bounds the block's columns to a predicted target.
@@ -260,7 +289,7 @@ __global__ __launch_bounds__(kAcaThreads) void aca_kernel(
         double last_p = 0.0;  // |u_r|^2 |v_r|^2 of the last term
 
         int r = 0, ncols_used = 0, nfailed = 0, steps = 0;
-        int j = first_column(soa64, n, d, bl, sh);
+        int j = first_column<T, NT>(soa64, n, d, bl, sh);
         double S2 = 0.0;
         for (;;) {
             if (r >= target) {
@@ -285,7 +314,7 @@ __global__ __launch_bounds__(kAcaThreads) void aca_kernel(
             load_pt(soa, n, d, (int64_t)bl.z + j, yj);
             Arg<T> am{(T)-1, INT_MAX, (T)0};
             double colmax = 0.0;
-            for (int i = tid; i < m; i += kAcaThreads) {
+            for (int i = tid; i < m; i += NT) {
                 T xi[3];
                 load_pt(soa, n, d, (int64_t)bl.x + i, xi);
                 T a = phi(K, xi, yj, d);
@@ -307,7 +336,7 @@ __global__ __launch_bounds__(kAcaThreads) void aca_kernel(
                 ++nfailed;
                 if (ncols_used >= nc || nfailed >= kmax) break;
                 int cand = INT_MAX;
-                for (int q = tid; q < nw; q += kAcaThreads) {
+                for (int q = tid; q < nw; q += NT) {
                     const uint32_t word = cmask[q];
                     if (word != 0xffffffffu) {
                         const int c = (q << 5) + __ffs(~word) - 1;
@@ -321,13 +350,29 @@ __global__ __launch_bounds__(kAcaThreads) void aca_kernel(
             }
             const int ip = am.idx;
             const T piv = am.val;
-            // ---- step 3a: normalise u_r ----
+            // ---- step 3a: normalise u_r; with it, u_r . u_l for l < r ----
             double nu2 = 0.0;
-            for (int i = tid; i < m; i += kAcaThreads) {
-                const T u = U[(int64_t)r * m + i] / piv;
-                U[(int64_t)r * m + i] = u;
-                nu2 += (double)u * (double)u;
+            T* __restrict__ Ur = U + (int64_t)r * m;
+            for (int c0 = 0; c0 == 0 || c0 < r; c0 += DC) {
+                const int nk = r - c0 < DC ? r - c0 : DC;
+                const T* __restrict__ Uc = U + (int64_t)c0 * m;
+                double acc[DC];
+#pragma unroll
+                for (int k = 0; k < DC; ++k) acc[k] = 0.0;
+                for (int i = tid; i < m; i += NT) {
+                    T u = Ur[i];
+                    if (c0 == 0) {
+                        u = u / piv;
+                        Ur[i] = u;
+                        nu2 += (double)u * (double)u;
+                    }
+#pragma unroll
+                    for (int k = 0; k < DC; ++k)
+                        if (k < nk) acc[k] += (double)u * (double)Uc[k * m + i];
+                }
+                if (nk > 0) block_sum_cols<DC>(acc, nk, sh.gu + c0, sh);
             }
+            nu2 = block_sum(nu2, sh, 0);
             if (tid < r) sh.vec[tid] = U[(int64_t)tid * m + ip];
             if (tid == 0) rmask[ip >> 5] |= 1u << (ip & 31);
             __syncthreads();
@@ -336,7 +381,7 @@ __global__ __launch_bounds__(kAcaThreads) void aca_kernel(
             load_pt(soa, n, d, (int64_t)bl.x + ip, xp);
             double nv2 = 0.0;
             Arg<T> cm{(T)-1, INT_MAX, (T)0};
-            for (int q = tid; q < nc; q += kAcaThreads) {
+            for (int q = tid; q < nc; q += NT) {
                 T yq[3];
                 load_pt(soa, n, d, (int64_t)bl.z + q, yq);
                 T a = phi(K, xp, yq, d);
@@ -350,21 +395,26 @@ __global__ __launch_bounds__(kAcaThreads) void aca_kernel(
                     cm.val = a;
                 }
             }
-            __syncthreads();
-            // ---- step 4: cross terms (u_r.u_l)(v_r.v_l), one wave per l ----
-            double cross = 0.0;
-            for (int l = w; l < r; l += kAcaWaves) {
-                double du = 0.0, dv = 0.0;
-                for (int i = lane; i < m; i += kWave)
-                    du += (double)U[(int64_t)r * m + i] * (double)U[(int64_t)l * m + i];
-                for (int q = lane; q < nc; q += kWave)
-                    dv += (double)V[(int64_t)r * nc + q] * (double)V[(int64_t)l * nc + q];
-                du = wave_sum(du);
-                dv = wave_sum(dv);
-                if (lane == 0) cross += du * dv;
-            }
-            block_sum3(nu2, nv2, cross, sh);
+            nv2 = block_sum(nv2, sh, 1);
             cm = block_argmax(cm, sh);
+            // ---- step 4: v_r . v_l for l < r, then the norm update ----
+            const T* __restrict__ Vr = V + (int64_t)r * nc;
+            for (int c0 = 0; c0 < r; c0 += DC) {
+                const int nk = r - c0 < DC ? r - c0 : DC;
+                const T* __restrict__ Vc = V + (int64_t)c0 * nc;
+                double acc[DC];
+#pragma unroll
+                for (int k = 0; k < DC; ++k) acc[k] = 0.0;
+                for (int q = tid; q < nc; q += NT) {
+                    const double v = (double)Vr[q];
+#pragma unroll
+                    for (int k = 0; k < DC; ++k)
+                        if (k < nk) acc[k] += v * (double)Vc[k * nc + q];
+                }
+                block_sum_cols<DC>(acc, nk, sh.gv + c0, sh);
+            }
+            double cross = 0.0;
+            for (int l = 0; l < r; ++l) cross += sh.gu[l] * sh.gv[l];
             ++r;
             S2 += 2.0 * cross + nu2 * nv2;
             last_p = nu2 * nv2;
@@ -382,24 +432,53 @@ __global__ __launch_bounds__(kAcaThreads) void aca_kernel(
     }
 }
 
+template <typename T, int NT>
+void launch_class(const AcaArgs& a, int64_t b0, int64_t nb, int lds_words, hipStream_t st) {
+    if (nb <= 0) return;
+    const unsigned grid = (unsigned)(nb < 0x7fffffff ? nb : 0x7fffffff);
+    KernelEval<T> K(a.kern);
+    hipLaunchKernelGGL((aca_kernel<T, NT>), dim3(grid), dim3(NT),
+                       (size_t)lds_words * sizeof(uint32_t), st, (const T*)a.soa, a.soa64, a.n,
+                       a.d, K, a.blocks + b0, nb, a.uoff + b0, a.voff + b0, a.ubase, a.vbase,
+                       a.kmax, a.eps, a.aca_eta, (T)a.eps0, a.fixed,
+                       a.rtarget ? a.rtarget + b0 : nullptr, a.one_shot, a.cap_only, lds_words,
+                       (T*)a.U, (T*)a.V, a.rank + b0, a.steps ? a.steps + b0 : nullptr);
+}
+
+// first index b with level[b] >= lvl in the non-decreasing level[0..nb)
+__global__ void level_split_kernel(const int32_t* __restrict__ level, int64_t nb, int lvl,
+                                   int64_t* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t lo = 0, hi = nb;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (level[mid] < lvl)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    *out = lo;
+}
+
 }  // namespace
 
+hipError_t launch_level_split(const int32_t* level, int64_t nb, int lvl, int64_t* out,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(level_split_kernel, dim3(1), dim3(64), 0, st, level, nb, lvl, out);
+    return hipGetLastError();
+}
+
+// blocks [0, nbig) run in kBigThreads-thread workgroups with big_words LDS mask
+// words, the rest in 256-thread workgroups with small_words
 hipError_t launch_aca(const AcaArgs& a, int f64, hipStream_t st) {
     if (a.nblocks == 0) return hipSuccess;
-    const unsigned grid = (unsigned)(a.nblocks < 0x7fffffff ? a.nblocks : 0x7fffffff);
-    const size_t lds = (size_t)a.lds_words * sizeof(uint32_t);
+    const int64_t nbig = a.nbig < a.nblocks ? a.nbig : a.nblocks;
     if (f64) {
-        KernelEval<double> K(a.kern);
-        hipLaunchKernelGGL(aca_kernel<double>, dim3(grid), dim3(kAcaThreads), lds, st,
-                           (const double*)a.soa, a.soa64, a.n, a.d, K, a.blocks, a.nblocks, a.uoff, a.voff,
-                           a.ubase, a.vbase, a.kmax, a.eps, a.aca_eta, (double)a.eps0, a.fixed, a.rtarget, a.one_shot, a.cap_only, (double*)a.U,
-                           (double*)a.V, a.rank, a.steps);
+        launch_class<double, kBigThreads>(a, 0, nbig, a.big_words, st);
+        launch_class<double, 256>(a, nbig, a.nblocks - nbig, a.small_words, st);
     } else {
-        KernelEval<float> K(a.kern);
-        hipLaunchKernelGGL(aca_kernel<float>, dim3(grid), dim3(kAcaThreads), lds, st,
-                           (const float*)a.soa, a.soa64, a.n, a.d, K, a.blocks, a.nblocks, a.uoff, a.voff,
-                           a.ubase, a.vbase, a.kmax, a.eps, a.aca_eta, (float)a.eps0, a.fixed, a.rtarget, a.one_shot, a.cap_only, (float*)a.U,
-                           (float*)a.V, a.rank, a.steps);
+        launch_class<float, kBigThreads>(a, 0, nbig, a.big_words, st);
+        launch_class<float, 256>(a, nbig, a.nblocks - nbig, a.small_words, st);
     }
     return hipGetLastError();
 }

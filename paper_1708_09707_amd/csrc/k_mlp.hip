@@ -282,13 +282,17 @@ __global__ void fail_flags_kernel(const int32_t* __restrict__ rank, int64_t nb,
 __global__ void gather_failed_kernel(const int32_t* __restrict__ rank,
                                      const int64_t* __restrict__ pos, int64_t nb,
                                      const int4* __restrict__ blocks,
+                                     const int32_t* __restrict__ level,
                                      const int32_t* __restrict__ rt, int32_t* __restrict__ list,
-                                     int4* __restrict__ blocks_out, int32_t* __restrict__ rt_out) {
+                                     int4* __restrict__ blocks_out,
+                                     int32_t* __restrict__ level_out,
+                                     int32_t* __restrict__ rt_out) {
     const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (b >= nb || rank[b] >= 0) return;
     const int64_t i = pos[b];
     list[i] = (int32_t)b;
     blocks_out[i] = blocks[b];
+    level_out[i] = level[b];
     rt_out[i] = rt[b];
 }
 
@@ -430,11 +434,12 @@ hipError_t launch_fail_flags(const int32_t* rank, int64_t nb, int64_t* flag, hip
 }
 
 hipError_t launch_gather_failed(const int32_t* rank, const int64_t* pos, int64_t nb,
-                                const int4* blocks, const int32_t* rt, int32_t* list,
-                                int4* blocks_out, int32_t* rt_out, hipStream_t st) {
+                                const int4* blocks, const int32_t* level, const int32_t* rt,
+                                int32_t* list, int4* blocks_out, int32_t* level_out,
+                                int32_t* rt_out, hipStream_t st) {
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(gather_failed_kernel, dim3(g1d(nb)), dim3(256), 0, st, rank, pos, nb,
-                       blocks, rt, list, blocks_out, rt_out);
+                       blocks, level, rt, list, blocks_out, level_out, rt_out);
     return hipGetLastError();
 }
 
