@@ -133,9 +133,11 @@ typedef struct {
                                 HMX_F32 with BF16 factors */
     hmx_rank_mode rank_mode;
     int32_t aca_chunk_mb;    /* ACA scratch budget per chunk of admissible blocks,
-                                MiB; 0 selects 8192.  Blocks are approximated in
-                                chunks whose k_max-column scratch fits the budget,
-                                then compacted to their exact ranks */
+                                MiB; 0 selects 40% of the device memory free
+                                when the ACA starts.  Blocks are approximated in
+                                chunks whose column scratch (k_max, or the
+                                predicted target) fits the budget, then
+                                compacted to their exact ranks */
     int32_t aca_only;        /* 1: stop after the ACA (no matrix pool).  The
                                 handle then serves partition, ranks, features
                                 and stats; hmx_matvec returns UNSUPPORTED.
@@ -163,7 +165,8 @@ typedef struct {
     int64_t aca_columns;      /* ACA residual columns evaluated (incl. skipped) */
     int64_t aca_chunks;       /* chunks the admissible leaves were approximated in */
     int32_t near_entry_bytes; /* bytes per stored near-field entry */
-    int32_t reserved1;
+    int32_t tile_config;      /* row-tile kernel configuration in use (-1:
+                                 default shape; see hmx_autotune) */
     double matvec_bytes;      /* algorithmic HBM bytes of one matvec (beta = 0) */
     double phase_ms[8];       /* build phases: order, tree, traversal, aca,
                                  compaction, near field, matvec plan, total */
@@ -193,6 +196,33 @@ hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t
                      const hmx_kernel* kernel, const hmx_params* params, void* stream,
                      hmx_hmatrix* out);
 
+/* Batched build of nprob independent problems (the same kind of kernel,
+ * Gaussian or Matern-3/2, each with its own p0 and point set, one shared
+ * params) as ONE handle: the block-diagonal H-matrix diag(H_1, ..., H_nprob)
+ * over the concatenated index set, problem p owning indices
+ * [off_p, off_p + n_p) with off_p = n_0 + ... + n_{p-1}.  Every problem's
+ * ordering, cluster tree and block partition are those of its own build; the
+ * ACA of all problems' admissible leaves, the near field and every matvec
+ * then run as single batched launches over the union.  hmx_matvec and
+ * hmx_cg_solve on the handle act on concatenated vectors of n_0 + ... +
+ * n_{nprob-1} entries (each problem in its own original point order).
+ * Internally problem p's coordinates are divided by its kernel length
+ * (sqrt(p0) Gaussian, p0 Matern) and padded to d = 3 with zeros, so matrix
+ * entries may differ from a single build's in the last bits.
+ *   points : host array of nprob device pointers (n_p x d_p row-major, all
+ *            in pts_dtype); n, d, kernels: host arrays of nprob entries.
+ * hmx_get_partition lists the leaves of all problems in union indices
+ * (upper-level leaves of all problems first, each problem in canonical
+ * order); hmx_get_boxes and hmx_block_features return UNSUPPORTED.
+ * Limits: sum of n_p < 2^31.  Host-blocking like hmx_build. */
+hmx_status hmx_build_batched(int32_t nprob, const void* const* points, hmx_dtype pts_dtype,
+                             const int64_t* n, const int32_t* d, const hmx_kernel* kernels,
+                             const hmx_params* params, void* stream, hmx_hmatrix* out);
+
+/* Problems of a handle: *nprob (1 for hmx_build) and, if offsets != NULL
+ * (host, nprob + 1 entries), each problem's first index and the total. */
+hmx_status hmx_get_batch(hmx_hmatrix h, int32_t* nprob, int64_t* offsets);
+
 /* z := alpha (H + sigma2 I) x + beta z in the ORIGINAL point order
  * (Algorithm 3; x is permuted to Morton order and z back, Section 5.1).
  *   x, z : device vectors of n entries in vec_dtype, which must equal the
@@ -201,6 +231,40 @@ hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t
  * Fully asynchronous on `stream`; allocates nothing. */
 hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype, double alpha,
                       double beta, void* stream);
+
+/* ---- hipGraph-captured matvecs ---- */
+typedef struct hmx_graph_s* hmx_graph; /* opaque; an instantiated HIP graph */
+
+/* Capture reps consecutive hmx_matvec(h, x, z, vec_dtype, alpha, beta) into
+ * one HIP graph (captured on a private stream; nothing runs yet).  x and z
+ * (device) are baked into the graph: they and h must stay alive while the
+ * graph is used, and the graph uses the tile configuration h had when it was
+ * captured.  The matvec kernels record no memory-set nodes.  reps in
+ * [1, 4096]. */
+hmx_status hmx_matvec_graph(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype,
+                            double alpha, double beta, int32_t reps, hmx_graph* out);
+/* Replay the captured matvecs on `stream` (asynchronous). */
+hmx_status hmx_graph_launch(hmx_graph g, void* stream);
+/* Release the graph (synchronises the device). */
+hmx_status hmx_graph_destroy(hmx_graph g);
+
+/* ---- autotuner of the matvec's row-tile kernel ---- */
+/* Row-tile configurations: shape c % 5 of (lanes per row group, row vectors
+ * per lane) = (16,1), (32,1), (64,1), (64,2), (64,4); c >= 5 adds a
+ * persistent grid of 2048 workgroups looping over the tiles.  Configurations
+ * sum in different orders, so results may differ in the last bits. */
+#define HMX_TILE_CONFIGS 10
+
+/* Time every configuration on this handle (reps row-tile launches each, HIP
+ * events on `stream`, on scratch vectors it allocates) and keep the fastest
+ * for later matvecs (lowest index on ties).  choice (host, optional): the
+ * configuration chosen; times_ms (host, optional, HMX_TILE_CONFIGS entries):
+ * mean milliseconds per launch.  Host-blocking. */
+hmx_status hmx_autotune(hmx_hmatrix h, int32_t reps, void* stream, int32_t* choice,
+                        double* times_ms);
+/* Select a configuration directly (-1: the default shape for the handle's
+ * largest tile). */
+hmx_status hmx_set_tile_config(hmx_hmatrix h, int32_t config);
 
 /* Conjugate gradients for (H + sigma2 I) c = b, the kernel ridge regression
  * / Gaussian process system of Section 1, with H this handle's H-matrix and

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -189,6 +190,12 @@ struct hmx_mlp_s {
     DevBuf act, scratch, grad, Xb, yb, loss;
 };
 
+// a captured sequence of matvecs (hmx_matvec_graph)
+struct hmx_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct hmx_hmatrix_s {
     int64_t n = 0;
     int d = 0;
@@ -205,6 +212,12 @@ struct hmx_hmatrix_s {
     int64_t nslots = 0;
     int64_t n_adm = 0, n_dense = 0, ntiles = 0, npieces = 0, sum_rank = 0;
     int max_tile = 0;
+    int64_t big_adm = 0;  // rows of the largest admissible leaf's clusters
+    // batched build: problem p owns indices [offsets[p], offsets[p + 1])
+    int32_t nprob = 1;
+    bool batched = false;
+    int rt_config = -1;  // row-tile kernel configuration (-1: default shape)
+    std::vector<int64_t> offsets;
     int64_t factor_entries = 0, near_entries = 0;
     DevBuf codes, perm, soa64, soa32, node_lo, node_hi, bmin, bmax;
     DevBuf adm, adm_level, adm_ids, dense, dense_level;
@@ -255,6 +268,7 @@ void finish_stats(hmx_hmatrix_s* h, std::chrono::steady_clock::time_point t_all)
     S.near_entries = h->near_entries;
     S.entry_bytes = (int32_t)ssz;
     S.near_entry_bytes = (int32_t)h->nsz;
+    S.tile_config = h->rt_config;
     S.phase_ms[7] = ms_since(t_all);
     // algorithmic bytes of one matvec with beta = 0: stored data once, the
     // vectors x and z once, perm for gather and scatter, t written and read
@@ -294,17 +308,76 @@ int max_depth(int64_t n, int leaf) {
     return L;
 }
 
-void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) {
+
+// dimensions, kernel, parameters and the storage modes they imply
+void init_handle(hmx_hmatrix_s* h, int64_t n, int d, const hmx_kernel& k, const hmx_params& p) {
+    h->n = n;
+    h->d = d;
+    h->kern = k;
+    h->prm = p;
+    h->f64 = p.compute_dtype == HMX_F64;
+    h->esz = h->f64 ? 8 : 4;
+    h->smode = p.storage_dtype == HMX_F64 ? 0 : (p.storage_dtype == HMX_F32 ? 1 : 2);
+    h->ssz = h->smode == 0 ? 8 : (h->smode == 1 ? 4 : 2);
+    h->nmode = p.near_dtype == HMX_F64 ? 0 : (p.near_dtype == HMX_F32 ? 1 : 2);
+    h->nsz = h->nmode == 0 ? 8 : (h->nmode == 1 ? 4 : 2);
+}
+
+// validation shared by the single and the batched build
+hmx_status check_params(const hmx_params& p) {
+    if (p.leaf_size < 1 || !(p.eta >= 0) || !std::isfinite(p.eta) || !(p.aca_eps >= 0) ||
+        !(p.aca_eta >= 0 && p.aca_eta < 1) || p.max_rank < 1 || p.max_rank > kMaxRankCap ||
+        !(p.sigma2 >= 0) || !std::isfinite(p.sigma2)) {
+        set_err("invalid params (leaf %d, eta %g, eps %g, aca_eta %g, max_rank %d, sigma2 %g)",
+                p.leaf_size, p.eta, p.aca_eps, p.aca_eta, p.max_rank, p.sigma2);
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (p.compute_dtype != HMX_F64 && p.compute_dtype != HMX_F32) {
+        set_err("compute_dtype must be F64 or F32");
+        return HMX_ERR_UNSUPPORTED;
+    }
+    if ((p.compute_dtype == HMX_F64) != (p.storage_dtype == HMX_F64) ||
+        (p.storage_dtype != HMX_F64 && p.storage_dtype != HMX_F32 && p.storage_dtype != HMX_BF16)) {
+        set_err("storage_dtype must be F64 with F64 compute, F32 or BF16 with F32 compute");
+        return HMX_ERR_UNSUPPORTED;
+    }
+    {
+        const bool ok = (p.near_dtype == p.storage_dtype) ||
+                        (p.storage_dtype == HMX_BF16 && p.near_dtype == HMX_F32);
+        if (!ok) {
+            set_err("near_dtype must equal storage_dtype, or be F32 with BF16 factors");
+            return HMX_ERR_UNSUPPORTED;
+        }
+    }
+    if (p.rank_mode != HMX_RANK_ADAPTIVE && p.rank_mode != HMX_RANK_FIXED &&
+        p.rank_mode != HMX_RANK_LEARNED) {
+        set_err("unsupported rank mode %d", (int)p.rank_mode);
+        return HMX_ERR_UNSUPPORTED;
+    }
+    if (p.rank_mode == HMX_RANK_LEARNED && !p.mlp) {
+        set_err("HMX_RANK_LEARNED needs a rank predictor (params.mlp)");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (p.aca_only != 0 && p.aca_only != 1) {
+        set_err("aca_only must be 0 or 1");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (p.learned_one_shot != 0 && p.learned_one_shot != 1) {
+        set_err("learned_one_shot must be 0 or 1");
+        return HMX_ERR_INVALID_ARG;
+    }
+    return HMX_OK;
+}
+
+
+// phases 1-3: ordering, cluster tree and boxes, block-tree traversal
+void stage_partition(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) {
     using clk = std::chrono::steady_clock;
-    const auto t_all = clk::now();
     const int64_t n = h->n;
     const int d = h->d;
     const int leaf = h->prm.leaf_size;
     const double eta = h->prm.eta;
     const int f64 = h->f64;
-    const size_t esz = h->esz;
-    const size_t ssz = h->ssz;
-    const int smode = h->smode;
     hmx_stats& S = h->stats;
     auto t0 = clk::now();
 
@@ -460,7 +533,70 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
         for (int l = 0; l < std::max(min_adm_level, 0); ++l) big_adm = (big_adm + 1) / 2;
     }
     S.phase_ms[2] = ms_since(t0);
-    t0 = clk::now();
+    h->big_adm = big_adm;
+}
+
+// how the ACA treats the admissible leaves of a handle: size classes and
+// (learned sizing) the predicted targets
+struct AcaPlan {
+    const int32_t* cls = nullptr;  // per leaf, non-decreasing; < split: 512-thread class
+    int split = 0;
+    int big_words = 2, small_words = 2;  // LDS mask words of the two classes
+    const int32_t* rt = nullptr;         // learned targets, or null
+};
+
+// rows above which a cluster's blocks run in the 512-thread class
+constexpr int64_t kBigRows = 4096;
+
+// size classes of a single problem by tree level: clusters at level l hold at
+// most s_l points (s_0 = n, s_{l+1} = ceil(s_l / 2)); levels whose clusters
+// can reach kBigRows points form the 512-thread class
+AcaPlan level_plan(const hmx_hmatrix_s* h) {
+    AcaPlan p;
+    int64_t s_split = h->n;
+    while (s_split >= kBigRows) {
+        s_split = (s_split + 1) / 2;
+        ++p.split;
+    }
+    const int64_t big = h->big_adm;
+    const int64_t words = 2 * ((big + 31) / 32);
+    if (words * 4 > 64 * 1024) {
+        set_err("admissible block of %lld rows exceeds the ACA bitmask capacity", (long long)big);
+        throw Fail{HMX_ERR_UNSUPPORTED};
+    }
+    p.cls = h->adm_level.as<int32_t>();
+    p.big_words = (int)std::max<int64_t>(words, 2);
+    p.small_words = (int)std::max<int64_t>(2 * ((std::min(s_split, big) + 31) / 32), 2);
+    return p;
+}
+
+// learned sizing: the predictor's target for every admissible leaf
+void stage_predict(hmx_hmatrix_s* h, DevBuf& rt, hipStream_t st) {
+    alloc(rt, std::max<int64_t>(h->n_adm, 1) * 4, "rank targets");
+    const auto tp = std::chrono::steady_clock::now();
+    const hmx_mlp_s* mp = h->prm.mlp;
+    check(launch_rank_predict(h->adm.as<int4>(), h->adm_ids.as<int2>(), h->n_adm,
+                              h->bmin.as<double>(), h->bmax.as<double>(), h->d,
+                              kernel_length(h->kern), mp->w.as<float>(), mp->mean.as<float>(),
+                              mp->scale.as<float>(), h->prm.max_rank, nullptr, rt.as<int32_t>(),
+                              st),
+          "rank prediction");
+    check(hipStreamSynchronize(st), "prediction sync");
+    h->stats.predict_ms += ms_since(tp);
+}
+
+// phases 4-5: batched ACA, compaction, the tile-major matrix pool
+void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
+                   std::chrono::steady_clock::time_point t_all) {
+    using clk = std::chrono::steady_clock;
+    const int64_t n = h->n;
+    const int d = h->d;
+    const int f64 = h->f64;
+    const size_t esz = h->esz;
+    const size_t ssz = h->ssz;
+    const int smode = h->smode;
+    hmx_stats& S = h->stats;
+    auto t0 = clk::now();
 
     const int kmax = h->prm.max_rank;
     DevBuf scan_scr;
@@ -475,10 +611,10 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
 
     // ---- 4. batched ACA of the admissible leaves, in chunks ----
     // A pass approximates a list of blocks in chunks: every block gets
-    // scratch for its column capacity (k_max, or the predicted target in the
-    // learned one-shot pass) within the chunk budget; after the chunk's ACA
-    // the factors are compacted to their exact ranks (U in the compute type
-    // as the source of the tile-major pool, V in the storage type) and
+    // scratch for its column capacity (k_max, or the predicted target of the
+    // learned sizing) within the chunk budget; after the chunk's ACA the
+    // factors are compacted to their exact ranks in the storage type (U as
+    // the source of the tile-major pool, V as phase 1's operand) and
     // appended to the pools.
     alloc(h->rank, std::max<int64_t>(h->n_adm, 1) * 4, "ranks");
     alloc(h->steps, std::max<int64_t>(h->n_adm, 1) * 4, "steps");
@@ -488,29 +624,23 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
     int nchunks = 0;
     double aca_ms = 0.0;
     int64_t utot = 0, vtot = 0;
-    const bool learned = h->prm.rank_mode == HMX_RANK_LEARNED;
+    const bool learned = plan.rt != nullptr;
     const bool aca_only = h->prm.aca_only != 0;
     if (h->n_adm > 0) {
-        // size classes by tree level: clusters at level l hold at most s_l
-        // points (s_0 = n, s_{l+1} = ceil(s_l / 2)); levels whose clusters can
-        // exceed kBigRows points form the 512-thread class
-        constexpr int64_t kBigRows = 4096;
-        int lvl_split = 0;
-        int64_t s_split = n;
-        while (s_split >= kBigRows) {
-            s_split = (s_split + 1) / 2;
-            ++lvl_split;
+        // chunk budget: the caller's, else 40% of the device memory that is
+        // free now (the library's cached blocks count as free)
+        int64_t budget_bytes = (int64_t)h->prm.aca_chunk_mb << 20;
+        if (h->prm.aca_chunk_mb <= 0) {
+            size_t fr = 0, tot = 0;
+            check(hipMemGetInfo(&fr, &tot), "memory info");
+            size_t cached = 0;
+            {
+                std::lock_guard<std::mutex> lk(cache().mu);
+                cached = cache().cached;
+            }
+            budget_bytes = std::max<int64_t>((int64_t)((fr + cached) / 10 * 4), (int64_t)1 << 30);
         }
-        const int64_t big = big_adm;
-        const int words = (int)(2 * ((big + 31) / 32));
-        if ((size_t)words * 4 > 64 * 1024) {
-            set_err("admissible block of %lld rows exceeds the ACA bitmask capacity",
-                    (long long)big);
-            throw Fail{HMX_ERR_UNSUPPORTED};
-        }
-        const int small_words = (int)(2 * ((std::min(s_split, big) + 31) / 32));
-        const int64_t budget_mb = h->prm.aca_chunk_mb > 0 ? h->prm.aca_chunk_mb : 8192;
-        const int64_t budget = std::max<int64_t>(budget_mb * ((int64_t)1 << 20) / (int64_t)esz, 1);
+        const int64_t budget = std::max<int64_t>(budget_bytes / (int64_t)esz, 1);
         AcaArgs a{};
         a.soa = f64 ? h->soa64.p : h->soa32.p;
         a.soa64 = h->soa64.as<double>();
@@ -522,8 +652,8 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
         a.aca_eta = h->prm.aca_eta;
         a.eps0 = h->prm.aca_eps0 >= 0 ? h->prm.aca_eps0 : (f64 ? 1e-14 : 1e-7);
         a.fixed = h->prm.rank_mode == HMX_RANK_FIXED;
-        a.big_words = std::max(words, 2);
-        a.small_words = std::max(small_words, 2);
+        a.big_words = plan.big_words;
+        a.small_words = plan.small_words;
         DevBuf split;
         alloc(split, 8, "class split");
 
@@ -533,7 +663,7 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
         auto pass = [&](const int4* blocks, const int32_t* levels, int64_t nb, const int32_t* cap,
                         const int32_t* rt, int one_shot, int cap_only, int32_t* rank,
                         int32_t* steps, int64_t* ue_all, int64_t* ve_all) {
-            check(launch_level_split(levels, nb, lvl_split, split.as<int64_t>(), st),
+            check(launch_level_split(levels, nb, plan.split, split.as<int64_t>(), st),
                   "class split");
             const int64_t nbig_all = read_scalar(split.as<int64_t>(), st);
             DevBuf cu, cv, cc, Ucap, Vcap;
@@ -608,10 +738,10 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
                 const int64_t uk = scan(ue, nbk), vk = scan(ve, nbk);
                 check(launch_add_const(ue, nbk, utot, st), "offsets");
                 check(launch_add_const(ve, nbk, vtot, st), "offsets");
-                grow(Uex, (size_t)(utot + uk) * esz, (size_t)utot * esz, st, "U pool");
+                grow(Uex, (size_t)(utot + uk) * ssz, (size_t)utot * ssz, st, "U pool");
                 grow(h->V, (size_t)(vtot + vk) * ssz, (size_t)vtot * ssz, st, "V pool");
                 check(launch_compact_u(a.blocks, nbk, a.rank, a.uoff, a.ubase, ue, Ucap.p, Uex.p,
-                                       f64, st),
+                                       smode, st),
                       "compact U");
                 check(launch_compact_v(a.blocks, nbk, a.rank, a.voff, a.vbase, ve, Vcap.p,
                                        h->V.p, smode, st),
@@ -623,7 +753,7 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
         };
 
         if (!learned) {
-            pass(h->adm.as<int4>(), h->adm_level.as<int32_t>(), h->n_adm, nullptr, nullptr, 0, 0,
+            pass(h->adm.as<int4>(), plan.cls, h->n_adm, nullptr, nullptr, 0, 0,
                  h->rank.as<int32_t>(), h->steps.as<int32_t>(), uoff_ex.as<int64_t>(),
                  h->voff.as<int64_t>());
         } else {
@@ -632,21 +762,10 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
             // (sizing form: plain adaptive; one-shot form: the same target
             // steps, the test, then adaptive)
             const int one_shot = h->prm.learned_one_shot;
-            DevBuf rt;
-            alloc(rt, h->n_adm * 4, "rank targets");
-            const auto tp = clk::now();
-            const double ell = kernel_length(h->kern);
-            const hmx_mlp_s* mp = h->prm.mlp;
-            check(launch_rank_predict(h->adm.as<int4>(), h->adm_ids.as<int2>(), h->n_adm,
-                                      h->bmin.as<double>(), h->bmax.as<double>(), d, ell,
-                                      mp->w.as<float>(), mp->mean.as<float>(),
-                                      mp->scale.as<float>(), kmax, nullptr, rt.as<int32_t>(), st),
-                  "rank prediction");
-            check(hipStreamSynchronize(st), "prediction sync");
-            S.predict_ms = ms_since(tp);
-            pass(h->adm.as<int4>(), h->adm_level.as<int32_t>(), h->n_adm, rt.as<int32_t>(),
-                 rt.as<int32_t>(), one_shot, 1, h->rank.as<int32_t>(), h->steps.as<int32_t>(),
-                 uoff_ex.as<int64_t>(), h->voff.as<int64_t>());
+            const int32_t* rt = plan.rt;
+            pass(h->adm.as<int4>(), plan.cls, h->n_adm, rt, rt, one_shot, 1,
+                 h->rank.as<int32_t>(), h->steps.as<int32_t>(), uoff_ex.as<int64_t>(),
+                 h->voff.as<int64_t>());
             DevBuf flag;
             alloc(flag, (h->n_adm + 1) * 8, "fallback flags");
             check(launch_fail_flags(h->rank.as<int32_t>(), h->n_adm, flag.as<int64_t>(), st),
@@ -664,9 +783,9 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
                 alloc(uefb, (nfb + 1) * 8, "fallback U offsets");
                 alloc(vefb, (nfb + 1) * 8, "fallback V offsets");
                 check(launch_gather_failed(h->rank.as<int32_t>(), flag.as<int64_t>(), h->n_adm,
-                                           h->adm.as<int4>(), h->adm_level.as<int32_t>(),
-                                           rt.as<int32_t>(), list.as<int32_t>(), bfb.as<int4>(),
-                                           lvfb.as<int32_t>(), rtfb.as<int32_t>(), st),
+                                           h->adm.as<int4>(), plan.cls, rt, list.as<int32_t>(),
+                                           bfb.as<int4>(), lvfb.as<int32_t>(),
+                                           rtfb.as<int32_t>(), st),
                       "fallback gather");
                 pass(bfb.as<int4>(), lvfb.as<int32_t>(), nfb, nullptr,
                      one_shot ? rtfb.as<int32_t>() : nullptr, one_shot, 0, rkfb.as<int32_t>(),
@@ -709,7 +828,7 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
     if (!h->V.p) alloc(h->V, 16, "V pool");
     if (!Uex.p) alloc(Uex, 16, "U pool");
     S.aca_chunks = nchunks;
-    S.phase_ms[4] = ms_since(t0) - S.phase_ms[3] - S.predict_ms;
+    S.phase_ms[4] = ms_since(t0) - S.phase_ms[3];
     if (aca_only) {
         Uex.release();
         finish_stats(h, t_all);
@@ -820,6 +939,230 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
     finish_stats(h, t_all);
 }
 
+void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) {
+    const auto t_all = std::chrono::steady_clock::now();
+    stage_partition(h, pts, pts_f64, st);
+    AcaPlan plan = h->n_adm > 0 ? level_plan(h) : AcaPlan{};
+    DevBuf rt;
+    if (h->prm.rank_mode == HMX_RANK_LEARNED && h->n_adm > 0) {
+        stage_predict(h, rt, st);
+        plan.rt = rt.as<int32_t>();
+    }
+    stage_factors(h, plan, st, t_all);
+}
+
+// Many independent problems as one block-diagonal H-matrix.  Each problem's
+// ordering, cluster tree and traversal run on its own points (bit for bit
+// what a single build computes); the union then takes the problems' index
+// ranges one after another: problem p owns [off_p, off_p + n_p).  Its
+// coordinates are scaled by 1 / l_p (l the kernel's length: sqrt(p0) for the
+// Gaussian, p0 for Matern-3/2) and padded to three dimensions with zeros,
+// so phi with length 1 gives every problem its own kernel.  The admissible
+// leaves of all problems are ordered upper-level class first, then the ACA,
+// near field and matvec run once over the union.
+void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
+                  const int64_t* n, const int32_t* d, const hmx_kernel* kern, hipStream_t st) {
+    const auto t_all = std::chrono::steady_clock::now();
+    const bool learned = u->prm.rank_mode == HMX_RANK_LEARNED;
+    std::vector<std::unique_ptr<hmx_hmatrix_s>> parts(np);
+    std::unique_ptr<DevBuf[]> rts(new DevBuf[np]);
+    std::vector<int64_t> nbig(np, 0);
+    hmx_stats& S = u->stats;
+    DevBuf split;
+    alloc(split, 8, "class split");
+    int64_t nadm = 0, ndense = 0, ntiles = 0, big = 0, nbig_tot = 0;
+    for (int p = 0; p < np; ++p) {
+        hmx_hmatrix_s* hp = new hmx_hmatrix_s();
+        parts[p].reset(hp);
+        init_handle(hp, n[p], d[p], kern[p], u->prm);
+        stage_partition(hp, pts[p], pts_f64, st);
+        if (learned && hp->n_adm > 0) stage_predict(hp, rts[p], st);
+        if (hp->n_adm > 0) {
+            const AcaPlan lp = level_plan(hp);
+            check(launch_level_split(hp->adm_level.as<int32_t>(), hp->n_adm, lp.split,
+                                     split.as<int64_t>(), st),
+                  "class split");
+            nbig[p] = read_scalar(split.as<int64_t>(), st);
+        }
+        nadm += hp->n_adm;
+        ndense += hp->n_dense;
+        ntiles += hp->ntiles;
+        nbig_tot += nbig[p];
+        big = std::max(big, hp->big_adm);
+        u->max_tile = std::max(u->max_tile, hp->max_tile);
+        for (int k = 0; k < 3; ++k) S.phase_ms[k] += hp->stats.phase_ms[k];
+        S.predict_ms += hp->stats.predict_ms;
+        S.levels = std::max(S.levels, hp->stats.levels);
+        for (int l = 0; l < 64; ++l) S.level_sizes[l] += hp->stats.level_sizes[l];
+    }
+    const int64_t N = u->n;
+    alloc(u->codes, N * 8, "morton codes");
+    alloc(u->perm, N * 4, "permutation");
+    alloc(u->soa64, (size_t)N * 3 * 8, "coords f64");
+    if (!u->f64) alloc(u->soa32, (size_t)N * 3 * 4, "coords f32");
+    alloc(u->tile_of_point, N * 4, "tile of point");
+    alloc(u->tile_lo, (ntiles + 1) * 4, "tile lo");
+    alloc(u->adm, std::max<int64_t>(nadm, 1) * sizeof(int4), "adm leaves");
+    alloc(u->adm_level, std::max<int64_t>(nadm, 1) * 4, "adm levels");
+    alloc(u->adm_ids, 16, "adm node ids");
+    alloc(u->dense, std::max<int64_t>(ndense, 1) * sizeof(int4), "dense leaves");
+    alloc(u->dense_level, std::max<int64_t>(ndense, 1) * 4, "dense levels");
+    DevBuf cls, rt;
+    alloc(cls, std::max<int64_t>(nadm, 1) * 4, "size classes");
+    if (learned) alloc(rt, std::max<int64_t>(nadm, 1) * 4, "rank targets");
+    int64_t base = 0, tbase = 0, abig = 0, asmall = nbig_tot, dcur = 0;
+    u->offsets.assign(1, 0);
+    for (int p = 0; p < np; ++p) {
+        hmx_hmatrix_s* hp = parts[p].get();
+        const int64_t np_ = hp->n;
+        const int32_t b32 = (int32_t)base;
+        check(hipMemcpyAsync(u->codes.as<uint64_t>() + base, hp->codes.p, np_ * 8,
+                             hipMemcpyDeviceToDevice, st),
+              "codes");
+        check(launch_add_i32(u->perm.as<int32_t>() + base, hp->perm.as<int32_t>(), np_, b32, st),
+              "perm");
+        const double ell = kernel_length(hp->kern);
+        check(launch_scale_coords(hp->soa64.as<double>(), np_, hp->d, 1.0 / ell,
+                                  u->soa64.as<double>(), u->f64 ? nullptr : u->soa32.as<float>(),
+                                  N, base, st),
+              "coords");
+        check(launch_add_i32(u->tile_of_point.as<int32_t>() + base,
+                             hp->tile_of_point.as<int32_t>(), np_, (int32_t)tbase, st),
+              "tiles");
+        check(launch_add_i32(u->tile_lo.as<int32_t>() + tbase, hp->tile_lo.as<int32_t>(),
+                             hp->ntiles, b32, st),
+              "tile starts");
+        // the upper-level class of every problem first, then the rest
+        const int64_t nb = nbig[p], ns = hp->n_adm - nbig[p];
+        const int4* ha = hp->adm.as<int4>();
+        const int32_t* hl = hp->adm_level.as<int32_t>();
+        check(launch_shift_blocks(u->adm.as<int4>() + abig, ha, nb, b32, st), "adm");
+        check(launch_shift_blocks(u->adm.as<int4>() + asmall, ha + nb, ns, b32, st), "adm");
+        check(hipMemcpyAsync(u->adm_level.as<int32_t>() + abig, hl, nb * 4,
+                             hipMemcpyDeviceToDevice, st),
+              "adm levels");
+        check(hipMemcpyAsync(u->adm_level.as<int32_t>() + asmall, hl + nb, ns * 4,
+                             hipMemcpyDeviceToDevice, st),
+              "adm levels");
+        check(launch_fill_i32(cls.as<int32_t>() + abig, nb, 0, st), "classes");
+        check(launch_fill_i32(cls.as<int32_t>() + asmall, ns, 1, st), "classes");
+        if (learned && hp->n_adm > 0) {
+            check(hipMemcpyAsync(rt.as<int32_t>() + abig, rts[p].p, nb * 4,
+                                 hipMemcpyDeviceToDevice, st),
+                  "targets");
+            check(hipMemcpyAsync(rt.as<int32_t>() + asmall, rts[p].as<int32_t>() + nb, ns * 4,
+                                 hipMemcpyDeviceToDevice, st),
+                  "targets");
+        }
+        check(launch_shift_blocks(u->dense.as<int4>() + dcur, hp->dense.as<int4>(), hp->n_dense,
+                                  b32, st),
+              "dense");
+        check(hipMemcpyAsync(u->dense_level.as<int32_t>() + dcur, hp->dense_level.p,
+                             hp->n_dense * 4, hipMemcpyDeviceToDevice, st),
+              "dense levels");
+        base += np_;
+        tbase += hp->ntiles;
+        abig += nb;
+        asmall += ns;
+        dcur += hp->n_dense;
+        u->offsets.push_back(base);
+    }
+    const int32_t nend = (int32_t)N;
+    check(hipMemcpyAsync(u->tile_lo.as<int32_t>() + ntiles, &nend, 4, hipMemcpyHostToDevice, st),
+          "tile end");
+    check(hipStreamSynchronize(st), "batch assembly");
+    parts.clear();
+    rts.reset();
+    u->n_adm = nadm;
+    u->n_dense = ndense;
+    u->ntiles = ntiles;
+    u->big_adm = big;
+    AcaPlan plan;
+    if (nadm > 0) {
+        const int64_t words = 2 * ((big + 31) / 32);
+        if (words * 4 > 64 * 1024) {
+            set_err("admissible block of %lld rows exceeds the ACA bitmask capacity",
+                    (long long)big);
+            throw Fail{HMX_ERR_UNSUPPORTED};
+        }
+        plan.cls = cls.as<int32_t>();
+        plan.split = 1;
+        plan.big_words = (int)std::max<int64_t>(words, 2);
+        plan.small_words =
+            (int)std::max<int64_t>(2 * ((std::min(kBigRows - 1, big) + 31) / 32), 2);
+        plan.rt = learned ? rt.as<int32_t>() : nullptr;
+    }
+    stage_factors(u, plan, st, t_all);
+}
+
+}  // namespace
+
+
+namespace {
+
+const int64_t kP = HMX_MLP_NPARAMS;
+
+template <typename F>
+hmx_status guarded(F&& f) {
+    try {
+        f();
+    } catch (const Fail& e) {
+        return e.s;
+    } catch (const std::bad_alloc&) {
+        set_err("host allocation failed");
+        return HMX_ERR_OOM;
+    }
+    return HMX_OK;
+}
+
+// grow a work buffer without keeping its contents (the stream is synchronised
+// first: the old block may still be in use by queued work)
+void ensure(DevBuf& b, size_t bytes, hipStream_t st, const char* what) {
+    if (b.p && b.bytes >= bytes) return;
+    check(hipStreamSynchronize(st), "work buffer sync");
+    alloc(b, bytes, what);
+}
+
+// argument checks shared by hmx_matvec and hmx_matvec_graph
+hmx_status matvec_args(hmx_hmatrix_s* h, const void* x, const void* z, hmx_dtype vec_dtype) {
+    if (!h || !x || !z) {
+        set_err("NULL argument");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if ((vec_dtype == HMX_F64) != (h->f64 == 1) || vec_dtype == HMX_BF16) {
+        set_err("vector dtype must equal the compute dtype");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (h->prm.aca_only) {
+        set_err("handle was built with aca_only: no matrix to apply");
+        return HMX_ERR_UNSUPPORTED;
+    }
+    return HMX_OK;
+}
+
+// the three launches of one matvec: gather of x into Morton order, far-field
+// phase 1 (t = V^T x), row tiles (near field + U t, scatter to z); ev: four
+// events recorded around them, or null
+hipError_t matvec_launch(hmx_hmatrix_s* h, const void* x, void* z, double alpha, double beta,
+                         hipStream_t st, hipEvent_t* ev, int config) {
+    const int f64 = h->f64;
+    hipError_t e = ev ? hipEventRecord(ev[0], st) : hipSuccess;
+    if (e == hipSuccess) e = launch_gather_x(x, h->perm.as<int32_t>(), h->n, h->vecpool.p, f64, st);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
+    if (e == hipSuccess)
+        e = launch_far_phase1(h->adm.as<int4>(), h->col_block.as<int32_t>(),
+                              h->voff.as<int64_t>(), h->toff.as<int64_t>(), h->sum_rank, h->V.p,
+                              h->vecpool.p, h->n, h->smode, st);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
+    if (e == hipSuccess)
+        e = launch_rowtile(h->ntiles, h->tile_lo.as<int32_t>(), h->tile_meta.as<int64_t>(),
+                           h->widx.as<int64_t>(), h->upool.p, h->npool.p, h->vecpool.p,
+                           h->perm.as<int32_t>(), alpha, beta, h->prm.sigma2, z, h->max_tile,
+                           h->smode, h->nmode, config, st);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -879,46 +1222,9 @@ hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t
         return HMX_ERR_INVALID_ARG;
     }
     const hmx_params& p = *params;
-    if (p.leaf_size < 1 || !(p.eta >= 0) || !std::isfinite(p.eta) || !(p.aca_eps >= 0) ||
-        !(p.aca_eta >= 0 && p.aca_eta < 1) || p.max_rank < 1 || p.max_rank > kMaxRankCap ||
-        !(p.sigma2 >= 0) || !std::isfinite(p.sigma2)) {
-        set_err("invalid params (leaf %d, eta %g, eps %g, aca_eta %g, max_rank %d, sigma2 %g)",
-                p.leaf_size, p.eta, p.aca_eps, p.aca_eta, p.max_rank, p.sigma2);
-        return HMX_ERR_INVALID_ARG;
-    }
-    if (p.compute_dtype != HMX_F64 && p.compute_dtype != HMX_F32) {
-        set_err("compute_dtype must be F64 or F32");
-        return HMX_ERR_UNSUPPORTED;
-    }
-    if ((p.compute_dtype == HMX_F64) != (p.storage_dtype == HMX_F64) ||
-        (p.storage_dtype != HMX_F64 && p.storage_dtype != HMX_F32 && p.storage_dtype != HMX_BF16)) {
-        set_err("storage_dtype must be F64 with F64 compute, F32 or BF16 with F32 compute");
-        return HMX_ERR_UNSUPPORTED;
-    }
     {
-        const bool ok = (p.near_dtype == p.storage_dtype) ||
-                        (p.storage_dtype == HMX_BF16 && p.near_dtype == HMX_F32);
-        if (!ok) {
-            set_err("near_dtype must equal storage_dtype, or be F32 with BF16 factors");
-            return HMX_ERR_UNSUPPORTED;
-        }
-    }
-    if (p.rank_mode != HMX_RANK_ADAPTIVE && p.rank_mode != HMX_RANK_FIXED &&
-        p.rank_mode != HMX_RANK_LEARNED) {
-        set_err("unsupported rank mode %d", (int)p.rank_mode);
-        return HMX_ERR_UNSUPPORTED;
-    }
-    if (p.rank_mode == HMX_RANK_LEARNED && !p.mlp) {
-        set_err("HMX_RANK_LEARNED needs a rank predictor (params.mlp)");
-        return HMX_ERR_INVALID_ARG;
-    }
-    if (p.aca_only != 0 && p.aca_only != 1) {
-        set_err("aca_only must be 0 or 1");
-        return HMX_ERR_INVALID_ARG;
-    }
-    if (p.learned_one_shot != 0 && p.learned_one_shot != 1) {
-        set_err("learned_one_shot must be 0 or 1");
-        return HMX_ERR_INVALID_ARG;
+        const hmx_status ps = check_params(p);
+        if (ps != HMX_OK) return ps;
     }
     if (kernel->kind != HMX_GAUSSIAN && kernel->kind != HMX_MATERN32 &&
         kernel->kind != HMX_TEST_CONST && kernel->kind != HMX_TEST_LOWRANK) {
@@ -935,16 +1241,7 @@ hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t
         set_err("host allocation failed");
         return HMX_ERR_OOM;
     }
-    h->n = n;
-    h->d = d;
-    h->kern = *kernel;
-    h->prm = p;
-    h->f64 = p.compute_dtype == HMX_F64;
-    h->esz = h->f64 ? 8 : 4;
-    h->smode = p.storage_dtype == HMX_F64 ? 0 : (p.storage_dtype == HMX_F32 ? 1 : 2);
-    h->ssz = h->smode == 0 ? 8 : (h->smode == 1 ? 4 : 2);
-    h->nmode = p.near_dtype == HMX_F64 ? 0 : (p.near_dtype == HMX_F32 ? 1 : 2);
-    h->nsz = h->nmode == 0 ? 8 : (h->nmode == 1 ? 4 : 2);
+    init_handle(h, n, d, *kernel, p);
     try {
         build_impl(h, points, pts_dtype == HMX_F64, (hipStream_t)stream);
     } catch (const Fail& f) {
@@ -962,14 +1259,168 @@ hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t
     return HMX_OK;
 }
 
-hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype, double alpha,
-                      double beta, void* stream) {
-    if (!h || !x || !z) {
+hmx_status hmx_build_batched(int32_t nprob, const void* const* points, hmx_dtype pts_dtype,
+                             const int64_t* n, const int32_t* d, const hmx_kernel* kernels,
+                             const hmx_params* params, void* stream, hmx_hmatrix* out) {
+    if (out) *out = nullptr;
+    if (!out || !points || !n || !d || !kernels || !params || nprob < 1) {
+        set_err("NULL argument or nprob < 1");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (pts_dtype != HMX_F64 && pts_dtype != HMX_F32) {
+        set_err("points must be F64 or F32");
+        return HMX_ERR_INVALID_ARG;
+    }
+    const hmx_params& p = *params;
+    {
+        const hmx_status ps = check_params(p);
+        if (ps != HMX_OK) return ps;
+    }
+    const hmx_kernel_kind kind = kernels[0].kind;
+    if (kind != HMX_GAUSSIAN && kind != HMX_MATERN32) {
+        set_err("batched build supports the Gaussian and Matern-3/2 kernels");
+        return HMX_ERR_UNSUPPORTED;
+    }
+    int64_t total = 0;
+    for (int32_t q = 0; q < nprob; ++q) {
+        if (!points[q] || n[q] < 1 || d[q] < 1 || d[q] > 3) {
+            set_err("problem %d: NULL points, n < 1 or d not in {1,2,3}", q);
+            return HMX_ERR_INVALID_ARG;
+        }
+        if (kernels[q].kind != kind) {
+            set_err("problem %d: all problems of a batch need the same kernel kind", q);
+            return HMX_ERR_INVALID_ARG;
+        }
+        if (!(kernels[q].p0 > 0 && std::isfinite(kernels[q].p0))) {
+            set_err("problem %d: kernel parameter p0 must be positive and finite", q);
+            return HMX_ERR_INVALID_ARG;
+        }
+        total += n[q];
+    }
+    if (total >= (1ll << 31)) {
+        set_err("total points %lld exceed 2^31 - 1", (long long)total);
+        return HMX_ERR_INVALID_ARG;
+    }
+    hmx_hmatrix_s* h = new (std::nothrow) hmx_hmatrix_s();
+    if (!h) {
+        set_err("host allocation failed");
+        return HMX_ERR_OOM;
+    }
+    init_handle(h, total, 3, hmx_kernel{kind, 1.0, 0.0}, p);
+    h->nprob = nprob;
+    h->batched = true;
+    try {
+        batched_impl(h, nprob, points, pts_dtype == HMX_F64, n, d, kernels, (hipStream_t)stream);
+    } catch (const Fail& f) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        (void)hipGetLastError();
+        delete h;
+        return f.s;
+    } catch (const std::bad_alloc&) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        delete h;
+        set_err("host allocation failed");
+        return HMX_ERR_OOM;
+    }
+    *out = h;
+    return HMX_OK;
+}
+
+hmx_status hmx_get_batch(hmx_hmatrix h, int32_t* nprob, int64_t* offsets) {
+    if (!h || !nprob) {
         set_err("NULL argument");
         return HMX_ERR_INVALID_ARG;
     }
-    if ((vec_dtype == HMX_F64) != (h->f64 == 1) || vec_dtype == HMX_BF16) {
-        set_err("vector dtype must equal the compute dtype");
+    *nprob = h->nprob;
+    if (offsets) {
+        if (h->batched)
+            for (int32_t q = 0; q <= h->nprob; ++q) offsets[q] = h->offsets[q];
+        else {
+            offsets[0] = 0;
+            offsets[1] = h->n;
+        }
+    }
+    return HMX_OK;
+}
+
+hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype, double alpha,
+                      double beta, void* stream) {
+    const hmx_status cs = matvec_args(h, x, z, vec_dtype);
+    if (cs != HMX_OK) return cs;
+    hipEvent_t* ev = nullptr;
+    if (h->prof_calls < h->prof_max) ev = &h->prof_events[4 * h->prof_calls++];
+    const hipError_t e = matvec_launch(h, x, z, alpha, beta, (hipStream_t)stream, ev, h->rt_config);
+    if (e != hipSuccess) {
+        set_err("matvec launch: %s", hipGetErrorString(e));
+        return HMX_ERR_DEVICE;
+    }
+    return HMX_OK;
+}
+
+hmx_status hmx_matvec_graph(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype,
+                            double alpha, double beta, int32_t reps, hmx_graph* out) {
+    if (out) *out = nullptr;
+    if (!out || reps < 1 || reps > 4096) {
+        set_err("NULL output or reps not in [1, 4096]");
+        return HMX_ERR_INVALID_ARG;
+    }
+    const hmx_status cs = matvec_args(h, x, z, vec_dtype);
+    if (cs != HMX_OK) return cs;
+    hmx_graph_s* g = new (std::nothrow) hmx_graph_s();
+    if (!g) {
+        set_err("host allocation failed");
+        return HMX_ERR_OOM;
+    }
+    hipStream_t cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = hipSuccess;
+        for (int32_t r = 0; r < reps && le == hipSuccess; ++r)
+            le = matvec_launch(h, x, z, alpha, beta, cap, nullptr, h->rt_config);
+        e = hipStreamEndCapture(cap, &g->graph);  // always ends the capture
+        if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        set_err("matvec graph capture: %s", hipGetErrorString(e));
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        (void)hipGetLastError();
+        return HMX_ERR_DEVICE;
+    }
+    *out = g;
+    return HMX_OK;
+}
+
+hmx_status hmx_graph_launch(hmx_graph g, void* stream) {
+    if (!g) {
+        set_err("NULL graph");
+        return HMX_ERR_INVALID_ARG;
+    }
+    const hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        set_err("graph launch: %s", hipGetErrorString(e));
+        return HMX_ERR_DEVICE;
+    }
+    return HMX_OK;
+}
+
+hmx_status hmx_graph_destroy(hmx_graph g) {
+    if (!g) return HMX_OK;
+    (void)hipDeviceSynchronize();
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return HMX_OK;
+}
+
+hmx_status hmx_autotune(hmx_hmatrix h, int32_t reps, void* stream, int32_t* choice,
+                        double* times_ms) {
+    if (!h || reps < 1 || reps > 1000) {
+        set_err("NULL handle or reps not in [1, 1000]");
         return HMX_ERR_INVALID_ARG;
     }
     if (h->prm.aca_only) {
@@ -977,27 +1428,56 @@ hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype
         return HMX_ERR_UNSUPPORTED;
     }
     hipStream_t st = (hipStream_t)stream;
-    const int f64 = h->f64;
-    hipEvent_t* ev = nullptr;
-    if (h->prof_calls < h->prof_max) ev = &h->prof_events[4 * h->prof_calls++];
-    hipError_t e = ev ? hipEventRecord(ev[0], st) : hipSuccess;
-    if (e == hipSuccess) e = launch_gather_x(x, h->perm.as<int32_t>(), h->n, h->vecpool.p, f64, st);
-    if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
-    if (e == hipSuccess)
-        e = launch_far_phase1(h->adm.as<int4>(), h->col_block.as<int32_t>(),
-                              h->voff.as<int64_t>(), h->toff.as<int64_t>(), h->sum_rank, h->V.p,
-                              h->vecpool.p, h->n, h->smode, st);
-    if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
-    if (e == hipSuccess)
-        e = launch_rowtile(h->ntiles, h->tile_lo.as<int32_t>(), h->tile_meta.as<int64_t>(),
-                           h->widx.as<int64_t>(), h->upool.p, h->npool.p, h->vecpool.p,
-                           h->perm.as<int32_t>(), alpha, beta, h->prm.sigma2, z, h->max_tile,
-                           h->smode, h->nmode, st);
-    if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
-    if (e != hipSuccess) {
-        set_err("matvec launch: %s", hipGetErrorString(e));
-        return HMX_ERR_DEVICE;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hmx_status status = guarded([&] {
+        DevBuf x, z;
+        alloc(x, (size_t)h->n * h->esz, "tuning x");
+        alloc(z, (size_t)h->n * h->esz, "tuning z");
+        check(launch_fill_zero(x.p, h->n, h->f64, st), "fill");
+        check(matvec_launch(h, x.p, z.p, 1.0, 0.0, st, nullptr, -1), "matvec");
+        check(hipEventCreate(&e0), "event");
+        check(hipEventCreate(&e1), "event");
+        double best = INFINITY;
+        int bc = -1;
+        for (int c = 0; c < kRowtileConfigs; ++c) {
+            auto rt = [&] {
+                return launch_rowtile(h->ntiles, h->tile_lo.as<int32_t>(),
+                                      h->tile_meta.as<int64_t>(), h->widx.as<int64_t>(),
+                                      h->upool.p, h->npool.p, h->vecpool.p,
+                                      h->perm.as<int32_t>(), 1.0, 0.0, h->prm.sigma2, z.p,
+                                      h->max_tile, h->smode, h->nmode, c, st);
+            };
+            check(rt(), "tuning warm-up");
+            check(hipEventRecord(e0, st), "event");
+            for (int r = 0; r < reps; ++r) check(rt(), "tuning launch");
+            check(hipEventRecord(e1, st), "event");
+            check(hipEventSynchronize(e1), "event sync");
+            float ms = 0.f;
+            check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+            const double t = (double)ms / reps;
+            if (times_ms) times_ms[c] = t;
+            if (t < best) {
+                best = t;
+                bc = c;
+            }
+        }
+        check(hipStreamSynchronize(st), "tuning sync");
+        h->rt_config = bc;
+        h->stats.tile_config = bc;
+    });
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (status == HMX_OK && choice) *choice = h->rt_config;
+    return status;
+}
+
+hmx_status hmx_set_tile_config(hmx_hmatrix h, int32_t config) {
+    if (!h || config < -1 || config >= kRowtileConfigs) {
+        set_err("NULL handle or tile config not in [-1, %d)", kRowtileConfigs);
+        return HMX_ERR_INVALID_ARG;
     }
+    h->rt_config = config;
+    h->stats.tile_config = config;
     return HMX_OK;
 }
 
@@ -1140,6 +1620,10 @@ hmx_status hmx_get_partition(hmx_hmatrix h, uint64_t* codes, int32_t* perm, int3
 }
 
 hmx_status hmx_get_boxes(hmx_hmatrix h, double* global_box, double* leaf_boxes, void* stream) {
+    if (h && h->batched) {
+        set_err("batched handle: boxes belong to the individual problems");
+        return HMX_ERR_UNSUPPORTED;
+    }
     if (!h) {
         set_err("NULL handle");
         return HMX_ERR_INVALID_ARG;
@@ -1317,32 +1801,6 @@ hmx_status hmx_profile_end(hmx_hmatrix h, double* ms, int32_t* calls) {
 // rank predictor
 // ---------------------------------------------------------------------------
 
-extern "C++" {
-namespace {
-const int64_t kP = HMX_MLP_NPARAMS;
-
-template <typename F>
-hmx_status guarded(F&& f) {
-    try {
-        f();
-    } catch (const Fail& e) {
-        return e.s;
-    } catch (const std::bad_alloc&) {
-        set_err("host allocation failed");
-        return HMX_ERR_OOM;
-    }
-    return HMX_OK;
-}
-
-// grow a work buffer without keeping its contents (the stream is synchronised
-// first: the old block may still be in use by queued work)
-void ensure(DevBuf& b, size_t bytes, hipStream_t st, const char* what) {
-    if (b.p && b.bytes >= bytes) return;
-    check(hipStreamSynchronize(st), "work buffer sync");
-    alloc(b, bytes, what);
-}
-}  // namespace
-}  // extern "C++"
 
 hmx_status hmx_mlp_create(const float* params, hmx_mlp* out) {
     if (out) *out = nullptr;
@@ -1527,6 +1985,10 @@ hmx_status hmx_block_features(hmx_hmatrix h, float* features, float* ranks, int6
     if (!h || !n_adm || (h->n_adm > 0 && !features)) {
         set_err("invalid argument to hmx_block_features");
         return HMX_ERR_INVALID_ARG;
+    }
+    if (h->batched) {
+        set_err("batched handle: features belong to the individual problems");
+        return HMX_ERR_UNSUPPORTED;
     }
     if (*n_adm < h->n_adm) {
         set_err("capacity %lld below %lld admissible leaves", (long long)*n_adm,

@@ -209,7 +209,8 @@ hipError_t launch_tile_meta(const int64_t* tile_ptr, int64_t ntiles, int64_t np,
 int rows_per_unit(int fmode, int nmode);
 hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* tile_lo,
                              const int4* adm, const int4* dense, const int64_t* uoff,
-                             const void* Usrc, const void* soa, int64_t n, int d, KernelFn kern,
+                             const void* Usrc /* storage type */, const void* soa, int64_t n,
+                             int d, KernelFn kern,
                              void* upool, void* npool, int fmode, int nmode, hipStream_t st);
 // smode: storage mode 0 = F64, 1 = F32, 2 = BF16 storage with F32 arithmetic
 hipError_t launch_compact_v(const int4* blocks, int64_t nblocks, const int32_t* rank,
@@ -222,7 +223,7 @@ hipError_t launch_add_const(int64_t* data, int64_t n, int64_t c, hipStream_t st)
 // U compaction into the exact per-block pool (compute type)
 hipError_t launch_compact_u(const int4* blocks, int64_t nblocks, const int32_t* rank,
                             const int64_t* cap_uoff, int64_t cap_base, const int64_t* uoff,
-                            const void* Ucap, void* U, int f64, hipStream_t st);
+                            const void* Ucap, void* U, int smode, hipStream_t st);
 // chunk boundaries: bnd[k] = first block whose capacity offset is >= k * step
 hipError_t launch_chunk_bounds(const int64_t* cap_off, int64_t nb, int64_t step, int nchunks,
                                int64_t* bnd, hipStream_t st);
@@ -234,10 +235,15 @@ hipError_t launch_col_block(const int32_t* rank, const int64_t* toff, int64_t na
 hipError_t launch_far_phase1(const int4* adm, const int32_t* col_block, const int64_t* voff,
                              const int64_t* toff, int64_t ncols_total, const void* V,
                              void* vecpool, int64_t n, int smode, hipStream_t st);
+// config < 0: default tile shape; else shape config % kRowtileShapes with a
+// persistent grid of kPersistentGrid workgroups when config >= kRowtileShapes
+constexpr int kRowtileShapes = 5;
+constexpr int kRowtileConfigs = 2 * kRowtileShapes;
+constexpr unsigned kPersistentGrid = 2048;
 hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t* meta,
                           const int64_t* widx, const void* upool, const void* npool,
                           const void* vecpool, const int32_t* perm, double alpha, double beta,
-                          double sigma2, void* z, int max_tile, int fmode, int nmode,
+                          double sigma2, void* z, int max_tile, int fmode, int nmode, int config,
                           hipStream_t st);
 
 // conjugate gradients (k_blas.hip): FP64-accumulated inner products
@@ -289,5 +295,14 @@ hipError_t launch_scatter_i32(const int32_t* list, int64_t nl, const int32_t* sr
                               int add, hipStream_t st);
 hipError_t launch_scatter_i64(const int32_t* list, int64_t nl, const int64_t* src, int64_t* dst,
                               hipStream_t st);
+
+// batched build assembly (k_batch.hip)
+hipError_t launch_add_i32(int32_t* dst, const int32_t* src, int64_t cnt, int32_t c,
+                          hipStream_t st);
+hipError_t launch_shift_blocks(int4* dst, const int4* src, int64_t cnt, int32_t base,
+                               hipStream_t st);
+hipError_t launch_fill_i32(int32_t* dst, int64_t cnt, int32_t v, hipStream_t st);
+hipError_t launch_scale_coords(const double* src, int64_t n, int d, double scale, double* dst64,
+                               float* dst32, int64_t ntot, int64_t base, hipStream_t st);
 
 }  // namespace hmx

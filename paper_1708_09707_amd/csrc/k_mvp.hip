@@ -229,7 +229,7 @@ template <typename SU, typename SN, typename T>
 __global__ __launch_bounds__(256) void piece_data_kernel(
     const Piece* __restrict__ pieces, int64_t np, const int32_t* __restrict__ tile_lo,
     const int4* __restrict__ adm, const int4* __restrict__ dense,
-    const int64_t* __restrict__ uoff, const T* __restrict__ Usrc, const T* __restrict__ soa,
+    const int64_t* __restrict__ uoff, const SU* __restrict__ Usrc, const T* __restrict__ soa,
     int64_t n, int d, KernelEval<T> K, int R, SU* __restrict__ upool, SN* __restrict__ npool) {
     for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
         const Piece pc = pieces[p];
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void piece_data_kernel(
         const bool is_factor = pc.blk >= 0;
         const int4 bl = is_factor ? adm[pc.blk] : dense[-pc.blk - 1];
         const int m = bl.y - bl.x;
-        const T* __restrict__ src = is_factor ? Usrc + uoff[pc.blk] + pc.row0 : nullptr;
+        const SU* __restrict__ src = is_factor ? Usrc + uoff[pc.blk] + pc.row0 : nullptr;
         int i = threadIdx.x, c = 0;
         while (i >= ld) {
             i -= ld;
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(256) void piece_data_kernel(
         }
         for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
             if (is_factor) {
-                upool[pc.d_off + e] = Store<SU, T>::put(i < mt ? src[(int64_t)c * m + i] : (T)0);
+                upool[pc.d_off + e] = i < mt ? src[(int64_t)c * m + i] : (SU)0;
             } else {
                 T v = (T)0;
                 if (i < mt) {
@@ -294,42 +294,25 @@ __global__ void int_stats_kernel(const int32_t* __restrict__ a, int64_t n,
     }
 }
 
-// V compaction: the first r_b columns of each V_b from the capacity pool
+// compaction of the first r_b columns of each U_b (rows = 1: m rows) or V_b
+// (rows = 0: n rows) from the capacity pool into the exact-rank pool,
+// converted to the storage type
 template <typename S, typename T>
-__global__ __launch_bounds__(256) void compact_v_kernel(const int4* __restrict__ blocks,
-                                                        int64_t nblocks,
-                                                        const int32_t* __restrict__ rank,
-                                                        const int64_t* __restrict__ cv,
-                                                        int64_t cbase,
-                                                        const int64_t* __restrict__ ev,
-                                                        const T* __restrict__ Vcap,
-                                                        S* __restrict__ V) {
+__global__ __launch_bounds__(256) void compact_kernel(const int4* __restrict__ blocks,
+                                                      int64_t nblocks,
+                                                      const int32_t* __restrict__ rank,
+                                                      const int64_t* __restrict__ coff,
+                                                      int64_t cbase,
+                                                      const int64_t* __restrict__ eoff,
+                                                      const T* __restrict__ src,
+                                                      S* __restrict__ dst, int rows) {
     for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
         const int4 bl = blocks[b];
-        const int64_t nc = bl.w - bl.z, r = rank[b];
-        const T* sv = Vcap + (cv[b] - cbase);
-        S* dv = V + ev[b];
-        for (int64_t e = threadIdx.x; e < r * nc; e += blockDim.x) dv[e] = Store<S, T>::put(sv[e]);
-    }
-}
-
-// U compaction into the exact per-block pool (compute type, source of the
-// tile-major matrix pool)
-template <typename T>
-__global__ __launch_bounds__(256) void compact_u_kernel(const int4* __restrict__ blocks,
-                                                        int64_t nblocks,
-                                                        const int32_t* __restrict__ rank,
-                                                        const int64_t* __restrict__ cu,
-                                                        int64_t cbase,
-                                                        const int64_t* __restrict__ eu,
-                                                        const T* __restrict__ Ucap,
-                                                        T* __restrict__ U) {
-    for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
-        const int4 bl = blocks[b];
-        const int64_t m = bl.y - bl.x, r = rank[b];
-        const T* su = Ucap + (cu[b] - cbase);
-        T* du = U + eu[b];
-        for (int64_t e = threadIdx.x; e < r * m; e += blockDim.x) du[e] = su[e];
+        const int64_t len = rows ? bl.y - bl.x : bl.w - bl.z, r = rank[b];
+        const T* sv = src + (coff[b] - cbase);
+        S* dv = dst + eoff[b];
+        for (int64_t e = threadIdx.x; e < r * len; e += blockDim.x)
+            dv[e] = Store<S, T>::put(sv[e]);
     }
 }
 
@@ -560,33 +543,43 @@ __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
     }
 }
 
+// tile shapes of the row-tile kernel, (lanes per row group L, row vectors per
+// lane RV) = (16, 1), (32, 1), (64, 1), (64, 2), (64, 4); the grid is one
+// workgroup per tile or a fixed persistent grid looping over the tiles
+
 template <typename SU, typename SN, typename T>
 hipError_t rowtile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_t* meta,
                             const int64_t* widx, const void* upool, const void* npool,
                             const void* vecpool, const int32_t* perm, double alpha, double beta,
-                            double sigma2, void* z, int max_tile, hipStream_t st) {
+                            double sigma2, void* z, int max_tile, int config, hipStream_t st) {
     constexpr int VU = Dec<SU, T>::n, VN = Dec<SN, T>::n;
     constexpr int R = VU > VN ? VU : VN;
-    const int need = (max_tile + R - 1) / R;  // lane units per tile column
-    int L = 16, RV = 1;
-    while (L < need && L < 64) L *= 2;
-    while (L * RV < need && RV < 4) RV *= 2;
-    const unsigned grid = grid_cap(ntiles, 1 << 20);
+    int shape, persistent = 0;
+    if (config < 0) {
+        // default: the narrowest shape that covers the largest tile in one pass
+        const int need = (max_tile + R - 1) / R;  // lane units per tile column
+        int L = 16, RV = 1;
+        while (L < need && L < 64) L *= 2;
+        while (L * RV < need && RV < 4) RV *= 2;
+        shape = L == 16 ? 0 : (L == 32 ? 1 : (RV == 1 ? 2 : (RV == 2 ? 3 : 4)));
+    } else {
+        shape = config % kRowtileShapes;
+        persistent = config / kRowtileShapes;
+    }
+    const unsigned grid = persistent ? (unsigned)(ntiles < kPersistentGrid ? ntiles : kPersistentGrid)
+                                     : grid_cap(ntiles, 1 << 20);
 #define HMX_RT(LL, RR)                                                                       \
     hipLaunchKernelGGL((rowtile_kernel<SU, SN, T, LL, RR>), dim3(grid), dim3(kTileThreads), \
                        0, st, ntiles, tile_lo, meta, widx, (const SU*)upool,                 \
                        (const SN*)npool, (const T*)vecpool, perm, (T)alpha, (T)beta,        \
                        (T)sigma2, (T*)z)
-    if (L == 16)
-        HMX_RT(16, 1);
-    else if (L == 32)
-        HMX_RT(32, 1);
-    else if (RV == 1)
-        HMX_RT(64, 1);
-    else if (RV == 2)
-        HMX_RT(64, 2);
-    else
-        HMX_RT(64, 4);
+    switch (shape) {
+        case 0: HMX_RT(16, 1); break;
+        case 1: HMX_RT(32, 1); break;
+        case 2: HMX_RT(64, 1); break;
+        case 3: HMX_RT(64, 2); break;
+        default: HMX_RT(64, 4); break;
+    }
 #undef HMX_RT
     return hipGetLastError();
 }
@@ -662,7 +655,7 @@ hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* til
     const int R = rows_per_unit(fmode, nmode);
 #define HMX_PD(SU, SN, T)                                                                     \
     hipLaunchKernelGGL((piece_data_kernel<SU, SN, T>), dim3(grid), dim3(256), 0, st, pieces, \
-                       np, tile_lo, adm, dense, uoff, (const T*)Usrc, (const T*)soa, n, d,   \
+                       np, tile_lo, adm, dense, uoff, (const SU*)Usrc, (const T*)soa, n, d,  \
                        KernelEval<T>(kern), R, (SU*)upool, (SN*)npool)
     if (fmode == 0 && nmode == 0)
         HMX_PD(double, double, double);
@@ -678,38 +671,37 @@ hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* til
     return hipGetLastError();
 }
 
-hipError_t launch_compact_v(const int4* blocks, int64_t nblocks, const int32_t* rank,
-                            const int64_t* cap_voff, int64_t cap_base, const int64_t* voff,
-                            const void* Vcap, void* V, int smode, hipStream_t st) {
+namespace {
+hipError_t compact(const int4* blocks, int64_t nblocks, const int32_t* rank, const int64_t* coff,
+                   int64_t cbase, const int64_t* eoff, const void* src, void* dst, int smode,
+                   int rows, hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
     const unsigned grid = grid_cap(nblocks, 1 << 20);
     if (smode == 0)
-        hipLaunchKernelGGL((compact_v_kernel<double, double>), dim3(grid), dim3(256), 0, st,
-                           blocks, nblocks, rank, cap_voff, cap_base, voff, (const double*)Vcap,
-                           (double*)V);
+        hipLaunchKernelGGL((compact_kernel<double, double>), dim3(grid), dim3(256), 0, st, blocks,
+                           nblocks, rank, coff, cbase, eoff, (const double*)src, (double*)dst,
+                           rows);
     else if (smode == 1)
-        hipLaunchKernelGGL((compact_v_kernel<float, float>), dim3(grid), dim3(256), 0, st,
-                           blocks, nblocks, rank, cap_voff, cap_base, voff, (const float*)Vcap,
-                           (float*)V);
+        hipLaunchKernelGGL((compact_kernel<float, float>), dim3(grid), dim3(256), 0, st, blocks,
+                           nblocks, rank, coff, cbase, eoff, (const float*)src, (float*)dst, rows);
     else
-        hipLaunchKernelGGL((compact_v_kernel<uint16_t, float>), dim3(grid), dim3(256), 0, st,
-                           blocks, nblocks, rank, cap_voff, cap_base, voff, (const float*)Vcap,
-                           (uint16_t*)V);
+        hipLaunchKernelGGL((compact_kernel<uint16_t, float>), dim3(grid), dim3(256), 0, st,
+                           blocks, nblocks, rank, coff, cbase, eoff, (const float*)src,
+                           (uint16_t*)dst, rows);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_compact_v(const int4* blocks, int64_t nblocks, const int32_t* rank,
+                            const int64_t* cap_voff, int64_t cap_base, const int64_t* voff,
+                            const void* Vcap, void* V, int smode, hipStream_t st) {
+    return compact(blocks, nblocks, rank, cap_voff, cap_base, voff, Vcap, V, smode, 0, st);
 }
 
 hipError_t launch_compact_u(const int4* blocks, int64_t nblocks, const int32_t* rank,
                             const int64_t* cap_uoff, int64_t cap_base, const int64_t* uoff,
-                            const void* Ucap, void* U, int f64, hipStream_t st) {
-    if (nblocks == 0) return hipSuccess;
-    const unsigned grid = grid_cap(nblocks, 1 << 20);
-    if (f64)
-        hipLaunchKernelGGL(compact_u_kernel<double>, dim3(grid), dim3(256), 0, st, blocks, nblocks,
-                           rank, cap_uoff, cap_base, uoff, (const double*)Ucap, (double*)U);
-    else
-        hipLaunchKernelGGL(compact_u_kernel<float>, dim3(grid), dim3(256), 0, st, blocks, nblocks,
-                           rank, cap_uoff, cap_base, uoff, (const float*)Ucap, (float*)U);
-    return hipGetLastError();
+                            const void* Ucap, void* U, int smode, hipStream_t st) {
+    return compact(blocks, nblocks, rank, cap_uoff, cap_base, uoff, Ucap, U, smode, 1, st);
 }
 
 hipError_t launch_add_const(int64_t* data, int64_t n, int64_t c, hipStream_t st) {
@@ -779,24 +771,24 @@ hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t*
                           const int64_t* widx, const void* upool, const void* npool,
                           const void* vecpool, const int32_t* perm, double alpha, double beta,
                           double sigma2, void* z, int max_tile, int fmode, int nmode,
-                          hipStream_t st) {
+                          int config, hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
     if (fmode == 0 && nmode == 0)
         return rowtile_dispatch<double, double, double>(ntiles, tile_lo, meta, widx, upool, npool,
                                                         vecpool, perm, alpha, beta, sigma2, z,
-                                                        max_tile, st);
+                                                        max_tile, config, st);
     if (fmode == 1 && nmode == 1)
         return rowtile_dispatch<float, float, float>(ntiles, tile_lo, meta, widx, upool, npool,
                                                      vecpool, perm, alpha, beta, sigma2, z,
-                                                     max_tile, st);
+                                                     max_tile, config, st);
     if (fmode == 2 && nmode == 2)
         return rowtile_dispatch<uint16_t, uint16_t, float>(ntiles, tile_lo, meta, widx, upool,
                                                            npool, vecpool, perm, alpha, beta,
-                                                           sigma2, z, max_tile, st);
+                                                           sigma2, z, max_tile, config, st);
     if (fmode == 2 && nmode == 1)
         return rowtile_dispatch<uint16_t, float, float>(ntiles, tile_lo, meta, widx, upool,
                                                         npool, vecpool, perm, alpha, beta, sigma2,
-                                                        z, max_tile, st);
+                                                        z, max_tile, config, st);
     return hipErrorInvalidValue;
 }
 

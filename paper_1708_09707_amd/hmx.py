@@ -34,7 +34,9 @@ EXPORTS = ["hmx_params_default", "hmx_build", "hmx_matvec", "hmx_cg_solve", "hmx
            "hmx_status_string", "hmx_last_error", "hmx_mlp_create", "hmx_mlp_destroy",
            "hmx_mlp_set_params", "hmx_mlp_get_params", "hmx_mlp_fit_normalization",
            "hmx_mlp_forward", "hmx_mlp_loss_grad", "hmx_mlp_adam", "hmx_mlp_train",
-           "hmx_block_features"]
+           "hmx_block_features", "hmx_build_batched", "hmx_get_batch", "hmx_matvec_graph",
+           "hmx_graph_launch", "hmx_graph_destroy", "hmx_autotune", "hmx_set_tile_config"]
+HMX_TILE_CONFIGS = 10
 
 
 class hmx_kernel(C.Structure):
@@ -59,7 +61,8 @@ class hmx_stats(C.Structure):
                 ("u_entries", C.c_int64), ("v_entries", C.c_int64),
                 ("near_entries", C.c_int64), ("aca_columns", C.c_int64),
                 ("aca_chunks", C.c_int64), ("near_entry_bytes", C.c_int32),
-                ("reserved1", C.c_int32), ("matvec_bytes", C.c_double), ("phase_ms", C.c_double * 8),
+                ("tile_config", C.c_int32), ("matvec_bytes", C.c_double),
+                ("phase_ms", C.c_double * 8),
                 ("device_bytes", C.c_int64), ("level_sizes", C.c_int64 * 64),
                 ("aca_fallback", C.c_int64), ("aca_capacity", C.c_int64),
                 ("predict_ms", C.c_double)]
@@ -117,6 +120,14 @@ def lib():
         L.hmx_mlp_adam.argtypes = [P, P, f64, f64, f64, f64, P]
         L.hmx_mlp_train.argtypes = [P, P, P, i64, P, i64, i32, f64, f64, P, P]
         L.hmx_block_features.argtypes = [P, P, P, C.POINTER(i64), P]
+        L.hmx_build_batched.argtypes = [i32, P, C.c_int, P, P, P, C.POINTER(hmx_params), P,
+                                        C.POINTER(P)]
+        L.hmx_get_batch.argtypes = [P, C.POINTER(i32), P]
+        L.hmx_matvec_graph.argtypes = [P, P, P, C.c_int, f64, f64, i32, C.POINTER(P)]
+        L.hmx_graph_launch.argtypes = [P, P]
+        L.hmx_graph_destroy.argtypes = [P]
+        L.hmx_autotune.argtypes = [P, i32, P, C.POINTER(i32), P]
+        L.hmx_set_tile_config.argtypes = [P, i32]
         L.hmx_status_string.restype = C.c_char_p
         L.hmx_status_string.argtypes = [C.c_int]
         L.hmx_last_error.restype = C.c_char_p
@@ -385,6 +396,68 @@ def hmx_block_features(h, with_ranks=True, stream=None):
     return F[: na.value], (y[: na.value] if y is not None else None)
 
 
+def hmx_matvec_graph(h, x, z, alpha=1.0, beta=0.0, reps=1):
+    """Capture reps matvecs into a HIP graph; returns the graph handle."""
+    if not (x.is_cuda and z.is_cuda and x.is_contiguous() and z.is_contiguous()):
+        raise ValueError("x and z must be contiguous device tensors")
+    g = C.c_void_p()
+    _check(lib().hmx_matvec_graph(h, C.c_void_p(x.data_ptr()), C.c_void_p(z.data_ptr()),
+                                  _dtype_of(x), float(alpha), float(beta), int(reps),
+                                  C.byref(g)))
+    return g
+
+
+def hmx_graph_launch(g, stream=None):
+    _check(lib().hmx_graph_launch(g, _stream(stream)))
+
+
+def hmx_graph_destroy(g):
+    if g:
+        _check(lib().hmx_graph_destroy(g))
+
+
+def hmx_autotune(h, reps=5, stream=None):
+    """Returns (chosen configuration, mean ms per configuration)."""
+    ch = C.c_int32(-1)
+    t = np.zeros(HMX_TILE_CONFIGS)
+    _check(lib().hmx_autotune(h, int(reps), _stream(stream), C.byref(ch),
+                              t.ctypes.data_as(C.c_void_p)))
+    return ch.value, t
+
+
+def hmx_set_tile_config(h, config):
+    _check(lib().hmx_set_tile_config(h, int(config)))
+
+
+def hmx_build_batched(points_list, kernels, params: hmx_params, stream=None):
+    """points_list: device tensors (n_p, d_p), all float32 or all float64;
+    kernels: hmx_kernel per problem.  Returns (handle, offsets)."""
+    np_ = len(points_list)
+    if np_ < 1 or len(kernels) != np_:
+        raise ValueError("need one kernel per problem")
+    dt = _dtype_of(points_list[0])
+    for t in points_list:
+        if not t.is_cuda or not t.is_contiguous() or t.dim() != 2 or _dtype_of(t) != dt:
+            raise ValueError("points must be contiguous (n, d) device tensors of one dtype")
+    ptrs = (C.c_void_p * np_)(*[t.data_ptr() for t in points_list])
+    ns = (C.c_int64 * np_)(*[t.shape[0] for t in points_list])
+    ds = (C.c_int32 * np_)(*[t.shape[1] for t in points_list])
+    ks = (hmx_kernel * np_)(*kernels)
+    h = C.c_void_p()
+    _check(lib().hmx_build_batched(np_, ptrs, dt, ns, ds, ks, C.byref(params), _stream(stream),
+                                   C.byref(h)))
+    return h, hmx_get_batch(h)
+
+
+def hmx_get_batch(h):
+    """Problem offsets (nprob + 1 entries)."""
+    nprob = C.c_int32(0)
+    _check(lib().hmx_get_batch(h, C.byref(nprob), None))
+    off = np.zeros(nprob.value + 1, np.int64)
+    _check(lib().hmx_get_batch(h, C.byref(nprob), off.ctypes.data_as(C.c_void_p)))
+    return off
+
+
 class RankMLP:
     """Owner of an hmx_mlp rank predictor."""
 
@@ -432,6 +505,19 @@ class HMatrix:
         self.kernel = make_kernel(kernel, p0)
         self.n, self.d = int(points.shape[0]), int(points.shape[1])
         self.h = hmx_build(points, self.kernel, self.params, stream)
+        self.offsets = np.array([0, self.n], np.int64)
+
+    @classmethod
+    def batched(cls, points_list, kernel="gaussian", p0s=None, stream=None, **params):
+        """One block-diagonal handle over many problems (hmx_build_batched)."""
+        self = cls.__new__(cls)
+        self.params = hmx_params_default(**params)
+        p0s = [1.0] * len(points_list) if p0s is None else p0s
+        ks = [make_kernel(kernel, p) for p in p0s]
+        self.kernel = ks[0]
+        self.h, self.offsets = hmx_build_batched(points_list, ks, self.params, stream)
+        self.n, self.d = int(self.offsets[-1]), 3
+        return self
 
     def matvec(self, x, z=None, alpha=1.0, beta=0.0, stream=None):
         import torch
