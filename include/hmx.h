@@ -145,7 +145,13 @@ typedef struct {
     hmx_mlp mlp;             /* predictor for HMX_RANK_LEARNED (borrowed; must
                                 outlive hmx_build only), else NULL */
     int32_t learned_one_shot; /* HMX_RANK_LEARNED form: 0 sizing, 1 one-shot */
-    int32_t reserved[3];
+    int32_t near_recompute;  /* 1: the near field is not stored; every matvec
+                                evaluates the dense leaves' entries from the
+                                Morton-ordered coordinates in the compute type
+                                (the paper's no-storage mode for dense blocks,
+                                Section 5.4), same arithmetic as the stored
+                                assembly.  near_dtype is then ignored */
+    int32_t reserved[2];
 } hmx_params;
 
 /* Statistics of a built H-matrix (host struct). */

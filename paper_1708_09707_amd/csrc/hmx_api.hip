@@ -321,6 +321,10 @@ void init_handle(hmx_hmatrix_s* h, int64_t n, int d, const hmx_kernel& k, const 
     h->ssz = h->smode == 0 ? 8 : (h->smode == 1 ? 4 : 2);
     h->nmode = p.near_dtype == HMX_F64 ? 0 : (p.near_dtype == HMX_F32 ? 1 : 2);
     h->nsz = h->nmode == 0 ? 8 : (h->nmode == 1 ? 4 : 2);
+    if (p.near_recompute) {  // nothing stored: entries evaluated in every product
+        h->nmode = 3;
+        h->nsz = 0;
+    }
 }
 
 // validation shared by the single and the batched build
@@ -341,7 +345,11 @@ hmx_status check_params(const hmx_params& p) {
         set_err("storage_dtype must be F64 with F64 compute, F32 or BF16 with F32 compute");
         return HMX_ERR_UNSUPPORTED;
     }
-    {
+    if (p.near_recompute != 0 && p.near_recompute != 1) {
+        set_err("near_recompute must be 0 or 1");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (!p.near_recompute) {
         const bool ok = (p.near_dtype == p.storage_dtype) ||
                         (p.storage_dtype == HMX_BF16 && p.near_dtype == HMX_F32);
         if (!ok) {
@@ -893,7 +901,7 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
         check(launch_piece_gather(unsorted.as<Piece>(), vals.as<uint32_t>(), h->npieces,
                                   h->pieces.as<Piece>(), psu.as<int64_t>(), psn.as<int64_t>(),
                                   pc.as<int64_t>(), pcu.as<int64_t>(), h->tile_lo.as<int32_t>(), R,
-                                  st),
+                                  h->nmode != 3, st),
               "piece gather");
         h->upool_entries = scan(psu.as<int64_t>(), h->npieces);
         h->npool_entries = scan(psn.as<int64_t>(), h->npieces);
@@ -1158,7 +1166,8 @@ hipError_t matvec_launch(hmx_hmatrix_s* h, const void* x, void* z, double alpha,
         e = launch_rowtile(h->ntiles, h->tile_lo.as<int32_t>(), h->tile_meta.as<int64_t>(),
                            h->widx.as<int64_t>(), h->upool.p, h->npool.p, h->vecpool.p,
                            h->perm.as<int32_t>(), alpha, beta, h->prm.sigma2, z, h->max_tile,
-                           h->smode, h->nmode, config, st);
+                           h->smode, h->nmode, config, f64 ? h->soa64.p : h->soa32.p, h->n, h->d,
+                           KernelFn{(int)h->kern.kind, h->kern.p0}, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
     return e;
 }
@@ -1445,7 +1454,9 @@ hmx_status hmx_autotune(hmx_hmatrix h, int32_t reps, void* stream, int32_t* choi
                                       h->tile_meta.as<int64_t>(), h->widx.as<int64_t>(),
                                       h->upool.p, h->npool.p, h->vecpool.p,
                                       h->perm.as<int32_t>(), 1.0, 0.0, h->prm.sigma2, z.p,
-                                      h->max_tile, h->smode, h->nmode, c, st);
+                                      h->max_tile, h->smode, h->nmode, c,
+                                      h->f64 ? h->soa64.p : h->soa32.p, h->n, h->d,
+                                      KernelFn{(int)h->kern.kind, h->kern.p0}, st);
             };
             check(rt(), "tuning warm-up");
             check(hipEventRecord(e0, st), "event");

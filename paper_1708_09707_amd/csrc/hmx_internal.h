@@ -194,7 +194,8 @@ hipError_t launch_piece_fill(const int4* blocks, int64_t nblocks, const int32_t*
                              hipStream_t st);
 hipError_t launch_piece_gather(const Piece* src, const uint32_t* order, int64_t npieces,
                                Piece* dst, int64_t* size_u, int64_t* size_n, int64_t* cols,
-                               int64_t* cols_u, const int32_t* tile_lo, int R, hipStream_t st);
+                               int64_t* cols_u, const int32_t* tile_lo, int R, int near_stored,
+                               hipStream_t st);
 hipError_t launch_piece_layout(Piece* pieces, int64_t np, const int64_t* doff_u,
                                const int64_t* doff_n, const int64_t* coff, int64_t* widx,
                                hipStream_t st);
@@ -240,11 +241,12 @@ hipError_t launch_far_phase1(const int4* adm, const int32_t* col_block, const in
 constexpr int kRowtileShapes = 5;
 constexpr int kRowtileConfigs = 2 * kRowtileShapes;
 constexpr unsigned kPersistentGrid = 2048;
+// nmode 3: near field recomputed from soa (compute type, d x n) with kern
 hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t* meta,
                           const int64_t* widx, const void* upool, const void* npool,
                           const void* vecpool, const int32_t* perm, double alpha, double beta,
                           double sigma2, void* z, int max_tile, int fmode, int nmode, int config,
-                          hipStream_t st);
+                          const void* soa, int64_t n, int d, KernelFn kern, hipStream_t st);
 
 // conjugate gradients (k_blas.hip): FP64-accumulated inner products
 size_t cg_scratch_bytes();

@@ -94,6 +94,27 @@ struct Dec<uint16_t, float> {
     }
 };
 
+// near-field "storage" type of the recompute mode: entries are evaluated
+// from the coordinates in the matvec, with the compute type's row grouping
+template <typename T>
+struct Recompute {};
+template <typename S>
+struct is_recompute {
+    static constexpr bool value = false;
+};
+template <typename T>
+struct is_recompute<Recompute<T>> {
+    static constexpr bool value = true;
+};
+template <>
+struct Dec<Recompute<float>, float> {
+    static constexpr int n = 4;
+};
+template <>
+struct Dec<Recompute<double>, double> {
+    static constexpr int n = 2;
+};
+
 __device__ __forceinline__ u32x4 nt_load(const u32x4* p) { return __builtin_nontemporal_load(p); }
 
 // per-block sizes: mode 0: m * mult, 1: n * mult, 2: m * n, 3: r * m, 4: r * n,
@@ -161,7 +182,8 @@ __global__ void piece_gather_kernel(const Piece* __restrict__ src,
                                     Piece* __restrict__ dst, int64_t* __restrict__ size_u,
                                     int64_t* __restrict__ size_n, int64_t* __restrict__ cols,
                                     int64_t* __restrict__ cols_u,
-                                    const int32_t* __restrict__ tile_lo, int R) {
+                                    const int32_t* __restrict__ tile_lo, int R,
+                                    int near_stored) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= np) return;
     const Piece pc = src[order[i]];
@@ -170,7 +192,7 @@ __global__ void piece_gather_kernel(const Piece* __restrict__ src,
     const int64_t sz = (int64_t)tile_ld(mt, R) * pc.ncols;
     const bool f = pc.blk >= 0;
     size_u[i] = f ? sz : 0;
-    size_n[i] = f ? 0 : sz;
+    size_n[i] = f || !near_stored ? 0 : sz;
     cols[i] = pc.ncols;
     cols_u[i] = f ? pc.ncols : 0;
 }
@@ -233,6 +255,7 @@ __global__ __launch_bounds__(256) void piece_data_kernel(
     int64_t n, int d, KernelEval<T> K, int R, SU* __restrict__ upool, SN* __restrict__ npool) {
     for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
         const Piece pc = pieces[p];
+        if (is_recompute<SN>::value && pc.blk < 0) continue;  // near field evaluated per product
         const int32_t r0 = tile_lo[pc.tile];
         const int mt = tile_lo[pc.tile + 1] - r0;
         const int ld = tile_ld(mt, R);
@@ -249,7 +272,7 @@ __global__ __launch_bounds__(256) void piece_data_kernel(
         for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
             if (is_factor) {
                 upool[pc.d_off + e] = i < mt ? src[(int64_t)c * m + i] : (SU)0;
-            } else {
+            } else if constexpr (!is_recompute<SN>::value) {
                 T v = (T)0;
                 if (i < mt) {
                     T x[3], y[3];
@@ -485,19 +508,67 @@ __device__ __forceinline__ void rowtile_segment(const S* __restrict__ base, int 
     }
 }
 
+// near-field columns of a tile evaluated on the fly (recompute mode): the
+// column's point coordinates are staged in LDS with its weight, each lane
+// keeps the coordinates of its rows; phi as in the stored mode's assembly.
+// Rows past the tile (padding) read the tile's last point and are never
+// written out.
+template <typename T, int L, int RV, int R, int G>
+__device__ __forceinline__ void rowtile_near_eval(const T* __restrict__ soa, int64_t n, int d,
+                                                  const KernelEval<T>& K, int64_t row0,
+                                                  int rows, int64_t nk,
+                                                  const int64_t* __restrict__ wi,
+                                                  const T* __restrict__ vec, T* __restrict__ sw,
+                                                  T* __restrict__ sy, int g, int q, int nvec,
+                                                  T (&acc)[RV][R]) {
+    T xr[RV][R][3];
+#pragma unroll
+    for (int v = 0; v < RV; ++v)
+#pragma unroll
+        for (int e = 0; e < R; ++e) {
+            int i = (v * L + q) * R + e;
+            i = i < rows ? i : rows - 1;
+            load_pt(soa, n, d, row0 + i, xr[v][e]);
+        }
+    for (int64_t kc = 0; kc < nk; kc += kChunk) {
+        const int cnt = (nk - kc) < kChunk ? (int)(nk - kc) : kChunk;
+        for (int j = threadIdx.x; j < cnt; j += kTileThreads) {
+            const int64_t w = wi[kc + j];
+            sw[j] = vec[w];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) sy[k * kChunk + j] = k < d ? soa[(int64_t)k * n + w] : (T)0;
+        }
+        __syncthreads();
+        for (int c = g; c < cnt; c += G) {
+            const T w0 = sw[c];
+            const T y[3] = {sy[c], sy[kChunk + c], sy[2 * kChunk + c]};
+#pragma unroll
+            for (int v = 0; v < RV; ++v) {
+                if (v * L + q < nvec) {
+#pragma unroll
+                    for (int e = 0; e < R; ++e) acc[v][e] += phi(K, xr[v][e], y, d) * w0;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <typename SU, typename SN, typename T, int L, int RV>
 __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
     int64_t ntiles, const int32_t* __restrict__ tile_lo, const int64_t* __restrict__ meta,
     const int64_t* __restrict__ widx, const SU* __restrict__ upool, const SN* __restrict__ npool,
     const T* __restrict__ vec, const int32_t* __restrict__ perm, T alpha, T beta, T sigma2,
-    T* __restrict__ z) {
+    T* __restrict__ z, const T* __restrict__ soa, int64_t n, int d, KernelEval<T> K) {
     constexpr int VU = Dec<SU, T>::n, VN = Dec<SN, T>::n;
     constexpr int R = VU > VN ? VU : VN;  // rows per lane unit
     constexpr int SUB = 64 / L;
     constexpr int G = 4 * SUB;
     constexpr int RPG = L * RV * R;  // rows per pass
+    constexpr bool NR = is_recompute<SN>::value;
     __shared__ T red[G * RPG];
     __shared__ T sw[kChunk];
+    __shared__ T sy[NR ? 3 * kChunk : 1];
     const int tid = threadIdx.x, lane = tid & 63;
     // the group index is wave-uniform when a group is a whole wave
     const int g = (SUB == 1) ? __builtin_amdgcn_readfirstlane(tid >> 6) : (tid >> 6) * SUB + lane / L;
@@ -509,7 +580,7 @@ __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
         const int64_t k0 = meta[4 * t], k1 = meta[4 * t + 4];
         const int64_t ku = meta[4 * t + 5] - meta[4 * t + 1];  // factor columns of the tile
         const SU* __restrict__ ubase = upool + meta[4 * t + 2];
-        const SN* __restrict__ nbase = npool + meta[4 * t + 3];
+        const SN* __restrict__ nbase = NR ? npool : npool + meta[4 * t + 3];
         for (int rb = 0; rb < ld; rb += RPG) {
             const int nvec = ((ld - rb) < RPG ? (ld - rb) : RPG) / R;  // lane units in this pass
             T acc[RV][R];
@@ -519,8 +590,13 @@ __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
                 for (int e = 0; e < R; ++e) acc[v][e] = 0;
             rowtile_segment<SU, T, L, RV, R, G>(ubase + rb, ld, ku, widx + k0, vec, sw, g, q,
                                                  nvec, acc);
-            rowtile_segment<SN, T, L, RV, R, G>(nbase + rb, ld, k1 - k0 - ku, widx + k0 + ku, vec,
-                                                 sw, g, q, nvec, acc);
+            if constexpr (NR)
+                rowtile_near_eval<T, L, RV, R, G>(soa, n, d, K, (int64_t)r0 + rb, mt - rb,
+                                                  k1 - k0 - ku, widx + k0 + ku, vec, sw, sy, g, q,
+                                                  nvec, acc);
+            else
+                rowtile_segment<SN, T, L, RV, R, G>(nbase + rb, ld, k1 - k0 - ku, widx + k0 + ku,
+                                                     vec, sw, g, q, nvec, acc);
             // sum the G partial row sets in a fixed order
 #pragma unroll
             for (int v = 0; v < RV; ++v)
@@ -551,7 +627,8 @@ template <typename SU, typename SN, typename T>
 hipError_t rowtile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_t* meta,
                             const int64_t* widx, const void* upool, const void* npool,
                             const void* vecpool, const int32_t* perm, double alpha, double beta,
-                            double sigma2, void* z, int max_tile, int config, hipStream_t st) {
+                            double sigma2, void* z, int max_tile, int config, const void* soa,
+                            int64_t n, int d, KernelFn kern, hipStream_t st) {
     constexpr int VU = Dec<SU, T>::n, VN = Dec<SN, T>::n;
     constexpr int R = VU > VN ? VU : VN;
     int shape, persistent = 0;
@@ -572,7 +649,7 @@ hipError_t rowtile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_
     hipLaunchKernelGGL((rowtile_kernel<SU, SN, T, LL, RR>), dim3(grid), dim3(kTileThreads), \
                        0, st, ntiles, tile_lo, meta, widx, (const SU*)upool,                 \
                        (const SN*)npool, (const T*)vecpool, perm, (T)alpha, (T)beta,        \
-                       (T)sigma2, (T*)z)
+                       (T)sigma2, (T*)z, (const T*)soa, n, d, KernelEval<T>(kern))
     switch (shape) {
         case 0: HMX_RT(16, 1); break;
         case 1: HMX_RT(32, 1); break;
@@ -609,10 +686,12 @@ hipError_t launch_piece_fill(const int4* blocks, int64_t nblocks, const int32_t*
 
 hipError_t launch_piece_gather(const Piece* src, const uint32_t* order, int64_t npieces,
                                Piece* dst, int64_t* size_u, int64_t* size_n, int64_t* cols,
-                               int64_t* cols_u, const int32_t* tile_lo, int R, hipStream_t st) {
+                               int64_t* cols_u, const int32_t* tile_lo, int R, int near_stored,
+                               hipStream_t st) {
     if (npieces == 0) return hipSuccess;
     hipLaunchKernelGGL(piece_gather_kernel, dim3((unsigned)((npieces + 255) / 256)), dim3(256), 0,
-                       st, src, order, npieces, dst, size_u, size_n, cols, cols_u, tile_lo, R);
+                       st, src, order, npieces, dst, size_u, size_n, cols, cols_u, tile_lo, R,
+                       near_stored);
     return hipGetLastError();
 }
 
@@ -643,7 +722,9 @@ hipError_t launch_tile_meta(const int64_t* tile_ptr, int64_t ntiles, int64_t np,
 // storage modes: 0 = F64 (F64 arithmetic), 1 = F32, 2 = BF16 (F32 arithmetic)
 int rows_per_unit(int fmode, int nmode) {
     auto v = [](int m) { return m == 0 ? 2 : (m == 1 ? 4 : 8); };
-    return v(fmode) > v(nmode) ? v(fmode) : v(nmode);
+    // recompute mode (3): the compute type's grouping (F64 with F64 factors)
+    const int vn = nmode == 3 ? (fmode == 0 ? 2 : 4) : v(nmode);
+    return v(fmode) > vn ? v(fmode) : vn;
 }
 
 hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* tile_lo,
@@ -665,6 +746,12 @@ hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* til
         HMX_PD(uint16_t, uint16_t, float);
     else if (fmode == 2 && nmode == 1)
         HMX_PD(uint16_t, float, float);
+    else if (nmode == 3 && fmode == 0)
+        HMX_PD(double, Recompute<double>, double);
+    else if (nmode == 3 && fmode == 1)
+        HMX_PD(float, Recompute<float>, float);
+    else if (nmode == 3 && fmode == 2)
+        HMX_PD(uint16_t, Recompute<float>, float);
     else
         return hipErrorInvalidValue;
 #undef HMX_PD
@@ -771,24 +858,21 @@ hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t*
                           const int64_t* widx, const void* upool, const void* npool,
                           const void* vecpool, const int32_t* perm, double alpha, double beta,
                           double sigma2, void* z, int max_tile, int fmode, int nmode,
-                          int config, hipStream_t st) {
+                          int config, const void* soa, int64_t n, int d, KernelFn kern,
+                          hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
-    if (fmode == 0 && nmode == 0)
-        return rowtile_dispatch<double, double, double>(ntiles, tile_lo, meta, widx, upool, npool,
-                                                        vecpool, perm, alpha, beta, sigma2, z,
-                                                        max_tile, config, st);
-    if (fmode == 1 && nmode == 1)
-        return rowtile_dispatch<float, float, float>(ntiles, tile_lo, meta, widx, upool, npool,
-                                                     vecpool, perm, alpha, beta, sigma2, z,
-                                                     max_tile, config, st);
-    if (fmode == 2 && nmode == 2)
-        return rowtile_dispatch<uint16_t, uint16_t, float>(ntiles, tile_lo, meta, widx, upool,
-                                                           npool, vecpool, perm, alpha, beta,
-                                                           sigma2, z, max_tile, config, st);
-    if (fmode == 2 && nmode == 1)
-        return rowtile_dispatch<uint16_t, float, float>(ntiles, tile_lo, meta, widx, upool,
-                                                        npool, vecpool, perm, alpha, beta, sigma2,
-                                                        z, max_tile, config, st);
+#define HMX_RTD(SU, SN, T)                                                                     \
+    return rowtile_dispatch<SU, SN, T>(ntiles, tile_lo, meta, widx, upool, npool, vecpool, perm, \
+                                       alpha, beta, sigma2, z, max_tile, config, soa, n, d, kern, \
+                                       st)
+    if (fmode == 0 && nmode == 0) HMX_RTD(double, double, double);
+    if (fmode == 1 && nmode == 1) HMX_RTD(float, float, float);
+    if (fmode == 2 && nmode == 2) HMX_RTD(uint16_t, uint16_t, float);
+    if (fmode == 2 && nmode == 1) HMX_RTD(uint16_t, float, float);
+    if (fmode == 0 && nmode == 3) HMX_RTD(double, Recompute<double>, double);
+    if (fmode == 1 && nmode == 3) HMX_RTD(float, Recompute<float>, float);
+    if (fmode == 2 && nmode == 3) HMX_RTD(uint16_t, Recompute<float>, float);
+#undef HMX_RTD
     return hipErrorInvalidValue;
 }
 

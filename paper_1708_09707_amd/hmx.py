@@ -50,7 +50,8 @@ class hmx_params(C.Structure):
                 ("near_dtype", C.c_int),
                 ("rank_mode", C.c_int), ("aca_chunk_mb", C.c_int32),
                 ("aca_only", C.c_int32), ("mlp", C.c_void_p),
-                ("learned_one_shot", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("learned_one_shot", C.c_int32), ("near_recompute", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class hmx_stats(C.Structure):
