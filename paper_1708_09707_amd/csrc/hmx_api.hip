@@ -118,6 +118,25 @@ struct DevBuf {
     }
 };
 
+// a second stream (default priority, non-blocking) owned for one build
+struct AuxStream {
+    hipStream_t s = nullptr;
+    AuxStream() {
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            s = nullptr;  // the classes then run one after the other
+        }
+    }
+    ~AuxStream() {
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+    }
+    AuxStream(const AuxStream&) = delete;
+    AuxStream& operator=(const AuxStream&) = delete;
+};
+
 void check(hipError_t e, const char* what) {
     if (e != hipSuccess) {
         set_err("%s: %s", what, hipGetErrorString(e));
@@ -547,14 +566,16 @@ void stage_partition(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t
 // how the ACA treats the admissible leaves of a handle: size classes and
 // (learned sizing) the predicted targets
 struct AcaPlan {
-    const int32_t* cls = nullptr;  // per leaf, non-decreasing; < split: 512-thread class
-    int split = 0;
-    int big_words = 2, small_words = 2;  // LDS mask words of the two classes
+    const int32_t* cls = nullptr;  // per leaf, non-decreasing; < split: 512-thread class,
+    int split = 0, split2 = 0;     // < split2: 256-thread class, else single wave
+    int big_words = 2, med_words = 2, tiny_words = 2;  // LDS mask words per class
     const int32_t* rt = nullptr;         // learned targets, or null
 };
 
-// rows above which a cluster's blocks run in the 512-thread class
+// clusters of kBigRows or more points put their blocks in the 512-thread
+// class; clusters of at most kTinyRows points in the single-wave class
 constexpr int64_t kBigRows = 4096;
+constexpr int64_t kTinyRows = 256;
 
 // size classes of a single problem by tree level: clusters at level l hold at
 // most s_l points (s_0 = n, s_{l+1} = ceil(s_l / 2)); levels whose clusters
@@ -566,6 +587,12 @@ AcaPlan level_plan(const hmx_hmatrix_s* h) {
         s_split = (s_split + 1) / 2;
         ++p.split;
     }
+    int64_t s_split2 = s_split;
+    p.split2 = p.split;
+    while (s_split2 > kTinyRows) {
+        s_split2 = (s_split2 + 1) / 2;
+        ++p.split2;
+    }
     const int64_t big = h->big_adm;
     const int64_t words = 2 * ((big + 31) / 32);
     if (words * 4 > 64 * 1024) {
@@ -574,7 +601,8 @@ AcaPlan level_plan(const hmx_hmatrix_s* h) {
     }
     p.cls = h->adm_level.as<int32_t>();
     p.big_words = (int)std::max<int64_t>(words, 2);
-    p.small_words = (int)std::max<int64_t>(2 * ((std::min(s_split, big) + 31) / 32), 2);
+    p.med_words = (int)std::max<int64_t>(2 * ((std::min(s_split, big) + 31) / 32), 2);
+    p.tiny_words = (int)std::max<int64_t>(2 * ((std::min(s_split2, big) + 31) / 32), 2);
     return p;
 }
 
@@ -649,6 +677,7 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
             budget_bytes = std::max<int64_t>((int64_t)((fr + cached) / 10 * 4), (int64_t)1 << 30);
         }
         const int64_t budget = std::max<int64_t>(budget_bytes / (int64_t)esz, 1);
+        AuxStream aux1, aux2;  // the smaller block classes run beside the large one
         AcaArgs a{};
         a.soa = f64 ? h->soa64.p : h->soa32.p;
         a.soa64 = h->soa64.as<double>();
@@ -661,7 +690,8 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
         a.eps0 = h->prm.aca_eps0 >= 0 ? h->prm.aca_eps0 : (f64 ? 1e-14 : 1e-7);
         a.fixed = h->prm.rank_mode == HMX_RANK_FIXED;
         a.big_words = plan.big_words;
-        a.small_words = plan.small_words;
+        a.med_words = plan.med_words;
+        a.tiny_words = plan.tiny_words;
         DevBuf split;
         alloc(split, 8, "class split");
 
@@ -674,6 +704,9 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
             check(launch_level_split(levels, nb, plan.split, split.as<int64_t>(), st),
                   "class split");
             const int64_t nbig_all = read_scalar(split.as<int64_t>(), st);
+            check(launch_level_split(levels, nb, plan.split2, split.as<int64_t>(), st),
+                  "class split");
+            const int64_t nmed_all = read_scalar(split.as<int64_t>(), st);
             DevBuf cu, cv, cc, Ucap, Vcap;
             alloc(cu, (nb + 1) * 8, "U capacity offsets");
             alloc(cv, (nb + 1) * 8, "V capacity offsets");
@@ -731,9 +764,10 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                 a.vbase = hcv[k];
                 a.rtarget = rt ? rt + b0 : nullptr;
                 a.nbig = std::max<int64_t>(0, std::min(nbig_all - b0, nbk));
+                a.nmed = std::max<int64_t>(0, std::min(nmed_all - b0, nbk));
                 a.rank = rank + b0;
                 a.steps = steps + b0;
-                check(launch_aca(a, f64, st), "aca");
+                check(launch_aca(a, f64, st, aux1.s, aux2.s), "aca");
                 check(hipStreamSynchronize(st), "aca sync");
                 aca_ms += ms_since(ta);
                 if (aca_only) continue;
@@ -974,11 +1008,11 @@ void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
     const bool learned = u->prm.rank_mode == HMX_RANK_LEARNED;
     std::vector<std::unique_ptr<hmx_hmatrix_s>> parts(np);
     std::unique_ptr<DevBuf[]> rts(new DevBuf[np]);
-    std::vector<int64_t> nbig(np, 0);
+    std::vector<int64_t> nbig(np, 0), nmed(np, 0);
     hmx_stats& S = u->stats;
     DevBuf split;
     alloc(split, 8, "class split");
-    int64_t nadm = 0, ndense = 0, ntiles = 0, big = 0, nbig_tot = 0;
+    int64_t nadm = 0, ndense = 0, ntiles = 0, big = 0, nbig_tot = 0, nmed_tot = 0;
     for (int p = 0; p < np; ++p) {
         hmx_hmatrix_s* hp = new hmx_hmatrix_s();
         parts[p].reset(hp);
@@ -991,11 +1025,16 @@ void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
                                      split.as<int64_t>(), st),
                   "class split");
             nbig[p] = read_scalar(split.as<int64_t>(), st);
+            check(launch_level_split(hp->adm_level.as<int32_t>(), hp->n_adm, lp.split2,
+                                     split.as<int64_t>(), st),
+                  "class split");
+            nmed[p] = read_scalar(split.as<int64_t>(), st);
         }
         nadm += hp->n_adm;
         ndense += hp->n_dense;
         ntiles += hp->ntiles;
         nbig_tot += nbig[p];
+        nmed_tot += nmed[p] - nbig[p];
         big = std::max(big, hp->big_adm);
         u->max_tile = std::max(u->max_tile, hp->max_tile);
         for (int k = 0; k < 3; ++k) S.phase_ms[k] += hp->stats.phase_ms[k];
@@ -1018,7 +1057,9 @@ void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
     DevBuf cls, rt;
     alloc(cls, std::max<int64_t>(nadm, 1) * 4, "size classes");
     if (learned) alloc(rt, std::max<int64_t>(nadm, 1) * 4, "rank targets");
-    int64_t base = 0, tbase = 0, abig = 0, asmall = nbig_tot, dcur = 0;
+    // sections: the 512-thread class of every problem, then the 256-thread
+    // class, then the single-wave class
+    int64_t base = 0, tbase = 0, acur[3] = {0, nbig_tot, nbig_tot + nmed_tot}, dcur = 0;
     u->offsets.assign(1, 0);
     for (int p = 0; p < np; ++p) {
         hmx_hmatrix_s* hp = parts[p].get();
@@ -1040,27 +1081,24 @@ void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
         check(launch_add_i32(u->tile_lo.as<int32_t>() + tbase, hp->tile_lo.as<int32_t>(),
                              hp->ntiles, b32, st),
               "tile starts");
-        // the upper-level class of every problem first, then the rest
-        const int64_t nb = nbig[p], ns = hp->n_adm - nbig[p];
+        // the problem's three class ranges into the three sections
+        const int64_t lo3[3] = {0, nbig[p], nmed[p]};
+        const int64_t hi3[3] = {nbig[p], nmed[p], hp->n_adm};
         const int4* ha = hp->adm.as<int4>();
         const int32_t* hl = hp->adm_level.as<int32_t>();
-        check(launch_shift_blocks(u->adm.as<int4>() + abig, ha, nb, b32, st), "adm");
-        check(launch_shift_blocks(u->adm.as<int4>() + asmall, ha + nb, ns, b32, st), "adm");
-        check(hipMemcpyAsync(u->adm_level.as<int32_t>() + abig, hl, nb * 4,
-                             hipMemcpyDeviceToDevice, st),
-              "adm levels");
-        check(hipMemcpyAsync(u->adm_level.as<int32_t>() + asmall, hl + nb, ns * 4,
-                             hipMemcpyDeviceToDevice, st),
-              "adm levels");
-        check(launch_fill_i32(cls.as<int32_t>() + abig, nb, 0, st), "classes");
-        check(launch_fill_i32(cls.as<int32_t>() + asmall, ns, 1, st), "classes");
-        if (learned && hp->n_adm > 0) {
-            check(hipMemcpyAsync(rt.as<int32_t>() + abig, rts[p].p, nb * 4,
+        for (int c = 0; c < 3; ++c) {
+            const int64_t cnt = hi3[c] - lo3[c];
+            check(launch_shift_blocks(u->adm.as<int4>() + acur[c], ha + lo3[c], cnt, b32, st),
+                  "adm");
+            check(hipMemcpyAsync(u->adm_level.as<int32_t>() + acur[c], hl + lo3[c], cnt * 4,
                                  hipMemcpyDeviceToDevice, st),
-                  "targets");
-            check(hipMemcpyAsync(rt.as<int32_t>() + asmall, rts[p].as<int32_t>() + nb, ns * 4,
-                                 hipMemcpyDeviceToDevice, st),
-                  "targets");
+                  "adm levels");
+            check(launch_fill_i32(cls.as<int32_t>() + acur[c], cnt, c, st), "classes");
+            if (learned && cnt > 0)
+                check(hipMemcpyAsync(rt.as<int32_t>() + acur[c], rts[p].as<int32_t>() + lo3[c],
+                                     cnt * 4, hipMemcpyDeviceToDevice, st),
+                      "targets");
+            acur[c] += cnt;
         }
         check(launch_shift_blocks(u->dense.as<int4>() + dcur, hp->dense.as<int4>(), hp->n_dense,
                                   b32, st),
@@ -1070,8 +1108,6 @@ void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
               "dense levels");
         base += np_;
         tbase += hp->ntiles;
-        abig += nb;
-        asmall += ns;
         dcur += hp->n_dense;
         u->offsets.push_back(base);
     }
@@ -1095,9 +1131,11 @@ void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
         }
         plan.cls = cls.as<int32_t>();
         plan.split = 1;
+        plan.split2 = 2;
         plan.big_words = (int)std::max<int64_t>(words, 2);
-        plan.small_words =
+        plan.med_words =
             (int)std::max<int64_t>(2 * ((std::min(kBigRows - 1, big) + 31) / 32), 2);
+        plan.tiny_words = (int)std::max<int64_t>(2 * ((std::min(kTinyRows, big) + 31) / 32), 2);
         plan.rt = learned ? rt.as<int32_t>() : nullptr;
     }
     stage_factors(u, plan, st, t_all);

@@ -160,12 +160,16 @@ struct AcaArgs {
     int32_t* rank;
     int32_t* steps;
     // size classes: blocks [0, nbig) (upper tree levels) run in 512-thread
-    // workgroups, the rest in 256-thread ones; each class reserves the
-    // used-row + used-col bitmask words of its largest block
-    int64_t nbig;
-    int big_words, small_words;
+    // workgroups, [nbig, nmed) in 256-thread ones, the rest (leaf levels) in
+    // single-wave ones; each class reserves the used-row + used-col bitmask
+    // words of its largest block
+    int64_t nbig, nmed;
+    int big_words, med_words, tiny_words;
 };
-hipError_t launch_aca(const AcaArgs& a, int f64, hipStream_t st);
+// aux1, aux2: optional streams on which the 256-thread and single-wave
+// classes run concurrently with the 512-thread one
+hipError_t launch_aca(const AcaArgs& a, int f64, hipStream_t st, hipStream_t aux1,
+                      hipStream_t aux2);
 // *out = first index with level[index] >= lvl in the non-decreasing level[0..nb)
 hipError_t launch_level_split(const int32_t* level, int64_t nb, int lvl, int64_t* out,
                               hipStream_t st);

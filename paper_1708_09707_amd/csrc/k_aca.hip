@@ -3,8 +3,9 @@
 // One workgroup per admissible block, each running its own rank loop, so
 // blocks stop independently (no global "voting" bounded by the slowest
 // block).  Blocks of the upper tree levels (many rows) get 512-thread
-// workgroups, the rest 256; the canonical leaf order is level order, so the
-// large class is a prefix of every block list.  Per step r:
+// workgroups, those of the leaf levels (at most 256 rows) one wave, the rest
+// 256 threads; the canonical leaf order is level order, so each class is a
+// contiguous range of every block list.  Per step r:
 //   1. residual column  u^ = A[:, j] - sum_{l<r} u_l (v_l)_j   (rows over threads)
 //   2. row pivot        i  = argmax over unused rows |u^_i| (lowest index on ties)
 //      a column whose largest residual entry is <= eps0 times the column's own
@@ -39,6 +40,7 @@ namespace hmx {
 namespace {
 
 constexpr int kDotCols = 8;     // previous columns per inner-product pass
+constexpr int kRows = 4;        // rows per thread per residual pass
 constexpr int kBigThreads = 512;  // workgroup size of the upper-level class
 
 template <int NT>
@@ -262,6 +264,9 @@ __global__ __launch_bounds__(NT) void aca_kernel(
         R = nc < R ? nc : R;
         T* __restrict__ U = Upool + (uoff[b] - ubase);
         T* __restrict__ V = Vpool + (voff[b] - vbase);
+        // columns l < r are only read in a step, column r only written
+        const T* __restrict__ Uread = U;
+        const T* __restrict__ Vread = V;
         const int mw = (m + 31) >> 5, nw = (nc + 31) >> 5;
         if (mw + nw > lds_words) {  // outside this launch's size class (never by construction)
             if (tid == 0) {
@@ -314,19 +319,40 @@ __global__ __launch_bounds__(NT) void aca_kernel(
             load_pt(soa, n, d, (int64_t)bl.z + j, yj);
             Arg<T> am{(T)-1, INT_MAX, (T)0};
             double colmax = 0.0;
-            for (int i = tid; i < m; i += NT) {
-                T xi[3];
-                load_pt(soa, n, d, (int64_t)bl.x + i, xi);
-                T a = phi(K, xi, yj, d);
-                const double aa0 = a < (T)0 ? -(double)a : (double)a;
-                colmax = aa0 > colmax ? aa0 : colmax;
-                for (int l = 0; l < r; ++l) a -= U[(int64_t)l * m + i] * sh.vec[l];
-                U[(int64_t)r * m + i] = a;
-                const T aa = a < (T)0 ? -a : a;
-                if (!bit_get(rmask, i) && aa > am.best) {
-                    am.best = aa;
-                    am.idx = i;
-                    am.val = a;
+            // kRows rows per thread per pass, so kRows * r loads are in flight
+            for (int i0 = tid; i0 < m; i0 += kRows * NT) {
+                T a[kRows];
+#pragma unroll
+                for (int k = 0; k < kRows; ++k) {
+                    const int i = i0 + k * NT;
+                    a[k] = 0;
+                    if (i < m) {
+                        T xi[3];
+                        load_pt(soa, n, d, (int64_t)bl.x + i, xi);
+                        a[k] = phi(K, xi, yj, d);
+                        const double aa0 = a[k] < (T)0 ? -(double)a[k] : (double)a[k];
+                        colmax = aa0 > colmax ? aa0 : colmax;
+                    }
+                }
+                for (int l = 0; l < r; ++l) {
+                    const T vl = sh.vec[l];
+                    const T* __restrict__ Ul = Uread + (int64_t)l * m;
+#pragma unroll
+                    for (int k = 0; k < kRows; ++k)
+                        if (i0 + k * NT < m) a[k] -= Ul[i0 + k * NT] * vl;
+                }
+#pragma unroll
+                for (int k = 0; k < kRows; ++k) {
+                    const int i = i0 + k * NT;
+                    if (i < m) {
+                        U[(int64_t)r * m + i] = a[k];
+                        const T aa = a[k] < (T)0 ? -a[k] : a[k];
+                        if (!bit_get(rmask, i) && aa > am.best) {
+                            am.best = aa;
+                            am.idx = i;
+                            am.val = a[k];
+                        }
+                    }
                 }
             }
             am = block_argmax(am, sh);
@@ -359,16 +385,30 @@ __global__ __launch_bounds__(NT) void aca_kernel(
                 double acc[DC];
 #pragma unroll
                 for (int k = 0; k < DC; ++k) acc[k] = 0.0;
-                for (int i = tid; i < m; i += NT) {
-                    T u = Ur[i];
-                    if (c0 == 0) {
-                        u = u / piv;
-                        Ur[i] = u;
-                        nu2 += (double)u * (double)u;
+                for (int i0 = tid; i0 < m; i0 += kRows * NT) {
+                    T u[kRows];
+#pragma unroll
+                    for (int e = 0; e < kRows; ++e) {
+                        const int i = i0 + e * NT;
+                        u[e] = 0;
+                        if (i < m) {
+                            u[e] = Ur[i];
+                            if (c0 == 0) {
+                                u[e] = u[e] / piv;
+                                Ur[i] = u[e];
+                                nu2 += (double)u[e] * (double)u[e];
+                            }
+                        }
                     }
 #pragma unroll
-                    for (int k = 0; k < DC; ++k)
-                        if (k < nk) acc[k] += (double)u * (double)Uc[k * m + i];
+                    for (int e = 0; e < kRows; ++e) {
+                        const int i = i0 + e * NT;
+                        if (i < m) {
+#pragma unroll
+                            for (int k = 0; k < DC; ++k)
+                                if (k < nk) acc[k] += (double)u[e] * (double)Uc[k * m + i];
+                        }
+                    }
                 }
                 if (nk > 0) block_sum_cols<DC>(acc, nk, sh.gu + c0, sh);
             }
@@ -381,18 +421,38 @@ __global__ __launch_bounds__(NT) void aca_kernel(
             load_pt(soa, n, d, (int64_t)bl.x + ip, xp);
             double nv2 = 0.0;
             Arg<T> cm{(T)-1, INT_MAX, (T)0};
-            for (int q = tid; q < nc; q += NT) {
-                T yq[3];
-                load_pt(soa, n, d, (int64_t)bl.z + q, yq);
-                T a = phi(K, xp, yq, d);
-                for (int l = 0; l < r; ++l) a -= sh.vec[l] * V[(int64_t)l * nc + q];
-                V[(int64_t)r * nc + q] = a;
-                nv2 += (double)a * (double)a;
-                const T aa = a < (T)0 ? -a : a;
-                if (!bit_get(cmask, q) && aa > cm.best) {
-                    cm.best = aa;
-                    cm.idx = q;
-                    cm.val = a;
+            for (int q0 = tid; q0 < nc; q0 += kRows * NT) {
+                T a[kRows];
+#pragma unroll
+                for (int k = 0; k < kRows; ++k) {
+                    const int q = q0 + k * NT;
+                    a[k] = 0;
+                    if (q < nc) {
+                        T yq[3];
+                        load_pt(soa, n, d, (int64_t)bl.z + q, yq);
+                        a[k] = phi(K, xp, yq, d);
+                    }
+                }
+                for (int l = 0; l < r; ++l) {
+                    const T ul = sh.vec[l];
+                    const T* __restrict__ Vl = Vread + (int64_t)l * nc;
+#pragma unroll
+                    for (int k = 0; k < kRows; ++k)
+                        if (q0 + k * NT < nc) a[k] -= ul * Vl[q0 + k * NT];
+                }
+#pragma unroll
+                for (int k = 0; k < kRows; ++k) {
+                    const int q = q0 + k * NT;
+                    if (q < nc) {
+                        V[(int64_t)r * nc + q] = a[k];
+                        nv2 += (double)a[k] * (double)a[k];
+                        const T aa = a[k] < (T)0 ? -a[k] : a[k];
+                        if (!bit_get(cmask, q) && aa > cm.best) {
+                            cm.best = aa;
+                            cm.idx = q;
+                            cm.val = a[k];
+                        }
+                    }
                 }
             }
             nv2 = block_sum(nv2, sh, 1);
@@ -405,11 +465,17 @@ __global__ __launch_bounds__(NT) void aca_kernel(
                 double acc[DC];
 #pragma unroll
                 for (int k = 0; k < DC; ++k) acc[k] = 0.0;
-                for (int q = tid; q < nc; q += NT) {
-                    const double v = (double)Vr[q];
+                for (int q0 = tid; q0 < nc; q0 += kRows * NT) {
 #pragma unroll
-                    for (int k = 0; k < DC; ++k)
-                        if (k < nk) acc[k] += v * (double)Vc[k * nc + q];
+                    for (int e = 0; e < kRows; ++e) {
+                        const int q = q0 + e * NT;
+                        if (q < nc) {
+                            const double v = (double)Vr[q];
+#pragma unroll
+                            for (int k = 0; k < DC; ++k)
+                                if (k < nk) acc[k] += v * (double)Vc[k * nc + q];
+                        }
+                    }
                 }
                 block_sum_cols<DC>(acc, nk, sh.gv + c0, sh);
             }
@@ -468,19 +534,55 @@ hipError_t launch_level_split(const int32_t* level, int64_t nb, int lvl, int64_t
     return hipGetLastError();
 }
 
-// blocks [0, nbig) run in kBigThreads-thread workgroups with big_words LDS mask
-// words, the rest in 256-thread workgroups with small_words
-hipError_t launch_aca(const AcaArgs& a, int f64, hipStream_t st) {
+// Three size classes of the level-ordered block list, each in its own
+// launch: blocks [0, nbig) in kBigThreads-thread workgroups, [nbig, nmed) in
+// 256-thread ones, [nmed, nblocks) (the leaf levels) in single-wave
+// workgroups; each class reserves the LDS mask words of its largest block.
+// With second and third streams (aux1, aux2) the classes run concurrently:
+// the few large blocks of the upper levels would otherwise hold back the many
+// small ones.  The aux streams start after the work already queued on st, and
+// st waits for them before continuing.
+hipError_t launch_aca(const AcaArgs& a, int f64, hipStream_t st, hipStream_t aux1,
+                      hipStream_t aux2) {
     if (a.nblocks == 0) return hipSuccess;
     const int64_t nbig = a.nbig < a.nblocks ? a.nbig : a.nblocks;
-    if (f64) {
-        launch_class<double, kBigThreads>(a, 0, nbig, a.big_words, st);
-        launch_class<double, 256>(a, nbig, a.nblocks - nbig, a.small_words, st);
-    } else {
-        launch_class<float, kBigThreads>(a, 0, nbig, a.big_words, st);
-        launch_class<float, 256>(a, nbig, a.nblocks - nbig, a.small_words, st);
+    const int64_t nmed = a.nmed < nbig ? nbig : (a.nmed < a.nblocks ? a.nmed : a.nblocks);
+    hipStream_t s1 = aux1 ? aux1 : st;
+    hipStream_t s2 = aux2 ? aux2 : s1;
+    hipEvent_t go = nullptr, d1 = nullptr, d2 = nullptr;
+    hipError_t e = hipSuccess;
+    if (aux1 || aux2) {
+        e = hipEventCreateWithFlags(&go, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(go, st);
+        if (e == hipSuccess && aux1) e = hipStreamWaitEvent(aux1, go, 0);
+        if (e == hipSuccess && aux2) e = hipStreamWaitEvent(aux2, go, 0);
     }
-    return hipGetLastError();
+    if (e == hipSuccess) {
+        if (f64) {
+            launch_class<double, kBigThreads>(a, 0, nbig, a.big_words, st);
+            launch_class<double, 256>(a, nbig, nmed - nbig, a.med_words, s1);
+            launch_class<double, 64>(a, nmed, a.nblocks - nmed, a.tiny_words, s2);
+        } else {
+            launch_class<float, kBigThreads>(a, 0, nbig, a.big_words, st);
+            launch_class<float, 256>(a, nbig, nmed - nbig, a.med_words, s1);
+            launch_class<float, 64>(a, nmed, a.nblocks - nmed, a.tiny_words, s2);
+        }
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && aux1) {
+        e = hipEventCreateWithFlags(&d1, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(d1, aux1);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, d1, 0);
+    }
+    if (e == hipSuccess && aux2) {
+        e = hipEventCreateWithFlags(&d2, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(d2, aux2);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, d2, 0);
+    }
+    if (go) (void)hipEventDestroy(go);
+    if (d1) (void)hipEventDestroy(d1);
+    if (d2) (void)hipEventDestroy(d2);
+    return e;
 }
 
 }  // namespace hmx

@@ -449,6 +449,7 @@ __global__ __launch_bounds__(256) void far_phase1_kernel(
 constexpr int kTileThreads = 256;
 constexpr int kChunk = 1024;
 constexpr int kUnroll = 8;
+constexpr int kEvalUnroll = 4;  // near-field columns evaluated per iteration (recompute mode)
 
 // R consecutive rows of one column as T values (R / (16 / sizeof(S)) loads)
 template <typename S, typename T, int R>
@@ -539,7 +540,30 @@ __device__ __forceinline__ void rowtile_near_eval(const T* __restrict__ soa, int
             for (int k = 0; k < 3; ++k) sy[k * kChunk + j] = k < d ? soa[(int64_t)k * n + w] : (T)0;
         }
         __syncthreads();
-        for (int c = g; c < cnt; c += G) {
+        // kEvalUnroll columns per iteration: their LDS reads are issued
+        // together and the entries' exponentials overlap
+        int c = g;
+        for (; c + (kEvalUnroll - 1) * G < cnt; c += kEvalUnroll * G) {
+            T w[kEvalUnroll], y[kEvalUnroll][3];
+#pragma unroll
+            for (int u = 0; u < kEvalUnroll; ++u) {
+                const int cc = c + u * G;
+                w[u] = sw[cc];
+                y[u][0] = sy[cc];
+                y[u][1] = sy[kChunk + cc];
+                y[u][2] = sy[2 * kChunk + cc];
+            }
+#pragma unroll
+            for (int v = 0; v < RV; ++v) {
+                if (v * L + q < nvec) {
+#pragma unroll
+                    for (int u = 0; u < kEvalUnroll; ++u)
+#pragma unroll
+                        for (int e = 0; e < R; ++e) acc[v][e] += phi(K, xr[v][e], y[u], d) * w[u];
+                }
+            }
+        }
+        for (; c < cnt; c += G) {
             const T w0 = sw[c];
             const T y[3] = {sy[c], sy[kChunk + c], sy[2 * kChunk + c]};
 #pragma unroll
