@@ -566,14 +566,17 @@ void stage_partition(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t
 // how the ACA treats the admissible leaves of a handle: size classes and
 // (learned sizing) the predicted targets
 struct AcaPlan {
-    const int32_t* cls = nullptr;  // per leaf, non-decreasing; < split: 512-thread class,
-    int split = 0, split2 = 0;     // < split2: 256-thread class, else single wave
+    const int32_t* cls = nullptr;  // per leaf, non-decreasing; < split0: many workgroups,
+    int split0 = 0;                // < split: 512-thread class, < split2: 256-thread
+    int split = 0, split2 = 0;     // class, else single wave
     int big_words = 2, med_words = 2, tiny_words = 2;  // LDS mask words per class
     const int32_t* rt = nullptr;         // learned targets, or null
 };
 
-// clusters of kBigRows or more points put their blocks in the 512-thread
-// class; clusters of at most kTinyRows points in the single-wave class
+// clusters of kSplitRows or more points put their blocks on many workgroups
+// each, of kBigRows or more in the 512-thread class; clusters of at most
+// kTinyRows points in the single-wave class
+constexpr int64_t kSplitRows = 16384;
 constexpr int64_t kBigRows = 4096;
 constexpr int64_t kTinyRows = 256;
 
@@ -582,6 +585,13 @@ constexpr int64_t kTinyRows = 256;
 // can reach kBigRows points form the 512-thread class
 AcaPlan level_plan(const hmx_hmatrix_s* h) {
     AcaPlan p;
+    {
+        int64_t s0 = h->n;
+        while (s0 >= kSplitRows) {
+            s0 = (s0 + 1) / 2;
+            ++p.split0;
+        }
+    }
     int64_t s_split = h->n;
     while (s_split >= kBigRows) {
         s_split = (s_split + 1) / 2;
@@ -619,6 +629,69 @@ void stage_predict(hmx_hmatrix_s* h, DevBuf& rt, hipStream_t st) {
           "rank prediction");
     check(hipStreamSynchronize(st), "prediction sync");
     h->stats.predict_ms += ms_since(tp);
+}
+
+// the multi-workgroup ACA of a chunk's largest blocks a.blocks[0 .. a.nsplit):
+// tile maps and bitmask offsets built on the host from the blocks' sizes
+void run_split(hmx_hmatrix_s* h, const AcaArgs& a, int f64, hipStream_t st) {
+    const int64_t nb = a.nsplit;
+    std::vector<int4> hb(nb);
+    d2h(hb.data(), a.blocks, (size_t)nb * sizeof(int4), st);
+    const int tile = split_tile();
+    std::vector<int2> rt, ct;
+    std::vector<int64_t> rtoff(nb + 1), ctoff(nb + 1), moff(nb + 1);
+    rtoff[0] = ctoff[0] = moff[0] = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int m = hb[b].y - hb[b].x, nc = hb[b].w - hb[b].z;
+        for (int t = 0; t * (int64_t)tile < m; ++t) rt.push_back(make_int2((int)b, t));
+        for (int t = 0; t * (int64_t)tile < nc; ++t) ct.push_back(make_int2((int)b, t));
+        rtoff[b + 1] = (int64_t)rt.size();
+        ctoff[b + 1] = (int64_t)ct.size();
+        moff[b + 1] = moff[b] + (m + 31) / 32 + (nc + 31) / 32;
+    }
+    DevBuf drt, dct, drtoff, dctoff, dmoff, masks, state, cpart, rpart, urow, udp, vdp, act;
+    alloc(drt, rt.size() * sizeof(int2), "split row tiles");
+    alloc(dct, ct.size() * sizeof(int2), "split column tiles");
+    alloc(drtoff, (nb + 1) * 8, "split row tile offsets");
+    alloc(dctoff, (nb + 1) * 8, "split column tile offsets");
+    alloc(dmoff, (nb + 1) * 8, "split mask offsets");
+    alloc(masks, (size_t)moff[nb] * 4, "split masks");
+    alloc(state, (size_t)nb * split_state_bytes(), "split state");
+    alloc(cpart, rt.size() * split_colpart_bytes(f64), "split column partials");
+    alloc(rpart, ct.size() * split_rowpart_bytes(f64), "split row partials");
+    alloc(urow, (size_t)nb * (kMaxRankCap + 1) * h->esz, "split pivot rows");
+    alloc(udp, rt.size() * (kMaxRankCap + 1) * 8, "split U products");
+    alloc(vdp, ct.size() * (kMaxRankCap + 1) * 8, "split V products");
+    alloc(act, 8, "split active count");
+    check(hipMemcpyAsync(drt.p, rt.data(), rt.size() * sizeof(int2), hipMemcpyHostToDevice, st),
+          "split tiles");
+    check(hipMemcpyAsync(dct.p, ct.data(), ct.size() * sizeof(int2), hipMemcpyHostToDevice, st),
+          "split tiles");
+    check(hipMemcpyAsync(drtoff.p, rtoff.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st),
+          "split offsets");
+    check(hipMemcpyAsync(dctoff.p, ctoff.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st),
+          "split offsets");
+    check(hipMemcpyAsync(dmoff.p, moff.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st),
+          "split offsets");
+    SplitPlan P{};
+    P.nblocks = nb;
+    P.nrowtiles = (int64_t)rt.size();
+    P.ncoltiles = (int64_t)ct.size();
+    P.rowtiles = drt.as<int2>();
+    P.coltiles = dct.as<int2>();
+    P.rtoff = drtoff.as<int64_t>();
+    P.ctoff = dctoff.as<int64_t>();
+    P.moff = dmoff.as<int64_t>();
+    P.masks = masks.as<uint32_t>();
+    P.state = state.p;
+    P.colpart = cpart.p;
+    P.rowpart = rpart.p;
+    P.urow = urow.p;
+    P.udpart = udp.as<double>();
+    P.vdpart = vdp.as<double>();
+    P.active_dev = act.as<int>();
+    check(launch_aca_split(a, P, f64, st), "aca (many workgroups per block)");
+    check(hipStreamSynchronize(st), "split sync");  // before the buffers return to the cache
 }
 
 // phases 4-5: batched ACA, compaction, the tile-major matrix pool
@@ -677,7 +750,10 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
             budget_bytes = std::max<int64_t>((int64_t)((fr + cached) / 10 * 4), (int64_t)1 << 30);
         }
         const int64_t budget = std::max<int64_t>(budget_bytes / (int64_t)esz, 1);
-        AuxStream aux1, aux2;  // the smaller block classes run beside the large one
+        // the single-workgroup classes run beside the multi-workgroup path
+        AuxStream auxs[3];
+        const hipStream_t aux[3] = {auxs[0].s, auxs[1].s, auxs[2].s};
+        const bool have_aux = aux[0] && aux[1] && aux[2];
         AcaArgs a{};
         a.soa = f64 ? h->soa64.p : h->soa32.p;
         a.soa64 = h->soa64.as<double>();
@@ -701,6 +777,9 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
         auto pass = [&](const int4* blocks, const int32_t* levels, int64_t nb, const int32_t* cap,
                         const int32_t* rt, int one_shot, int cap_only, int32_t* rank,
                         int32_t* steps, int64_t* ue_all, int64_t* ve_all) {
+            check(launch_level_split(levels, nb, plan.split0, split.as<int64_t>(), st),
+                  "class split");
+            const int64_t nsplit_all = read_scalar(split.as<int64_t>(), st);
             check(launch_level_split(levels, nb, plan.split, split.as<int64_t>(), st),
                   "class split");
             const int64_t nbig_all = read_scalar(split.as<int64_t>(), st);
@@ -763,11 +842,14 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                 a.ubase = hcu[k];
                 a.vbase = hcv[k];
                 a.rtarget = rt ? rt + b0 : nullptr;
+                a.nsplit = std::max<int64_t>(0, std::min(nsplit_all - b0, nbk));
                 a.nbig = std::max<int64_t>(0, std::min(nbig_all - b0, nbk));
                 a.nmed = std::max<int64_t>(0, std::min(nmed_all - b0, nbk));
                 a.rank = rank + b0;
                 a.steps = steps + b0;
-                check(launch_aca(a, f64, st, aux1.s, aux2.s), "aca");
+                check(aca_classes_begin(a, f64, st, have_aux ? aux : nullptr), "aca");
+                if (a.nsplit > 0) run_split(h, a, f64, st);
+                check(aca_classes_join(st, have_aux ? aux : nullptr), "aca join");
                 check(hipStreamSynchronize(st), "aca sync");
                 aca_ms += ms_since(ta);
                 if (aca_only) continue;
@@ -1008,11 +1090,12 @@ void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
     const bool learned = u->prm.rank_mode == HMX_RANK_LEARNED;
     std::vector<std::unique_ptr<hmx_hmatrix_s>> parts(np);
     std::unique_ptr<DevBuf[]> rts(new DevBuf[np]);
-    std::vector<int64_t> nbig(np, 0), nmed(np, 0);
+    std::vector<int64_t> nspl(np, 0), nbig(np, 0), nmed(np, 0);
     hmx_stats& S = u->stats;
     DevBuf split;
     alloc(split, 8, "class split");
-    int64_t nadm = 0, ndense = 0, ntiles = 0, big = 0, nbig_tot = 0, nmed_tot = 0;
+    int64_t nadm = 0, ndense = 0, ntiles = 0, big = 0, nspl_tot = 0, nbig_tot = 0,
+            nmed_tot = 0;
     for (int p = 0; p < np; ++p) {
         hmx_hmatrix_s* hp = new hmx_hmatrix_s();
         parts[p].reset(hp);
@@ -1021,6 +1104,10 @@ void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
         if (learned && hp->n_adm > 0) stage_predict(hp, rts[p], st);
         if (hp->n_adm > 0) {
             const AcaPlan lp = level_plan(hp);
+            check(launch_level_split(hp->adm_level.as<int32_t>(), hp->n_adm, lp.split0,
+                                     split.as<int64_t>(), st),
+                  "class split");
+            nspl[p] = read_scalar(split.as<int64_t>(), st);
             check(launch_level_split(hp->adm_level.as<int32_t>(), hp->n_adm, lp.split,
                                      split.as<int64_t>(), st),
                   "class split");
@@ -1033,7 +1120,8 @@ void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
         nadm += hp->n_adm;
         ndense += hp->n_dense;
         ntiles += hp->ntiles;
-        nbig_tot += nbig[p];
+        nspl_tot += nspl[p];
+        nbig_tot += nbig[p] - nspl[p];
         nmed_tot += nmed[p] - nbig[p];
         big = std::max(big, hp->big_adm);
         u->max_tile = std::max(u->max_tile, hp->max_tile);
@@ -1057,9 +1145,10 @@ void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
     DevBuf cls, rt;
     alloc(cls, std::max<int64_t>(nadm, 1) * 4, "size classes");
     if (learned) alloc(rt, std::max<int64_t>(nadm, 1) * 4, "rank targets");
-    // sections: the 512-thread class of every problem, then the 256-thread
-    // class, then the single-wave class
-    int64_t base = 0, tbase = 0, acur[3] = {0, nbig_tot, nbig_tot + nmed_tot}, dcur = 0;
+    // sections: the multi-workgroup class of every problem, then the
+    // 512-thread, the 256-thread and the single-wave classes
+    int64_t base = 0, tbase = 0, dcur = 0;
+    int64_t acur[4] = {0, nspl_tot, nspl_tot + nbig_tot, nspl_tot + nbig_tot + nmed_tot};
     u->offsets.assign(1, 0);
     for (int p = 0; p < np; ++p) {
         hmx_hmatrix_s* hp = parts[p].get();
@@ -1081,12 +1170,12 @@ void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
         check(launch_add_i32(u->tile_lo.as<int32_t>() + tbase, hp->tile_lo.as<int32_t>(),
                              hp->ntiles, b32, st),
               "tile starts");
-        // the problem's three class ranges into the three sections
-        const int64_t lo3[3] = {0, nbig[p], nmed[p]};
-        const int64_t hi3[3] = {nbig[p], nmed[p], hp->n_adm};
+        // the problem's four class ranges into the four sections
+        const int64_t lo3[4] = {0, nspl[p], nbig[p], nmed[p]};
+        const int64_t hi3[4] = {nspl[p], nbig[p], nmed[p], hp->n_adm};
         const int4* ha = hp->adm.as<int4>();
         const int32_t* hl = hp->adm_level.as<int32_t>();
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < 4; ++c) {
             const int64_t cnt = hi3[c] - lo3[c];
             check(launch_shift_blocks(u->adm.as<int4>() + acur[c], ha + lo3[c], cnt, b32, st),
                   "adm");
@@ -1130,8 +1219,9 @@ void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
             throw Fail{HMX_ERR_UNSUPPORTED};
         }
         plan.cls = cls.as<int32_t>();
-        plan.split = 1;
-        plan.split2 = 2;
+        plan.split0 = 1;
+        plan.split = 2;
+        plan.split2 = 3;
         plan.big_words = (int)std::max<int64_t>(words, 2);
         plan.med_words =
             (int)std::max<int64_t>(2 * ((std::min(kBigRows - 1, big) + 31) / 32), 2);

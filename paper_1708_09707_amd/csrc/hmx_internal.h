@@ -159,17 +159,40 @@ struct AcaArgs {
     void* V;
     int32_t* rank;
     int32_t* steps;
-    // size classes: blocks [0, nbig) (upper tree levels) run in 512-thread
-    // workgroups, [nbig, nmed) in 256-thread ones, the rest (leaf levels) in
-    // single-wave ones; each class reserves the used-row + used-col bitmask
-    // words of its largest block
-    int64_t nbig, nmed;
+    // size classes of the level-ordered list: [0, nsplit) many workgroups per
+    // block, [nsplit, nbig) 512-thread workgroups, [nbig, nmed) 256-thread
+    // ones, the rest (leaf levels) single-wave ones; each single-workgroup
+    // class reserves the used-row + used-col bitmask words of its largest block
+    int64_t nsplit, nbig, nmed;
     int big_words, med_words, tiny_words;
 };
-// aux1, aux2: optional streams on which the 256-thread and single-wave
-// classes run concurrently with the 512-thread one
-hipError_t launch_aca(const AcaArgs& a, int f64, hipStream_t st, hipStream_t aux1,
-                      hipStream_t aux2);
+// queue the single-workgroup classes on aux[0..2] (3 streams, or null: all on
+// st) after the work queued on st; join makes st wait for them
+hipError_t aca_classes_begin(const AcaArgs& a, int f64, hipStream_t st, const hipStream_t* aux);
+hipError_t aca_classes_join(hipStream_t st, const hipStream_t* aux);
+
+// multi-workgroup ACA of blocks [0, nblocks) of an AcaArgs list (k_aca_split.hip)
+struct SplitPlan {
+    int64_t nblocks, nrowtiles, ncoltiles;
+    const int2* rowtiles;  // (block, tile) per row tile of split_tile() rows
+    const int2* coltiles;  // (block, tile) per column tile
+    const int64_t* rtoff;  // first row tile of each block (nblocks + 1)
+    const int64_t* ctoff;  // first column tile of each block (nblocks + 1)
+    const int64_t* moff;   // first bitmask word of each block
+    uint32_t* masks;       // used rows then used columns, per block
+    void* state;           // nblocks x split_state_bytes()
+    void* colpart;         // nrowtiles x split_colpart_bytes()
+    void* rowpart;         // ncoltiles x split_rowpart_bytes()
+    void* urow;            // nblocks x (kMaxRankCap + 1) compute-type values
+    double* udpart;        // nrowtiles x (kMaxRankCap + 1)
+    double* vdpart;        // ncoltiles x (kMaxRankCap + 1)
+    int* active_dev;       // one int
+};
+size_t split_state_bytes();
+size_t split_colpart_bytes(int f64);
+size_t split_rowpart_bytes(int f64);
+int split_tile();
+hipError_t launch_aca_split(const AcaArgs& a, const SplitPlan& p, int f64, hipStream_t st);
 // *out = first index with level[index] >= lvl in the non-decreasing level[0..nb)
 hipError_t launch_level_split(const int32_t* level, int64_t nb, int lvl, int64_t* out,
                               hipStream_t st);

@@ -4,8 +4,9 @@
 // blocks stop independently (no global "voting" bounded by the slowest
 // block).  Blocks of the upper tree levels (many rows) get 512-thread
 // workgroups, those of the leaf levels (at most 256 rows) one wave, the rest
-// 256 threads; the canonical leaf order is level order, so each class is a
-// contiguous range of every block list.  Per step r:
+// 256 threads (the very largest run on many workgroups each, k_aca_split.hip);
+// the canonical leaf order is level order, so each class is a contiguous
+// range of every block list.  Per step r:
 //   1. residual column  u^ = A[:, j] - sum_{l<r} u_l (v_l)_j   (rows over threads)
 //   2. row pivot        i  = argmax over unused rows |u^_i| (lowest index on ties)
 //      a column whose largest residual entry is <= eps0 times the column's own
@@ -534,54 +535,55 @@ hipError_t launch_level_split(const int32_t* level, int64_t nb, int lvl, int64_t
     return hipGetLastError();
 }
 
-// Three size classes of the level-ordered block list, each in its own
-// launch: blocks [0, nbig) in kBigThreads-thread workgroups, [nbig, nmed) in
+// Size classes of the level-ordered block list, each in its own launch:
+// blocks [nsplit, nbig) in kBigThreads-thread workgroups, [nbig, nmed) in
 // 256-thread ones, [nmed, nblocks) (the leaf levels) in single-wave
 // workgroups; each class reserves the LDS mask words of its largest block.
-// With second and third streams (aux1, aux2) the classes run concurrently:
-// the few large blocks of the upper levels would otherwise hold back the many
-// small ones.  The aux streams start after the work already queued on st, and
-// st waits for them before continuing.
-hipError_t launch_aca(const AcaArgs& a, int f64, hipStream_t st, hipStream_t aux1,
-                      hipStream_t aux2) {
-    if (a.nblocks == 0) return hipSuccess;
-    const int64_t nbig = a.nbig < a.nblocks ? a.nbig : a.nblocks;
+// (Blocks [0, nsplit) take the multi-workgroup path of k_aca_split.hip.)
+// aca_classes_begin queues the classes on the streams aux[0..2] (or on st
+// where null) after the work already queued on st; aca_classes_join makes
+// st wait for them.  Running the classes concurrently keeps the few large
+// blocks of the upper levels from holding back the many small ones.
+hipError_t aca_classes_begin(const AcaArgs& a, int f64, hipStream_t st, const hipStream_t* aux) {
+    const int64_t lo = a.nsplit < a.nblocks ? a.nsplit : a.nblocks;
+    const int64_t nbig = a.nbig < lo ? lo : (a.nbig < a.nblocks ? a.nbig : a.nblocks);
     const int64_t nmed = a.nmed < nbig ? nbig : (a.nmed < a.nblocks ? a.nmed : a.nblocks);
-    hipStream_t s1 = aux1 ? aux1 : st;
-    hipStream_t s2 = aux2 ? aux2 : s1;
-    hipEvent_t go = nullptr, d1 = nullptr, d2 = nullptr;
+    hipStream_t s0 = aux && aux[0] ? aux[0] : st;
+    hipStream_t s1 = aux && aux[1] ? aux[1] : s0;
+    hipStream_t s2 = aux && aux[2] ? aux[2] : s1;
     hipError_t e = hipSuccess;
-    if (aux1 || aux2) {
+    if (aux) {
+        hipEvent_t go = nullptr;
         e = hipEventCreateWithFlags(&go, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventRecord(go, st);
-        if (e == hipSuccess && aux1) e = hipStreamWaitEvent(aux1, go, 0);
-        if (e == hipSuccess && aux2) e = hipStreamWaitEvent(aux2, go, 0);
+        for (int k = 0; k < 3 && e == hipSuccess; ++k)
+            if (aux[k]) e = hipStreamWaitEvent(aux[k], go, 0);
+        if (go) (void)hipEventDestroy(go);
     }
-    if (e == hipSuccess) {
-        if (f64) {
-            launch_class<double, kBigThreads>(a, 0, nbig, a.big_words, st);
-            launch_class<double, 256>(a, nbig, nmed - nbig, a.med_words, s1);
-            launch_class<double, 64>(a, nmed, a.nblocks - nmed, a.tiny_words, s2);
-        } else {
-            launch_class<float, kBigThreads>(a, 0, nbig, a.big_words, st);
-            launch_class<float, 256>(a, nbig, nmed - nbig, a.med_words, s1);
-            launch_class<float, 64>(a, nmed, a.nblocks - nmed, a.tiny_words, s2);
-        }
-        e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (f64) {
+        launch_class<double, kBigThreads>(a, lo, nbig - lo, a.big_words, s0);
+        launch_class<double, 256>(a, nbig, nmed - nbig, a.med_words, s1);
+        launch_class<double, 64>(a, nmed, a.nblocks - nmed, a.tiny_words, s2);
+    } else {
+        launch_class<float, kBigThreads>(a, lo, nbig - lo, a.big_words, s0);
+        launch_class<float, 256>(a, nbig, nmed - nbig, a.med_words, s1);
+        launch_class<float, 64>(a, nmed, a.nblocks - nmed, a.tiny_words, s2);
     }
-    if (e == hipSuccess && aux1) {
-        e = hipEventCreateWithFlags(&d1, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventRecord(d1, aux1);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, d1, 0);
+    return hipGetLastError();
+}
+
+hipError_t aca_classes_join(hipStream_t st, const hipStream_t* aux) {
+    if (!aux) return hipSuccess;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+        if (!aux[k]) continue;
+        hipEvent_t done = nullptr;
+        e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(done, aux[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, done, 0);
+        if (done) (void)hipEventDestroy(done);
     }
-    if (e == hipSuccess && aux2) {
-        e = hipEventCreateWithFlags(&d2, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventRecord(d2, aux2);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, d2, 0);
-    }
-    if (go) (void)hipEventDestroy(go);
-    if (d1) (void)hipEventDestroy(d1);
-    if (d2) (void)hipEventDestroy(d2);
     return e;
 }
 

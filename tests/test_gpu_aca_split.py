@@ -1,0 +1,102 @@
+"""ACA of the largest blocks on many workgroups per block, against the
+oracle's Algorithm 2 on the same blocks: ranks (FP64), factor errors on
+sampled rows of each block, and the matvec."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SPLIT_ROWS = 16384  # clusters this large take the many-workgroup path
+
+
+@pytest.fixture(scope="module")
+def H():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1708_09707_amd import hmx
+    hmx.lib()
+    return hmx
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_split_blocks_match_oracle(H, orc, dtype):
+    n, p0, eps, kmax = 1 << 18, 0.02, 1e-6 if dtype == "f64" else 1e-5, 48
+    pts = synth.uniform_points(n, 2, 1717)
+    hm = H.HMatrix(_dev(pts), "gaussian", p0, compute_dtype=dtype, leaf_size=256, eta=1.5,
+                   aca_eps=eps, max_rank=kmax)
+    part = hm.partition()
+    adm = part["adm"]
+    ranks = hm.ranks()
+    big = np.where((adm[:, 1] - adm[:, 0]) >= SPLIT_ROWS)[0]
+    print("%d of %d admissible blocks on the many-workgroup path" % (len(big), len(adm)))
+    assert len(big) >= 8
+    _, _, soa = orc.order(pts)
+    g = synth.rng(1718)
+    picks = big if len(big) <= 24 else np.sort(g.choice(big, 24, replace=False))
+    eps0 = 1e-14 if dtype == "f64" else 1e-7
+    agree, errs = 0, []
+    for q in picks:
+        b = adm[q]
+        m, nn = b[1] - b[0], b[3] - b[2]
+        _, _, ro, _ = orc.aca(soa, "gaussian", p0, *b[:4], kmax, eps, eps0=eps0)
+        agree += int(ro == ranks[q])
+        U, V, r = H.hmx_get_factors(hm.h, int(q), m, nn, kmax)
+        rows = np.sort(g.choice(m, 128, replace=False))
+        A = np.stack([orc.dense_block(soa, "gaussian", p0, b[0] + i, b[0] + i + 1, b[2], b[3])[0]
+                      for i in rows])
+        err = np.linalg.norm(A - U[rows] @ V.T) / np.linalg.norm(A)
+        errs.append(err)
+        assert abs(int(r) - int(ro)) <= (2 if dtype == "f64" else 6), (q, r, ro)
+        if dtype == "f64":
+            assert err <= 10 * eps, (q, r, ro, err)
+    errs = np.array(errs)
+    print("rank agreement %d / %d, sampled block errors: median %.3e, worst %.3e"
+          % (agree, len(picks), np.median(errs), errs.max()))
+    if dtype == "f64":
+        assert agree >= 0.8 * len(picks)
+    else:
+        # the stopping test estimates the error from the last term; with FP32
+        # residuals a large block can stop a step before the FP64 oracle
+        assert np.median(errs) <= 10 * eps and errs.max() <= 50 * eps
+    x = synth.normal_vector(n, 1719)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    z = hm.matvec(_dev(x).to(tdt)).double().cpu().numpy()
+    rows = synth.sample_rows(n, 256, 1720)
+    zd = orc.dense_matvec(pts, x, "gaussian", p0, rows=rows)
+    err = np.linalg.norm(z[rows] - zd) / np.linalg.norm(zd)
+    print("matvec rel err on sampled rows %.3e" % err)
+    assert err <= 10 * eps + (4 * 2.0 ** -24 if dtype == "f32" else 0)
+    hm.close()
+
+
+def test_split_learned_and_batched(H):
+    """Learned sizing (sizing form) and the batched union keep the
+    many-workgroup path's results."""
+    n, p0 = 1 << 18, 0.02
+    pts = synth.uniform_points(n, 2, 1721, dtype=np.float32)
+    w = np.zeros(8961, np.float32)
+    w[-1] = 4.0
+    mlp = H.RankMLP(w)
+    kw = dict(compute_dtype="f32", leaf_size=256, eta=1.5, aca_eps=1e-5, max_rank=48)
+    ha = H.HMatrix(_dev(pts), "gaussian", p0, **kw)
+    hl = H.HMatrix(_dev(pts), "gaussian", p0, rank_mode="learned", mlp=mlp, **kw)
+    x = _dev(synth.normal_vector(n, 1722, dtype=np.float32))
+    assert np.array_equal(ha.ranks(), hl.ranks())
+    assert torch.equal(ha.matvec(x), hl.matvec(x))
+    hb = H.HMatrix.batched([_dev(pts), _dev(pts[: n // 2].copy())], "gaussian", [p0, p0], **kw)
+    zb = hb.matvec(torch.cat([x, x[: n // 2]]))
+    za = ha.matvec(x)
+    dev = (torch.linalg.norm((zb[:n] - za).double()) / torch.linalg.norm(za.double())).item()
+    print("batched vs single build: %.3e" % dev)
+    assert dev <= 1e-5
+    for h in (ha, hl, hb):
+        h.close()
+    mlp.close()
