@@ -171,24 +171,61 @@ T read_scalar(const T* dev, hipStream_t st) {
 }
 
 // device -> pageable host copy through a pinned staging buffer (large
-// readbacks never ask the runtime to pin caller memory)
+// readbacks never ask the runtime to pin caller memory).  The staging buffer
+// is allocated once and kept for the process: freeing pinned memory waits for
+// the whole device, which would serialise the build's concurrent streams.
+std::mutex g_stage_mu;
+void* g_stage = nullptr;
+constexpr size_t kStageBytes = (size_t)32 << 20;
+
+// pinned words the multi-workgroup ACA polls into, one per build in flight
+// (the set only grows; each word is reused once its build has finished)
+std::mutex g_poll_mu;
+std::vector<int*> g_poll_free;
+
+struct PollWord {
+    int* p = nullptr;
+    PollWord() {
+        std::lock_guard<std::mutex> lk(g_poll_mu);
+        if (!g_poll_free.empty()) {
+            p = g_poll_free.back();
+            g_poll_free.pop_back();
+            return;
+        }
+        void* q = nullptr;
+        hipError_t e = hipHostMalloc(&q, 64, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            set_err("pinned poll word allocation failed: %s", hipGetErrorString(e));
+            throw Fail{HMX_ERR_OOM};
+        }
+        p = (int*)q;
+    }
+    PollWord(const PollWord&) = delete;
+    PollWord& operator=(const PollWord&) = delete;
+    ~PollWord() {
+        std::lock_guard<std::mutex> lk(g_poll_mu);
+        g_poll_free.push_back(p);
+    }
+};
+
 void d2h(void* dst, const void* src, size_t bytes, hipStream_t st) {
     if (bytes == 0) return;
-    const size_t chunk = std::min<size_t>(bytes, (size_t)32 << 20);
-    void* stage = nullptr;
-    hipError_t e = hipHostMalloc(&stage, chunk, hipHostMallocDefault);
-    if (e != hipSuccess) {
-        set_err("pinned staging allocation failed: %s", hipGetErrorString(e));
-        throw Fail{HMX_ERR_OOM};
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    if (!g_stage) {
+        hipError_t e = hipHostMalloc(&g_stage, kStageBytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            g_stage = nullptr;
+            set_err("pinned staging allocation failed: %s", hipGetErrorString(e));
+            throw Fail{HMX_ERR_OOM};
+        }
     }
     hipError_t r = hipSuccess;
-    for (size_t off = 0; off < bytes && r == hipSuccess; off += chunk) {
-        const size_t nb = std::min(chunk, bytes - off);
-        r = hipMemcpyAsync(stage, (const char*)src + off, nb, hipMemcpyDeviceToHost, st);
+    for (size_t off = 0; off < bytes && r == hipSuccess; off += kStageBytes) {
+        const size_t nb = std::min(kStageBytes, bytes - off);
+        r = hipMemcpyAsync(g_stage, (const char*)src + off, nb, hipMemcpyDeviceToHost, st);
         if (r == hipSuccess) r = hipStreamSynchronize(st);
-        if (r == hipSuccess) memcpy((char*)dst + off, stage, nb);
+        if (r == hipSuccess) memcpy((char*)dst + off, g_stage, nb);
     }
-    (void)hipHostFree(stage);
     if (r != hipSuccess) {
         set_err("device to host copy: %s", hipGetErrorString(r));
         throw Fail{HMX_ERR_DEVICE};
@@ -633,7 +670,16 @@ void stage_predict(hmx_hmatrix_s* h, DevBuf& rt, hipStream_t st) {
 
 // the multi-workgroup ACA of a chunk's largest blocks a.blocks[0 .. a.nsplit):
 // tile maps and bitmask offsets built on the host from the blocks' sizes
-void run_split(hmx_hmatrix_s* h, const AcaArgs& a, int f64, hipStream_t st) {
+// (prepared before the other classes start, so that no host wait falls
+// inside the concurrent part)
+struct SplitBuffers {
+    DevBuf drt, dct, drtoff, dctoff, dmoff, masks, state, cpart, rpart, urow, udp, vdp, act;
+    std::unique_ptr<PollWord> poll;
+    SplitPlan P{};
+};
+
+void prepare_split(hmx_hmatrix_s* h, const AcaArgs& a, int f64, hipStream_t st,
+                   SplitBuffers& B) {
     const int64_t nb = a.nsplit;
     std::vector<int4> hb(nb);
     d2h(hb.data(), a.blocks, (size_t)nb * sizeof(int4), st);
@@ -649,49 +695,49 @@ void run_split(hmx_hmatrix_s* h, const AcaArgs& a, int f64, hipStream_t st) {
         ctoff[b + 1] = (int64_t)ct.size();
         moff[b + 1] = moff[b] + (m + 31) / 32 + (nc + 31) / 32;
     }
-    DevBuf drt, dct, drtoff, dctoff, dmoff, masks, state, cpart, rpart, urow, udp, vdp, act;
-    alloc(drt, rt.size() * sizeof(int2), "split row tiles");
-    alloc(dct, ct.size() * sizeof(int2), "split column tiles");
-    alloc(drtoff, (nb + 1) * 8, "split row tile offsets");
-    alloc(dctoff, (nb + 1) * 8, "split column tile offsets");
-    alloc(dmoff, (nb + 1) * 8, "split mask offsets");
-    alloc(masks, (size_t)moff[nb] * 4, "split masks");
-    alloc(state, (size_t)nb * split_state_bytes(), "split state");
-    alloc(cpart, rt.size() * split_colpart_bytes(f64), "split column partials");
-    alloc(rpart, ct.size() * split_rowpart_bytes(f64), "split row partials");
-    alloc(urow, (size_t)nb * (kMaxRankCap + 1) * h->esz, "split pivot rows");
-    alloc(udp, rt.size() * (kMaxRankCap + 1) * 8, "split U products");
-    alloc(vdp, ct.size() * (kMaxRankCap + 1) * 8, "split V products");
-    alloc(act, 8, "split active count");
-    check(hipMemcpyAsync(drt.p, rt.data(), rt.size() * sizeof(int2), hipMemcpyHostToDevice, st),
+    alloc(B.drt, rt.size() * sizeof(int2), "split row tiles");
+    alloc(B.dct, ct.size() * sizeof(int2), "split column tiles");
+    alloc(B.drtoff, (nb + 1) * 8, "split row tile offsets");
+    alloc(B.dctoff, (nb + 1) * 8, "split column tile offsets");
+    alloc(B.dmoff, (nb + 1) * 8, "split mask offsets");
+    alloc(B.masks, (size_t)moff[nb] * 4, "split masks");
+    alloc(B.state, (size_t)nb * split_state_bytes(), "split state");
+    alloc(B.cpart, rt.size() * split_colpart_bytes(f64), "split column partials");
+    alloc(B.rpart, ct.size() * split_rowpart_bytes(f64), "split row partials");
+    alloc(B.urow, (size_t)nb * (kMaxRankCap + 1) * h->esz, "split pivot rows");
+    alloc(B.udp, rt.size() * (kMaxRankCap + 1) * 8, "split U products");
+    alloc(B.vdp, ct.size() * (kMaxRankCap + 1) * 8, "split V products");
+    alloc(B.act, 8, "split active count");
+    check(hipMemcpyAsync(B.drt.p, rt.data(), rt.size() * sizeof(int2), hipMemcpyHostToDevice, st),
           "split tiles");
-    check(hipMemcpyAsync(dct.p, ct.data(), ct.size() * sizeof(int2), hipMemcpyHostToDevice, st),
+    check(hipMemcpyAsync(B.dct.p, ct.data(), ct.size() * sizeof(int2), hipMemcpyHostToDevice, st),
           "split tiles");
-    check(hipMemcpyAsync(drtoff.p, rtoff.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st),
+    check(hipMemcpyAsync(B.drtoff.p, rtoff.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st),
           "split offsets");
-    check(hipMemcpyAsync(dctoff.p, ctoff.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st),
+    check(hipMemcpyAsync(B.dctoff.p, ctoff.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st),
           "split offsets");
-    check(hipMemcpyAsync(dmoff.p, moff.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st),
+    check(hipMemcpyAsync(B.dmoff.p, moff.data(), (nb + 1) * 8, hipMemcpyHostToDevice, st),
           "split offsets");
-    SplitPlan P{};
+    check(hipStreamSynchronize(st), "split plan");  // the host vectors go out of scope
+    SplitPlan& P = B.P;
     P.nblocks = nb;
     P.nrowtiles = (int64_t)rt.size();
     P.ncoltiles = (int64_t)ct.size();
-    P.rowtiles = drt.as<int2>();
-    P.coltiles = dct.as<int2>();
-    P.rtoff = drtoff.as<int64_t>();
-    P.ctoff = dctoff.as<int64_t>();
-    P.moff = dmoff.as<int64_t>();
-    P.masks = masks.as<uint32_t>();
-    P.state = state.p;
-    P.colpart = cpart.p;
-    P.rowpart = rpart.p;
-    P.urow = urow.p;
-    P.udpart = udp.as<double>();
-    P.vdpart = vdp.as<double>();
-    P.active_dev = act.as<int>();
-    check(launch_aca_split(a, P, f64, st), "aca (many workgroups per block)");
-    check(hipStreamSynchronize(st), "split sync");  // before the buffers return to the cache
+    P.rowtiles = B.drt.as<int2>();
+    P.coltiles = B.dct.as<int2>();
+    P.rtoff = B.drtoff.as<int64_t>();
+    P.ctoff = B.dctoff.as<int64_t>();
+    P.moff = B.dmoff.as<int64_t>();
+    P.masks = B.masks.as<uint32_t>();
+    P.state = B.state.p;
+    P.colpart = B.cpart.p;
+    P.rowpart = B.rpart.p;
+    P.urow = B.urow.p;
+    P.udpart = B.udp.as<double>();
+    P.vdpart = B.vdp.as<double>();
+    P.active_dev = B.act.as<int>();
+    B.poll.reset(new PollWord);
+    P.active_host = B.poll->p;
 }
 
 // phases 4-5: batched ACA, compaction, the tile-major matrix pool
@@ -847,10 +893,13 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                 a.nmed = std::max<int64_t>(0, std::min(nmed_all - b0, nbk));
                 a.rank = rank + b0;
                 a.steps = steps + b0;
+                SplitBuffers sb;
+                if (a.nsplit > 0) prepare_split(h, a, f64, st, sb);
                 check(aca_classes_begin(a, f64, st, have_aux ? aux : nullptr), "aca");
-                if (a.nsplit > 0) run_split(h, a, f64, st);
+                if (a.nsplit > 0)
+                    check(launch_aca_split(a, sb.P, f64, st), "aca (many workgroups per block)");
                 check(aca_classes_join(st, have_aux ? aux : nullptr), "aca join");
-                check(hipStreamSynchronize(st), "aca sync");
+                check(hipStreamSynchronize(st), "aca sync");  // before sb returns to the cache
                 aca_ms += ms_since(ta);
                 if (aca_only) continue;
                 // exact offsets of this chunk's blocks: chunk-local scan plus the

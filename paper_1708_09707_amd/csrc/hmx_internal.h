@@ -187,6 +187,7 @@ struct SplitPlan {
     double* udpart;        // nrowtiles x (kMaxRankCap + 1)
     double* vdpart;        // ncoltiles x (kMaxRankCap + 1)
     int* active_dev;       // one int
+    int* active_host;      // one int in pinned host memory (the poll's target)
 };
 size_t split_state_bytes();
 size_t split_colpart_bytes(int f64);

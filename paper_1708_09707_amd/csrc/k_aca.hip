@@ -242,6 +242,63 @@ __device__ __forceinline__ bool bit_get(const uint32_t* m, int i) {
     return (m[i >> 5] >> (i & 31)) & 1u;
 }
 
+// products of column p of a column-major matrix X (len rows) with its columns
+// l < p into out[0..p), eight columns per pass, FP64, fixed reduction tree
+template <typename T, int NT, int DC>
+__device__ void column_products(const T* __restrict__ X, int len, int p, double* out,
+                                AcaShared<T, NT / kWave>& sh) {
+    const T* __restrict__ Xp = X + (int64_t)p * len;
+    for (int c0 = 0; c0 < p; c0 += DC) {
+        const int nk = p - c0 < DC ? p - c0 : DC;
+        const T* __restrict__ Xc = X + (int64_t)c0 * len;
+        double acc[DC];
+#pragma unroll
+        for (int k = 0; k < DC; ++k) acc[k] = 0.0;
+        for (int ib = 0; ib < len; ib += kRows * NT) {
+#pragma unroll
+            for (int e = 0; e < kRows; ++e) {
+                const int i = ib + threadIdx.x + e * NT;
+                if (i < len) {
+                    const double x = (double)Xp[i];
+#pragma unroll
+                    for (int k = 0; k < DC; ++k)
+                        if (k < nk) acc[k] += x * (double)Xc[k * len + i];
+                }
+            }
+        }
+        block_sum_cols<DC>(acc, nk, out + c0, sh);
+    }
+}
+
+// the same products in the order of the deferred accumulation of the step
+// loop (per batch of kRows rows per thread and per column: a wave sum, added
+// to the wave's row of acc; the waves' rows are summed in order by the caller),
+// so that a test taken on them decides as the deferred one would
+template <typename T, int NT>
+__device__ void column_products_waved(const T* __restrict__ X, int len, int p,
+                                      double (*acc)[kMaxRankCap]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int l = lane; l < p; l += kWave) acc[w][l] = 0.0;
+    __syncthreads();
+    for (int ib = 0; ib < len; ib += kRows * NT) {
+        const int i0 = ib + threadIdx.x;
+        T xp[kRows];
+#pragma unroll
+        for (int k = 0; k < kRows; ++k)
+            xp[k] = i0 + k * NT < len ? X[(int64_t)p * len + i0 + k * NT] : (T)0;
+        for (int l = 0; l < p; ++l) {
+            const T* __restrict__ Xl = X + (int64_t)l * len;
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < kRows; ++k)
+                s += (double)xp[k] * (double)(i0 + k * NT < len ? Xl[i0 + k * NT] : (T)0);
+            s = wave_sum(s);
+            if (lane == 0) acc[w][l] += s;
+        }
+    }
+    __syncthreads();
+}
+
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void aca_kernel(
     const T* __restrict__ soa, const double* __restrict__ soa64, int64_t n, int d, KernelEval<T> K,
@@ -254,7 +311,9 @@ __global__ __launch_bounds__(NT) void aca_kernel(
     constexpr int DC = dot_cols<NT>();
     extern __shared__ uint32_t smask[];
     __shared__ AcaShared<T, NW> sh;
-    const int tid = threadIdx.x;
+    __shared__ double accu[NW][kMaxRankCap];  // deferred products, one row per wave
+    __shared__ double accv[NW][kMaxRankCap];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const double tol = eps * (1.0 - aca_eta) / (1.0 + eps);
 
     for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
@@ -293,6 +352,14 @@ __global__ __launch_bounds__(NT) void aca_kernel(
         int target = sized ? (rtarget[b] < R ? rtarget[b] : R) : R;
         bool refused = false;
         double last_p = 0.0;  // |u_r|^2 |v_r|^2 of the last term
+        // With the test applied every step, term p's products with the
+        // earlier terms are gathered while the passes of term p + 1 read
+        // those columns anyway; term p's test is taken once they are
+        // complete, and term p + 1 is dropped if it passes (it was computed
+        // speculatively).  The decisions are those of the step-by-step order.
+        const bool fuse = !fixed && !one_shot;
+        bool pending = false;     // term r - 1's test is still open
+        double nu2p = 0.0, nv2p = 0.0;
 
         int r = 0, ncols_used = 0, nfailed = 0, steps = 0;
         int j = first_column<T, NT>(soa64, n, d, bl, sh);
@@ -304,15 +371,41 @@ __global__ __launch_bounds__(NT) void aca_kernel(
                     one_shot = false;
                     if (sqrt(last_p) <= tol * sqrt(S2)) break;
                 }
+                if (pending) {
+                    // no room for a speculative term: term r - 1's products now,
+                    // summed in the order of the deferred accumulation
+                    column_products_waved<T, NT>(Uread, m, r - 1, accu);
+                    column_products_waved<T, NT>(Vread, nc, r - 1, accv);
+                    double cross = 0.0;
+                    for (int l = 0; l < r - 1; ++l) {
+                        double gu = accu[0][l], gv = accv[0][l];
+                        for (int q = 1; q < NW; ++q) {
+                            gu += accu[q][l];
+                            gv += accv[q][l];
+                        }
+                        cross += gu * gv;
+                    }
+                    __syncthreads();  // every wave has read the rows before any clears them
+                    S2 += 2.0 * cross + nu2p * nv2p;
+                    last_p = nu2p * nv2p;
+                    pending = false;
+                    if (sqrt(last_p) <= tol * sqrt(S2)) break;
+                }
                 if (cap_only) {
                     refused = true;
                     break;
                 }
                 target = R;
             }
+            const int p = r - 1;  // the open term, when pending
             // ---- step 1: residual column j into U[:, r] ----
-            if (tid < r) sh.vec[tid] = V[(int64_t)tid * nc + j];
+            for (int l = tid; l < r; l += NT) sh.vec[l] = V[(int64_t)l * nc + j];
             if (tid == 0) cmask[j >> 5] |= 1u << (j & 31);
+            if (pending)
+                for (int l = lane; l < p; l += kWave) {
+                    accu[w][l] = 0.0;
+                    accv[w][l] = 0.0;
+                }
             __syncthreads();
             ++ncols_used;
             ++steps;
@@ -320,27 +413,41 @@ __global__ __launch_bounds__(NT) void aca_kernel(
             load_pt(soa, n, d, (int64_t)bl.z + j, yj);
             Arg<T> am{(T)-1, INT_MAX, (T)0};
             double colmax = 0.0;
-            // kRows rows per thread per pass, so kRows * r loads are in flight
-            for (int i0 = tid; i0 < m; i0 += kRows * NT) {
-                T a[kRows];
+            // kRows rows per thread per pass (kRows * r loads in flight); the
+            // trip count is the same for every thread of the workgroup
+            for (int ib = 0; ib < m; ib += kRows * NT) {
+                const int i0 = ib + tid;
+                T a[kRows], up[kRows];
 #pragma unroll
                 for (int k = 0; k < kRows; ++k) {
                     const int i = i0 + k * NT;
                     a[k] = 0;
+                    up[k] = 0;
                     if (i < m) {
                         T xi[3];
                         load_pt(soa, n, d, (int64_t)bl.x + i, xi);
                         a[k] = phi(K, xi, yj, d);
                         const double aa0 = a[k] < (T)0 ? -(double)a[k] : (double)a[k];
                         colmax = aa0 > colmax ? aa0 : colmax;
+                        if (pending) up[k] = Uread[(int64_t)p * m + i];
                     }
                 }
                 for (int l = 0; l < r; ++l) {
                     const T vl = sh.vec[l];
                     const T* __restrict__ Ul = Uread + (int64_t)l * m;
+                    T val[kRows];
 #pragma unroll
-                    for (int k = 0; k < kRows; ++k)
-                        if (i0 + k * NT < m) a[k] -= Ul[i0 + k * NT] * vl;
+                    for (int k = 0; k < kRows; ++k) {
+                        val[k] = i0 + k * NT < m ? Ul[i0 + k * NT] : (T)0;
+                        a[k] -= val[k] * vl;
+                    }
+                    if (pending && l < p) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int k = 0; k < kRows; ++k) s += (double)up[k] * (double)val[k];
+                        s = wave_sum(s);
+                        if (lane == 0) accu[w][l] += s;
+                    }
                 }
 #pragma unroll
                 for (int k = 0; k < kRows; ++k) {
@@ -377,44 +484,23 @@ __global__ __launch_bounds__(NT) void aca_kernel(
             }
             const int ip = am.idx;
             const T piv = am.val;
-            // ---- step 3a: normalise u_r; with it, u_r . u_l for l < r ----
+            // ---- step 3a: normalise u_r, |u_r|^2 ----
             double nu2 = 0.0;
             T* __restrict__ Ur = U + (int64_t)r * m;
-            for (int c0 = 0; c0 == 0 || c0 < r; c0 += DC) {
-                const int nk = r - c0 < DC ? r - c0 : DC;
-                const T* __restrict__ Uc = U + (int64_t)c0 * m;
-                double acc[DC];
+            for (int ib = 0; ib < m; ib += kRows * NT) {
 #pragma unroll
-                for (int k = 0; k < DC; ++k) acc[k] = 0.0;
-                for (int i0 = tid; i0 < m; i0 += kRows * NT) {
-                    T u[kRows];
-#pragma unroll
-                    for (int e = 0; e < kRows; ++e) {
-                        const int i = i0 + e * NT;
-                        u[e] = 0;
-                        if (i < m) {
-                            u[e] = Ur[i];
-                            if (c0 == 0) {
-                                u[e] = u[e] / piv;
-                                Ur[i] = u[e];
-                                nu2 += (double)u[e] * (double)u[e];
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int e = 0; e < kRows; ++e) {
-                        const int i = i0 + e * NT;
-                        if (i < m) {
-#pragma unroll
-                            for (int k = 0; k < DC; ++k)
-                                if (k < nk) acc[k] += (double)u[e] * (double)Uc[k * m + i];
-                        }
+                for (int e = 0; e < kRows; ++e) {
+                    const int i = ib + tid + e * NT;
+                    if (i < m) {
+                        const T u = Ur[i] / piv;
+                        Ur[i] = u;
+                        nu2 += (double)u * (double)u;
                     }
                 }
-                if (nk > 0) block_sum_cols<DC>(acc, nk, sh.gu + c0, sh);
             }
             nu2 = block_sum(nu2, sh, 0);
-            if (tid < r) sh.vec[tid] = U[(int64_t)tid * m + ip];
+            if (!fuse && !fixed) column_products<T, NT, DC>(Uread, m, r, sh.gu, sh);
+            for (int l = tid; l < r; l += NT) sh.vec[l] = U[(int64_t)l * m + ip];
             if (tid == 0) rmask[ip >> 5] |= 1u << (ip & 31);
             __syncthreads();
             // ---- step 3b: residual row i_r into V[:, r] ----
@@ -422,24 +508,37 @@ __global__ __launch_bounds__(NT) void aca_kernel(
             load_pt(soa, n, d, (int64_t)bl.x + ip, xp);
             double nv2 = 0.0;
             Arg<T> cm{(T)-1, INT_MAX, (T)0};
-            for (int q0 = tid; q0 < nc; q0 += kRows * NT) {
-                T a[kRows];
+            for (int qb = 0; qb < nc; qb += kRows * NT) {
+                const int q0 = qb + tid;
+                T a[kRows], vp[kRows];
 #pragma unroll
                 for (int k = 0; k < kRows; ++k) {
                     const int q = q0 + k * NT;
                     a[k] = 0;
+                    vp[k] = 0;
                     if (q < nc) {
                         T yq[3];
                         load_pt(soa, n, d, (int64_t)bl.z + q, yq);
                         a[k] = phi(K, xp, yq, d);
+                        if (pending) vp[k] = Vread[(int64_t)p * nc + q];
                     }
                 }
                 for (int l = 0; l < r; ++l) {
                     const T ul = sh.vec[l];
                     const T* __restrict__ Vl = Vread + (int64_t)l * nc;
+                    T val[kRows];
 #pragma unroll
-                    for (int k = 0; k < kRows; ++k)
-                        if (q0 + k * NT < nc) a[k] -= ul * Vl[q0 + k * NT];
+                    for (int k = 0; k < kRows; ++k) {
+                        val[k] = q0 + k * NT < nc ? Vl[q0 + k * NT] : (T)0;
+                        a[k] -= ul * val[k];
+                    }
+                    if (pending && l < p) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int k = 0; k < kRows; ++k) s += (double)vp[k] * (double)val[k];
+                        s = wave_sum(s);
+                        if (lane == 0) accv[w][l] += s;
+                    }
                 }
 #pragma unroll
                 for (int k = 0; k < kRows; ++k) {
@@ -457,36 +556,54 @@ __global__ __launch_bounds__(NT) void aca_kernel(
                 }
             }
             nv2 = block_sum(nv2, sh, 1);
+            // term p's products are complete once every wave has passed the
+            // barrier of the sum above; they are read here, before the
+            // barriers of the argmax, so that no wave clears its row for the
+            // next step while another still reads it
+            double cross_p = 0.0;
+            if (pending) {
+                for (int l = 0; l < p; ++l) {
+                    double gu = accu[0][l], gv = accv[0][l];
+                    for (int q = 1; q < NW; ++q) {
+                        gu += accu[q][l];
+                        gv += accv[q][l];
+                    }
+                    cross_p += gu * gv;
+                }
+            }
             cm = block_argmax(cm, sh);
-            // ---- step 4: v_r . v_l for l < r, then the norm update ----
-            const T* __restrict__ Vr = V + (int64_t)r * nc;
-            for (int c0 = 0; c0 < r; c0 += DC) {
-                const int nk = r - c0 < DC ? r - c0 : DC;
-                const T* __restrict__ Vc = V + (int64_t)c0 * nc;
-                double acc[DC];
-#pragma unroll
-                for (int k = 0; k < DC; ++k) acc[k] = 0.0;
-                for (int q0 = tid; q0 < nc; q0 += kRows * NT) {
-#pragma unroll
-                    for (int e = 0; e < kRows; ++e) {
-                        const int q = q0 + e * NT;
-                        if (q < nc) {
-                            const double v = (double)Vr[q];
-#pragma unroll
-                            for (int k = 0; k < DC; ++k)
-                                if (k < nk) acc[k] += v * (double)Vc[k * nc + q];
-                        }
+            // ---- step 4: the norm recursion and the stopping test ----
+            ++r;
+            if (!fuse) {
+                double cross = 0.0;
+                if (!fixed) {
+                    column_products<T, NT, DC>(Vread, nc, r - 1, sh.gv, sh);
+                    for (int l = 0; l < r - 1; ++l) cross += sh.gu[l] * sh.gv[l];
+                }
+                S2 += 2.0 * cross + nu2 * nv2;
+                last_p = nu2 * nv2;
+                if (!fixed && !one_shot && sqrt(last_p) <= tol * sqrt(S2)) break;
+            } else {
+                if (pending) {
+                    // term r - 2 = p, its products summed over the waves in order
+                    S2 += 2.0 * cross_p + nu2p * nv2p;
+                    last_p = nu2p * nv2p;
+                    if (sqrt(last_p) <= tol * sqrt(S2)) {
+                        r -= 1;  // the speculative term is dropped
+                        break;
                     }
                 }
-                block_sum_cols<DC>(acc, nk, sh.gv + c0, sh);
+                if (r == 1) {  // the first term has no products
+                    S2 = nu2 * nv2;
+                    last_p = S2;
+                    pending = false;
+                    if (sqrt(last_p) <= tol * sqrt(S2)) break;
+                } else {
+                    pending = true;
+                    nu2p = nu2;
+                    nv2p = nv2;
+                }
             }
-            double cross = 0.0;
-            for (int l = 0; l < r; ++l) cross += sh.gu[l] * sh.gv[l];
-            ++r;
-            S2 += 2.0 * cross + nu2 * nv2;
-            last_p = nu2 * nv2;
-            // ---- step 5: stopping criterion ----
-            if (!fixed && !one_shot && sqrt(last_p) <= tol * sqrt(S2)) break;
             // ---- step 6: next column pivot ----
             if (cm.idx == INT_MAX) break;
             j = cm.idx;

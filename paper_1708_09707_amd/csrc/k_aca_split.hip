@@ -26,6 +26,7 @@ constexpr int kST = 256;           // threads per workgroup
 constexpr int kSRows = 8;          // rows (columns) per thread per tile
 constexpr int kTile = kST * kSRows;  // rows per row tile, columns per column tile
 constexpr int kSDot = 8;           // previous columns per inner-product pass
+static_assert(kST > kMaxRankCap, "one thread per previous column and the pivot slot");
 
 template <typename T>
 struct Arg {
@@ -647,10 +648,10 @@ hipError_t run_split(const AcaArgs& A, const SplitPlan& P, hipStream_t st) {
             // poll: stop once every block has finished
             hipLaunchKernelGGL(split_count_kernel, dim3(1), dim3(kST), 0, st, state, nb,
                                P.active_dev);
-            int active = 1;
-            e = hipMemcpyAsync(&active, P.active_dev, sizeof(int), hipMemcpyDeviceToHost, st);
+            e = hipMemcpyAsync(P.active_host, P.active_dev, sizeof(int), hipMemcpyDeviceToHost,
+                               st);
             if (e == hipSuccess) e = hipStreamSynchronize(st);
-            if (e == hipSuccess && active == 0) break;
+            if (e == hipSuccess && *P.active_host == 0) break;
         }
     }
     if (e != hipSuccess) return e;
