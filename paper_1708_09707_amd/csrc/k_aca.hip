@@ -16,9 +16,12 @@
 //   4. |S_r|_F^2 += 2 sum_{l<r} (u_r.u_l)(v_r.v_l) + |u_r|^2 |v_r|^2   in FP64
 //   5. stop if |u_r| |v_r| <= eps (1 - aca_eta) / (1 + eps) |S_r|_F
 //   6. next column pivot j = argmax over unused columns |(v_r)_j|
-// The inner products of step 4 are computed by the whole workgroup, eight
-// previous columns per pass, in FP64; the U products ride along with the
-// normalisation of u_r.
+// The inner products of step 4 are FP64.  With the test applied every step,
+// term r's products with the earlier terms are gathered during the residual
+// passes of step r + 1, which read those columns anyway (term r + 1 is then
+// speculative and dropped if term r's test passes); otherwise the whole
+// workgroup computes them after the row, eight previous columns per pass.
+// Every pass issues the loads of several previous columns before using them.
 // Learned rank sizing gives every block a predicted target: storage for that
 // many columns with the test in 5 applied every step (sizing form), or
 // exactly that many steps with the test applied to the last term only
@@ -42,6 +45,7 @@ namespace {
 
 constexpr int kDotCols = 8;     // previous columns per inner-product pass
 constexpr int kRows = 4;        // rows per thread per residual pass
+constexpr int kLU = 8;          // previous columns whose loads are in flight together
 constexpr int kBigThreads = 512;  // workgroup size of the upper-level class
 
 template <int NT>
@@ -72,6 +76,95 @@ __device__ __forceinline__ Arg<T> wave_argmax(Arg<T> a) {
         arg_combine(a, b);
     }
     return a;
+}
+
+// ---------------------------------------------------------------------------
+// Wave reductions on the DPP crossbar: the quad swaps (lane i with i ^ 1, then
+// i ^ 2), the half-row mirror (i with 7 - i) and the row mirror (i with
+// 15 - i) leave every lane of a row of 16 holding the row's total; the four
+// rows are then combined from scalar reads.  The result is the same on every
+// lane and needs no permute indices or LDS traffic.
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v) {
+    return dpp_i<CTRL>(v);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)dpp_i<CTRL>((int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)dpp_i<CTRL>((int)(uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int lane_read(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float lane_read(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// sum over the wave, (row 0 + row 1) + (row 2 + row 3)
+__device__ __forceinline__ double wave_total(double v) {
+    v += dpp<kDppXor1>(v);
+    v += dpp<kDppXor2>(v);
+    v += dpp<kDppHalfMirror>(v);
+    v += dpp<kDppMirror>(v);
+    return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+    double u = dpp<kDppXor1>(v);
+    v = u > v ? u : v;
+    u = dpp<kDppXor2>(v);
+    v = u > v ? u : v;
+    u = dpp<kDppHalfMirror>(v);
+    v = u > v ? u : v;
+    u = dpp<kDppMirror>(v);
+    v = u > v ? u : v;
+    double r = lane_read(v, 0);
+#pragma unroll
+    for (int q = 16; q < 64; q += 16) {
+        const double t = lane_read(v, q);
+        r = t > r ? t : r;
+    }
+    return r;
+}
+
+template <typename T, int CTRL>
+__device__ __forceinline__ Arg<T> dpp_arg(const Arg<T>& a) {
+    return Arg<T>{dpp<CTRL>(a.best), dpp<CTRL>(a.idx), dpp<CTRL>(a.val)};
+}
+
+// the largest |value| of the wave, lowest index on ties (the same element
+// whatever the order of combination)
+template <typename T>
+__device__ __forceinline__ Arg<T> wave_argmax_u(Arg<T> a) {
+    arg_combine(a, dpp_arg<T, kDppXor1>(a));
+    arg_combine(a, dpp_arg<T, kDppXor2>(a));
+    arg_combine(a, dpp_arg<T, kDppHalfMirror>(a));
+    arg_combine(a, dpp_arg<T, kDppMirror>(a));
+    Arg<T> r{lane_read(a.best, 0), lane_read(a.idx, 0), lane_read(a.val, 0)};
+#pragma unroll
+    for (int q = 16; q < 64; q += 16)
+        arg_combine(r, Arg<T>{lane_read(a.best, q), lane_read(a.idx, q), lane_read(a.val, q)});
+    return r;
 }
 
 template <typename T, int NW>
@@ -270,6 +363,107 @@ __device__ void column_products(const T* __restrict__ X, int len, int p, double*
     }
 }
 
+// Rows i0 + k NT (k < kRows) of a pass: indices clamped into [0, len) so that
+// every load is issued unconditionally (the loads of a batch then overlap
+// instead of each waiting behind the branch of its own bounds test).
+template <int NT>
+__device__ __forceinline__ void clamp_rows(int i0, int len, int (&ic)[kRows], bool (&ok)[kRows]) {
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int i = i0 + k * NT;
+        ok[k] = i < len;
+        ic[k] = ok[k] ? i : len - 1;
+    }
+}
+
+// element at a 32-bit byte offset from a wave-uniform base
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* __restrict__ base, uint32_t byte_off) {
+    return *(const T*)((const char*)base + byte_off);
+}
+
+// Loads through a raw buffer descriptor on a wave-uniform base: the per-lane
+// part of the address is one 32-bit offset shared by all columns of a pass,
+// the column offset a scalar.  Every index is clamped into its array before
+// the load, so the descriptor's range check never applies (its size is the
+// largest the field holds).
+constexpr int kBufWord3 = 0x00020000;  // 32-bit data format, the raw-buffer form on CDNA
+
+template <typename T>
+struct BufView {
+    __amdgpu_buffer_rsrc_t rs;
+    __device__ __forceinline__ explicit BufView(const T* base)
+        : rs(__builtin_amdgcn_make_buffer_rsrc((void*)base, 0, 0x7fffffff, kBufWord3)) {}
+    __device__ __forceinline__ T at(uint32_t voff, uint32_t soff) const;
+};
+
+template <>
+__device__ __forceinline__ float BufView<float>::at(uint32_t voff, uint32_t soff) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, 0));
+}
+
+template <>
+__device__ __forceinline__ double BufView<double>::at(uint32_t voff, uint32_t soff) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0));
+}
+
+// coordinates of point first + row (row's byte offset boff) of a d x n SoA array
+template <typename T>
+__device__ __forceinline__ void load_pt_buf(const BufView<T>& pts, int64_t n, int d, uint32_t boff,
+                                            T* p) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        p[k] = (k < d) ? pts.at(boff, (uint32_t)((int64_t)k * n * (int64_t)sizeof(T))) : (T)0;
+}
+
+// a[k] -= X_l[row k] c_l for l = 0, 1, ..., r - 1 in that order (columns of
+// the column-major X, leading dimension ld; coefficients c in LDS), kLU
+// columns' loads in flight at once; padding columns beyond r weigh zero.
+// With pend, also the products of column p's rows xp[k] (zero on rows outside
+// the block) with every column l < p, per column a wave sum added to acc[l]
+// (lane 0): the deferred inner products of the open term.
+template <typename T>
+__device__ __forceinline__ void subtract_columns(const T* __restrict__ X, int64_t ld, int r,
+                                                 const T* coef, const int (&ic)[kRows],
+                                                 T (&a)[kRows], bool pend, int p,
+                                                 const T (&xp)[kRows], double* acc, int lane) {
+    // r and p are the same on every lane; saying so keeps the column bases scalar
+    r = __builtin_amdgcn_readfirstlane(r);
+    p = __builtin_amdgcn_readfirstlane(p);
+    uint32_t off[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) off[k] = (uint32_t)ic[k] * (uint32_t)sizeof(T);
+    for (int l0 = 0; l0 < r; l0 += kLU) {
+        const BufView<T> cols(X + (int64_t)l0 * ld);
+        T c[kLU], val[kLU][kRows];
+#pragma unroll
+        for (int q = 0; q < kLU; ++q) {
+            const bool in = l0 + q < r;
+            const int l = in ? l0 + q : r - 1;
+            c[q] = in ? coef[l] : (T)0;
+            const uint32_t soff = (uint32_t)((int64_t)(l - l0) * ld * (int64_t)sizeof(T));
+#pragma unroll
+            for (int k = 0; k < kRows; ++k) val[q][k] = cols.at(off[k], soff);
+        }
+#pragma unroll
+        for (int q = 0; q < kLU; ++q)
+#pragma unroll
+            for (int k = 0; k < kRows; ++k) a[k] -= val[q][k] * c[q];
+        if (pend) {
+#pragma unroll
+            for (int q = 0; q < kLU; ++q) {
+                if (l0 + q < p) {
+                    double sum = 0.0;
+#pragma unroll
+                    for (int k = 0; k < kRows; ++k) sum += (double)xp[k] * (double)val[q][k];
+                    sum = wave_total(sum);
+                    if (lane == 0) acc[l0 + q] += sum;
+                }
+            }
+        }
+    }
+}
+
 // the same products in the order of the deferred accumulation of the step
 // loop (per batch of kRows rows per thread and per column: a wave sum, added
 // to the wave's row of acc; the waves' rows are summed in order by the caller),
@@ -278,22 +472,41 @@ template <typename T, int NT>
 __device__ void column_products_waved(const T* __restrict__ X, int len, int p,
                                       double (*acc)[kMaxRankCap]) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    p = __builtin_amdgcn_readfirstlane(p);
     for (int l = lane; l < p; l += kWave) acc[w][l] = 0.0;
     __syncthreads();
     for (int ib = 0; ib < len; ib += kRows * NT) {
-        const int i0 = ib + threadIdx.x;
+        int ic[kRows];
+        bool ok[kRows];
+        clamp_rows<NT>(ib + threadIdx.x, len, ic, ok);
+        uint32_t off[kRows];
         T xp[kRows];
 #pragma unroll
-        for (int k = 0; k < kRows; ++k)
-            xp[k] = i0 + k * NT < len ? X[(int64_t)p * len + i0 + k * NT] : (T)0;
-        for (int l = 0; l < p; ++l) {
-            const T* __restrict__ Xl = X + (int64_t)l * len;
-            double s = 0.0;
+        for (int k = 0; k < kRows; ++k) {
+            off[k] = (uint32_t)ic[k] * (uint32_t)sizeof(T);
+            const T v = ld_at(X + (int64_t)p * len, off[k]);
+            xp[k] = ok[k] ? v : (T)0;
+        }
+        for (int l0 = 0; l0 < p; l0 += kLU) {
+            const BufView<T> cols(X + (int64_t)l0 * len);
+            T val[kLU][kRows];
 #pragma unroll
-            for (int k = 0; k < kRows; ++k)
-                s += (double)xp[k] * (double)(i0 + k * NT < len ? Xl[i0 + k * NT] : (T)0);
-            s = wave_sum(s);
-            if (lane == 0) acc[w][l] += s;
+            for (int q = 0; q < kLU; ++q) {
+                const int l = l0 + q < p ? l0 + q : p - 1;
+                const uint32_t soff = (uint32_t)((int64_t)(l - l0) * len * (int64_t)sizeof(T));
+#pragma unroll
+                for (int k = 0; k < kRows; ++k) val[q][k] = cols.at(off[k], soff);
+            }
+#pragma unroll
+            for (int q = 0; q < kLU; ++q) {
+                if (l0 + q < p) {
+                    double sum = 0.0;
+#pragma unroll
+                    for (int k = 0; k < kRows; ++k) sum += (double)xp[k] * (double)val[q][k];
+                    sum = wave_total(sum);
+                    if (lane == 0) acc[w][l0 + q] += sum;
+                }
+            }
         }
     }
     __syncthreads();
@@ -324,10 +537,12 @@ __global__ __launch_bounds__(NT) void aca_kernel(
         R = nc < R ? nc : R;
         T* __restrict__ U = Upool + (uoff[b] - ubase);
         T* __restrict__ V = Vpool + (voff[b] - vbase);
+        const BufView<T> rows_pts(soa + bl.x), cols_pts(soa + bl.z);
         // columns l < r are only read in a step, column r only written
         const T* __restrict__ Uread = U;
         const T* __restrict__ Vread = V;
         const int mw = (m + 31) >> 5, nw = (nc + 31) >> 5;
+        const bool single = m <= kRows * NT;  // one pass covers every row
         if (mw + nw > lds_words) {  // outside this launch's size class (never by construction)
             if (tid == 0) {
                 rank_out[b] = 0;
@@ -413,47 +628,37 @@ __global__ __launch_bounds__(NT) void aca_kernel(
             load_pt(soa, n, d, (int64_t)bl.z + j, yj);
             Arg<T> am{(T)-1, INT_MAX, (T)0};
             double colmax = 0.0;
-            // kRows rows per thread per pass (kRows * r loads in flight); the
-            // trip count is the same for every thread of the workgroup
+            T keep[kRows];  // the residual column itself when the block has one pass of rows
+            // kRows rows per thread per pass; the trip count is the same for
+            // every thread of the workgroup
             for (int ib = 0; ib < m; ib += kRows * NT) {
-                const int i0 = ib + tid;
-                T a[kRows], up[kRows];
+                int ic[kRows];
+                bool ok[kRows];
+                clamp_rows<NT>(ib + tid, m, ic, ok);
+                T xi[kRows][3], a[kRows], up[kRows];
 #pragma unroll
                 for (int k = 0; k < kRows; ++k) {
-                    const int i = i0 + k * NT;
-                    a[k] = 0;
-                    up[k] = 0;
-                    if (i < m) {
-                        T xi[3];
-                        load_pt(soa, n, d, (int64_t)bl.x + i, xi);
-                        a[k] = phi(K, xi, yj, d);
-                        const double aa0 = a[k] < (T)0 ? -(double)a[k] : (double)a[k];
-                        colmax = aa0 > colmax ? aa0 : colmax;
-                        if (pending) up[k] = Uread[(int64_t)p * m + i];
-                    }
-                }
-                for (int l = 0; l < r; ++l) {
-                    const T vl = sh.vec[l];
-                    const T* __restrict__ Ul = Uread + (int64_t)l * m;
-                    T val[kRows];
-#pragma unroll
-                    for (int k = 0; k < kRows; ++k) {
-                        val[k] = i0 + k * NT < m ? Ul[i0 + k * NT] : (T)0;
-                        a[k] -= val[k] * vl;
-                    }
-                    if (pending && l < p) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int k = 0; k < kRows; ++k) s += (double)up[k] * (double)val[k];
-                        s = wave_sum(s);
-                        if (lane == 0) accu[w][l] += s;
+                    const uint32_t off = (uint32_t)ic[k] * (uint32_t)sizeof(T);
+                    load_pt_buf(rows_pts, n, d, off, xi[k]);
+                    up[k] = (T)0;
+                    if (pending) {
+                        const T v = ld_at(Uread + (int64_t)p * m, off);
+                        up[k] = ok[k] ? v : (T)0;
                     }
                 }
 #pragma unroll
                 for (int k = 0; k < kRows; ++k) {
-                    const int i = i0 + k * NT;
-                    if (i < m) {
-                        U[(int64_t)r * m + i] = a[k];
+                    a[k] = ok[k] ? phi(K, xi[k], yj, d) : (T)0;
+                    const double aa0 = a[k] < (T)0 ? -(double)a[k] : (double)a[k];
+                    colmax = aa0 > colmax ? aa0 : colmax;
+                }
+                subtract_columns(Uread, m, r, sh.vec, ic, a, pending, p, up, accu[w], lane);
+#pragma unroll
+                for (int k = 0; k < kRows; ++k) {
+                    keep[k] = a[k];
+                    if (ok[k]) {
+                        const int i = ic[k];
+                        if (!single) U[(int64_t)r * m + i] = a[k];
                         const T aa = a[k] < (T)0 ? -a[k] : a[k];
                         if (!bit_get(rmask, i) && aa > am.best) {
                             am.best = aa;
@@ -463,8 +668,25 @@ __global__ __launch_bounds__(NT) void aca_kernel(
                     }
                 }
             }
-            am = block_argmax(am, sh);
-            colmax = block_minmax(colmax, 1, sh);
+            // row pivot and the column's largest |entry| in one reduction
+            am = wave_argmax_u(am);
+            colmax = wave_max(colmax);
+            if constexpr (NW > 1) {
+                if (lane == 0) {
+                    sh.abest[w] = am.best;
+                    sh.aidx[w] = am.idx;
+                    sh.aval[w] = am.val;
+                    sh.dkey[w] = colmax;
+                }
+                __syncthreads();
+                am = Arg<T>{sh.abest[0], sh.aidx[0], sh.aval[0]};
+                colmax = sh.dkey[0];
+                for (int q = 1; q < NW; ++q) {
+                    arg_combine(am, Arg<T>{sh.abest[q], sh.aidx[q], sh.aval[q]});
+                    colmax = sh.dkey[q] > colmax ? sh.dkey[q] : colmax;
+                }
+                __syncthreads();
+            }
             if (am.idx == INT_MAX || (double)am.best <= (double)eps0 * colmax) {
                 // no usable pivot in this column: try the lowest unused column
                 ++nfailed;
@@ -484,21 +706,40 @@ __global__ __launch_bounds__(NT) void aca_kernel(
             }
             const int ip = am.idx;
             const T piv = am.val;
-            // ---- step 3a: normalise u_r, |u_r|^2 ----
+            // ---- step 3a: u_r = u^ / pivot; |u_r|^2 is reduced with the row's sums ----
             double nu2 = 0.0;
             T* __restrict__ Ur = U + (int64_t)r * m;
-            for (int ib = 0; ib < m; ib += kRows * NT) {
+            if (single) {
+                int ic[kRows];
+                bool ok[kRows];
+                clamp_rows<NT>(tid, m, ic, ok);
 #pragma unroll
-                for (int e = 0; e < kRows; ++e) {
-                    const int i = ib + tid + e * NT;
-                    if (i < m) {
-                        const T u = Ur[i] / piv;
-                        Ur[i] = u;
+                for (int k = 0; k < kRows; ++k) {
+                    if (ok[k]) {
+                        const T u = keep[k] / piv;
+                        Ur[ic[k]] = u;
                         nu2 += (double)u * (double)u;
                     }
                 }
+            } else {
+                for (int ib = 0; ib < m; ib += kRows * NT) {
+                    int ic[kRows];
+                    bool ok[kRows];
+                    clamp_rows<NT>(ib + tid, m, ic, ok);
+                    T u[kRows];
+#pragma unroll
+                    for (int k = 0; k < kRows; ++k)
+                        u[k] = ld_at(Ur, (uint32_t)ic[k] * (uint32_t)sizeof(T));
+#pragma unroll
+                    for (int k = 0; k < kRows; ++k) {
+                        if (ok[k]) {
+                            u[k] = u[k] / piv;
+                            Ur[ic[k]] = u[k];
+                            nu2 += (double)u[k] * (double)u[k];
+                        }
+                    }
+                }
             }
-            nu2 = block_sum(nu2, sh, 0);
             if (!fuse && !fixed) column_products<T, NT, DC>(Uread, m, r, sh.gu, sh);
             for (int l = tid; l < r; l += NT) sh.vec[l] = U[(int64_t)l * m + ip];
             if (tid == 0) rmask[ip >> 5] |= 1u << (ip & 31);
@@ -509,41 +750,27 @@ __global__ __launch_bounds__(NT) void aca_kernel(
             double nv2 = 0.0;
             Arg<T> cm{(T)-1, INT_MAX, (T)0};
             for (int qb = 0; qb < nc; qb += kRows * NT) {
-                const int q0 = qb + tid;
-                T a[kRows], vp[kRows];
+                int ic[kRows];
+                bool ok[kRows];
+                clamp_rows<NT>(qb + tid, nc, ic, ok);
+                T yq[kRows][3], a[kRows], vp[kRows];
 #pragma unroll
                 for (int k = 0; k < kRows; ++k) {
-                    const int q = q0 + k * NT;
-                    a[k] = 0;
-                    vp[k] = 0;
-                    if (q < nc) {
-                        T yq[3];
-                        load_pt(soa, n, d, (int64_t)bl.z + q, yq);
-                        a[k] = phi(K, xp, yq, d);
-                        if (pending) vp[k] = Vread[(int64_t)p * nc + q];
-                    }
-                }
-                for (int l = 0; l < r; ++l) {
-                    const T ul = sh.vec[l];
-                    const T* __restrict__ Vl = Vread + (int64_t)l * nc;
-                    T val[kRows];
-#pragma unroll
-                    for (int k = 0; k < kRows; ++k) {
-                        val[k] = q0 + k * NT < nc ? Vl[q0 + k * NT] : (T)0;
-                        a[k] -= ul * val[k];
-                    }
-                    if (pending && l < p) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int k = 0; k < kRows; ++k) s += (double)vp[k] * (double)val[k];
-                        s = wave_sum(s);
-                        if (lane == 0) accv[w][l] += s;
+                    const uint32_t off = (uint32_t)ic[k] * (uint32_t)sizeof(T);
+                    load_pt_buf(cols_pts, n, d, off, yq[k]);
+                    vp[k] = (T)0;
+                    if (pending) {
+                        const T v = ld_at(Vread + (int64_t)p * nc, off);
+                        vp[k] = ok[k] ? v : (T)0;
                     }
                 }
 #pragma unroll
+                for (int k = 0; k < kRows; ++k) a[k] = ok[k] ? phi(K, xp, yq[k], d) : (T)0;
+                subtract_columns(Vread, nc, r, sh.vec, ic, a, pending, p, vp, accv[w], lane);
+#pragma unroll
                 for (int k = 0; k < kRows; ++k) {
-                    const int q = q0 + k * NT;
-                    if (q < nc) {
+                    if (ok[k]) {
+                        const int q = ic[k];
                         V[(int64_t)r * nc + q] = a[k];
                         nv2 += (double)a[k] * (double)a[k];
                         const T aa = a[k] < (T)0 ? -a[k] : a[k];
@@ -555,11 +782,31 @@ __global__ __launch_bounds__(NT) void aca_kernel(
                     }
                 }
             }
-            nv2 = block_sum(nv2, sh, 1);
-            // term p's products are complete once every wave has passed the
-            // barrier of the sum above; they are read here, before the
-            // barriers of the argmax, so that no wave clears its row for the
-            // next step while another still reads it
+            // next column pivot, |u_r|^2, |v_r|^2 and (term p's products being
+            // complete) the cross sum of term p, in one reduction; the rows of
+            // the deferred products are read before its closing barrier so
+            // that no wave clears them for the next step while another reads
+            cm = wave_argmax_u(cm);
+            nu2 = wave_total(nu2);
+            nv2 = wave_total(nv2);
+            if constexpr (NW > 1) {
+                if (lane == 0) {
+                    sh.abest[w] = cm.best;
+                    sh.aidx[w] = cm.idx;
+                    sh.aval[w] = cm.val;
+                    sh.dsum[0][w] = nu2;
+                    sh.dsum[1][w] = nv2;
+                }
+                __syncthreads();
+                cm = Arg<T>{sh.abest[0], sh.aidx[0], sh.aval[0]};
+                nu2 = sh.dsum[0][0];
+                nv2 = sh.dsum[1][0];
+                for (int q = 1; q < NW; ++q) {
+                    arg_combine(cm, Arg<T>{sh.abest[q], sh.aidx[q], sh.aval[q]});
+                    nu2 += sh.dsum[0][q];
+                    nv2 += sh.dsum[1][q];
+                }
+            }
             double cross_p = 0.0;
             if (pending) {
                 for (int l = 0; l < p; ++l) {
@@ -571,7 +818,7 @@ __global__ __launch_bounds__(NT) void aca_kernel(
                     cross_p += gu * gv;
                 }
             }
-            cm = block_argmax(cm, sh);
+            if constexpr (NW > 1) __syncthreads();
             // ---- step 4: the norm recursion and the stopping test ----
             ++r;
             if (!fuse) {

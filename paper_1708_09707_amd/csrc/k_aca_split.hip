@@ -26,6 +26,7 @@ constexpr int kST = 256;           // threads per workgroup
 constexpr int kSRows = 8;          // rows (columns) per thread per tile
 constexpr int kTile = kST * kSRows;  // rows per row tile, columns per column tile
 constexpr int kSDot = 8;           // previous columns per inner-product pass
+constexpr int kSLU = 4;            // previous columns whose loads are in flight together
 static_assert(kST > kMaxRankCap, "one thread per previous column and the pivot slot");
 
 template <typename T>
@@ -87,6 +88,96 @@ __device__ double wg_max(double v, double* sh) {
 
 __device__ __forceinline__ bool bit_get(const uint32_t* m, int i) {
     return (m[i >> 5] >> (i & 31)) & 1u;
+}
+
+// rows tile0 + threadIdx.x + k kST of a tile, clamped into [0, len) so that
+// every load is issued unconditionally and a batch of loads overlaps
+__device__ __forceinline__ void tile_rows(int first, int len, int (&ic)[kSRows], bool (&ok)[kSRows]) {
+#pragma unroll
+    for (int k = 0; k < kSRows; ++k) {
+        const int i = first + k * kST;
+        ok[k] = i < len;
+        ic[k] = ok[k] ? i : len - 1;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_pts(const T* __restrict__ soa, int64_t n, int d, int64_t base,
+                                         const int (&ic)[kSRows], T (&p)[kSRows][3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < kSRows; ++k)
+            p[k][c] = c < d ? soa[(int64_t)c * n + base + ic[k]] : (T)0;
+}
+
+// x[k] -= X_l[row k] coef_l for l = 0 .. r - 1 in that order, kSLU columns'
+// loads in flight at once (padding columns weigh zero)
+template <typename T>
+__device__ __forceinline__ void tile_subtract(const T* __restrict__ X, int64_t ld, int r,
+                                              const T* coef, const int (&ic)[kSRows],
+                                              T (&x)[kSRows]) {
+    r = __builtin_amdgcn_readfirstlane(r);
+    for (int l0 = 0; l0 < r; l0 += kSLU) {
+        T c[kSLU], val[kSLU][kSRows];
+#pragma unroll
+        for (int q = 0; q < kSLU; ++q) {
+            const bool in = l0 + q < r;
+            const int l = in ? l0 + q : r - 1;
+            c[q] = in ? coef[l] : (T)0;
+            const T* __restrict__ Xl = X + (int64_t)l * ld;
+#pragma unroll
+            for (int k = 0; k < kSRows; ++k) val[q][k] = Xl[ic[k]];
+        }
+#pragma unroll
+        for (int q = 0; q < kSLU; ++q)
+#pragma unroll
+            for (int k = 0; k < kSRows; ++k) x[k] -= val[q][k] * c[q];
+    }
+}
+
+// dp[l] = sum over the tile of y[k] X_l[row k] (l < r; y zero outside the
+// block), per column: rows in k order per thread, a wave sum, the waves in
+// order; kSLU columns' loads in flight at once
+template <typename T>
+__device__ __forceinline__ void tile_products(const T* __restrict__ X, int64_t ld, int r,
+                                              const int (&ic)[kSRows], const T (&y)[kSRows],
+                                              double (*shp)[kSDot], double* dp) {
+    r = __builtin_amdgcn_readfirstlane(r);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int c0 = 0; c0 < r; c0 += kSDot) {
+        const int nk = r - c0 < kSDot ? r - c0 : kSDot;
+        double acc[kSDot];
+#pragma unroll
+        for (int q = 0; q < kSDot; ++q) acc[q] = 0.0;
+#pragma unroll
+        for (int h = 0; h < kSDot; h += kSLU) {
+            T val[kSLU][kSRows];
+#pragma unroll
+            for (int q = 0; q < kSLU; ++q) {
+                const int l = c0 + h + q < r ? c0 + h + q : r - 1;
+                const T* __restrict__ Xl = X + (int64_t)l * ld;
+#pragma unroll
+                for (int k = 0; k < kSRows; ++k) val[q][k] = Xl[ic[k]];
+            }
+#pragma unroll
+            for (int q = 0; q < kSLU; ++q)
+#pragma unroll
+                for (int k = 0; k < kSRows; ++k) acc[h + q] += (double)y[k] * (double)val[q][k];
+        }
+#pragma unroll
+        for (int q = 0; q < kSDot; ++q) acc[q] = wave_sum(acc[q]);
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < kSDot; ++q) shp[w][q] = acc[q];
+        __syncthreads();
+        if ((int)threadIdx.x < nk) {
+            double t = shp[0][threadIdx.x];
+            for (int q = 1; q < kST / 64; ++q) t += shp[q][threadIdx.x];
+            dp[c0 + threadIdx.x] = t;
+        }
+        __syncthreads();
+    }
 }
 
 // per-block state of the step loop
@@ -236,31 +327,22 @@ __global__ __launch_bounds__(kST) void split_col_kernel(SplitArgs a, KernelEval<
     load_pt(soa, a.n, a.d, (int64_t)bl.z + j, yj);
     Arg<T> am{(T)-1, INT_MAX, (T)0};
     double colmax = 0.0;
-    const int i0 = tl.y * kTile + threadIdx.x;
-    T v[kSRows];
+    int ic[kSRows];
+    bool ok[kSRows];
+    tile_rows(tl.y * kTile + threadIdx.x, m, ic, ok);
+    T xi[kSRows][3], v[kSRows];
+    load_pts(soa, a.n, a.d, (int64_t)bl.x, ic, xi);
 #pragma unroll
     for (int k = 0; k < kSRows; ++k) {
-        const int i = i0 + k * kST;
-        v[k] = 0;
-        if (i < m) {
-            T xi[3];
-            load_pt(soa, a.n, a.d, (int64_t)bl.x + i, xi);
-            v[k] = phi(K, xi, yj, a.d);
-            const double aa0 = v[k] < (T)0 ? -(double)v[k] : (double)v[k];
-            colmax = aa0 > colmax ? aa0 : colmax;
-        }
+        v[k] = ok[k] ? phi(K, xi[k], yj, a.d) : (T)0;
+        const double aa0 = v[k] < (T)0 ? -(double)v[k] : (double)v[k];
+        colmax = aa0 > colmax ? aa0 : colmax;
     }
-    for (int l = 0; l < r; ++l) {
-        const T vl = vec[l];
-        const T* __restrict__ Ul = Uread + (int64_t)l * m;
-#pragma unroll
-        for (int k = 0; k < kSRows; ++k)
-            if (i0 + k * kST < m) v[k] -= Ul[i0 + k * kST] * vl;
-    }
+    tile_subtract(Uread, m, r, vec, ic, v);
 #pragma unroll
     for (int k = 0; k < kSRows; ++k) {
-        const int i = i0 + k * kST;
-        if (i < m) {
+        if (ok[k]) {
+            const int i = ic[k];
             U[(int64_t)r * m + i] = v[k];
             const T aa = v[k] < (T)0 ? -v[k] : v[k];
             if (!bit_get(rmask, i) && aa > am.best) {
@@ -371,50 +453,27 @@ __global__ __launch_bounds__(kST) void split_norm_kernel(SplitArgs a, const int2
     T* __restrict__ U = (T*)a.U + (a.uoff[tl.x] - a.ubase);
     const int r = s.r;
     const T piv = urow[(int64_t)tl.x * (kMaxRankCap + 1) + kMaxRankCap];
-    const int i0 = tl.y * kTile + threadIdx.x;
     double* dp = dpart + (int64_t)blockIdx.x * (kMaxRankCap + 1);
+    int ic[kSRows];
+    bool ok[kSRows];
+    tile_rows(tl.y * kTile + threadIdx.x, m, ic, ok);
     T u[kSRows];
+#pragma unroll
+    for (int k = 0; k < kSRows; ++k) u[k] = U[(int64_t)r * m + ic[k]];
     double nu2 = 0.0;
 #pragma unroll
     for (int k = 0; k < kSRows; ++k) {
-        const int i = i0 + k * kST;
-        u[k] = 0;
-        if (i < m) {
-            u[k] = U[(int64_t)r * m + i] / piv;
-            U[(int64_t)r * m + i] = u[k];
+        if (ok[k]) {
+            u[k] = u[k] / piv;
+            U[(int64_t)r * m + ic[k]] = u[k];
             nu2 += (double)u[k] * (double)u[k];
+        } else {
+            u[k] = (T)0;
         }
     }
     nu2 = wg_sum(nu2, shd);
     if (threadIdx.x == 0) dp[kMaxRankCap] = nu2;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int c0 = 0; c0 < r; c0 += kSDot) {
-        const int nk = r - c0 < kSDot ? r - c0 : kSDot;
-        double acc[kSDot];
-#pragma unroll
-        for (int q = 0; q < kSDot; ++q) acc[q] = 0.0;
-#pragma unroll
-        for (int k = 0; k < kSRows; ++k) {
-            const int i = i0 + k * kST;
-            if (i < m) {
-#pragma unroll
-                for (int q = 0; q < kSDot; ++q)
-                    if (q < nk) acc[q] += (double)u[k] * (double)U[(int64_t)(c0 + q) * m + i];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < kSDot; ++q) acc[q] = wave_sum(acc[q]);
-        if (lane == 0)
-#pragma unroll
-            for (int q = 0; q < kSDot; ++q) shp[w][q] = acc[q];
-        __syncthreads();
-        if ((int)threadIdx.x < nk) {
-            double t = shp[0][threadIdx.x];
-            for (int q = 1; q < kST / 64; ++q) t += shp[q][threadIdx.x];
-            dp[c0 + threadIdx.x] = t;
-        }
-        __syncthreads();
-    }
+    tile_products(U, m, r, ic, u, shp, dp);
 }
 
 // residual row i_r on one column tile: V[:, r], partial argmax over unused
@@ -446,31 +505,20 @@ __global__ __launch_bounds__(kST) void split_row_kernel(SplitArgs a, KernelEval<
     const uint32_t* cmask = masks + moff[tl.x] + (m + 31) / 32;
     T xp[3];
     load_pt(soa, a.n, a.d, (int64_t)bl.x + s.ip, xp);
-    const int q0 = tl.y * kTile + threadIdx.x;
-    T v[kSRows];
+    int ic[kSRows];
+    bool ok[kSRows];
+    tile_rows(tl.y * kTile + threadIdx.x, nc, ic, ok);
+    T yq[kSRows][3], v[kSRows];
+    load_pts(soa, a.n, a.d, (int64_t)bl.z, ic, yq);
 #pragma unroll
-    for (int k = 0; k < kSRows; ++k) {
-        const int q = q0 + k * kST;
-        v[k] = 0;
-        if (q < nc) {
-            T yq[3];
-            load_pt(soa, a.n, a.d, (int64_t)bl.z + q, yq);
-            v[k] = phi(K, xp, yq, a.d);
-        }
-    }
-    for (int l = 0; l < r; ++l) {
-        const T ul = vec[l];
-        const T* __restrict__ Vl = Vread + (int64_t)l * nc;
-#pragma unroll
-        for (int k = 0; k < kSRows; ++k)
-            if (q0 + k * kST < nc) v[k] -= ul * Vl[q0 + k * kST];
-    }
+    for (int k = 0; k < kSRows; ++k) v[k] = ok[k] ? phi(K, xp, yq[k], a.d) : (T)0;
+    tile_subtract(Vread, nc, r, vec, ic, v);
     Arg<T> cm{(T)-1, INT_MAX, (T)0};
     double nv2 = 0.0;
 #pragma unroll
     for (int k = 0; k < kSRows; ++k) {
-        const int q = q0 + k * kST;
-        if (q < nc) {
+        if (ok[k]) {
+            const int q = ic[k];
             V[(int64_t)r * nc + q] = v[k];
             nv2 += (double)v[k] * (double)v[k];
             const T aa = v[k] < (T)0 ? -v[k] : v[k];
@@ -479,40 +527,15 @@ __global__ __launch_bounds__(kST) void split_row_kernel(SplitArgs a, KernelEval<
                 cm.idx = q;
                 cm.val = v[k];
             }
+        } else {
+            v[k] = (T)0;
         }
     }
     cm = wg_argmax(cm, sha);
     nv2 = wg_sum(nv2, shd);
     if (threadIdx.x == 0) part[blockIdx.x] = RowPart<T>{cm.best, cm.val, cm.idx, nv2};
     double* dp = dpart + (int64_t)blockIdx.x * (kMaxRankCap + 1);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int c0 = 0; c0 < r; c0 += kSDot) {
-        const int nk = r - c0 < kSDot ? r - c0 : kSDot;
-        double acc[kSDot];
-#pragma unroll
-        for (int q = 0; q < kSDot; ++q) acc[q] = 0.0;
-#pragma unroll
-        for (int k = 0; k < kSRows; ++k) {
-            const int q = q0 + k * kST;
-            if (q < nc) {
-#pragma unroll
-                for (int e = 0; e < kSDot; ++e)
-                    if (e < nk) acc[e] += (double)v[k] * (double)Vread[(int64_t)(c0 + e) * nc + q];
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < kSDot; ++e) acc[e] = wave_sum(acc[e]);
-        if (lane == 0)
-#pragma unroll
-            for (int e = 0; e < kSDot; ++e) shp[w][e] = acc[e];
-        __syncthreads();
-        if ((int)threadIdx.x < nk) {
-            double t = shp[0][threadIdx.x];
-            for (int q = 1; q < kST / 64; ++q) t += shp[q][threadIdx.x];
-            dp[c0 + threadIdx.x] = t;
-        }
-        __syncthreads();
-    }
+    tile_products(Vread, nc, r, ic, v, shp, dp);
 }
 
 // the norm recursion, the stopping test and the next column pivot
