@@ -178,6 +178,7 @@ def n22_aca_builds(torch, H, log):
             r["phase_ms_each"].append(list(st.phase_ms))
             r.update({"build_s": min(r["build_s_each"]), "aca_chunks": st.aca_chunks,
                       "aca_capacity_entries": st.aca_capacity, "aca_fallback": st.aca_fallback,
+                      "aca_overflow": st.aca_overflow,
                       "predict_ms": st.predict_ms, "n_adm": st.n_adm, "n_dense": st.n_dense,
                       "sum_rank": st.sum_rank})
             r["aca_ms"] = min(ph[3] for ph in r["phase_ms_each"])
@@ -333,7 +334,7 @@ def main():
             "build_phase_ms": list(st.phase_ms),
             "predict_ms": st.predict_ms,
             "aca_chunks": st.aca_chunks, "aca_capacity_entries": st.aca_capacity,
-            "aca_fallback": st.aca_fallback,
+            "aca_fallback": st.aca_fallback, "aca_overflow": st.aca_overflow,
             "n_adm": st.n_adm, "n_dense": st.n_dense, "sum_rank": st.sum_rank,
             "max_rank": st.max_rank_used, "near_entries": st.near_entries,
             "factor_entries": st.factor_entries, "matvec_bytes": st.matvec_bytes,

@@ -179,10 +179,14 @@ typedef struct {
     int64_t device_bytes;     /* device memory held by the handle */
     int64_t level_sizes[64];  /* |V(l)| per level */
     int64_t aca_fallback;     /* HMX_RANK_LEARNED: blocks left unfinished by
-                                 their target and approximated again */
+                                 their target that did not fit the overflow
+                                 reserve, approximated again in a second pass */
     int64_t aca_capacity;     /* entries of ACA storage reserved: sum over the
                                  blocks of (target or max_rank) * (m + n) */
     double predict_ms;        /* HMX_RANK_LEARNED: rank prediction time */
+    int64_t aca_overflow;     /* HMX_RANK_LEARNED: blocks that outgrew their
+                                 target and continued, in the same launch, in
+                                 overflow storage for max_rank columns */
 } hmx_stats;
 
 /* Fill *p with the defaults: leaf 256, eta 1.5, eps 1e-5, aca_eta 0,

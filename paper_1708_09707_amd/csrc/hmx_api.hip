@@ -870,12 +870,26 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                 max_u = std::max(max_u, hcu[k + 1] - hcu[k]);
                 max_v = std::max(max_v, hcv[k + 1] - hcv[k]);
             }
-            alloc(Ucap, (size_t)std::max<int64_t>(max_u, 1) * esz, "U chunk scratch");
-            alloc(Vcap, (size_t)std::max<int64_t>(max_v, 1) * esz, "V chunk scratch");
+            // a pass with storage for the targets only keeps a reserve behind
+            // the chunk's capacity, where blocks that need more columns
+            // continue (those it cannot hold are approximated again later)
+            const int64_t ovf_cap =
+                cap_only ? std::max<int64_t>(std::max(max_u, max_v) / 16, 2 * kSplitRows * kmax) : 0;
+            alloc(Ucap, (size_t)std::max<int64_t>(max_u + ovf_cap, 1) * esz, "U chunk scratch");
+            alloc(Vcap, (size_t)std::max<int64_t>(max_v + ovf_cap, 1) * esz, "V chunk scratch");
+            DevBuf ovf_used, moved;
+            if (cap_only) {
+                alloc(ovf_used, 8, "overflow counter");
+                alloc(moved, (size_t)nb * 8, "overflow offsets");
+                check(hipMemsetAsync(moved.p, 0xff, (size_t)nb * 8, st), "overflow offsets");
+            }
             a.U = Ucap.p;
             a.V = Vcap.p;
             a.one_shot = one_shot;
             a.cap_only = cap_only;
+            a.ovf_used = cap_only ? ovf_used.as<unsigned long long>() : nullptr;
+            a.ovf_cap = ovf_cap;
+            a.ovf_moved = cap_only ? moved.as<int64_t>() : nullptr;
             for (int k = 0; k < nch; ++k) {
                 const int64_t b0 = hb[k], nbk = hb[k + 1] - hb[k];
                 if (nbk == 0) continue;
@@ -893,12 +907,22 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                 a.nmed = std::max<int64_t>(0, std::min(nmed_all - b0, nbk));
                 a.rank = rank + b0;
                 a.steps = steps + b0;
+                a.ovf_u0 = hcu[k] + max_u;
+                a.ovf_v0 = hcv[k] + max_v;
+                a.ovf_moved = cap_only ? moved.as<int64_t>() + b0 : nullptr;
+                if (a.ovf_used)
+                    check(hipMemsetAsync(a.ovf_used, 0, sizeof(unsigned long long), st),
+                          "overflow counter");
                 SplitBuffers sb;
                 if (a.nsplit > 0) prepare_split(h, a, f64, st, sb);
                 check(aca_classes_begin(a, f64, st, have_aux ? aux : nullptr), "aca");
                 if (a.nsplit > 0)
                     check(launch_aca_split(a, sb.P, f64, st), "aca (many workgroups per block)");
                 check(aca_classes_join(st, have_aux ? aux : nullptr), "aca join");
+                if (a.ovf_moved)
+                    check(launch_apply_moved(a.ovf_moved, nbk, a.ovf_u0, a.ovf_v0,
+                                             cu.as<int64_t>() + b0, cv.as<int64_t>() + b0, st),
+                          "overflow offsets");
                 check(hipStreamSynchronize(st), "aca sync");  // before sb returns to the cache
                 aca_ms += ms_since(ta);
                 if (aca_only) continue;
@@ -941,6 +965,9 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                  h->voff.as<int64_t>());
             DevBuf flag;
             alloc(flag, (h->n_adm + 1) * 8, "fallback flags");
+            check(launch_over_flags(h->rank.as<int32_t>(), rt, h->n_adm, flag.as<int64_t>(), st),
+                  "overflow flags");
+            S.aca_overflow = scan(flag.as<int64_t>(), h->n_adm);
             check(launch_fail_flags(h->rank.as<int32_t>(), h->n_adm, flag.as<int64_t>(), st),
                   "fallback flags");
             const int64_t nfb = scan(flag.as<int64_t>(), h->n_adm);

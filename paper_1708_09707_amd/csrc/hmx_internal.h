@@ -63,6 +63,31 @@ __device__ __forceinline__ T phi(const KernelEval<T>& K, const T* x, const T* y,
     }
 }
 
+// phi for a fixed kernel kind, coordinates padded to three with zeros (the
+// padding adds exact zeros, so the value equals phi's)
+template <int KIND, typename T>
+__device__ __forceinline__ T phi_kind(const KernelEval<T>& K, const T* x, const T* y) {
+    T r2 = 0, dot = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        T t = x[k] - y[k];
+        r2 += t * t;
+        if constexpr (KIND == HMX_TEST_LOWRANK) dot += x[k] * y[k];
+    }
+    if constexpr (KIND == HMX_GAUSSIAN) {
+        return kexp(-r2 * K.inv_p0);
+    } else if constexpr (KIND == HMX_MATERN32) {
+        T s = ksqrt(r2) * K.s3_inv;
+        return ((T)1 + s) * kexp(-s);
+    } else if constexpr (KIND == HMX_TEST_CONST) {
+        (void)r2;
+        return (T)1;
+    } else {
+        T u = (T)1 + dot;
+        return u * u;
+    }
+}
+
 // load point i of a d x n SoA array
 template <typename T>
 __device__ __forceinline__ void load_pt(const T* __restrict__ soa, int64_t n, int d, int64_t i,
@@ -155,6 +180,15 @@ struct AcaArgs {
     const int32_t* rtarget;  // per-block target ranks, or null (adaptive)
     int one_shot;            // targets are run without the test, then judged by it
     int cap_only;            // storage holds only the target: unfinished blocks get rank -1
+    // with cap_only, a block that reaches its target unfinished takes k_max
+    // columns of overflow storage (one request on *ovf_used, in entries of
+    // both U and V) and continues; ovf_moved[b] (preset to -1) receives the
+    // offset granted, and launch_apply_moved moves the block's uoff / voff
+    // there.  Overflow regions: uoff ovf_u0 / voff ovf_v0 onwards, ovf_cap
+    // entries each.  ovf_used null: no overflow (rank -1 instead).
+    unsigned long long* ovf_used;
+    int64_t ovf_cap, ovf_u0, ovf_v0;
+    int64_t* ovf_moved;
     void* U;
     void* V;
     int32_t* rank;
@@ -168,6 +202,8 @@ struct AcaArgs {
 };
 // queue the single-workgroup classes on aux[0..2] (3 streams, or null: all on
 // st) after the work queued on st; join makes st wait for them
+hipError_t launch_apply_moved(const int64_t* moved, int64_t nb, int64_t u0, int64_t v0,
+                              int64_t* uoff, int64_t* voff, hipStream_t st);
 hipError_t aca_classes_begin(const AcaArgs& a, int f64, hipStream_t st, const hipStream_t* aux);
 hipError_t aca_classes_join(hipStream_t st, const hipStream_t* aux);
 
@@ -316,6 +352,9 @@ hipError_t launch_rank_predict(const int4* blocks, const int2* ids, int64_t nb, 
 // fallback lists: flag[b] = rank[b] < 0 (int64, scanned by the caller into
 // positions pos), then the flagged blocks gathered in order
 hipError_t launch_fail_flags(const int32_t* rank, int64_t nb, int64_t* flag, hipStream_t st);
+// flag[b] = 1 where rank[b] > rt[b] > 0 (the block outgrew its target)
+hipError_t launch_over_flags(const int32_t* rank, const int32_t* rt, int64_t nb, int64_t* flag,
+                             hipStream_t st);
 hipError_t launch_gather_failed(const int32_t* rank, const int64_t* pos, int64_t nb,
                                 const int4* blocks, const int32_t* level, const int32_t* rt,
                                 int32_t* list, int4* blocks_out, int32_t* level_out,

@@ -180,6 +180,15 @@ struct AcaShared {
     int imin[NW];
     double dkey[NW];
     int dkidx[NW];
+    long long ovf;  // overflow offset granted to the block, or -1
+    long long uo, vo;  // the block's current storage offsets (moved by an overflow)
+};
+
+// overflow storage of the learned sizing pass (see AcaArgs)
+struct Overflow {
+    unsigned long long* used;
+    int64_t cap, u0, v0;
+    int64_t* moved;  // per block of the launch: the offset granted, else left as is
 };
 
 template <typename T, int NW>
@@ -512,13 +521,48 @@ __device__ void column_products_waved(const T* __restrict__ X, int len, int p,
     __syncthreads();
 }
 
+// a value known to be the same on every lane, in scalar registers
+__device__ __forceinline__ long long uniform_i64(long long v) {
+    const unsigned long long u = (unsigned long long)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// A block of the learned sizing pass that reached its target unfinished:
+// request R columns of overflow storage (one atomic, by thread 0), copy the
+// r columns computed so far and return the offset granted (the same on every
+// thread), or -1 when the reserve is exhausted.  Kept out of line: the step
+// loop's code stays compact.
+template <typename T, int NT>
+__device__ __noinline__ long long aca_overflow_move(const Overflow& ovf, int m, int nc, int R, int r,
+                                                    const T* __restrict__ U,
+                                                    const T* __restrict__ V,
+                                                    T* __restrict__ Upool, T* __restrict__ Vpool,
+                                                    int64_t ubase, int64_t vbase, long long* slot) {
+    if (threadIdx.x == 0) {
+        const unsigned long long need = (unsigned long long)(m > nc ? m : nc) * (unsigned long long)R;
+        const unsigned long long old = atomicAdd(ovf.used, need);
+        *slot = old + need <= (unsigned long long)ovf.cap ? (long long)old : -1;
+    }
+    __syncthreads();
+    const long long off = *slot;
+    if (off < 0) return -1;
+    T* __restrict__ Un = Upool + (ovf.u0 + off - ubase);
+    T* __restrict__ Vn = Vpool + (ovf.v0 + off - vbase);
+    for (int e = threadIdx.x; e < r * m; e += NT) Un[e] = U[e];
+    for (int e = threadIdx.x; e < r * nc; e += NT) Vn[e] = V[e];
+    __syncthreads();
+    return off;
+}
+
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void aca_kernel(
     const T* __restrict__ soa, const double* __restrict__ soa64, int64_t n, int d, KernelEval<T> K,
     const int4* __restrict__ blocks, int64_t nblocks, const int64_t* __restrict__ uoff,
-    const int64_t* __restrict__ voff, int64_t ubase, int64_t vbase, int kmax, double eps,
-    double aca_eta, T eps0, int fixed, const int32_t* __restrict__ rtarget, int one_shot_mode,
-    int cap_only, int lds_words, T* __restrict__ Upool, T* __restrict__ Vpool,
+    const int64_t* __restrict__ voff, int64_t ubase, int64_t vbase, int kmax, double eps, double aca_eta, T eps0, int fixed,
+    const int32_t* __restrict__ rtarget, int one_shot_mode, int cap_only, Overflow ovf,
+    int lds_words, T* __restrict__ Upool, T* __restrict__ Vpool,
     int32_t* __restrict__ rank_out, int32_t* __restrict__ steps_out) {
     constexpr int NW = NT / kWave;
     constexpr int DC = dot_cols<NT>();
@@ -535,12 +579,14 @@ __global__ __launch_bounds__(NT) void aca_kernel(
         int R = kmax;
         R = m < R ? m : R;
         R = nc < R ? nc : R;
-        T* __restrict__ U = Upool + (uoff[b] - ubase);
-        T* __restrict__ V = Vpool + (voff[b] - vbase);
+        // the block's storage offsets live in LDS and are read at every step
+        // (they move once if the block outgrows its target into overflow
+        // storage; a loop-carried pointer would cost the loop its hoisting)
+        if (tid == 0) {
+            sh.uo = uoff[b] - ubase;
+            sh.vo = voff[b] - vbase;
+        }
         const BufView<T> rows_pts(soa + bl.x), cols_pts(soa + bl.z);
-        // columns l < r are only read in a step, column r only written
-        const T* __restrict__ Uread = U;
-        const T* __restrict__ Vread = V;
         const int mw = (m + 31) >> 5, nw = (nc + 31) >> 5;
         const bool single = m <= kRows * NT;  // one pass covers every row
         if (mw + nw > lds_words) {  // outside this launch's size class (never by construction)
@@ -577,7 +623,7 @@ __global__ __launch_bounds__(NT) void aca_kernel(
         double nu2p = 0.0, nv2p = 0.0;
 
         int r = 0, ncols_used = 0, nfailed = 0, steps = 0;
-        int j = first_column<T, NT>(soa64, n, d, bl, sh);
+        int j = first_column<T, NT>(soa64, n, d, bl, sh);  // (its barriers publish sh.uo, sh.vo)
         double S2 = 0.0;
         for (;;) {
             if (r >= target) {
@@ -589,8 +635,8 @@ __global__ __launch_bounds__(NT) void aca_kernel(
                 if (pending) {
                     // no room for a speculative term: term r - 1's products now,
                     // summed in the order of the deferred accumulation
-                    column_products_waved<T, NT>(Uread, m, r - 1, accu);
-                    column_products_waved<T, NT>(Vread, nc, r - 1, accv);
+                    column_products_waved<T, NT>(Upool + uniform_i64(sh.uo), m, r - 1, accu);
+                    column_products_waved<T, NT>(Vpool + uniform_i64(sh.vo), nc, r - 1, accv);
                     double cross = 0.0;
                     for (int l = 0; l < r - 1; ++l) {
                         double gu = accu[0][l], gv = accv[0][l];
@@ -607,11 +653,32 @@ __global__ __launch_bounds__(NT) void aca_kernel(
                     if (sqrt(last_p) <= tol * sqrt(S2)) break;
                 }
                 if (cap_only) {
-                    refused = true;
-                    break;
+                    // storage for the target only: continue in overflow
+                    // storage for R columns if the reserve has room
+                    const long long off = uniform_i64(
+                        ovf.used ? aca_overflow_move<T, NT>(ovf, m, nc, R, r,
+                                                            Upool + uniform_i64(sh.uo),
+                                                            Vpool + uniform_i64(sh.vo), Upool,
+                                                            Vpool, ubase, vbase, &sh.ovf)
+                                 : -1);
+                    if (off < 0) {
+                        refused = true;
+                        break;
+                    }
+                    if (tid == 0) {
+                        sh.uo = ovf.u0 + off - ubase;
+                        sh.vo = ovf.v0 + off - vbase;
+                        ovf.moved[b] = off;
+                    }
+                    __syncthreads();
                 }
                 target = R;
             }
+            // columns l < r are only read in a step, column r only written
+            T* __restrict__ U = Upool + uniform_i64(sh.uo);
+            T* __restrict__ V = Vpool + uniform_i64(sh.vo);
+            const T* __restrict__ Uread = U;
+            const T* __restrict__ Vread = V;
             const int p = r - 1;  // the open term, when pending
             // ---- step 1: residual column j into U[:, r] ----
             for (int l = tid; l < r; l += NT) sh.vec[l] = V[(int64_t)l * nc + j];
@@ -872,8 +939,22 @@ void launch_class(const AcaArgs& a, int64_t b0, int64_t nb, int lds_words, hipSt
                        (size_t)lds_words * sizeof(uint32_t), st, (const T*)a.soa, a.soa64, a.n,
                        a.d, K, a.blocks + b0, nb, a.uoff + b0, a.voff + b0, a.ubase, a.vbase,
                        a.kmax, a.eps, a.aca_eta, (T)a.eps0, a.fixed,
-                       a.rtarget ? a.rtarget + b0 : nullptr, a.one_shot, a.cap_only, lds_words,
-                       (T*)a.U, (T*)a.V, a.rank + b0, a.steps ? a.steps + b0 : nullptr);
+                       a.rtarget ? a.rtarget + b0 : nullptr, a.one_shot, a.cap_only,
+                       Overflow{a.ovf_used, a.ovf_cap, a.ovf_u0, a.ovf_v0,
+                                a.ovf_moved ? a.ovf_moved + b0 : nullptr},
+                       lds_words, (T*)a.U, (T*)a.V, a.rank + b0,
+                       a.steps ? a.steps + b0 : nullptr);
+}
+
+// blocks that continued in overflow storage: their storage offsets move there
+__global__ void apply_moved_kernel(const int64_t* __restrict__ moved, int64_t nb, int64_t u0,
+                                   int64_t v0, int64_t* __restrict__ uoff,
+                                   int64_t* __restrict__ voff) {
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b < nb && moved[b] >= 0) {
+        uoff[b] = u0 + moved[b];
+        voff[b] = v0 + moved[b];
+    }
 }
 
 // first index b with level[b] >= lvl in the non-decreasing level[0..nb)
@@ -908,6 +989,14 @@ hipError_t launch_level_split(const int32_t* level, int64_t nb, int lvl, int64_t
 // where null) after the work already queued on st; aca_classes_join makes
 // st wait for them.  Running the classes concurrently keeps the few large
 // blocks of the upper levels from holding back the many small ones.
+hipError_t launch_apply_moved(const int64_t* moved, int64_t nb, int64_t u0, int64_t v0,
+                              int64_t* uoff, int64_t* voff, hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(apply_moved_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st,
+                       moved, nb, u0, v0, uoff, voff);
+    return hipGetLastError();
+}
+
 hipError_t aca_classes_begin(const AcaArgs& a, int f64, hipStream_t st, const hipStream_t* aux) {
     const int64_t lo = a.nsplit < a.nblocks ? a.nsplit : a.nblocks;
     const int64_t nbig = a.nbig < lo ? lo : (a.nbig < a.nblocks ? a.nbig : a.nblocks);

@@ -279,6 +279,12 @@ __global__ void fail_flags_kernel(const int32_t* __restrict__ rank, int64_t nb,
     if (b < nb) flag[b] = rank[b] < 0 ? 1 : 0;
 }
 
+__global__ void over_flags_kernel(const int32_t* __restrict__ rank, const int32_t* __restrict__ rt,
+                                  int64_t nb, int64_t* __restrict__ flag) {
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b < nb) flag[b] = rt[b] > 0 && rank[b] > rt[b] ? 1 : 0;
+}
+
 __global__ void gather_failed_kernel(const int32_t* __restrict__ rank,
                                      const int64_t* __restrict__ pos, int64_t nb,
                                      const int4* __restrict__ blocks,
@@ -430,6 +436,13 @@ hipError_t launch_rank_predict(const int4* blocks, const int2* ids, int64_t nb, 
 hipError_t launch_fail_flags(const int32_t* rank, int64_t nb, int64_t* flag, hipStream_t st) {
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(fail_flags_kernel, dim3(g1d(nb)), dim3(256), 0, st, rank, nb, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_over_flags(const int32_t* rank, const int32_t* rt, int64_t nb, int64_t* flag,
+                             hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(over_flags_kernel, dim3(g1d(nb)), dim3(256), 0, st, rank, rt, nb, flag);
     return hipGetLastError();
 }
 

@@ -39,11 +39,18 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// the hardware conversion (round to nearest even, NaN stays NaN)
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
+}
+
+// two values in one packed conversion: a in the low half, b in the high half
+__device__ __forceinline__ uint32_t f32x2_to_bf16x2(float a, float b) {
+    const f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
 }
 
 template <typename S, typename T>
@@ -247,45 +254,145 @@ __global__ void tile_meta_kernel(const int64_t* __restrict__ tile_ptr, int64_t n
 // Fill the matrix pool piece by piece: dense pieces evaluate phi (the near
 // field, Section 5.4.2), factor pieces copy the tile's rows of U_b from the
 // ACA capacity pool.  Padding rows are zero.
-template <typename SU, typename SN, typename T>
+// R values of S at an R-aligned element offset, as 16-byte stores
+template <typename S, int R>
+__device__ __forceinline__ void store_unit(S* __restrict__ dst, const S (&v)[R]) {
+    static_assert((R * sizeof(S)) % 16 == 0, "a unit is whole 16-byte vectors");
+    constexpr int kVec = (int)(R * sizeof(S) / 16);
+    u32x4 w[kVec];
+    __builtin_memcpy(w, v, sizeof(w));
+    u32x4* out = reinterpret_cast<u32x4*>(dst);
+#pragma unroll
+    for (int q = 0; q < kVec; ++q) out[q] = w[q];
+}
+
+// R values of T, converted to S, stored as one unit
+template <typename S, typename T, int R>
+struct UnitStore {
+    static __device__ __forceinline__ void put(S* __restrict__ dst, const T (&v)[R]) {
+        S o[R];
+#pragma unroll
+        for (int e = 0; e < R; ++e) o[e] = Store<S, T>::put(v[e]);
+        store_unit<S, R>(dst, o);
+    }
+};
+template <int R>
+struct UnitStore<uint16_t, float, R> {
+    static __device__ __forceinline__ void put(uint16_t* __restrict__ dst, const float (&v)[R]) {
+        static_assert(R % 8 == 0, "BF16 units are whole 16-byte vectors");
+        uint32_t w[R / 2];
+#pragma unroll
+        for (int e = 0; e < R / 2; ++e) w[e] = f32x2_to_bf16x2(v[2 * e], v[2 * e + 1]);
+        u32x4* out = reinterpret_cast<u32x4*>(dst);
+#pragma unroll
+        for (int q = 0; q < R / 8; ++q) out[q] = u32x4{w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
+    }
+};
+
+// the near-field columns c = cstart, cstart + per, ... < ncols of rows
+// i0 .. i0 + R - 1 (coordinates x, zero past the tile's mt rows) for one
+// kernel kind; four columns' coordinates are loaded before they are used
+template <int KIND, typename SN, typename T, int R>
+__device__ __forceinline__ void fill_near(const KernelEval<T>& K, const T* __restrict__ soa, int64_t n,
+                                          int d, int64_t ybase, const T (&x)[R][3], int i0, int mt,
+                                          int cstart, int per, int ncols, int ld,
+                                          SN* __restrict__ dst) {
+    int c = cstart;
+    for (; c + 3 * per < ncols; c += 4 * per) {
+        T y[4][3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) load_pt(soa, n, d, ybase + c + q * per, y[q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            T v[R];
+#pragma unroll
+            for (int e = 0; e < R; ++e) v[e] = i0 + e < mt ? phi_kind<KIND>(K, x[e], y[q]) : (T)0;
+            UnitStore<SN, T, R>::put(dst + (int64_t)(c + q * per) * ld + i0, v);
+        }
+    }
+    for (; c < ncols; c += per) {
+        T y[3];
+        load_pt(soa, n, d, ybase + c, y);
+        T v[R];
+#pragma unroll
+        for (int e = 0; e < R; ++e) v[e] = i0 + e < mt ? phi_kind<KIND>(K, x[e], y) : (T)0;
+        UnitStore<SN, T, R>::put(dst + (int64_t)c * ld + i0, v);
+    }
+}
+
+// the near-field fill specialised on the kernel kind
+template <typename SN, typename T, int R>
+__device__ __forceinline__ void near_dispatch(const KernelEval<T>& K, const T* __restrict__ soa,
+                                              int64_t n, int d, int64_t ybase, const T (&x)[R][3],
+                                              int i0, int mt, int cstart, int per, int ncols,
+                                              int ld, SN* __restrict__ dst) {
+    switch (K.kind) {
+        case HMX_GAUSSIAN:
+            fill_near<HMX_GAUSSIAN, SN, T, R>(K, soa, n, d, ybase, x, i0, mt, cstart, per,
+                                              ncols, ld, dst);
+            break;
+        case HMX_MATERN32:
+            fill_near<HMX_MATERN32, SN, T, R>(K, soa, n, d, ybase, x, i0, mt, cstart, per,
+                                              ncols, ld, dst);
+            break;
+        case HMX_TEST_CONST:
+            fill_near<HMX_TEST_CONST, SN, T, R>(K, soa, n, d, ybase, x, i0, mt, cstart, per,
+                                                ncols, ld, dst);
+            break;
+        default:
+            fill_near<HMX_TEST_LOWRANK, SN, T, R>(K, soa, n, d, ybase, x, i0, mt, cstart, per,
+                                                  ncols, ld, dst);
+            break;
+    }
+}
+
+// One workgroup per piece.  Each thread owns a group of R consecutive rows
+// of the tile (their coordinates stay in registers) and sweeps a set of the
+// piece's columns, writing R entries per column with 16-byte stores; rows
+// past the tile's end are zero.  A factor piece copies rows row0 .. of its U
+// columns, a near-field piece evaluates phi.
+template <typename SU, typename SN, typename T, int R>
 __global__ __launch_bounds__(256) void piece_data_kernel(
     const Piece* __restrict__ pieces, int64_t np, const int32_t* __restrict__ tile_lo,
     const int4* __restrict__ adm, const int4* __restrict__ dense,
     const int64_t* __restrict__ uoff, const SU* __restrict__ Usrc, const T* __restrict__ soa,
-    int64_t n, int d, KernelEval<T> K, int R, SU* __restrict__ upool, SN* __restrict__ npool) {
+    int64_t n, int d, KernelEval<T> K, SU* __restrict__ upool, SN* __restrict__ npool) {
+    const int tid = threadIdx.x;
     for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
         const Piece pc = pieces[p];
         if (is_recompute<SN>::value && pc.blk < 0) continue;  // near field evaluated per product
         const int32_t r0 = tile_lo[pc.tile];
         const int mt = tile_lo[pc.tile + 1] - r0;
         const int ld = tile_ld(mt, R);
-        const int64_t tot = (int64_t)ld * pc.ncols;
+        const int upc = ld / R;  // row groups per column
         const bool is_factor = pc.blk >= 0;
         const int4 bl = is_factor ? adm[pc.blk] : dense[-pc.blk - 1];
         const int m = bl.y - bl.x;
-        const SU* __restrict__ src = is_factor ? Usrc + uoff[pc.blk] + pc.row0 : nullptr;
-        int i = threadIdx.x, c = 0;
-        while (i >= ld) {
-            i -= ld;
-            ++c;
-        }
-        for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+        // thread -> row group g and columns cstart, cstart + per, ...
+        const int per = upc <= 256 ? 256 / upc : 1;
+        for (int gs = 0; gs < upc; gs += 256) {
+            const int g = upc <= 256 ? tid % upc : gs + tid;
+            const int cstart = upc <= 256 ? tid / upc : 0;
+            if (upc <= 256 ? tid >= per * upc : g >= upc) continue;
+            const int i0 = g * R;
             if (is_factor) {
-                upool[pc.d_off + e] = i < mt ? src[(int64_t)c * m + i] : (SU)0;
-            } else if constexpr (!is_recompute<SN>::value) {
-                T v = (T)0;
-                if (i < mt) {
-                    T x[3], y[3];
-                    load_pt(soa, n, d, (int64_t)r0 + i, x);
-                    load_pt(soa, n, d, (int64_t)bl.z + c, y);
-                    v = phi(K, x, y, d);
+                const SU* __restrict__ src = Usrc + uoff[pc.blk] + pc.row0 + i0;
+                for (int c = cstart; c < pc.ncols; c += per) {
+                    SU v[R];
+#pragma unroll
+                    for (int e = 0; e < R; ++e) v[e] = i0 + e < mt ? src[(int64_t)c * m + e] : (SU)0;
+                    store_unit<SU, R>(upool + pc.d_off + (int64_t)c * ld + i0, v);
                 }
-                npool[pc.d_off + e] = Store<SN, T>::put(v);
-            }
-            i += blockDim.x;
-            while (i >= ld) {
-                i -= ld;
-                ++c;
+            } else if constexpr (!is_recompute<SN>::value) {
+                T x[R][3];
+#pragma unroll
+                for (int e = 0; e < R; ++e) {
+                    const int i = i0 + e < mt ? i0 + e : mt - 1;
+                    load_pt(soa, n, d, (int64_t)r0 + i, x[e]);
+                }
+                SN* __restrict__ dst = npool + pc.d_off;
+                near_dispatch<SN, T, R>(K, soa, n, d, bl.z, x, i0, mt, cstart, per, pc.ncols, ld,
+                                        dst);
             }
         }
     }
@@ -329,13 +436,26 @@ __global__ __launch_bounds__(256) void compact_kernel(const int4* __restrict__ b
                                                       const int64_t* __restrict__ eoff,
                                                       const T* __restrict__ src,
                                                       S* __restrict__ dst, int rows) {
+    constexpr int kU = 8;  // elements per thread per pass, loaded before any is stored
     for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
         const int4 bl = blocks[b];
         const int64_t len = rows ? bl.y - bl.x : bl.w - bl.z, r = rank[b];
+        const int64_t tot = r * len;
         const T* sv = src + (coff[b] - cbase);
         S* dv = dst + eoff[b];
-        for (int64_t e = threadIdx.x; e < r * len; e += blockDim.x)
-            dv[e] = Store<S, T>::put(sv[e]);
+        for (int64_t e0 = 0; e0 < tot; e0 += (int64_t)kU * blockDim.x) {
+            T v[kU];
+#pragma unroll
+            for (int k = 0; k < kU; ++k) {
+                const int64_t e = e0 + threadIdx.x + (int64_t)k * blockDim.x;
+                v[k] = sv[e < tot ? e : tot - 1];
+            }
+#pragma unroll
+            for (int k = 0; k < kU; ++k) {
+                const int64_t e = e0 + threadIdx.x + (int64_t)k * blockDim.x;
+                if (e < tot) dv[e] = Store<S, T>::put(v[k]);
+            }
+        }
     }
 }
 
@@ -757,27 +877,29 @@ hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* til
                              void* upool, void* npool, int fmode, int nmode, hipStream_t st) {
     if (np == 0) return hipSuccess;
     const unsigned grid = grid_cap(np, 1 << 20);
-    const int R = rows_per_unit(fmode, nmode);
-#define HMX_PD(SU, SN, T)                                                                     \
-    hipLaunchKernelGGL((piece_data_kernel<SU, SN, T>), dim3(grid), dim3(256), 0, st, pieces, \
-                       np, tile_lo, adm, dense, uoff, (const SU*)Usrc, (const T*)soa, n, d,  \
-                       KernelEval<T>(kern), R, (SU*)upool, (SN*)npool)
-    if (fmode == 0 && nmode == 0)
-        HMX_PD(double, double, double);
-    else if (fmode == 1 && nmode == 1)
-        HMX_PD(float, float, float);
-    else if (fmode == 2 && nmode == 2)
-        HMX_PD(uint16_t, uint16_t, float);
-    else if (fmode == 2 && nmode == 1)
-        HMX_PD(uint16_t, float, float);
-    else if (nmode == 3 && fmode == 0)
-        HMX_PD(double, Recompute<double>, double);
-    else if (nmode == 3 && fmode == 1)
-        HMX_PD(float, Recompute<float>, float);
-    else if (nmode == 3 && fmode == 2)
-        HMX_PD(uint16_t, Recompute<float>, float);
-    else
+// each combination's unit (rows_per_unit) is a template argument
+#define HMX_PD(SU, SN, T, R)                                                                  \
+    if (R != rows_per_unit(fmode, nmode)) return hipErrorInvalidValue;                        \
+    else hipLaunchKernelGGL((piece_data_kernel<SU, SN, T, R>), dim3(grid), dim3(256), 0, st,     \
+                       pieces, np, tile_lo, adm, dense, uoff, (const SU*)Usrc, (const T*)soa, \
+                       n, d, KernelEval<T>(kern), (SU*)upool, (SN*)npool)
+    if (fmode == 0 && nmode == 0) {
+        HMX_PD(double, double, double, 2);
+    } else if (fmode == 1 && nmode == 1) {
+        HMX_PD(float, float, float, 4);
+    } else if (fmode == 2 && nmode == 2) {
+        HMX_PD(uint16_t, uint16_t, float, 8);
+    } else if (fmode == 2 && nmode == 1) {
+        HMX_PD(uint16_t, float, float, 8);
+    } else if (nmode == 3 && fmode == 0) {
+        HMX_PD(double, Recompute<double>, double, 2);
+    } else if (nmode == 3 && fmode == 1) {
+        HMX_PD(float, Recompute<float>, float, 4);
+    } else if (nmode == 3 && fmode == 2) {
+        HMX_PD(uint16_t, Recompute<float>, float, 8);
+    } else {
         return hipErrorInvalidValue;
+    }
 #undef HMX_PD
     return hipGetLastError();
 }
