@@ -260,10 +260,13 @@ hmx_status hmx_graph_destroy(hmx_graph g);
 
 /* ---- autotuner of the matvec's row-tile kernel ---- */
 /* Row-tile configurations: shape c % 5 of (lanes per row group, row vectors
- * per lane) = (16,1), (32,1), (64,1), (64,2), (64,4); c >= 5 adds a
- * persistent grid of 2048 workgroups looping over the tiles.  Configurations
- * sum in different orders, so results may differ in the last bits. */
-#define HMX_TILE_CONFIGS 10
+ * per lane) = (16,1), (32,1), (64,1), (64,2), (64,4); grid c / 5: 0 one
+ * workgroup per tile, 1 a persistent grid of 2048 workgroups looping over the
+ * tiles, 2 one workgroup per row pass of a tile (shapes whose pass covers
+ * fewer rows than a tile split each tile's rows over several workgroups).
+ * Configurations sum in different orders, so results may differ in the last
+ * bits. */
+#define HMX_TILE_CONFIGS 15
 
 /* Time every configuration on this handle (reps row-tile launches each, HIP
  * events on `stream`, on scratch vectors it allocates) and keep the fastest

@@ -300,10 +300,11 @@ hipError_t launch_col_block(const int32_t* rank, const int64_t* toff, int64_t na
 hipError_t launch_far_phase1(const int4* adm, const int32_t* col_block, const int64_t* voff,
                              const int64_t* toff, int64_t ncols_total, const void* V,
                              void* vecpool, int64_t n, int smode, hipStream_t st);
-// config < 0: default tile shape; else shape config % kRowtileShapes with a
-// persistent grid of kPersistentGrid workgroups when config >= kRowtileShapes
+// config < 0: default tile shape; else shape config % kRowtileShapes, grid
+// config / kRowtileShapes: one workgroup per tile, a persistent grid of
+// kPersistentGrid workgroups, or one workgroup per (tile, row pass)
 constexpr int kRowtileShapes = 5;
-constexpr int kRowtileConfigs = 2 * kRowtileShapes;
+constexpr int kRowtileConfigs = 3 * kRowtileShapes;
 constexpr unsigned kPersistentGrid = 2048;
 // nmode 3: near field recomputed from soa (compute type, d x n) with kern
 hipError_t launch_rowtile(int64_t ntiles, const int32_t* tile_lo, const int64_t* meta,

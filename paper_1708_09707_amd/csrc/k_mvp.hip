@@ -557,27 +557,81 @@ __global__ __launch_bounds__(256) void far_phase1_kernel(
     if (lane == 0) vec[n + k] = acc;
 }
 
-// phase 2: one workgroup per row tile.  The tile is a contiguous ld x C
+// phase 2: one workgroup per row tile (or per row pass of a tile, the split
+// grid of the autotuner's third group).  The tile is a contiguous ld x C
 // column-major matrix; column k is weighted by vec[widx[k]].  Weights are
 // gathered into LDS a chunk of kChunk columns at a time, so the streaming
 // loads never wait on an index lookup.  The 4 waves split into
 // G = 4 * (64 / L) column groups of L lanes; lane q of a group owns RV
 // 16-byte vectors of rows (vector v * L + q).  Groups take interleaved
-// columns, kUnroll in flight per lane, with non-temporal loads (every matrix
-// byte is read once per product); the G partial row sets are summed in LDS
-// in a fixed order and the tile is scattered to the original order.
+// columns, kUnroll in flight per lane (raw 16-byte vectors, decoded one
+// column at a time: two waves per SIMD with 16 columns in flight each move
+// more bytes than three with 8; a chunk's last batch is masked), with
+// non-temporal loads (every matrix byte is read once per product); the G
+// partial row sets are summed in LDS in a fixed order and the tile is
+// scattered to the original order.
 constexpr int kTileThreads = 256;
-constexpr int kChunk = 1024;
-constexpr int kUnroll = 8;
+constexpr int kChunk = 2048;
+constexpr int kUnroll = 16;
 constexpr int kEvalUnroll = 4;  // near-field columns evaluated per iteration (recompute mode)
 
-// R consecutive rows of one column as T values (R / (16 / sizeof(S)) loads)
-template <typename S, typename T, int R>
-__device__ __forceinline__ void load_rows(const S* __restrict__ col, int unit, T* out) {
-    constexpr int VS = Dec<S, T>::n;
-    const u32x4* p = (const u32x4*)(col + (int64_t)unit * R);
+
+// sw[j] = vec[wi[j]] for j < cnt: eight indices, then eight weights, in
+// flight per thread at a time (the gather's latency is paid once per eight)
+template <typename T>
+__device__ __forceinline__ void stage_weights(const int64_t* __restrict__ wi, int cnt,
+                                              const T* __restrict__ vec, T* __restrict__ sw) {
+    constexpr int kG = 8;
+    for (int j0 = threadIdx.x; j0 < cnt; j0 += kG * kTileThreads) {
+        int64_t idx[kG];
 #pragma unroll
-    for (int k = 0; k < R / VS; ++k) Dec<S, T>::get(nt_load(p + k), out + k * VS);
+        for (int u = 0; u < kG; ++u) {
+            const int j = j0 + u * kTileThreads;
+            idx[u] = wi[j < cnt ? j : cnt - 1];
+        }
+        T val[kG];
+#pragma unroll
+        for (int u = 0; u < kG; ++u) val[u] = vec[idx[u]];
+#pragma unroll
+        for (int u = 0; u < kG; ++u) {
+            const int j = j0 + u * kTileThreads;
+            if (j < cnt) sw[j] = val[u];
+        }
+    }
+}
+
+// raw 16-byte vectors of kUnroll columns c, c + G, ... of a chunk (b: its
+// first column) for lane unit vi; MASKED: columns at or past cnt read column
+// cnt - 1 (their weight is zero)
+template <typename S, typename T, int R, int G, bool MASKED>
+__device__ __forceinline__ void batch_load(const S* __restrict__ b, int ld, int c, int cnt,
+                                           int vi, u32x4 (&raw)[kUnroll][R / Dec<S, T>::n]) {
+    constexpr int VS = Dec<S, T>::n;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        int cu = c + u * G;
+        if (MASKED) cu = cu < cnt ? cu : cnt - 1;
+        const u32x4* p = (const u32x4*)(b + (int64_t)cu * ld + (int64_t)vi * R);
+#pragma unroll
+        for (int k = 0; k < R / VS; ++k) raw[u][k] = nt_load(p + k);
+    }
+}
+
+// acc += the batch's columns times their weights, decoded one column at a time
+template <typename S, typename T, int R, int G, bool MASKED>
+__device__ __forceinline__ void batch_fma(const u32x4 (&raw)[kUnroll][R / Dec<S, T>::n], int c,
+                                          int cnt, const T* __restrict__ sw, T (&acc)[R]) {
+    constexpr int VS = Dec<S, T>::n;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        const int cu = c + u * G;
+        const T w = (!MASKED || cu < cnt) ? sw[MASKED && cu >= cnt ? cnt - 1 : cu] : (T)0;
+        T a[R];
+#pragma unroll
+        for (int k = 0; k < R / VS; ++k) Dec<S, T>::get(raw[u][k], a + k * VS);
+#pragma unroll
+        for (int e = 0; e < R; ++e) acc[e] += a[e] * w;
+    }
 }
 
 // accumulate nk columns of one pool segment (base: row pass start of the
@@ -589,39 +643,27 @@ __device__ __forceinline__ void rowtile_segment(const S* __restrict__ base, int 
                                                 int g, int q, int nvec, T (&acc)[RV][R]) {
     for (int64_t kc = 0; kc < nk; kc += kChunk) {
         const int cnt = (nk - kc) < kChunk ? (int)(nk - kc) : kChunk;
-        for (int j = threadIdx.x; j < cnt; j += kTileThreads) sw[j] = vec[wi[kc + j]];
+        stage_weights(wi + kc, cnt, vec, sw);
         __syncthreads();
         const S* __restrict__ b = base + kc * ld;
-        int c = g;
-        for (; c + (kUnroll - 1) * G < cnt; c += kUnroll * G) {
-            T w[kUnroll];
+        // kUnroll columns per group in flight; full batches are pipelined (the
+        // next batch's loads are issued before the current one is used, two
+        // register sets in turn); the last batch of the chunk is masked (its
+        // missing columns weigh zero and read a valid column: pool entries are
+        // finite, so they add exact zeros)
+        constexpr int VS = Dec<S, T>::n;
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) w[u] = sw[c + u * G];
-#pragma unroll
-            for (int v = 0; v < RV; ++v) {
-                const int vi = v * L + q;
-                if (vi < nvec) {
-                    T a[kUnroll][R];
-#pragma unroll
-                    for (int u = 0; u < kUnroll; ++u)
-                        load_rows<S, T, R>(b + (int64_t)(c + u * G) * ld, vi, a[u]);
-#pragma unroll
-                    for (int u = 0; u < kUnroll; ++u)
-#pragma unroll
-                        for (int e = 0; e < R; ++e) acc[v][e] += a[u][e] * w[u];
-                }
-            }
-        }
-        for (; c < cnt; c += G) {
-            const T w0 = sw[c];
-#pragma unroll
-            for (int v = 0; v < RV; ++v) {
-                const int vi = v * L + q;
-                if (vi < nvec) {
-                    T a[R];
-                    load_rows<S, T, R>(b + (int64_t)c * ld, vi, a);
-#pragma unroll
-                    for (int e = 0; e < R; ++e) acc[v][e] += a[e] * w0;
+        for (int v = 0; v < RV; ++v) {
+            const int vi = v * L + q;
+            if (vi >= nvec) continue;
+            for (int c = g; c < cnt; c += kUnroll * G) {
+                u32x4 ra[kUnroll][R / VS];
+                if (c + (kUnroll - 1) * G < cnt) {
+                    batch_load<S, T, R, G, false>(b, ld, c, cnt, vi, ra);
+                    batch_fma<S, T, R, G, false>(ra, c, cnt, sw, acc[v]);
+                } else {
+                    batch_load<S, T, R, G, true>(b, ld, c, cnt, vi, ra);
+                    batch_fma<S, T, R, G, true>(ra, c, cnt, sw, acc[v]);
                 }
             }
         }
@@ -703,7 +745,8 @@ __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
     int64_t ntiles, const int32_t* __restrict__ tile_lo, const int64_t* __restrict__ meta,
     const int64_t* __restrict__ widx, const SU* __restrict__ upool, const SN* __restrict__ npool,
     const T* __restrict__ vec, const int32_t* __restrict__ perm, T alpha, T beta, T sigma2,
-    T* __restrict__ z, const T* __restrict__ soa, int64_t n, int d, KernelEval<T> K) {
+    T* __restrict__ z, const T* __restrict__ soa, int64_t n, int d, KernelEval<T> K,
+    int split) {
     constexpr int VU = Dec<SU, T>::n, VN = Dec<SN, T>::n;
     constexpr int R = VU > VN ? VU : VN;  // rows per lane unit
     constexpr int SUB = 64 / L;
@@ -725,7 +768,8 @@ __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
         const int64_t ku = meta[4 * t + 5] - meta[4 * t + 1];  // factor columns of the tile
         const SU* __restrict__ ubase = upool + meta[4 * t + 2];
         const SN* __restrict__ nbase = NR ? npool : npool + meta[4 * t + 3];
-        for (int rb = 0; rb < ld; rb += RPG) {
+        // split: this workgroup's row pass only (blockIdx.y), else all of them
+        for (int rb = split ? (int)blockIdx.y * RPG : 0; rb < ld; rb += split ? ld : RPG) {
             const int nvec = ((ld - rb) < RPG ? (ld - rb) : RPG) / R;  // lane units in this pass
             T acc[RV][R];
 #pragma unroll
@@ -775,7 +819,7 @@ hipError_t rowtile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_
                             int64_t n, int d, KernelFn kern, hipStream_t st) {
     constexpr int VU = Dec<SU, T>::n, VN = Dec<SN, T>::n;
     constexpr int R = VU > VN ? VU : VN;
-    int shape, persistent = 0;
+    int shape, mode = 0;
     if (config < 0) {
         // default: the narrowest shape that covers the largest tile in one pass
         const int need = (max_tile + R - 1) / R;  // lane units per tile column
@@ -785,15 +829,22 @@ hipError_t rowtile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_
         shape = L == 16 ? 0 : (L == 32 ? 1 : (RV == 1 ? 2 : (RV == 2 ? 3 : 4)));
     } else {
         shape = config % kRowtileShapes;
-        persistent = config / kRowtileShapes;
+        mode = config / kRowtileShapes;
     }
-    const unsigned grid = persistent ? (unsigned)(ntiles < kPersistentGrid ? ntiles : kPersistentGrid)
-                                     : grid_cap(ntiles, 1 << 20);
+    static constexpr int kL[kRowtileShapes] = {16, 32, 64, 64, 64};
+    static constexpr int kRV[kRowtileShapes] = {1, 1, 1, 2, 4};
+    const int rpg = kL[shape] * kRV[shape] * R;  // rows per pass
+    const unsigned passes =
+        mode == 2 ? (unsigned)((tile_ld(max_tile, R) + rpg - 1) / rpg) : 1u;
+    const dim3 grid(mode == 1 ? (unsigned)(ntiles < kPersistentGrid ? ntiles : kPersistentGrid)
+                              : grid_cap(ntiles, 1 << 20),
+                    passes);
+    const int split = mode == 2 ? 1 : 0;
 #define HMX_RT(LL, RR)                                                                       \
-    hipLaunchKernelGGL((rowtile_kernel<SU, SN, T, LL, RR>), dim3(grid), dim3(kTileThreads), \
-                       0, st, ntiles, tile_lo, meta, widx, (const SU*)upool,                 \
-                       (const SN*)npool, (const T*)vecpool, perm, (T)alpha, (T)beta,        \
-                       (T)sigma2, (T*)z, (const T*)soa, n, d, KernelEval<T>(kern))
+    hipLaunchKernelGGL((rowtile_kernel<SU, SN, T, LL, RR>), grid, dim3(kTileThreads), 0, st,  \
+                       ntiles, tile_lo, meta, widx, (const SU*)upool, (const SN*)npool,      \
+                       (const T*)vecpool, perm, (T)alpha, (T)beta, (T)sigma2, (T*)z,         \
+                       (const T*)soa, n, d, KernelEval<T>(kern), split)
     switch (shape) {
         case 0: HMX_RT(16, 1); break;
         case 1: HMX_RT(32, 1); break;

@@ -36,7 +36,7 @@ EXPORTS = ["hmx_params_default", "hmx_build", "hmx_matvec", "hmx_cg_solve", "hmx
            "hmx_mlp_forward", "hmx_mlp_loss_grad", "hmx_mlp_adam", "hmx_mlp_train",
            "hmx_block_features", "hmx_build_batched", "hmx_get_batch", "hmx_matvec_graph",
            "hmx_graph_launch", "hmx_graph_destroy", "hmx_autotune", "hmx_set_tile_config"]
-HMX_TILE_CONFIGS = 10
+HMX_TILE_CONFIGS = 15
 
 
 class hmx_kernel(C.Structure):
