@@ -48,6 +48,7 @@ import synth  # noqa: E402
 
 METRIC = "H-build seconds + H-matvec GB/s at N=2^22, learned/mixed vs plain, equal rel err"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+FP32_PEAK = 157.3e12   # MI355X FP32 vector FLOP/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rowtile_traffic.json")
 
 # the forms compared (hmx_params overrides on top of the workload's settings)
@@ -201,6 +202,25 @@ def n22_aca_builds(torch, H, log):
     return res
 
 
+def stream_copy_gbs(torch, dev, mib=4096, reps=5):
+    """Bytes read + written per second of a plain device-to-device copy of
+    mib MiB (torch's copy kernel), the best of reps: the box's measured
+    stream bandwidth beside the HBM specification."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    return 2.0 * (mib << 20) / (best * 1e-3) / 1e9
+
+
 def cpu_baseline(wl, pts, x0, z_gpu_first, perm_gpu):
     """The oracle (FP64, stored mode) on a bounded sample of the workload: all
     leaves whose row cluster meets a contiguous range of Morton-order rows."""
@@ -262,6 +282,8 @@ def main():
     dev = torch.device("cuda:0")
     log("bench: workload %s n=%d d=%d matvecs/step=%d steps=%d warmup=%d" % (
         args.workload, n, d, M, args.steps, args.warmup))
+    copy_gbs = stream_copy_gbs(torch, dev)
+    log("bench: device copy %.0f GB/s (read + write)" % copy_gbs)
     pts = synth.uniform_points(n, d, wl["pts_seed"], dtype=np.float32)
     nvec = min(M, 100)
     xs = [synth.normal_vector(n, wl["x_seed"] + k, dtype=np.float32) for k in range(nvec)]
@@ -329,11 +351,25 @@ def main():
         torch.cuda.synchronize()
         err = (torch.linalg.norm(z0.double()[rows_d] - ref) / torch.linalg.norm(ref)).item()
         st = recs[-1]["stats"]
-        mv_ms = float(np.mean([r["mv_ms"] for r in recs]))
+        eager_ms = float(np.mean([r["mv_ms"] for r in recs]))
+        # the matvec time: M replays of a captured one-matvec HIP graph
+        zg = torch.empty(n, dtype=torch.float32, device=dev)
+        g = H.hmx_matvec_graph(h, xs_d[0], zg)
+        H.hmx_graph_launch(g, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(M):
+            H.hmx_graph_launch(g, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        mv_ms = e0.elapsed_time(e1) / M
+        assert torch.equal(zg, z0), "graph replay differs from the eager matvec"
+        H.hmx_graph_destroy(g)
         res = {
             "build_s": float(np.mean([r["build_s"] for r in recs])),
             "build_s_min": float(np.min([r["build_s"] for r in recs])),
             "matvec_ms": mv_ms,
+            "matvec_eager_ms": eager_ms,
             "matvec_gbs": st.matvec_bytes / (mv_ms * 1e-3) / 1e9,
             "rel_err_256rows": err,
             "rowtile_ms": float(np.mean([r["phase_ms"][2] for r in recs])),
@@ -349,6 +385,13 @@ def main():
             "step_ms": 1e3 * float(np.mean([r["step_s"] for r in recs])),
             "rowtile_bytes": rowtile_bytes(st),
             "tile_config": tile_config[label],
+            # the ACA (phase 3) and the tile-major pool phase (5, the near-field
+            # evaluation and the factor rows) as work rates
+            "aca_kernel_evals": st.aca_kernel_evals,
+            "aca_evals_per_s": st.aca_kernel_evals / (st.phase_ms[3] * 1e-3),
+            "aca_flops_per_s": st.aca_flops / (st.phase_ms[3] * 1e-3),
+            "aca_flops_frac_fp32_peak": st.aca_flops / (st.phase_ms[3] * 1e-3) / FP32_PEAK,
+            "near_evals_per_s": st.near_entries / (st.phase_ms[5] * 1e-3),
         }
         log("bench: %s build %.3f s, matvec %.3f ms (%.0f GB/s), rel err %.2e" % (
             label, res["build_s"], mv_ms, res["matvec_gbs"], err))
@@ -412,7 +455,7 @@ def main():
         "roofline": {"kernel": "rowtile_kernel", "bound": "hbm", "achieved": rt_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": rt_gbs / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_launch": lm["rowtile_bytes"],
-                     "avg_launch_ms": lm["rowtile_ms"]},
+                     "avg_launch_ms": lm["rowtile_ms"], "stream_copy_gbs": copy_gbs},
     }
     if args.calibrate_copy > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give

@@ -187,6 +187,11 @@ typedef struct {
     int64_t aca_overflow;     /* HMX_RANK_LEARNED: blocks that outgrew their
                                  target and continued, in the same launch, in
                                  overflow storage for max_rank columns */
+    int64_t aca_kernel_evals; /* ACA kernel evaluations: sum over admissible
+                                 blocks of steps m + rank n */
+    double aca_flops;         /* ACA multiply-add flops: sum of
+                                 2 rank (rank - 1) (m + n) (residual updates
+                                 and the norm recursion's inner products) */
 } hmx_stats;
 
 /* Fill *p with the defaults: leaf 256, eta 1.5, eps 1e-5, aca_eta 0,

@@ -1014,16 +1014,21 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
         S.phase_ms[3] = aca_ms;
         // rank statistics, reduced on the device
         DevBuf red;
-        alloc(red, 4 * sizeof(unsigned long long), "stats");
+        alloc(red, 6 * sizeof(unsigned long long), "stats");
         unsigned long long* rd = red.as<unsigned long long>();
         check(launch_int_stats(h->rank.as<int32_t>(), h->n_adm, rd, st), "rank stats");
         check(launch_int_stats(h->steps.as<int32_t>(), h->n_adm, rd + 2, st), "step stats");
-        unsigned long long hv[4];
+        check(launch_aca_work(h->adm.as<int4>(), h->rank.as<int32_t>(), h->steps.as<int32_t>(),
+                              h->n_adm, rd + 4, st),
+              "aca work");
+        unsigned long long hv[6];
         check(hipMemcpyAsync(hv, rd, sizeof hv, hipMemcpyDeviceToHost, st), "stats readback");
         check(hipStreamSynchronize(st), "stats sync");
         S.max_rank_used = (int32_t)hv[0];
         S.sum_rank = (int64_t)hv[1];
         S.aca_columns = (int64_t)hv[3];
+        S.aca_kernel_evals = (int64_t)hv[4];
+        S.aca_flops = (double)hv[5];
     }
     if (!h->V.p) alloc(h->V, 16, "V pool");
     if (!Uex.p) alloc(Uex, 16, "U pool");

@@ -293,6 +293,10 @@ hipError_t launch_compact_u(const int4* blocks, int64_t nblocks, const int32_t* 
 hipError_t launch_chunk_bounds(const int64_t* cap_off, int64_t nb, int64_t step, int nchunks,
                                int64_t* bnd, hipStream_t st);
 // out[0] = max and out[1] = sum of n non-negative int32 values (device)
+// out[0] = sum over blocks of steps m + rank n (ACA kernel evaluations),
+// out[1] = sum of 2 rank (rank - 1) (m + n) (update and inner-product flops)
+hipError_t launch_aca_work(const int4* blocks, const int32_t* rank, const int32_t* steps,
+                           int64_t nb, unsigned long long* out, hipStream_t st);
 hipError_t launch_int_stats(const int32_t* a, int64_t n, unsigned long long* out,
                             hipStream_t st);
 hipError_t launch_col_block(const int32_t* rank, const int64_t* toff, int64_t nadm,

@@ -1040,4 +1040,43 @@ hipError_t aca_classes_join(hipStream_t st, const hipStream_t* aux) {
     return e;
 }
 
+namespace {
+// out[0] += steps_b m_b + rank_b n_b (kernel evaluations: a column per step,
+// a row per accepted step), out[1] += 2 rank_b (rank_b - 1) (m_b + n_b)
+// (multiply-adds of the residual updates and of the norm recursion's inner
+// products); integer atomics, order-free
+__global__ void aca_work_kernel(const int4* __restrict__ blocks, const int32_t* __restrict__ rank,
+                                const int32_t* __restrict__ steps, int64_t nb,
+                                unsigned long long* __restrict__ out) {
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    unsigned long long ev = 0, fl = 0;
+    if (b < nb) {
+        const int4 bl = blocks[b];
+        const unsigned long long m = bl.y - bl.x, nc = bl.w - bl.z;
+        const unsigned long long r = rank[b] > 0 ? rank[b] : 0, s = steps[b] > 0 ? steps[b] : 0;
+        ev = s * m + r * nc;
+        fl = r > 0 ? 2ull * r * (r - 1) * (m + nc) : 0;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        ev += __shfl_xor(ev, o, 64);
+        fl += __shfl_xor(fl, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&out[0], ev);
+        atomicAdd(&out[1], fl);
+    }
+}
+}  // namespace
+
+hipError_t launch_aca_work(const int4* blocks, const int32_t* rank, const int32_t* steps,
+                           int64_t nb, unsigned long long* out, hipStream_t st) {
+    hipError_t e = hipMemsetAsync(out, 0, 2 * sizeof(unsigned long long), st);
+    if (e != hipSuccess || nb == 0) return e;
+    hipLaunchKernelGGL(aca_work_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st,
+                       blocks, rank, steps, nb, out);
+    return hipGetLastError();
+}
+
+
 }  // namespace hmx

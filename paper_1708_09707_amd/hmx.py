@@ -66,7 +66,8 @@ class hmx_stats(C.Structure):
                 ("phase_ms", C.c_double * 8),
                 ("device_bytes", C.c_int64), ("level_sizes", C.c_int64 * 64),
                 ("aca_fallback", C.c_int64), ("aca_capacity", C.c_int64),
-                ("predict_ms", C.c_double), ("aca_overflow", C.c_int64)]
+                ("predict_ms", C.c_double), ("aca_overflow", C.c_int64),
+                ("aca_kernel_evals", C.c_int64), ("aca_flops", C.c_double)]
 
 
 class HmxError(RuntimeError):
