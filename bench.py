@@ -202,6 +202,96 @@ def n22_aca_builds(torch, H, log):
     return res
 
 
+def batched_problems(torch, lo, hi, nprob=64):
+    """nprob problems: N_p = round(2^U(lo, hi)), d_p in {2, 3}, points uniform,
+    Gaussian p0 log-uniform in [0.005, 0.05] (seeds 41, 42, 4100 + p)."""
+    g = synth.rng(41)
+    ns = np.round(2.0 ** (lo + (hi - lo) * g.random(nprob))).astype(int)
+    ds = g.integers(2, 4, nprob)
+    p0s = synth.log_uniform(0.005, 0.05, nprob, 42)
+    pts = [torch.from_numpy(synth.uniform_points(int(ns[q]), int(ds[q]), 4100 + q,
+                                                 dtype=np.float32)).cuda() for q in range(nprob)]
+    return ns, ds, p0s, pts
+
+
+def batched_leg(torch, H, log, M=20):
+    """64 independent problems as one block-diagonal handle against the same
+    problems built (and multiplied) one by one, all on one stream.  The full
+    recipe (N_p in [2^14, 2^18], 6.7M points) stores ~1e11 factor entries at
+    eps 1e-5, beyond one GPU: it is built up to the ACA; build and matvec are
+    compared on the same recipe with N_p in [2^12, 2^16]."""
+    kw = dict(compute_dtype="f32", leaf_size=128, eta=1.5, aca_eps=1e-5, max_rank=64)
+    stream = torch.cuda.current_stream()
+
+    def timed(f):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = f()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    res = {}
+    # the full recipe, up to the ACA
+    ns, ds, p0s, pts = batched_problems(torch, 14, 18)
+    H.HMatrix.batched(pts, "gaussian", list(p0s), aca_only=1, **kw).close()
+    hb, tb = timed(lambda: H.HMatrix.batched(pts, "gaussian", list(p0s), aca_only=1, **kw))
+    st = hb.stats()
+    hb.close()
+    t1 = 0.0
+    for q in range(len(ns)):
+        hq, t = timed(lambda: H.HMatrix(pts[q], "gaussian", float(p0s[q]), aca_only=1, **kw))
+        t1 += t
+        hq.close()
+    res["aca_only"] = {"workload": "64 problems, N_p = round(2^U(14,18)) (total %d), d_p in "
+                                   "{2,3}, Gaussian p0 log-uniform [0.005, 0.05], FP32, leaf 128, "
+                                   "eta 1.5, eps 1e-5; build up to the ACA" % int(ns.sum()),
+                       "batched_build_s": tb, "one_by_one_build_s": t1, "build_speedup": t1 / tb,
+                       "n_adm": st.n_adm, "n_dense": st.n_dense, "aca_chunks": st.aca_chunks}
+    log("bench: 64 problems (2^14-2^18, ACA only): batched build %.3f s, one by one %.3f s"
+        % (tb, t1))
+    del pts
+    H.hmx_trim()
+    # the reduced recipe, full builds and matvecs
+    ns, ds, p0s, pts = batched_problems(torch, 12, 16)
+    ntot = int(ns.sum())
+    x = torch.from_numpy(synth.normal_vector(ntot, 4300, dtype=np.float32)).cuda()
+    H.HMatrix.batched(pts, "gaussian", list(p0s), **kw).close()
+    hb, tb = timed(lambda: H.HMatrix.batched(pts, "gaussian", list(p0s), **kw))
+    st = hb.stats()
+    H.hmx_autotune(hb.h, 3, stream)
+    z = torch.empty_like(x)
+    gr = H.hmx_matvec_graph(hb.h, x, z)
+    H.hmx_graph_launch(gr, stream)
+    _, tm = timed(lambda: [H.hmx_graph_launch(gr, stream) for _ in range(M)])
+    H.hmx_graph_destroy(gr)
+    hb.close()
+    off = np.concatenate([[0], np.cumsum(ns)])
+    t_build, t_mv = 0.0, 0.0
+    for q in range(len(ns)):
+        hq, t = timed(lambda: H.HMatrix(pts[q], "gaussian", float(p0s[q]), **kw))
+        t_build += t
+        xq = x[off[q]:off[q + 1]].contiguous()
+        zq = torch.empty_like(xq)
+        H.hmx_matvec(hq.h, xq, zq, 1.0, 0.0, stream)
+        _, t = timed(lambda: [H.hmx_matvec(hq.h, xq, zq, 1.0, 0.0, stream) for _ in range(M)])
+        t_mv += t
+        hq.close()
+    res["full"] = {"workload": "64 problems, N_p = round(2^U(12,16)) (total %d), d_p in {2,3}, "
+                               "Gaussian p0 log-uniform [0.005, 0.05], FP32, leaf 128, eta 1.5, "
+                               "eps 1e-5" % ntot,
+                   "batched_build_s": tb, "batched_matvec_ms": tm / M * 1e3,
+                   "batched_matvec_gbs": st.matvec_bytes / (tm / M) / 1e9,
+                   "one_by_one_build_s": t_build, "one_by_one_matvec_ms": t_mv / M * 1e3,
+                   "build_speedup": t_build / tb, "matvec_speedup": t_mv / tm,
+                   "n_adm": st.n_adm, "n_dense": st.n_dense}
+    log("bench: 64 problems (2^12-2^16): batched build %.3f s, matvec %.3f ms (%.0f GB/s); one "
+        "by one build %.3f s, matvec %.3f ms" % (tb, tm / M * 1e3, res["full"]["batched_matvec_gbs"],
+                                                  t_build, t_mv / M * 1e3))
+    del pts
+    H.hmx_trim()
+    return res
+
+
 def stream_copy_gbs(torch, dev, mib=4096, reps=5):
     """Bytes read + written per second of a plain device-to-device copy of
     mib MiB (torch's copy kernel), the best of reps: the box's measured
@@ -262,6 +352,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-n22", action="store_true",
                     help="skip the N = 2^22 three-dimensional build comparison")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-problem batched build and matvec")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -468,6 +560,9 @@ def main():
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = nel * 4
         del src, dst
+    if not args.no_batched:
+        H.hmx_trim()
+        out["batched_64"] = batched_leg(torch, H, log)
     if not args.no_n22:
         H.hmx_trim()
         out["n22_build"] = n22_aca_builds(torch, H, log)
