@@ -815,23 +815,17 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
         a.med_words = plan.med_words;
         a.tiny_words = plan.tiny_words;
         DevBuf split;
-        alloc(split, 8, "class split");
+        alloc(split, 3 * 8, "class split");
 
         // one pass over blocks[0..nb): cap = per-block column capacity (null:
         // k_max), rt = one-shot targets (null: adaptive); exact offsets of the
         // blocks' factors in the pools go to ue_all / ve_all
+        // (bounds: the chunks' first blocks and the end, when the caller cut
+        // the list; each chunk must be level-sorted)
         auto pass = [&](const int4* blocks, const int32_t* levels, int64_t nb, const int32_t* cap,
                         const int32_t* rt, int one_shot, int cap_only, int32_t* rank,
-                        int32_t* steps, int64_t* ue_all, int64_t* ve_all) {
-            check(launch_level_split(levels, nb, plan.split0, split.as<int64_t>(), st),
-                  "class split");
-            const int64_t nsplit_all = read_scalar(split.as<int64_t>(), st);
-            check(launch_level_split(levels, nb, plan.split, split.as<int64_t>(), st),
-                  "class split");
-            const int64_t nbig_all = read_scalar(split.as<int64_t>(), st);
-            check(launch_level_split(levels, nb, plan.split2, split.as<int64_t>(), st),
-                  "class split");
-            const int64_t nmed_all = read_scalar(split.as<int64_t>(), st);
+                        int32_t* steps, int64_t* ue_all, int64_t* ve_all,
+                        const std::vector<int64_t>* bounds) {
             DevBuf cu, cv, cc, Ucap, Vcap;
             alloc(cu, (nb + 1) * 8, "U capacity offsets");
             alloc(cv, (nb + 1) * 8, "V capacity offsets");
@@ -846,16 +840,24 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
             scan(cv.as<int64_t>(), nb);
             const int64_t ctot = scan(cc.as<int64_t>(), nb);
             S.aca_capacity += ctot;
-            // each chunk's capacity is at most step + one block
-            int nch = (int)std::min<int64_t>((ctot + budget - 1) / budget, 1 << 20);
-            nch = std::max(nch, 1);
-            const int64_t step = (ctot + nch - 1) / nch;
-            DevBuf bnd;
-            alloc(bnd, (size_t)(nch + 1) * 8, "chunk bounds");
-            check(launch_chunk_bounds(cc.as<int64_t>(), nb, step, nch, bnd.as<int64_t>(), st),
-                  "chunk bounds");
-            std::vector<int64_t> hb(nch + 1), hcu(nch + 1), hcv(nch + 1);
-            d2h(hb.data(), bnd.p, (nch + 1) * 8, st);
+            std::vector<int64_t> hb;
+            int nch;
+            if (bounds) {
+                hb = *bounds;
+                nch = (int)hb.size() - 1;
+            } else {
+                // each chunk's capacity is at most step + one block
+                nch = (int)std::min<int64_t>((ctot + budget - 1) / budget, 1 << 20);
+                nch = std::max(nch, 1);
+                const int64_t step = (ctot + nch - 1) / nch;
+                DevBuf bnd;
+                alloc(bnd, (size_t)(nch + 1) * 8, "chunk bounds");
+                check(launch_chunk_bounds(cc.as<int64_t>(), nb, step, nch, bnd.as<int64_t>(), st),
+                      "chunk bounds");
+                hb.resize(nch + 1);
+                d2h(hb.data(), bnd.p, (nch + 1) * 8, st);
+            }
+            std::vector<int64_t> hcu(nch + 1), hcv(nch + 1);
             int64_t max_u = 0, max_v = 0;
             for (int k = 0; k <= nch; ++k) {
                 check(hipMemcpyAsync(&hcu[k], cu.as<int64_t>() + hb[k], 8, hipMemcpyDeviceToHost,
@@ -902,9 +904,16 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                 a.ubase = hcu[k];
                 a.vbase = hcv[k];
                 a.rtarget = rt ? rt + b0 : nullptr;
-                a.nsplit = std::max<int64_t>(0, std::min(nsplit_all - b0, nbk));
-                a.nbig = std::max<int64_t>(0, std::min(nbig_all - b0, nbk));
-                a.nmed = std::max<int64_t>(0, std::min(nmed_all - b0, nbk));
+                // the size classes of this chunk (level-sorted within the chunk)
+                int64_t cls[3];
+                const int lv[3] = {plan.split0, plan.split, plan.split2};
+                for (int c = 0; c < 3; ++c)
+                    check(launch_level_split(levels + b0, nbk, lv[c], split.as<int64_t>() + c, st),
+                          "class split");
+                d2h(cls, split.p, sizeof cls, st);
+                a.nsplit = cls[0];
+                a.nbig = cls[1];
+                a.nmed = cls[2];
                 a.rank = rank + b0;
                 a.steps = steps + b0;
                 a.ovf_u0 = hcu[k] + max_u;
@@ -949,10 +958,105 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
             }
         };
 
+        // The level-ordered list cut into chunks by capacity would give each
+        // chunk one or two size classes (the largest blocks first, the leaf
+        // level last), so the classes, which run concurrently, would rarely
+        // overlap.  A list that needs several chunks is reordered so that every
+        // chunk holds the same share of every level (level-sorted within the
+        // chunk); ranks, steps and pool offsets return to the canonical order.
+        auto chunked_pass = [&](const int4* blocks, const int32_t* levels, int64_t nb,
+                                const int32_t* cap, const int32_t* rt, int one_shot, int cap_only,
+                                int32_t* rank, int32_t* steps, int64_t* ue_all, int64_t* ve_all) {
+            DevBuf cc;
+            alloc(cc, (nb + 1) * 8, "capacity");
+            check(launch_extent(blocks, nb, cap ? 8 : 7, kmax, cap, nullptr, cc.as<int64_t>(), st),
+                  "extent");
+            const int64_t ctot = scan(cc.as<int64_t>(), nb);
+            cc.release();
+            if (ctot <= budget) {
+                pass(blocks, levels, nb, cap, rt, one_shot, cap_only, rank, steps, ue_all, ve_all,
+                     nullptr);
+                return;
+            }
+            // slices of equal shares, with room for the variation of the
+            // per-block capacities between slices
+            const int nsl = (int)std::min<int64_t>((ctot + ctot / 8 + budget - 1) / budget, 1 << 20);
+            DevBuf lb;
+            alloc(lb, 2 * 64 * 8, "level bounds");
+            check(hipMemsetAsync(lb.p, 0, 2 * 64 * 8, st), "level bounds");
+            int64_t* lstart = lb.as<int64_t>();
+            int64_t* lend = lstart + 64;
+            check(launch_level_bounds(levels, nb, lstart, lend, st), "level bounds");
+            int64_t hl[128];
+            d2h(hl, lb.p, sizeof hl, st);
+            // chunk k: the positions p of each level (c blocks) with
+            // floor(p nsl / c) == k, i.e. [ceil(k c / nsl), ceil((k + 1) c / nsl))
+            std::vector<int64_t> bounds(nsl + 1, 0);
+            for (int l = 0; l < 64; ++l) {
+                const int64_t c = hl[64 + l] - hl[l];
+                if (c <= 0) continue;
+                for (int k = 0; k < nsl; ++k)
+                    bounds[k + 1] += ((int64_t)(k + 1) * c + nsl - 1) / nsl -
+                                     ((int64_t)k * c + nsl - 1) / nsl;
+            }
+            for (int k = 0; k < nsl; ++k) bounds[k + 1] += bounds[k];
+            if (bounds[nsl] != nb) {
+                set_err("interleaved chunks cover %lld of %lld blocks", (long long)bounds[nsl],
+                        (long long)nb);
+                throw Fail{HMX_ERR_DEVICE};
+            }
+            DevBuf keys, perm, sscr;
+            alloc(keys, (size_t)nb * 8, "interleave keys");
+            alloc(perm, (size_t)nb * 4, "interleave order");
+            check(launch_interleave_keys(levels, nb, lstart, lend, nsl, keys.as<uint64_t>(),
+                                         perm.as<uint32_t>(), st),
+                  "interleave keys");
+            int bits = 8;
+            while ((1ll << (bits - 8)) < nsl) ++bits;
+            alloc(sscr, radix_sort_scratch_bytes(nb), "interleave sort");
+            check(radix_sort_pairs(keys.as<uint64_t>(), perm.as<uint32_t>(), nb, bits, sscr.p, st),
+                  "interleave sort");
+            keys.release();
+            sscr.release();
+            DevBuf pb, pl, pc, pr, prk, pst, pue, pve;
+            alloc(pb, (size_t)nb * sizeof(int4), "interleaved blocks");
+            alloc(pl, (size_t)nb * 4, "interleaved levels");
+            if (cap) alloc(pc, (size_t)nb * 4, "interleaved capacities");
+            if (rt) alloc(pr, (size_t)nb * 4, "interleaved targets");
+            check(launch_gather_blocks(perm.as<uint32_t>(), nb, blocks, levels, cap, rt,
+                                       pb.as<int4>(), pl.as<int32_t>(),
+                                       cap ? pc.as<int32_t>() : nullptr,
+                                       rt ? pr.as<int32_t>() : nullptr, st),
+                  "interleave gather");
+            alloc(prk, (size_t)nb * 4, "interleaved ranks");
+            alloc(pst, (size_t)nb * 4, "interleaved steps");
+            alloc(pue, (size_t)(nb + 1) * 8, "interleaved U offsets");
+            alloc(pve, (size_t)(nb + 1) * 8, "interleaved V offsets");
+            // the same targets serve as capacity and as the kernel's target (cap == rt)
+            const int32_t* pcap = cap ? (cap == rt ? pr.as<int32_t>() : pc.as<int32_t>()) : nullptr;
+            pass(pb.as<int4>(), pl.as<int32_t>(), nb, pcap, rt ? pr.as<int32_t>() : nullptr,
+                 one_shot, cap_only, prk.as<int32_t>(), pst.as<int32_t>(), pue.as<int64_t>(),
+                 pve.as<int64_t>(), &bounds);
+            const int32_t* li = (const int32_t*)perm.p;
+            check(launch_scatter_i32(li, nb, prk.as<int32_t>(), rank, 0, st), "interleaved ranks");
+            check(launch_scatter_i32(li, nb, pst.as<int32_t>(), steps, 0, st), "interleaved steps");
+            if (!aca_only) {
+                check(launch_scatter_i64(li, nb, pue.as<int64_t>(), ue_all, st), "interleaved U");
+                check(launch_scatter_i64(li, nb, pve.as<int64_t>(), ve_all, st), "interleaved V");
+                check(hipMemcpyAsync(ue_all + nb, pue.as<int64_t>() + nb, 8,
+                                     hipMemcpyDeviceToDevice, st),
+                      "U total");
+                check(hipMemcpyAsync(ve_all + nb, pve.as<int64_t>() + nb, 8,
+                                     hipMemcpyDeviceToDevice, st),
+                      "V total");
+            }
+            check(hipStreamSynchronize(st), "interleave sync");  // before the buffers return
+        };
+
         if (!learned) {
-            pass(h->adm.as<int4>(), plan.cls, h->n_adm, nullptr, nullptr, 0, 0,
-                 h->rank.as<int32_t>(), h->steps.as<int32_t>(), uoff_ex.as<int64_t>(),
-                 h->voff.as<int64_t>());
+            chunked_pass(h->adm.as<int4>(), plan.cls, h->n_adm, nullptr, nullptr, 0, 0,
+                         h->rank.as<int32_t>(), h->steps.as<int32_t>(), uoff_ex.as<int64_t>(),
+                         h->voff.as<int64_t>());
         } else {
             // learned sizing: predicted targets, a pass with storage of that
             // size, then the blocks left unfinished again with k_max columns
@@ -960,9 +1064,9 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
             // steps, the test, then adaptive)
             const int one_shot = h->prm.learned_one_shot;
             const int32_t* rt = plan.rt;
-            pass(h->adm.as<int4>(), plan.cls, h->n_adm, rt, rt, one_shot, 1,
-                 h->rank.as<int32_t>(), h->steps.as<int32_t>(), uoff_ex.as<int64_t>(),
-                 h->voff.as<int64_t>());
+            chunked_pass(h->adm.as<int4>(), plan.cls, h->n_adm, rt, rt, one_shot, 1,
+                         h->rank.as<int32_t>(), h->steps.as<int32_t>(), uoff_ex.as<int64_t>(),
+                         h->voff.as<int64_t>());
             DevBuf flag;
             alloc(flag, (h->n_adm + 1) * 8, "fallback flags");
             check(launch_over_flags(h->rank.as<int32_t>(), rt, h->n_adm, flag.as<int64_t>(), st),
@@ -989,7 +1093,7 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                       "fallback gather");
                 pass(bfb.as<int4>(), lvfb.as<int32_t>(), nfb, nullptr,
                      one_shot ? rtfb.as<int32_t>() : nullptr, one_shot, 0, rkfb.as<int32_t>(),
-                     stfb.as<int32_t>(), uefb.as<int64_t>(), vefb.as<int64_t>());
+                     stfb.as<int32_t>(), uefb.as<int64_t>(), vefb.as<int64_t>(), nullptr);
                 const int32_t* li = list.as<int32_t>();
                 check(launch_scatter_i32(li, nfb, rkfb.as<int32_t>(), h->rank.as<int32_t>(), 0,
                                          st),

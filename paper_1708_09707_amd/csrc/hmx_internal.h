@@ -202,6 +202,19 @@ struct AcaArgs {
 };
 // queue the single-workgroup classes on aux[0..2] (3 streams, or null: all on
 // st) after the work queued on st; join makes st wait for them
+// chunking the ACA's level-ordered block list into slices that each hold a
+// share of every level (k_batch.hip): level bounds of a level-sorted list
+// (lstart/lend preset to zero, 64 entries each), interleave keys for a stable
+// sort, and the gather of blocks, levels and two optional int32 arrays
+hipError_t launch_level_bounds(const int32_t* level, int64_t nb, int64_t* lstart, int64_t* lend,
+                               hipStream_t st);
+hipError_t launch_interleave_keys(const int32_t* level, int64_t nb, const int64_t* lstart,
+                                  const int64_t* lend, int nch, uint64_t* keys, uint32_t* vals,
+                                  hipStream_t st);
+hipError_t launch_gather_blocks(const uint32_t* perm, int64_t n, const int4* blocks,
+                                const int32_t* level, const int32_t* a, const int32_t* b,
+                                int4* blocks_out, int32_t* level_out, int32_t* a_out,
+                                int32_t* b_out, hipStream_t st);
 hipError_t launch_apply_moved(const int64_t* moved, int64_t nb, int64_t u0, int64_t v0,
                               int64_t* uoff, int64_t* voff, hipStream_t st);
 hipError_t aca_classes_begin(const AcaArgs& a, int f64, hipStream_t st, const hipStream_t* aux);

@@ -556,8 +556,17 @@ __device__ __noinline__ long long aca_overflow_move(const Overflow& ovf, int m, 
     return off;
 }
 
+// waves per SIMD the compiler must leave room for: four for the multi-wave
+// classes (their latency-bound steps gain from the occupancy more than the
+// few spilled registers cost), the register-limited default for the
+// single-wave class (whose blocks are many and short)
+template <int NT>
+constexpr int aca_min_waves() {
+    return NT > kWave ? 4 : 1;
+}
+
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void aca_kernel(
+__global__ __launch_bounds__(NT, aca_min_waves<NT>()) void aca_kernel(
     const T* __restrict__ soa, const double* __restrict__ soa64, int64_t n, int d, KernelEval<T> K,
     const int4* __restrict__ blocks, int64_t nblocks, const int64_t* __restrict__ uoff,
     const int64_t* __restrict__ voff, int64_t ubase, int64_t vbase, int kmax, double eps, double aca_eta, T eps0, int fixed,

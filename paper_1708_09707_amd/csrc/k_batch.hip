@@ -44,7 +44,77 @@ __global__ void scale_coords_kernel(const double* __restrict__ src, int64_t n, i
     }
 }
 
+// lstart[l] / lend[l]: first / one past the last index of level l in a
+// level-sorted list (levels absent from the list keep the preset zeros)
+__global__ void level_bounds_kernel(const int32_t* __restrict__ level, int64_t nb,
+                                    int64_t* __restrict__ lstart, int64_t* __restrict__ lend) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const int32_t l = level[i];
+    if (i == 0 || level[i - 1] != l) lstart[l] = i;
+    if (i == nb - 1 || level[i + 1] != l) lend[l] = i + 1;
+}
+
+// key (slice << 8 | level): block i at position pos of its level's c blocks
+// belongs to slice floor(pos nch / c), so every slice holds a contiguous
+// share of every level; a stable sort by the key keeps each slice level-sorted
+__global__ void interleave_keys_kernel(const int32_t* __restrict__ level, int64_t nb,
+                                       const int64_t* __restrict__ lstart,
+                                       const int64_t* __restrict__ lend, int nch,
+                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const int32_t l = level[i];
+    const int64_t s = lstart[l], c = lend[l] - s;
+    const uint64_t slice = (uint64_t)((i - s) * (int64_t)nch / c);
+    keys[i] = (slice << 8) | (uint64_t)l;
+    vals[i] = (uint32_t)i;
+}
+
+// the blocks, levels and (optional) two per-block int32 arrays in the order perm
+__global__ void gather_blocks_kernel(const uint32_t* __restrict__ perm, int64_t n,
+                                     const int4* __restrict__ blocks,
+                                     const int32_t* __restrict__ level,
+                                     const int32_t* __restrict__ a, const int32_t* __restrict__ b,
+                                     int4* __restrict__ blocks_out, int32_t* __restrict__ level_out,
+                                     int32_t* __restrict__ a_out, int32_t* __restrict__ b_out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t j = perm[i];
+    blocks_out[i] = blocks[j];
+    level_out[i] = level[j];
+    if (a) a_out[i] = a[j];
+    if (b) b_out[i] = b[j];
+}
+
 }  // namespace
+
+hipError_t launch_level_bounds(const int32_t* level, int64_t nb, int64_t* lstart, int64_t* lend,
+                               hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(level_bounds_kernel, dim3(g1d(nb)), dim3(256), 0, st, level, nb, lstart,
+                       lend);
+    return hipGetLastError();
+}
+
+hipError_t launch_interleave_keys(const int32_t* level, int64_t nb, const int64_t* lstart,
+                                  const int64_t* lend, int nch, uint64_t* keys, uint32_t* vals,
+                                  hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(interleave_keys_kernel, dim3(g1d(nb)), dim3(256), 0, st, level, nb, lstart,
+                       lend, nch, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_blocks(const uint32_t* perm, int64_t n, const int4* blocks,
+                                const int32_t* level, const int32_t* a, const int32_t* b,
+                                int4* blocks_out, int32_t* level_out, int32_t* a_out,
+                                int32_t* b_out, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_blocks_kernel, dim3(g1d(n)), dim3(256), 0, st, perm, n, blocks,
+                       level, a, b, blocks_out, level_out, a_out, b_out);
+    return hipGetLastError();
+}
 
 hipError_t launch_add_i32(int32_t* dst, const int32_t* src, int64_t cnt, int32_t c,
                           hipStream_t st) {

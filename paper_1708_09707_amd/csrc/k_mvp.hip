@@ -544,13 +544,23 @@ __global__ __launch_bounds__(256) void far_phase1_kernel(
             for (int e = 0; e < VS; ++e) acc += a[e] * xv[e];
         }
     } else {
-        for (int j = lane; j < nc; j += 64) {
-            T a;
-            if constexpr (sizeof(S) == 2)
-                a = __uint_as_float((uint32_t)(*(const uint16_t*)(col + j)) << 16);
-            else
-                a = (T)col[j];
-            acc += a * xs[j];
+        // the same assignment of entries to lanes and the same order as the
+        // vector path (lane j: entries j VS .. j VS + VS - 1), so a column's
+        // sum does not depend on where it lies in the pool
+        const int nv = (nc + VS - 1) / VS;
+        for (int j = lane; j < nv; j += 64) {
+#pragma unroll
+            for (int e = 0; e < VS; ++e) {
+                const int i = j * VS + e;
+                if (i < nc) {
+                    T a;
+                    if constexpr (sizeof(S) == 2)
+                        a = __uint_as_float((uint32_t)(*(const uint16_t*)(col + i)) << 16);
+                    else
+                        a = (T)col[i];
+                    acc += a * xs[i];
+                }
+            }
         }
     }
     acc = wave_sum(acc);
