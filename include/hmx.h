@@ -151,7 +151,11 @@ typedef struct {
                                 (the paper's no-storage mode for dense blocks,
                                 Section 5.4), same arithmetic as the stored
                                 assembly.  near_dtype is then ignored */
-    int32_t reserved[2];
+    int32_t aca_split_rows;  /* admissible blocks whose clusters hold at least
+                                this many points run their ACA on many
+                                workgroups each (0: 262144, which also bounds
+                                the single-workgroup classes' LDS bitmasks) */
+    int32_t reserved;
 } hmx_params;
 
 /* Statistics of a built H-matrix (host struct). */

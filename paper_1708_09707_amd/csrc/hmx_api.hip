@@ -405,6 +405,10 @@ hmx_status check_params(const hmx_params& p) {
         set_err("near_recompute must be 0 or 1");
         return HMX_ERR_INVALID_ARG;
     }
+    if (p.aca_split_rows < 0) {
+        set_err("aca_split_rows must be >= 0 (0: default)");
+        return HMX_ERR_INVALID_ARG;
+    }
     if (!p.near_recompute) {
         const bool ok = (p.near_dtype == p.storage_dtype) ||
                         (p.storage_dtype == HMX_BF16 && p.near_dtype == HMX_F32);
@@ -610,24 +614,30 @@ struct AcaPlan {
     const int32_t* rt = nullptr;         // learned targets, or null
 };
 
-// clusters of kSplitRows or more points put their blocks on many workgroups
-// each, of kBigRows or more in the 512-thread class; clusters of at most
-// kTinyRows points in the single-wave class
-constexpr int64_t kSplitRows = 16384;
+// clusters of split_rows(h) or more points put their blocks on many
+// workgroups each, of kBigRows or more in the 512-thread class; clusters of
+// at most kTinyRows points in the single-wave class.  With the chunks
+// interleaving the levels, a block of up to 2^17 rows runs as well on one
+// 512-thread workgroup beside the other classes as on many workgroups; the
+// default keeps the many-workgroup path for blocks whose bitmasks would not
+// fit a workgroup's LDS
+constexpr int64_t kDefaultSplitRows = (int64_t)1 << 18;
 constexpr int64_t kBigRows = 4096;
 constexpr int64_t kTinyRows = 256;
 
 // size classes of a single problem by tree level: clusters at level l hold at
 // most s_l points (s_0 = n, s_{l+1} = ceil(s_l / 2)); levels whose clusters
 // can reach kBigRows points form the 512-thread class
+int64_t split_rows(const hmx_hmatrix_s* h) {
+    return h->prm.aca_split_rows > 0 ? h->prm.aca_split_rows : kDefaultSplitRows;
+}
+
 AcaPlan level_plan(const hmx_hmatrix_s* h) {
     AcaPlan p;
-    {
-        int64_t s0 = h->n;
-        while (s0 >= kSplitRows) {
-            s0 = (s0 + 1) / 2;
-            ++p.split0;
-        }
+    int64_t s0 = h->n;  // the largest cluster below the many-workgroup levels
+    while (s0 >= split_rows(h)) {
+        s0 = (s0 + 1) / 2;
+        ++p.split0;
     }
     int64_t s_split = h->n;
     while (s_split >= kBigRows) {
@@ -640,7 +650,7 @@ AcaPlan level_plan(const hmx_hmatrix_s* h) {
         s_split2 = (s_split2 + 1) / 2;
         ++p.split2;
     }
-    const int64_t big = h->big_adm;
+    const int64_t big = std::min(h->big_adm, s0);  // the largest single-workgroup block
     const int64_t words = 2 * ((big + 31) / 32);
     if (words * 4 > 64 * 1024) {
         set_err("admissible block of %lld rows exceeds the ACA bitmask capacity", (long long)big);
@@ -876,7 +886,9 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
             // the chunk's capacity, where blocks that need more columns
             // continue (those it cannot hold are approximated again later)
             const int64_t ovf_cap =
-                cap_only ? std::max<int64_t>(std::max(max_u, max_v) / 16, 2 * kSplitRows * kmax) : 0;
+                cap_only ? std::max<int64_t>(std::max(max_u, max_v) / 16,
+                                             2 * std::min(h->big_adm, split_rows(h)) * kmax)
+                         : 0;
             alloc(Ucap, (size_t)std::max<int64_t>(max_u + ovf_cap, 1) * esz, "U chunk scratch");
             alloc(Vcap, (size_t)std::max<int64_t>(max_v + ovf_cap, 1) * esz, "V chunk scratch");
             DevBuf ovf_used, moved;

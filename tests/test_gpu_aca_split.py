@@ -10,7 +10,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-SPLIT_ROWS = 16384  # clusters this large take the many-workgroup path
+SPLIT_ROWS = 16384  # clusters this large take the many-workgroup path (aca_split_rows)
 
 
 @pytest.fixture(scope="module")
@@ -31,7 +31,7 @@ def test_split_blocks_match_oracle(H, orc, dtype):
     n, p0, eps, kmax = 1 << 18, 0.02, 1e-6 if dtype == "f64" else 1e-5, 48
     pts = synth.uniform_points(n, 2, 1717)
     hm = H.HMatrix(_dev(pts), "gaussian", p0, compute_dtype=dtype, leaf_size=256, eta=1.5,
-                   aca_eps=eps, max_rank=kmax)
+                   aca_eps=eps, max_rank=kmax, aca_split_rows=SPLIT_ROWS)
     part = hm.partition()
     adm = part["adm"]
     ranks = hm.ranks()
@@ -85,7 +85,8 @@ def test_split_learned_and_batched(H):
     w = np.zeros(8961, np.float32)
     w[-1] = 4.0
     mlp = H.RankMLP(w)
-    kw = dict(compute_dtype="f32", leaf_size=256, eta=1.5, aca_eps=1e-5, max_rank=48)
+    kw = dict(compute_dtype="f32", leaf_size=256, eta=1.5, aca_eps=1e-5, max_rank=48,
+              aca_split_rows=SPLIT_ROWS)
     ha = H.HMatrix(_dev(pts), "gaussian", p0, **kw)
     hl = H.HMatrix(_dev(pts), "gaussian", p0, rank_mode="learned", mlp=mlp, **kw)
     x = _dev(synth.normal_vector(n, 1722, dtype=np.float32))
