@@ -61,9 +61,18 @@ TRAIN = dict(builds=24, log2n_lo=14, log2n_hi=18, p0_lo=0.002, p0_hi=0.05, seed=
              steps=800, batch=2048, lr=3e-3, q=0.9)
 
 
-def kernel_source_hash() -> str:
-    with open(os.path.join(ROOT, "paper_1708_09707_amd", "csrc", "k_mvp.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_source_hash(text=None) -> str:
+    """Hash of the row-tile kernel's source: the storage decoders it reads the
+    pools with and the phase-2 section of k_mvp.hip up to the end of its
+    launcher (the counters stay valid while this text is unchanged)."""
+    if text is None:
+        with open(os.path.join(ROOT, "paper_1708_09707_amd", "csrc", "k_mvp.hip")) as f:
+            text = f.read()
+    a = text.index("template <typename S, typename T>\nstruct Dec;")
+    b = text.index("\n", text.index("__device__ __forceinline__ u32x4 nt_load("))
+    c = text.index("// phase 2: one workgroup per row tile")
+    d = text.index("}  // namespace", text.index("hipError_t rowtile_dispatch("))
+    return hashlib.sha256((text[a:b] + text[c:d]).encode()).hexdigest()[:16]
 
 
 def rowtile_bytes(st) -> float:
