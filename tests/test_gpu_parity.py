@@ -236,6 +236,49 @@ def test_aca_chunking_is_invisible(H):
     assert np.array_equal(outs[0][2], outs[1][2])
 
 
+def test_aca_chunking_is_invisible_learned(H):
+    """The learned sizing in many small chunks (the chunks interleave the tree
+    levels; blocks past their target continue in each chunk's overflow
+    reserve) gives the same ranks and product bits as in one chunk."""
+    pts = synth.uniform_points(40000, 3, 25)
+    x = _dev(synth.normal_vector(40000, 26)).float()
+    w = np.zeros(8961, np.float32)
+    w[-1] = 3.0  # a constant target well below most ranks: many overflows
+    mlp = H.RankMLP(w)
+    outs = []
+    for mb in [0, 1]:
+        hm = _build(H, pts, "gaussian", 0.02, "f32", leaf_size=64, eta=1.5, aca_eps=1e-5,
+                    aca_chunk_mb=mb, rank_mode="learned", mlp=mlp)
+        st = hm.stats()
+        print("chunks %d, overflows %d, fallbacks %d" % (st.aca_chunks, st.aca_overflow,
+                                                         st.aca_fallback))
+        outs.append((st.aca_chunks, hm.ranks(), hm.matvec(x).cpu().numpy()))
+        hm.close()
+    mlp.close()
+    assert outs[0][0] <= 2 and outs[1][0] > 10
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[0][2], outs[1][2])
+
+
+def test_aca_work_stats(H):
+    """The ACA work counters: multiply-add flops sum 2 r (r - 1) (m + n) over
+    the admissible blocks exactly; kernel evaluations (a column per step, a row
+    per accepted step) lie between sum r (m + n) and sum (r + 2 k_max) m + r n."""
+    pts = synth.uniform_points(30000, 2, 27)
+    kmax = 32
+    hm = _build(H, pts, "gaussian", 0.01, "f32", leaf_size=64, eta=1.5, aca_eps=1e-5,
+                max_rank=kmax)
+    st = hm.stats()
+    adm = hm.partition()["adm"].astype(np.int64)
+    r = hm.ranks().astype(np.int64)
+    m, nc = adm[:, 1] - adm[:, 0], adm[:, 3] - adm[:, 2]
+    assert st.aca_flops == float(np.sum(2 * r * (r - 1) * (m + nc)))
+    lo, hi = np.sum(r * (m + nc)), np.sum((r + 2 * kmax) * m + r * nc)
+    print("kernel evaluations %d in [%d, %d]" % (st.aca_kernel_evals, lo, hi))
+    assert lo <= st.aca_kernel_evals <= hi
+    hm.close()
+
+
 def test_invalid_arguments(H):
     pts = _dev(synth.uniform_points(100, 2, 1))
     K = H.make_kernel("gaussian", 0.1)
