@@ -5,8 +5,10 @@
 // block).  Blocks of the upper tree levels (many rows) get 512-thread
 // workgroups, those of the leaf levels (at most 256 rows) one wave, the rest
 // 256 threads (the very largest run on many workgroups each, k_aca_split.hip);
-// the canonical leaf order is level order, so each class is a contiguous
-// range of every block list.  Per step r:
+// every chunk of blocks handed to the ACA is level-sorted (the canonical leaf
+// order is level order; a list cut into several chunks is first reordered so
+// that each chunk holds a share of every level), so each class is a contiguous
+// range of a chunk and the classes of a chunk run concurrently.  Per step r:
 //   1. residual column  u^ = A[:, j] - sum_{l<r} u_l (v_l)_j   (rows over threads)
 //   2. row pivot        i  = argmax over unused rows |u^_i| (lowest index on ties)
 //      a column whose largest residual entry is <= eps0 times the column's own

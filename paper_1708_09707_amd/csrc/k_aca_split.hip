@@ -1,6 +1,8 @@
 // Batched ACA (Algorithm 2) of the largest admissible blocks with many
-// workgroups per block.  One workgroup per block serialises a block of
-// 10^5 rows on one compute unit for every rank-one step; here every step of
+// workgroups per block (by default those of clusters of 2^18 or more points,
+// whose used-row bitmasks would not fit one workgroup's LDS).  One workgroup
+// per block serialises such a block on one compute unit for every rank-one
+// step; here every step of
 // every such block is a short sequence of launches over row and column tiles
 // of all the blocks at once, with the per-block decisions (pivots, the FP64
 // norm recursion, the stopping test) in one workgroup per block:
