@@ -84,6 +84,11 @@ def test_validation_before_device_work():
         Q = hmx.hmx_params_default(**{field: val})
         assert L.hmx_build(dummy, 0, 10, 2, C.byref(K), C.byref(Q), None, C.byref(h)) == 1, field
         assert b"invalid params" in L.hmx_last_error()
+    for field, val, msg in [("aca_split_rows", -1, b"aca_split_rows"),
+                            ("near_recompute", 2, b"near_recompute")]:
+        Q = hmx.hmx_params_default(**{field: val})
+        assert L.hmx_build(dummy, 0, 10, 2, C.byref(K), C.byref(Q), None, C.byref(h)) == 1, field
+        assert msg in L.hmx_last_error()
     Q = hmx.hmx_params_default(compute_dtype=hmx.HMX_BF16)
     assert L.hmx_build(dummy, 0, 10, 2, C.byref(K), C.byref(Q), None, C.byref(h)) == 5
     Q = hmx.hmx_params_default(compute_dtype="f64", storage_dtype="bf16")
