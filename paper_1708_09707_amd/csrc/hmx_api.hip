@@ -1165,9 +1165,9 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
         h->sum_rank = scan(h->toff.as<int64_t>(), h->n_adm);
     }
     alloc(h->vecpool, (size_t)(n + h->sum_rank) * esz, "vector pool");
-    alloc(h->col_block, (size_t)std::max<int64_t>(h->sum_rank, 1) * 4, "column map");
-    check(launch_col_block(h->rank.as<int32_t>(), h->toff.as<int64_t>(), h->n_adm,
-                           h->col_block.as<int32_t>(), st),
+    alloc(h->col_block, (size_t)std::max<int64_t>(h->sum_rank, 1) * sizeof(int4), "column map");
+    check(launch_col_meta(h->adm.as<int4>(), h->rank.as<int32_t>(), h->toff.as<int64_t>(),
+                          h->voff.as<int64_t>(), h->n_adm, h->col_block.as<int4>(), st),
           "column map");
     S.phase_ms[4] += ms_since(t0);
     t0 = clk::now();
@@ -1483,9 +1483,8 @@ hipError_t matvec_launch(hmx_hmatrix_s* h, const void* x, void* z, double alpha,
     if (e == hipSuccess) e = launch_gather_x(x, h->perm.as<int32_t>(), h->n, h->vecpool.p, f64, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
     if (e == hipSuccess)
-        e = launch_far_phase1(h->adm.as<int4>(), h->col_block.as<int32_t>(),
-                              h->voff.as<int64_t>(), h->toff.as<int64_t>(), h->sum_rank, h->V.p,
-                              h->vecpool.p, h->n, h->smode, st);
+        e = launch_far_phase1(h->col_block.as<int4>(), h->sum_rank, h->V.p, h->vecpool.p, h->n,
+                              h->smode, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
     if (e == hipSuccess)
         e = launch_rowtile(h->ntiles, h->tile_lo.as<int32_t>(), h->tile_meta.as<int64_t>(),

@@ -312,10 +312,11 @@ hipError_t launch_aca_work(const int4* blocks, const int32_t* rank, const int32_
                            int64_t nb, unsigned long long* out, hipStream_t st);
 hipError_t launch_int_stats(const int32_t* a, int64_t n, unsigned long long* out,
                             hipStream_t st);
-hipError_t launch_col_block(const int32_t* rank, const int64_t* toff, int64_t nadm,
-                            int32_t* col_block, hipStream_t st);
-hipError_t launch_far_phase1(const int4* adm, const int32_t* col_block, const int64_t* voff,
-                             const int64_t* toff, int64_t ncols_total, const void* V,
+// one record per factor column for phase 1: {V offset low, high, first point
+// of sigma_b, |sigma_b|}
+hipError_t launch_col_meta(const int4* adm, const int32_t* rank, const int64_t* toff,
+                           const int64_t* voff, int64_t nadm, int4* meta, hipStream_t st);
+hipError_t launch_far_phase1(const int4* col_meta, int64_t ncols_total, const void* V,
                              void* vecpool, int64_t n, int smode, hipStream_t st);
 // config < 0: default tile shape; else shape config % kRowtileShapes, grid
 // config / kRowtileShapes: one workgroup per tile, a persistent grid of

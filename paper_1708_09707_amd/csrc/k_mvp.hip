@@ -486,13 +486,22 @@ __global__ void chunk_bounds_kernel(const int64_t* __restrict__ cap_off, int64_t
 }
 
 // column -> admissible leaf map for the flattened factor columns
-__global__ void col_block_kernel(const int32_t* __restrict__ rank,
-                                 const int64_t* __restrict__ toff, int64_t nadm,
-                                 int32_t* __restrict__ col_block) {
+// phase-1 record of factor column k = toff[b] + l of admissible block b:
+// {V offset (low, high 32 bits), first point of sigma_b, |sigma_b|}, so a
+// phase-1 wave finds its column with one load
+__global__ void col_meta_kernel(const int4* __restrict__ adm, const int32_t* __restrict__ rank,
+                                const int64_t* __restrict__ toff,
+                                const int64_t* __restrict__ voff, int64_t nadm,
+                                int4* __restrict__ meta) {
     const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (b >= nadm) return;
     const int64_t o = toff[b];
-    for (int l = 0; l < rank[b]; ++l) col_block[o + l] = (int32_t)b;
+    const int4 bl = adm[b];
+    const int nc = bl.w - bl.z;
+    for (int l = 0; l < rank[b]; ++l) {
+        const int64_t cofs = voff[b] + (int64_t)l * nc;
+        meta[o + l] = int4{(int)(uint32_t)cofs, (int)(uint32_t)(cofs >> 32), bl.z, nc};
+    }
 }
 
 // phase 1: t_b[l] = sum_j V_b[j, l] x[slo + j]; one wave per column of the
@@ -515,24 +524,22 @@ __device__ __forceinline__ void load_x16<double>(const double* p, double* o) {
 }
 
 template <typename S, typename T>
-__global__ __launch_bounds__(256) void far_phase1_kernel(
-    const int4* __restrict__ adm, const int32_t* __restrict__ col_block,
-    const int64_t* __restrict__ voff, const int64_t* __restrict__ toff, const S* __restrict__ V,
-    T* __restrict__ vec, int64_t n, int64_t ncols_total) {
+__global__ __launch_bounds__(256) void far_phase1_kernel(const int4* __restrict__ col_meta,
+                                                         const S* __restrict__ V,
+                                                         T* __restrict__ vec, int64_t n,
+                                                         int64_t ncols_total) {
     constexpr int VS = Dec<S, T>::n;  // values per 16-byte load of V
     constexpr int VT = 16 / sizeof(T);
     const int lane = threadIdx.x & 63;
     const int64_t k = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     if (k >= ncols_total) return;
-    const int b = col_block[k];
-    const int4 bl = adm[b];
-    const int nc = bl.w - bl.z;
-    const int l = (int)(k - toff[b]);
-    const int64_t cofs = voff[b] + (int64_t)l * nc;
+    const int4 cm = col_meta[k];
+    const int nc = cm.w;
+    const int64_t cofs = (int64_t)(((uint64_t)(uint32_t)cm.y << 32) | (uint32_t)cm.x);
     const S* __restrict__ col = V + cofs;
-    const T* __restrict__ xs = vec + bl.z;
+    const T* __restrict__ xs = vec + cm.z;
     T acc = 0;
-    if ((cofs % VS) == 0 && (nc % VS) == 0 && ((int64_t)bl.z % VT) == 0) {
+    if ((cofs % VS) == 0 && (nc % VS) == 0 && ((int64_t)cm.z % VT) == 0) {
         const u32x4* __restrict__ c16 = (const u32x4*)col;
         const int nv = nc / VS;
         for (int j = lane; j < nv; j += 64) {
@@ -1032,32 +1039,28 @@ hipError_t launch_int_stats(const int32_t* a, int64_t n, unsigned long long* out
     return hipGetLastError();
 }
 
-hipError_t launch_col_block(const int32_t* rank, const int64_t* toff, int64_t nadm,
-                            int32_t* col_block, hipStream_t st) {
+hipError_t launch_col_meta(const int4* adm, const int32_t* rank, const int64_t* toff,
+                           const int64_t* voff, int64_t nadm, int4* meta, hipStream_t st) {
     if (nadm == 0) return hipSuccess;
-    hipLaunchKernelGGL(col_block_kernel, dim3((unsigned)((nadm + 255) / 256)), dim3(256), 0, st,
-                       rank, toff, nadm, col_block);
+    hipLaunchKernelGGL(col_meta_kernel, dim3((unsigned)((nadm + 255) / 256)), dim3(256), 0, st,
+                       adm, rank, toff, voff, nadm, meta);
     return hipGetLastError();
 }
 
-hipError_t launch_far_phase1(const int4* adm, const int32_t* col_block, const int64_t* voff,
-                             const int64_t* toff, int64_t ncols_total, const void* V,
+hipError_t launch_far_phase1(const int4* col_meta, int64_t ncols_total, const void* V,
                              void* vecpool, int64_t n, int smode, hipStream_t st) {
     if (ncols_total == 0) return hipSuccess;
     const int64_t nblk = (ncols_total + 3) / 4;  // 4 waves (columns) per workgroup
     if (nblk > 0x7fffffffll) return hipErrorInvalidValue;
     if (smode == 0)
         hipLaunchKernelGGL((far_phase1_kernel<double, double>), dim3((unsigned)nblk), dim3(256),
-                           0, st, adm, col_block, voff, toff, (const double*)V, (double*)vecpool,
-                           n, ncols_total);
+                           0, st, col_meta, (const double*)V, (double*)vecpool, n, ncols_total);
     else if (smode == 1)
         hipLaunchKernelGGL((far_phase1_kernel<float, float>), dim3((unsigned)nblk), dim3(256), 0,
-                           st, adm, col_block, voff, toff, (const float*)V, (float*)vecpool, n,
-                           ncols_total);
+                           st, col_meta, (const float*)V, (float*)vecpool, n, ncols_total);
     else
         hipLaunchKernelGGL((far_phase1_kernel<uint16_t, float>), dim3((unsigned)nblk), dim3(256),
-                           0, st, adm, col_block, voff, toff, (const uint16_t*)V,
-                           (float*)vecpool, n, ncols_total);
+                           0, st, col_meta, (const uint16_t*)V, (float*)vecpool, n, ncols_total);
     return hipGetLastError();
 }
 
