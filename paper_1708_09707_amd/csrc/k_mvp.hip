@@ -505,7 +505,8 @@ __global__ void col_meta_kernel(const int4* __restrict__ adm, const int32_t* __r
 }
 
 // phase 1: t_b[l] = sum_j V_b[j, l] x[slo + j]; one wave per column of the
-// flattened list of all factor columns
+// flattened list of all factor columns (lane j: 16-byte vectors j, j + 64,
+// ... in order, then a DPP sum over the wave)
 template <typename T>
 __device__ __forceinline__ void load_x16(const T* p, T* o);
 template <>
@@ -521,6 +522,40 @@ __device__ __forceinline__ void load_x16<double>(const double* p, double* o) {
     const f64x2 v = *(const f64x2*)p;
     o[0] = v[0];
     o[1] = v[1];
+}
+
+// sum over the wave with DPP moves (in registers, no LDS round trips): pairs,
+// quads, half rows, rows, then (row 0 + row 1) + (row 2 + row 3) read from
+// one lane of each row; the result is the same on every lane
+template <int CTRL>
+__device__ __forceinline__ float p1_dpp(float v) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double p1_dpp(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ float p1_lane(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double p1_lane(double v, int l) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T p1_wave_total(T v) {
+    v += p1_dpp<0xB1>(v);   // quad_perm [1,0,3,2]: pairs
+    v += p1_dpp<0x4E>(v);   // quad_perm [2,3,0,1]: quads
+    v += p1_dpp<0x141>(v);  // row_half_mirror: eight lanes
+    v += p1_dpp<0x140>(v);  // row_mirror: sixteen lanes
+    return (p1_lane(v, 0) + p1_lane(v, 16)) + (p1_lane(v, 32) + p1_lane(v, 48));
 }
 
 template <typename S, typename T>
@@ -570,8 +605,8 @@ __global__ __launch_bounds__(256) void far_phase1_kernel(const int4* __restrict_
             }
         }
     }
-    acc = wave_sum(acc);
-    if (lane == 0) vec[n + k] = acc;
+    const T tot = p1_wave_total(acc);
+    if (lane == 0) vec[n + k] = tot;
 }
 
 // phase 2: one workgroup per row tile (or per row pass of a tile, the split
