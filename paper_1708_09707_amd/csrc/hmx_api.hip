@@ -279,7 +279,7 @@ struct hmx_hmatrix_s {
     DevBuf adm, adm_level, adm_ids, dense, dense_level;
     DevBuf tile_of_point, tile_lo;
     DevBuf rank, steps, voff, toff, V;
-    DevBuf pieces, upool, npool, widx, tile_meta, vecpool, col_block;
+    DevBuf pieces, upool, npool, widx, tile_meta, vecpool, col_meta;
     int64_t upool_entries = 0, npool_entries = 0, ncols_total = 0;
     hmx_stats stats{};
     // matvec phase tracing (hmx_profile_begin / end)
@@ -300,7 +300,7 @@ struct hmx_hmatrix_s {
                                &dense,     &dense_level,   &tile_of_point, &tile_lo, &rank,
                                &steps,     &voff,          &toff,    &V,         &pieces,
                                &upool,     &npool,         &widx,    &tile_meta, &vecpool,
-                               &col_block};
+                               &col_meta};
         int64_t s = 0;
         for (auto* b : all) s += (int64_t)b->bytes;
         return s;
@@ -1165,9 +1165,9 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
         h->sum_rank = scan(h->toff.as<int64_t>(), h->n_adm);
     }
     alloc(h->vecpool, (size_t)(n + h->sum_rank) * esz, "vector pool");
-    alloc(h->col_block, (size_t)std::max<int64_t>(h->sum_rank, 1) * sizeof(int4), "column map");
+    alloc(h->col_meta, (size_t)std::max<int64_t>(h->sum_rank, 1) * sizeof(int4), "column map");
     check(launch_col_meta(h->adm.as<int4>(), h->rank.as<int32_t>(), h->toff.as<int64_t>(),
-                          h->voff.as<int64_t>(), h->n_adm, h->col_block.as<int4>(), st),
+                          h->voff.as<int64_t>(), h->n_adm, h->col_meta.as<int4>(), st),
           "column map");
     S.phase_ms[4] += ms_since(t0);
     t0 = clk::now();
@@ -1483,7 +1483,7 @@ hipError_t matvec_launch(hmx_hmatrix_s* h, const void* x, void* z, double alpha,
     if (e == hipSuccess) e = launch_gather_x(x, h->perm.as<int32_t>(), h->n, h->vecpool.p, f64, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
     if (e == hipSuccess)
-        e = launch_far_phase1(h->col_block.as<int4>(), h->sum_rank, h->V.p, h->vecpool.p, h->n,
+        e = launch_far_phase1(h->col_meta.as<int4>(), h->sum_rank, h->V.p, h->vecpool.p, h->n,
                               h->smode, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
     if (e == hipSuccess)
