@@ -59,6 +59,7 @@ def lib():
         L.hmxo_partition.argtypes = [P, i64, i32, i32, f64, i64, P, P, i64, P, P, P, P]
         L.hmxo_aca.argtypes = [P, i64, i32, i32, f64, i64, i64, i64, i64, i32, f64, f64, f64,
                                i32, i32, P, P, P, P]
+        L.hmxo_aca_traced.argtypes = L.hmxo_aca.argtypes + [P]
         L.hmxo_hmvp.argtypes = [P, i64, i32, i32, f64, i32, f64, i32, f64, f64, f64, i32, f64,
                                 f64, f64, P, P, i64, P, P]
         L.hmxo_dense_matvec.argtypes = [P, i64, i32, i32, f64, f64, P, P, i64, P]
@@ -189,7 +190,10 @@ def partition(soa, leaf, eta):
 
 
 def aca(soa, kind, p0, tlo, thi, slo, shi, kmax, eps, aca_eta=0.0, eps0=1e-14, fixed=False,
-        r_start=0):
+        r_start=0, want_trace=False):
+    """Algorithm 2 on one block: (U, V, rank, steps), plus the per-step trace
+    (rank x 5: row pivot, column, row-pivot gap, stop-test ratio, next column
+    gap) when want_trace."""
     soa = _f64(soa)
     d, n = soa.shape
     m, nc = thi - tlo, shi - slo
@@ -197,12 +201,16 @@ def aca(soa, kind, p0, tlo, thi, slo, shi, kmax, eps, aca_eta=0.0, eps0=1e-14, f
     V = np.zeros((kmax, nc))
     rk = C.c_int32(0)
     st = C.c_int32(0)
-    rc = lib().hmxo_aca(_p(soa), n, d, kind_of(kind), float(p0), tlo, thi, slo, shi, int(kmax),
-                        float(eps), float(aca_eta), float(eps0), int(bool(fixed)), int(r_start),
-                        _p(U), _p(V), C.byref(rk), C.byref(st))
+    tr = np.zeros((kmax, 5)) if want_trace else None
+    rc = lib().hmxo_aca_traced(_p(soa), n, d, kind_of(kind), float(p0), tlo, thi, slo, shi,
+                               int(kmax), float(eps), float(aca_eta), float(eps0),
+                               int(bool(fixed)), int(r_start), _p(U), _p(V), C.byref(rk),
+                               C.byref(st), _p(tr))
     assert rc == 0
     r = rk.value
     # stored column-major m x kmax == row-major (kmax, m)
+    if want_trace:
+        return U[:r].T.copy(), V[:r].T.copy(), r, st.value, tr[:r].copy()
     return U[:r].T.copy(), V[:r].T.copy(), r, st.value
 
 

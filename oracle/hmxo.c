@@ -473,6 +473,34 @@ int hmxo_aca(const double* soa, int64_t n, int32_t d, int32_t kind, double p0, i
              double eps0, int32_t fixed, int32_t r_start, double* U, double* V, int32_t* rank,
              int32_t* steps)
 {
+    return hmxo_aca_traced(soa, n, d, kind, p0, tlo, thi, slo, shi, kmax, eps, aca_eta, eps0,
+                           fixed, r_start, U, V, rank, steps, NULL);
+}
+
+/* relative gap between the largest and the second largest |w_k| over the
+ * unmarked k (1 when fewer than two remain): how close an argmax was to a tie */
+static double pivot_margin(const double* w, const char* used, int64_t len)
+{
+    double b1 = -1.0, b2 = -1.0;
+    for (int64_t k = 0; k < len; ++k) {
+        if (used[k]) continue;
+        const double a = fabs(w[k]);
+        if (a > b1) {
+            b2 = b1;
+            b1 = a;
+        } else if (a > b2) {
+            b2 = a;
+        }
+    }
+    if (b2 < 0.0 || !(b1 > 0.0)) return 1.0;
+    return (b1 - b2) / b1;
+}
+
+int hmxo_aca_traced(const double* soa, int64_t n, int32_t d, int32_t kind, double p0,
+                    int64_t tlo, int64_t thi, int64_t slo, int64_t shi, int32_t kmax, double eps,
+                    double aca_eta, double eps0, int32_t fixed, int32_t r_start, double* U,
+                    double* V, int32_t* rank, int32_t* steps, double* trace)
+{
     const int64_t m = thi - tlo, nc = shi - slo;
     if (m < 1 || nc < 1 || kmax < 1) return -1;
     int64_t R = kmax;
@@ -529,6 +557,13 @@ int hmxo_aca(const double* soa, int64_t n, int32_t d, int32_t kind, double p0, i
             j = q;
             continue;
         }
+        if (trace) {
+            trace[5 * r + 0] = (double)ip;
+            trace[5 * r + 1] = (double)j;
+            trace[5 * r + 2] = pivot_margin(uh, used_r, m);
+            trace[5 * r + 3] = 0.0;
+            trace[5 * r + 4] = 1.0;
+        }
         const double piv = uh[ip];
         for (int64_t i = 0; i < m; ++i) U[r * m + i] = uh[i] / piv;
         /* residual row v = A[i_r, :]^T - sum_l (u_l)_{i_r} v_l */
@@ -549,6 +584,10 @@ int hmxo_aca(const double* soa, int64_t n, int32_t d, int32_t kind, double p0, i
             cross += du * dv;
         }
         S2 += 2.0 * cross + nu2 * nv2;
+        if (trace) {
+            trace[5 * r + 3] = sqrt(nu2 * nv2) / (tol * sqrt(S2));
+            trace[5 * r + 4] = pivot_margin(V + r * nc, used_c, nc);
+        }
         ++r;
         if (!fixed && !one_shot && sqrt(nu2 * nv2) <= tol * sqrt(S2)) break;
         /* next column pivot: largest |(v_r)_j| over unused columns */

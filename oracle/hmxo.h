@@ -71,6 +71,18 @@ int hmxo_aca(const double* soa, int64_t n, int32_t d, int32_t kind, double p0,
              int64_t tlo, int64_t thi, int64_t slo, int64_t shi, int32_t kmax,
              double eps, double aca_eta, double eps0, int32_t fixed, int32_t r_start,
              double* U, double* V, int32_t* rank, int32_t* steps);
+/* hmxo_aca with a trace (optional, kmax x 5 doubles): for accepted step r,
+ * the row pivot i_r and the column j_r (block-local indices), the relative
+ * gap between the largest and second largest |residual| over unused rows
+ * at the row pivot choice, the stopping test's ratio
+ * |u_r| |v_r| / (eps (1 - aca_eta) / (1 + eps) |S_r|_F) (the test passes at
+ * <= 1), and the relative gap of the next column pivot's choice.  Used to
+ * show that a rank another implementation finds differently was decided by
+ * a near-tie. */
+int hmxo_aca_traced(const double* soa, int64_t n, int32_t d, int32_t kind, double p0,
+                    int64_t tlo, int64_t thi, int64_t slo, int64_t shi, int32_t kmax, double eps,
+                    double aca_eta, double eps0, int32_t fixed, int32_t r_start, double* U,
+                    double* V, int32_t* rank, int32_t* steps, double* trace);
 
 /* Algorithm 3 in flat form (no-storage mode: every block is built, applied and
  * discarded):  z = alpha * (H x + sigma2 x) + beta * z, vectors in the

@@ -234,3 +234,55 @@ def test_cg_dense_matches_cholesky(orc):
     assert rc1 == 1 and it1 == 1
     x0, rc0, it0, _ = orc.cg_dense(pts, np.zeros(600), "matern32", 0.1, 1e-2)
     assert rc0 == 0 and it0 == 0 and not x0.any()
+
+
+@pytest.mark.parametrize("lo,hi", [(0, 1500), (0, 1), (700, 701), (333, 1111), (1499, 1500),
+                                   (64, 128), (37, 1300)])
+def test_hmvp_rows_equals_full_hmvp_slice(orc, lo, hi):
+    """The row-range form of the H-matrix-vector product (Algorithm 3
+    restricted to Morton rows [lo, hi), every block meeting the range built
+    by Algorithm 2 and applied once) equals the Morton-ordered slice of the
+    full product; ranges that cut through leaf clusters included.  The full
+    product itself is pinned to the dense product above, and the slice is
+    checked against the dense rows here as well."""
+    n, leaf, eps = 1500, 32, 1e-7
+    p = synth.uniform_points(n, 2, 101)
+    x = synth.normal_vector(n, 102)
+    z_full, _, _ = orc.hmvp(p, x, "gaussian", 0.05, leaf, 1.5, 48, eps)
+    codes, perm, _ = orc.order(p)
+    zr, perm_r, info = orc.hmvp_rows(p, x, "gaussian", 0.05, leaf, 1.5, 48, eps, lo, hi)
+    assert np.array_equal(perm_r, perm)
+    want = z_full[perm[lo:hi]]
+    assert zr.shape == (hi - lo,)
+    assert np.max(np.abs(zr - want)) <= 1e-14 * max(1.0, np.max(np.abs(want)))
+    zd = orc.dense_matvec(p, x, "gaussian", 0.05, rows=perm[lo:hi])
+    assert np.linalg.norm(zr - zd) <= 10 * eps * np.linalg.norm(zd) + 1e-14
+    assert info["blocks"] > 0 and info["entries"] > 0
+
+
+def test_hmvp_rows_invalid_ranges(orc):
+    p = synth.uniform_points(100, 2, 103)
+    x = synth.normal_vector(100, 104)
+    for lo, hi in [(5, 5), (-1, 10), (0, 101), (50, 20)]:
+        with pytest.raises(ValueError):
+            orc.hmvp_rows(p, x, "gaussian", 0.05, 16, 1.5, 16, 1e-6, lo, hi)
+
+
+def test_aca_trace_describes_the_run(orc):
+    """The traced ACA returns the same factors as the plain call, and its
+    trace is consistent with them: u_r is 1 at its pivot row, the stop-test
+    ratio exceeds 1 before the last step and not at it, and every recorded
+    gap lies in [0, 1]."""
+    p = synth.uniform_points(2000, 2, 31)
+    _, _, soa = orc.order(p)
+    adm, _, _ = orc.partition(soa, 64, 1.5)
+    b = adm[len(adm) // 3]
+    U0, V0, r0, s0 = orc.aca(soa, "gaussian", 0.05, *b[:4], 32, 1e-6)
+    U, V, r, s, tr = orc.aca(soa, "gaussian", 0.05, *b[:4], 32, 1e-6, want_trace=True)
+    assert r == r0 and s == s0 and np.array_equal(U, U0) and np.array_equal(V, V0)
+    assert r >= 3
+    for q in range(r):
+        assert U[int(tr[q, 0]), q] == 1.0
+    assert np.all(tr[: r - 1, 3] > 1.0) and tr[r - 1, 3] <= 1.0
+    assert np.all((tr[:, 2] >= 0) & (tr[:, 2] <= 1)) and np.all((tr[:, 4] >= 0) & (tr[:, 4] <= 1))
+    assert len(set(tr[:, 1].astype(int))) == r  # distinct columns
