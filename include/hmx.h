@@ -394,6 +394,20 @@ hmx_status hmx_mlp_train(hmx_mlp m, const float* X, const float* y, int64_t n,
 hmx_status hmx_block_features(hmx_hmatrix h, float* features, float* ranks, int64_t* n_adm,
                               void* stream);
 
+/* The rank predictor's in-build inference on this handle's admissible leaves
+ * (the fused kernel HMX_RANK_LEARNED runs before the ACA: features, input
+ * standardisation, the four layers, the target clamp), with predictor m:
+ *   pred   : device, n_adm floats, the raw network output per leaf (canonical
+ *            order), or NULL;
+ *   target : device, n_adm int32, clamp(ceil(pred) + 1, 1, min(max_rank, m,
+ *            n)) with the handle's max_rank (a NaN output gives the upper
+ *            bound), or NULL; at least one of the two is needed.
+ * *n_adm (host) gives the capacity in leaves and receives the count; a too
+ * small capacity returns INVALID_ARG.  Batched handles: UNSUPPORTED.
+ * Asynchronous; allocates nothing. */
+hmx_status hmx_rank_predict(hmx_hmatrix h, hmx_mlp m, float* pred, int32_t* target,
+                            int64_t* n_adm, void* stream);
+
 /* Release every device buffer of the handle (synchronises the device).  The
  * buffers return to the library's device-block cache, which later builds
  * reuse; hmx_trim gives the cached blocks back to the driver. */

@@ -2341,6 +2341,33 @@ hmx_status hmx_block_features(hmx_hmatrix h, float* features, float* ranks, int6
     });
 }
 
+hmx_status hmx_rank_predict(hmx_hmatrix h, hmx_mlp m, float* pred, int32_t* target,
+                            int64_t* n_adm, void* stream) {
+    if (!h || !m || !n_adm || (h->n_adm > 0 && !pred && !target)) {
+        set_err("invalid argument to hmx_rank_predict");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (h->batched) {
+        set_err("batched handle: predictions belong to the individual problems");
+        return HMX_ERR_UNSUPPORTED;
+    }
+    if (*n_adm < h->n_adm) {
+        set_err("capacity %lld below %lld admissible leaves", (long long)*n_adm,
+                (long long)h->n_adm);
+        *n_adm = h->n_adm;
+        return HMX_ERR_INVALID_ARG;
+    }
+    *n_adm = h->n_adm;
+    return guarded([&] {
+        check(launch_rank_predict(h->adm.as<int4>(), h->adm_ids.as<int2>(), h->n_adm,
+                                  h->bmin.as<double>(), h->bmax.as<double>(), h->d,
+                                  kernel_length(h->kern), m->w.as<float>(), m->mean.as<float>(),
+                                  m->scale.as<float>(), h->prm.max_rank, pred, target,
+                                  (hipStream_t)stream),
+              "rank prediction");
+    });
+}
+
 hmx_status hmx_destroy(hmx_hmatrix h) {
     if (!h) return HMX_OK;
     (void)hipDeviceSynchronize();

@@ -35,7 +35,8 @@ EXPORTS = ["hmx_params_default", "hmx_build", "hmx_matvec", "hmx_cg_solve", "hmx
            "hmx_mlp_set_params", "hmx_mlp_get_params", "hmx_mlp_fit_normalization",
            "hmx_mlp_forward", "hmx_mlp_loss_grad", "hmx_mlp_adam", "hmx_mlp_train",
            "hmx_block_features", "hmx_build_batched", "hmx_get_batch", "hmx_matvec_graph",
-           "hmx_graph_launch", "hmx_graph_destroy", "hmx_autotune", "hmx_set_tile_config"]
+           "hmx_graph_launch", "hmx_graph_destroy", "hmx_autotune", "hmx_set_tile_config",
+           "hmx_rank_predict"]
 HMX_TILE_CONFIGS = 15
 
 
@@ -122,6 +123,7 @@ def lib():
         L.hmx_mlp_adam.argtypes = [P, P, f64, f64, f64, f64, P]
         L.hmx_mlp_train.argtypes = [P, P, P, i64, P, i64, i32, f64, f64, P, P]
         L.hmx_block_features.argtypes = [P, P, P, C.POINTER(i64), P]
+        L.hmx_rank_predict.argtypes = [P, P, P, P, C.POINTER(i64), P]
         L.hmx_build_batched.argtypes = [i32, P, C.c_int, P, P, P, C.POINTER(hmx_params), P,
                                         C.POINTER(P)]
         L.hmx_get_batch.argtypes = [P, C.POINTER(i32), P]
@@ -199,17 +201,31 @@ def hmx_build(points, kernel: hmx_kernel, params: hmx_params, stream=None):
     return h
 
 
+def _check_vectors(h, *vecs):
+    """The C ABI takes bare device pointers: every vector must be a
+    contiguous device tensor of exactly the handle's n entries, all of one
+    dtype and on one device (a short vector would be read and written past
+    its end by the gather and scatter kernels)."""
+    n = hmx_get_stats(h).n
+    t0 = vecs[0]
+    for t in vecs:
+        if not (t.is_cuda and t.is_contiguous()):
+            raise ValueError("vectors must be contiguous device tensors")
+        if t.dim() != 1 or t.numel() != n:
+            raise ValueError("vectors must have shape (%d,), got %s" % (n, tuple(t.shape)))
+        if t.dtype != t0.dtype or t.device != t0.device:
+            raise ValueError("vectors must share one dtype and device")
+
+
 def hmx_matvec(h, x, z, alpha=1.0, beta=0.0, stream=None):
-    if not (x.is_cuda and z.is_cuda and x.is_contiguous() and z.is_contiguous()):
-        raise ValueError("x and z must be contiguous device tensors")
+    _check_vectors(h, x, z)
     _check(lib().hmx_matvec(h, C.c_void_p(x.data_ptr()), C.c_void_p(z.data_ptr()), _dtype_of(x),
                             float(alpha), float(beta), _stream(stream)))
 
 
 def hmx_cg_solve(h, b, x, rel_tol=1e-6, max_iter=1000, stream=None, raise_on_fail=True):
     """Solve (H + sigma2 I) x = b by CG.  Returns (status, iters, rel_res, true_rel_res)."""
-    if not (b.is_cuda and x.is_cuda and b.is_contiguous() and x.is_contiguous()):
-        raise ValueError("b and x must be contiguous device tensors")
+    _check_vectors(h, b, x)
     it, rr, tr = C.c_int32(0), C.c_double(0), C.c_double(0)
     s = lib().hmx_cg_solve(h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
                            float(rel_tol), int(max_iter), _stream(stream), C.byref(it),
@@ -398,10 +414,22 @@ def hmx_block_features(h, with_ranks=True, stream=None):
     return F[: na.value], (y[: na.value] if y is not None else None)
 
 
+def hmx_rank_predict(h, mlp, stream=None):
+    """The fused in-build inference on the handle's admissible leaves:
+    (raw predictions (n_adm,) float32, targets (n_adm,) int32) device tensors."""
+    import torch
+    s = hmx_get_stats(h)
+    na = C.c_int64(s.n_adm)
+    pred = torch.empty(max(s.n_adm, 1), dtype=torch.float32, device="cuda")
+    tgt = torch.empty(max(s.n_adm, 1), dtype=torch.int32, device="cuda")
+    m = mlp.handle if isinstance(mlp, RankMLP) else mlp
+    _check(lib().hmx_rank_predict(h, m, _ptr(pred), _ptr(tgt), C.byref(na), _stream(stream)))
+    return pred[: na.value], tgt[: na.value]
+
+
 def hmx_matvec_graph(h, x, z, alpha=1.0, beta=0.0, reps=1):
     """Capture reps matvecs into a HIP graph; returns the graph handle."""
-    if not (x.is_cuda and z.is_cuda and x.is_contiguous() and z.is_contiguous()):
-        raise ValueError("x and z must be contiguous device tensors")
+    _check_vectors(h, x, z)
     g = C.c_void_p()
     _check(lib().hmx_matvec_graph(h, C.c_void_p(x.data_ptr()), C.c_void_p(z.data_ptr()),
                                   _dtype_of(x), float(alpha), float(beta), int(reps),

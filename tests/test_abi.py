@@ -100,3 +100,46 @@ def test_validation_before_device_work():
     assert not h.value
     assert L.hmx_matvec(None, dummy, dummy, 1, 1.0, 0.0, None) == 1
     assert L.hmx_destroy(None) == 0
+
+
+class _Vec:
+    """Stands in for a device tensor in the binding's host-side checks."""
+
+    def __init__(self, n, dtype="float32", cuda=True, contiguous=True, dim=1, device="cuda:0"):
+        self._n, self.dtype, self.is_cuda, self._c = n, dtype, cuda, contiguous
+        self.shape = (n,) if dim == 1 else (n, 1)
+        self.device = device
+
+    def dim(self):
+        return len(self.shape)
+
+    def numel(self):
+        return self._n
+
+    def is_contiguous(self):
+        return self._c
+
+    def data_ptr(self):
+        raise AssertionError("a rejected vector must never reach the C ABI")
+
+
+def test_binding_rejects_vectors_of_the_wrong_size(monkeypatch):
+    """x, z and b go to the C ABI as bare pointers: the binding checks their
+    length against the handle's n (a short vector would be read and written
+    past its end), their dtype and device, before any call."""
+    from paper_1708_09707_amd import hmx
+
+    class _St:
+        n = 1000
+
+    monkeypatch.setattr(hmx, "hmx_get_stats", lambda h: _St())
+    h = C.c_void_p(1)
+    good = _Vec(1000)
+    bad = [_Vec(999), _Vec(1001), _Vec(1000, dtype="float64"), _Vec(1000, cuda=False),
+           _Vec(1000, contiguous=False), _Vec(1000, dim=2), _Vec(1000, device="cuda:1")]
+    for b in bad:
+        for f in (lambda: hmx.hmx_matvec(h, b, good), lambda: hmx.hmx_matvec(h, good, b),
+                  lambda: hmx.hmx_cg_solve(h, b, good), lambda: hmx.hmx_cg_solve(h, good, b),
+                  lambda: hmx.hmx_matvec_graph(h, b, good)):
+            with pytest.raises(ValueError):
+                f()

@@ -4,6 +4,7 @@ sampled rows of each block, and the matvec."""
 import numpy as np
 import pytest
 
+import aca_ties
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -42,30 +43,43 @@ def test_split_blocks_match_oracle(H, orc, dtype):
     g = synth.rng(1718)
     picks = big if len(big) <= 24 else np.sort(g.choice(big, 24, replace=False))
     eps0 = 1e-14 if dtype == "f64" else 1e-7
-    agree, errs = 0, []
+    agree, errs, errs_o = 0, [], []
     for q in picks:
         b = adm[q]
         m, nn = b[1] - b[0], b[3] - b[2]
-        _, _, ro, _ = orc.aca(soa, "gaussian", p0, *b[:4], kmax, eps, eps0=eps0)
+        Uo, Vo, ro, _, tr = orc.aca(soa, "gaussian", p0, *b[:4], kmax, eps, eps0=eps0,
+                                    want_trace=True)
         agree += int(ro == ranks[q])
         U, V, r = H.hmx_get_factors(hm.h, int(q), m, nn, kmax)
         rows = np.sort(g.choice(m, 128, replace=False))
         A = np.stack([orc.dense_block(soa, "gaussian", p0, b[0] + i, b[0] + i + 1, b[2], b[3])[0]
                       for i in rows])
         err = np.linalg.norm(A - U[rows] @ V.T) / np.linalg.norm(A)
+        err_o = np.linalg.norm(A - Uo[rows] @ Vo.T) / np.linalg.norm(A)
         errs.append(err)
-        assert abs(int(r) - int(ro)) <= (2 if dtype == "f64" else 6), (q, r, ro)
+        errs_o.append(err_o)
         if dtype == "f64":
             assert err <= 10 * eps, (q, r, ro, err)
+            if r != ro:
+                # the same algorithm in the same precision parts ways only at
+                # a near tie of one of its decisions
+                s = aca_ties.first_divergence(U, V, Uo, Vo)
+                what, gap = aca_ties.explain(tr, s, r, ro, 1e-6)
+                print("  block %d (%dx%d): GPU rank %d, oracle %d, part at step %d: %s gap "
+                      "%.2e" % (q, m, nn, r, ro, s, what, gap))
+                assert gap <= 1e-6, (q, r, ro, s, what, gap)
+        else:
+            # FP32 residuals: the stopping test (an estimate from the last
+            # term) can fire a step before or after the FP64 oracle's, so the
+            # bound is the stated 10 eps or the oracle's own error on the same
+            # rows, whichever is larger, with FP32 rounding on top
+            assert err <= max(10 * eps, 2.0 * err_o) + 1e-6, (q, r, ro, err, err_o)
     errs = np.array(errs)
-    print("rank agreement %d / %d, sampled block errors: median %.3e, worst %.3e"
-          % (agree, len(picks), np.median(errs), errs.max()))
-    if dtype == "f64":
-        assert agree >= 0.8 * len(picks)
-    else:
-        # the stopping test estimates the error from the last term; with FP32
-        # residuals a large block can stop a step before the FP64 oracle
-        assert np.median(errs) <= 10 * eps and errs.max() <= 50 * eps
+    print("rank agreement %d / %d, sampled block errors: median %.3e, worst %.3e (oracle's own: "
+          "median %.3e, worst %.3e)" % (agree, len(picks), np.median(errs), errs.max(),
+                                         np.median(errs_o), np.max(errs_o)))
+    if dtype == "f32":
+        assert np.median(errs) <= 10 * eps
     x = synth.normal_vector(n, 1719)
     tdt = torch.float64 if dtype == "f64" else torch.float32
     z = hm.matvec(_dev(x).to(tdt)).double().cpu().numpy()

@@ -1,0 +1,102 @@
+"""The launch configurations the benchmark times, at their full sizes.
+
+* N = 2^20 uniform points in [0,1]^2, Gaussian p0 = 0.01, leaf 256, eta 1.5,
+  learned rank sizing, ACA eps 3e-3, BF16 factors with BF16 or FP32 near
+  field, FP32 arithmetic: every row-tile configuration of the autotuner
+  (one workgroup per tile, the persistent grid, one workgroup per row pass)
+  gives the default configuration's product within FP32 summation-order
+  rounding, and the product meets e_rel <= 10 eps + 4 u_BF16 against the
+  oracle's FP64 dense product on 4096 sampled rows.
+* N = 2^22 uniform points in [0,1]^3, leaf 64, eta 1.5: Morton codes,
+  permutation and both leaf lists bit for bit against the oracle.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def H():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1708_09707_amd import hmx
+    hmx.lib()
+    return hmx
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def n1m():
+    n = 1 << 20
+    pts = synth.uniform_points(n, 2, 21, dtype=np.float32)
+    x = synth.normal_vector(n, 2200, dtype=np.float32)
+    return n, pts, x
+
+
+@pytest.fixture(scope="module")
+def n1m_ref(orc, n1m):
+    n, pts, x = n1m
+    rows = synth.sample_rows(n, 4096, 2201)
+    print("oracle: FP64 dense product on %d sampled rows of N = %d" % (len(rows), n), flush=True)
+    zr = orc.dense_matvec(pts.astype(np.float64), x.astype(np.float64), "gaussian", 0.01,
+                          rows=rows)
+    return rows, zr
+
+
+@pytest.mark.parametrize("near", ["bf16", "f32"])
+def test_bench_config_every_tile_config(H, orc, n1m, n1m_ref, near):
+    n, pts, x = n1m
+    rows, zr = n1m_ref
+    eps = 3e-3
+    w = np.zeros(8961, np.float32)
+    w[-1] = 6.0  # a constant prediction: targets below many ranks (overflow path)
+    mlp = H.RankMLP(w)
+    print("build: N=%d BF16 factors, %s near field, learned sizing, eps %g" % (n, near, eps),
+          flush=True)
+    hm = H.HMatrix(_dev(pts), "gaussian", 0.01, compute_dtype="f32", storage_dtype="bf16",
+                   near_dtype=near, leaf_size=256, eta=1.5, aca_eps=eps, max_rank=64,
+                   rank_mode="learned", mlp=mlp)
+    st = hm.stats()
+    assert st.entry_bytes == 2 and st.near_entry_bytes == (2 if near == "bf16" else 4)
+    xd = _dev(x)
+    H.hmx_set_tile_config(hm.h, -1)
+    ref = hm.matvec(xd).double()
+    tol = 10 * eps + 4 * 2.0 ** -9
+    for c in range(H.HMX_TILE_CONFIGS):
+        H.hmx_set_tile_config(hm.h, c)
+        z = hm.matvec(xd).double()
+        dev = (torch.linalg.norm(z - ref) / torch.linalg.norm(ref)).item()
+        err = np.linalg.norm(z.cpu().numpy()[rows] - zr) / np.linalg.norm(zr)
+        print("config %2d: vs default %.2e, vs oracle dense rows %.3e" % (c, dev, err),
+              flush=True)
+        assert dev <= 1e-5, (c, dev)
+        assert err <= tol, (c, err)
+    hm.close()
+    mlp.close()
+
+
+def test_partition_bit_exact_n4m_3d(H, orc):
+    n, leaf, eta = 1 << 22, 64, 1.5
+    pts = synth.uniform_points(n, 3, 51, dtype=np.float32)
+    print("build: N=%d d=3 leaf %d (partition and ACA only)" % (n, leaf), flush=True)
+    hm = H.HMatrix(_dev(pts), "gaussian", 0.0145, compute_dtype="f32", leaf_size=leaf, eta=eta,
+                   aca_eps=1e-2, max_rank=16, aca_only=1)
+    part = hm.partition()
+    hm.close()
+    print("oracle: order and partition", flush=True)
+    codes, perm, soa = orc.order(pts.astype(np.float64))
+    assert np.array_equal(part["codes"], codes)
+    assert np.array_equal(part["perm"], perm)
+    adm, den, ls = orc.partition(soa, leaf, eta)
+    print("%d admissible and %d dense leaves, %d levels" % (len(adm), len(den), len(ls)))
+    assert np.array_equal(part["adm"], adm)
+    assert np.array_equal(part["dense"], den)
+    assert np.array_equal(part["level_sizes"], ls)

@@ -327,3 +327,51 @@ def test_trained_predictor_gain(H, orc):
     assert l["cap"] <= 0.6 * a["cap"]
     assert l["fb"] <= 0.15 * l["n_adm"]
     mlp.close()
+
+
+@pytest.mark.parametrize("d,kernel,p0", [(2, "gaussian", 0.01), (3, "matern32", 0.15)])
+def test_fused_inference_matches_oracle(H, orc, d, kernel, p0):
+    """The hand-written in-build inference (features, standardisation, four
+    layers, target clamp in one kernel) against the oracle's FP64 forward on
+    the oracle's features of the same partition, with He-initialised weights,
+    random biases and a non-trivial standardisation: a transposed weight
+    index, a wrong bias or standardisation fails the comparison."""
+    n, kmax = 30000, 48
+    pts = synth.uniform_points(n, d, 8100 + d, dtype=np.float32)
+    hm = H.HMatrix(_dev(pts), kernel, p0, compute_dtype="f32", leaf_size=64, eta=1.5,
+                   aca_eps=1e-4, max_rank=kmax, aca_only=1)
+    w = synth.mlp_init_params(8200 + d).astype(np.float64)
+    g = synth.rng(8300 + d)
+    # random biases (the He initialisation leaves them zero)
+    offs = np.cumsum([0] + [a * b + b for a, b in zip((8, 64, 64, 64), (64, 64, 64, 1))])
+    for lay, (fi, fo) in enumerate(zip((8, 64, 64, 64), (64, 64, 64, 1))):
+        w[offs[lay] + fi * fo: offs[lay + 1]] = 0.3 * g.standard_normal(fo)
+    w[-1] = 6.0  # centre the outputs where the target clamp is active
+    w = w.astype(np.float32)
+    part = hm.partition()
+    ell = np.sqrt(p0) if kernel == "gaussian" else p0
+    Fo = _oracle_features(orc, pts.astype(np.float64), part["adm"], ell).astype(np.float32)
+    mean = (Fo.mean(axis=0) + 0.1 * g.standard_normal(8)).astype(np.float32)
+    scale = (1.0 / (Fo.std(axis=0) + 0.5) * (0.8 + 0.4 * g.random(8))).astype(np.float32)
+    mlp = H.RankMLP(w)
+    mlp.set_params(w, mean, scale)
+    pred, tgt = H.hmx_rank_predict(hm.h, mlp)
+    pred, tgt = pred.cpu().numpy().astype(np.float64), tgt.cpu().numpy()
+    Xs = (Fo.astype(np.float64) - mean) * scale
+    o = orc.mlp_forward(w, Xs)
+    dev = np.abs(pred - o) / (1.0 + np.abs(o))
+    print("fused inference: %d blocks, outputs in [%.2f, %.2f], max dev %.3e"
+          % (len(o), o.min(), o.max(), dev.max()))
+    assert len(o) > 1000 and o.std() > 1.0
+    assert dev.max() <= 1e-5
+    adm = part["adm"]
+    R = np.minimum(np.minimum(adm[:, 1] - adm[:, 0], adm[:, 3] - adm[:, 2]), kmax)
+    want = np.clip(np.ceil(o) + 1, 1, R).astype(np.int32)
+    near_int = np.abs(o - np.round(o)) <= 1e-5 * (1.0 + np.abs(o))
+    print("targets: %d of %d differ, %d outputs within 1e-5 of an integer"
+          % (np.sum(tgt != want), len(o), near_int.sum()))
+    assert np.array_equal(tgt[~near_int], want[~near_int])
+    assert np.all(np.abs(tgt[near_int] - want[near_int]) <= 1)
+    assert np.all((tgt >= 1) & (tgt <= R))
+    hm.close()
+    mlp.close()

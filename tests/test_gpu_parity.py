@@ -8,6 +8,7 @@ the oracle's H-matrix-vector product within the same bound.
 import numpy as np
 import pytest
 
+import aca_ties
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -113,9 +114,11 @@ def test_small_workload_matvec(H, orc, dtype):
     s = hm.stats()
     assert s.n_adm == st["n_adm"] and s.n_dense == st["n_dense"]
     if dtype == "f64":
-        # same arithmetic up to summation order: ranks agree almost everywhere
-        assert np.mean(ranks == ranks_o) >= 0.95
-        assert np.abs(ranks.astype(int) - ranks_o).max() <= 2
+        # same arithmetic up to summation order: every rank difference must
+        # come from a decision of Algorithm 2 that was a near tie
+        _, _, soa = orc.order(pts)
+        explain_rank_mismatches(H, hm, orc, soa, hm.partition()["adm"], ranks, ranks_o,
+                                "gaussian", 0.1, 32, eps, 1e-14)
     assert s.near_entries == st["dense_entries"]
     hm.close()
 
@@ -140,6 +143,27 @@ def test_aca_block_errors(H, orc, dtype):
         s = np.linalg.svd(A, compute_uv=False)
         assert r >= 1 and np.linalg.norm(A - U @ V.T) >= np.sqrt((s[r:] ** 2).sum()) * (1 - 1e-6) - 1e-12
     hm.close()
+
+
+TIE_GAP = 1e-6  # a decision this close to a tie may go either way in FP64
+
+
+def explain_rank_mismatches(H, hm, orc, soa, adm, ranks, ranks_o, kind, p0, kmax, eps, eps0):
+    """Every block whose GPU rank differs from the oracle's: the first step
+    at which the factors part ways must be a near tie of the oracle's traced
+    decisions (row pivot, column pivot or stopping test within TIE_GAP)."""
+    bad = np.where(ranks != ranks_o)[0]
+    print("ranks: %d of %d blocks differ" % (len(bad), len(ranks)))
+    for q in bad:
+        b = adm[q]
+        m, nn = b[1] - b[0], b[3] - b[2]
+        Ug, Vg, rg = H.hmx_get_factors(hm.h, int(q), m, nn, kmax)
+        Uo, Vo, ro, _, tr = orc.aca(soa, kind, p0, *b[:4], kmax, eps, eps0=eps0, want_trace=True)
+        s = aca_ties.first_divergence(Ug, Vg, Uo, Vo)
+        what, gap = aca_ties.explain(tr, s, rg, ro, TIE_GAP)
+        print("  block %d (%dx%d): GPU rank %d, oracle %d, part at step %d: %s gap %.2e"
+              % (q, m, nn, rg, ro, s, what, gap))
+        assert gap <= TIE_GAP, (q, rg, ro, s, what, gap)
 
 
 def test_special_cases_reduce_to_dense(H, orc):
