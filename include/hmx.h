@@ -155,7 +155,19 @@ typedef struct {
                                 this many points run their ACA on many
                                 workgroups each (0: 262144, which also bounds
                                 the single-workgroup classes' LDS bitmasks) */
-    int32_t reserved;
+    int32_t symmetric_far;   /* 1: symmetric far field.  The kernel matrix is
+                                symmetric, and the partition is too: with every
+                                admissible leaf (tau, sigma) its mirror
+                                (sigma, tau) is a leaf.  Only the leaf with
+                                tau before sigma is approximated by the ACA;
+                                the mirror uses its factors transposed
+                                (A|sigma x tau ~ V U^T), which halves the
+                                ACA work and the stored factors and makes H
+                                exactly symmetric (as CG on (H + sigma2 I)
+                                assumes).  0: Algorithm 1's separate
+                                approximations of both leaves.  The matvec
+                                reads every stored factor twice (as a leaf's
+                                U and as its mirror's V) */
 } hmx_params;
 
 /* Statistics of a built H-matrix (host struct). */
@@ -168,9 +180,13 @@ typedef struct {
     int64_t sum_rank;         /* sum of ACA ranks */
     int32_t max_rank_used;
     int32_t entry_bytes;      /* bytes per stored factor entry (storage dtype) */
-    int64_t factor_entries;   /* sum_adm rank * (|tau| + |sigma|) */
-    int64_t u_entries;        /* sum_adm rank * |tau|   (U pool) */
-    int64_t v_entries;        /* sum_adm rank * |sigma| (V pool) */
+    int64_t factor_entries;   /* stored factor entries: sum over the approximated
+                                 leaves of rank * (|tau| + |sigma|) (with
+                                 symmetric_far only the primary leaves) */
+    int64_t u_entries;        /* sum over all admissible leaves of rank * |tau|
+                                 (the U rows phase 2 of a matvec reads) */
+    int64_t v_entries;        /* sum over all admissible leaves of rank * |sigma|
+                                 (the V rows phase 1 reads) */
     int64_t near_entries;     /* sum_dense |tau| * |sigma| */
     int64_t aca_columns;      /* ACA residual columns evaluated (incl. skipped) */
     int64_t aca_chunks;       /* chunks the admissible leaves were approximated in */

@@ -62,6 +62,8 @@ def lib():
         L.hmxo_aca_traced.argtypes = L.hmxo_aca.argtypes + [P]
         L.hmxo_hmvp.argtypes = [P, i64, i32, i32, f64, i32, f64, i32, f64, f64, f64, i32, f64,
                                 f64, f64, P, P, i64, P, P]
+        L.hmxo_hmvp_ex.argtypes = [P, i64, i32, i32, f64, i32, f64, i32, f64, f64, f64, i32, i32,
+                                   f64, f64, f64, P, P, i64, P, P]
         L.hmxo_dense_matvec.argtypes = [P, i64, i32, i32, f64, f64, P, P, i64, P]
         L.hmxo_dense_block.argtypes = [P, i64, i32, i32, f64, i64, i64, i64, i64, P]
         L.hmxo_hmvp_rows.argtypes = [P, i64, i32, i32, f64, i32, f64, i32, f64, f64, f64, i32,
@@ -223,8 +225,10 @@ def dense_block(soa, kind, p0, tlo, thi, slo, shi):
 
 
 def hmvp(pts, x, kind, p0, leaf, eta, kmax, eps, aca_eta=0.0, eps0=1e-14, fixed=False,
-         sigma2=0.0, alpha=1.0, beta=0.0, z=None, want_ranks=False):
-    """z = alpha (H x + sigma2 x) + beta z; returns (z, ranks or None, stats dict)."""
+         sigma2=0.0, alpha=1.0, beta=0.0, z=None, want_ranks=False, symmetric=False):
+    """z = alpha (H x + sigma2 x) + beta z; returns (z, ranks or None, stats dict).
+    symmetric: only the admissible leaf with tau before sigma is approximated,
+    its mirror applies the transposed factors."""
     pts = _f64(pts)
     n, d = pts.shape
     x = _f64(x)
@@ -235,10 +239,10 @@ def hmvp(pts, x, kind, p0, leaf, eta, kmax, eps, aca_eta=0.0, eps0=1e-14, fixed=
     if want_ranks:
         cap = 1 << 22
         ranks = np.zeros(cap, np.int32)
-    rc = lib().hmxo_hmvp(_p(pts), n, d, kind_of(kind), float(p0), int(leaf), float(eta),
-                         int(kmax), float(eps), float(aca_eta), float(eps0), int(bool(fixed)),
-                         float(sigma2), float(alpha), float(beta), _p(x), _p(zz), cap,
-                         _p(ranks), _p(stats))
+    rc = lib().hmxo_hmvp_ex(_p(pts), n, d, kind_of(kind), float(p0), int(leaf), float(eta),
+                            int(kmax), float(eps), float(aca_eta), float(eps0), int(bool(fixed)),
+                            int(bool(symmetric)), float(sigma2), float(alpha), float(beta), _p(x),
+                            _p(zz), cap, _p(ranks), _p(stats))
     if rc != 0:
         raise ValueError("hmxo_hmvp failed: %d" % rc)
     st = dict(n_adm=int(stats[0]), n_dense=int(stats[1]), sum_rank=int(stats[2]),

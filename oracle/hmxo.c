@@ -627,6 +627,34 @@ int hmxo_hmvp(const double* pts, int64_t n, int32_t d, int32_t kind, double p0, 
               double sigma2, double alpha, double beta, const double* x, double* z,
               int64_t ranks_cap, int32_t* ranks, double* stats)
 {
+    return hmxo_hmvp_ex(pts, n, d, kind, p0, leaf, eta, kmax, eps, aca_eta, eps0, fixed, 0,
+                        sigma2, alpha, beta, x, z, ranks_cap, ranks, stats);
+}
+
+/* admissible leaf q of the partition whose (first row, first column) is
+ * (r0, c0): the leaves partition I x I, so the pair names one leaf */
+typedef struct {
+    int64_t r0, c0, q;
+} leafkey;
+
+static int leafkey_cmp(const void* a, const void* b)
+{
+    const leafkey* x = (const leafkey*)a;
+    const leafkey* y = (const leafkey*)b;
+    if (x->r0 != y->r0) return x->r0 < y->r0 ? -1 : 1;
+    if (x->c0 != y->c0) return x->c0 < y->c0 ? -1 : 1;
+    return 0;
+}
+
+/* symmetric = 1: the kernel matrix is symmetric and so is the partition
+ * (Alg. 1 visits (tau, sigma) and (sigma, tau) alike), so only the leaf with
+ * tau before sigma (or tau = sigma) is approximated and its mirror (sigma,
+ * tau) uses the transposed factors, A|sigma x tau ~ V U^T. */
+int hmxo_hmvp_ex(const double* pts, int64_t n, int32_t d, int32_t kind, double p0, int32_t leaf,
+                 double eta, int32_t kmax, double eps, double aca_eta, double eps0, int32_t fixed,
+                 int32_t symmetric, double sigma2, double alpha, double beta, const double* x,
+                 double* z, int64_t ranks_cap, int32_t* ranks, double* stats)
+{
     if (n < 1 || d < 1 || d > 3 || leaf < 1 || !(eta >= 0.0) || kmax < 1) return -1;
     double lo[3], hi[3];
     hmxo_global_box(pts, n, d, lo, hi);
@@ -658,11 +686,13 @@ int hmxo_hmvp(const double* pts, int64_t n, int32_t d, int32_t kind, double p0, 
         tid = omp_get_thread_num();
 #endif
         double* zt = zpriv + (int64_t)tid * n;
-        /* admissible leaves: z|tau += U (V^T x|sigma) */
+        /* admissible leaves: z|tau += U (V^T x|sigma); with the symmetric
+         * far field a primary leaf also gives its mirror z|sigma += V (U^T x|tau) */
 #pragma omp for schedule(dynamic, 1) nowait
         for (int64_t q = 0; q < P.adm.n; ++q) {
             int64_t t = P.adm.a[2 * q], s = P.adm.a[2 * q + 1];
             int64_t tlo = T.lo[t], thi = T.hi[t], slo = T.lo[s], shi = T.hi[s];
+            if (symmetric && tlo > slo) continue; /* a mirror: done by its primary */
             int64_t m = thi - tlo, nc = shi - slo;
             int64_t R = kmax;
             double* U = (double*)malloc(sizeof(double) * m * R);
@@ -675,6 +705,14 @@ int hmxo_hmvp(const double* pts, int64_t n, int32_t d, int32_t kind, double p0, 
                 double tl = 0.0;
                 for (int64_t jj = 0; jj < nc; ++jj) tl += V[l * nc + jj] * xm[slo + jj];
                 for (int64_t i = 0; i < m; ++i) zt[tlo + i] += U[l * m + i] * tl;
+            }
+            if (symmetric && tlo != slo) {
+                for (int64_t l = 0; l < rk; ++l) {
+                    double tl = 0.0;
+                    for (int64_t i = 0; i < m; ++i) tl += U[l * m + i] * xm[tlo + i];
+                    for (int64_t jj = 0; jj < nc; ++jj) zt[slo + jj] += V[l * nc + jj] * tl;
+                }
+                sum_rank += rk;
             }
             sum_rank += rk;
             factor_entries += (double)rk * (double)(m + nc);
@@ -701,6 +739,30 @@ int hmxo_hmvp(const double* pts, int64_t n, int32_t d, int32_t kind, double p0, 
         int64_t p = perm[k];
         double hz = zm[k] + sigma2 * xm[k];
         z[p] = alpha * hz + (beta != 0.0 ? beta * z[p] : 0.0);
+    }
+    if (symmetric && ranks && P.adm.n <= ranks_cap && P.adm.n > 0) {
+        /* a mirror's rank is its primary's */
+        leafkey* K = (leafkey*)malloc(sizeof(leafkey) * P.adm.n);
+        if (!K) return -2;
+        for (int64_t q = 0; q < P.adm.n; ++q) {
+            K[q].r0 = T.lo[P.adm.a[2 * q]];
+            K[q].c0 = T.lo[P.adm.a[2 * q + 1]];
+            K[q].q = q;
+        }
+        qsort(K, (size_t)P.adm.n, sizeof(leafkey), leafkey_cmp);
+        for (int64_t q = 0; q < P.adm.n; ++q) {
+            const int64_t r0 = T.lo[P.adm.a[2 * q]], c0 = T.lo[P.adm.a[2 * q + 1]];
+            if (r0 <= c0) continue;
+            leafkey want = {c0, r0, 0};
+            const leafkey* hit =
+                (const leafkey*)bsearch(&want, K, (size_t)P.adm.n, sizeof(leafkey), leafkey_cmp);
+            if (!hit) {
+                free(K);
+                return -4; /* the partition has no mirror for this leaf */
+            }
+            ranks[q] = ranks[hit->q];
+        }
+        free(K);
     }
     if (stats) {
         stats[0] = (double)P.adm.n;

@@ -93,6 +93,16 @@ int hmxo_hmvp(const double* pts, int64_t n, int32_t d, int32_t kind, double p0,
               int32_t leaf, double eta, int32_t kmax, double eps, double aca_eta,
               double eps0, int32_t fixed, double sigma2, double alpha, double beta,
               const double* x, double* z, int64_t ranks_cap, int32_t* ranks, double* stats);
+/* hmxo_hmvp with the symmetric far field (symmetric = 1): only the
+ * admissible leaf with tau before sigma (or tau = sigma) is approximated, its
+ * mirror (sigma, tau) applies the transposed factors V U^T; ranks of a
+ * mirror are its primary's; stats[4] counts the stored factor entries.
+ * Returns -4 if an admissible leaf has no mirror. */
+int hmxo_hmvp_ex(const double* pts, int64_t n, int32_t d, int32_t kind, double p0,
+                 int32_t leaf, double eta, int32_t kmax, double eps, double aca_eta,
+                 double eps0, int32_t fixed, int32_t symmetric, double sigma2, double alpha,
+                 double beta, const double* x, double* z, int64_t ranks_cap, int32_t* ranks,
+                 double* stats);
 
 /* Stored-mode product restricted to the Morton-order rows [row_lo, row_hi):
  * the leaves whose tau meets the range are built (ACA / dense entries),

@@ -278,9 +278,17 @@ struct hmx_hmatrix_s {
     DevBuf codes, perm, soa64, soa32, node_lo, node_hi, bmin, bmax;
     DevBuf adm, adm_level, adm_ids, dense, dense_level;
     DevBuf tile_of_point, tile_lo;
-    DevBuf rank, steps, voff, toff, V;
-    DevBuf pieces, upool, npool, widx, tile_meta, vecpool, col_meta;
+    DevBuf rank, steps, toff;
+    DevBuf pieces, upool, npool, widx, tile_meta, vecpool;
     int64_t upool_entries = 0, npool_entries = 0, ncols_total = 0;
+    // phase 1 (t = V^T x) by row tiles: the V pool (pieces of V_b rows per
+    // row tile of sigma_b; with the symmetric far field only for leaves that
+    // are their own mirror), partial sums per source column, and per t entry
+    // the first of its source pieces in pfc
+    int sym = 0;       // symmetric far field: the mirror of a leaf reuses its factors
+    int Ru = 0, Rv = 0;  // row units of the factor pool and of the V pool
+    int64_t ncols_u = 0, ncols_v = 0, nvpieces = 0, vtpool_entries = 0;
+    DevBuf partner, vpieces, vtpool, vt_meta, p1rec, pfc, partial;
     hmx_stats stats{};
     // matvec phase tracing (hmx_profile_begin / end)
     std::vector<hipEvent_t> prof_events;
@@ -294,13 +302,13 @@ struct hmx_hmatrix_s {
     ~hmx_hmatrix_s() { prof_release(); }
 
     int64_t device_bytes() const {
-        const DevBuf* all[] = {&codes,     &perm,          &soa64,   &soa32,     &node_lo,
-                               &node_hi,   &bmin,          &bmax,    &adm,       &adm_level,
-                               &adm_ids,
-                               &dense,     &dense_level,   &tile_of_point, &tile_lo, &rank,
-                               &steps,     &voff,          &toff,    &V,         &pieces,
-                               &upool,     &npool,         &widx,    &tile_meta, &vecpool,
-                               &col_meta};
+        const DevBuf* all[] = {&codes,   &perm,    &soa64,     &soa32,         &node_lo,
+                               &node_hi, &bmin,    &bmax,      &adm,           &adm_level,
+                               &adm_ids, &dense,   &dense_level, &tile_of_point, &tile_lo,
+                               &rank,    &steps,   &toff,      &pieces,        &upool,
+                               &npool,   &widx,    &tile_meta, &vecpool,       &partner,
+                               &vpieces, &vtpool,  &vt_meta,   &p1rec,         &pfc,
+                               &partial};
         int64_t s = 0;
         for (auto* b : all) s += (int64_t)b->bytes;
         return s;
@@ -326,11 +334,15 @@ void finish_stats(hmx_hmatrix_s* h, std::chrono::steady_clock::time_point t_all)
     S.near_entry_bytes = (int32_t)h->nsz;
     S.tile_config = h->rt_config;
     S.phase_ms[7] = ms_since(t_all);
-    // algorithmic bytes of one matvec with beta = 0: stored data once, the
-    // vectors x and z once, perm for gather and scatter, t written and read
+    // algorithmic bytes of one matvec with beta = 0: the near field once,
+    // U_b and V_b of every admissible leaf once (with the symmetric far
+    // field each stored factor serves twice: as a leaf's U in phase 2 and as
+    // its mirror's V in phase 1), the vectors x and z once, perm for gather
+    // and scatter, t written and read
     S.matvec_bytes = h->prm.aca_only
                          ? 0.0
-                         : (double)h->near_entries * h->nsz + (double)h->factor_entries * ssz +
+                         : (double)h->near_entries * h->nsz +
+                               (double)(S.u_entries + S.v_entries) * ssz +
                                (double)n * (2.0 * esz + 8.0) + (double)S.sum_rank * 2.0 * esz;
     S.device_bytes = h->device_bytes();
 }
@@ -381,6 +393,7 @@ void init_handle(hmx_hmatrix_s* h, int64_t n, int d, const hmx_kernel& k, const 
         h->nmode = 3;
         h->nsz = 0;
     }
+    h->sym = p.symmetric_far;
 }
 
 // validation shared by the single and the batched build
@@ -432,6 +445,10 @@ hmx_status check_params(const hmx_params& p) {
     }
     if (p.learned_one_shot != 0 && p.learned_one_shot != 1) {
         set_err("learned_one_shot must be 0 or 1");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (p.symmetric_far != 0 && p.symmetric_far != 1) {
+        set_err("symmetric_far must be 0 or 1");
         return HMX_ERR_INVALID_ARG;
     }
     return HMX_OK;
@@ -783,15 +800,74 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
     // appended to the pools.
     alloc(h->rank, std::max<int64_t>(h->n_adm, 1) * 4, "ranks");
     alloc(h->steps, std::max<int64_t>(h->n_adm, 1) * 4, "steps");
-    alloc(h->voff, (h->n_adm + 1) * 8, "V offsets");
-    DevBuf Uex, uoff_ex;
-    alloc(uoff_ex, (h->n_adm + 1) * 8, "U offsets");
+    // F: the exact-rank factors of every approximated leaf (per chunk its U_b
+    // then its V_b, column-major, storage type).  rfo[b]: offset of leaf b's
+    // row factor (its U_b; with the symmetric far field a mirror's row factor
+    // is its primary's V), vfo[b]: offset of V_b (approximated leaves)
+    DevBuf F, rfo, vfo;
+    alloc(rfo, (h->n_adm + 1) * 8, "row factor offsets");
+    alloc(vfo, (h->n_adm + 1) * 8, "V offsets");
     int nchunks = 0;
     double aca_ms = 0.0;
-    int64_t utot = 0, vtot = 0;
+    int64_t ftot = 0;
     const bool learned = plan.rt != nullptr;
     const bool aca_only = h->prm.aca_only != 0;
-    if (h->n_adm > 0) {
+    // The ACA list: every admissible leaf, or with the symmetric far field the
+    // primary ones (tau before sigma, or tau = sigma) in their canonical order,
+    // which keeps the levels sorted; results return to the leaves at the end
+    int64_t nl = h->n_adm;
+    DevBuf lst, lblk, llev, lrt, lrank, lsteps, lue, lve;
+    const int4* Lb = h->adm.as<int4>();
+    const int32_t* Ll = plan.cls;
+    const int32_t* Lrt = plan.rt;
+    if (h->n_adm > 0 && h->sym) {
+        const int64_t na = h->n_adm;
+        alloc(h->partner, (size_t)na * 4, "mirror table");
+        {
+            DevBuf keys, vals, sscr, bad;
+            alloc(keys, (size_t)na * 8, "mirror keys");
+            alloc(vals, (size_t)na * 4, "mirror order");
+            alloc(bad, 8, "mirror check");
+            check(hipMemsetAsync(bad.p, 0, 8, st), "mirror check");
+            check(launch_mirror_keys(h->adm.as<int4>(), na, keys.as<uint64_t>(),
+                                     vals.as<uint32_t>(), st),
+                  "mirror keys");
+            int bits = 32;
+            while (bits < 64 && (1ll << (bits - 32)) <= n) ++bits;
+            alloc(sscr, radix_sort_scratch_bytes(na), "mirror sort");
+            check(radix_sort_pairs(keys.as<uint64_t>(), vals.as<uint32_t>(), na, bits, sscr.p, st),
+                  "mirror sort");
+            check(launch_mirror_find(h->adm.as<int4>(), na, keys.as<uint64_t>(),
+                                     vals.as<uint32_t>(), h->partner.as<int32_t>(), bad.as<int>(),
+                                     st),
+                  "mirror find");
+            if (read_scalar(bad.as<int>(), st) != 0) {
+                set_err("symmetric far field: an admissible leaf has no mirror in the partition");
+                throw Fail{HMX_ERR_DEVICE};
+            }
+        }
+        DevBuf pos;
+        alloc(pos, (size_t)(na + 1) * 8, "primary flags");
+        check(launch_primary_flags(h->adm.as<int4>(), na, 1, pos.as<int64_t>(), st),
+              "primary flags");
+        nl = scan(pos.as<int64_t>(), na);
+        alloc(lst, (size_t)std::max<int64_t>(nl, 1) * 4, "ACA list");
+        alloc(lblk, (size_t)std::max<int64_t>(nl, 1) * sizeof(int4), "ACA list blocks");
+        alloc(llev, (size_t)std::max<int64_t>(nl, 1) * 4, "ACA list levels");
+        if (Lrt) alloc(lrt, (size_t)std::max<int64_t>(nl, 1) * 4, "ACA list targets");
+        check(launch_gather_list(pos.as<int64_t>(), na, h->adm.as<int4>(), plan.cls, Lrt,
+                                 lst.as<int32_t>(), lblk.as<int4>(), llev.as<int32_t>(),
+                                 Lrt ? lrt.as<int32_t>() : nullptr, st),
+              "ACA list");
+        Lb = lblk.as<int4>();
+        Ll = llev.as<int32_t>();
+        if (Lrt) Lrt = lrt.as<int32_t>();
+    }
+    alloc(lrank, (size_t)std::max<int64_t>(nl, 1) * 4, "list ranks");
+    alloc(lsteps, (size_t)std::max<int64_t>(nl, 1) * 4, "list steps");
+    alloc(lue, (size_t)(nl + 1) * 8, "list U offsets");
+    alloc(lve, (size_t)(nl + 1) * 8, "list V offsets");
+    if (nl > 0) {
         // chunk budget: the caller's, else 40% of the device memory that is
         // free now (the library's cached blocks count as free)
         int64_t budget_bytes = (int64_t)h->prm.aca_chunk_mb << 20;
@@ -947,26 +1023,24 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                 check(hipStreamSynchronize(st), "aca sync");  // before sb returns to the cache
                 aca_ms += ms_since(ta);
                 if (aca_only) continue;
-                // exact offsets of this chunk's blocks: chunk-local scan plus the
-                // running totals
+                // exact offsets of this chunk's blocks: chunk-local scans plus the
+                // running total; the chunk's U factors, then its V factors
                 int64_t* ue = ue_all + b0;
                 int64_t* ve = ve_all + b0;
                 check(launch_extent(a.blocks, nbk, 3, 0, a.rank, nullptr, ue, st), "extent");
                 check(launch_extent(a.blocks, nbk, 4, 0, a.rank, nullptr, ve, st), "extent");
                 const int64_t uk = scan(ue, nbk), vk = scan(ve, nbk);
-                check(launch_add_const(ue, nbk, utot, st), "offsets");
-                check(launch_add_const(ve, nbk, vtot, st), "offsets");
-                grow(Uex, (size_t)(utot + uk) * ssz, (size_t)utot * ssz, st, "U pool");
-                grow(h->V, (size_t)(vtot + vk) * ssz, (size_t)vtot * ssz, st, "V pool");
-                check(launch_compact_u(a.blocks, nbk, a.rank, a.uoff, a.ubase, ue, Ucap.p, Uex.p,
+                check(launch_add_const(ue, nbk, ftot, st), "offsets");
+                check(launch_add_const(ve, nbk, ftot + uk, st), "offsets");
+                grow(F, (size_t)(ftot + uk + vk) * ssz, (size_t)ftot * ssz, st, "factor pool");
+                check(launch_compact_u(a.blocks, nbk, a.rank, a.uoff, a.ubase, ue, Ucap.p, F.p,
                                        smode, st),
                       "compact U");
-                check(launch_compact_v(a.blocks, nbk, a.rank, a.voff, a.vbase, ve, Vcap.p,
-                                       h->V.p, smode, st),
+                check(launch_compact_v(a.blocks, nbk, a.rank, a.voff, a.vbase, ve, Vcap.p, F.p,
+                                       smode, st),
                       "compact V");
                 check(hipStreamSynchronize(st), "compact sync");
-                utot += uk;
-                vtot += vk;
+                ftot += uk + vk;
             }
         };
 
@@ -1065,28 +1139,26 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
             check(hipStreamSynchronize(st), "interleave sync");  // before the buffers return
         };
 
+        int32_t* Lrank = lrank.as<int32_t>();
+        int32_t* Lsteps = lsteps.as<int32_t>();
+        int64_t* Lue = lue.as<int64_t>();
+        int64_t* Lve = lve.as<int64_t>();
         if (!learned) {
-            chunked_pass(h->adm.as<int4>(), plan.cls, h->n_adm, nullptr, nullptr, 0, 0,
-                         h->rank.as<int32_t>(), h->steps.as<int32_t>(), uoff_ex.as<int64_t>(),
-                         h->voff.as<int64_t>());
+            chunked_pass(Lb, Ll, nl, nullptr, nullptr, 0, 0, Lrank, Lsteps, Lue, Lve);
         } else {
             // learned sizing: predicted targets, a pass with storage of that
             // size, then the blocks left unfinished again with k_max columns
             // (sizing form: plain adaptive; one-shot form: the same target
             // steps, the test, then adaptive)
             const int one_shot = h->prm.learned_one_shot;
-            const int32_t* rt = plan.rt;
-            chunked_pass(h->adm.as<int4>(), plan.cls, h->n_adm, rt, rt, one_shot, 1,
-                         h->rank.as<int32_t>(), h->steps.as<int32_t>(), uoff_ex.as<int64_t>(),
-                         h->voff.as<int64_t>());
+            const int32_t* rt = Lrt;
+            chunked_pass(Lb, Ll, nl, rt, rt, one_shot, 1, Lrank, Lsteps, Lue, Lve);
             DevBuf flag;
-            alloc(flag, (h->n_adm + 1) * 8, "fallback flags");
-            check(launch_over_flags(h->rank.as<int32_t>(), rt, h->n_adm, flag.as<int64_t>(), st),
-                  "overflow flags");
-            S.aca_overflow = scan(flag.as<int64_t>(), h->n_adm);
-            check(launch_fail_flags(h->rank.as<int32_t>(), h->n_adm, flag.as<int64_t>(), st),
-                  "fallback flags");
-            const int64_t nfb = scan(flag.as<int64_t>(), h->n_adm);
+            alloc(flag, (nl + 1) * 8, "fallback flags");
+            check(launch_over_flags(Lrank, rt, nl, flag.as<int64_t>(), st), "overflow flags");
+            S.aca_overflow = scan(flag.as<int64_t>(), nl);
+            check(launch_fail_flags(Lrank, nl, flag.as<int64_t>(), st), "fallback flags");
+            const int64_t nfb = scan(flag.as<int64_t>(), nl);
             S.aca_fallback = nfb;
             if (nfb > 0) {
                 DevBuf list, bfb, lvfb, rtfb, rkfb, stfb, uefb, vefb;
@@ -1098,45 +1170,44 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                 alloc(stfb, nfb * 4, "fallback steps");
                 alloc(uefb, (nfb + 1) * 8, "fallback U offsets");
                 alloc(vefb, (nfb + 1) * 8, "fallback V offsets");
-                check(launch_gather_failed(h->rank.as<int32_t>(), flag.as<int64_t>(), h->n_adm,
-                                           h->adm.as<int4>(), plan.cls, rt, list.as<int32_t>(),
-                                           bfb.as<int4>(), lvfb.as<int32_t>(),
-                                           rtfb.as<int32_t>(), st),
+                check(launch_gather_failed(Lrank, flag.as<int64_t>(), nl, Lb, Ll, rt,
+                                           list.as<int32_t>(), bfb.as<int4>(),
+                                           lvfb.as<int32_t>(), rtfb.as<int32_t>(), st),
                       "fallback gather");
                 pass(bfb.as<int4>(), lvfb.as<int32_t>(), nfb, nullptr,
                      one_shot ? rtfb.as<int32_t>() : nullptr, one_shot, 0, rkfb.as<int32_t>(),
                      stfb.as<int32_t>(), uefb.as<int64_t>(), vefb.as<int64_t>(), nullptr);
                 const int32_t* li = list.as<int32_t>();
-                check(launch_scatter_i32(li, nfb, rkfb.as<int32_t>(), h->rank.as<int32_t>(), 0,
-                                         st),
+                check(launch_scatter_i32(li, nfb, rkfb.as<int32_t>(), Lrank, 0, st),
                       "fallback ranks");
-                check(launch_scatter_i32(li, nfb, stfb.as<int32_t>(), h->steps.as<int32_t>(), 1,
-                                         st),
+                check(launch_scatter_i32(li, nfb, stfb.as<int32_t>(), Lsteps, 1, st),
                       "fallback steps");
                 if (!aca_only) {
-                    check(launch_scatter_i64(li, nfb, uefb.as<int64_t>(), uoff_ex.as<int64_t>(),
-                                             st),
+                    check(launch_scatter_i64(li, nfb, uefb.as<int64_t>(), Lue, st),
                           "fallback offsets");
-                    check(launch_scatter_i64(li, nfb, vefb.as<int64_t>(), h->voff.as<int64_t>(),
-                                             st),
+                    check(launch_scatter_i64(li, nfb, vefb.as<int64_t>(), Lve, st),
                           "fallback offsets");
                 }
                 check(hipStreamSynchronize(st), "fallback sync");
             }
         }
-        S.u_entries = utot;
-        S.v_entries = vtot;
-        h->factor_entries = utot + vtot;
+        h->factor_entries = ftot;
         S.phase_ms[3] = aca_ms;
-        // rank statistics, reduced on the device
+        // the list's results back to the leaves (a mirror takes its
+        // primary's rank, and its primary's V as its row factor)
+        check(launch_scatter_list(h->sym ? lst.as<int32_t>() : nullptr, nl,
+                                  h->sym ? h->partner.as<int32_t>() : nullptr, Lrank, Lsteps,
+                                  Lue, Lve, h->rank.as<int32_t>(), h->steps.as<int32_t>(),
+                                  aca_only ? nullptr : rfo.as<int64_t>(),
+                                  aca_only ? nullptr : vfo.as<int64_t>(), st),
+              "ACA results");
+        // rank statistics over the leaves, ACA work over the list, on the device
         DevBuf red;
         alloc(red, 6 * sizeof(unsigned long long), "stats");
         unsigned long long* rd = red.as<unsigned long long>();
         check(launch_int_stats(h->rank.as<int32_t>(), h->n_adm, rd, st), "rank stats");
-        check(launch_int_stats(h->steps.as<int32_t>(), h->n_adm, rd + 2, st), "step stats");
-        check(launch_aca_work(h->adm.as<int4>(), h->rank.as<int32_t>(), h->steps.as<int32_t>(),
-                              h->n_adm, rd + 4, st),
-              "aca work");
+        check(launch_int_stats(Lsteps, nl, rd + 2, st), "step stats");
+        check(launch_aca_work(Lb, Lrank, Lsteps, nl, rd + 4, st), "aca work");
         unsigned long long hv[6];
         check(hipMemcpyAsync(hv, rd, sizeof hv, hipMemcpyDeviceToHost, st), "stats readback");
         check(hipStreamSynchronize(st), "stats sync");
@@ -1146,14 +1217,33 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
         S.aca_kernel_evals = (int64_t)hv[4];
         S.aca_flops = (double)hv[5];
     }
-    if (!h->V.p) alloc(h->V, 16, "V pool");
-    if (!Uex.p) alloc(Uex, 16, "U pool");
+    if (!F.p) alloc(F, 16, "factor pool");
     S.aca_chunks = nchunks;
     S.phase_ms[4] = ms_since(t0) - S.phase_ms[3];
+    lst.release();
+    lblk.release();
+    llev.release();
+    lrt.release();
+    lrank.release();
+    lsteps.release();
+    lue.release();
+    lve.release();
     if (aca_only) {
-        Uex.release();
+        F.release();
         finish_stats(h, t_all);
         return;
+    }
+    if (h->n_adm > 0) {  // entries the two phases of a matvec read
+        DevBuf ex;
+        alloc(ex, (h->n_adm + 1) * 8, "entry counts");
+        check(launch_extent(h->adm.as<int4>(), h->n_adm, 3, 0, h->rank.as<int32_t>(), nullptr,
+                            ex.as<int64_t>(), st),
+              "extent");
+        S.u_entries = scan(ex.as<int64_t>(), h->n_adm);
+        check(launch_extent(h->adm.as<int4>(), h->n_adm, 4, 0, h->rank.as<int32_t>(), nullptr,
+                            ex.as<int64_t>(), st),
+              "extent");
+        S.v_entries = scan(ex.as<int64_t>(), h->n_adm);
     }
     t0 = clk::now();
     // t offsets, vector pool, column -> leaf map of phase 1
@@ -1165,10 +1255,6 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
         h->sum_rank = scan(h->toff.as<int64_t>(), h->n_adm);
     }
     alloc(h->vecpool, (size_t)(n + h->sum_rank) * esz, "vector pool");
-    alloc(h->col_meta, (size_t)std::max<int64_t>(h->sum_rank, 1) * sizeof(int4), "column map");
-    check(launch_col_meta(h->adm.as<int4>(), h->rank.as<int32_t>(), h->toff.as<int64_t>(),
-                          h->voff.as<int64_t>(), h->n_adm, h->col_meta.as<int4>(), st),
-          "column map");
     S.phase_ms[4] += ms_since(t0);
     t0 = clk::now();
 
@@ -1219,7 +1305,7 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
         h->upool_entries = scan(psu.as<int64_t>(), h->npieces);
         h->npool_entries = scan(psn.as<int64_t>(), h->npieces);
         h->ncols_total = scan(pc.as<int64_t>(), h->npieces);
-        scan(pcu.as<int64_t>(), h->npieces);
+        h->ncols_u = scan(pcu.as<int64_t>(), h->npieces);
         alloc(h->widx, (size_t)std::max<int64_t>(h->ncols_total, 1) * 8, "column weights");
         check(launch_piece_layout(h->pieces.as<Piece>(), h->npieces, psu.as<int64_t>(),
                                   psn.as<int64_t>(), pc.as<int64_t>(), h->widx.as<int64_t>(), st),
@@ -1237,14 +1323,101 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
         alloc(h->upool, (size_t)std::max<int64_t>(h->upool_entries, 1) * ssz, "factor pool");
         alloc(h->npool, (size_t)std::max<int64_t>(h->npool_entries, 1) * h->nsz, "near-field pool");
         check(launch_piece_data(h->pieces.as<Piece>(), h->npieces, h->tile_lo.as<int32_t>(),
-                                h->adm.as<int4>(), h->dense.as<int4>(), uoff_ex.as<int64_t>(), Uex.p,
+                                h->adm.as<int4>(), h->dense.as<int4>(), rfo.as<int64_t>(), F.p,
                                 f64 ? h->soa64.p : h->soa32.p, n, d,
                                 KernelFn{(int)h->kern.kind, h->kern.p0}, h->upool.p, h->npool.p,
                                 smode, h->nmode, st),
               "piece data");
+        h->Ru = R;
+        // ---- phase-1 sources (t = V^T x by row tiles) ----
+        // the V pool: pieces of V_b rows per row tile of sigma_b for every
+        // leaf, or (symmetric far field) for the leaves that are their own
+        // mirror; the other leaves read their mirror's factor pieces
+        const int32_t* prt = h->sym ? h->partner.as<int32_t>() : nullptr;
+        const int64_t nadm_pieces = h->n_adm > 0 ? read_scalar(cnt.as<int64_t>() + h->n_adm, st) : 0;
+        const int64_t pfc_u = h->sym ? nadm_pieces : 0;  // pfc entries of the factor pieces
+        DevBuf cntv;
+        alloc(cntv, (h->n_adm + 1) * 8, "V piece counts");
+        check(launch_vpiece_count(h->adm.as<int4>(), h->n_adm, h->rank.as<int32_t>(), prt,
+                                  h->tile_of_point.as<int32_t>(), cntv.as<int64_t>(), st),
+              "V piece counts");
+        h->nvpieces = h->n_adm > 0 ? scan(cntv.as<int64_t>(), h->n_adm) : 0;
+        alloc(h->pfc, (size_t)std::max<int64_t>(pfc_u + h->nvpieces, 1) * 8, "source columns");
+        if (h->sym && nadm_pieces > 0)
+            check(launch_pfc(h->pieces.as<Piece>(), vals.as<uint32_t>(), pcu.as<int64_t>(),
+                             h->npieces, nadm_pieces, 0, h->pfc.as<int64_t>(), st),
+                  "source columns");
+        const int64_t vbase = h->sym ? h->ncols_u : 0;  // first source column of the V pool
+        h->Rv = rows_per_unit(smode, smode);
+        h->ncols_v = 0;
+        alloc(h->vt_meta, (size_t)(h->ntiles + 1) * 4 * 8, "V pool tile meta");
+        if (h->nvpieces > 0) {
+            const int64_t nv = h->nvpieces;
+            DevBuf vun, vk, vv, vs, vsz, vcl, vptr;
+            alloc(vun, (size_t)nv * sizeof(Piece), "V pieces");
+            alloc(vk, (size_t)nv * 8, "V piece keys");
+            alloc(vv, (size_t)nv * 4, "V piece vals");
+            check(launch_vpiece_fill(h->adm.as<int4>(), h->n_adm, h->rank.as<int32_t>(),
+                                     cntv.as<int64_t>(), h->tile_of_point.as<int32_t>(),
+                                     h->tile_lo.as<int32_t>(), vun.as<Piece>(), vk.as<uint64_t>(),
+                                     vv.as<uint32_t>(), st),
+                  "V pieces");
+            alloc(vs, radix_sort_scratch_bytes(nv), "V piece sort");
+            check(radix_sort_pairs(vk.as<uint64_t>(), vv.as<uint32_t>(), nv, bits, vs.p, st),
+                  "V piece sort");
+            vs.release();
+            alloc(h->vpieces, (size_t)nv * sizeof(Piece), "sorted V pieces");
+            alloc(vsz, (size_t)(nv + 1) * 8, "V piece sizes");
+            alloc(vcl, (size_t)(nv + 1) * 8, "V piece columns");
+            check(launch_vpiece_sizes(vun.as<Piece>(), vv.as<uint32_t>(), nv, h->vpieces.as<Piece>(),
+                                      h->tile_lo.as<int32_t>(), h->Rv, vsz.as<int64_t>(),
+                                      vcl.as<int64_t>(), st),
+                  "V piece sizes");
+            h->vtpool_entries = scan(vsz.as<int64_t>(), nv);
+            h->ncols_v = scan(vcl.as<int64_t>(), nv);
+            check(launch_vpiece_layout(h->vpieces.as<Piece>(), nv, vsz.as<int64_t>(), st),
+                  "V piece layout");
+            alloc(vptr, (h->ntiles + 1) * 8, "V tile ptr");
+            check(launch_tile_offsets(vk.as<uint64_t>(), nv, h->ntiles, vptr.as<int64_t>(), st),
+                  "V tile ptr");
+            check(launch_tile_meta(vptr.as<int64_t>(), h->ntiles, nv, vcl.as<int64_t>(),
+                                   vcl.as<int64_t>(), vsz.as<int64_t>(), vsz.as<int64_t>(),
+                                   h->vt_meta.as<int64_t>(), st),
+                  "V tile meta");
+            alloc(h->vtpool, (size_t)std::max<int64_t>(h->vtpool_entries, 1) * ssz, "V pool");
+            check(launch_vpiece_data(h->vpieces.as<Piece>(), nv, h->tile_lo.as<int32_t>(),
+                                     h->adm.as<int4>(), vfo.as<int64_t>(), F.p, h->Rv,
+                                     h->vtpool.p, smode, st),
+                  "V pool");
+            check(launch_pfc(h->vpieces.as<Piece>(), vv.as<uint32_t>(), vcl.as<int64_t>(), nv, nv,
+                             vbase, h->pfc.as<int64_t>() + pfc_u, st),
+                  "V source columns");
+            check(hipStreamSynchronize(st), "V pool sync");
+        } else {
+            check(hipMemsetAsync(h->vt_meta.p, 0, (size_t)(h->ntiles + 1) * 4 * 8, st),
+                  "V pool tile meta");
+        }
+        alloc(h->partial, (size_t)std::max<int64_t>(vbase + h->ncols_v, 1) * esz,
+              "phase-1 partial sums");
+        // per t entry: where its source pieces start in pfc, and how many
+        if (h->n_adm > 0) {
+            DevBuf sb, sn;
+            alloc(sb, (size_t)h->n_adm * 8, "source bases");
+            alloc(sn, (size_t)h->n_adm * 4, "source counts");
+            check(launch_p1_source(h->n_adm, prt, cnt.as<int64_t>(), cntv.as<int64_t>(), pfc_u,
+                                   sb.as<int64_t>(), sn.as<int32_t>(), st),
+                  "phase-1 sources");
+            alloc(h->p1rec, (size_t)std::max<int64_t>(h->sum_rank, 1) * sizeof(int4),
+                  "phase-1 records");
+            check(launch_p1_rec(h->rank.as<int32_t>(), h->toff.as<int64_t>(), sb.as<int64_t>(),
+                                sn.as<int32_t>(), h->n_adm, h->p1rec.as<int4>(), st),
+                  "phase-1 records");
+        } else {
+            alloc(h->p1rec, 16, "phase-1 records");
+        }
         check(hipStreamSynchronize(st), "pool sync");
     }
-    Uex.release();
+    F.release();
     // near-field entry count (algorithmic, unpadded)
     if (h->n_dense > 0) {
         DevBuf ne;
@@ -1482,9 +1655,19 @@ hipError_t matvec_launch(hmx_hmatrix_s* h, const void* x, void* z, double alpha,
     hipError_t e = ev ? hipEventRecord(ev[0], st) : hipSuccess;
     if (e == hipSuccess) e = launch_gather_x(x, h->perm.as<int32_t>(), h->n, h->vecpool.p, f64, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
+    // phase 1 by row tiles: partial sums of every source column, then the t
+    // entries; the sources are the factor pool (symmetric far field) and the V pool
+    if (e == hipSuccess && h->sym && h->ncols_u > 0)
+        e = launch_p1_tile(h->ntiles, h->tile_lo.as<int32_t>(), h->tile_meta.as<int64_t>(), 4,
+                           h->Ru, h->max_tile, h->upool.p, h->vecpool.p, h->partial.p, 0,
+                           h->smode, st);
+    if (e == hipSuccess && h->ncols_v > 0)
+        e = launch_p1_tile(h->ntiles, h->tile_lo.as<int32_t>(), h->vt_meta.as<int64_t>(), 4,
+                           h->Rv, h->max_tile, h->vtpool.p, h->vecpool.p, h->partial.p,
+                           h->sym ? h->ncols_u : 0, h->smode, st);
     if (e == hipSuccess)
-        e = launch_far_phase1(h->col_meta.as<int4>(), h->sum_rank, h->V.p, h->vecpool.p, h->n,
-                              h->smode, st);
+        e = launch_p1_reduce(h->p1rec.as<int4>(), h->sum_rank, h->pfc.as<int64_t>(),
+                             h->partial.p, h->vecpool.p, h->n, f64, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
     if (e == hipSuccess)
         e = launch_rowtile(h->ntiles, h->tile_lo.as<int32_t>(), h->tile_meta.as<int64_t>(),
@@ -2027,11 +2210,13 @@ hmx_status hmx_get_factors(hmx_hmatrix h, int64_t leaf, double* U, double* V, in
     hipStream_t st = (hipStream_t)stream;
     try {
         int4 bl;
-        int32_t r;
-        int64_t vo;
+        int32_t r, mirror = (int32_t)leaf;
         check(hipMemcpyAsync(&bl, h->adm.as<int4>() + leaf, 16, hipMemcpyDeviceToHost, st), "blk");
         check(hipMemcpyAsync(&r, h->rank.as<int32_t>() + leaf, 4, hipMemcpyDeviceToHost, st), "r");
-        check(hipMemcpyAsync(&vo, h->voff.as<int64_t>() + leaf, 8, hipMemcpyDeviceToHost, st), "vo");
+        if (h->sym)
+            check(hipMemcpyAsync(&mirror, h->partner.as<int32_t>() + leaf, 4,
+                                 hipMemcpyDeviceToHost, st),
+                  "mirror");
         check(hipStreamSynchronize(st), "sync");
         const int64_t m = bl.y - bl.x, nc = bl.w - bl.z;
         const size_t esz = h->ssz;  // stored entry size
@@ -2050,27 +2235,34 @@ hmx_status hmx_get_factors(hmx_hmatrix h, int64_t leaf, double* U, double* V, in
                 }
             }
         };
-        // V: one column-major region
-        std::vector<char> raw((size_t)r * nc * esz + 1);
-        d2h(raw.data(), (const char*)h->V.p + vo * esz, (size_t)r * nc * esz, st);
-        to_double(raw, (size_t)r * nc, V);
-        // U: the factor pieces of this leaf, one per row tile, in the tile-major pool
-        std::vector<Piece> pcs(h->npieces);
-        d2h(pcs.data(), h->pieces.p, h->npieces * sizeof(Piece), st);
         std::vector<int32_t> tlo(h->ntiles + 1);
         d2h(tlo.data(), h->tile_lo.p, (h->ntiles + 1) * 4, st);
-        for (const Piece& pc : pcs) {
-            if (pc.blk != (int32_t)leaf) continue;
-            const int mt = tlo[pc.tile + 1] - tlo[pc.tile];
-            const int R = rows_per_unit(h->smode, h->nmode);
-            const int ld = (mt + R - 1) / R * R;
-            std::vector<char> col((size_t)ld * r * esz + 1);
-            d2h(col.data(), (const char*)h->upool.p + pc.d_off * esz, (size_t)ld * r * esz, st);
-            std::vector<double> cd((size_t)ld * r);
-            to_double(col, (size_t)ld * r, cd.data());
-            for (int l = 0; l < r; ++l)
-                for (int i = 0; i < mt; ++i) U[(int64_t)l * m + pc.row0 + i] = cd[(size_t)l * ld + i];
-        }
+        // the rows of leaf blk's r columns held by its pieces in a row-tile
+        // pool (one piece per row tile), into out (len x r, column-major)
+        auto rows_of = [&](const DevBuf& dpcs, int64_t npcs, int32_t blk, const DevBuf& pool, int R,
+                           int64_t len, double* out) {
+            std::vector<Piece> pcs(npcs);
+            if (npcs > 0) d2h(pcs.data(), dpcs.p, npcs * sizeof(Piece), st);
+            for (const Piece& pc : pcs) {
+                if (pc.blk != blk) continue;
+                const int mt = tlo[pc.tile + 1] - tlo[pc.tile];
+                const int ld = (mt + R - 1) / R * R;
+                std::vector<char> col((size_t)ld * r * esz + 1);
+                d2h(col.data(), (const char*)pool.p + pc.d_off * esz, (size_t)ld * r * esz, st);
+                std::vector<double> cd((size_t)ld * r);
+                to_double(col, (size_t)ld * r, cd.data());
+                for (int l = 0; l < r; ++l)
+                    for (int i = 0; i < mt; ++i)
+                        out[(int64_t)l * len + pc.row0 + i] = cd[(size_t)l * ld + i];
+            }
+        };
+        // U: the leaf's factor pieces; V: its V pieces, or (symmetric far
+        // field) the factor pieces of its mirror, whose rows are sigma's
+        rows_of(h->pieces, h->npieces, (int32_t)leaf, h->upool, h->Ru, m, U);
+        if (mirror != (int32_t)leaf)
+            rows_of(h->pieces, h->npieces, mirror, h->upool, h->Ru, nc, V);
+        else
+            rows_of(h->vpieces, h->nvpieces, (int32_t)leaf, h->vtpool, h->Rv, nc, V);
     } catch (const Fail& f) {
         return f.s;
     }

@@ -312,12 +312,6 @@ hipError_t launch_aca_work(const int4* blocks, const int32_t* rank, const int32_
                            int64_t nb, unsigned long long* out, hipStream_t st);
 hipError_t launch_int_stats(const int32_t* a, int64_t n, unsigned long long* out,
                             hipStream_t st);
-// one record per factor column for phase 1: {V offset low, high, first point
-// of sigma_b, |sigma_b|}
-hipError_t launch_col_meta(const int4* adm, const int32_t* rank, const int64_t* toff,
-                           const int64_t* voff, int64_t nadm, int4* meta, hipStream_t st);
-hipError_t launch_far_phase1(const int4* col_meta, int64_t ncols_total, const void* V,
-                             void* vecpool, int64_t n, int smode, hipStream_t st);
 // config < 0: default tile shape; else shape config % kRowtileShapes, grid
 // config / kRowtileShapes: one workgroup per tile, a persistent grid of
 // kPersistentGrid workgroups, or one workgroup per (tile, row pass)
@@ -383,6 +377,55 @@ hipError_t launch_scatter_i32(const int32_t* list, int64_t nl, const int32_t* sr
                               int add, hipStream_t st);
 hipError_t launch_scatter_i64(const int32_t* list, int64_t nl, const int64_t* src, int64_t* dst,
                               hipStream_t st);
+
+// far-field phase 1 by row tiles and the symmetric far field (k_phase1.hip)
+// tile pass: partial[pbase + c] for every source column c of every tile
+// (meta[ms t + 1]: first source column of tile t, meta[ms t + 2]: its data
+// offset in pool; tiles padded to multiples of R rows)
+hipError_t launch_p1_tile(int64_t ntiles, const int32_t* tile_lo, const int64_t* meta, int ms,
+                          int R, int max_tile, const void* pool, const void* vec, void* partial,
+                          int64_t pbase, int smode, hipStream_t st);
+// t entries: vec[n + k] = sum over j < rec[k].nt of partial[pfc[base + j] + l]
+hipError_t launch_p1_reduce(const int4* rec, int64_t ncols, const int64_t* pfc,
+                            const void* partial, void* vec, int64_t n, int f64, hipStream_t st);
+hipError_t launch_p1_rec(const int32_t* rank, const int64_t* toff, const int64_t* sbase,
+                         const int32_t* snt, int64_t nadm, int4* rec, hipStream_t st);
+hipError_t launch_p1_source(int64_t nadm, const int32_t* partner, const int64_t* cnt,
+                            const int64_t* cntv, int64_t vbase, int64_t* sbase, int32_t* snt,
+                            hipStream_t st);
+hipError_t launch_pfc(const Piece* sorted, const uint32_t* order, const int64_t* colscan,
+                      int64_t np, int64_t limit, int64_t cbase, int64_t* pfc, hipStream_t st);
+// mirror table of the admissible leaves (keys/vals: sort scratch of nadm)
+hipError_t launch_mirror_keys(const int4* adm, int64_t nadm, uint64_t* keys, uint32_t* vals,
+                              hipStream_t st);
+hipError_t launch_mirror_find(const int4* adm, int64_t nadm, const uint64_t* keys,
+                              const uint32_t* vals, int32_t* partner, int* bad, hipStream_t st);
+hipError_t launch_primary_flags(const int4* adm, int64_t nadm, int sym, int64_t* flag,
+                                hipStream_t st);
+hipError_t launch_gather_list(const int64_t* pos, int64_t nadm, const int4* adm,
+                              const int32_t* level, const int32_t* rt, int32_t* list,
+                              int4* blocks, int32_t* lev, int32_t* rt_out, hipStream_t st);
+// list null: entry i is leaf i; partner null: no mirrors
+hipError_t launch_scatter_list(const int32_t* list, int64_t nl, const int32_t* partner,
+                               const int32_t* rank_l, const int32_t* steps_l, const int64_t* ue,
+                               const int64_t* ve, int32_t* rank, int32_t* steps, int64_t* rfo,
+                               int64_t* vfo, hipStream_t st);
+// the V pool: pieces of V_b rows per row tile of sigma_b (partner null: every
+// leaf, else the leaves that are their own mirror)
+hipError_t launch_vpiece_count(const int4* adm, int64_t nadm, const int32_t* rank,
+                               const int32_t* partner, const int32_t* tile_of_point, int64_t* cnt,
+                               hipStream_t st);
+hipError_t launch_vpiece_fill(const int4* adm, int64_t nadm, const int32_t* rank,
+                              const int64_t* cnt, const int32_t* tile_of_point,
+                              const int32_t* tile_lo, Piece* pieces, uint64_t* keys,
+                              uint32_t* vals, hipStream_t st);
+hipError_t launch_vpiece_sizes(const Piece* src, const uint32_t* order, int64_t np, Piece* dst,
+                               const int32_t* tile_lo, int R, int64_t* size, int64_t* cols,
+                               hipStream_t st);
+hipError_t launch_vpiece_layout(Piece* pieces, int64_t np, const int64_t* doff, hipStream_t st);
+hipError_t launch_vpiece_data(const Piece* pieces, int64_t np, const int32_t* tile_lo,
+                              const int4* adm, const int64_t* vfo, const void* src, int R,
+                              void* pool, int smode, hipStream_t st);
 
 // batched build assembly (k_batch.hip)
 hipError_t launch_add_i32(int32_t* dst, const int32_t* src, int64_t cnt, int32_t c,

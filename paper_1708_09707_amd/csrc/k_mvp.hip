@@ -485,130 +485,6 @@ __global__ void chunk_bounds_kernel(const int64_t* __restrict__ cap_off, int64_t
     bnd[k] = lo;
 }
 
-// column -> admissible leaf map for the flattened factor columns
-// phase-1 record of factor column k = toff[b] + l of admissible block b:
-// {V offset (low, high 32 bits), first point of sigma_b, |sigma_b|}, so a
-// phase-1 wave finds its column with one load
-__global__ void col_meta_kernel(const int4* __restrict__ adm, const int32_t* __restrict__ rank,
-                                const int64_t* __restrict__ toff,
-                                const int64_t* __restrict__ voff, int64_t nadm,
-                                int4* __restrict__ meta) {
-    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (b >= nadm) return;
-    const int64_t o = toff[b];
-    const int4 bl = adm[b];
-    const int nc = bl.w - bl.z;
-    for (int l = 0; l < rank[b]; ++l) {
-        const int64_t cofs = voff[b] + (int64_t)l * nc;
-        meta[o + l] = int4{(int)(uint32_t)cofs, (int)(uint32_t)(cofs >> 32), bl.z, nc};
-    }
-}
-
-// phase 1: t_b[l] = sum_j V_b[j, l] x[slo + j]; one wave per column of the
-// flattened list of all factor columns (lane j: 16-byte vectors j, j + 64,
-// ... in order, then a DPP sum over the wave)
-template <typename T>
-__device__ __forceinline__ void load_x16(const T* p, T* o);
-template <>
-__device__ __forceinline__ void load_x16<float>(const float* p, float* o) {
-    const f32x4 v = *(const f32x4*)p;
-    o[0] = v[0];
-    o[1] = v[1];
-    o[2] = v[2];
-    o[3] = v[3];
-}
-template <>
-__device__ __forceinline__ void load_x16<double>(const double* p, double* o) {
-    const f64x2 v = *(const f64x2*)p;
-    o[0] = v[0];
-    o[1] = v[1];
-}
-
-// sum over the wave with DPP moves (in registers, no LDS round trips): pairs,
-// quads, half rows, rows, then (row 0 + row 1) + (row 2 + row 3) read from
-// one lane of each row; the result is the same on every lane
-template <int CTRL>
-__device__ __forceinline__ float p1_dpp(float v) {
-    return __builtin_bit_cast(
-        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ double p1_dpp(double v) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
-    const uint32_t hi =
-        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-__device__ __forceinline__ float p1_lane(float v, int l) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
-}
-__device__ __forceinline__ double p1_lane(double v, int l) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-template <typename T>
-__device__ __forceinline__ T p1_wave_total(T v) {
-    v += p1_dpp<0xB1>(v);   // quad_perm [1,0,3,2]: pairs
-    v += p1_dpp<0x4E>(v);   // quad_perm [2,3,0,1]: quads
-    v += p1_dpp<0x141>(v);  // row_half_mirror: eight lanes
-    v += p1_dpp<0x140>(v);  // row_mirror: sixteen lanes
-    return (p1_lane(v, 0) + p1_lane(v, 16)) + (p1_lane(v, 32) + p1_lane(v, 48));
-}
-
-template <typename S, typename T>
-__global__ __launch_bounds__(256) void far_phase1_kernel(const int4* __restrict__ col_meta,
-                                                         const S* __restrict__ V,
-                                                         T* __restrict__ vec, int64_t n,
-                                                         int64_t ncols_total) {
-    constexpr int VS = Dec<S, T>::n;  // values per 16-byte load of V
-    constexpr int VT = 16 / sizeof(T);
-    const int lane = threadIdx.x & 63;
-    const int64_t k = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    if (k >= ncols_total) return;
-    const int4 cm = col_meta[k];
-    const int nc = cm.w;
-    const int64_t cofs = (int64_t)(((uint64_t)(uint32_t)cm.y << 32) | (uint32_t)cm.x);
-    const S* __restrict__ col = V + cofs;
-    const T* __restrict__ xs = vec + cm.z;
-    T acc = 0;
-    if ((cofs % VS) == 0 && (nc % VS) == 0 && ((int64_t)cm.z % VT) == 0) {
-        const u32x4* __restrict__ c16 = (const u32x4*)col;
-        const int nv = nc / VS;
-        for (int j = lane; j < nv; j += 64) {
-            T a[VS], xv[VS];
-            Dec<S, T>::get(nt_load(c16 + j), a);
-#pragma unroll
-            for (int u = 0; u < VS / VT; ++u) load_x16<T>(xs + (int64_t)j * VS + u * VT, xv + u * VT);
-#pragma unroll
-            for (int e = 0; e < VS; ++e) acc += a[e] * xv[e];
-        }
-    } else {
-        // the same assignment of entries to lanes and the same order as the
-        // vector path (lane j: entries j VS .. j VS + VS - 1), so a column's
-        // sum does not depend on where it lies in the pool
-        const int nv = (nc + VS - 1) / VS;
-        for (int j = lane; j < nv; j += 64) {
-#pragma unroll
-            for (int e = 0; e < VS; ++e) {
-                const int i = j * VS + e;
-                if (i < nc) {
-                    T a;
-                    if constexpr (sizeof(S) == 2)
-                        a = __uint_as_float((uint32_t)(*(const uint16_t*)(col + i)) << 16);
-                    else
-                        a = (T)col[i];
-                    acc += a * xs[i];
-                }
-            }
-        }
-    }
-    const T tot = p1_wave_total(acc);
-    if (lane == 0) vec[n + k] = tot;
-}
-
 // phase 2: one workgroup per row tile (or per row pass of a tile, the split
 // grid of the autotuner's third group).  The tile is a contiguous ld x C
 // column-major matrix; column k is weighted by vec[widx[k]].  Weights are
@@ -1071,31 +947,6 @@ hipError_t launch_int_stats(const int32_t* a, int64_t n, unsigned long long* out
     if (e != hipSuccess || n == 0) return e;
     hipLaunchKernelGGL(int_stats_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a,
                        n, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_col_meta(const int4* adm, const int32_t* rank, const int64_t* toff,
-                           const int64_t* voff, int64_t nadm, int4* meta, hipStream_t st) {
-    if (nadm == 0) return hipSuccess;
-    hipLaunchKernelGGL(col_meta_kernel, dim3((unsigned)((nadm + 255) / 256)), dim3(256), 0, st,
-                       adm, rank, toff, voff, nadm, meta);
-    return hipGetLastError();
-}
-
-hipError_t launch_far_phase1(const int4* col_meta, int64_t ncols_total, const void* V,
-                             void* vecpool, int64_t n, int smode, hipStream_t st) {
-    if (ncols_total == 0) return hipSuccess;
-    const int64_t nblk = (ncols_total + 3) / 4;  // 4 waves (columns) per workgroup
-    if (nblk > 0x7fffffffll) return hipErrorInvalidValue;
-    if (smode == 0)
-        hipLaunchKernelGGL((far_phase1_kernel<double, double>), dim3((unsigned)nblk), dim3(256),
-                           0, st, col_meta, (const double*)V, (double*)vecpool, n, ncols_total);
-    else if (smode == 1)
-        hipLaunchKernelGGL((far_phase1_kernel<float, float>), dim3((unsigned)nblk), dim3(256), 0,
-                           st, col_meta, (const float*)V, (float*)vecpool, n, ncols_total);
-    else
-        hipLaunchKernelGGL((far_phase1_kernel<uint16_t, float>), dim3((unsigned)nblk), dim3(256),
-                           0, st, col_meta, (const uint16_t*)V, (float*)vecpool, n, ncols_total);
     return hipGetLastError();
 }
 

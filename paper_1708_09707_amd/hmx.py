@@ -52,7 +52,7 @@ class hmx_params(C.Structure):
                 ("rank_mode", C.c_int), ("aca_chunk_mb", C.c_int32),
                 ("aca_only", C.c_int32), ("mlp", C.c_void_p),
                 ("learned_one_shot", C.c_int32), ("near_recompute", C.c_int32),
-                ("aca_split_rows", C.c_int32), ("reserved", C.c_int32)]
+                ("aca_split_rows", C.c_int32), ("symmetric_far", C.c_int32)]
 
 
 class hmx_stats(C.Structure):

@@ -37,7 +37,7 @@ def test_struct_layout_matches_c(tmp_path):
 int main(void) {
   printf("%zu %zu %zu\\n", sizeof(hmx_params), sizeof(hmx_stats), sizeof(hmx_kernel));
   printf("%zu %zu %zu %zu %zu\\n", offsetof(hmx_params, max_rank), offsetof(hmx_params, sigma2),
-         offsetof(hmx_params, rank_mode), offsetof(hmx_params, reserved),
+         offsetof(hmx_params, rank_mode), offsetof(hmx_params, symmetric_far),
          offsetof(hmx_params, storage_dtype));
   printf("%zu %zu %zu %zu\\n", offsetof(hmx_stats, matvec_bytes), offsetof(hmx_stats, device_bytes),
          offsetof(hmx_stats, level_sizes), offsetof(hmx_stats, v_entries));
@@ -50,7 +50,7 @@ int main(void) {
     out = subprocess.check_output([str(exe)]).decode().split()
     want = [C.sizeof(hmx.hmx_params), C.sizeof(hmx.hmx_stats), C.sizeof(hmx.hmx_kernel),
             hmx.hmx_params.max_rank.offset, hmx.hmx_params.sigma2.offset,
-            hmx.hmx_params.rank_mode.offset, hmx.hmx_params.reserved.offset,
+            hmx.hmx_params.rank_mode.offset, hmx.hmx_params.symmetric_far.offset,
             hmx.hmx_params.storage_dtype.offset,
             hmx.hmx_stats.matvec_bytes.offset, hmx.hmx_stats.device_bytes.offset,
             hmx.hmx_stats.level_sizes.offset, hmx.hmx_stats.v_entries.offset]

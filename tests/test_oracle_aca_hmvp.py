@@ -286,3 +286,58 @@ def test_aca_trace_describes_the_run(orc):
     assert np.all(tr[: r - 1, 3] > 1.0) and tr[r - 1, 3] <= 1.0
     assert np.all((tr[:, 2] >= 0) & (tr[:, 2] <= 1)) and np.all((tr[:, 4] >= 0) & (tr[:, 4] <= 1))
     assert len(set(tr[:, 1].astype(int))) == r  # distinct columns
+
+
+def test_symmetric_far_field_oracle(orc):
+    """The symmetric far field: each admissible leaf with tau before sigma is
+    approximated once and its mirror (sigma, tau) applies V U^T.  Pinned by
+    (a) exact symmetry of the operator, which the two-sided form lacks,
+    (b) an independent assembly of the dense H from the leaves (ACA of the
+    primary leaves, transposed at their mirrors, dense leaves entry by
+    entry), (c) the error bound against the dense product, (d) the ranks:
+    a mirror carries its primary's rank and a primary's rank is the
+    two-sided run's, (e) exact ACA reducing it to the dense product."""
+    n, leaf, eta, kmax, eps, p0 = 1500, 32, 1.5, 32, 1e-7, 0.05
+    p = synth.uniform_points(n, 2, 4401)
+    x = synth.normal_vector(n, 4402)
+    y = synth.normal_vector(n, 4403)
+    kw = dict(want_ranks=True)
+    zx, rs, st = orc.hmvp(p, x, "gaussian", p0, leaf, eta, kmax, eps, symmetric=True, **kw)
+    zy, _, _ = orc.hmvp(p, y, "gaussian", p0, leaf, eta, kmax, eps, symmetric=True)
+    zx2, r2, st2 = orc.hmvp(p, x, "gaussian", p0, leaf, eta, kmax, eps, **kw)
+    zy2, _, _ = orc.hmvp(p, y, "gaussian", p0, leaf, eta, kmax, eps)
+    asym = abs(y @ zx - x @ zy) / (np.linalg.norm(y) * np.linalg.norm(zx))
+    asym2 = abs(y @ zx2 - x @ zy2) / (np.linalg.norm(y) * np.linalg.norm(zx2))
+    assert asym <= 1e-14 and asym2 > 100 * asym, (asym, asym2)
+    # (b) assembly of the dense H in Morton order from the leaves
+    _, perm, soa = orc.order(p)
+    adm, den, _ = orc.partition(soa, leaf, eta)
+    Hm = np.zeros((n, n))
+    for b in den:
+        Hm[b[0]:b[1], b[2]:b[3]] = orc.dense_block(soa, "gaussian", p0, *b[:4])
+    for b in adm:
+        if b[0] > b[2]:
+            continue
+        U, V, r, _ = orc.aca(soa, "gaussian", p0, *b[:4], kmax, eps)
+        Hm[b[0]:b[1], b[2]:b[3]] = U @ V.T
+        Hm[b[2]:b[3], b[0]:b[1]] = (U @ V.T).T
+    zm = np.empty(n)
+    zm[perm] = Hm @ x[perm]
+    assert np.linalg.norm(zm - zx) <= 1e-13 * np.linalg.norm(zx)
+    # (c) the bound of the two-sided form
+    zd = orc.dense_matvec(p, x, "gaussian", p0)
+    assert np.linalg.norm(zx - zd) <= 10 * eps * np.linalg.norm(zd)
+    # (d) ranks: mirrors carry their primary's, primaries the two-sided run's
+    key = {(int(b[0]), int(b[2])): q for q, b in enumerate(adm)}
+    prim = adm[:, 0] <= adm[:, 2]
+    assert np.array_equal(rs[prim], r2[prim])
+    for q, b in enumerate(adm):
+        if b[0] > b[2]:
+            assert rs[q] == rs[key[(int(b[2]), int(b[0]))]]
+    assert st["sum_rank"] == rs.sum() and st["factor_entries"] < st2["factor_entries"]
+    # (e) exact ACA: the dense product
+    q = synth.uniform_points(600, 2, 4404)
+    xq = synth.normal_vector(600, 4405)
+    ze, _, _ = orc.hmvp(q, xq, "gaussian", p0, 16, eta, 128, 0.0, eps0=0.0, symmetric=True)
+    zdq = orc.dense_matvec(q, xq, "gaussian", p0)
+    assert np.linalg.norm(ze - zdq) <= 1e-12 * np.linalg.norm(zdq)
