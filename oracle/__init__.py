@@ -20,8 +20,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hmxo.c")
 _LIB = os.path.join(_HERE, "libhmxo.so")
 
-GAUSSIAN, MATERN32, CONST, LOWRANK = 0, 1, 3, 4
-KINDS = {"gaussian": GAUSSIAN, "matern32": MATERN32, "const": CONST, "lowrank": LOWRANK}
+GAUSSIAN, MATERN32, MATERN_NU1, CONST, LOWRANK = 0, 1, 2, 3, 4
+KINDS = {"gaussian": GAUSSIAN, "matern32": MATERN32, "matern_nu1": MATERN_NU1, "const": CONST,
+         "lowrank": LOWRANK}
 
 
 def build(force: bool = True) -> str:
@@ -48,6 +49,8 @@ def lib():
         i32, i64, f64 = C.c_int32, C.c_int64, C.c_double
         L.hmxo_kernel.restype = f64
         L.hmxo_kernel.argtypes = [C.c_int, f64, P, P, C.c_int]
+        L.hmxo_xk1.restype = f64
+        L.hmxo_xk1.argtypes = [f64]
         L.hmxo_global_box.argtypes = [P, i64, i32, P, P]
         L.hmxo_morton.argtypes = [P, i64, i32, P, P, P]
         L.hmxo_sort.argtypes = [P, i64, P]
@@ -98,6 +101,11 @@ def num_threads() -> int:
 def kernel(kind, p0, x, y):
     x, y = _f64(x), _f64(y)
     return lib().hmxo_kernel(kind_of(kind), float(p0), _p(x), _p(y), int(x.shape[0]))
+
+
+def xk1(s):
+    """s K_1(s) (modified Bessel function of the second kind, order 1)."""
+    return lib().hmxo_xk1(float(s))
 
 
 def global_box(pts):

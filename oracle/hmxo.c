@@ -32,6 +32,50 @@ int hmxo_num_threads(void)
 /* Kernel functions (eq. (2) matrix entries; Section 6.2 model problem with a
  * length scale, and two exactly-low-rank test kernels).                     */
 /* ------------------------------------------------------------------------ */
+/* s K_1(s), written out from two textbook representations of K_1:
+ *  - s <= 2: the power series of K_n at n = 1 (Abramowitz & Stegun 9.6.11),
+ *      K_1(s) = 1/s + ln(s/2) I_1(s)
+ *               - (s/4) sum_k (psi(k+1) + psi(k+2)) q^k / (k! (k+1)!),
+ *      I_1(s) = (s/2) sum_k q^k / (k! (k+1)!),  q = s^2/4,
+ *    psi(1) = -Euler's gamma, psi(k+1) = psi(k) + 1/k; the sums run until
+ *    their terms no longer change them;
+ *  - s > 2: the integral K_1(s) = int_0^inf exp(-s cosh t) cosh t dt
+ *    (A&S 9.6.24) by the trapezoidal rule, written as
+ *      s K_1(s) = s e^-s int_0^inf exp(-2 s sinh^2(t/2)) cosh t dt
+ *    with step h = 0.25 / sqrt(s) (the integrand's width is about 1/sqrt(s)),
+ *    summed until a term is below 1e-20 of the sum. */
+double hmxo_xk1(double s)
+{
+    if (s == 0.0) return 1.0;
+    if (s <= 2.0) {
+        const double euler_gamma = 0.57721566490153286061;
+        double q = 0.25 * s * s;
+        double a = 1.0, s1 = 0.0, s2 = 0.0;
+        double psi1 = -euler_gamma, psi2 = 1.0 - euler_gamma; /* psi(k+1), psi(k+2) */
+        for (int k = 0; k < 60; ++k) {
+            double n1 = s1 + a, n2 = s2 + (psi1 + psi2) * a;
+            if (n1 == s1 && n2 == s2) break;
+            s1 = n1;
+            s2 = n2;
+            a = a * q / ((double)(k + 1) * (double)(k + 2));
+            psi1 += 1.0 / (double)(k + 1);
+            psi2 += 1.0 / (double)(k + 2);
+        }
+        /* s K_1(s) = 1 + s ln(s/2) I_1(s) - (s^2/4) S2 with s I_1(s) = 2 q S1 */
+        return 1.0 + 2.0 * q * log(0.5 * s) * s1 - q * s2;
+    }
+    double h = 0.25 / sqrt(s);
+    double sum = 0.5; /* the t = 0 term, halved */
+    for (int k = 1; k < 100000; ++k) {
+        double t = k * h;
+        double sh = sinh(0.5 * t);
+        double term = exp(-2.0 * s * sh * sh) * cosh(t);
+        sum += term;
+        if (term < 1e-20 * sum) break;
+    }
+    return s * exp(-s) * h * sum;
+}
+
 double hmxo_kernel(int kind, double p0, const double* x, const double* y, int d)
 {
     double r2 = 0.0, dot = 0.0;
@@ -46,6 +90,11 @@ double hmxo_kernel(int kind, double p0, const double* x, const double* y, int d)
     case HMXO_MATERN32: {
         double s = sqrt(3.0) * sqrt(r2) / p0;
         return (1.0 + s) * exp(-s);
+    }
+    case HMXO_MATERN_NU1: {
+        /* beta = 1 + d/2: the normalisation 2^(beta-1) Gamma(beta) */
+        double beta = 1.0 + 0.5 * d;
+        return hmxo_xk1(sqrt(r2) / p0) / (pow(2.0, beta - 1.0) * tgamma(beta));
     }
     case HMXO_CONST:
         return 1.0;

@@ -24,10 +24,17 @@ extern "C" {
 /* kernel kinds; p0 is the kernel parameter */
 #define HMXO_GAUSSIAN 0   /* exp(-r^2 / p0)                                */
 #define HMXO_MATERN32 1   /* (1 + sqrt(3) r / p0) exp(-sqrt(3) r / p0)      */
+#define HMXO_MATERN_NU1 2 /* Section 6.2 Matern, beta - d/2 = 1, length p0:
+                             (r/p0) K_1(r/p0) / (2^(beta-1) Gamma(beta)),
+                             beta = 1 + d/2                                 */
 #define HMXO_CONST    3   /* 1 (rank-one matrix)                            */
 #define HMXO_LOWRANK  4   /* (1 + x.y)^2 (rank <= 1 + d + d(d+1)/2)         */
 
 double hmxo_kernel(int kind, double p0, const double* x, const double* y, int d);
+
+/* s K_1(s) for s >= 0 (modified Bessel function of the second kind, order 1;
+ * the limit 1 at s = 0) */
+double hmxo_xk1(double s);
 
 /* Section 4.4 (Z-order curve) and Algorithm 6 */
 int hmxo_global_box(const double* pts, int64_t n, int32_t d, double* lo, double* hi);

@@ -11,6 +11,7 @@ results section (points in the unit square / cube) and the synthetic point
 clouds this project measures on:
 
 * uniform i.i.d. points in [0,1)^d,
+* the Halton sequence (deterministic low-discrepancy points) in [0,1)^d,
 * a Gaussian mixture in [0,1]^d (rejection of out-of-cube samples),
 * standard-normal right-hand sides x,
 * the regression target y = sin(2 pi p0) p1 + 0.01 xi of the kernel ridge
@@ -51,6 +52,27 @@ def gmm_points(n: int, d: int, seed: int, ncomp: int = 32, std_lo: float = 0.02,
         p = p[ok][: n - filled]
         out[filled: filled + len(p)] = p
         filled += len(p)
+    return np.ascontiguousarray(out.astype(dtype))
+
+
+def halton_points(n: int, d: int, start: int = 1, dtype=np.float64) -> np.ndarray:
+    """The first n points of the Halton sequence in [0,1)^d (the point sets of
+    the paper's model problem, Section 6.2): coordinate k of point i is the
+    radical inverse of the index start + i in the k-th prime base (2, 3, 5),
+    i.e. the base-b digits of the index mirrored at the radix point.  The
+    default start 1 skips the origin."""
+    bases = (2, 3, 5)[: int(d)]
+    idx = np.arange(int(start), int(start) + int(n), dtype=np.int64)
+    out = np.empty((int(n), int(d)), dtype=np.float64)
+    for k, b in enumerate(bases):
+        v = np.zeros(int(n), dtype=np.float64)
+        f = 1.0 / b
+        i = idx.copy()
+        while np.any(i > 0):
+            v += f * (i % b)
+            i //= b
+            f /= b
+        out[:, k] = v
     return np.ascontiguousarray(out.astype(dtype))
 
 

@@ -107,3 +107,15 @@ def test_ordered_coords(orc):
     p = synth.uniform_points(777, 3, 6)
     codes, perm, soa = orc.order(p)
     assert np.array_equal(soa, p[perm].T)
+
+
+def test_halton_points_first_terms():
+    """Radical inverses: index 1..4 in base 2 are 1/2, 1/4, 3/4, 1/8; in base
+    3 1/3, 2/3, 1/9, 4/9; in base 5 1/5, 2/5, 3/5, 4/5."""
+    import synth
+    p = synth.halton_points(4, 3)
+    want = np.array([[1 / 2, 1 / 3, 1 / 5], [1 / 4, 2 / 3, 2 / 5], [3 / 4, 1 / 9, 3 / 5],
+                     [1 / 8, 4 / 9, 4 / 5]])
+    assert np.allclose(p, want, rtol=0, atol=4e-16)
+    q = synth.halton_points(4096, 2)
+    assert q.min() > 0 and q.max() < 1 and len(np.unique(q[:, 0])) == 4096
