@@ -49,6 +49,7 @@ def lib():
         i32, i64, f64 = C.c_int32, C.c_int64, C.c_double
         L.hmxo_kernel.restype = f64
         L.hmxo_kernel.argtypes = [C.c_int, f64, P, P, C.c_int]
+        L.hmxo_dense_matmat.argtypes = [P, i64, i32, i32, f64, f64, P, i32, P, i64, P]
         L.hmxo_xk1.restype = f64
         L.hmxo_xk1.argtypes = [f64]
         L.hmxo_global_box.argtypes = [P, i64, i32, P, P]
@@ -261,9 +262,20 @@ def hmvp(pts, x, kind, p0, leaf, eta, kmax, eps, aca_eta=0.0, eps0=1e-14, fixed=
 
 
 def dense_matvec(pts, x, kind, p0, sigma2=0.0, rows=None):
+    """z = (A + sigma2 I) x (rows of z only, if given); x may be n x m."""
     pts = _f64(pts)
     n, d = pts.shape
     x = _f64(x)
+    if x.ndim == 2:
+        m = x.shape[1]
+        r = None if rows is None else np.ascontiguousarray(rows, np.int64)
+        cnt = n if r is None else r.shape[0]
+        Z = np.empty((cnt, m))
+        rc = lib().hmxo_dense_matmat(_p(pts), n, d, kind_of(kind), float(p0), float(sigma2),
+                                     _p(x), m, None if r is None else _p(r), cnt, _p(Z))
+        if rc != 0:
+            raise ValueError("at most 64 right-hand sides")
+        return Z
     if rows is None:
         z = np.empty(n)
         lib().hmxo_dense_matvec(_p(pts), n, d, kind_of(kind), float(p0), float(sigma2), _p(x),

@@ -849,6 +849,29 @@ int hmxo_dense_matvec(const double* pts, int64_t n, int32_t d, int32_t kind, dou
     return 0;
 }
 
+/* The same dense product for m right-hand sides at once (X: n x m
+ * row-major, Z: rows x m); each matrix entry is evaluated once and every
+ * column is summed in the order of hmxo_dense_matvec. */
+int hmxo_dense_matmat(const double* pts, int64_t n, int32_t d, int32_t kind, double p0,
+                      double sigma2, const double* X, int32_t m, const int64_t* rows,
+                      int64_t nrows, double* Z)
+{
+    if (m < 1 || m > 64) return -1;
+    int64_t cnt = rows ? nrows : n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < cnt; ++q) {
+        int64_t i = rows ? rows[q] : q;
+        double acc[64];
+        for (int c = 0; c < m; ++c) acc[c] = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double a = hmxo_kernel(kind, p0, pts + i * d, pts + j * d, d);
+            for (int c = 0; c < m; ++c) acc[c] += a * X[j * m + c];
+        }
+        for (int c = 0; c < m; ++c) Z[q * m + c] = acc[c] + sigma2 * X[i * m + c];
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Stored-mode H-matrix-vector product restricted to the Morton-order rows  */
 /* [row_lo, row_hi): every leaf whose tau meets the range is built (ACA or  */

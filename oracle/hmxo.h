@@ -126,6 +126,11 @@ int hmxo_hmvp_rows(const double* pts, int64_t n, int32_t d, int32_t kind, double
 int hmxo_dense_matvec(const double* pts, int64_t n, int32_t d, int32_t kind, double p0,
                       double sigma2, const double* x, const int64_t* rows, int64_t nrows,
                       double* z);
+/* the dense product for m <= 64 right-hand sides (X n x m, Z rows x m,
+ * row-major), each column summed as hmxo_dense_matvec sums it */
+int hmxo_dense_matmat(const double* pts, int64_t n, int32_t d, int32_t kind, double p0,
+                      double sigma2, const double* X, int32_t m, const int64_t* rows,
+                      int64_t nrows, double* Z);
 
 /* Conjugate gradients on the dense system (A + sigma2 I) x = b, x from 0,
  * stopping at |r| / |b| <= tol.  Returns 0 converged, 1 not converged,

@@ -34,6 +34,24 @@ def test_dense_matvec_matches_scipy(orc, kind, p0):
                        rtol=1e-12, atol=1e-12 * np.abs(want).max())
 
 
+@pytest.mark.parametrize("kind,p0", [("gaussian", 0.1), ("matern_nu1", 0.2)])
+def test_dense_matmat_columns_equal_matvec(orc, kind, p0):
+    """The multi-right-hand-side dense product sums every column as the
+    single-vector one does: equal bit for bit, with rows and the shift."""
+    p = synth.uniform_points(500, 2, 7)
+    X = np.stack([synth.normal_vector(500, 20 + c) for c in range(5)], axis=1)
+    Z = orc.dense_matvec(p, X, kind, p0, sigma2=0.25)
+    rows = np.array([3, 0, 499])
+    Zr = orc.dense_matvec(p, X, kind, p0, sigma2=0.25, rows=rows)
+    for c in range(5):
+        z = orc.dense_matvec(p, X[:, c], kind, p0, sigma2=0.25)
+        assert np.array_equal(Z[:, c], z)
+        assert np.array_equal(Zr[:, c], z[rows])
+    want = _dense(p, "gaussian", p0) @ X if kind == "gaussian" else None
+    if want is not None:
+        assert np.allclose(Z - 0.25 * X, want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
+
+
 def _block(seed=3, n=2000, d=2, leaf=64, eta=1.5, pick=-1):
     p = synth.uniform_points(n, d, seed)
     _, _, soa = __import__("oracle").order(p)
