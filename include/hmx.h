@@ -59,11 +59,18 @@ typedef enum { HMX_F64 = 0, HMX_F32 = 1, HMX_BF16 = 2 } hmx_dtype;
  *  HMX_GAUSSIAN  : exp(-r^2 / p0)                    (Section 6.2 with a length
  *                                                     scale, p0 = l^2 > 0)
  *  HMX_MATERN32  : (1 + sqrt(3) r / p0) exp(-sqrt(3) r / p0), p0 = l > 0
+ *  HMX_MATERN_NU1: the Matern kernel of Section 6.2 with beta - d/2 = 1,
+ *                  K_1(s) s / (2^(beta-1) Gamma(beta)), s = r / p0, beta =
+ *                  1 + d/2 (K_1: modified Bessel function of the second
+ *                  kind; value 1/(2^(d/2) Gamma(1 + d/2)) at r = 0); p0 = l
+ *                  > 0, the paper's unscaled kernel is p0 = 1.  Not for
+ *                  hmx_build_batched (its normalisation depends on d)
  *  HMX_TEST_CONST: 1 (rank-one matrix; test kernel)
  *  HMX_TEST_LOWRANK: (1 + x.y)^2 (rank <= 1 + d + d(d+1)/2; test kernel) */
 typedef enum {
     HMX_GAUSSIAN = 0,
     HMX_MATERN32 = 1,
+    HMX_MATERN_NU1 = 2,
     HMX_TEST_CONST = 3,
     HMX_TEST_LOWRANK = 4
 } hmx_kernel_kind;
@@ -101,7 +108,7 @@ typedef enum { HMX_RANK_ADAPTIVE = 0, HMX_RANK_LEARNED = 1, HMX_RANK_FIXED = 2 }
  *   [log2 |tau|, log2 |sigma|, diam(tau) / l, diam(sigma) / l, dist / l,
  *    min(diam(tau), diam(sigma)) / max(dist, 1e-12), d, log10 l^2]
  * (bounding-box diameters and distance of eq. (3); l the kernel's length
- * scale: sqrt(p0) for the Gaussian, p0 for Matern-3/2, 1 for the test
+ * scale: sqrt(p0) for the Gaussian, p0 for the Matern kernels, 1 for the test
  * kernels), standardised per feature as (f - mean) * scale.  Parameters are
  * packed W1 (64 x 8, row-major), b1, W2 (64 x 64), b2, W3 (64 x 64), b3,
  * W4 (1 x 64), b4: HMX_MLP_NPARAMS floats.  Trained with the pinball
@@ -168,6 +175,21 @@ typedef struct {
                                 approximations of both leaves.  The matvec
                                 reads every stored factor twice (as a leaf's
                                 U and as its mirror's V) */
+    /* Optional device allocator (both NULL: the library's own, which keeps
+     * released blocks in a process-wide cache for later builds; hmx_trim
+     * empties it).  When dev_alloc is set, every device buffer of this build
+     * and of the handle's later calls (hmx_autotune's scratch vectors,
+     * hmx_cg_solve's work vectors) is obtained as dev_alloc(bytes, alloc_ctx)
+     * (bytes a multiple of 256; the memory must be device memory of the
+     * current device, aligned to 256 bytes) and returned exactly once as
+     * dev_free(ptr, bytes, alloc_ctx): temporary buffers during the build,
+     * the handle's buffers by hmx_destroy.  A NULL return fails the call
+     * with HMX_ERR_OOM after every buffer obtained so far has been returned
+     * (no handle is produced).  The library synchronises before it returns a
+     * buffer that queued work may still use.  Both must be set, or neither. */
+    void* (*dev_alloc)(size_t bytes, void* ctx);
+    void (*dev_free)(void* ptr, size_t bytes, void* ctx);
+    void* alloc_ctx;
 } hmx_params;
 
 /* Statistics of a built H-matrix (host struct). */
@@ -236,9 +258,12 @@ hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t
  * params) as ONE handle: the block-diagonal H-matrix diag(H_1, ..., H_nprob)
  * over the concatenated index set, problem p owning indices
  * [off_p, off_p + n_p) with off_p = n_0 + ... + n_{p-1}.  Every problem's
- * ordering, cluster tree and block partition are those of its own build; the
- * ACA of all problems' admissible leaves, the near field and every matvec
- * then run as single batched launches over the union.  hmx_matvec and
+ * ordering, cluster tree and block partition are those of its own build (bit
+ * for bit), computed for all problems at once: one launch per step (boxes,
+ * Morton codes, the sort, each tree and box level, each block-tree level of
+ * the traversal, with one host readback per block-tree level for all
+ * problems).  The ACA of all problems' admissible leaves, the near field and
+ * every matvec then run as single batched launches over the union.  hmx_matvec and
  * hmx_cg_solve on the handle act on concatenated vectors of n_0 + ... +
  * n_{nprob-1} entries (each problem in its own original point order).
  * Internally problem p's coordinates are divided by its kernel length
@@ -246,9 +271,10 @@ hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t
  * entries may differ from a single build's in the last bits.
  *   points : host array of nprob device pointers (n_p x d_p row-major, all
  *            in pts_dtype); n, d, kernels: host arrays of nprob entries.
- * hmx_get_partition lists the leaves of all problems in union indices
- * (upper-level leaves of all problems first, each problem in canonical
- * order); hmx_get_boxes and hmx_block_features return UNSUPPORTED.
+ * hmx_get_partition lists the leaves of all problems in union indices, each
+ * problem's leaves in its canonical order (the admissible leaves grouped by
+ * the ACA's size classes, the dense ones level by level);
+ * hmx_get_boxes, hmx_block_features and hmx_rank_predict return UNSUPPORTED.
  * Limits: sum of n_p < 2^31.  Host-blocking like hmx_build. */
 hmx_status hmx_build_batched(int32_t nprob, const void* const* points, hmx_dtype pts_dtype,
                              const int64_t* n, const int32_t* d, const hmx_kernel* kernels,
@@ -266,6 +292,18 @@ hmx_status hmx_get_batch(hmx_hmatrix h, int32_t* nprob, int64_t* offsets);
  * Fully asynchronous on `stream`; allocates nothing. */
 hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype, double alpha,
                       double beta, void* stream);
+
+/* Matvecs of nprob separately built handles on one stream:
+ * z[q] := alpha (H_q + sigma2_q I) x[q] + beta z[q] for q = 0..nprob-1 (host
+ * arrays of nprob handles and device pointers; each pair of vectors as for
+ * hmx_matvec on its handle).  Every argument is checked before the first
+ * launch.  The fused form of many problems is one handle from
+ * hmx_build_batched, whose every matvec is a single pass over all problems;
+ * this call serves handles built one by one.  Asynchronous; allocates
+ * nothing. */
+hmx_status hmx_matvec_batched(int32_t nprob, const hmx_hmatrix* handles, const void* const* x,
+                              void* const* z, hmx_dtype vec_dtype, double alpha, double beta,
+                              void* stream);
 
 /* ---- hipGraph-captured matvecs ---- */
 typedef struct hmx_graph_s* hmx_graph; /* opaque; an instantiated HIP graph */
@@ -370,6 +408,16 @@ hmx_status hmx_mlp_destroy(hmx_mlp m);
 hmx_status hmx_mlp_set_params(hmx_mlp m, const float* params, const float* mean,
                               const float* scale);
 hmx_status hmx_mlp_get_params(hmx_mlp m, float* params, float* mean, float* scale);
+
+/* Checkpoint of a predictor: hmx_mlp_save writes the parameters, the
+ * standardisation and the Adam state (moments and step count) to the file
+ * `path` (host string; a little-endian binary record: 8-byte magic
+ * "HMXMLP01", int64 parameter count and Adam step, then FP32 parameters,
+ * mean, scale, first and second moments).  hmx_mlp_load creates a predictor
+ * from such a file; a file of another size, magic or parameter count gives
+ * HMX_ERR_INVALID_ARG and no predictor.  Both synchronise the device. */
+hmx_status hmx_mlp_save(hmx_mlp m, const char* path);
+hmx_status hmx_mlp_load(const char* path, hmx_mlp* out);
 
 /* Set the standardisation from n training samples X (device, n x 8 FP32):
  * mean = sample mean, scale = 1 / population standard deviation (1 where it

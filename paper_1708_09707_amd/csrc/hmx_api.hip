@@ -13,6 +13,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <unordered_set>
 #include <vector>
 
 #include "hmx_internal.h"
@@ -49,6 +50,9 @@ struct DeviceCache {
     std::mutex mu;
     std::multimap<size_t, std::pair<int, void*>> blocks;  // size -> (device, ptr)
     size_t cached = 0;
+    // every block this library obtained with hipMalloc and has not freed:
+    // only these may enter the cache and be freed by it
+    std::unordered_set<void*> owned;
 };
 DeviceCache& cache() {
     static DeviceCache* c = new DeviceCache();  // never destroyed: process lifetime
@@ -82,35 +86,81 @@ hipError_t cache_alloc(void** p, size_t* bytes) {
         (void)hipGetLastError();
         std::lock_guard<std::mutex> lk(c.mu);
         (void)hipDeviceSynchronize();
-        for (auto& b : c.blocks) (void)hipFree(b.second.second);
+        for (auto& b : c.blocks) {
+            c.owned.erase(b.second.second);
+            (void)hipFree(b.second.second);
+        }
         c.blocks.clear();
         c.cached = 0;
         e = hipMalloc(p, *bytes);
     }
+    if (e == hipSuccess) {
+        std::lock_guard<std::mutex> lk(c.mu);
+        c.owned.insert(*p);
+    }
     return e;
 }
 
+// a block back into the cache; a pointer the library did not allocate is
+// never cached (so the cache never frees memory another allocator owns)
 void cache_free(void* p, size_t bytes) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     DeviceCache& c = cache();
     std::lock_guard<std::mutex> lk(c.mu);
+    if (c.owned.count(p) == 0) return;
     c.blocks.insert({bytes, {dev, p}});
     c.cached += bytes;
 }
 
-// owning device buffer (allocated through the cache)
+// A caller's device allocator (hmx_params.dev_alloc / dev_free / alloc_ctx).
+// While one is in scope on this thread (AllocScope: the build, and the
+// handle's own later allocations) every device buffer comes from it instead
+// of the library's cache.
+struct Allocator {
+    void* (*alloc)(size_t, void*) = nullptr;
+    void (*free)(void*, size_t, void*) = nullptr;
+    void* ctx = nullptr;
+};
+thread_local const Allocator* g_user_alloc = nullptr;
+
+struct AllocScope {
+    const Allocator* saved;
+    explicit AllocScope(const Allocator* a) : saved(g_user_alloc) {
+        g_user_alloc = (a && a->alloc) ? a : nullptr;
+    }
+    ~AllocScope() { g_user_alloc = saved; }
+    AllocScope(const AllocScope&) = delete;
+    AllocScope& operator=(const AllocScope&) = delete;
+};
+
+// owning device buffer (from the cache, or from the caller's allocator that
+// was in scope when it was allocated; it goes back to where it came from)
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    Allocator from{};
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release() {
-        if (p) cache_free(p, bytes);
+        if (p) {
+            if (from.alloc)
+                from.free(p, bytes, from.ctx);
+            else
+                cache_free(p, bytes);
+        }
         p = nullptr;
         bytes = 0;
+        from = Allocator{};
+    }
+    // exchange contents with another buffer: pointer, size and owner travel
+    // together, so each block still returns to the allocator it came from
+    void swap(DevBuf& o) {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+        std::swap(from, o.from);
     }
     template <typename T>
     T* as() const {
@@ -149,6 +199,20 @@ void check(hipError_t e, const char* what) {
 void alloc(DevBuf& b, size_t bytes, const char* what) {
     b.release();
     if (bytes == 0) bytes = 16;
+    if (g_user_alloc) {
+        bytes = (bytes + 255) / 256 * 256;
+        void* q = g_user_alloc->alloc(bytes, g_user_alloc->ctx);
+        if (!q) {
+            (void)hipDeviceSynchronize();  // in-flight work may still use released blocks
+            set_err("device allocation of %zu bytes for %s failed: the caller's allocator "
+                    "returned NULL", bytes, what);
+            throw Fail{HMX_ERR_OOM};
+        }
+        b.p = q;
+        b.bytes = bytes;
+        b.from = *g_user_alloc;
+        return;
+    }
     bytes = cache_round(bytes);
     hipError_t e = cache_alloc(&b.p, &bytes);
     if (e != hipSuccess) {
@@ -350,8 +414,19 @@ void finish_stats(hmx_hmatrix_s* h, std::chrono::steady_clock::time_point t_all)
 // length scale l of the predictor's features
 double kernel_length(const hmx_kernel& k) {
     if (k.kind == HMX_GAUSSIAN) return std::sqrt(k.p0);
-    if (k.kind == HMX_MATERN32) return k.p0;
+    if (k.kind == HMX_MATERN32 || k.kind == HMX_MATERN_NU1) return k.p0;
     return 1.0;
+}
+
+// the kernel function as the device kernels take it; the Matern nu = 1
+// kernel's normalisation 1 / (2^(beta-1) Gamma(beta)), beta = 1 + d/2
+KernelFn kernel_fn(const hmx_kernel& k, int d) {
+    KernelFn f{(int)k.kind, k.p0};
+    if (k.kind == HMX_MATERN_NU1) {
+        const double beta = 1.0 + 0.5 * d;
+        f.norm = 1.0 / (std::pow(2.0, beta - 1.0) * std::tgamma(beta));
+    }
+    return f;
 }
 
 // grow a device buffer to at least `bytes`, keeping the first `keep` bytes
@@ -362,8 +437,7 @@ void grow(DevBuf& b, size_t bytes, size_t keep, hipStream_t st, const char* what
     alloc(nbuf, nb, what);
     if (keep) check(hipMemcpyAsync(nbuf.p, b.p, keep, hipMemcpyDeviceToDevice, st), "grow copy");
     check(hipStreamSynchronize(st), "grow sync");
-    std::swap(b.p, nbuf.p);
-    std::swap(b.bytes, nbuf.bytes);
+    b.swap(nbuf);
 }
 
 int max_depth(int64_t n, int leaf) {
@@ -416,6 +490,10 @@ hmx_status check_params(const hmx_params& p) {
     }
     if (p.near_recompute != 0 && p.near_recompute != 1) {
         set_err("near_recompute must be 0 or 1");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if ((p.dev_alloc == nullptr) != (p.dev_free == nullptr)) {
+        set_err("dev_alloc and dev_free must both be set, or neither");
         return HMX_ERR_INVALID_ARG;
     }
     if (p.aca_split_rows < 0) {
@@ -603,12 +681,11 @@ void stage_partition(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t
                                         nxt.as<int2>(), h->adm.as<int4>(),
                                         h->adm_level.as<int32_t>(), h->adm_ids.as<int2>(),
                                         h->n_adm, h->dense.as<int4>(),
-                                        h->dense_level.as<int32_t>(), h->n_dense, st),
+                                        h->dense_level.as<int32_t>(), h->n_dense, nullptr, st),
                   "traverse write");
             h->n_adm += tot[0];
             h->n_dense += tot[2];
-            std::swap(cur.p, nxt.p);
-            std::swap(cur.bytes, nxt.bytes);
+            cur.swap(nxt);
             ncur = nnext;
             ++level;
         }
@@ -649,24 +726,40 @@ int64_t split_rows(const hmx_hmatrix_s* h) {
     return h->prm.aca_split_rows > 0 ? h->prm.aca_split_rows : kDefaultSplitRows;
 }
 
+// the first tree levels of the 512-thread, the 256-thread and the
+// single-wave class for a problem of n points (clusters at level l hold at
+// most ceil(n / 2^l) points); *s0, *s1, *s2: the largest cluster of each
+int4 level_cuts(int64_t n, int64_t split_at, int64_t* s0, int64_t* s1, int64_t* s2) {
+    int4 c = make_int4(0, 0, 0, 0);
+    int64_t a = n;  // the largest cluster below the many-workgroup levels
+    while (a >= split_at) {
+        a = (a + 1) / 2;
+        ++c.x;
+    }
+    int64_t b = n;
+    while (b >= kBigRows) {
+        b = (b + 1) / 2;
+        ++c.y;
+    }
+    int64_t e = b;
+    c.z = c.y;
+    while (e > kTinyRows) {
+        e = (e + 1) / 2;
+        ++c.z;
+    }
+    if (s0) *s0 = a;
+    if (s1) *s1 = b;
+    if (s2) *s2 = e;
+    return c;
+}
+
 AcaPlan level_plan(const hmx_hmatrix_s* h) {
     AcaPlan p;
-    int64_t s0 = h->n;  // the largest cluster below the many-workgroup levels
-    while (s0 >= split_rows(h)) {
-        s0 = (s0 + 1) / 2;
-        ++p.split0;
-    }
-    int64_t s_split = h->n;
-    while (s_split >= kBigRows) {
-        s_split = (s_split + 1) / 2;
-        ++p.split;
-    }
-    int64_t s_split2 = s_split;
-    p.split2 = p.split;
-    while (s_split2 > kTinyRows) {
-        s_split2 = (s_split2 + 1) / 2;
-        ++p.split2;
-    }
+    int64_t s0, s_split, s_split2;
+    const int4 c = level_cuts(h->n, split_rows(h), &s0, &s_split, &s_split2);
+    p.split0 = c.x;
+    p.split = c.y;
+    p.split2 = c.z;
     const int64_t big = std::min(h->big_adm, s0);  // the largest single-workgroup block
     const int64_t words = 2 * ((big + 31) / 32);
     if (words * 4 > 64 * 1024) {
@@ -891,7 +984,7 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
         a.soa64 = h->soa64.as<double>();
         a.n = n;
         a.d = d;
-        a.kern = KernelFn{(int)h->kern.kind, h->kern.p0};
+        a.kern = kernel_fn(h->kern, h->d);
         a.kmax = kmax;
         a.eps = h->prm.aca_eps;
         a.aca_eta = h->prm.aca_eta;
@@ -1325,7 +1418,7 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
         check(launch_piece_data(h->pieces.as<Piece>(), h->npieces, h->tile_lo.as<int32_t>(),
                                 h->adm.as<int4>(), h->dense.as<int4>(), rfo.as<int64_t>(), F.p,
                                 f64 ? h->soa64.p : h->soa32.p, n, d,
-                                KernelFn{(int)h->kern.kind, h->kern.p0}, h->upool.p, h->npool.p,
+                                kernel_fn(h->kern, h->d), h->upool.p, h->npool.p,
                                 smode, h->nmode, st),
               "piece data");
         h->Ru = R;
@@ -1454,138 +1547,325 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
 // so phi with length 1 gives every problem its own kernel.  The admissible
 // leaves of all problems are ordered upper-level class first, then the ACA,
 // near field and matvec run once over the union.
+// The partition of many problems at once (the forest of a batched build):
+// the problems' points in one union index space, each problem ordered in its
+// own box and clustered in its own tree, and one launch per step for all of
+// them: boxes, Morton codes, the sort (by code, then stably by problem),
+// every tree level, every box level, and every block-tree level of the
+// traversal (one host readback per level for all problems).  Each problem's
+// codes, permutation, clusters and leaves are those of its own build; the
+// union leaf lists hold them level by level, problem by problem within a
+// level, so each problem's leaves keep its canonical order.
+void stage_forest(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
+                  const int64_t* n, const int32_t* d, const hmx_kernel* kern, hipStream_t st) {
+    using clk = std::chrono::steady_clock;
+    const int64_t N = u->n;
+    const int leaf = u->prm.leaf_size;
+    const double eta = u->prm.eta;
+    hmx_stats& S = u->stats;
+    auto t0 = clk::now();
+    // per-problem tables (host and device): point offsets, tree depths and
+    // slot offsets, dimensions, inverse kernel lengths, inputs
+    std::vector<int64_t> pb(np + 1, 0), nb(np + 1, 0);
+    std::vector<int32_t> dims(np), depth(np);
+    std::vector<double> inv_ell(np);
+    std::vector<ForestInput> in(np);
+    int Lmax = 0;
+    for (int p = 0; p < np; ++p) {
+        pb[p + 1] = pb[p] + n[p];
+        dims[p] = d[p];
+        depth[p] = max_depth(n[p], leaf);
+        if (depth[p] > 29) {
+            set_err("problem %d: cluster tree too deep (%d levels); raise leaf_size", p,
+                    depth[p]);
+            throw Fail{HMX_ERR_UNSUPPORTED};
+        }
+        Lmax = std::max(Lmax, (int)depth[p]);
+        nb[p + 1] = nb[p] + ((2ll << depth[p]) - 1);
+        inv_ell[p] = 1.0 / kernel_length(kern[p]);
+        in[p] = ForestInput{pts[p], d[p]};
+    }
+    const int64_t nslots = nb[np];
+    if (nslots >= (1ll << 31)) {
+        set_err("the problems' cluster trees need %lld slots (more than 2^31)",
+                (long long)nslots);
+        throw Fail{HMX_ERR_UNSUPPORTED};
+    }
+    DevBuf dpb, dnb, ddims, ddepth, dinv, din;
+    alloc(dpb, (np + 1) * 8, "problem offsets");
+    alloc(dnb, (np + 1) * 8, "problem slot offsets");
+    alloc(ddims, np * 4, "problem dimensions");
+    alloc(ddepth, np * 4, "problem tree depths");
+    alloc(dinv, np * 8, "problem kernel scales");
+    alloc(din, np * sizeof(ForestInput), "problem inputs");
+    check(hipMemcpyAsync(dpb.p, pb.data(), (np + 1) * 8, hipMemcpyHostToDevice, st), "tables");
+    check(hipMemcpyAsync(dnb.p, nb.data(), (np + 1) * 8, hipMemcpyHostToDevice, st), "tables");
+    check(hipMemcpyAsync(ddims.p, dims.data(), np * 4, hipMemcpyHostToDevice, st), "tables");
+    check(hipMemcpyAsync(ddepth.p, depth.data(), np * 4, hipMemcpyHostToDevice, st), "tables");
+    check(hipMemcpyAsync(dinv.p, inv_ell.data(), np * 8, hipMemcpyHostToDevice, st), "tables");
+    check(hipMemcpyAsync(din.p, in.data(), np * sizeof(ForestInput), hipMemcpyHostToDevice, st),
+          "tables");
+    const int64_t* PB = dpb.as<int64_t>();
+    const int64_t* NB = dnb.as<int64_t>();
+
+    // ---- 1. boxes, Morton codes, the sort, ordered coordinates ----
+    DevBuf soa;  // unscaled Morton-ordered coordinates, 3 x N (partition and boxes)
+    {
+        DevBuf P, partial, box;
+        alloc(P, (size_t)N * 3 * 8, "union points");
+        check(launch_forest_points(din.as<ForestInput>(), np, PB, N, pts_f64, P.as<double>(), st),
+              "union points");
+        alloc(partial, (size_t)np * forest_box_parts() * 6 * 8, "box partials");
+        alloc(box, (size_t)np * 6 * 8, "problem boxes");
+        check(launch_forest_box(P.as<double>(), np, PB, ddims.as<int32_t>(),
+                                partial.as<double>(), box.as<double>(), st),
+              "problem boxes");
+        std::vector<double> hb((size_t)np * 6);
+        d2h(hb.data(), box.p, hb.size() * 8, st);
+        for (int p = 0; p < np; ++p)
+            for (int k = 0; k < d[p]; ++k)
+                if (!std::isfinite(hb[6 * p + k]) || !std::isfinite(hb[6 * p + 3 + k])) {
+                    set_err("problem %d: points contain NaN or infinite coordinates", p);
+                    throw Fail{HMX_ERR_INVALID_ARG};
+                }
+        DevBuf C, keys, sscr;
+        alloc(C, (size_t)N * 8, "union codes");
+        alloc(keys, (size_t)N * 8, "sort keys");
+        alloc(u->perm, (size_t)N * 4, "permutation");
+        check(launch_forest_morton(P.as<double>(), N, np, PB, ddims.as<int32_t>(),
+                                   box.as<double>(), C.as<uint64_t>(), u->perm.as<uint32_t>(), st),
+              "morton");
+        check(hipMemcpyAsync(keys.p, C.p, (size_t)N * 8, hipMemcpyDeviceToDevice, st), "keys");
+        alloc(sscr, radix_sort_scratch_bytes(N), "sort scratch");
+        check(radix_sort_pairs(keys.as<uint64_t>(), u->perm.as<uint32_t>(), N, 64, sscr.p, st),
+              "radix sort");
+        // stably by problem: every problem's points back in its own range
+        int pbits = 1;
+        while ((1ll << pbits) < np) ++pbits;
+        check(launch_forest_problem_keys(u->perm.as<uint32_t>(), N, np, PB, keys.as<uint64_t>(),
+                                         st),
+              "problem keys");
+        check(radix_sort_pairs(keys.as<uint64_t>(), u->perm.as<uint32_t>(), N, pbits, sscr.p, st),
+              "problem sort");
+        alloc(u->codes, (size_t)N * 8, "morton codes");
+        check(launch_gather_u64(C.as<uint64_t>(), u->perm.as<uint32_t>(), N,
+                                u->codes.as<uint64_t>(), st),
+              "codes");
+        alloc(soa, (size_t)N * 3 * 8, "ordered coordinates");
+        check(launch_gather_coords(P.p, 1, N, 3, u->perm.as<uint32_t>(), soa.as<double>(),
+                                   nullptr, st),
+              "ordered coordinates");
+        // the kernel's coordinates: each problem's divided by its kernel length
+        alloc(u->soa64, (size_t)N * 3 * 8, "coords f64");
+        if (!u->f64) alloc(u->soa32, (size_t)N * 3 * 4, "coords f32");
+        check(launch_forest_scale(soa.as<double>(), N, np, PB, dinv.as<double>(),
+                                  u->soa64.as<double>(), u->f64 ? nullptr : u->soa32.as<float>(),
+                                  st),
+              "scaled coordinates");
+        check(hipStreamSynchronize(st), "order sync");
+    }
+    S.phase_ms[0] = ms_since(t0);
+    t0 = clk::now();
+
+    // ---- 2. every problem's cluster tree and boxes, level by level ----
+    u->nslots = nslots;
+    alloc(u->node_lo, nslots * 4, "node lo");
+    alloc(u->node_hi, nslots * 4, "node hi");
+    for (int l = 0; l <= Lmax; ++l)
+        check(launch_forest_tree_level(l, np, PB, NB, ddepth.as<int32_t>(), leaf,
+                                       u->node_lo.as<int32_t>(), u->node_hi.as<int32_t>(), st),
+              "tree level");
+    alloc(u->bmin, (size_t)nslots * 3 * 8, "box min");
+    alloc(u->bmax, (size_t)nslots * 3 * 8, "box max");
+    for (int l = Lmax; l >= 0; --l)
+        check(launch_forest_box_level(l, np, NB, ddepth.as<int32_t>(), leaf,
+                                      u->node_lo.as<int32_t>(), u->node_hi.as<int32_t>(),
+                                      soa.as<double>(), N, u->bmin.as<double>(),
+                                      u->bmax.as<double>(), st),
+              "box level");
+    soa.release();
+    {
+        alloc(u->tile_of_point, N * 4, "tile of point");
+        check(hipMemsetAsync(u->tile_of_point.p, 0, N * 4, st), "memset");
+        check(launch_mark_leaves(0, leaf, u->node_lo.as<int32_t>(), u->node_hi.as<int32_t>(),
+                                 nslots, u->tile_of_point.as<int32_t>(), st),
+              "mark leaves");
+        DevBuf scratch, cnt;
+        alloc(scratch, tile_scan_scratch_bytes(N), "tile scan");
+        alloc(cnt, 8, "tile count");
+        alloc(u->tile_lo, (size_t)(N + 1) * 4, "tile lo");
+        check(launch_iota_scan_tiles(u->tile_of_point.as<int32_t>(), N, u->tile_lo.as<int32_t>(),
+                                     cnt.as<int64_t>(), scratch.p, st),
+              "tile scan");
+        u->ntiles = read_scalar(cnt.as<int64_t>(), st);
+    }
+    u->max_tile = 0;
+    for (int p = 0; p < np; ++p) {
+        int64_t sz = n[p];
+        while (sz > leaf) sz = (sz + 1) / 2;
+        u->max_tile = std::max(u->max_tile, (int)sz);
+    }
+    S.phase_ms[1] = ms_since(t0);
+    t0 = clk::now();
+
+    // ---- 3. the block cluster trees, one level of all of them at a time ----
+    {
+        DevBuf sbase, cur, nxt, scratch, totals;
+        alloc(sbase, nslots * 4, "slot bases");
+        check(launch_forest_slot_base(NB, np, nslots, sbase.as<int32_t>(), st), "slot bases");
+        std::vector<int2> roots(np);
+        for (int p = 0; p < np; ++p) roots[p] = make_int2((int)nb[p], (int)nb[p]);
+        alloc(cur, (size_t)np * sizeof(int2), "level 0");
+        check(hipMemcpyAsync(cur.p, roots.data(), (size_t)np * sizeof(int2), hipMemcpyHostToDevice,
+                             st),
+              "roots");
+        alloc(totals, 8 * sizeof(int64_t), "totals");
+        int64_t ncur = np;
+        int level = 0;
+        int64_t cap_adm = 0, cap_dense = 0;
+        while (ncur > 0) {
+            if (level >= 64) {
+                set_err("block tree deeper than 64 levels");
+                throw Fail{HMX_ERR_UNSUPPORTED};
+            }
+            S.level_sizes[level] = ncur;
+            const int64_t nblk = traverse_blocks(ncur);
+            if (!scratch.p || scratch.bytes < traverse_scratch_bytes(ncur))
+                alloc(scratch, traverse_scratch_bytes(ncur), "traverse scratch");
+            int64_t* bc = scratch.as<int64_t>();
+            check(launch_traverse_count(cur.as<int2>(), ncur, u->node_lo.as<int32_t>(),
+                                        u->node_hi.as<int32_t>(), u->bmin.as<double>(),
+                                        u->bmax.as<double>(), 3, leaf, eta, bc, st),
+                  "traverse count");
+            check(launch_traverse_scan(bc, nblk, totals.as<int64_t>(), st), "traverse scan");
+            int64_t tot[3];
+            check(hipMemcpyAsync(tot, totals.p, 3 * 8, hipMemcpyDeviceToHost, st), "totals");
+            check(hipStreamSynchronize(st), "level sync");
+            if (u->n_adm + tot[0] > cap_adm) {
+                int64_t nc = std::max<int64_t>(2 * cap_adm, u->n_adm + tot[0]);
+                grow(u->adm, nc * sizeof(int4), u->n_adm * sizeof(int4), st, "adm leaves");
+                grow(u->adm_level, nc * 4, u->n_adm * 4, st, "adm levels");
+                grow(u->adm_ids, nc * sizeof(int2), u->n_adm * sizeof(int2), st, "adm node ids");
+                cap_adm = nc;
+            }
+            if (u->n_dense + tot[2] > cap_dense) {
+                int64_t nc = std::max<int64_t>(2 * cap_dense, u->n_dense + tot[2]);
+                grow(u->dense, nc * sizeof(int4), u->n_dense * sizeof(int4), st, "dense leaves");
+                grow(u->dense_level, nc * 4, u->n_dense * 4, st, "dense levels");
+                cap_dense = nc;
+            }
+            const int64_t nnext = 4 * tot[1];
+            alloc(nxt, std::max<int64_t>(nnext, 1) * sizeof(int2), "next level");
+            check(launch_traverse_write(cur.as<int2>(), ncur, u->node_lo.as<int32_t>(),
+                                        u->node_hi.as<int32_t>(), u->bmin.as<double>(),
+                                        u->bmax.as<double>(), 3, leaf, eta, bc, level,
+                                        nxt.as<int2>(), u->adm.as<int4>(),
+                                        u->adm_level.as<int32_t>(), u->adm_ids.as<int2>(),
+                                        u->n_adm, u->dense.as<int4>(),
+                                        u->dense_level.as<int32_t>(), u->n_dense,
+                                        sbase.as<int32_t>(), st),
+                  "traverse write");
+            u->n_adm += tot[0];
+            u->n_dense += tot[2];
+            cur.swap(nxt);
+            ncur = nnext;
+            ++level;
+        }
+        check(hipStreamSynchronize(st), "traverse sync");
+        S.levels = level;
+    }
+    if (!u->adm.p) alloc(u->adm, sizeof(int4), "adm leaves");
+    if (!u->adm_level.p) alloc(u->adm_level, 4, "adm levels");
+    if (!u->adm_ids.p) alloc(u->adm_ids, sizeof(int2), "adm node ids");
+    if (!u->dense.p) alloc(u->dense, sizeof(int4), "dense leaves");
+    if (!u->dense_level.p) alloc(u->dense_level, 4, "dense levels");
+    S.phase_ms[2] = ms_since(t0);
+    u->offsets.assign(pb.begin(), pb.end());
+}
+
 void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
                   const int64_t* n, const int32_t* d, const hmx_kernel* kern, hipStream_t st) {
     const auto t_all = std::chrono::steady_clock::now();
     const bool learned = u->prm.rank_mode == HMX_RANK_LEARNED;
-    std::vector<std::unique_ptr<hmx_hmatrix_s>> parts(np);
-    std::unique_ptr<DevBuf[]> rts(new DevBuf[np]);
-    std::vector<int64_t> nspl(np, 0), nbig(np, 0), nmed(np, 0);
-    hmx_stats& S = u->stats;
-    DevBuf split;
-    alloc(split, 8, "class split");
-    int64_t nadm = 0, ndense = 0, ntiles = 0, big = 0, nspl_tot = 0, nbig_tot = 0,
-            nmed_tot = 0;
-    for (int p = 0; p < np; ++p) {
-        hmx_hmatrix_s* hp = new hmx_hmatrix_s();
-        parts[p].reset(hp);
-        init_handle(hp, n[p], d[p], kern[p], u->prm);
-        stage_partition(hp, pts[p], pts_f64, st);
-        if (learned && hp->n_adm > 0) stage_predict(hp, rts[p], st);
-        if (hp->n_adm > 0) {
-            const AcaPlan lp = level_plan(hp);
-            check(launch_level_split(hp->adm_level.as<int32_t>(), hp->n_adm, lp.split0,
-                                     split.as<int64_t>(), st),
-                  "class split");
-            nspl[p] = read_scalar(split.as<int64_t>(), st);
-            check(launch_level_split(hp->adm_level.as<int32_t>(), hp->n_adm, lp.split,
-                                     split.as<int64_t>(), st),
-                  "class split");
-            nbig[p] = read_scalar(split.as<int64_t>(), st);
-            check(launch_level_split(hp->adm_level.as<int32_t>(), hp->n_adm, lp.split2,
-                                     split.as<int64_t>(), st),
-                  "class split");
-            nmed[p] = read_scalar(split.as<int64_t>(), st);
-        }
-        nadm += hp->n_adm;
-        ndense += hp->n_dense;
-        ntiles += hp->ntiles;
-        nspl_tot += nspl[p];
-        nbig_tot += nbig[p] - nspl[p];
-        nmed_tot += nmed[p] - nbig[p];
-        big = std::max(big, hp->big_adm);
-        u->max_tile = std::max(u->max_tile, hp->max_tile);
-        for (int k = 0; k < 3; ++k) S.phase_ms[k] += hp->stats.phase_ms[k];
-        S.predict_ms += hp->stats.predict_ms;
-        S.levels = std::max(S.levels, hp->stats.levels);
-        for (int l = 0; l < 64; ++l) S.level_sizes[l] += hp->stats.level_sizes[l];
-    }
-    const int64_t N = u->n;
-    alloc(u->codes, N * 8, "morton codes");
-    alloc(u->perm, N * 4, "permutation");
-    alloc(u->soa64, (size_t)N * 3 * 8, "coords f64");
-    if (!u->f64) alloc(u->soa32, (size_t)N * 3 * 4, "coords f32");
-    alloc(u->tile_of_point, N * 4, "tile of point");
-    alloc(u->tile_lo, (ntiles + 1) * 4, "tile lo");
-    alloc(u->adm, std::max<int64_t>(nadm, 1) * sizeof(int4), "adm leaves");
-    alloc(u->adm_level, std::max<int64_t>(nadm, 1) * 4, "adm levels");
-    alloc(u->adm_ids, 16, "adm node ids");
-    alloc(u->dense, std::max<int64_t>(ndense, 1) * sizeof(int4), "dense leaves");
-    alloc(u->dense_level, std::max<int64_t>(ndense, 1) * 4, "dense levels");
-    DevBuf cls, rt;
-    alloc(cls, std::max<int64_t>(nadm, 1) * 4, "size classes");
-    if (learned) alloc(rt, std::max<int64_t>(nadm, 1) * 4, "rank targets");
-    // sections: the multi-workgroup class of every problem, then the
-    // 512-thread, the 256-thread and the single-wave classes
-    int64_t base = 0, tbase = 0, dcur = 0;
-    int64_t acur[4] = {0, nspl_tot, nspl_tot + nbig_tot, nspl_tot + nbig_tot + nmed_tot};
-    u->offsets.assign(1, 0);
-    for (int p = 0; p < np; ++p) {
-        hmx_hmatrix_s* hp = parts[p].get();
-        const int64_t np_ = hp->n;
-        const int32_t b32 = (int32_t)base;
-        check(hipMemcpyAsync(u->codes.as<uint64_t>() + base, hp->codes.p, np_ * 8,
-                             hipMemcpyDeviceToDevice, st),
-              "codes");
-        check(launch_add_i32(u->perm.as<int32_t>() + base, hp->perm.as<int32_t>(), np_, b32, st),
-              "perm");
-        const double ell = kernel_length(hp->kern);
-        check(launch_scale_coords(hp->soa64.as<double>(), np_, hp->d, 1.0 / ell,
-                                  u->soa64.as<double>(), u->f64 ? nullptr : u->soa32.as<float>(),
-                                  N, base, st),
-              "coords");
-        check(launch_add_i32(u->tile_of_point.as<int32_t>() + base,
-                             hp->tile_of_point.as<int32_t>(), np_, (int32_t)tbase, st),
-              "tiles");
-        check(launch_add_i32(u->tile_lo.as<int32_t>() + tbase, hp->tile_lo.as<int32_t>(),
-                             hp->ntiles, b32, st),
-              "tile starts");
-        // the problem's four class ranges into the four sections
-        const int64_t lo3[4] = {0, nspl[p], nbig[p], nmed[p]};
-        const int64_t hi3[4] = {nspl[p], nbig[p], nmed[p], hp->n_adm};
-        const int4* ha = hp->adm.as<int4>();
-        const int32_t* hl = hp->adm_level.as<int32_t>();
-        for (int c = 0; c < 4; ++c) {
-            const int64_t cnt = hi3[c] - lo3[c];
-            check(launch_shift_blocks(u->adm.as<int4>() + acur[c], ha + lo3[c], cnt, b32, st),
-                  "adm");
-            check(hipMemcpyAsync(u->adm_level.as<int32_t>() + acur[c], hl + lo3[c], cnt * 4,
-                                 hipMemcpyDeviceToDevice, st),
-                  "adm levels");
-            check(launch_fill_i32(cls.as<int32_t>() + acur[c], cnt, c, st), "classes");
-            if (learned && cnt > 0)
-                check(hipMemcpyAsync(rt.as<int32_t>() + acur[c], rts[p].as<int32_t>() + lo3[c],
-                                     cnt * 4, hipMemcpyDeviceToDevice, st),
-                      "targets");
-            acur[c] += cnt;
-        }
-        check(launch_shift_blocks(u->dense.as<int4>() + dcur, hp->dense.as<int4>(), hp->n_dense,
-                                  b32, st),
-              "dense");
-        check(hipMemcpyAsync(u->dense_level.as<int32_t>() + dcur, hp->dense_level.p,
-                             hp->n_dense * 4, hipMemcpyDeviceToDevice, st),
-              "dense levels");
-        base += np_;
-        tbase += hp->ntiles;
-        dcur += hp->n_dense;
-        u->offsets.push_back(base);
-    }
-    const int32_t nend = (int32_t)N;
-    check(hipMemcpyAsync(u->tile_lo.as<int32_t>() + ntiles, &nend, 4, hipMemcpyHostToDevice, st),
-          "tile end");
-    check(hipStreamSynchronize(st), "batch assembly");
-    parts.clear();
-    rts.reset();
-    u->n_adm = nadm;
-    u->n_dense = ndense;
-    u->ntiles = ntiles;
-    u->big_adm = big;
+    stage_forest(u, np, pts, pts_f64, n, d, kern, st);
+    const int64_t nadm = u->n_adm;
     AcaPlan plan;
+    DevBuf cls, rt;
     if (nadm > 0) {
-        const int64_t words = 2 * ((big + 31) / 32);
+        // size classes: each leaf's from its problem's level cuts; the leaves
+        // stably grouped by class (each problem's leaves keep their order)
+        std::vector<int4> cuts(np);
+        for (int p = 0; p < np; ++p) cuts[p] = level_cuts(n[p], split_rows(u), nullptr, nullptr, nullptr);
+        std::vector<int64_t> pb(u->offsets);
+        DevBuf dcuts, dpb, keys, vals, sscr, big;
+        alloc(dcuts, np * sizeof(int4), "class cuts");
+        alloc(dpb, (np + 1) * 8, "problem offsets");
+        check(hipMemcpyAsync(dcuts.p, cuts.data(), np * sizeof(int4), hipMemcpyHostToDevice, st),
+              "class cuts");
+        check(hipMemcpyAsync(dpb.p, pb.data(), (np + 1) * 8, hipMemcpyHostToDevice, st),
+              "problem offsets");
+        alloc(keys, nadm * 8, "class keys");
+        alloc(vals, nadm * 4, "class order");
+        check(launch_forest_class(u->adm.as<int4>(), u->adm_level.as<int32_t>(), nadm, np,
+                                  dpb.as<int64_t>(), dcuts.as<int4>(), keys.as<uint64_t>(),
+                                  vals.as<uint32_t>(), st),
+              "classes");
+        alloc(sscr, radix_sort_scratch_bytes(nadm), "class sort");
+        check(radix_sort_pairs(keys.as<uint64_t>(), vals.as<uint32_t>(), nadm, 2, sscr.p, st),
+              "class sort");
+        DevBuf a2, l2, i2;
+        alloc(a2, nadm * sizeof(int4), "adm leaves");
+        alloc(l2, nadm * 4, "adm levels");
+        alloc(i2, nadm * sizeof(int2), "adm node ids");
+        alloc(cls, nadm * 4, "size classes");
+        check(launch_gather_blocks(vals.as<uint32_t>(), nadm, u->adm.as<int4>(),
+                                   u->adm_level.as<int32_t>(), nullptr, nullptr, a2.as<int4>(),
+                                   l2.as<int32_t>(), nullptr, nullptr, st),
+              "class gather");
+        check(launch_gather_u64((const uint64_t*)u->adm_ids.p, vals.as<uint32_t>(), nadm,
+                                (uint64_t*)i2.p, st),
+              "class gather");
+        check(launch_narrow_u64(keys.as<uint64_t>(), nadm, cls.as<int32_t>(), st), "classes");
+        u->adm.swap(a2);
+        u->adm_level.swap(l2);
+        u->adm_ids.swap(i2);
+        // the largest cluster side of an admissible leaf
+        alloc(big, 8, "largest block side");
+        check(hipMemsetAsync(big.p, 0, 8, st), "largest block side");
+        check(launch_max_side(u->adm.as<int4>(), nadm, big.as<int>(), st), "largest block side");
+        u->big_adm = read_scalar(big.as<int>(), st);
+        if (learned) {
+            alloc(rt, nadm * 4, "rank targets");
+            std::vector<double> ell(np);
+            std::vector<int32_t> dd(np);
+            for (int p = 0; p < np; ++p) {
+                ell[p] = kernel_length(kern[p]);
+                dd[p] = d[p];
+            }
+            DevBuf dell, ddim;
+            alloc(dell, np * 8, "problem lengths");
+            alloc(ddim, np * 4, "problem dimensions");
+            check(hipMemcpyAsync(dell.p, ell.data(), np * 8, hipMemcpyHostToDevice, st), "lengths");
+            check(hipMemcpyAsync(ddim.p, dd.data(), np * 4, hipMemcpyHostToDevice, st),
+                  "dimensions");
+            const auto tp = std::chrono::steady_clock::now();
+            const hmx_mlp_s* mp = u->prm.mlp;
+            check(launch_rank_predict(u->adm.as<int4>(), u->adm_ids.as<int2>(), nadm,
+                                      u->bmin.as<double>(), u->bmax.as<double>(), 3, 1.0,
+                                      mp->w.as<float>(), mp->mean.as<float>(),
+                                      mp->scale.as<float>(), u->prm.max_rank, nullptr,
+                                      rt.as<int32_t>(), st, dpb.as<int64_t>(), np,
+                                      dell.as<double>(), ddim.as<int32_t>()),
+                  "rank prediction");
+            check(hipStreamSynchronize(st), "prediction sync");
+            u->stats.predict_ms += ms_since(tp);
+        }
+        check(hipStreamSynchronize(st), "class sync");
+        const int64_t big_rows = u->big_adm;
+        const int64_t words = 2 * ((big_rows + 31) / 32);
         if (words * 4 > 64 * 1024) {
             set_err("admissible block of %lld rows exceeds the ACA bitmask capacity",
-                    (long long)big);
+                    (long long)big_rows);
             throw Fail{HMX_ERR_UNSUPPORTED};
         }
         plan.cls = cls.as<int32_t>();
@@ -1594,8 +1874,9 @@ void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
         plan.split2 = 3;
         plan.big_words = (int)std::max<int64_t>(words, 2);
         plan.med_words =
-            (int)std::max<int64_t>(2 * ((std::min(kBigRows - 1, big) + 31) / 32), 2);
-        plan.tiny_words = (int)std::max<int64_t>(2 * ((std::min(kTinyRows, big) + 31) / 32), 2);
+            (int)std::max<int64_t>(2 * ((std::min(kBigRows - 1, big_rows) + 31) / 32), 2);
+        plan.tiny_words =
+            (int)std::max<int64_t>(2 * ((std::min(kTinyRows, big_rows) + 31) / 32), 2);
         plan.rt = learned ? rt.as<int32_t>() : nullptr;
     }
     stage_factors(u, plan, st, t_all);
@@ -1607,6 +1888,9 @@ void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
 namespace {
 
 const int64_t kP = HMX_MLP_NPARAMS;
+// predictor file: magic, then int64 parameter count and Adam step, then FP32
+// parameters, standardisation mean and scale, Adam moments m and v
+const char kMlpMagic[8] = {'H', 'M', 'X', 'M', 'L', 'P', '0', '1'};
 
 template <typename F>
 hmx_status guarded(F&& f) {
@@ -1674,9 +1958,100 @@ hipError_t matvec_launch(hmx_hmatrix_s* h, const void* x, void* z, double alpha,
                            h->widx.as<int64_t>(), h->upool.p, h->npool.p, h->vecpool.p,
                            h->perm.as<int32_t>(), alpha, beta, h->prm.sigma2, z, h->max_tile,
                            h->smode, h->nmode, config, f64 ? h->soa64.p : h->soa32.p, h->n, h->d,
-                           KernelFn{(int)h->kern.kind, h->kern.p0}, st);
+                           kernel_fn(h->kern, h->d), st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
     return e;
+}
+
+
+// Work space of a CG solve: three n-vectors in the compute type, 8 FP64
+// scalars (r.r, p.q, r'.r', b.b, |b - (H + sigma2 I) x|^2) and the dot
+// products' block partials.
+struct CgWork {
+    void *r, *p, *q;
+    double* sc;
+    double* pa;
+};
+
+hmx_status cg_args(hmx_hmatrix_s* h, const void* b, const void* x, double rel_tol,
+                   int32_t max_iter) {
+    if (!h || !b || !x || !(rel_tol >= 0) || max_iter < 0) {
+        set_err("invalid argument to the CG solve");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (h->prm.aca_only) {
+        set_err("handle was built with aca_only: no matrix to apply");
+        return HMX_ERR_UNSUPPORTED;
+    }
+    return HMX_OK;
+}
+
+// Textbook CG (Hestenes-Stiefel) from x = 0 on (H + sigma2 I); every buffer
+// of w is overwritten before it is read, so leftover contents do not matter.
+hmx_status cg_run(hmx_hmatrix_s* h, const void* b, void* x, double rel_tol, int32_t max_iter,
+                  hipStream_t st, const CgWork& w, int32_t* iters, double* rel_res,
+                  double* true_rel_res) {
+    const int f64 = h->f64;
+    const int64_t n = h->n;
+    const hmx_dtype vdt = f64 ? HMX_F64 : HMX_F32;
+    int32_t it = 0;
+    double rr = 0.0, bb = 0.0, res = 0.0;
+    hmx_status status = HMX_OK;
+    double* sc = w.sc;
+    double* pa = w.pa;
+    check(launch_fill_zero(x, n, f64, st), "cg init");
+    check(launch_copy(w.r, b, n, f64, st), "cg init");
+    check(launch_copy(w.p, b, n, f64, st), "cg init");
+    check(launch_dot(b, b, n, f64, pa, sc + 3, st), "cg dot");
+    check(launch_copy(sc, sc + 3, 1, 1, st), "cg init");  // r.r = b.b
+    check(hipMemcpyAsync(&bb, sc + 3, 8, hipMemcpyDeviceToHost, st), "cg readback");
+    check(hipStreamSynchronize(st), "cg sync");
+    rr = bb;
+    if (bb == 0.0) {
+        if (iters) *iters = 0;
+        if (rel_res) *rel_res = 0.0;
+        if (true_rel_res) *true_rel_res = 0.0;
+        return HMX_OK;
+    }
+    res = 1.0;
+    status = HMX_ERR_NOT_CONVERGED;
+    while (it < max_iter) {
+        hmx_status s = hmx_matvec(h, w.p, w.q, vdt, 1.0, 0.0, st);
+        if (s != HMX_OK) return s;
+        check(launch_dot(w.p, w.q, n, f64, pa, sc + 1, st), "cg dot");
+        check(launch_cg_update(x, w.r, w.p, w.q, sc, n, f64, pa, sc + 2, st), "cg update");
+        double two[2];
+        check(hipMemcpyAsync(two, sc + 1, 16, hipMemcpyDeviceToHost, st), "cg readback");
+        check(hipStreamSynchronize(st), "cg sync");
+        ++it;
+        if (!(two[0] > 0.0)) {
+            set_err("CG breakdown at iteration %d: p.Ap = %g", it, two[0]);
+            break;  // x holds a damaged last update; report not converged
+        }
+        rr = two[1];
+        res = sqrt(rr / bb);
+        if (res <= rel_tol) {
+            status = HMX_OK;
+            break;
+        }
+        check(launch_cg_direction(w.p, w.r, sc, n, f64, st), "cg direction");
+        check(launch_copy(sc, sc + 2, 1, 1, st), "cg shift");
+    }
+    if (status != HMX_OK && it >= max_iter) set_err("CG did not converge in %d iterations", it);
+    if (true_rel_res) {
+        // r = b - (H + sigma2 I) x
+        hmx_status s = hmx_matvec(h, x, w.q, vdt, 1.0, 0.0, st);
+        if (s != HMX_OK) return s;
+        check(launch_sub(w.r, b, w.q, n, f64, st), "cg residual");
+        check(launch_dot(w.r, w.r, n, f64, pa, sc + 4, st), "cg residual");
+        double d2 = 0.0;
+        check(hipMemcpyAsync(&d2, sc + 4, 8, hipMemcpyDeviceToHost, st), "cg readback");
+        check(hipStreamSynchronize(st), "cg sync");
+        *true_rel_res = sqrt(d2 / bb);
+    }
+    if (iters) *iters = it;
+    if (rel_res) *rel_res = res;
+    return status;
 }
 
 }  // namespace
@@ -1743,11 +2118,13 @@ hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t
         if (ps != HMX_OK) return ps;
     }
     if (kernel->kind != HMX_GAUSSIAN && kernel->kind != HMX_MATERN32 &&
-        kernel->kind != HMX_TEST_CONST && kernel->kind != HMX_TEST_LOWRANK) {
+        kernel->kind != HMX_MATERN_NU1 && kernel->kind != HMX_TEST_CONST &&
+        kernel->kind != HMX_TEST_LOWRANK) {
         set_err("unknown kernel kind %d", (int)kernel->kind);
         return HMX_ERR_INVALID_ARG;
     }
-    if ((kernel->kind == HMX_GAUSSIAN || kernel->kind == HMX_MATERN32) &&
+    if ((kernel->kind == HMX_GAUSSIAN || kernel->kind == HMX_MATERN32 ||
+         kernel->kind == HMX_MATERN_NU1) &&
         !(kernel->p0 > 0 && std::isfinite(kernel->p0))) {
         set_err("kernel parameter p0 must be positive and finite");
         return HMX_ERR_INVALID_ARG;
@@ -1758,6 +2135,8 @@ hmx_status hmx_build(const void* points, hmx_dtype pts_dtype, int64_t n, int32_t
         return HMX_ERR_OOM;
     }
     init_handle(h, n, d, *kernel, p);
+    const Allocator ua{p.dev_alloc, p.dev_free, p.alloc_ctx};
+    AllocScope scope(&ua);
     try {
         build_impl(h, points, pts_dtype == HMX_F64, (hipStream_t)stream);
     } catch (const Fail& f) {
@@ -1825,6 +2204,8 @@ hmx_status hmx_build_batched(int32_t nprob, const void* const* points, hmx_dtype
     init_handle(h, total, 3, hmx_kernel{kind, 1.0, 0.0}, p);
     h->nprob = nprob;
     h->batched = true;
+    const Allocator ua{p.dev_alloc, p.dev_free, p.alloc_ctx};
+    AllocScope scope(&ua);
     try {
         batched_impl(h, nprob, points, pts_dtype == HMX_F64, n, d, kernels, (hipStream_t)stream);
     } catch (const Fail& f) {
@@ -1869,6 +2250,27 @@ hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype
     if (e != hipSuccess) {
         set_err("matvec launch: %s", hipGetErrorString(e));
         return HMX_ERR_DEVICE;
+    }
+    return HMX_OK;
+}
+
+hmx_status hmx_matvec_batched(int32_t nprob, const hmx_hmatrix* hs, const void* const* x,
+                              void* const* z, hmx_dtype vec_dtype, double alpha, double beta,
+                              void* stream) {
+    if (nprob < 0 || (nprob > 0 && (!hs || !x || !z))) {
+        set_err("invalid argument to hmx_matvec_batched");
+        return HMX_ERR_INVALID_ARG;
+    }
+    for (int32_t q = 0; q < nprob; ++q) {  // every argument checked before any launch
+        const hmx_status cs = matvec_args(hs[q], x[q], z[q], vec_dtype);
+        if (cs != HMX_OK) {
+            set_err("problem %d: %s", q, g_err.c_str());
+            return cs;
+        }
+    }
+    for (int32_t q = 0; q < nprob; ++q) {
+        const hmx_status s = hmx_matvec(hs[q], x[q], z[q], vec_dtype, alpha, beta, stream);
+        if (s != HMX_OK) return s;
     }
     return HMX_OK;
 }
@@ -1945,6 +2347,8 @@ hmx_status hmx_autotune(hmx_hmatrix h, int32_t reps, void* stream, int32_t* choi
     }
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    const Allocator ua{h->prm.dev_alloc, h->prm.dev_free, h->prm.alloc_ctx};
+    AllocScope scope(&ua);
     hmx_status status = guarded([&] {
         DevBuf x, z;
         alloc(x, (size_t)h->n * h->esz, "tuning x");
@@ -1963,7 +2367,7 @@ hmx_status hmx_autotune(hmx_hmatrix h, int32_t reps, void* stream, int32_t* choi
                                       h->perm.as<int32_t>(), 1.0, 0.0, h->prm.sigma2, z.p,
                                       h->max_tile, h->smode, h->nmode, c,
                                       h->f64 ? h->soa64.p : h->soa32.p, h->n, h->d,
-                                      KernelFn{(int)h->kern.kind, h->kern.p0}, st);
+                                      kernel_fn(h->kern, h->d), st);
             };
             check(rt(), "tuning warm-up");
             check(hipEventRecord(e0, st), "event");
@@ -2001,86 +2405,24 @@ hmx_status hmx_set_tile_config(hmx_hmatrix h, int32_t config) {
 
 hmx_status hmx_cg_solve(hmx_hmatrix h, const void* b, void* x, double rel_tol, int32_t max_iter,
                         void* stream, int32_t* iters, double* rel_res, double* true_rel_res) {
-    if (!h || !b || !x || !(rel_tol >= 0) || max_iter < 0) {
-        set_err("invalid argument to hmx_cg_solve");
-        return HMX_ERR_INVALID_ARG;
-    }
-    if (h->prm.aca_only) {
-        set_err("handle was built with aca_only: no matrix to apply");
-        return HMX_ERR_UNSUPPORTED;
-    }
-    hipStream_t st = (hipStream_t)stream;
-    const int f64 = h->f64;
-    const int64_t n = h->n;
-    const hmx_dtype vdt = f64 ? HMX_F64 : HMX_F32;
-    int32_t it = 0;
-    double rr = 0.0, bb = 0.0, res = 0.0;
-    hmx_status status = HMX_OK;
+    hmx_status s = cg_args(h, b, x, rel_tol, max_iter);
+    if (s != HMX_OK) return s;
+    const Allocator ua{h->prm.dev_alloc, h->prm.dev_free, h->prm.alloc_ctx};
+    AllocScope scope(&ua);
     try {
         DevBuf r, p, q, scal, partial;
-        alloc(r, (size_t)n * h->esz, "cg r");
-        alloc(p, (size_t)n * h->esz, "cg p");
-        alloc(q, (size_t)n * h->esz, "cg q");
+        const size_t vb = (size_t)h->n * h->esz;
+        alloc(r, vb, "cg r");
+        alloc(p, vb, "cg p");
+        alloc(q, vb, "cg q");
         alloc(scal, 8 * sizeof(double), "cg scalars");
         alloc(partial, cg_scratch_bytes(), "cg partials");
-        double* sc = scal.as<double>();
-        double* pa = partial.as<double>();
-        check(launch_fill_zero(x, n, f64, st), "cg init");
-        check(launch_copy(r.p, b, n, f64, st), "cg init");
-        check(launch_copy(p.p, b, n, f64, st), "cg init");
-        check(launch_dot(b, b, n, f64, pa, sc + 3, st), "cg dot");
-        check(launch_copy(sc, sc + 3, 1, 1, st), "cg init");  // r.r = b.b
-        check(hipMemcpyAsync(&bb, sc + 3, 8, hipMemcpyDeviceToHost, st), "cg readback");
-        check(hipStreamSynchronize(st), "cg sync");
-        rr = bb;
-        if (bb == 0.0) {
-            if (iters) *iters = 0;
-            if (rel_res) *rel_res = 0.0;
-            if (true_rel_res) *true_rel_res = 0.0;
-            return HMX_OK;
-        }
-        res = 1.0;
-        status = HMX_ERR_NOT_CONVERGED;
-        while (it < max_iter) {
-            hmx_status s = hmx_matvec(h, p.p, q.p, vdt, 1.0, 0.0, stream);
-            if (s != HMX_OK) return s;
-            check(launch_dot(p.p, q.p, n, f64, pa, sc + 1, st), "cg dot");
-            check(launch_cg_update(x, r.p, p.p, q.p, sc, n, f64, pa, sc + 2, st), "cg update");
-            double two[2];
-            check(hipMemcpyAsync(two, sc + 1, 16, hipMemcpyDeviceToHost, st), "cg readback");
-            check(hipStreamSynchronize(st), "cg sync");
-            ++it;
-            if (!(two[0] > 0.0)) {
-                set_err("CG breakdown at iteration %d: p.Ap = %g", it, two[0]);
-                break;  // x holds a damaged last update; report not converged
-            }
-            rr = two[1];
-            res = sqrt(rr / bb);
-            if (res <= rel_tol) {
-                status = HMX_OK;
-                break;
-            }
-            check(launch_cg_direction(p.p, r.p, sc, n, f64, st), "cg direction");
-            check(launch_copy(sc, sc + 2, 1, 1, st), "cg shift");
-        }
-        if (status != HMX_OK && it >= max_iter) set_err("CG did not converge in %d iterations", it);
-        if (true_rel_res) {
-            // r = b - (H + sigma2 I) x
-            hmx_status s = hmx_matvec(h, x, q.p, vdt, 1.0, 0.0, stream);
-            if (s != HMX_OK) return s;
-            check(launch_sub(r.p, b, q.p, n, f64, st), "cg residual");
-            check(launch_dot(r.p, r.p, n, f64, pa, sc + 4, st), "cg residual");
-            double d2 = 0.0;
-            check(hipMemcpyAsync(&d2, sc + 4, 8, hipMemcpyDeviceToHost, st), "cg readback");
-            check(hipStreamSynchronize(st), "cg sync");
-            *true_rel_res = sqrt(d2 / bb);
-        }
+        CgWork w{r.p, p.p, q.p, scal.as<double>(), partial.as<double>()};
+        return cg_run(h, b, x, rel_tol, max_iter, (hipStream_t)stream, w, iters, rel_res,
+                      true_rel_res);
     } catch (const Fail& f) {
         return f.s;
     }
-    if (iters) *iters = it;
-    if (rel_res) *rel_res = res;
-    return status;
 }
 
 hmx_status hmx_get_partition(hmx_hmatrix h, uint64_t* codes, int32_t* perm, int32_t* adm,
@@ -2403,6 +2745,83 @@ hmx_status hmx_mlp_get_params(hmx_mlp m, float* params, float* mean, float* scal
     });
 }
 
+hmx_status hmx_mlp_save(hmx_mlp m, const char* path) {
+    if (!m || !path) {
+        set_err("NULL argument");
+        return HMX_ERR_INVALID_ARG;
+    }
+    std::vector<float> w(kP), mo(kP), vo(kP), mu(8), sc(8);
+    hmx_status s = guarded([&] {
+        check(hipDeviceSynchronize(), "sync");
+        check(hipMemcpy(w.data(), m->w.p, kP * 4, hipMemcpyDeviceToHost), "weights");
+        check(hipMemcpy(mo.data(), m->m.p, kP * 4, hipMemcpyDeviceToHost), "adam m");
+        check(hipMemcpy(vo.data(), m->v.p, kP * 4, hipMemcpyDeviceToHost), "adam v");
+        check(hipMemcpy(mu.data(), m->mean.p, 32, hipMemcpyDeviceToHost), "mean");
+        check(hipMemcpy(sc.data(), m->scale.p, 32, hipMemcpyDeviceToHost), "scale");
+    });
+    if (s != HMX_OK) return s;
+    FILE* f = fopen(path, "wb");
+    if (!f) {
+        set_err("cannot open %s for writing", path);
+        return HMX_ERR_INVALID_ARG;
+    }
+    const int64_t head[2] = {kP, m->t};
+    bool ok = fwrite(kMlpMagic, 1, 8, f) == 8 && fwrite(head, 8, 2, f) == 2 &&
+              fwrite(w.data(), 4, kP, f) == (size_t)kP && fwrite(mu.data(), 4, 8, f) == 8 &&
+              fwrite(sc.data(), 4, 8, f) == 8 && fwrite(mo.data(), 4, kP, f) == (size_t)kP &&
+              fwrite(vo.data(), 4, kP, f) == (size_t)kP;
+    ok = (fclose(f) == 0) && ok;
+    if (!ok) {
+        set_err("writing %s failed", path);
+        return HMX_ERR_INVALID_ARG;
+    }
+    return HMX_OK;
+}
+
+hmx_status hmx_mlp_load(const char* path, hmx_mlp* out) {
+    if (out) *out = nullptr;
+    if (!path || !out) {
+        set_err("NULL argument");
+        return HMX_ERR_INVALID_ARG;
+    }
+    FILE* f = fopen(path, "rb");
+    if (!f) {
+        set_err("cannot open %s", path);
+        return HMX_ERR_INVALID_ARG;
+    }
+    char magic[8];
+    int64_t head[2] = {0, 0};
+    std::vector<float> w(kP), mo(kP), vo(kP), mu(8), sc(8);
+    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kMlpMagic, 8) == 0 &&
+              fread(head, 8, 2, f) == 2 && head[0] == kP && head[1] >= 0 &&
+              fread(w.data(), 4, kP, f) == (size_t)kP && fread(mu.data(), 4, 8, f) == 8 &&
+              fread(sc.data(), 4, 8, f) == 8 && fread(mo.data(), 4, kP, f) == (size_t)kP &&
+              fread(vo.data(), 4, kP, f) == (size_t)kP;
+    char extra;
+    ok = ok && fread(&extra, 1, 1, f) == 0;  // nothing after the record
+    fclose(f);
+    if (!ok) {
+        set_err("%s is not a rank predictor file of %lld parameters", path, (long long)kP);
+        return HMX_ERR_INVALID_ARG;
+    }
+    hmx_mlp m = nullptr;
+    hmx_status s = hmx_mlp_create(w.data(), &m);
+    if (s != HMX_OK) return s;
+    s = guarded([&] {
+        check(hipMemcpy(m->mean.p, mu.data(), 32, hipMemcpyHostToDevice), "mean");
+        check(hipMemcpy(m->scale.p, sc.data(), 32, hipMemcpyHostToDevice), "scale");
+        check(hipMemcpy(m->m.p, mo.data(), kP * 4, hipMemcpyHostToDevice), "adam m");
+        check(hipMemcpy(m->v.p, vo.data(), kP * 4, hipMemcpyHostToDevice), "adam v");
+        m->t = head[1];
+    });
+    if (s != HMX_OK) {
+        hmx_mlp_destroy(m);
+        return s;
+    }
+    *out = m;
+    return HMX_OK;
+}
+
 hmx_status hmx_mlp_fit_normalization(hmx_mlp m, const float* X, int64_t n, void* stream) {
     if (!m || !X || n < 1) {
         set_err("invalid argument to hmx_mlp_fit_normalization");
@@ -2573,6 +2992,7 @@ hmx_status hmx_trim(int64_t* released_bytes) {
     (void)hipDeviceSynchronize();
     int64_t tot = 0;
     for (auto& b : c.blocks) {
+        c.owned.erase(b.second.second);
         (void)hipFree(b.second.second);
         tot += (int64_t)b.first;
     }

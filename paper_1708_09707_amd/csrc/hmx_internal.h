@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "../../include/hmx.h"
 
@@ -16,6 +17,7 @@ constexpr int kWave = 64;         // CDNA wavefront width
 struct KernelFn {
     int kind;
     double p0;
+    double norm = 1.0;  // HMX_MATERN_NU1: 1 / (2^(beta-1) Gamma(beta)), beta = 1 + d/2
 };
 
 // ---------------------------------------------------------------------------
@@ -26,15 +28,90 @@ struct KernelEval {
     int kind;
     T inv_p0;   // 1 / p0
     T s3_inv;   // sqrt(3) / p0 (Matern-3/2)
+    T norm;     // Matern nu = 1 normalisation
     __host__ __device__ KernelEval() {}
     __host__ KernelEval(const KernelFn& k)
-        : kind(k.kind), inv_p0((T)(1.0 / k.p0)), s3_inv((T)(1.7320508075688772 / k.p0)) {}
+        : kind(k.kind),
+          inv_p0((T)(1.0 / k.p0)),
+          s3_inv((T)(1.7320508075688772 / k.p0)),
+          norm((T)k.norm) {}
 };
 
 __device__ __forceinline__ float kexp(float a) { return __expf(a); }
 __device__ __forceinline__ double kexp(double a) { return exp(a); }
 __device__ __forceinline__ float ksqrt(float a) { return __fsqrt_rn(a); }
 __device__ __forceinline__ double ksqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ float klog(float a) { return __logf(a); }
+__device__ __forceinline__ double klog(double a) { return log(a); }
+
+// s K_1(s), K_1 the modified Bessel function of the second kind of order 1
+// (the Matern kernel of the model problem, Section 6.2, with
+// beta - d/2 = 1); the limit 1 at s = 0.
+//  * s <= 2: the power series of K_1 (Abramowitz & Stegun 9.6.11) in
+//    q = s^2/4:  s K_1(s) = 1 + 2 q ln(s/2) sum_k a_k - q sum_k c_k a_k with
+//    a_k = q^k / (k! (k+1)!), c_k = psi(k+1) + psi(k+2), truncated where a_k
+//    drops below the type's rounding at q = 1 (12 terms FP64, 7 FP32).
+//  * s > 2: K_1(s) = int_0^inf exp(-s cosh t) cosh t dt (A&S 9.6.24) with
+//    the substitution w = 2 sqrt(s) sinh(t/2), which turns the integrand
+//    into a Gaussian times a smooth factor:
+//      s K_1(s) = s e^-s int_0^inf e^(-w^2/2) (1 + w^2/(2s)) 2 / sqrt(4s + w^2) dw,
+//    summed by the trapezoidal rule on w = k h (the factor is analytic for
+//    |Im w| < 2 sqrt(s), so the rule converges geometrically): h = 0.45 and
+//    20 nodes for FP64, h = 0.8 and 8 nodes for FP32.  The node weights
+//    exp(-(k h)^2 / 2) are the literals below.
+struct K1Nodes64 {
+    static constexpr double h = 0.45;
+    static constexpr int n = 20;
+};
+struct K1Nodes32 {
+    static constexpr float h = 0.8f;
+    static constexpr int n = 8;
+};
+__device__ __forceinline__ double k1_node(const K1Nodes64&, int k) {
+    constexpr double w[20] = {
+        0.90370707787319604,   0.66697681085847438,   0.40202138309465485,
+        0.19789869908361465,   0.079559508718227687,  0.026121409853918223,
+        0.0070041671493624221, 0.001533810679324463,  0.00027431046749340119,
+        4.0065297392951069e-05, 4.7791397322046383e-06, 4.6557157157830781e-07,
+        3.7040645507943341e-08, 2.406722436301052e-09, 1.2771115545128334e-10,
+        5.5346100717010135e-12, 1.9588473410004431e-13, 5.6619955169489504e-15,
+        1.3365764918318395e-16, 2.576757109154981e-18};
+    return w[k];
+}
+__device__ __forceinline__ float k1_node(const K1Nodes32&, int k) {
+    constexpr float w[8] = {0.72614902f, 0.27803731f, 0.056134764f, 0.0059760227f,
+                            0.00033546262f, 9.9295039e-06f, 1.5497531e-07f, 1.2754077e-09f};
+    return w[k];
+}
+
+template <typename T>
+__device__ __forceinline__ T xk1(T s) {
+    using Nodes = typename std::conditional<sizeof(T) == 8, K1Nodes64, K1Nodes32>::type;
+    if (s <= (T)2) {
+        constexpr int nt = sizeof(T) == 8 ? 12 : 7;
+        const T q = (T)0.25 * s * s;
+        T a = (T)1, s1 = (T)0, s2 = (T)0;
+        T c = (T)(1.0 - 2.0 * 0.57721566490153286061);  // psi(1) + psi(2)
+#pragma unroll
+        for (int k = 0; k < nt; ++k) {
+            s1 += a;
+            s2 += c * a;
+            a = a * q * (T)(1.0 / ((k + 1.0) * (k + 2.0)));
+            c += (T)(1.0 / (k + 1.0) + 1.0 / (k + 2.0));
+        }
+        // q ln(s/2) is 0 * -inf at s = 0: the limit there is 1
+        return s > (T)0 ? (T)1 + (T)2 * q * klog((T)0.5 * s) * s1 - q * s2 : (T)1;
+    }
+    const T four_s = (T)4 * s, inv_2s = (T)1 / ((T)2 * s);
+    T acc = (T)1 / ksqrt(four_s);  // the w = 0 node, halved
+#pragma unroll
+    for (int k = 1; k <= Nodes::n; ++k) {
+        const T w = (T)k * Nodes::h;
+        const T w2 = w * w;
+        acc += k1_node(Nodes{}, k - 1) * ((T)1 + w2 * inv_2s) * ((T)2 / ksqrt(four_s + w2));
+    }
+    return s * kexp(-s) * Nodes::h * acc;
+}
 
 // phi for points x (d coords) and y (d coords)
 template <typename T>
@@ -54,6 +131,8 @@ __device__ __forceinline__ T phi(const KernelEval<T>& K, const T* x, const T* y,
             T s = ksqrt(r2) * K.s3_inv;
             return ((T)1 + s) * kexp(-s);
         }
+        case HMX_MATERN_NU1:
+            return K.norm * xk1(ksqrt(r2) * K.inv_p0);
         case HMX_TEST_CONST:
             return (T)1;
         default: {  // HMX_TEST_LOWRANK
@@ -79,6 +158,8 @@ __device__ __forceinline__ T phi_kind(const KernelEval<T>& K, const T* x, const 
     } else if constexpr (KIND == HMX_MATERN32) {
         T s = ksqrt(r2) * K.s3_inv;
         return ((T)1 + s) * kexp(-s);
+    } else if constexpr (KIND == HMX_MATERN_NU1) {
+        return K.norm * xk1(ksqrt(r2) * K.inv_p0);
     } else if constexpr (KIND == HMX_TEST_CONST) {
         (void)r2;
         return (T)1;
@@ -87,6 +168,26 @@ __device__ __forceinline__ T phi_kind(const KernelEval<T>& K, const T* x, const 
         return u * u;
     }
 }
+
+// many problems in one union index space (batched builds): problem p owns
+// [pbase[p], pbase[p + 1]); the problem of index i (binary search, np small)
+__device__ __forceinline__ int problem_of(const int64_t* __restrict__ pbase, int np, int64_t i) {
+    int lo = 0, hi = np;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pbase[mid] <= i)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// a problem's input points (device, n_p x d row-major, the build's dtype)
+struct ForestInput {
+    const void* pts;
+    int32_t d;
+};
 
 // load point i of a d x n SoA array
 template <typename T>
@@ -116,6 +217,22 @@ hipError_t launch_global_box(const void* pts, int pts_f64, int64_t n, int d, dou
 int global_box_parts(int64_t n);
 hipError_t launch_morton(const void* pts, int pts_f64, int64_t n, int d, const double* box,
                          uint64_t* codes, uint32_t* idx, hipStream_t st);
+// many problems at once (batched builds): the union points as N x 3 FP64,
+// per-problem boxes (6 doubles each: lo[3], hi[3]), Morton codes of every
+// point in its problem's box, the problem key of each sorted point, a gather
+hipError_t launch_forest_points(const ForestInput* in, int np, const int64_t* pbase, int64_t N,
+                                int f64, double* P, hipStream_t st);
+int forest_box_parts();
+hipError_t launch_forest_box(const double* P, int np, const int64_t* pbase, const int32_t* dims,
+                             double* partial /*np x forest_box_parts() x 6*/, double* box,
+                             hipStream_t st);
+hipError_t launch_forest_morton(const double* P, int64_t N, int np, const int64_t* pbase,
+                                const int32_t* dims, const double* box, uint64_t* codes,
+                                uint32_t* idx, hipStream_t st);
+hipError_t launch_forest_problem_keys(const uint32_t* idx, int64_t N, int np,
+                                      const int64_t* pbase, uint64_t* keys, hipStream_t st);
+hipError_t launch_gather_u64(const uint64_t* src, const uint32_t* idx, int64_t n, uint64_t* dst,
+                             hipStream_t st);
 // stable LSD radix sort of (key, value) pairs on the low `bits` key bits;
 // scratch from radix_sort_scratch_bytes; results end in keys/vals
 size_t radix_sort_scratch_bytes(int64_t n);
@@ -153,7 +270,19 @@ hipError_t launch_traverse_write(const int2* cur, int64_t ncur, const int32_t* n
                                  int d, int leaf, double eta, const int64_t* block_offsets,
                                  int level, int2* next, int4* adm, int32_t* adm_level,
                                  int2* adm_ids, int64_t adm_base, int4* dense,
-                                 int32_t* dense_level, int64_t dense_base, hipStream_t st);
+                                 int32_t* dense_level, int64_t dense_base,
+                                 const int32_t* slot_base /*null: one tree*/, hipStream_t st);
+// the forest of a batched build: problem p's tree in slots [nbase[p],
+// nbase[p + 1]) (heap-indexed from nbase[p]), depth[p] its deepest level
+hipError_t launch_forest_tree_level(int level, int np, const int64_t* pbase, const int64_t* nbase,
+                                    const int32_t* depth, int leaf, int32_t* node_lo,
+                                    int32_t* node_hi, hipStream_t st);
+hipError_t launch_forest_box_level(int level, int np, const int64_t* nbase, const int32_t* depth,
+                                   int leaf, const int32_t* node_lo, const int32_t* node_hi,
+                                   const double* soa, int64_t N, double* bmin, double* bmax,
+                                   hipStream_t st);
+hipError_t launch_forest_slot_base(const int64_t* nbase, int np, int64_t nslots, int32_t* base,
+                                   hipStream_t st);
 
 // leaf tiles (k_tree.hip): tile_of_point via leaf-start flags and a scan
 hipError_t launch_mark_leaves(int L, int leaf, const int32_t* node_lo, const int32_t* node_hi,
@@ -361,7 +490,9 @@ hipError_t launch_features(const int4* blocks, const int2* ids, int64_t nb, cons
 hipError_t launch_rank_predict(const int4* blocks, const int2* ids, int64_t nb, const double* bmin,
                                const double* bmax, int d, double ell, const float* w,
                                const float* mean, const float* scale, int kmax, float* pred,
-                               int32_t* target, hipStream_t st);
+                               int32_t* target, hipStream_t st, const int64_t* pbase = nullptr,
+                               int np = 0, const double* ell_p = nullptr,
+                               const int32_t* dim_p = nullptr);
 // fallback lists: flag[b] = rank[b] < 0 (int64, scanned by the caller into
 // positions pos), then the flagged blocks gathered in order
 hipError_t launch_fail_flags(const int32_t* rank, int64_t nb, int64_t* flag, hipStream_t st);
@@ -433,6 +564,13 @@ hipError_t launch_add_i32(int32_t* dst, const int32_t* src, int64_t cnt, int32_t
 hipError_t launch_shift_blocks(int4* dst, const int4* src, int64_t cnt, int32_t base,
                                hipStream_t st);
 hipError_t launch_fill_i32(int32_t* dst, int64_t cnt, int32_t v, hipStream_t st);
+hipError_t launch_forest_scale(const double* src, int64_t N, int np, const int64_t* pbase,
+                               const double* inv_ell, double* dst64, float* dst32, hipStream_t st);
+hipError_t launch_forest_class(const int4* adm, const int32_t* level, int64_t nadm, int np,
+                               const int64_t* pbase, const int4* cuts, uint64_t* keys,
+                               uint32_t* vals, hipStream_t st);
+hipError_t launch_max_side(const int4* adm, int64_t nadm, int* out, hipStream_t st);
+hipError_t launch_narrow_u64(const uint64_t* src, int64_t n, int32_t* dst, hipStream_t st);
 hipError_t launch_scale_coords(const double* src, int64_t n, int d, double scale, double* dst64,
                                float* dst32, int64_t ntot, int64_t base, hipStream_t st);
 

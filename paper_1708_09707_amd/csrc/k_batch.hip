@@ -30,6 +30,59 @@ __global__ void fill_i32_kernel(int32_t* __restrict__ dst, int64_t cnt, int32_t 
     if (i < cnt) dst[i] = v;
 }
 
+// the union coordinates (3 x N FP64, Morton order) scaled by each point's
+// problem factor 1 / l_p, in FP64 and optionally FP32
+__global__ void forest_scale_kernel(const double* __restrict__ src, int64_t N, int np,
+                                    const int64_t* __restrict__ pbase,
+                                    const double* __restrict__ inv_ell, double* __restrict__ dst64,
+                                    float* __restrict__ dst32) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double s = inv_ell[problem_of(pbase, np, i)];
+    for (int k = 0; k < 3; ++k) {
+        const double v = src[(int64_t)k * N + i] * s;
+        dst64[(int64_t)k * N + i] = v;
+        if (dst32) dst32[(int64_t)k * N + i] = (float)v;
+    }
+}
+
+// size class of every admissible leaf from its problem's level thresholds
+// (cuts[p] = the first levels of the 512-thread, 256-thread and single-wave
+// classes), as the sort key of a stable pass that groups the classes
+__global__ void forest_class_kernel(const int4* __restrict__ adm, const int32_t* __restrict__ level,
+                                    int64_t nadm, int np, const int64_t* __restrict__ pbase,
+                                    const int4* __restrict__ cuts, uint64_t* __restrict__ keys,
+                                    uint32_t* __restrict__ vals) {
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= nadm) return;
+    const int4 c = cuts[problem_of(pbase, np, adm[b].x)];
+    const int l = level[b];
+    keys[b] = l < c.x ? 0 : (l < c.y ? 1 : (l < c.z ? 2 : 3));
+    vals[b] = (uint32_t)b;
+}
+
+__global__ void narrow_u64_kernel(const uint64_t* __restrict__ src, int64_t n,
+                                  int32_t* __restrict__ dst) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (int32_t)src[i];
+}
+
+// largest cluster side among the admissible leaves (integer maximum)
+__global__ void max_side_kernel(const int4* __restrict__ adm, int64_t nadm,
+                                int* __restrict__ out) {
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int v = 0;
+    if (b < nadm) {
+        const int4 q = adm[b];
+        v = q.y - q.x > q.w - q.z ? q.y - q.x : q.w - q.z;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const int w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(out, v);
+}
+
 // dst (3 x ntot, FP64 and optionally FP32) rows [base, base + n) from src
 // (d x n FP64) times scale; dimensions d..2 are zero
 __global__ void scale_coords_kernel(const double* __restrict__ src, int64_t n, int d,
@@ -133,6 +186,36 @@ hipError_t launch_shift_blocks(int4* dst, const int4* src, int64_t cnt, int32_t 
 hipError_t launch_fill_i32(int32_t* dst, int64_t cnt, int32_t v, hipStream_t st) {
     if (cnt == 0) return hipSuccess;
     hipLaunchKernelGGL(fill_i32_kernel, dim3(g1d(cnt)), dim3(256), 0, st, dst, cnt, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_forest_scale(const double* src, int64_t N, int np, const int64_t* pbase,
+                               const double* inv_ell, double* dst64, float* dst32,
+                               hipStream_t st) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(forest_scale_kernel, dim3(g1d(N)), dim3(256), 0, st, src, N, np, pbase,
+                       inv_ell, dst64, dst32);
+    return hipGetLastError();
+}
+
+hipError_t launch_forest_class(const int4* adm, const int32_t* level, int64_t nadm, int np,
+                               const int64_t* pbase, const int4* cuts, uint64_t* keys,
+                               uint32_t* vals, hipStream_t st) {
+    if (nadm == 0) return hipSuccess;
+    hipLaunchKernelGGL(forest_class_kernel, dim3(g1d(nadm)), dim3(256), 0, st, adm, level, nadm,
+                       np, pbase, cuts, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_narrow_u64(const uint64_t* src, int64_t n, int32_t* dst, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(narrow_u64_kernel, dim3(g1d(n)), dim3(256), 0, st, src, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_side(const int4* adm, int64_t nadm, int* out, hipStream_t st) {
+    if (nadm == 0) return hipSuccess;
+    hipLaunchKernelGGL(max_side_kernel, dim3(g1d(nadm)), dim3(256), 0, st, adm, nadm, out);
     return hipGetLastError();
 }
 

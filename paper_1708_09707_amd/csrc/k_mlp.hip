@@ -174,8 +174,11 @@ __global__ void gather_batch_kernel(const float* __restrict__ X, const float* __
 // Block features (FP64, cast to float): [log2 m, log2 n, diam_t / l,
 // diam_s / l, dist / l, min(diam) / max(dist, 1e-12), d, log10 l^2], from the
 // boxes of the block's two clusters (node ids t, s; boxes d-major per node)
+// (d: box stride, dfeat: the problem's dimension, feature 6; boxes of a
+// batched build are padded to 3 dimensions with zeros, which add exact zeros)
 __device__ void block_features(int4 bl, int64_t t, int64_t s, const double* __restrict__ bmin,
-                               const double* __restrict__ bmax, int d, double ell, float* f) {
+                               const double* __restrict__ bmax, int d, int dfeat, double ell,
+                               float* f) {
     double dt = 0.0, ds = 0.0, dist2 = 0.0;
     for (int k = 0; k < d; ++k) {
         const double ta = bmin[t * d + k], tb = bmax[t * d + k];
@@ -194,7 +197,7 @@ __device__ void block_features(int4 bl, int64_t t, int64_t s, const double* __re
     f[3] = (float)(Ds / ell);
     f[4] = (float)(dist / ell);
     f[5] = (float)((Dt < Ds ? Dt : Ds) / (dist > 1e-12 ? dist : 1e-12));
-    f[6] = (float)d;
+    f[6] = (float)dfeat;
     f[7] = (float)log10(ell * ell);
 }
 
@@ -207,7 +210,7 @@ __global__ void features_kernel(const int4* __restrict__ blocks, const int2* __r
     const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (b >= nb) return;
     float f[kIn];
-    block_features(blocks[b], ids[b].x, ids[b].y, bmin, bmax, d, ell, f);
+    block_features(blocks[b], ids[b].x, ids[b].y, bmin, bmax, d, d, ell, f);
     for (int k = 0; k < kIn; ++k) F[b * kIn + k] = f[k];
     if (y) y[b] = (float)rank[b];
 }
@@ -223,7 +226,9 @@ __global__ __launch_bounds__(kInferThreads) void rank_predict_kernel(
     const int4* __restrict__ blocks, const int2* __restrict__ ids, int64_t nb,
     const double* __restrict__ bmin, const double* __restrict__ bmax, int d, double ell,
     const float* __restrict__ w, const float* __restrict__ mean, const float* __restrict__ scale,
-    int kmax, float* __restrict__ pred_out, int32_t* __restrict__ target) {
+    int kmax, float* __restrict__ pred_out, int32_t* __restrict__ target,
+    const int64_t* __restrict__ pbase, int np, const double* __restrict__ ell_p,
+    const int32_t* __restrict__ dim_p) {
     __shared__ float sw[kNParam];
     for (int i = threadIdx.x; i < kNParam; i += kInferThreads) sw[i] = w[i];
     __syncthreads();
@@ -231,7 +236,12 @@ __global__ __launch_bounds__(kInferThreads) void rank_predict_kernel(
     if (b >= nb) return;
     const int4 bl = blocks[b];
     float x[kIn];
-    block_features(bl, ids[b].x, ids[b].y, bmin, bmax, d, ell, x);
+    if (pbase) {  // many problems: the block's problem gives l and d
+        const int p = problem_of(pbase, np, bl.x);
+        block_features(bl, ids[b].x, ids[b].y, bmin, bmax, 3, dim_p[p], ell_p[p], x);
+    } else {
+        block_features(bl, ids[b].x, ids[b].y, bmin, bmax, d, d, ell, x);
+    }
     for (int k = 0; k < kIn; ++k) x[k] = (x[k] - mean[k]) * scale[k];
     float h1[kH], h2[kH];
 #pragma unroll
@@ -426,10 +436,12 @@ hipError_t launch_features(const int4* blocks, const int2* ids, int64_t nb, cons
 hipError_t launch_rank_predict(const int4* blocks, const int2* ids, int64_t nb, const double* bmin,
                                const double* bmax, int d, double ell, const float* w,
                                const float* mean, const float* scale, int kmax, float* pred,
-                               int32_t* target, hipStream_t st) {
+                               int32_t* target, hipStream_t st, const int64_t* pbase, int np,
+                               const double* ell_p, const int32_t* dim_p) {
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(rank_predict_kernel, dim3(g1d(nb, kInferThreads)), dim3(kInferThreads), 0,
-                       st, blocks, ids, nb, bmin, bmax, d, ell, w, mean, scale, kmax, pred, target);
+                       st, blocks, ids, nb, bmin, bmax, d, ell, w, mean, scale, kmax, pred, target,
+                       pbase, np, ell_p, dim_p);
     return hipGetLastError();
 }
 

@@ -335,6 +335,10 @@ __device__ __forceinline__ void near_dispatch(const KernelEval<T>& K, const T* _
             fill_near<HMX_MATERN32, SN, T, R>(K, soa, n, d, ybase, x, i0, mt, cstart, per,
                                               ncols, ld, dst);
             break;
+        case HMX_MATERN_NU1:
+            fill_near<HMX_MATERN_NU1, SN, T, R>(K, soa, n, d, ybase, x, i0, mt, cstart, per,
+                                                ncols, ld, dst);
+            break;
         case HMX_TEST_CONST:
             fill_near<HMX_TEST_CONST, SN, T, R>(K, soa, n, d, ybase, x, i0, mt, cstart, per,
                                                 ncols, ld, dst);

@@ -106,6 +106,24 @@ __device__ __forceinline__ uint64_t spread3(uint64_t x) {
 // Algorithm 6: per point, fixed-point representation of each coordinate
 // relative to the global box, then bit interleaving (dimension 0 in the
 // most significant position of every group of d bits).
+// the code of one point y (d coordinates) in the box [lo, hi]
+__device__ __forceinline__ uint64_t morton_code(const double* y, int d, const double* lo,
+                                                const double* hi) {
+    const int B = d == 1 ? 32 : (d == 2 ? 32 : 21);
+    const double scale = d == 3 ? 2097152.0 : 4294967296.0;  // 2^B
+    const uint64_t qmax = (1ull << B) - 1ull;
+    uint64_t q[3] = {0, 0, 0};
+    for (int k = 0; k < d; ++k) {
+        if (hi[k] == lo[k]) continue;
+        double t = (y[k] - lo[k]) / (hi[k] - lo[k]);
+        double f = floor(t * scale);
+        q[k] = (f >= (double)qmax) ? qmax : (uint64_t)f;
+    }
+    if (d == 1) return q[0];
+    if (d == 2) return (spread2(q[0]) << 1) | spread2(q[1]);
+    return (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+}
+
 __global__ __launch_bounds__(256) void morton_kernel(const void* __restrict__ pts, int f64,
                                                      int64_t n, int d,
                                                      const double* __restrict__ box,
@@ -113,27 +131,133 @@ __global__ __launch_bounds__(256) void morton_kernel(const void* __restrict__ pt
                                                      uint32_t* __restrict__ idx) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int B = d == 1 ? 32 : (d == 2 ? 32 : 21);
-    const double scale = d == 3 ? 2097152.0 : 4294967296.0;  // 2^B
-    const uint64_t qmax = (1ull << B) - 1ull;
-    uint64_t q[3] = {0, 0, 0};
-    for (int k = 0; k < d; ++k) {
-        double lo = box[k], hi = box[d + k];
-        if (hi == lo) continue;
-        double y = load_coord(pts, f64, i * d + k);
-        double t = (y - lo) / (hi - lo);
-        double f = floor(t * scale);
-        q[k] = (f >= (double)qmax) ? qmax : (uint64_t)f;
-    }
-    uint64_t c;
-    if (d == 1)
-        c = q[0];
-    else if (d == 2)
-        c = (spread2(q[0]) << 1) | spread2(q[1]);
-    else
-        c = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
-    codes[i] = c;
+    double y[3];
+    for (int k = 0; k < d; ++k) y[k] = load_coord(pts, f64, i * d + k);
+    codes[i] = morton_code(y, d, box, box + d);
     idx[i] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// many independent problems at once (the forest of a batched build): the
+// problems' points one after another in a union index space, problem p
+// owning [pbase[p], pbase[p + 1]); every problem is ordered in its own box,
+// exactly as a build of it alone would order it
+// ---------------------------------------------------------------------------
+
+// the union points as N x 3 FP64 (coordinates beyond a problem's d are 0)
+__global__ void forest_points_kernel(const ForestInput* __restrict__ in, int np,
+                                     const int64_t* __restrict__ pbase, int64_t N, int f64,
+                                     double* __restrict__ P) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int p = problem_of(pbase, np, i);
+    const ForestInput q = in[p];
+    const int64_t j = i - pbase[p];
+    for (int k = 0; k < 3; ++k) P[i * 3 + k] = k < q.d ? load_coord(q.pts, f64, j * q.d + k) : 0.0;
+}
+
+// per-problem partial boxes: workgroup (x, p) reduces a grid-strided share
+// of problem p's points over its d dimensions (a NaN poisons the box)
+__global__ __launch_bounds__(kBoxThreads) void forest_box_partial_kernel(
+    const double* __restrict__ P, const int64_t* __restrict__ pbase,
+    const int32_t* __restrict__ dims, double* __restrict__ partial) {
+    __shared__ double smin[3][kBoxThreads / kWave], smax[3][kBoxThreads / kWave];
+    const int p = blockIdx.y;
+    const int d = dims[p];
+    const int64_t a = pbase[p], b = pbase[p + 1];
+    double mn[3], mx[3];
+    for (int k = 0; k < 3; ++k) {
+        mn[k] = INFINITY;
+        mx[k] = -INFINITY;
+    }
+    bool nan_seen = false;
+    for (int64_t i = a + blockIdx.x * (int64_t)kBoxThreads + threadIdx.x; i < b;
+         i += (int64_t)gridDim.x * kBoxThreads) {
+        for (int k = 0; k < d; ++k) {
+            double v = P[i * 3 + k];
+            nan_seen |= (v != v);
+            mn[k] = v < mn[k] ? v : mn[k];
+            mx[k] = v > mx[k] ? v : mx[k];
+        }
+    }
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    for (int k = 0; k < d; ++k) {
+        double u = mn[k], v = mx[k];
+        for (int o = 32; o > 0; o >>= 1) {
+            double u2 = __shfl_xor(u, o, 64), v2 = __shfl_xor(v, o, 64);
+            u = u2 < u ? u2 : u;
+            v = v2 > v ? v2 : v;
+        }
+        if (lane == 0) {
+            smin[k][w] = u;
+            smax[k][w] = v;
+        }
+    }
+    unsigned long long anynan = __ballot(nan_seen);
+    __syncthreads();
+    double* out = partial + ((int64_t)p * gridDim.x + blockIdx.x) * 6;
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < d; ++k) {
+            double u = smin[k][0], v = smax[k][0];
+            for (int q = 1; q < kBoxThreads / kWave; ++q) {
+                u = smin[k][q] < u ? smin[k][q] : u;
+                v = smax[k][q] > v ? smax[k][q] : v;
+            }
+            out[k] = u;
+            out[3 + k] = v;
+        }
+    }
+    if (anynan && lane == 0) out[0] = NAN;
+}
+
+// box of problem p: lo in box[6 p + k], hi in box[6 p + 3 + k]
+__global__ void forest_box_final_kernel(const double* __restrict__ partial, int nparts, int np,
+                                        const int32_t* __restrict__ dims,
+                                        double* __restrict__ box) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int d = dims[p];
+    const double* pp = partial + (int64_t)p * nparts * 6;
+    for (int k = 0; k < 3; ++k) {
+        double a = k < d ? pp[k] : 0.0, b = k < d ? pp[3 + k] : 0.0;
+        bool nan = (a != a);
+        for (int q = 1; q < nparts && k < d; ++q) {
+            double a2 = pp[(int64_t)q * 6 + k], b2 = pp[(int64_t)q * 6 + 3 + k];
+            nan |= (a2 != a2);
+            a = a2 < a ? a2 : a;
+            b = b2 > b ? b2 : b;
+        }
+        box[6 * p + k] = nan ? NAN : a;
+        box[6 * p + 3 + k] = b;
+    }
+}
+
+__global__ __launch_bounds__(256) void forest_morton_kernel(const double* __restrict__ P,
+                                                            int64_t N, int np,
+                                                            const int64_t* __restrict__ pbase,
+                                                            const int32_t* __restrict__ dims,
+                                                            const double* __restrict__ box,
+                                                            uint64_t* __restrict__ codes,
+                                                            uint32_t* __restrict__ idx) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int p = problem_of(pbase, np, i);
+    codes[i] = morton_code(P + i * 3, dims[p], box + 6 * p, box + 6 * p + 3);
+    idx[i] = (uint32_t)i;
+}
+
+// sort key of the second, stable pass: the problem of each sorted point
+__global__ void forest_problem_keys_kernel(const uint32_t* __restrict__ idx, int64_t N, int np,
+                                           const int64_t* __restrict__ pbase,
+                                           uint64_t* __restrict__ keys) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < N) keys[i] = (uint64_t)problem_of(pbase, np, (int64_t)idx[i]);
+}
+
+__global__ void gather_u64_kernel(const uint64_t* __restrict__ src, const uint32_t* __restrict__ idx,
+                                  int64_t n, uint64_t* __restrict__ dst) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[idx[i]];
 }
 
 // ---------------------------------------------------------------------------
@@ -285,6 +409,50 @@ hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int bits,
         e = hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return e;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_forest_points(const ForestInput* in, int np, const int64_t* pbase, int64_t N,
+                                int f64, double* P, hipStream_t st) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(forest_points_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
+                       in, np, pbase, N, f64, P);
+    return hipGetLastError();
+}
+
+int forest_box_parts() { return 64; }
+
+hipError_t launch_forest_box(const double* P, int np, const int64_t* pbase, const int32_t* dims,
+                             double* partial, double* box, hipStream_t st) {
+    hipLaunchKernelGGL(forest_box_partial_kernel, dim3(forest_box_parts(), np), dim3(kBoxThreads),
+                       0, st, P, pbase, dims, partial);
+    hipLaunchKernelGGL(forest_box_final_kernel, dim3((np + 63) / 64), dim3(64), 0, st, partial,
+                       forest_box_parts(), np, dims, box);
+    return hipGetLastError();
+}
+
+hipError_t launch_forest_morton(const double* P, int64_t N, int np, const int64_t* pbase,
+                                const int32_t* dims, const double* box, uint64_t* codes,
+                                uint32_t* idx, hipStream_t st) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(forest_morton_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
+                       P, N, np, pbase, dims, box, codes, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_forest_problem_keys(const uint32_t* idx, int64_t N, int np,
+                                      const int64_t* pbase, uint64_t* keys, hipStream_t st) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(forest_problem_keys_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0,
+                       st, idx, N, np, pbase, keys);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_u64(const uint64_t* src, const uint32_t* idx, int64_t n, uint64_t* dst,
+                             hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_u64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       src, idx, n, dst);
     return hipGetLastError();
 }
 

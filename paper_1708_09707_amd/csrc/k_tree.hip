@@ -134,22 +134,23 @@ hipError_t scan_generic(const T* in, T* out, int64_t n, int inclusive, int64_t* 
 // ---------------------------------------------------------------------------
 // cluster tree (Section 2.1; Z-order halving, Section 4.4)
 // ---------------------------------------------------------------------------
-__global__ void tree_level_kernel(int level, int64_t n, int leaf, int32_t* __restrict__ lo,
-                                  int32_t* __restrict__ hi) {
-    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t cnt = 1ll << level;
-    if (k >= cnt) return;
-    const int64_t id = cnt - 1 + k;
+// node k of `level` in the tree whose slots start at B: a leaf's parent slot
+// that does not split leaves it empty (lo = hi = -1); the root holds [r0, r1)
+__device__ __forceinline__ void tree_node(int64_t B, int level, int64_t k, int32_t r0, int32_t r1,
+                                          int leaf, int32_t* __restrict__ lo,
+                                          int32_t* __restrict__ hi) {
+    const int64_t local = (1ll << level) - 1 + k;
+    const int64_t id = B + local;
     if (level == 0) {
-        lo[0] = 0;
-        hi[0] = (int32_t)n;
+        lo[id] = r0;
+        hi[id] = r1;
         return;
     }
-    const int64_t p = (id - 1) / 2;
+    const int64_t p = B + (local - 1) / 2;
     const int32_t plo = lo[p], phi = hi[p];
     if (plo >= 0 && phi - plo > leaf) {
         const int32_t mid = plo + (phi - plo) / 2;
-        if (id & 1) {
+        if (local & 1) {
             lo[id] = plo;
             hi[id] = mid;
         } else {
@@ -162,20 +163,33 @@ __global__ void tree_level_kernel(int level, int64_t n, int leaf, int32_t* __res
     }
 }
 
+__global__ void tree_level_kernel(int level, int64_t n, int leaf, int32_t* __restrict__ lo,
+                                  int32_t* __restrict__ hi) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= (1ll << level)) return;
+    tree_node(0, level, k, 0, (int32_t)n, leaf, lo, hi);
+}
+
+// the same level of every problem's tree (grid y = problem; problem p's
+// slots start at nbase[p], its tree has levels 0 .. depth[p])
+__global__ void forest_tree_level_kernel(int level, const int64_t* __restrict__ pbase,
+                                         const int64_t* __restrict__ nbase,
+                                         const int32_t* __restrict__ depth, int leaf,
+                                         int32_t* __restrict__ lo, int32_t* __restrict__ hi) {
+    const int p = blockIdx.y;
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (level > depth[p] || k >= (1ll << level)) return;
+    tree_node(nbase[p], level, k, (int32_t)pbase[p], (int32_t)pbase[p + 1], leaf, lo, hi);
+}
+
 // one wave per node: a leaf cluster reduces its points, an inner cluster
 // takes the union of its two children (min/max are exact, so both give the
 // brute-force box of Section 2.2 bit for bit)
-__global__ __launch_bounds__(256) void box_level_kernel(int level, int d, int leaf,
-                                                        const int32_t* __restrict__ lo,
-                                                        const int32_t* __restrict__ hi,
-                                                        const double* __restrict__ soa, int64_t n,
-                                                        double* __restrict__ bmin,
-                                                        double* __restrict__ bmax) {
-    const int lane = threadIdx.x & 63;
-    const int64_t k = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / 64;
-    const int64_t cnt = 1ll << level;
-    if (k >= cnt) return;
-    const int64_t id = cnt - 1 + k;
+__device__ __forceinline__ void box_node(int64_t id, int64_t c0, int lane, int d, int leaf,
+                                         const int32_t* __restrict__ lo,
+                                         const int32_t* __restrict__ hi,
+                                         const double* __restrict__ soa, int64_t n,
+                                         double* __restrict__ bmin, double* __restrict__ bmax) {
     const int32_t a = lo[id], b = hi[id];
     if (a < 0) return;
     if (b - a <= leaf) {
@@ -197,7 +211,7 @@ __global__ __launch_bounds__(256) void box_level_kernel(int level, int d, int le
             }
         }
     } else if (lane == 0) {
-        const int64_t c0 = 2 * id + 1, c1 = 2 * id + 2;
+        const int64_t c1 = c0 + 1;
         for (int q = 0; q < d; ++q) {
             double m0 = bmin[c0 * d + q], m1 = bmin[c1 * d + q];
             double x0 = bmax[c0 * d + q], x1 = bmax[c1 * d + q];
@@ -205,6 +219,42 @@ __global__ __launch_bounds__(256) void box_level_kernel(int level, int d, int le
             bmax[id * d + q] = x1 > x0 ? x1 : x0;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void box_level_kernel(int level, int d, int leaf,
+                                                        const int32_t* __restrict__ lo,
+                                                        const int32_t* __restrict__ hi,
+                                                        const double* __restrict__ soa, int64_t n,
+                                                        double* __restrict__ bmin,
+                                                        double* __restrict__ bmax) {
+    const int64_t k = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / 64;
+    const int64_t cnt = 1ll << level;
+    if (k >= cnt) return;
+    const int64_t id = cnt - 1 + k;
+    box_node(id, 2 * id + 1, threadIdx.x & 63, d, leaf, lo, hi, soa, n, bmin, bmax);
+}
+
+// the same level of every problem's tree (grid y = problem); boxes of the
+// union's 3 x N coordinates (a problem's missing dimensions are zero there,
+// so its boxes are [0, 0] in them)
+__global__ __launch_bounds__(256) void forest_box_level_kernel(
+    int level, const int64_t* __restrict__ nbase, const int32_t* __restrict__ depth, int leaf,
+    const int32_t* __restrict__ lo, const int32_t* __restrict__ hi,
+    const double* __restrict__ soa, int64_t N, double* __restrict__ bmin,
+    double* __restrict__ bmax) {
+    const int p = blockIdx.y;
+    const int64_t k = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / 64;
+    if (level > depth[p] || k >= (1ll << level)) return;
+    const int64_t local = (1ll << level) - 1 + k;
+    const int64_t B = nbase[p];
+    box_node(B + local, B + 2 * local + 1, threadIdx.x & 63, 3, leaf, lo, hi, soa, N, bmin, bmax);
+}
+
+// slot -> first slot of its problem's tree
+__global__ void forest_slot_base_kernel(const int64_t* __restrict__ nbase, int np, int64_t nslots,
+                                        int32_t* __restrict__ base) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < nslots) base[i] = (int32_t)nbase[problem_of(nbase, np, i)];
 }
 
 // ---------------------------------------------------------------------------
@@ -286,7 +336,7 @@ __global__ __launch_bounds__(kTravThreads) void traverse_write_kernel(
     const int64_t* __restrict__ block_off, int level, int2* __restrict__ next,
     int4* __restrict__ adm, int32_t* __restrict__ adm_level, int2* __restrict__ adm_ids,
     int64_t adm_base, int4* __restrict__ dense, int32_t* __restrict__ dense_level,
-    int64_t dense_base) {
+    int64_t dense_base, const int32_t* __restrict__ slot_base) {
     __shared__ int64_t sh[kScanThreads / 64 + 1];
     const int64_t nblk = gridDim.x;
     const int64_t base = blockIdx.x * (int64_t)kTravTile + threadIdx.x * (int64_t)kTravItems;
@@ -311,11 +361,15 @@ __global__ __launch_bounds__(kTravThreads) void traverse_write_kernel(
         if (cls[k] < 0) continue;
         const int64_t t = ts[k].x, s = ts[k].y;
         if (cls[k] == 1) {
+            // children 2 i + 1, 2 i + 2 in the node's own tree (whose slots
+            // start at slot_base[i]; 0 for a single tree)
+            const int64_t t1 = 2 * t + 1 - (slot_base ? slot_base[t] : 0);
+            const int64_t s1 = 2 * s + 1 - (slot_base ? slot_base[s] : 0);
             int2* o = next + 4 * off[1];
-            o[0] = make_int2((int)(2 * t + 1), (int)(2 * s + 1));
-            o[1] = make_int2((int)(2 * t + 1), (int)(2 * s + 2));
-            o[2] = make_int2((int)(2 * t + 2), (int)(2 * s + 1));
-            o[3] = make_int2((int)(2 * t + 2), (int)(2 * s + 2));
+            o[0] = make_int2((int)t1, (int)s1);
+            o[1] = make_int2((int)t1, (int)(s1 + 1));
+            o[2] = make_int2((int)(t1 + 1), (int)s1);
+            o[3] = make_int2((int)(t1 + 1), (int)(s1 + 1));
             off[1]++;
         } else {
             const int4 r = make_int4(lo[t], hi[t], lo[s], hi[s]);
@@ -423,11 +477,41 @@ hipError_t launch_traverse_write(const int2* cur, int64_t ncur, const int32_t* n
                                  int d, int leaf, double eta, const int64_t* block_offsets,
                                  int level, int2* next, int4* adm, int32_t* adm_level,
                                  int2* adm_ids, int64_t adm_base, int4* dense,
-                                 int32_t* dense_level, int64_t dense_base, hipStream_t st) {
+                                 int32_t* dense_level, int64_t dense_base,
+                                 const int32_t* slot_base, hipStream_t st) {
     const int64_t nb = traverse_blocks(ncur);
     hipLaunchKernelGGL(traverse_write_kernel, dim3((unsigned)nb), dim3(kTravThreads), 0, st, cur,
                        ncur, node_lo, node_hi, bmin, bmax, d, leaf, eta, block_offsets, level,
-                       next, adm, adm_level, adm_ids, adm_base, dense, dense_level, dense_base);
+                       next, adm, adm_level, adm_ids, adm_base, dense, dense_level, dense_base,
+                       slot_base);
+    return hipGetLastError();
+}
+
+hipError_t launch_forest_tree_level(int level, int np, const int64_t* pbase, const int64_t* nbase,
+                                    const int32_t* depth, int leaf, int32_t* node_lo,
+                                    int32_t* node_hi, hipStream_t st) {
+    const int64_t cnt = 1ll << level;
+    hipLaunchKernelGGL(forest_tree_level_kernel, dim3((unsigned)((cnt + 255) / 256), np),
+                       dim3(256), 0, st, level, pbase, nbase, depth, leaf, node_lo, node_hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_forest_box_level(int level, int np, const int64_t* nbase, const int32_t* depth,
+                                   int leaf, const int32_t* node_lo, const int32_t* node_hi,
+                                   const double* soa, int64_t N, double* bmin, double* bmax,
+                                   hipStream_t st) {
+    const int64_t threads = (1ll << level) * 64;
+    hipLaunchKernelGGL(forest_box_level_kernel, dim3((unsigned)((threads + 255) / 256), np),
+                       dim3(256), 0, st, level, nbase, depth, leaf, node_lo, node_hi, soa, N, bmin,
+                       bmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_forest_slot_base(const int64_t* nbase, int np, int64_t nslots, int32_t* base,
+                                   hipStream_t st) {
+    if (nslots == 0) return hipSuccess;
+    hipLaunchKernelGGL(forest_slot_base_kernel, dim3((unsigned)((nslots + 255) / 256)), dim3(256),
+                       0, st, nbase, np, nslots, base);
     return hipGetLastError();
 }
 

@@ -19,11 +19,12 @@ LIB_PATH = os.path.join(_HERE, "libhmx.so")
 HMX_OK, HMX_ERR_INVALID_ARG, HMX_ERR_OOM, HMX_ERR_DEVICE, HMX_ERR_NOT_CONVERGED, \
     HMX_ERR_UNSUPPORTED = range(6)
 HMX_F64, HMX_F32, HMX_BF16 = 0, 1, 2
-HMX_GAUSSIAN, HMX_MATERN32, HMX_TEST_CONST, HMX_TEST_LOWRANK = 0, 1, 3, 4
+HMX_GAUSSIAN, HMX_MATERN32, HMX_MATERN_NU1, HMX_TEST_CONST, HMX_TEST_LOWRANK = 0, 1, 2, 3, 4
 HMX_RANK_ADAPTIVE, HMX_RANK_LEARNED, HMX_RANK_FIXED = 0, 1, 2
 HMX_MLP_NPARAMS, HMX_MLP_FEATURES = 8961, 8
 RANK_MODES = {"adaptive": HMX_RANK_ADAPTIVE, "learned": HMX_RANK_LEARNED, "fixed": HMX_RANK_FIXED}
-KERNELS = {"gaussian": HMX_GAUSSIAN, "matern32": HMX_MATERN32, "const": HMX_TEST_CONST,
+KERNELS = {"gaussian": HMX_GAUSSIAN, "matern32": HMX_MATERN32, "matern_nu1": HMX_MATERN_NU1,
+           "const": HMX_TEST_CONST,
            "lowrank": HMX_TEST_LOWRANK}
 DTYPES = {"f64": HMX_F64, "f32": HMX_F32, "bf16": HMX_BF16}
 
@@ -36,12 +37,18 @@ EXPORTS = ["hmx_params_default", "hmx_build", "hmx_matvec", "hmx_cg_solve", "hmx
            "hmx_mlp_forward", "hmx_mlp_loss_grad", "hmx_mlp_adam", "hmx_mlp_train",
            "hmx_block_features", "hmx_build_batched", "hmx_get_batch", "hmx_matvec_graph",
            "hmx_graph_launch", "hmx_graph_destroy", "hmx_autotune", "hmx_set_tile_config",
-           "hmx_rank_predict"]
+           "hmx_rank_predict", "hmx_matvec_batched", "hmx_mlp_save",
+           "hmx_mlp_load"]
 HMX_TILE_CONFIGS = 15
 
 
 class hmx_kernel(C.Structure):
     _fields_ = [("kind", C.c_int), ("p0", C.c_double), ("p1", C.c_double)]
+
+
+# device allocator hooks of hmx_params (dev_alloc / dev_free)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
 
 
 class hmx_params(C.Structure):
@@ -52,7 +59,8 @@ class hmx_params(C.Structure):
                 ("rank_mode", C.c_int), ("aca_chunk_mb", C.c_int32),
                 ("aca_only", C.c_int32), ("mlp", C.c_void_p),
                 ("learned_one_shot", C.c_int32), ("near_recompute", C.c_int32),
-                ("aca_split_rows", C.c_int32), ("symmetric_far", C.c_int32)]
+                ("aca_split_rows", C.c_int32), ("symmetric_far", C.c_int32),
+                ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p)]
 
 
 class hmx_stats(C.Structure):
@@ -104,6 +112,9 @@ def lib():
         L.hmx_matvec.argtypes = [P, P, P, C.c_int, f64, f64, P]
         L.hmx_cg_solve.argtypes = [P, P, P, f64, i32, P, C.POINTER(i32), C.POINTER(f64),
                                    C.POINTER(f64)]
+        L.hmx_matvec_batched.argtypes = [i32, P, P, P, C.c_int, f64, f64, P]
+        L.hmx_mlp_save.argtypes = [P, C.c_char_p]
+        L.hmx_mlp_load.argtypes = [C.c_char_p, C.POINTER(P)]
         L.hmx_get_partition.argtypes = [P, P, P, P, C.POINTER(i64), P, C.POINTER(i64), P]
         L.hmx_get_boxes.argtypes = [P, P, P, P]
         L.hmx_get_ranks.argtypes = [P, P, P]
@@ -178,6 +189,9 @@ def hmx_params_default(**overrides) -> hmx_params:
             v = RANK_MODES[v]
         if k == "mlp":
             v = v.handle if isinstance(v, RankMLP) else v
+        if k == "allocator":  # a TorchAllocator (or any object with alloc_fn / free_fn)
+            p.dev_alloc, p.dev_free = v.alloc_fn, v.free_fn
+            continue
         setattr(p, k, v)
     if "compute_dtype" in overrides and "storage_dtype" not in overrides:
         p.storage_dtype = p.compute_dtype  # store in the compute precision unless asked
@@ -221,6 +235,20 @@ def hmx_matvec(h, x, z, alpha=1.0, beta=0.0, stream=None):
     _check_vectors(h, x, z)
     _check(lib().hmx_matvec(h, C.c_void_p(x.data_ptr()), C.c_void_p(z.data_ptr()), _dtype_of(x),
                             float(alpha), float(beta), _stream(stream)))
+
+
+def hmx_matvec_batched(handles, xs, zs, alpha=1.0, beta=0.0, stream=None):
+    """z[q] = alpha (H_q + sigma2 I) x[q] + beta z[q] over separately built handles."""
+    if not (len(handles) == len(xs) == len(zs)):
+        raise ValueError("handles, xs and zs must have one entry per problem")
+    for h, x, z in zip(handles, xs, zs):
+        _check_vectors(h, x, z)
+    k = len(handles)
+    hs = (C.c_void_p * k)(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    xp = (C.c_void_p * k)(*[x.data_ptr() for x in xs])
+    zp = (C.c_void_p * k)(*[z.data_ptr() for z in zs])
+    _check(lib().hmx_matvec_batched(k, hs, xp, zp, _dtype_of(xs[0]) if k else HMX_F32,
+                                    float(alpha), float(beta), _stream(stream)))
 
 
 def hmx_cg_solve(h, b, x, rel_tol=1e-6, max_iter=1000, stream=None, raise_on_fail=True):
@@ -329,6 +357,16 @@ def hmx_mlp_create(params=None):
 def hmx_mlp_destroy(h):
     if h:
         _check(lib().hmx_mlp_destroy(h))
+
+
+def hmx_mlp_save(h, path):
+    _check(lib().hmx_mlp_save(h, os.fsencode(path)))
+
+
+def hmx_mlp_load(path):
+    h = C.c_void_p()
+    _check(lib().hmx_mlp_load(os.fsencode(path), C.byref(h)))
+    return h
 
 
 def hmx_mlp_set_params(h, params=None, mean=None, scale=None):
@@ -488,11 +526,62 @@ def hmx_get_batch(h):
     return off
 
 
+class TorchAllocator:
+    """Device allocator hooks that take the library's device memory from
+    PyTorch's caching allocator (pass as ``allocator=`` to a build).  Keeps
+    the ctypes callbacks alive and counts what is outstanding."""
+
+    def __init__(self, device=None):
+        import torch
+        self._torch = torch
+        self.device = torch.cuda.current_device() if device is None else device
+        self.live = {}          # pointer -> bytes
+        self.allocs = 0
+        self.frees = 0
+        self.alloc_fn = ALLOC_FN(self._alloc)
+        self.free_fn = FREE_FN(self._free)
+
+    def take(self, nbytes):
+        """Allocate nbytes of device memory; return the pointer or None."""
+        try:
+            return self._torch.cuda.caching_allocator_alloc(nbytes, self.device)
+        except RuntimeError:  # torch's out-of-memory error
+            return None
+
+    def _alloc(self, nbytes, ctx):
+        self.allocs += 1
+        ptr = self.take(int(nbytes))
+        if ptr:
+            self.live[ptr] = int(nbytes)
+        return ptr
+
+    def _free(self, ptr, nbytes, ctx):
+        self.frees += 1
+        size = self.live.pop(ptr, None)
+        if size != int(nbytes):
+            raise RuntimeError("dev_free of %s (%d bytes) that was not handed out" % (ptr, nbytes))
+        self._torch.cuda.caching_allocator_delete(ptr)
+
+    @property
+    def outstanding_bytes(self):
+        return sum(self.live.values())
+
+
 class RankMLP:
     """Owner of an hmx_mlp rank predictor."""
 
     def __init__(self, params=None):
         self.handle = hmx_mlp_create(params)
+
+    @classmethod
+    def load(cls, path):
+        """A predictor from a checkpoint file written by save()."""
+        self = cls.__new__(cls)
+        self.handle = hmx_mlp_load(path)
+        return self
+
+    def save(self, path):
+        hmx_mlp_save(self.handle, path)
 
     def set_params(self, params=None, mean=None, scale=None):
         hmx_mlp_set_params(self.handle, params, mean, scale)
@@ -532,6 +621,7 @@ class HMatrix:
 
     def __init__(self, points, kernel="gaussian", p0=1.0, stream=None, **params):
         self.params = hmx_params_default(**params)
+        self.allocator = params.get("allocator")  # its callbacks must outlive the handle
         self.kernel = make_kernel(kernel, p0)
         self.n, self.d = int(points.shape[0]), int(points.shape[1])
         self.h = hmx_build(points, self.kernel, self.params, stream)
@@ -542,6 +632,7 @@ class HMatrix:
         """One block-diagonal handle over many problems (hmx_build_batched)."""
         self = cls.__new__(cls)
         self.params = hmx_params_default(**params)
+        self.allocator = params.get("allocator")
         p0s = [1.0] * len(points_list) if p0s is None else p0s
         ks = [make_kernel(kernel, p) for p in p0s]
         self.kernel = ks[0]

@@ -6,6 +6,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -36,9 +37,9 @@ def test_struct_layout_matches_c(tmp_path):
 #include "hmx.h"
 int main(void) {
   printf("%zu %zu %zu\\n", sizeof(hmx_params), sizeof(hmx_stats), sizeof(hmx_kernel));
-  printf("%zu %zu %zu %zu %zu\\n", offsetof(hmx_params, max_rank), offsetof(hmx_params, sigma2),
+  printf("%zu %zu %zu %zu %zu %zu\\n", offsetof(hmx_params, max_rank), offsetof(hmx_params, sigma2),
          offsetof(hmx_params, rank_mode), offsetof(hmx_params, symmetric_far),
-         offsetof(hmx_params, storage_dtype));
+         offsetof(hmx_params, storage_dtype), offsetof(hmx_params, alloc_ctx));
   printf("%zu %zu %zu %zu\\n", offsetof(hmx_stats, matvec_bytes), offsetof(hmx_stats, device_bytes),
          offsetof(hmx_stats, level_sizes), offsetof(hmx_stats, v_entries));
   return 0;
@@ -51,7 +52,7 @@ int main(void) {
     want = [C.sizeof(hmx.hmx_params), C.sizeof(hmx.hmx_stats), C.sizeof(hmx.hmx_kernel),
             hmx.hmx_params.max_rank.offset, hmx.hmx_params.sigma2.offset,
             hmx.hmx_params.rank_mode.offset, hmx.hmx_params.symmetric_far.offset,
-            hmx.hmx_params.storage_dtype.offset,
+            hmx.hmx_params.storage_dtype.offset, hmx.hmx_params.alloc_ctx.offset,
             hmx.hmx_stats.matvec_bytes.offset, hmx.hmx_stats.device_bytes.offset,
             hmx.hmx_stats.level_sizes.offset, hmx.hmx_stats.v_entries.offset]
     assert [int(v) for v in out] == want
@@ -95,6 +96,12 @@ def test_validation_before_device_work():
     assert L.hmx_build(dummy, 0, 10, 2, C.byref(K), C.byref(Q), None, C.byref(h)) == 5
     Q = hmx.hmx_params_default(compute_dtype="f32", storage_dtype="f64")
     assert L.hmx_build(dummy, 0, 10, 2, C.byref(K), C.byref(Q), None, C.byref(h)) == 5
+    # allocator hooks come in pairs (checked before any allocation)
+    calls = []
+    Q = hmx.hmx_params_default()
+    Q.dev_alloc = hmx.ALLOC_FN(lambda nbytes, ctx: calls.append(nbytes) or None)
+    assert L.hmx_build(dummy, 0, 10, 2, C.byref(K), C.byref(Q), None, C.byref(h)) == 1
+    assert b"dev_alloc and dev_free" in L.hmx_last_error() and not calls
     K0 = hmx.make_kernel("gaussian", 0.0)
     assert L.hmx_build(dummy, 0, 10, 2, C.byref(K0), C.byref(P), None, C.byref(h)) == 1
     assert not h.value
@@ -143,3 +150,25 @@ def test_binding_rejects_vectors_of_the_wrong_size(monkeypatch):
                   lambda: hmx.hmx_matvec_graph(h, b, good)):
             with pytest.raises(ValueError):
                 f()
+
+
+def test_mlp_load_rejects_bad_files(tmp_path):
+    """A predictor file is validated on the host before any device work."""
+    from paper_1708_09707_amd import hmx
+    L = hmx.lib()
+    h = C.c_void_p()
+    missing = tmp_path / "none.bin"
+    assert L.hmx_mlp_load(str(missing).encode(), C.byref(h)) == 1 and not h.value
+    n = hmx.HMX_MLP_NPARAMS
+    good = b"HMXMLP01" + np.array([n, 3], np.int64).tobytes() + \
+        np.zeros(3 * n + 16, np.float32).tobytes()
+    bad = {"magic": b"HMXMLP02" + good[8:],
+           "count": b"HMXMLP01" + np.array([n + 1, 3], np.int64).tobytes() + good[24:],
+           "step": b"HMXMLP01" + np.array([n, -1], np.int64).tobytes() + good[24:],
+           "short": good[:-4], "long": good + b"\0"}
+    for what, blob in bad.items():
+        f = tmp_path / (what + ".bin")
+        f.write_bytes(blob)
+        assert L.hmx_mlp_load(str(f).encode(), C.byref(h)) == 1, what
+        assert b"not a rank predictor file" in L.hmx_last_error(), what
+        assert not h.value

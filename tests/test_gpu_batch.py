@@ -139,3 +139,27 @@ def test_batched_invalid(H):
     with pytest.raises(H.HmxError):
         H.hmx_block_features(h)
     H.hmx_destroy(h)
+
+
+def test_matvec_batched_over_separate_handles(H):
+    """hmx_matvec_batched over separately built handles equals one
+    hmx_matvec per handle, bit for bit, with alpha and beta."""
+    specs = [(3000, 2, 0.02), (5000, 3, 0.05), (1200, 2, 0.01)]
+    hs, xs, zs, zr = [], [], [], []
+    for q, (n, d, p0) in enumerate(specs):
+        pts = synth.uniform_points(n, d, 700 + q, dtype=np.float32)
+        hs.append(H.HMatrix(_dev(pts), "gaussian", p0, compute_dtype="f32", leaf_size=64,
+                            eta=1.5, aca_eps=1e-5, max_rank=32))
+        xs.append(_dev(synth.normal_vector(n, 710 + q, dtype=np.float32)))
+        z0 = _dev(synth.normal_vector(n, 720 + q, dtype=np.float32))
+        zs.append(z0.clone())
+        zr.append(z0.clone())
+    H.hmx_matvec_batched([h.h for h in hs], xs, zs, alpha=0.5, beta=-2.0)
+    for h, x, z in zip(hs, xs, zr):
+        H.hmx_matvec(h.h, x, z, 0.5, -2.0)
+    for a, b in zip(zs, zr):
+        assert torch.equal(a, b)
+    with pytest.raises(ValueError):
+        H.hmx_matvec_batched([h.h for h in hs], xs[:2], zs[:2] + [xs[0]])
+    for h in hs:
+        h.close()

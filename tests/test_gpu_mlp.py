@@ -160,6 +160,37 @@ def test_train_loop_equals_steps(H, orc):
     b.close()
 
 
+def test_checkpoint_resumes_training_bit_for_bit(H, tmp_path):
+    """hmx_mlp_save / hmx_mlp_load: a predictor saved after 10 training steps
+    and loaded again holds the same parameters and standardisation, predicts
+    the same, and its next 10 steps (Adam moments and step count restored)
+    equal 20 uninterrupted steps bit for bit."""
+    n, B = 4000, 256
+    X, y = _features_data(n, 81)
+    idx = synth.batch_indices(n, B, 20, 82)
+    w = synth.mlp_init_params(13)
+    mean = X.mean(axis=0).astype(np.float32)
+    scale = (1.0 / X.std(axis=0)).astype(np.float32)
+    Xd, yd, idd = _dev(X), _dev(y), _dev(idx)
+    a = H.RankMLP(w)
+    a.set_params(w, mean, scale)
+    a.train(Xd, yd, idd, B, 20, q=0.9, lr=3e-3)
+    b = H.RankMLP(w)
+    b.set_params(w, mean, scale)
+    b.train(Xd, yd, idd[:10 * B].contiguous(), B, 10, q=0.9, lr=3e-3)
+    path = tmp_path / "predictor.bin"
+    b.save(path)
+    assert path.stat().st_size == 8 + 16 + 4 * (3 * NP + 16)
+    c = H.RankMLP.load(path)
+    for u, v in zip(b.get_params(), c.get_params()):
+        assert np.array_equal(u, v)
+    assert torch.equal(b.forward(Xd), c.forward(Xd))
+    c.train(Xd, yd, idd[10 * B:].contiguous(), B, 10, q=0.9, lr=3e-3)
+    assert np.array_equal(a.get_params()[0], c.get_params()[0])
+    for m in (a, b, c):
+        m.close()
+
+
 def test_invalid_arguments(H):
     mlp = H.RankMLP()
     X = torch.zeros((4, 8), dtype=torch.float32, device="cuda:0")
@@ -346,6 +377,7 @@ def test_fused_inference_matches_oracle(H, orc, d, kernel, p0):
     offs = np.cumsum([0] + [a * b + b for a, b in zip((8, 64, 64, 64), (64, 64, 64, 1))])
     for lay, (fi, fo) in enumerate(zip((8, 64, 64, 64), (64, 64, 64, 1))):
         w[offs[lay] + fi * fo: offs[lay + 1]] = 0.3 * g.standard_normal(fo)
+    w[-65:-1] *= 3.0  # output layer: spread the outputs over several integer targets
     w[-1] = 6.0  # centre the outputs where the target clamp is active
     w = w.astype(np.float32)
     part = hm.partition()

@@ -129,8 +129,10 @@ def test_symmetric_f32_bf16(H, orc, storage):
 
 def test_symmetric_learned_recompute_batched(H):
     """Learned sizing keeps the symmetric build's ranks and product bits; the
-    no-storage near field gives the stored product's bits; two problems in
-    one handle give each problem's product."""
+    no-storage near field gives the stored product within FP32 rounding (the
+    entries are evaluated by another instance of the same formula, whose
+    compiled FP32 exponent argument can differ in the last bit); two problems
+    in one handle give each problem's product."""
     n, p0 = 20000, 0.01
     pts = synth.uniform_points(n, 2, 4601, dtype=np.float32)
     x = _dev(synth.normal_vector(n, 4602, dtype=np.float32))
@@ -144,7 +146,10 @@ def test_symmetric_learned_recompute_batched(H):
     hr = H.HMatrix(_dev(pts), "gaussian", p0, near_recompute=1, **kw)
     za = ha.matvec(x)
     assert np.array_equal(ha.ranks(), hl.ranks()) and torch.equal(za, hl.matvec(x))
-    assert torch.equal(za, hr.matvec(x))
+    zr = hr.matvec(x)
+    dev = (torch.linalg.norm((zr - za).double()) / torch.linalg.norm(za.double())).item()
+    print("no-storage near field vs stored: %.2e" % dev)
+    assert dev <= 1e-6
     pts2 = synth.uniform_points(n // 2, 3, 4603, dtype=np.float32)
     h2 = H.HMatrix(_dev(pts2), "gaussian", p0, **kw)
     x2 = _dev(synth.normal_vector(n // 2, 4604, dtype=np.float32))
