@@ -53,6 +53,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rowtile_traffic.json")
 
 # the forms compared (hmx_params overrides on top of the workload's settings)
 FORMS = {
+    "plain_f64": dict(compute_dtype="f64", storage_dtype="f64", near_dtype="f64",
+                      rank_mode="adaptive"),
     "plain": dict(storage_dtype="f32", near_dtype="f32", rank_mode="adaptive"),
     "learned_mixed": dict(storage_dtype="bf16", near_dtype="bf16", rank_mode="learned"),
 }
@@ -75,11 +77,11 @@ def kernel_source_hash(text=None) -> str:
     return hashlib.sha256((text[a:b] + text[c:d]).encode()).hexdigest()[:16]
 
 
-def rowtile_bytes(st) -> float:
+def rowtile_bytes(st, esz=4) -> float:
     """Algorithmic bytes of one row-tile launch: the stored near field and U
-    read once, t read once, z written once, the permutation read once.
-    Re-reads of x|sigma segments served from cache are not counted."""
-    esz = 4  # FP32 vectors
+    read once, t read once, z written once, the permutation read once
+    (esz: bytes per vector entry, 8 for FP64 arithmetic).  Re-reads of
+    x|sigma segments served from cache are not counted."""
     return (st.near_entries * st.near_entry_bytes + st.u_entries * st.entry_bytes
             + st.sum_rank * esz + st.n * (esz + 4))
 
@@ -322,7 +324,11 @@ def stream_copy_gbs(torch, dev, mib=4096, reps=5):
 
 def cpu_baseline(wl, pts, x0, z_gpu_first, perm_gpu):
     """The oracle (FP64, stored mode) on a bounded sample of the workload: all
-    leaves whose row cluster meets a contiguous range of Morton-order rows."""
+    leaves whose row cluster meets a contiguous range of Morton-order rows.
+    Beside it, the measured FP64 form's product is checked against the
+    oracle: against its H-matrix rows (same method, same arithmetic) and
+    against its FP64 dense product on 4096 sampled rows (the tolerance
+    10 eps + rounding)."""
     import oracle
     n = wl["n"]
     frac = wl.get("cpu_rows_frac", 1.0 / 32)
@@ -333,19 +339,25 @@ def cpu_baseline(wl, pts, x0, z_gpu_first, perm_gpu):
     z_rows, perm, t = oracle.hmvp_rows(pts.astype(np.float64), x0.astype(np.float64),
                                        wl["kernel"], wl["p0"], wl["leaf"], wl["eta"], wl["kmax"],
                                        wl["eps"], row_lo, row_hi,
-                                       eps0=1e-7 if wl["dtype"] == "f32" else 1e-14)
+                                       eps0=1e-14)
     wall = time.perf_counter() - t0
     gbs = t["entries"] * 8 / t["apply_s"] / 1e9
     zg = z_gpu_first[perm[row_lo:row_hi]]
     err = float(np.linalg.norm(zg - z_rows) / np.linalg.norm(z_rows))
     assert np.array_equal(perm, perm_gpu), "GPU permutation differs from the oracle"
+    rows = synth.sample_rows(n, 4096, 2201)
+    zd = oracle.dense_matvec(pts.astype(np.float64), x0.astype(np.float64), wl["kernel"],
+                             wl["p0"], rows=rows)
+    err_dense = float(np.linalg.norm(z_gpu_first[rows] - zd) / np.linalg.norm(zd))
     return {
         "value": gbs, "unit": "GB/s", "cores": oracle.num_threads(), "kind": "oracle",
         "sample": "stored-mode H-matvec of Morton rows [%d, %d) (%d of %d rows, every leaf "
                   "meeting them built in FP64); apply %.3f s over %.3g stored entries" % (
                       row_lo, row_hi, nrows, n, t["apply_s"], t["entries"]),
         "build_s_sample": t["build_s"], "partition_s": t["partition_s"], "wall_s": wall,
-        "plain_gpu_vs_oracle_rel_err": err,
+        "gpu_f64_vs_oracle_hmatrix_rel_err": err,
+        "gpu_f64_vs_oracle_dense_rel_err_4096rows": err_dense,
+        "tolerance_10eps": 10 * wl["eps"],
     }
 
 
@@ -363,6 +375,9 @@ def main():
                     help="skip the N = 2^22 three-dimensional build comparison")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-problem batched build and matvec")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the measured FP64 form (no predictor training, no other forms "
+                         "or legs): the run the hardware counters are taken on")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -390,24 +405,31 @@ def main():
     xs = [synth.normal_vector(n, wl["x_seed"] + k, dtype=np.float32) for k in range(nvec)]
     pts_d = torch.from_numpy(pts).to(dev)
     xs_d = [torch.from_numpy(x).to(dev) for x in xs]
-    z_d = torch.empty(n, dtype=torch.float32, device=dev)
+    xs64_d = [x.double() for x in xs_d]  # the same values, for FP64 arithmetic
     rows_d = torch.from_numpy(synth.sample_rows(n, 256, 99)).to(dev)
     ref = dense_rows_fp64(torch, pts_d, xs_d[0], wl["p0"], rows_d)
     kern = H.make_kernel(wl["kernel"], wl["p0"])
     stream = torch.cuda.current_stream()
 
     mixed_eps = wl.get("mixed_eps", wl["eps"])
-    mlp, train_info = train_predictor(torch, H, wl, mixed_eps, log)
+    mlp, train_info = (None, None) if args.headline_only else train_predictor(
+        torch, H, wl, mixed_eps, log)
 
     def params(form, eps=None):
         o = dict(FORMS[form])
         if o.get("rank_mode") == "learned":
             o["mlp"] = mlp
+        o.setdefault("compute_dtype", "f32")
         return H.hmx_params_default(leaf_size=wl["leaf"], eta=wl["eta"],
                                     aca_eps=wl["eps"] if eps is None else eps,
-                                    max_rank=wl["kmax"], compute_dtype="f32", **o)
+                                    max_rank=wl["kmax"], **o)
+
+    def vectors(prm):
+        return xs64_d if prm.compute_dtype == H.HMX_F64 else xs_d
 
     def one_step(prm, timed, label):
+        xv = vectors(prm)
+        z_d = torch.empty_like(xv[0])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         h = H.hmx_build(pts_d, kern, prm, stream)
@@ -421,7 +443,7 @@ def main():
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for k in range(M):
-            H.hmx_matvec(h, xs_d[k % nvec], z_d, 1.0, 0.0, stream)
+            H.hmx_matvec(h, xv[k % nvec], z_d, 1.0, 0.0, stream)
         e1.record(stream)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
@@ -447,15 +469,16 @@ def main():
             if s < steps - 1:
                 H.hmx_destroy(h)
             recs.append(rec)
-        z0 = torch.empty(n, dtype=torch.float32, device=dev)
-        H.hmx_matvec(h, xs_d[0], z0, 1.0, 0.0, stream)
+        xv = vectors(prm)
+        z0 = torch.empty_like(xv[0])
+        H.hmx_matvec(h, xv[0], z0, 1.0, 0.0, stream)
         torch.cuda.synchronize()
         err = (torch.linalg.norm(z0.double()[rows_d] - ref) / torch.linalg.norm(ref)).item()
         st = recs[-1]["stats"]
         eager_ms = float(np.mean([r["mv_ms"] for r in recs]))
         # the matvec time: M replays of a captured one-matvec HIP graph
-        zg = torch.empty(n, dtype=torch.float32, device=dev)
-        g = H.hmx_matvec_graph(h, xs_d[0], zg)
+        zg = torch.empty_like(xv[0])
+        g = H.hmx_matvec_graph(h, xv[0], zg)
         H.hmx_graph_launch(g, stream)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -484,7 +507,7 @@ def main():
             "factor_entries": st.factor_entries, "matvec_bytes": st.matvec_bytes,
             "device_bytes": st.device_bytes,
             "step_ms": 1e3 * float(np.mean([r["step_s"] for r in recs])),
-            "rowtile_bytes": rowtile_bytes(st),
+            "rowtile_bytes": rowtile_bytes(st, xv[0].element_size()),
             "tile_config": tile_config[label],
             # the ACA (phase 3) and the tile-major pool phase (5, the near-field
             # evaluation and the factor rows) as work rates
@@ -498,16 +521,44 @@ def main():
             label, res["build_s"], mv_ms, res["matvec_gbs"], err))
         return h, z0, res
 
-    # the measured form: learned sizing + BF16 factors
-    hL, zL, lm = run_form(params("learned_mixed", mixed_eps), "learned_mixed", args.steps,
-                          args.warmup)
+    # the measured form (the printed value): the plain method in FP64, the
+    # paper's arithmetic, on the workload's geometry, kernel and tolerance
+    hD, zD, pd = run_form(params("plain_f64"), "plain_f64", args.steps, args.warmup)
+    pd["aca_eps"] = wl["eps"]
+    part_perm = H.hmx_get_partition(hD)["perm"]
+    H.hmx_destroy(hD)
+    z_f64_first = zD.cpu().numpy()
+    H.hmx_trim()
+    if args.headline_only:
+        rt_gbs = pd["rowtile_bytes"] / (pd["rowtile_ms"] * 1e-3) / 1e9
+        out = {"metric": METRIC, "value": pd["matvec_gbs"], "unit": "GB/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": pd["step_ms"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "f64", "data": "synthetic", "plain_f64": pd,
+               "roofline": {"kernel": "rowtile_kernel (FP64)", "bound": "hbm",
+                            "achieved": rt_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": rt_gbs / HBM_PEAK_GBS,
+                            "algorithmic_bytes_per_launch": pd["rowtile_bytes"],
+                            "avg_launch_ms": pd["rowtile_ms"]}}
+        if args.calibrate_copy > 0:
+            nel = args.calibrate_copy * (1 << 20) // 4
+            src = torch.ones(nel, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            out["calibration_copy_bytes"] = nel * 4
+        print(json.dumps(out), flush=True)
+        return
+    # the learned / mixed-precision form against the plain FP32 form (extra
+    # keys; fewer steps)
+    ext_steps = max(1, min(args.steps, 3))
+    hL, zL, lm = run_form(params("learned_mixed", mixed_eps), "learned_mixed", ext_steps, 1)
     lm["aca_eps"] = mixed_eps
     H.hmx_destroy(hL)
     # the plain form at the workload's eps
-    hP, zP, pl = run_form(params("plain"), "plain", args.steps, args.warmup)
-    part_perm = H.hmx_get_partition(hP)["perm"]
+    hP, zP, pl = run_form(params("plain"), "plain", ext_steps, 1)
     H.hmx_destroy(hP)
-    z_plain_first = zP.double().cpu().numpy()
     # the plain form at equal error: the largest eps of the grid whose error
     # does not exceed learned_mixed's
     if args.plain_eq_eps is not None:
@@ -524,39 +575,37 @@ def main():
             if err > lm["rel_err_256rows"]:
                 break
             eq_eps = e
-    hQ, _, pe = run_form(params("plain", eq_eps), "plain_eq(eps=%g)" % eq_eps, args.steps, 1)
+    hQ, _, pe = run_form(params("plain", eq_eps), "plain_eq(eps=%g)" % eq_eps, ext_steps, 1)
     H.hmx_destroy(hQ)
     pe["aca_eps"] = eq_eps
 
-    rt_gbs = lm["rowtile_bytes"] / (lm["rowtile_ms"] * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, "learned_mixed")
+    rt_gbs = pd["rowtile_bytes"] / (pd["rowtile_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, "plain_f64")
     out = {
-        "metric": METRIC, "value": lm["matvec_gbs"], "unit": "GB/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": lm["step_ms"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "metric": METRIC, "value": pd["matvec_gbs"], "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": pd["step_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "%s: N=%d points uniform in [0,1]^%d, %s kernel p0=%g, leaf %d, "
-                               "eta %g, max rank %d; learned rank sizing, ACA eps %g, BF16 "
-                               "factors and near field, FP32 arithmetic; %d matvecs per step "
-                               "(the largest listed configuration that fits one GPU: the 2^22 "
-                               "three-dimensional ones need 1.5e11-2.4e11 stored factor "
-                               "entries)" % (
+                               "eta %g, ACA eps %g, max rank %d; the plain method (adaptive "
+                               "ACA, stored near field and factors) in FP64 arithmetic and "
+                               "storage; %d matvecs per step" % (
                                    args.workload, n, d, wl["kernel"], wl["p0"], wl["leaf"],
-                                   wl["eta"], wl["kmax"], mixed_eps, M),
+                                   wl["eta"], wl["eps"], wl["kmax"], M),
                    "n": n, "d": d, "matvecs_per_step": M},
-        "build_s": lm["build_s"], "matvec_ms": lm["matvec_ms"],
-        "learned_mixed": lm, "plain": pl, "plain_equal_error": pe,
+        "build_s": pd["build_s"], "matvec_ms": pd["matvec_ms"],
+        "plain_f64": pd, "learned_mixed": lm, "plain": pl, "plain_equal_error": pe,
         "predictor_training": train_info,
         "vs_plain": {"build_speedup": pl["build_s"] / lm["build_s"],
                      "matvec_speedup": pl["matvec_ms"] / lm["matvec_ms"],
                      "build_speedup_equal_error": pe["build_s"] / lm["build_s"],
                      "matvec_speedup_equal_error": pe["matvec_ms"] / lm["matvec_ms"]},
-        "matvec_roofline": {"bound": "hbm", "achieved": lm["matvec_gbs"], "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": lm["matvec_gbs"] / HBM_PEAK_GBS},
-        "roofline": {"kernel": "rowtile_kernel", "bound": "hbm", "achieved": rt_gbs,
+        "matvec_roofline": {"bound": "hbm", "achieved": pd["matvec_gbs"], "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": pd["matvec_gbs"] / HBM_PEAK_GBS},
+        "roofline": {"kernel": "rowtile_kernel (FP64)", "bound": "hbm", "achieved": rt_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": rt_gbs / HBM_PEAK_GBS,
-                     "traffic": traffic, "algorithmic_bytes_per_launch": lm["rowtile_bytes"],
-                     "avg_launch_ms": lm["rowtile_ms"], "stream_copy_gbs": copy_gbs},
+                     "traffic": traffic, "algorithmic_bytes_per_launch": pd["rowtile_bytes"],
+                     "avg_launch_ms": pd["rowtile_ms"], "stream_copy_gbs": copy_gbs},
     }
     if args.calibrate_copy > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
@@ -577,7 +626,7 @@ def main():
         out["n22_build"] = n22_aca_builds(torch, H, log)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle on a row sample)")
-        out["cpu_baseline"] = cpu_baseline(wl, pts, xs[0], z_plain_first, part_perm)
+        out["cpu_baseline"] = cpu_baseline(wl, pts, xs[0], z_f64_first, part_perm)
     print(json.dumps(out), flush=True)
 
 
