@@ -337,6 +337,7 @@ struct hmx_hmatrix_s {
     int32_t nprob = 1;
     bool batched = false;
     int rt_config = -1;  // row-tile kernel configuration (-1: default shape)
+    int p1_lanes = 0;    // phase-1 lanes per column group (0: chosen by tile height)
     std::vector<int64_t> offsets;
     int64_t factor_entries = 0, near_entries = 0;
     DevBuf codes, perm, soa64, soa32, node_lo, node_hi, bmin, bmax;
@@ -1930,6 +1931,21 @@ hmx_status matvec_args(hmx_hmatrix_s* h, const void* x, const void* z, hmx_dtype
     return HMX_OK;
 }
 
+// phase 1's tile passes (t = V^T x partial sums per row tile): the factor
+// pool (symmetric far field) and the V pool
+hipError_t p1_tiles(hmx_hmatrix_s* h, hipStream_t st, int lanes) {
+    hipError_t e = hipSuccess;
+    if (h->sym && h->ncols_u > 0)
+        e = launch_p1_tile(h->ntiles, h->tile_lo.as<int32_t>(), h->tile_meta.as<int64_t>(), 4,
+                           h->Ru, h->max_tile, h->upool.p, h->vecpool.p, h->partial.p, 0,
+                           h->smode, lanes, st);
+    if (e == hipSuccess && h->ncols_v > 0)
+        e = launch_p1_tile(h->ntiles, h->tile_lo.as<int32_t>(), h->vt_meta.as<int64_t>(), 4,
+                           h->Rv, h->max_tile, h->vtpool.p, h->vecpool.p, h->partial.p,
+                           h->sym ? h->ncols_u : 0, h->smode, lanes, st);
+    return e;
+}
+
 // the three launches of one matvec: gather of x into Morton order, far-field
 // phase 1 (t = V^T x), row tiles (near field + U t, scatter to z); ev: four
 // events recorded around them, or null
@@ -1941,14 +1957,7 @@ hipError_t matvec_launch(hmx_hmatrix_s* h, const void* x, void* z, double alpha,
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
     // phase 1 by row tiles: partial sums of every source column, then the t
     // entries; the sources are the factor pool (symmetric far field) and the V pool
-    if (e == hipSuccess && h->sym && h->ncols_u > 0)
-        e = launch_p1_tile(h->ntiles, h->tile_lo.as<int32_t>(), h->tile_meta.as<int64_t>(), 4,
-                           h->Ru, h->max_tile, h->upool.p, h->vecpool.p, h->partial.p, 0,
-                           h->smode, st);
-    if (e == hipSuccess && h->ncols_v > 0)
-        e = launch_p1_tile(h->ntiles, h->tile_lo.as<int32_t>(), h->vt_meta.as<int64_t>(), 4,
-                           h->Rv, h->max_tile, h->vtpool.p, h->vecpool.p, h->partial.p,
-                           h->sym ? h->ncols_u : 0, h->smode, st);
+    if (e == hipSuccess) e = p1_tiles(h, st, h->p1_lanes);
     if (e == hipSuccess)
         e = launch_p1_reduce(h->p1rec.as<int4>(), h->sum_rank, h->pfc.as<int64_t>(),
                              h->partial.p, h->vecpool.p, h->n, f64, st);
@@ -2383,9 +2392,26 @@ hmx_status hmx_autotune(hmx_hmatrix h, int32_t reps, void* stream, int32_t* choi
                 bc = c;
             }
         }
+        // phase 1: lanes per column group
+        double pbest = INFINITY;
+        int pl = 0;
+        for (int lanes : {16, 32, 64}) {
+            check(p1_tiles(h, st, lanes), "tuning warm-up");
+            check(hipEventRecord(e0, st), "event");
+            for (int r = 0; r < reps; ++r) check(p1_tiles(h, st, lanes), "tuning launch");
+            check(hipEventRecord(e1, st), "event");
+            check(hipEventSynchronize(e1), "event sync");
+            float ms = 0.f;
+            check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+            if (ms < pbest) {
+                pbest = ms;
+                pl = lanes;
+            }
+        }
         check(hipStreamSynchronize(st), "tuning sync");
         h->rt_config = bc;
         h->stats.tile_config = bc;
+        h->p1_lanes = pl;
     });
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

@@ -515,7 +515,8 @@ hipError_t launch_scatter_i64(const int32_t* list, int64_t nl, const int64_t* sr
 // offset in pool; tiles padded to multiples of R rows)
 hipError_t launch_p1_tile(int64_t ntiles, const int32_t* tile_lo, const int64_t* meta, int ms,
                           int R, int max_tile, const void* pool, const void* vec, void* partial,
-                          int64_t pbase, int smode, hipStream_t st);
+                          int64_t pbase, int smode, int lanes /*16, 32, 64; 0 = by tile height*/,
+                          hipStream_t st);
 // t entries: vec[n + k] = sum over j < rec[k].nt of partial[pfc[base + j] + l]
 hipError_t launch_p1_reduce(const int4* rec, int64_t ncols, const int64_t* pfc,
                             const void* partial, void* vec, int64_t n, int f64, hipStream_t st);

@@ -65,17 +65,20 @@ struct P1Dec<uint16_t, float> {
 };
 
 constexpr int kP1Threads = 256;
-constexpr int kP1Cols = 16;  // columns per lane group in flight
+constexpr int kP1Cols = 16;     // columns per lane group in flight
+constexpr int kP1Stage = 2048;  // rows of x a tile stages in LDS (taller tiles read x directly)
 
 // Tile pass.  meta[ms * t + 1] = first source column of tile t (tile t + 1's
 // entry ends it), meta[ms * t + 2] = data offset of the tile's matrix in
-// pool.  The workgroup's 256 threads form groups of L lanes; a group takes
-// kP1Cols consecutive columns at a time, lane q covering 16-byte row vectors
-// q, q + L, ... of each, and sums each lane's products in registers; the
-// kP1Cols sums are then reduced over the group's lanes by a butterfly that
-// halves the values per lane at each of the first four exchanges (one
-// shuffle per column instead of log2 L), after which every lane holds the
-// total of one column.
+// pool.  The tile's x rows are staged in LDS.  The workgroup's 256 threads
+// form groups of L lanes; a group takes kP1Cols consecutive columns at a
+// time, lane q covering 16-byte row vectors q, q + L, ... of each, and sums
+// each lane's products in registers; the kP1Cols sums are then reduced over
+// the group's lanes by a butterfly that halves the values per lane at each
+// of the first four exchanges (one shuffle per column instead of log2 L),
+// after which every lane holds the total of one column.  Narrow groups (16
+// lanes) give each lane several row vectors per column before the
+// reduction, so the exchanges are a small share of the work on tall tiles.
 template <typename S, typename T, int L>
 __global__ __launch_bounds__(kP1Threads) void p1_tile_kernel(
     int64_t ntiles, const int32_t* __restrict__ tile_lo, const int64_t* __restrict__ meta, int ms,
@@ -84,6 +87,7 @@ __global__ __launch_bounds__(kP1Threads) void p1_tile_kernel(
     constexpr int VS = P1Dec<S, T>::n;
     constexpr int G = kP1Threads / L;
     static_assert(L >= 16 && L <= 64, "groups of 16, 32 or 64 lanes");
+    __shared__ T sx[kP1Stage];
     const int g = threadIdx.x / L;
     const int q = threadIdx.x % L;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -95,34 +99,28 @@ __global__ __launch_bounds__(kP1Threads) void p1_tile_kernel(
         const int ld = p1_ld(mt, R);
         const int nvec = ld / VS;
         const S* __restrict__ base = pool + meta[ms * t + 2];
-        // x of this lane's first row vector (rows past the tile read as zero)
-        T x0[VS];
-#pragma unroll
-        for (int e = 0; e < VS; ++e) {
-            const int row = q * VS + e;
-            x0[e] = row < mt ? vec[r0 + row] : (T)0;
+        // x of the tile (rows past it read as zero)
+        const bool staged = ld <= kP1Stage;
+        if (staged) {
+            for (int i = threadIdx.x; i < ld; i += kP1Threads) sx[i] = i < mt ? vec[r0 + i] : (T)0;
+            __syncthreads();
         }
         for (int cb = g * kP1Cols; cb < nc; cb += G * kP1Cols) {
             T acc[kP1Cols];
 #pragma unroll
             for (int u = 0; u < kP1Cols; ++u) acc[u] = 0;
             for (int vi = q; vi < nvec; vi += L) {
-                T xv[VS];
-                if (vi == q) {
-#pragma unroll
-                    for (int e = 0; e < VS; ++e) xv[e] = x0[e];
-                } else {
-#pragma unroll
-                    for (int e = 0; e < VS; ++e) {
-                        const int row = vi * VS + e;
-                        xv[e] = row < mt ? vec[r0 + row] : (T)0;
-                    }
-                }
                 u32x4 raw[kP1Cols];
 #pragma unroll
                 for (int u = 0; u < kP1Cols; ++u) {
                     const int c = cb + u < nc ? cb + u : nc - 1;  // past the end: never stored
                     raw[u] = __builtin_nontemporal_load((const u32x4*)(base + (int64_t)c * ld) + vi);
+                }
+                T xv[VS];
+#pragma unroll
+                for (int e = 0; e < VS; ++e) {
+                    const int row = vi * VS + e;
+                    xv[e] = staged ? sx[row] : (row < mt ? vec[r0 + row] : (T)0);
                 }
 #pragma unroll
                 for (int u = 0; u < kP1Cols; ++u) {
@@ -155,6 +153,7 @@ __global__ __launch_bounds__(kP1Threads) void p1_tile_kernel(
             }
             if ((q & (L / 16 - 1)) == 0 && cb + off < nc) partial[pbase + c0 + cb + off] = acc[0];
         }
+        if (staged) __syncthreads();  // sx is refilled by the next tile
     }
 }
 
@@ -408,19 +407,22 @@ unsigned g1(int64_t n, int bs = 256) {
     return (unsigned)(b < (1 << 30) ? b : (1 << 30));
 }
 
+// lanes: 16, 32 or 64 lanes per column group; 0 picks the narrowest group
+// that leaves each lane at most 8 row vectors of the tallest tile
 template <typename S, typename T>
 hipError_t p1_tile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_t* meta, int ms,
                             int R, int max_ld, const void* pool, const void* vec, void* partial,
-                            int64_t pbase, hipStream_t st) {
+                            int64_t pbase, int lanes, hipStream_t st) {
     constexpr int VS = P1Dec<S, T>::n;
     const int need = (max_ld + VS - 1) / VS;  // row vectors of the tallest tile
+    if (lanes == 0) lanes = need <= 8 * 16 ? 16 : (need <= 8 * 32 ? 32 : 64);
     const unsigned grid = (unsigned)(ntiles < (1 << 30) ? ntiles : (1 << 30));
 #define HMX_P1(LL)                                                                             \
     hipLaunchKernelGGL((p1_tile_kernel<S, T, LL>), dim3(grid), dim3(kP1Threads), 0, st, ntiles, \
                        tile_lo, meta, ms, R, (const S*)pool, (const T*)vec, (T*)partial, pbase)
-    if (need <= 16)
+    if (lanes == 16)
         HMX_P1(16);
-    else if (need <= 32)
+    else if (lanes == 32)
         HMX_P1(32);
     else
         HMX_P1(64);
@@ -432,17 +434,17 @@ hipError_t p1_tile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_
 
 hipError_t launch_p1_tile(int64_t ntiles, const int32_t* tile_lo, const int64_t* meta, int ms,
                           int R, int max_tile, const void* pool, const void* vec, void* partial,
-                          int64_t pbase, int smode, hipStream_t st) {
+                          int64_t pbase, int smode, int lanes, hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
     const int max_ld = (max_tile + R - 1) / R * R;
     if (smode == 0)
         return p1_tile_dispatch<double, double>(ntiles, tile_lo, meta, ms, R, max_ld, pool, vec,
-                                                partial, pbase, st);
+                                                partial, pbase, lanes, st);
     if (smode == 1)
         return p1_tile_dispatch<float, float>(ntiles, tile_lo, meta, ms, R, max_ld, pool, vec,
-                                              partial, pbase, st);
+                                              partial, pbase, lanes, st);
     return p1_tile_dispatch<uint16_t, float>(ntiles, tile_lo, meta, ms, R, max_ld, pool, vec,
-                                             partial, pbase, st);
+                                             partial, pbase, lanes, st);
 }
 
 hipError_t launch_p1_reduce(const int4* rec, int64_t ncols, const int64_t* pfc,
