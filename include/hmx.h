@@ -361,6 +361,25 @@ hmx_status hmx_set_tile_config(hmx_hmatrix h, int32_t config);
 hmx_status hmx_cg_solve(hmx_hmatrix h, const void* b, void* x, double rel_tol, int32_t max_iter,
                         void* stream, int32_t* iters, double* rel_res, double* true_rel_res);
 
+/* hmx_cg_solve for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same solve, the same kernels and the same results bit for bit, with its
+ * three work vectors, scalars and partial sums in a fixed device array of
+ * HMX_CG_NOALLOC_MAX_BYTES that the library holds on every device it runs on
+ * until the process ends.  The work space needs 3 * ceil256(n * e) + 256 +
+ * 8256 bytes (e = 8 with F64 arithmetic, else 4; ceil256 rounds up to a
+ * multiple of 256), which admits n up to 2^22 + 4736 in FP32 and 2^21 + 2368
+ * in FP64; a larger handle returns HMX_ERR_INVALID_ARG before any work.
+ * Calls no device allocation or free.  All calls on one device share the
+ * array, so calls that overlap on one device (two threads, or two streams
+ * without ordering between them) race; the array keeps the last call's
+ * contents, every buffer is overwritten before it is read.  b, x, stream and
+ * the outputs as for hmx_cg_solve. */
+#define HMX_CG_NOALLOC_MAX_BYTES ((size_t)50397184) /* 48 MiB + 64 KiB */
+hmx_status hmx_cg_solve_noalloc(hmx_hmatrix h, const void* b, void* x, double rel_tol,
+                                int32_t max_iter, void* stream, int32_t* iters, double* rel_res,
+                                double* true_rel_res);
+
 /* Copy the ordering and the partition to host memory (any pointer may be
  * NULL to skip it):
  *   codes : n Morton codes in the ORIGINAL point order

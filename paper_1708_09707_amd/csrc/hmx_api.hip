@@ -1982,6 +1982,10 @@ struct CgWork {
     double* pa;
 };
 
+constexpr size_t kCgScalBytes = 256;
+
+size_t cg_vec_bytes(int64_t n, size_t esz) { return ((size_t)n * esz + 255) / 256 * 256; }
+
 hmx_status cg_args(hmx_hmatrix_s* h, const void* b, const void* x, double rel_tol,
                    int32_t max_iter) {
     if (!h || !b || !x || !(rel_tol >= 0) || max_iter < 0) {
@@ -2063,6 +2067,29 @@ hmx_status cg_run(hmx_hmatrix_s* h, const void* b, void* x, double rel_tol, int3
     return status;
 }
 
+// Fixed work space of hmx_cg_solve_noalloc.  In host code `cg_scratch` names
+// a host-side stand-in, not the device array: its device address is looked up
+// once per device (hipGetSymbolAddress) and only that address is used.
+__device__ __align__(256) unsigned char cg_scratch[HMX_CG_NOALLOC_MAX_BYTES];
+
+std::mutex g_cg_scratch_mu;
+void* g_cg_scratch_dev[64] = {};
+
+void* cg_scratch_device() {
+    int dev = 0;
+    check(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= 64) {
+        set_err("device ordinal %d out of range", dev);
+        throw Fail{HMX_ERR_DEVICE};
+    }
+    std::lock_guard<std::mutex> lk(g_cg_scratch_mu);
+    if (!g_cg_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(cg_scratch)), "hipGetSymbolAddress(cg_scratch)");
+        g_cg_scratch_dev[dev] = ptr;
+    }
+    return g_cg_scratch_dev[dev];
+}
 }  // namespace
 
 extern "C" {
@@ -2444,6 +2471,30 @@ hmx_status hmx_cg_solve(hmx_hmatrix h, const void* b, void* x, double rel_tol, i
         alloc(scal, 8 * sizeof(double), "cg scalars");
         alloc(partial, cg_scratch_bytes(), "cg partials");
         CgWork w{r.p, p.p, q.p, scal.as<double>(), partial.as<double>()};
+        return cg_run(h, b, x, rel_tol, max_iter, (hipStream_t)stream, w, iters, rel_res,
+                      true_rel_res);
+    } catch (const Fail& f) {
+        return f.s;
+    }
+}
+
+hmx_status hmx_cg_solve_noalloc(hmx_hmatrix h, const void* b, void* x, double rel_tol,
+                                int32_t max_iter, void* stream, int32_t* iters, double* rel_res,
+                                double* true_rel_res) {
+    hmx_status s = cg_args(h, b, x, rel_tol, max_iter);
+    if (s != HMX_OK) return s;
+    const size_t vb = cg_vec_bytes(h->n, h->esz);
+    if (3 * vb + kCgScalBytes + cg_scratch_bytes() > HMX_CG_NOALLOC_MAX_BYTES) {
+        set_err("hmx_cg_solve_noalloc: %lld entries of %zu bytes need %zu bytes of work space, "
+                "more than its fixed %zu",
+                (long long)h->n, h->esz, 3 * vb + kCgScalBytes + cg_scratch_bytes(),
+                (size_t)HMX_CG_NOALLOC_MAX_BYTES);
+        return HMX_ERR_INVALID_ARG;
+    }
+    try {
+        char* base = (char*)cg_scratch_device();
+        CgWork w{base, base + vb, base + 2 * vb, (double*)(base + 3 * vb),
+                 (double*)(base + 3 * vb + kCgScalBytes)};
         return cg_run(h, b, x, rel_tol, max_iter, (hipStream_t)stream, w, iters, rel_res,
                       true_rel_res);
     } catch (const Fail& f) {

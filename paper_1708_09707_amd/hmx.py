@@ -37,8 +37,9 @@ EXPORTS = ["hmx_params_default", "hmx_build", "hmx_matvec", "hmx_cg_solve", "hmx
            "hmx_mlp_forward", "hmx_mlp_loss_grad", "hmx_mlp_adam", "hmx_mlp_train",
            "hmx_block_features", "hmx_build_batched", "hmx_get_batch", "hmx_matvec_graph",
            "hmx_graph_launch", "hmx_graph_destroy", "hmx_autotune", "hmx_set_tile_config",
-           "hmx_rank_predict", "hmx_matvec_batched", "hmx_mlp_save",
+           "hmx_rank_predict", "hmx_cg_solve_noalloc", "hmx_matvec_batched", "hmx_mlp_save",
            "hmx_mlp_load"]
+HMX_CG_NOALLOC_MAX_BYTES = 50397184
 HMX_TILE_CONFIGS = 15
 
 
@@ -112,6 +113,8 @@ def lib():
         L.hmx_matvec.argtypes = [P, P, P, C.c_int, f64, f64, P]
         L.hmx_cg_solve.argtypes = [P, P, P, f64, i32, P, C.POINTER(i32), C.POINTER(f64),
                                    C.POINTER(f64)]
+        L.hmx_cg_solve_noalloc.argtypes = [P, P, P, f64, i32, P, C.POINTER(i32), C.POINTER(f64),
+                                           C.POINTER(f64)]
         L.hmx_matvec_batched.argtypes = [i32, P, P, P, C.c_int, f64, f64, P]
         L.hmx_mlp_save.argtypes = [P, C.c_char_p]
         L.hmx_mlp_load.argtypes = [C.c_char_p, C.POINTER(P)]
@@ -251,13 +254,15 @@ def hmx_matvec_batched(handles, xs, zs, alpha=1.0, beta=0.0, stream=None):
                                     float(alpha), float(beta), _stream(stream)))
 
 
-def hmx_cg_solve(h, b, x, rel_tol=1e-6, max_iter=1000, stream=None, raise_on_fail=True):
-    """Solve (H + sigma2 I) x = b by CG.  Returns (status, iters, rel_res, true_rel_res)."""
+def hmx_cg_solve(h, b, x, rel_tol=1e-6, max_iter=1000, stream=None, raise_on_fail=True,
+                 noalloc=False):
+    """Solve (H + sigma2 I) x = b by CG.  Returns (status, iters, rel_res, true_rel_res).
+    noalloc=True calls hmx_cg_solve_noalloc (fixed work space, no allocation)."""
     _check_vectors(h, b, x)
     it, rr, tr = C.c_int32(0), C.c_double(0), C.c_double(0)
-    s = lib().hmx_cg_solve(h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
-                           float(rel_tol), int(max_iter), _stream(stream), C.byref(it),
-                           C.byref(rr), C.byref(tr))
+    fn = lib().hmx_cg_solve_noalloc if noalloc else lib().hmx_cg_solve
+    s = fn(h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), float(rel_tol), int(max_iter),
+           _stream(stream), C.byref(it), C.byref(rr), C.byref(tr))
     if s not in (HMX_OK, HMX_ERR_NOT_CONVERGED) or (raise_on_fail and s != HMX_OK):
         _check(s)
     return s, it.value, rr.value, tr.value
