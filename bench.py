@@ -161,7 +161,7 @@ def train_predictor(torch, H, wl, eps, log, d=None):
     return mlp, info
 
 
-def n22_aca_builds(torch, H, log):
+def n22_aca_builds(torch, H, log, full=True):
     """Builds up to the ACA at N = 2^22 in 3-d (the stored pools exceed one
     GPU): plain (k_max-sized ACA scratch, in chunks) against learned sizing
     (sizing form: identical ranks, storage from the predictor)."""
@@ -208,9 +208,164 @@ def n22_aca_builds(torch, H, log):
             hm.close()
     res["ranks_identical"] = bool(np.array_equal(ranks["plain"], ranks["learned"]))
     res["build_speedup"] = res["plain"]["build_s"] / res["learned"]["build_s"]
+    H.hmx_trim()
+    if full:
+        res["learned_mixed_full"] = n22_full_path(torch, H, log, wl, pts_d, p0, mlp)
     mlp.close()
     H.hmx_trim()
     return res
+
+
+def n22_full_path(torch, H, log, wl, pts_d, p0, mlp, eps=3e-3, M=10, nrows=1024):
+    """The whole path at N = 2^22 in 3-d for the learned / mixed-precision
+    form: learned sizing, BF16 factors and near field, the symmetric far
+    field (each factor pair stored once).  Build time, matvec time and bytes,
+    and the product's error on sampled rows against an FP64 dense product."""
+    n = wl["n"]
+    kw = dict(compute_dtype="f32", storage_dtype="bf16", leaf_size=wl["leaf"], eta=wl["eta"],
+              aca_eps=eps, max_rank=wl["kmax"], rank_mode="learned", mlp=mlp, symmetric_far=1)
+    times = []
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hm = H.HMatrix(pts_d, wl["kernel"], p0, **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        st = hm.stats()
+        if rep == 0:
+            hm.close()
+    stream = torch.cuda.current_stream()
+    H.hmx_autotune(hm.h, 2, stream)
+    x = torch.from_numpy(synth.normal_vector(n, 5400, dtype=np.float32)).cuda()
+    z = torch.empty_like(x)
+    g = H.hmx_matvec_graph(hm.h, x, z)
+    H.hmx_graph_launch(g, stream)
+    H.hmx_profile_begin(hm.h, 3)
+    for _ in range(3):
+        H.hmx_matvec(hm.h, x, z, 1.0, 0.0, stream)
+    phase_ms, calls = H.hmx_profile_end(hm.h)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(M):
+        H.hmx_graph_launch(g, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    mv_ms = e0.elapsed_time(e1) / M
+    H.hmx_graph_destroy(g)
+    rows_d = torch.from_numpy(synth.sample_rows(n, nrows, 5401)).cuda()
+    ref = dense_rows_fp64(torch, pts_d, x, p0, rows_d)
+    err = (torch.linalg.norm(z.double()[rows_d] - ref) / torch.linalg.norm(ref)).item()
+    fb = (st.u_entries + st.v_entries) * st.entry_bytes
+    out = {"eps": eps, "build_s_each": times, "build_s": min(times),
+           "matvec_bytes": st.matvec_bytes, "matvec_gbs": st.matvec_bytes / (mv_ms * 1e-3) / 1e9,
+           "build_phase_ms": list(st.phase_ms), "sum_rank": st.sum_rank,
+           "factor_entries": st.factor_entries, "near_entries": st.near_entries,
+           "device_bytes": st.device_bytes, "aca_overflow": st.aca_overflow,
+           "aca_fallback": st.aca_fallback, "matvec_ms": mv_ms,
+           "matvec_phase_ms": list(phase_ms / max(calls, 1)),
+           "factor_bytes_read_per_matvec": fb, "factor_gbs": fb / (mv_ms * 1e-3) / 1e9,
+           "near_evals_per_s": st.near_entries / (mv_ms * 1e-3), "rel_err_rows": err,
+           "rows": nrows}
+    log("bench: 2^22 3-d learned/mixed full path: build %.2f s, device %.1f GB, matvec %.2f ms "
+        "(%.3g B, %.0f GB/s), rel err %.2e"
+        % (out["build_s"], st.device_bytes / 1e9, mv_ms, st.matvec_bytes, out["matvec_gbs"],
+           err))
+    hm.close()
+    return out
+
+
+def dense_rows_matern32(torch, pts_d, x_d, ell, rows_d):
+    """z[rows] of the FP64 dense Matern-3/2 product (plain PyTorch on the GPU)."""
+    P = pts_d.double()
+    x = x_d.double()
+    ref = torch.zeros(rows_d.numel(), dtype=torch.float64, device=P.device)
+    step = 1 << 15
+    s3 = np.sqrt(3.0) / ell
+    for c0 in range(0, P.shape[0], step):
+        r = torch.sqrt(((P[rows_d, None, :] - P[None, c0:c0 + step, :]) ** 2).sum(-1)) * s3
+        ref += ((1.0 + r) * torch.exp(-r)) @ x[c0:c0 + step]
+    return ref
+
+
+def krr_leg(torch, H, log, cg_iters=400, nrows=1024):
+    """Kernel ridge regression at N = 2^22: points from a 32-component
+    Gaussian mixture in [0,1]^3, Matern-3/2 with l = 0.1, (A + 1e-2 I) c = y,
+    y = sin(2 pi p0) p1 + 0.01 xi; BF16 factors and near field with FP32
+    arithmetic, the symmetric far field; ACA eps 1e-4, leaf 64, eta 1.5,
+    k_max 64.  Build time, matvec time and bytes, the product's
+    error on sampled rows against an FP64 dense product, and CG on the system
+    (FP64 inner products) to relative residual 1e-6 or its breakdown."""
+    n, ell, sigma2, eps = 1 << 22, 0.1, 1e-2, 1e-4
+    pts = synth.gmm_points(n, 3, 31, dtype=np.float32)
+    y = synth.krr_target(pts, 32, dtype=np.float32)
+    pts_d = torch.from_numpy(pts).cuda()
+    y_d = torch.from_numpy(y).cuda()
+    kw = dict(compute_dtype="f32", storage_dtype="bf16", leaf_size=64, eta=1.5, aca_eps=eps,
+              max_rank=64, sigma2=sigma2, symmetric_far=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hm = H.HMatrix(pts_d, "matern32", ell, **kw)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    st = hm.stats()
+    log("bench: KRR 2^22 build %.2f s (phases %s), %d adm %d dense, factors %.3g entries, "
+        "device %.1f GB" % (build_s, " ".join("%.0f" % v for v in st.phase_ms[:6]), st.n_adm,
+                            st.n_dense, st.factor_entries, st.device_bytes / 1e9))
+    stream = torch.cuda.current_stream()
+    H.hmx_autotune(hm.h, 2, stream)
+    x = torch.from_numpy(synth.normal_vector(n, 33, dtype=np.float32)).cuda()
+    z = torch.empty_like(x)
+    g = H.hmx_matvec_graph(hm.h, x, z)
+    H.hmx_graph_launch(g, stream)
+    H.hmx_profile_begin(hm.h, 5)
+    for _ in range(5):
+        H.hmx_matvec(hm.h, x, z, 1.0, 0.0, stream)
+    phase_ms, calls = H.hmx_profile_end(hm.h)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    M = 10
+    e0.record(stream)
+    for _ in range(M):
+        H.hmx_graph_launch(g, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    mv_ms = e0.elapsed_time(e1) / M
+    H.hmx_graph_destroy(g)
+    rows_d = torch.from_numpy(synth.sample_rows(n, nrows, 34)).cuda()
+    ref = dense_rows_matern32(torch, pts_d, x, ell, rows_d) + sigma2 * x.double()[rows_d]
+    err = (torch.linalg.norm(z.double()[rows_d] - ref) / torch.linalg.norm(ref)).item()
+    # A's scale on the same rows: the product's error measured against the shift
+    abs_err = (torch.linalg.norm(z.double()[rows_d] - ref) / torch.linalg.norm(
+        x.double()[rows_d])).item()
+    c = torch.zeros_like(y_d)
+    t0 = time.perf_counter()
+    s, it, res, tres = H.hmx_cg_solve(hm.h, y_d, c, rel_tol=1e-6, max_iter=cg_iters,
+                                      raise_on_fail=False)
+    cg_s = time.perf_counter() - t0
+    msg = H.lib().hmx_last_error().decode() if s != H.HMX_OK else ""
+    res_out = {
+        "workload": "krr_gmm3d_n4m: N=2^22 points from a 32-component Gaussian mixture in "
+                    "[0,1]^3 (seed 31), Matern-3/2 l=0.1, (A + 1e-2 I) c = y, y = sin(2 pi p0) "
+                    "p1 + 0.01 xi; BF16 factors and near field, FP32 arithmetic, symmetric "
+                    "far field; ACA eps 1e-4, leaf 64, eta 1.5, k_max 64",
+        "build_s": build_s, "build_phase_ms": list(st.phase_ms), "n_adm": st.n_adm,
+        "n_dense": st.n_dense, "sum_rank": st.sum_rank, "factor_entries": st.factor_entries,
+        "near_entries": st.near_entries, "device_bytes": st.device_bytes,
+        "matvec_ms": mv_ms, "matvec_phase_ms": list(phase_ms / max(calls, 1)),
+        "matvec_bytes": st.matvec_bytes, "matvec_gbs": st.matvec_bytes / (mv_ms * 1e-3) / 1e9,
+        "factor_bytes_read_per_matvec": (st.u_entries + st.v_entries) * st.entry_bytes,
+        "factor_gbs": (st.u_entries + st.v_entries) * st.entry_bytes / (mv_ms * 1e-3) / 1e9,
+        "near_evals_per_s": st.near_entries / (mv_ms * 1e-3),
+        "rel_err_rows": err, "rows": nrows, "err_per_unit_x": abs_err,
+        "cg": {"status": int(s), "iters": it, "rel_res": res, "true_rel_res": tres,
+               "seconds": cg_s, "message": msg, "tol": 1e-6, "max_iter": cg_iters}}
+    log("bench: KRR 2^22 matvec %.2f ms (%.3g B, %.0f GB/s), rel err %.2e on %d rows; CG status "
+        "%d after %d iterations, res %.2e (%s)"
+        % (mv_ms, st.matvec_bytes, res_out["matvec_gbs"], err, nrows, s, it, res, msg))
+    hm.close()
+    H.hmx_trim()
+    return res_out
 
 
 def batched_problems(torch, lo, hi, nprob=64):
@@ -375,6 +530,9 @@ def main():
                     help="skip the N = 2^22 three-dimensional build comparison")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-problem batched build and matvec")
+    ap.add_argument("--krr", action="store_true",
+                    help="also run kernel ridge regression at N = 2^22 (Gaussian-mixture points, "
+                         "Matern-3/2, BF16, CG): about a minute")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the measured FP64 form (no predictor training, no other forms "
                          "or legs): the run the hardware counters are taken on")
@@ -624,6 +782,9 @@ def main():
     if not args.no_n22:
         H.hmx_trim()
         out["n22_build"] = n22_aca_builds(torch, H, log)
+    if args.krr:
+        H.hmx_trim()
+        out["krr_n4m"] = krr_leg(torch, H, log)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle on a row sample)")
         out["cpu_baseline"] = cpu_baseline(wl, pts, xs[0], z_f64_first, part_perm)

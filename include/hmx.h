@@ -334,15 +334,16 @@ hmx_status hmx_graph_destroy(hmx_graph g);
 /* Time every configuration on this handle (reps row-tile launches each, HIP
  * events on `stream`, on scratch vectors it allocates) and keep the fastest
  * for later matvecs (lowest index on ties); likewise the lanes per column
- * group (16, 32 or 64) of the far field's first product t = V^T x, whose
+ * group (8, 16, 32 or 64) of the far field's first product t = V^T x, whose
  * partial sums change order with it (results within rounding).  choice
  * (host, optional): the row-tile configuration chosen; times_ms (host,
  * optional, HMX_TILE_CONFIGS entries): mean milliseconds per row-tile
  * launch.  Host-blocking. */
 hmx_status hmx_autotune(hmx_hmatrix h, int32_t reps, void* stream, int32_t* choice,
                         double* times_ms);
-/* Select a configuration directly (-1: the default shape for the handle's
- * largest tile). */
+/* Select a row-tile configuration directly (-1: the default shape for the
+ * handle's largest tile, and the default phase-1 lanes too, so a handle
+ * returns to its untuned products). */
 hmx_status hmx_set_tile_config(hmx_hmatrix h, int32_t config);
 
 /* Conjugate gradients for (H + sigma2 I) c = b, the kernel ridge regression

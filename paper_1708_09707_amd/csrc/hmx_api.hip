@@ -431,9 +431,10 @@ KernelFn kernel_fn(const hmx_kernel& k, int d) {
 }
 
 // grow a device buffer to at least `bytes`, keeping the first `keep` bytes
-void grow(DevBuf& b, size_t bytes, size_t keep, hipStream_t st, const char* what) {
+void grow(DevBuf& b, size_t bytes, size_t keep, hipStream_t st, const char* what,
+          bool exact = false) {
     if (b.p && b.bytes >= bytes) return;
-    size_t nb = std::max(bytes, b.bytes * 2);
+    size_t nb = exact ? bytes : std::max(bytes, b.bytes * 2);
     DevBuf nbuf;
     alloc(nbuf, nb, what);
     if (keep) check(hipMemcpyAsync(nbuf.p, b.p, keep, hipMemcpyDeviceToDevice, st), "grow copy");
@@ -1126,7 +1127,14 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                 const int64_t uk = scan(ue, nbk), vk = scan(ve, nbk);
                 check(launch_add_const(ue, nbk, ftot, st), "offsets");
                 check(launch_add_const(ve, nbk, ftot + uk, st), "offsets");
-                grow(F, (size_t)(ftot + uk + vk) * ssz, (size_t)ftot * ssz, st, "factor pool");
+                // the pool's size extrapolated from the chunks so far (each chunk
+                // holds a share of every level), so it grows in one step
+                // rather than by doublings that copy tens of GB
+                int64_t want = ftot + uk + vk;
+                if (nch > 1 && (size_t)want * ssz > F.bytes)
+                    want = std::max<int64_t>(
+                        want, (int64_t)((double)want / (k + 1) * nch * 1.05) + 1);
+                grow(F, (size_t)want * ssz, (size_t)ftot * ssz, st, "factor pool", true);
                 check(launch_compact_u(a.blocks, nbk, a.rank, a.uoff, a.ubase, ue, Ucap.p, F.p,
                                        smode, st),
                       "compact U");
@@ -1414,14 +1422,15 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                                pcu.as<int64_t>(), psu.as<int64_t>(), psn.as<int64_t>(),
                                h->tile_meta.as<int64_t>(), st),
               "tile meta");
+        // the factor rows first; the near field's pool is allocated once the
+        // exact-rank factors are released (the two never coexist)
         alloc(h->upool, (size_t)std::max<int64_t>(h->upool_entries, 1) * ssz, "factor pool");
-        alloc(h->npool, (size_t)std::max<int64_t>(h->npool_entries, 1) * h->nsz, "near-field pool");
         check(launch_piece_data(h->pieces.as<Piece>(), h->npieces, h->tile_lo.as<int32_t>(),
                                 h->adm.as<int4>(), h->dense.as<int4>(), rfo.as<int64_t>(), F.p,
                                 f64 ? h->soa64.p : h->soa32.p, n, d,
-                                kernel_fn(h->kern, h->d), h->upool.p, h->npool.p,
-                                smode, h->nmode, st),
-              "piece data");
+                                kernel_fn(h->kern, h->d), h->upool.p, nullptr, smode, h->nmode, 1,
+                                st),
+              "piece data (factors)");
         h->Ru = R;
         // ---- phase-1 sources (t = V^T x by row tiles) ----
         // the V pool: pieces of V_b rows per row tile of sigma_b for every
@@ -1510,6 +1519,16 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
             alloc(h->p1rec, 16, "phase-1 records");
         }
         check(hipStreamSynchronize(st), "pool sync");
+        F.release();
+        alloc(h->npool, (size_t)std::max<int64_t>(h->npool_entries, 1) * h->nsz, "near-field pool");
+        if (h->nmode != 3)
+            check(launch_piece_data(h->pieces.as<Piece>(), h->npieces, h->tile_lo.as<int32_t>(),
+                                    h->adm.as<int4>(), h->dense.as<int4>(), nullptr, nullptr,
+                                    f64 ? h->soa64.p : h->soa32.p, n, d,
+                                    kernel_fn(h->kern, h->d), h->upool.p, h->npool.p, smode,
+                                    h->nmode, 2, st),
+                  "piece data (near field)");
+        check(hipStreamSynchronize(st), "near-field sync");
     }
     F.release();
     // near-field entry count (algorithmic, unpadded)
@@ -2422,7 +2441,7 @@ hmx_status hmx_autotune(hmx_hmatrix h, int32_t reps, void* stream, int32_t* choi
         // phase 1: lanes per column group
         double pbest = INFINITY;
         int pl = 0;
-        for (int lanes : {16, 32, 64}) {
+        for (int lanes : {8, 16, 32, 64}) {
             check(p1_tiles(h, st, lanes), "tuning warm-up");
             check(hipEventRecord(e0, st), "event");
             for (int r = 0; r < reps; ++r) check(p1_tiles(h, st, lanes), "tuning launch");
@@ -2453,6 +2472,7 @@ hmx_status hmx_set_tile_config(hmx_hmatrix h, int32_t config) {
     }
     h->rt_config = config;
     h->stats.tile_config = config;
+    if (config < 0) h->p1_lanes = 0;  // the defaults of both phases
     return HMX_OK;
 }
 

@@ -418,7 +418,9 @@ hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* til
                              const int4* adm, const int4* dense, const int64_t* uoff,
                              const void* Usrc /* storage type */, const void* soa, int64_t n,
                              int d, KernelFn kern,
-                             void* upool, void* npool, int fmode, int nmode, hipStream_t st);
+                             void* upool, void* npool, int fmode, int nmode,
+                             int which /*0 all, 1 factor pieces, 2 near-field pieces*/,
+                             hipStream_t st);
 // smode: storage mode 0 = F64, 1 = F32, 2 = BF16 storage with F32 arithmetic
 hipError_t launch_compact_v(const int4* blocks, int64_t nblocks, const int32_t* rank,
                             const int64_t* cap_voff, int64_t cap_base, const int64_t* voff,
@@ -515,7 +517,7 @@ hipError_t launch_scatter_i64(const int32_t* list, int64_t nl, const int64_t* sr
 // offset in pool; tiles padded to multiples of R rows)
 hipError_t launch_p1_tile(int64_t ntiles, const int32_t* tile_lo, const int64_t* meta, int ms,
                           int R, int max_tile, const void* pool, const void* vec, void* partial,
-                          int64_t pbase, int smode, int lanes /*16, 32, 64; 0 = by tile height*/,
+                          int64_t pbase, int smode, int lanes /*8, 16, 32, 64; 0 = by tile height*/,
                           hipStream_t st);
 // t entries: vec[n + k] = sum over j < rec[k].nt of partial[pfc[base + j] + l]
 hipError_t launch_p1_reduce(const int4* rec, int64_t ncols, const int64_t* pfc,

@@ -360,11 +360,13 @@ __global__ __launch_bounds__(256) void piece_data_kernel(
     const Piece* __restrict__ pieces, int64_t np, const int32_t* __restrict__ tile_lo,
     const int4* __restrict__ adm, const int4* __restrict__ dense,
     const int64_t* __restrict__ uoff, const SU* __restrict__ Usrc, const T* __restrict__ soa,
-    int64_t n, int d, KernelEval<T> K, SU* __restrict__ upool, SN* __restrict__ npool) {
+    int64_t n, int d, KernelEval<T> K, SU* __restrict__ upool, SN* __restrict__ npool,
+    int which) {
     const int tid = threadIdx.x;
     for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
         const Piece pc = pieces[p];
         if (is_recompute<SN>::value && pc.blk < 0) continue;  // near field evaluated per product
+        if ((which == 1 && pc.blk < 0) || (which == 2 && pc.blk >= 0)) continue;
         const int32_t r0 = tile_lo[pc.tile];
         const int mt = tile_lo[pc.tile + 1] - r0;
         const int ld = tile_ld(mt, R);
@@ -857,7 +859,8 @@ int rows_per_unit(int fmode, int nmode) {
 hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* tile_lo,
                              const int4* adm, const int4* dense, const int64_t* uoff,
                              const void* Usrc, const void* soa, int64_t n, int d, KernelFn kern,
-                             void* upool, void* npool, int fmode, int nmode, hipStream_t st) {
+                             void* upool, void* npool, int fmode, int nmode, int which,
+                             hipStream_t st) {
     if (np == 0) return hipSuccess;
     const unsigned grid = grid_cap(np, 1 << 20);
 // each combination's unit (rows_per_unit) is a template argument
@@ -865,7 +868,7 @@ hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* til
     if (R != rows_per_unit(fmode, nmode)) return hipErrorInvalidValue;                        \
     else hipLaunchKernelGGL((piece_data_kernel<SU, SN, T, R>), dim3(grid), dim3(256), 0, st,     \
                        pieces, np, tile_lo, adm, dense, uoff, (const SU*)Usrc, (const T*)soa, \
-                       n, d, KernelEval<T>(kern), (SU*)upool, (SN*)npool)
+                       n, d, KernelEval<T>(kern), (SU*)upool, (SN*)npool, which)
     if (fmode == 0 && nmode == 0) {
         HMX_PD(double, double, double, 2);
     } else if (fmode == 1 && nmode == 1) {

@@ -86,7 +86,11 @@ __global__ __launch_bounds__(kP1Threads) void p1_tile_kernel(
     int64_t pbase) {
     constexpr int VS = P1Dec<S, T>::n;
     constexpr int G = kP1Threads / L;
-    static_assert(L >= 16 && L <= 64, "groups of 16, 32 or 64 lanes");
+    static_assert(L >= 8 && L <= 64, "groups of 8, 16, 32 or 64 lanes");
+    // halving exchanges (at most four: 16 values per lane down to one);
+    // with 8 lanes three, and each lane keeps two column totals
+    constexpr int HS = L >= 16 ? 4 : 3;
+    constexpr int KEEP = kP1Cols >> HS;
     __shared__ T sx[kP1Stage];
     const int g = threadIdx.x / L;
     const int q = threadIdx.x % L;
@@ -130,13 +134,14 @@ __global__ __launch_bounds__(kP1Threads) void p1_tile_kernel(
                     for (int e = 0; e < VS; ++e) acc[u] += a[e] * xv[e];
                 }
             }
-            // butterfly over the group's lanes: exchanges L/2, L/4, L/8, L/16
-            // halve the values held per lane, the rest add the one left
+            // butterfly over the group's lanes: the first HS exchanges (L/2,
+            // L/4, ...) halve the values held per lane, the rest add the one
+            // left; each lane ends with the totals of KEEP consecutive columns
             int off = 0;
 #pragma unroll
             for (int s = 0, m = L / 2; m >= 1; ++s, m >>= 1) {
                 const bool hi = (q & m) != 0;
-                if (s < 4) {
+                if (s < HS) {
                     const int h = kP1Cols >> (s + 1);
 #pragma unroll
                     for (int i = 0; i < kP1Cols / 2; ++i) {
@@ -151,7 +156,11 @@ __global__ __launch_bounds__(kP1Threads) void p1_tile_kernel(
                     acc[0] += __shfl_xor(acc[0], m, 64);
                 }
             }
-            if ((q & (L / 16 - 1)) == 0 && cb + off < nc) partial[pbase + c0 + cb + off] = acc[0];
+            if ((q & (L >= 16 ? L / 16 - 1 : 0)) == 0) {
+#pragma unroll
+                for (int i = 0; i < KEEP; ++i)
+                    if (cb + off + i < nc) partial[pbase + c0 + cb + off + i] = acc[i];
+            }
         }
         if (staged) __syncthreads();  // sx is refilled by the next tile
     }
@@ -407,20 +416,23 @@ unsigned g1(int64_t n, int bs = 256) {
     return (unsigned)(b < (1 << 30) ? b : (1 << 30));
 }
 
-// lanes: 16, 32 or 64 lanes per column group; 0 picks the narrowest group
-// that leaves each lane at most 8 row vectors of the tallest tile
+// lanes: 8, 16, 32 or 64 lanes per column group; 0 picks the narrowest
+// group that leaves each lane at most 8 row vectors of the tallest tile and
+// no lane idle
 template <typename S, typename T>
 hipError_t p1_tile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_t* meta, int ms,
                             int R, int max_ld, const void* pool, const void* vec, void* partial,
                             int64_t pbase, int lanes, hipStream_t st) {
     constexpr int VS = P1Dec<S, T>::n;
     const int need = (max_ld + VS - 1) / VS;  // row vectors of the tallest tile
-    if (lanes == 0) lanes = need <= 8 * 16 ? 16 : (need <= 8 * 32 ? 32 : 64);
+    if (lanes == 0) lanes = need <= 8 ? 8 : (need <= 8 * 16 ? 16 : (need <= 8 * 32 ? 32 : 64));
     const unsigned grid = (unsigned)(ntiles < (1 << 30) ? ntiles : (1 << 30));
 #define HMX_P1(LL)                                                                             \
     hipLaunchKernelGGL((p1_tile_kernel<S, T, LL>), dim3(grid), dim3(kP1Threads), 0, st, ntiles, \
                        tile_lo, meta, ms, R, (const S*)pool, (const T*)vec, (T*)partial, pbase)
-    if (lanes == 16)
+    if (lanes == 8)
+        HMX_P1(8);
+    else if (lanes == 16)
         HMX_P1(16);
     else if (lanes == 32)
         HMX_P1(32);
