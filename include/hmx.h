@@ -190,6 +190,29 @@ typedef struct {
     void* (*dev_alloc)(size_t bytes, void* ctx);
     void (*dev_free)(void* ptr, size_t bytes, void* ctx);
     void* alloc_ctx;
+    int32_t far_recompute;   /* 1: no precomputation of the far field (the
+                                paper's default mode, Section 5.4).  The build
+                                runs ordering, cluster tree, traversal and the
+                                chunk plan of the ACA list only (no ACA, no
+                                factors); every hmx_matvec approximates the
+                                admissible leaves again, chunk by chunk within
+                                the aca_chunk_mb budget (bs_ACA of Section
+                                5.4.1), applying each chunk's U (V^T x) at
+                                once, so the device holds one chunk's ACA
+                                scratch instead of all factors.  The ACA is
+                                Algorithm 2 with the same pivots and tests as
+                                the stored mode, so the ranks and factors equal
+                                a stored build's; the sums run in another
+                                order (per chunk), so products agree to
+                                rounding.  With near_recompute also the near
+                                field is evaluated in every product.  Adaptive
+                                or fixed rank modes only (LEARNED:
+                                UNSUPPORTED); excludes aca_only.  hmx_matvec
+                                then waits for its stream to finish;
+                                hmx_matvec_graph, hmx_cg_solve_noalloc and
+                                hmx_get_factors return UNSUPPORTED;
+                                hmx_get_ranks reports the ranks of the last
+                                matvec (0 before the first) */
 } hmx_params;
 
 /* Statistics of a built H-matrix (host struct). */
@@ -414,7 +437,10 @@ hmx_status hmx_get_stats(hmx_hmatrix h, hmx_stats* s);
  * recorded event, writes the summed milliseconds of each phase to ms[0..2]
  * (host) and the number of recorded calls to *calls, and releases the
  * events.  begin allocates the events (host-side HIP objects, no device
- * memory); matvec itself still allocates nothing. */
+ * memory); matvec itself still allocates nothing.  For a handle built with
+ * far_recompute the three phases are: the near field (gather and row
+ * tiles), the far field (ACA and application of every chunk), and the
+ * ranks' bookkeeping; that matvec allocates its chunk scratch. */
 hmx_status hmx_profile_begin(hmx_hmatrix h, int32_t max_calls);
 hmx_status hmx_profile_end(hmx_hmatrix h, double* ms, int32_t* calls);
 

@@ -316,6 +316,18 @@ struct hmx_graph_s {
     hipGraphExec_t exec = nullptr;
 };
 
+// The far field without precomputation: the ACA list in chunk order (each
+// chunk's column scratch within the budget), per entry its leaf, capacity
+// offsets and the ranks of the last matvec, and the apply pieces sorted by
+// (chunk, row tile) with their segments
+struct NpPlan {
+    int64_t nl = 0, npcs = 0, nseg = 0;
+    int64_t max_u = 0, max_v = 0, max_nb = 0;
+    int big_words = 0, med_words = 0, tiny_words = 0;  // the ACA classes' bitmask words
+    DevBuf blocks, lmap, cu, cv, rank, steps, spcs, seg_start, seg_tile;
+    std::vector<int64_t> bounds, hcu, hcv, cseg, cls;  // cls: nsplit, nbig, nmed per chunk
+};
+
 struct hmx_hmatrix_s {
     int64_t n = 0;
     int d = 0;
@@ -354,6 +366,8 @@ struct hmx_hmatrix_s {
     int Ru = 0, Rv = 0;  // row units of the factor pool and of the V pool
     int64_t ncols_u = 0, ncols_v = 0, nvpieces = 0, vtpool_entries = 0;
     DevBuf partner, vpieces, vtpool, vt_meta, p1rec, pfc, partial;
+    int far_np = 0;  // factors recomputed by every matvec
+    NpPlan np;
     hmx_stats stats{};
     // matvec phase tracing (hmx_profile_begin / end)
     std::vector<hipEvent_t> prof_events;
@@ -373,7 +387,8 @@ struct hmx_hmatrix_s {
                                &rank,    &steps,   &toff,      &pieces,        &upool,
                                &npool,   &widx,    &tile_meta, &vecpool,       &partner,
                                &vpieces, &vtpool,  &vt_meta,   &p1rec,         &pfc,
-                               &partial};
+                               &partial, &np.blocks, &np.lmap, &np.cu,  &np.cv,
+                               &np.rank, &np.steps, &np.spcs,  &np.seg_start, &np.seg_tile};
         int64_t s = 0;
         for (auto* b : all) s += (int64_t)b->bytes;
         return s;
@@ -470,6 +485,7 @@ void init_handle(hmx_hmatrix_s* h, int64_t n, int d, const hmx_kernel& k, const 
         h->nsz = 0;
     }
     h->sym = p.symmetric_far;
+    h->far_np = p.far_recompute;
 }
 
 // validation shared by the single and the batched build
@@ -530,6 +546,18 @@ hmx_status check_params(const hmx_params& p) {
     if (p.symmetric_far != 0 && p.symmetric_far != 1) {
         set_err("symmetric_far must be 0 or 1");
         return HMX_ERR_INVALID_ARG;
+    }
+    if (p.far_recompute != 0 && p.far_recompute != 1) {
+        set_err("far_recompute must be 0 or 1");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (p.far_recompute && p.aca_only) {
+        set_err("far_recompute and aca_only exclude each other (the build runs no ACA)");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (p.far_recompute && p.rank_mode == HMX_RANK_LEARNED) {
+        set_err("far_recompute supports the adaptive and fixed rank modes");
+        return HMX_ERR_UNSUPPORTED;
     }
     return HMX_OK;
 }
@@ -862,6 +890,251 @@ void prepare_split(hmx_hmatrix_s* h, const AcaArgs& a, int f64, hipStream_t st,
     P.active_host = B.poll->p;
 }
 
+// The blocks of a level-sorted list regrouped into nsl chunks that each hold
+// the same share of every level, level-sorted within the chunk (so the size
+// classes of the ACA run side by side in every chunk): entry i of the chunk
+// order is list entry perm[i]; bounds: the chunks' first entries and the end.
+// cap and rt (optional per-block int32 arrays) are gathered along.
+struct ChunkOrder {
+    DevBuf perm, blocks, levels, cap, rt;
+    std::vector<int64_t> bounds;
+};
+
+void interleave(const int4* blocks, const int32_t* levels, int64_t nb, const int32_t* cap,
+                const int32_t* rt, int nsl, hipStream_t st, ChunkOrder& o) {
+    DevBuf lb;
+    alloc(lb, 2 * 64 * 8, "level bounds");
+    check(hipMemsetAsync(lb.p, 0, 2 * 64 * 8, st), "level bounds");
+    int64_t* lstart = lb.as<int64_t>();
+    int64_t* lend = lstart + 64;
+    check(launch_level_bounds(levels, nb, lstart, lend, st), "level bounds");
+    int64_t hl[128];
+    d2h(hl, lb.p, sizeof hl, st);
+    // chunk k: the positions p of each level (c blocks) with
+    // floor(p nsl / c) == k, i.e. [ceil(k c / nsl), ceil((k + 1) c / nsl))
+    std::vector<int64_t>& bounds = o.bounds;
+    bounds.assign(nsl + 1, 0);
+    for (int l = 0; l < 64; ++l) {
+        const int64_t c = hl[64 + l] - hl[l];
+        if (c <= 0) continue;
+        for (int k = 0; k < nsl; ++k)
+            bounds[k + 1] +=
+                ((int64_t)(k + 1) * c + nsl - 1) / nsl - ((int64_t)k * c + nsl - 1) / nsl;
+    }
+    for (int k = 0; k < nsl; ++k) bounds[k + 1] += bounds[k];
+    if (bounds[nsl] != nb) {
+        set_err("interleaved chunks cover %lld of %lld blocks", (long long)bounds[nsl],
+                (long long)nb);
+        throw Fail{HMX_ERR_DEVICE};
+    }
+    DevBuf keys, sscr;
+    alloc(keys, (size_t)nb * 8, "interleave keys");
+    alloc(o.perm, (size_t)nb * 4, "interleave order");
+    check(launch_interleave_keys(levels, nb, lstart, lend, nsl, keys.as<uint64_t>(),
+                                 o.perm.as<uint32_t>(), st),
+          "interleave keys");
+    int bits = 8;
+    while ((1ll << (bits - 8)) < nsl) ++bits;
+    alloc(sscr, radix_sort_scratch_bytes(nb), "interleave sort");
+    check(radix_sort_pairs(keys.as<uint64_t>(), o.perm.as<uint32_t>(), nb, bits, sscr.p, st),
+          "interleave sort");
+    keys.release();
+    sscr.release();
+    alloc(o.blocks, (size_t)nb * sizeof(int4), "interleaved blocks");
+    alloc(o.levels, (size_t)nb * 4, "interleaved levels");
+    if (cap) alloc(o.cap, (size_t)nb * 4, "interleaved capacities");
+    if (rt) alloc(o.rt, (size_t)nb * 4, "interleaved targets");
+    check(launch_gather_blocks(o.perm.as<uint32_t>(), nb, blocks, levels, cap, rt,
+                               o.blocks.as<int4>(), o.levels.as<int32_t>(),
+                               cap ? o.cap.as<int32_t>() : nullptr,
+                               rt ? o.rt.as<int32_t>() : nullptr, st),
+          "interleave gather");
+}
+
+// the ACA arguments every chunk shares
+AcaArgs aca_args_base(const hmx_hmatrix_s* h, const AcaPlan& plan) {
+    AcaArgs a{};
+    const int f64 = h->f64;
+    a.soa = f64 ? h->soa64.p : h->soa32.p;
+    a.soa64 = h->soa64.as<double>();
+    a.n = h->n;
+    a.d = h->d;
+    a.kern = kernel_fn(h->kern, h->d);
+    a.kmax = h->prm.max_rank;
+    a.eps = h->prm.aca_eps;
+    a.aca_eta = h->prm.aca_eta;
+    a.eps0 = h->prm.aca_eps0 >= 0 ? h->prm.aca_eps0 : (f64 ? 1e-14 : 1e-7);
+    a.fixed = h->prm.rank_mode == HMX_RANK_FIXED;
+    a.big_words = plan.big_words;
+    a.med_words = plan.med_words;
+    a.tiny_words = plan.tiny_words;
+    return a;
+}
+
+// ACA scratch budget of one chunk, in compute-type entries: the caller's, else
+// 40% of the device memory that is free now (the library's cached blocks
+// count as free)
+int64_t aca_budget(const hmx_hmatrix_s* h) {
+    int64_t budget_bytes = (int64_t)h->prm.aca_chunk_mb << 20;
+    if (h->prm.aca_chunk_mb <= 0) {
+        size_t fr = 0, tot = 0;
+        check(hipMemGetInfo(&fr, &tot), "memory info");
+        size_t cached = 0;
+        {
+            std::lock_guard<std::mutex> lk(cache().mu);
+            cached = cache().cached;
+        }
+        budget_bytes = std::max<int64_t>((int64_t)((fr + cached) / 10 * 4), (int64_t)1 << 30);
+    }
+    return std::max<int64_t>(budget_bytes / (int64_t)h->esz, 1);
+}
+
+// The far field without precomputation: the ACA list (blocks Lb with levels
+// Ll, level-sorted; lmap: the leaf of each entry, null: entry i is leaf i)
+// cut into chunks whose k_max column scratch fits the budget, each holding a
+// share of every level as in the stored build, and the pieces that each
+// chunk's products add to the row tiles, sorted by (chunk, tile)
+void np_plan(hmx_hmatrix_s* h, const AcaPlan& plan, const int4* Lb, const int32_t* Ll,
+             int64_t nl, const int32_t* lmap, hipStream_t st) {
+    NpPlan& P = h->np;
+    P.nl = nl;
+    P.big_words = plan.big_words;
+    P.med_words = plan.med_words;
+    P.tiny_words = plan.tiny_words;
+    const int kmax = h->prm.max_rank;
+    DevBuf scan_scr;
+    auto scan = [&](int64_t* data, int64_t cnt) -> int64_t {
+        const size_t need = scan_scratch_bytes(cnt + 1) + 64;
+        if (!scan_scr.p || scan_scr.bytes < need) alloc(scan_scr, need, "scan scratch");
+        check(exclusive_scan_i64(data, cnt, data + cnt, scan_scr.p, st), "scan");
+        return read_scalar(data + cnt, st);
+    };
+    DevBuf ident;
+    if (!lmap) {
+        alloc(ident, (size_t)nl * 4, "list leaves");
+        check(launch_np_iota(ident.as<int32_t>(), nl, st), "list leaves");
+        lmap = ident.as<int32_t>();
+    }
+    DevBuf cc;
+    alloc(cc, (size_t)(nl + 1) * 8, "capacity");
+    check(launch_extent(Lb, nl, 7, kmax, nullptr, nullptr, cc.as<int64_t>(), st), "extent");
+    const int64_t ctot = scan(cc.as<int64_t>(), nl);
+    cc.release();
+    const int64_t budget = aca_budget(h);
+    const int32_t* levels = Ll;
+    ChunkOrder o;
+    if (ctot > budget) {
+        const int nsl = (int)std::min<int64_t>((ctot + ctot / 8 + budget - 1) / budget, 1 << 20);
+        interleave(Lb, Ll, nl, lmap, nullptr, nsl, st, o);
+        P.blocks.swap(o.blocks);
+        P.lmap.swap(o.cap);
+        levels = o.levels.as<int32_t>();
+        P.bounds = o.bounds;
+    } else {
+        alloc(P.blocks, (size_t)nl * sizeof(int4), "list blocks");
+        alloc(P.lmap, (size_t)nl * 4, "list leaves");
+        check(hipMemcpyAsync(P.blocks.p, Lb, (size_t)nl * sizeof(int4), hipMemcpyDeviceToDevice,
+                             st),
+              "list blocks");
+        check(hipMemcpyAsync(P.lmap.p, lmap, (size_t)nl * 4, hipMemcpyDeviceToDevice, st),
+              "list leaves");
+        P.bounds = {0, nl};
+    }
+    const int nch = (int)P.bounds.size() - 1;
+    const int4* B = P.blocks.as<int4>();
+    // k_max columns of U and V per block, offsets in chunk order
+    alloc(P.cu, (size_t)(nl + 1) * 8, "U capacity offsets");
+    alloc(P.cv, (size_t)(nl + 1) * 8, "V capacity offsets");
+    check(launch_extent(B, nl, 0, kmax, nullptr, nullptr, P.cu.as<int64_t>(), st), "extent");
+    check(launch_extent(B, nl, 1, kmax, nullptr, nullptr, P.cv.as<int64_t>(), st), "extent");
+    scan(P.cu.as<int64_t>(), nl);
+    scan(P.cv.as<int64_t>(), nl);
+    P.hcu.assign(nch + 1, 0);
+    P.hcv.assign(nch + 1, 0);
+    for (int k = 0; k <= nch; ++k) {
+        check(hipMemcpyAsync(&P.hcu[k], P.cu.as<int64_t>() + P.bounds[k], 8,
+                             hipMemcpyDeviceToHost, st),
+              "cu");
+        check(hipMemcpyAsync(&P.hcv[k], P.cv.as<int64_t>() + P.bounds[k], 8,
+                             hipMemcpyDeviceToHost, st),
+              "cv");
+    }
+    // the size classes of every chunk (level-sorted within the chunk)
+    DevBuf split;
+    alloc(split, (size_t)nch * 3 * 8, "class split");
+    check(hipMemsetAsync(split.p, 0, (size_t)nch * 3 * 8, st), "class split");
+    const int lv[3] = {plan.split0, plan.split, plan.split2};
+    for (int k = 0; k < nch; ++k)
+        for (int c = 0; c < 3; ++c)
+            check(launch_level_split(levels + P.bounds[k], P.bounds[k + 1] - P.bounds[k], lv[c],
+                                     split.as<int64_t>() + 3 * k + c, st),
+                  "class split");
+    P.cls.assign((size_t)nch * 3, 0);
+    d2h(P.cls.data(), split.p, (size_t)nch * 3 * 8, st);
+    P.max_u = P.max_v = P.max_nb = 0;
+    for (int k = 0; k < nch; ++k) {
+        P.max_u = std::max(P.max_u, P.hcu[k + 1] - P.hcu[k]);
+        P.max_v = std::max(P.max_v, P.hcv[k + 1] - P.hcv[k]);
+        P.max_nb = std::max(P.max_nb, P.bounds[k + 1] - P.bounds[k]);
+    }
+    alloc(P.rank, (size_t)nl * 4, "list ranks");
+    alloc(P.steps, (size_t)nl * 4, "list steps");
+    check(hipMemsetAsync(P.rank.p, 0, (size_t)nl * 4, st), "list ranks");
+    check(hipMemsetAsync(P.steps.p, 0, (size_t)nl * 4, st), "list steps");
+    // apply pieces: (entry, side) per row tile of tau (side 0) and, for a
+    // mirrored primary, of sigma (side 1), sorted by (chunk, tile)
+    DevBuf cnt;
+    alloc(cnt, (size_t)(nl + 1) * 8, "piece counts");
+    check(launch_np_piece_count(B, nl, h->sym, h->tile_of_point.as<int32_t>(),
+                                cnt.as<int64_t>(), st),
+          "piece counts");
+    const int64_t npcs = scan(cnt.as<int64_t>(), nl);
+    if (npcs >= ((int64_t)1 << 32)) {
+        set_err("far_recompute: %lld apply pieces exceed the sort's 2^32", (long long)npcs);
+        throw Fail{HMX_ERR_UNSUPPORTED};
+    }
+    P.npcs = npcs;
+    int tbits = 1, cbits = 1;
+    while ((1ll << tbits) < h->ntiles) ++tbits;
+    while ((1ll << cbits) < nch) ++cbits;
+    DevBuf dbounds, keys, vals, pcs, sscr, flags, dcseg;
+    alloc(dbounds, (size_t)(nch + 1) * 8, "chunk bounds");
+    check(hipMemcpyAsync(dbounds.p, P.bounds.data(), (size_t)(nch + 1) * 8,
+                         hipMemcpyHostToDevice, st),
+          "chunk bounds");
+    alloc(keys, (size_t)npcs * 8, "piece keys");
+    alloc(vals, (size_t)npcs * 4, "piece order");
+    alloc(pcs, (size_t)npcs * sizeof(int2), "pieces");
+    check(launch_np_piece_fill(B, nl, h->sym, h->tile_of_point.as<int32_t>(), cnt.as<int64_t>(),
+                               dbounds.as<int64_t>(), nch, tbits, keys.as<uint64_t>(),
+                               vals.as<uint32_t>(), pcs.as<int2>(), st),
+          "piece fill");
+    alloc(sscr, radix_sort_scratch_bytes(npcs), "piece sort");
+    check(radix_sort_pairs(keys.as<uint64_t>(), vals.as<uint32_t>(), npcs, tbits + cbits, sscr.p,
+                           st),
+          "piece sort");
+    sscr.release();
+    alloc(flags, (size_t)(npcs + 1) * 8, "segment flags");
+    check(launch_np_seg_flags(keys.as<uint64_t>(), npcs, flags.as<int64_t>(), st),
+          "segment flags");
+    P.nseg = npcs > 0 ? scan(flags.as<int64_t>(), npcs) : 0;
+    alloc(P.seg_start, (size_t)(P.nseg + 1) * 8, "segment starts");
+    alloc(P.seg_tile, (size_t)std::max<int64_t>(P.nseg, 1) * 4, "segment tiles");
+    alloc(P.spcs, (size_t)std::max<int64_t>(npcs, 1) * sizeof(int2), "sorted pieces");
+    check(launch_np_seg_fill(keys.as<uint64_t>(), vals.as<uint32_t>(), pcs.as<int2>(),
+                             flags.as<int64_t>(), npcs, P.nseg, tbits, P.seg_start.as<int64_t>(),
+                             P.seg_tile.as<int32_t>(), P.spcs.as<int2>(), st),
+          "segments");
+    alloc(dcseg, (size_t)(nch + 1) * 8, "chunk segments");
+    check(hipMemsetAsync(dcseg.p, 0, (size_t)(nch + 1) * 8, st), "chunk segments");
+    check(launch_np_chunk_segs(keys.as<uint64_t>(), P.seg_start.as<int64_t>(), P.nseg, tbits,
+                               nch, dcseg.as<int64_t>(), st),
+          "chunk segments");
+    P.cseg.assign(nch + 1, 0);
+    d2h(P.cseg.data(), dcseg.p, (size_t)(nch + 1) * 8, st);
+    check(hipStreamSynchronize(st), "plan sync");
+}
+
 // phases 4-5: batched ACA, compaction, the tile-major matrix pool
 void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                    std::chrono::steady_clock::time_point t_all) {
@@ -962,39 +1235,22 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
     alloc(lsteps, (size_t)std::max<int64_t>(nl, 1) * 4, "list steps");
     alloc(lue, (size_t)(nl + 1) * 8, "list U offsets");
     alloc(lve, (size_t)(nl + 1) * 8, "list V offsets");
-    if (nl > 0) {
-        // chunk budget: the caller's, else 40% of the device memory that is
-        // free now (the library's cached blocks count as free)
-        int64_t budget_bytes = (int64_t)h->prm.aca_chunk_mb << 20;
-        if (h->prm.aca_chunk_mb <= 0) {
-            size_t fr = 0, tot = 0;
-            check(hipMemGetInfo(&fr, &tot), "memory info");
-            size_t cached = 0;
-            {
-                std::lock_guard<std::mutex> lk(cache().mu);
-                cached = cache().cached;
-            }
-            budget_bytes = std::max<int64_t>((int64_t)((fr + cached) / 10 * 4), (int64_t)1 << 30);
-        }
-        const int64_t budget = std::max<int64_t>(budget_bytes / (int64_t)esz, 1);
+    if (h->far_np) {
+        // no precomputation: the chunk plan only; the leaves keep rank 0 (no
+        // factor pieces in the matrix pool) until a matvec approximates them
+        if (nl > 0) np_plan(h, plan, Lb, Ll, nl, h->sym ? lst.as<int32_t>() : nullptr, st);
+        nchunks = nl > 0 ? (int)h->np.bounds.size() - 1 : 0;
+        check(hipMemsetAsync(h->rank.p, 0, h->rank.bytes, st), "ranks");
+        check(hipMemsetAsync(h->steps.p, 0, h->steps.bytes, st), "steps");
+        check(hipMemsetAsync(rfo.p, 0, rfo.bytes, st), "row factor offsets");
+        check(hipMemsetAsync(vfo.p, 0, vfo.bytes, st), "V offsets");
+    } else if (nl > 0) {
+        const int64_t budget = aca_budget(h);
         // the single-workgroup classes run beside the multi-workgroup path
         AuxStream auxs[3];
         const hipStream_t aux[3] = {auxs[0].s, auxs[1].s, auxs[2].s};
         const bool have_aux = aux[0] && aux[1] && aux[2];
-        AcaArgs a{};
-        a.soa = f64 ? h->soa64.p : h->soa32.p;
-        a.soa64 = h->soa64.as<double>();
-        a.n = n;
-        a.d = d;
-        a.kern = kernel_fn(h->kern, h->d);
-        a.kmax = kmax;
-        a.eps = h->prm.aca_eps;
-        a.aca_eta = h->prm.aca_eta;
-        a.eps0 = h->prm.aca_eps0 >= 0 ? h->prm.aca_eps0 : (f64 ? 1e-14 : 1e-7);
-        a.fixed = h->prm.rank_mode == HMX_RANK_FIXED;
-        a.big_words = plan.big_words;
-        a.med_words = plan.med_words;
-        a.tiny_words = plan.tiny_words;
+        AcaArgs a = aca_args_base(h, plan);
         DevBuf split;
         alloc(split, 3 * 8, "class split");
 
@@ -1169,53 +1425,11 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
             // slices of equal shares, with room for the variation of the
             // per-block capacities between slices
             const int nsl = (int)std::min<int64_t>((ctot + ctot / 8 + budget - 1) / budget, 1 << 20);
-            DevBuf lb;
-            alloc(lb, 2 * 64 * 8, "level bounds");
-            check(hipMemsetAsync(lb.p, 0, 2 * 64 * 8, st), "level bounds");
-            int64_t* lstart = lb.as<int64_t>();
-            int64_t* lend = lstart + 64;
-            check(launch_level_bounds(levels, nb, lstart, lend, st), "level bounds");
-            int64_t hl[128];
-            d2h(hl, lb.p, sizeof hl, st);
-            // chunk k: the positions p of each level (c blocks) with
-            // floor(p nsl / c) == k, i.e. [ceil(k c / nsl), ceil((k + 1) c / nsl))
-            std::vector<int64_t> bounds(nsl + 1, 0);
-            for (int l = 0; l < 64; ++l) {
-                const int64_t c = hl[64 + l] - hl[l];
-                if (c <= 0) continue;
-                for (int k = 0; k < nsl; ++k)
-                    bounds[k + 1] += ((int64_t)(k + 1) * c + nsl - 1) / nsl -
-                                     ((int64_t)k * c + nsl - 1) / nsl;
-            }
-            for (int k = 0; k < nsl; ++k) bounds[k + 1] += bounds[k];
-            if (bounds[nsl] != nb) {
-                set_err("interleaved chunks cover %lld of %lld blocks", (long long)bounds[nsl],
-                        (long long)nb);
-                throw Fail{HMX_ERR_DEVICE};
-            }
-            DevBuf keys, perm, sscr;
-            alloc(keys, (size_t)nb * 8, "interleave keys");
-            alloc(perm, (size_t)nb * 4, "interleave order");
-            check(launch_interleave_keys(levels, nb, lstart, lend, nsl, keys.as<uint64_t>(),
-                                         perm.as<uint32_t>(), st),
-                  "interleave keys");
-            int bits = 8;
-            while ((1ll << (bits - 8)) < nsl) ++bits;
-            alloc(sscr, radix_sort_scratch_bytes(nb), "interleave sort");
-            check(radix_sort_pairs(keys.as<uint64_t>(), perm.as<uint32_t>(), nb, bits, sscr.p, st),
-                  "interleave sort");
-            keys.release();
-            sscr.release();
-            DevBuf pb, pl, pc, pr, prk, pst, pue, pve;
-            alloc(pb, (size_t)nb * sizeof(int4), "interleaved blocks");
-            alloc(pl, (size_t)nb * 4, "interleaved levels");
-            if (cap) alloc(pc, (size_t)nb * 4, "interleaved capacities");
-            if (rt) alloc(pr, (size_t)nb * 4, "interleaved targets");
-            check(launch_gather_blocks(perm.as<uint32_t>(), nb, blocks, levels, cap, rt,
-                                       pb.as<int4>(), pl.as<int32_t>(),
-                                       cap ? pc.as<int32_t>() : nullptr,
-                                       rt ? pr.as<int32_t>() : nullptr, st),
-                  "interleave gather");
+            ChunkOrder o;
+            interleave(blocks, levels, nb, cap, rt, nsl, st, o);
+            const std::vector<int64_t>& bounds = o.bounds;
+            DevBuf &perm = o.perm, &pb = o.blocks, &pl = o.levels, &pc = o.cap, &pr = o.rt;
+            DevBuf prk, pst, pue, pve;
             alloc(prk, (size_t)nb * 4, "interleaved ranks");
             alloc(pst, (size_t)nb * 4, "interleaved steps");
             alloc(pue, (size_t)(nb + 1) * 8, "interleaved U offsets");
@@ -1992,6 +2206,97 @@ hipError_t matvec_launch(hmx_hmatrix_s* h, const void* x, void* z, double alpha,
 }
 
 
+// A matvec without precomputed factors: the near field (and sigma2 x, beta z)
+// by the row tiles, then chunk by chunk the ACA of the chunk's blocks into
+// the column scratch, t = V^T x per block and z|tile += alpha U t per row
+// tile, then the ranks back to the leaves.  Synchronises st.
+void np_matvec(hmx_hmatrix_s* h, const void* x, void* z, double alpha, double beta,
+               hipStream_t st, hipEvent_t* ev) {
+    const int f64 = h->f64;
+    const size_t esz = h->esz;
+    const int kmax = h->prm.max_rank;
+    NpPlan& P = h->np;
+    if (ev) check(hipEventRecord(ev[0], st), "event");
+    check(matvec_launch(h, x, z, alpha, beta, st, nullptr, h->rt_config), "matvec (near field)");
+    if (ev) check(hipEventRecord(ev[1], st), "event");
+    if (P.nl > 0) {
+        AcaPlan plan{};
+        plan.big_words = P.big_words;
+        plan.med_words = P.med_words;
+        plan.tiny_words = P.tiny_words;
+        DevBuf Ucap, Vcap, tb, t2b;
+        alloc(Ucap, (size_t)std::max<int64_t>(P.max_u, 1) * esz, "U chunk scratch");
+        alloc(Vcap, (size_t)std::max<int64_t>(P.max_v, 1) * esz, "V chunk scratch");
+        alloc(tb, (size_t)std::max<int64_t>(P.max_nb, 1) * kmax * esz, "chunk t");
+        if (h->sym) alloc(t2b, (size_t)std::max<int64_t>(P.max_nb, 1) * kmax * esz, "chunk t'");
+        AuxStream auxs[3];
+        const hipStream_t aux[3] = {auxs[0].s, auxs[1].s, auxs[2].s};
+        const bool have_aux = aux[0] && aux[1] && aux[2];
+        AcaArgs a = aca_args_base(h, plan);
+        a.U = Ucap.p;
+        a.V = Vcap.p;
+        const int4* B = P.blocks.as<int4>();
+        const int64_t* cu = P.cu.as<int64_t>();
+        const int64_t* cv = P.cv.as<int64_t>();
+        int32_t* rank = P.rank.as<int32_t>();
+        const int nch = (int)P.bounds.size() - 1;
+        for (int k = 0; k < nch; ++k) {
+            const int64_t b0 = P.bounds[k], nbk = P.bounds[k + 1] - b0;
+            if (nbk == 0) continue;
+            a.blocks = B + b0;
+            a.nblocks = nbk;
+            a.uoff = cu + b0;
+            a.voff = cv + b0;
+            a.ubase = P.hcu[k];
+            a.vbase = P.hcv[k];
+            a.rank = rank + b0;
+            a.steps = P.steps.as<int32_t>() + b0;
+            a.nsplit = P.cls[3 * k];
+            a.nbig = P.cls[3 * k + 1];
+            a.nmed = P.cls[3 * k + 2];
+            SplitBuffers sb;
+            if (a.nsplit > 0) prepare_split(h, a, f64, st, sb);
+            check(aca_classes_begin(a, f64, st, have_aux ? aux : nullptr), "aca");
+            if (a.nsplit > 0)
+                check(launch_aca_split(a, sb.P, f64, st), "aca (many workgroups per block)");
+            check(aca_classes_join(st, have_aux ? aux : nullptr), "aca join");
+            check(launch_np_t(B + b0, nbk, rank + b0, cu + b0, cv + b0, P.hcu[k], P.hcv[k], Ucap.p,
+                              Vcap.p, h->vecpool.p, kmax, h->sym, tb.p, h->sym ? t2b.p : nullptr,
+                              f64, st),
+                  "far field t");
+            check(launch_np_apply(P.seg_start.as<int64_t>(), P.seg_tile.as<int32_t>(), P.cseg[k],
+                                  P.cseg[k + 1] - P.cseg[k], P.spcs.as<int2>(), B, rank, cu, cv,
+                                  P.hcu[k], P.hcv[k], b0, Ucap.p, Vcap.p, tb.p,
+                                  h->sym ? t2b.p : nullptr, kmax, h->tile_lo.as<int32_t>(),
+                                  h->perm.as<int32_t>(), alpha, z, h->max_tile, f64, st),
+                  "far field apply");
+            if (a.nsplit > 0) check(hipStreamSynchronize(st), "chunk sync");  // sb returns
+        }
+        if (ev) check(hipEventRecord(ev[2], st), "event");
+        // the ranks of this product back to the leaves (a mirror takes its
+        // primary's), and their statistics
+        check(launch_scatter_list(P.lmap.as<int32_t>(), P.nl,
+                                  h->sym ? h->partner.as<int32_t>() : nullptr, rank,
+                                  P.steps.as<int32_t>(), nullptr, nullptr,
+                                  h->rank.as<int32_t>(), h->steps.as<int32_t>(), nullptr, nullptr,
+                                  st),
+              "ranks");
+        DevBuf red;
+        alloc(red, 2 * sizeof(unsigned long long), "stats");
+        check(launch_int_stats(h->rank.as<int32_t>(), h->n_adm, red.as<unsigned long long>(), st),
+              "rank stats");
+        unsigned long long hv[2];
+        check(hipMemcpyAsync(hv, red.p, sizeof hv, hipMemcpyDeviceToHost, st), "stats readback");
+        if (ev) check(hipEventRecord(ev[3], st), "event");
+        check(hipStreamSynchronize(st), "matvec sync");  // before the scratch returns
+        h->stats.max_rank_used = (int32_t)hv[0];
+        h->stats.sum_rank = (int64_t)hv[1];
+    } else if (ev) {
+        check(hipEventRecord(ev[2], st), "event");
+        check(hipEventRecord(ev[3], st), "event");
+    }
+}
+
 // Work space of a CG solve: three n-vectors in the compute type, 8 FP64
 // scalars (r.r, p.q, r'.r', b.b, |b - (H + sigma2 I) x|^2) and the dot
 // products' block partials.
@@ -2301,6 +2606,11 @@ hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype
     if (cs != HMX_OK) return cs;
     hipEvent_t* ev = nullptr;
     if (h->prof_calls < h->prof_max) ev = &h->prof_events[4 * h->prof_calls++];
+    if (h->far_np) {
+        const Allocator ua{h->prm.dev_alloc, h->prm.dev_free, h->prm.alloc_ctx};
+        AllocScope scope(&ua);
+        return guarded([&] { np_matvec(h, x, z, alpha, beta, (hipStream_t)stream, ev); });
+    }
     const hipError_t e = matvec_launch(h, x, z, alpha, beta, (hipStream_t)stream, ev, h->rt_config);
     if (e != hipSuccess) {
         set_err("matvec launch: %s", hipGetErrorString(e));
@@ -2339,6 +2649,10 @@ hmx_status hmx_matvec_graph(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec
     }
     const hmx_status cs = matvec_args(h, x, z, vec_dtype);
     if (cs != HMX_OK) return cs;
+    if (h->far_np) {
+        set_err("far_recompute: the matvec waits for its chunks on the host; no graph");
+        return HMX_ERR_UNSUPPORTED;
+    }
     hmx_graph_s* g = new (std::nothrow) hmx_graph_s();
     if (!g) {
         set_err("host allocation failed");
@@ -2503,6 +2817,10 @@ hmx_status hmx_cg_solve_noalloc(hmx_hmatrix h, const void* b, void* x, double re
                                 double* true_rel_res) {
     hmx_status s = cg_args(h, b, x, rel_tol, max_iter);
     if (s != HMX_OK) return s;
+    if (h->far_np) {
+        set_err("hmx_cg_solve_noalloc: a far_recompute handle allocates chunk scratch per matvec");
+        return HMX_ERR_UNSUPPORTED;
+    }
     const size_t vb = cg_vec_bytes(h->n, h->esz);
     if (3 * vb + kCgScalBytes + cg_scratch_bytes() > HMX_CG_NOALLOC_MAX_BYTES) {
         set_err("hmx_cg_solve_noalloc: %lld entries of %zu bytes need %zu bytes of work space, "
@@ -2642,8 +2960,9 @@ hmx_status hmx_get_factors(hmx_hmatrix h, int64_t leaf, double* U, double* V, in
         set_err("invalid argument to hmx_get_factors");
         return HMX_ERR_INVALID_ARG;
     }
-    if (h->prm.aca_only) {
-        set_err("handle was built with aca_only: factors were not kept");
+    if (h->prm.aca_only || h->far_np) {
+        set_err("handle was built with %s: factors were not kept",
+                h->far_np ? "far_recompute" : "aca_only");
         return HMX_ERR_UNSUPPORTED;
     }
     hipStream_t st = (hipStream_t)stream;

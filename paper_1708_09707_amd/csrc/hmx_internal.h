@@ -577,4 +577,34 @@ hipError_t launch_narrow_u64(const uint64_t* src, int64_t n, int32_t* dst, hipSt
 hipError_t launch_scale_coords(const double* src, int64_t n, int d, double scale, double* dst64,
                                float* dst32, int64_t ntot, int64_t base, hipStream_t st);
 
+// the far field without precomputation (k_np.hip): the ACA list's pieces
+// (block, side) per (chunk, row tile), and per chunk of a matvec t_b = V_b^T x
+// (t'_b = U_b^T x for mirrored primaries) and z|tile += alpha F_b t_b
+hipError_t launch_np_iota(int32_t* a, int64_t n, hipStream_t st);
+hipError_t launch_np_piece_count(const int4* blk, int64_t nl, int sym,
+                                 const int32_t* tile_of_point, int64_t* cnt, hipStream_t st);
+hipError_t launch_np_piece_fill(const int4* blk, int64_t nl, int sym,
+                                const int32_t* tile_of_point, const int64_t* off,
+                                const int64_t* bounds, int nch, int tbits, uint64_t* keys,
+                                uint32_t* vals, int2* pcs, hipStream_t st);
+hipError_t launch_np_seg_flags(const uint64_t* keys, int64_t np, int64_t* flag, hipStream_t st);
+hipError_t launch_np_seg_fill(const uint64_t* keys, const uint32_t* vals, const int2* pcs,
+                              const int64_t* sidx, int64_t np, int64_t nseg, int tbits,
+                              int64_t* seg_start, int32_t* seg_tile, int2* spcs, hipStream_t st);
+hipError_t launch_np_chunk_segs(const uint64_t* keys, const int64_t* seg_start, int64_t nseg,
+                                int tbits, int nch, int64_t* cseg, hipStream_t st);
+// blk, rank, cu, cv: the chunk's first entry; t, t2: kmax entries per block
+hipError_t launch_np_t(const int4* blk, int64_t nbk, const int32_t* rank, const int64_t* cu,
+                       const int64_t* cv, int64_t ubase, int64_t vbase, const void* U,
+                       const void* V, const void* xm, int kmax, int sym, void* t, void* t2,
+                       int f64, hipStream_t st);
+// segments [s0, s0 + ns) of one chunk; blk, rank, cu, cv: the whole list
+hipError_t launch_np_apply(const int64_t* seg_start, const int32_t* seg_tile, int64_t s0,
+                           int64_t ns, const int2* spcs, const int4* blk, const int32_t* rank,
+                           const int64_t* cu, const int64_t* cv, int64_t ubase, int64_t vbase,
+                           int64_t b0, const void* U, const void* V, const void* t,
+                           const void* t2, int kmax, const int32_t* tile_lo,
+                           const int32_t* perm, double alpha, void* z, int max_tile, int f64,
+                           hipStream_t st);
+
 }  // namespace hmx

@@ -61,7 +61,8 @@ class hmx_params(C.Structure):
                 ("aca_only", C.c_int32), ("mlp", C.c_void_p),
                 ("learned_one_shot", C.c_int32), ("near_recompute", C.c_int32),
                 ("aca_split_rows", C.c_int32), ("symmetric_far", C.c_int32),
-                ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p)]
+                ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p),
+                ("far_recompute", C.c_int32)]
 
 
 class hmx_stats(C.Structure):

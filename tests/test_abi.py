@@ -37,9 +37,10 @@ def test_struct_layout_matches_c(tmp_path):
 #include "hmx.h"
 int main(void) {
   printf("%zu %zu %zu\\n", sizeof(hmx_params), sizeof(hmx_stats), sizeof(hmx_kernel));
-  printf("%zu %zu %zu %zu %zu %zu\\n", offsetof(hmx_params, max_rank), offsetof(hmx_params, sigma2),
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", offsetof(hmx_params, max_rank), offsetof(hmx_params, sigma2),
          offsetof(hmx_params, rank_mode), offsetof(hmx_params, symmetric_far),
-         offsetof(hmx_params, storage_dtype), offsetof(hmx_params, alloc_ctx));
+         offsetof(hmx_params, storage_dtype), offsetof(hmx_params, alloc_ctx),
+         offsetof(hmx_params, far_recompute));
   printf("%zu %zu %zu %zu\\n", offsetof(hmx_stats, matvec_bytes), offsetof(hmx_stats, device_bytes),
          offsetof(hmx_stats, level_sizes), offsetof(hmx_stats, v_entries));
   return 0;
@@ -53,6 +54,7 @@ int main(void) {
             hmx.hmx_params.max_rank.offset, hmx.hmx_params.sigma2.offset,
             hmx.hmx_params.rank_mode.offset, hmx.hmx_params.symmetric_far.offset,
             hmx.hmx_params.storage_dtype.offset, hmx.hmx_params.alloc_ctx.offset,
+            hmx.hmx_params.far_recompute.offset,
             hmx.hmx_stats.matvec_bytes.offset, hmx.hmx_stats.device_bytes.offset,
             hmx.hmx_stats.level_sizes.offset, hmx.hmx_stats.v_entries.offset]
     assert [int(v) for v in out] == want
@@ -86,10 +88,19 @@ def test_validation_before_device_work():
         assert L.hmx_build(dummy, 0, 10, 2, C.byref(K), C.byref(Q), None, C.byref(h)) == 1, field
         assert b"invalid params" in L.hmx_last_error()
     for field, val, msg in [("aca_split_rows", -1, b"aca_split_rows"),
-                            ("near_recompute", 2, b"near_recompute")]:
+                            ("near_recompute", 2, b"near_recompute"),
+                            ("far_recompute", 2, b"far_recompute")]:
         Q = hmx.hmx_params_default(**{field: val})
         assert L.hmx_build(dummy, 0, 10, 2, C.byref(K), C.byref(Q), None, C.byref(h)) == 1, field
         assert msg in L.hmx_last_error()
+    # no precomputation runs no ACA at build time: aca_only makes no sense with
+    # it, and the learned sizing (which sizes a stored build) is not offered
+    Q = hmx.hmx_params_default(far_recompute=1, aca_only=1)
+    assert L.hmx_build(dummy, 0, 10, 2, C.byref(K), C.byref(Q), None, C.byref(h)) == 1
+    assert b"aca_only" in L.hmx_last_error()
+    Q = hmx.hmx_params_default(far_recompute=1, rank_mode="learned", mlp=C.c_void_p(1))
+    assert L.hmx_build(dummy, 0, 10, 2, C.byref(K), C.byref(Q), None, C.byref(h)) == 5
+    assert b"far_recompute" in L.hmx_last_error()
     Q = hmx.hmx_params_default(compute_dtype=hmx.HMX_BF16)
     assert L.hmx_build(dummy, 0, 10, 2, C.byref(K), C.byref(Q), None, C.byref(h)) == 5
     Q = hmx.hmx_params_default(compute_dtype="f64", storage_dtype="bf16")
