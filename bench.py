@@ -275,6 +275,58 @@ def n22_full_path(torch, H, log, wl, pts_d, p0, mlp, eps=3e-3, M=10, nrows=1024)
     return out
 
 
+def np_leg(torch, H, log, n, d, kw, p0=1.0, reps=2, nrows=256, forms=("np", "p", "stored"),
+           points="halton", seed=0):
+    """Build and matvec times of the far field without precomputation (np: ACA
+    and near field recomputed in every product), with stored factors and a
+    recomputed near field (p: the paper's precomputed mode, whose dense blocks
+    are never stored) and with everything stored; the products' error on
+    sampled rows against an FP64 dense product (Gaussian exp(-r^2 / p0))."""
+    if points == "halton":
+        pts = synth.halton_points(n, d)
+    else:
+        pts = synth.uniform_points(n, d, seed)
+    dt = torch.float64 if kw.get("compute_dtype") == "f64" else torch.float32
+    pts_d = torch.from_numpy(pts).cuda().to(dt)
+    x = torch.from_numpy(synth.normal_vector(n, 7100)).cuda().to(dt)
+    z = torch.empty_like(x)
+    rows_d = torch.from_numpy(synth.sample_rows(n, nrows, 7101)).cuda()
+    ref = dense_rows_fp64(torch, pts_d, x, p0, rows_d)
+    out = {}
+    for form in forms:
+        extra = {"np": dict(far_recompute=1, near_recompute=1),
+                 "p": dict(near_recompute=1), "stored": {}}[form]
+        H.hmx_trim()
+        times = []
+        for rep in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hm = H.HMatrix(pts_d, "gaussian", p0, **kw, **extra)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            if rep + 1 < reps:
+                hm.close()
+        st = hm.stats()
+        mv = []
+        for rep in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            H.hmx_matvec(hm.h, x, z)
+            torch.cuda.synchronize()
+            mv.append(time.perf_counter() - t0)
+        err = (torch.linalg.norm(z.double()[rows_d] - ref) / torch.linalg.norm(ref)).item()
+        st2 = hm.stats()
+        out[form] = {"build_s_each": times, "build_s": min(times), "matvec_s_each": mv,
+                     "matvec_s": min(mv[1:]), "rel_err_rows": err, "n_adm": st.n_adm,
+                     "n_dense": st.n_dense, "sum_rank": st2.sum_rank, "aca_chunks": st.aca_chunks,
+                     "near_entries": st.near_entries, "device_bytes": st.device_bytes}
+        log("bench: N=%d d=%d %s: build %.3f s, matvec %.3f s, rel err %.2e, device %.2f GB, "
+            "%d chunks" % (n, d, form, min(times), min(mv[1:]), err, st.device_bytes / 1e9,
+                           st.aca_chunks))
+        hm.close()
+    return out
+
+
 def dense_rows_matern32(torch, pts_d, x_d, ell, rows_d):
     """z[rows] of the FP64 dense Matern-3/2 product (plain PyTorch on the GPU)."""
     P = pts_d.double()
@@ -533,6 +585,11 @@ def main():
     ap.add_argument("--krr", action="store_true",
                     help="also run kernel ridge regression at N = 2^22 (Gaussian-mixture points, "
                          "Matern-3/2, BF16, CG): about a minute")
+    ap.add_argument("--no-np", action="store_true",
+                    help="skip the paper's N = 2^19 workload with and without precomputation")
+    ap.add_argument("--np-large", action="store_true",
+                    help="also the product without precomputation at N = 2^25 (d = 2, the "
+                         "paper's largest) and N = 2^23 (d = 3): a few minutes")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the measured FP64 form (no predictor training, no other forms "
                          "or legs): the run the hardware counters are taken on")
@@ -785,6 +842,27 @@ def main():
     if args.krr:
         H.hmx_trim()
         out["krr_n4m"] = krr_leg(torch, H, log)
+    paper_kw = dict(compute_dtype="f64", leaf_size=2048, eta=1.5, aca_eps=0.0, max_rank=16,
+                    rank_mode="fixed")
+    paper_desc = ("Halton points in [0,1]^2, unscaled Gaussian exp(-r^2), C_leaf 2048, eta 1.5, "
+                  "fixed rank 16, FP64")
+    if not args.no_np:
+        out["paper_n512k"] = {
+            "workload": "N=2^19 " + paper_desc,
+            "paper_p100": {"setup_p_s": 1.3, "setup_np_s": 0.8, "matvec_p_s": 1.7,
+                           "matvec_np_s": 2.7},
+            **np_leg(torch, H, log, 1 << 19, 2, paper_kw)}
+    if args.np_large:
+        out["paper_n32m_np"] = {
+            "workload": "N=2^25 " + paper_desc, "paper_p100": {"matvec_np_s": 360.0},
+            **np_leg(torch, H, log, 1 << 25, 2, paper_kw, reps=1, forms=("np",))}
+        out["gauss3d_n8m_np"] = {
+            "workload": "N=2^23 uniform in [0,1]^3, gaussian p0=0.0145, leaf 64, eta 1.5, ACA eps "
+                        "1e-5, max rank 64, FP32, symmetric far field, nothing stored",
+            **np_leg(torch, H, log, 1 << 23, 3,
+                     dict(compute_dtype="f32", leaf_size=64, eta=1.5, aca_eps=1e-5, max_rank=64,
+                          symmetric_far=1),
+                     p0=0.0145, reps=1, forms=("np",), points="uniform", seed=51)}
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle on a row sample)")
         out["cpu_baseline"] = cpu_baseline(wl, pts, xs[0], z_f64_first, part_perm)

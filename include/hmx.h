@@ -364,9 +364,11 @@ hmx_status hmx_graph_destroy(hmx_graph g);
  * launch.  Host-blocking. */
 hmx_status hmx_autotune(hmx_hmatrix h, int32_t reps, void* stream, int32_t* choice,
                         double* times_ms);
-/* Select a row-tile configuration directly (-1: the default shape for the
- * handle's largest tile, and the default phase-1 lanes too, so a handle
- * returns to its untuned products). */
+/* Select a row-tile configuration directly (-1: the default, which is the
+ * narrowest shape covering the handle's largest tile in one pass on the
+ * one-workgroup-per-tile grid, or configuration 10 when the handle has fewer
+ * than 2048 tiles or evaluates its near field in the product; and the
+ * default phase-1 lanes too, so a handle returns to its untuned products). */
 hmx_status hmx_set_tile_config(hmx_hmatrix h, int32_t config);
 
 /* Conjugate gradients for (H + sigma2 I) c = b, the kernel ridge regression

@@ -101,7 +101,10 @@ def test_batched_f32_like_uneven_workload(H, orc):
         one.close()
         print("problem %2d: n %5d d %d p0 %.4f  batched err %.3e  single err %.3e"
               % (q, b - a, ds[q], p0s[q], err, erri))
-        assert err <= 1e-4 and err <= 3 * max(erri, 1e-7)
+        # below 1e-6 both errors are FP32 rounding of the row sums, whose
+        # order depends on the row-tile grid (the batched handle and the
+        # single ones may use different default grids)
+        assert err <= 1e-4 and err <= 3 * max(erri, 1e-6)
     hm.close()
 
 
