@@ -1173,6 +1173,10 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
     // row factor (its U_b; with the symmetric far field a mirror's row factor
     // is its primary's V), vfo[b]: offset of V_b (approximated leaves)
     DevBuf F, rfo, vfo;
+    // the largest ACA chunk scratch, kept past the ACA: the near-field pool
+    // reuses it when it fits (new device memory that was used and released
+    // before is cleared by the driver on allocation, tens of GB per second)
+    DevBuf aca_keep;
     alloc(rfo, (h->n_adm + 1) * 8, "row factor offsets");
     alloc(vfo, (h->n_adm + 1) * 8, "V offsets");
     int nchunks = 0;
@@ -1263,7 +1267,7 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                         const int32_t* rt, int one_shot, int cap_only, int32_t* rank,
                         int32_t* steps, int64_t* ue_all, int64_t* ve_all,
                         const std::vector<int64_t>* bounds) {
-            DevBuf cu, cv, cc, Ucap, Vcap;
+            DevBuf cu, cv, cc, Ucap;
             alloc(cu, (nb + 1) * 8, "U capacity offsets");
             alloc(cv, (nb + 1) * 8, "V capacity offsets");
             alloc(cc, (nb + 1) * 8, "capacity offsets");
@@ -1316,8 +1320,14 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                 cap_only ? std::max<int64_t>(std::max(max_u, max_v) / 16,
                                              2 * std::min(h->big_adm, split_rows(h)) * kmax)
                          : 0;
-            alloc(Ucap, (size_t)std::max<int64_t>(max_u + ovf_cap, 1) * esz, "U chunk scratch");
-            alloc(Vcap, (size_t)std::max<int64_t>(max_v + ovf_cap, 1) * esz, "V chunk scratch");
+            // U and V scratch in one block: a single large block can serve
+            // the near-field pool once the ACA is done (the cache reuses a
+            // block for requests of 3/4 of its size or more), so that pool
+            // takes no new device memory, which the driver would clear first
+            const int64_t ucols = (std::max<int64_t>(max_u + ovf_cap, 1) + 63) / 64 * 64;
+            alloc(Ucap, (size_t)(ucols + std::max<int64_t>(max_v + ovf_cap, 1)) * esz,
+                  "ACA chunk scratch");
+            void* const vcap = (char*)Ucap.p + (size_t)ucols * esz;
             DevBuf ovf_used, moved;
             if (cap_only) {
                 alloc(ovf_used, 8, "overflow counter");
@@ -1325,7 +1335,7 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                 check(hipMemsetAsync(moved.p, 0xff, (size_t)nb * 8, st), "overflow offsets");
             }
             a.U = Ucap.p;
-            a.V = Vcap.p;
+            a.V = vcap;
             a.one_shot = one_shot;
             a.cap_only = cap_only;
             a.ovf_used = cap_only ? ovf_used.as<unsigned long long>() : nullptr;
@@ -1394,12 +1404,13 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                 check(launch_compact_u(a.blocks, nbk, a.rank, a.uoff, a.ubase, ue, Ucap.p, F.p,
                                        smode, st),
                       "compact U");
-                check(launch_compact_v(a.blocks, nbk, a.rank, a.voff, a.vbase, ve, Vcap.p, F.p,
+                check(launch_compact_v(a.blocks, nbk, a.rank, a.voff, a.vbase, ve, vcap, F.p,
                                        smode, st),
                       "compact V");
                 check(hipStreamSynchronize(st), "compact sync");
                 ftot += uk + vk;
             }
+            if (!aca_only && Ucap.bytes > aca_keep.bytes) aca_keep.swap(Ucap);
         };
 
         // The level-ordered list cut into chunks by capacity would give each
@@ -1637,8 +1648,28 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
                                h->tile_meta.as<int64_t>(), st),
               "tile meta");
         // the factor rows first; the near field's pool is allocated once the
-        // exact-rank factors are released (the two never coexist)
-        alloc(h->upool, (size_t)std::max<int64_t>(h->upool_entries, 1) * ssz, "factor pool");
+        // exact-rank factors are released (the two never coexist).  It takes
+        // over the kept ACA scratch when that block fits it (a block serves
+        // requests of 3/4 of its size or more) and the factor rows still fit
+        // in the free memory beside it; otherwise the scratch returns to the
+        // cache now, where it can serve the factor rows or be released.
+        const size_t near_bytes =
+            h->nmode == 3 ? 0 : (size_t)std::max<int64_t>(h->npool_entries, 1) * h->nsz;
+        const size_t ubytes = (size_t)std::max<int64_t>(h->upool_entries, 1) * ssz;
+        bool keep = aca_keep.p && near_bytes > 0 && aca_keep.bytes >= near_bytes &&
+                    aca_keep.bytes / 4 * 3 <= near_bytes;
+        if (keep && !aca_keep.from.alloc) {
+            size_t fr = 0, tot = 0;
+            check(hipMemGetInfo(&fr, &tot), "memory info");
+            size_t cached = 0;
+            {
+                std::lock_guard<std::mutex> lk(cache().mu);
+                cached = cache().cached;
+            }
+            keep = fr + cached >= ubytes + ((size_t)4 << 30);
+        }
+        if (!keep) aca_keep.release();
+        alloc(h->upool, ubytes, "factor pool");
         check(launch_piece_data(h->pieces.as<Piece>(), h->npieces, h->tile_lo.as<int32_t>(),
                                 h->adm.as<int4>(), h->dense.as<int4>(), rfo.as<int64_t>(), F.p,
                                 f64 ? h->soa64.p : h->soa32.p, n, d,
@@ -1734,7 +1765,11 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
         }
         check(hipStreamSynchronize(st), "pool sync");
         F.release();
-        alloc(h->npool, (size_t)std::max<int64_t>(h->npool_entries, 1) * h->nsz, "near-field pool");
+        if (keep)
+            h->npool.swap(aca_keep);
+        else
+            alloc(h->npool, (size_t)std::max<int64_t>(h->npool_entries, 1) * h->nsz,
+                  "near-field pool");
         if (h->nmode != 3)
             check(launch_piece_data(h->pieces.as<Piece>(), h->npieces, h->tile_lo.as<int32_t>(),
                                     h->adm.as<int4>(), h->dense.as<int4>(), nullptr, nullptr,
@@ -2224,9 +2259,10 @@ void np_matvec(hmx_hmatrix_s* h, const void* x, void* z, double alpha, double be
         plan.big_words = P.big_words;
         plan.med_words = P.med_words;
         plan.tiny_words = P.tiny_words;
-        DevBuf Ucap, Vcap, tb, t2b;
-        alloc(Ucap, (size_t)std::max<int64_t>(P.max_u, 1) * esz, "U chunk scratch");
-        alloc(Vcap, (size_t)std::max<int64_t>(P.max_v, 1) * esz, "V chunk scratch");
+        DevBuf Ucap, tb, t2b;
+        const int64_t ucols = (std::max<int64_t>(P.max_u, 1) + 63) / 64 * 64;
+        alloc(Ucap, (size_t)(ucols + std::max<int64_t>(P.max_v, 1)) * esz, "ACA chunk scratch");
+        void* const vcap = (char*)Ucap.p + (size_t)ucols * esz;
         alloc(tb, (size_t)std::max<int64_t>(P.max_nb, 1) * kmax * esz, "chunk t");
         if (h->sym) alloc(t2b, (size_t)std::max<int64_t>(P.max_nb, 1) * kmax * esz, "chunk t'");
         AuxStream auxs[3];
@@ -2234,7 +2270,7 @@ void np_matvec(hmx_hmatrix_s* h, const void* x, void* z, double alpha, double be
         const bool have_aux = aux[0] && aux[1] && aux[2];
         AcaArgs a = aca_args_base(h, plan);
         a.U = Ucap.p;
-        a.V = Vcap.p;
+        a.V = vcap;
         const int4* B = P.blocks.as<int4>();
         const int64_t* cu = P.cu.as<int64_t>();
         const int64_t* cv = P.cv.as<int64_t>();
@@ -2261,12 +2297,12 @@ void np_matvec(hmx_hmatrix_s* h, const void* x, void* z, double alpha, double be
                 check(launch_aca_split(a, sb.P, f64, st), "aca (many workgroups per block)");
             check(aca_classes_join(st, have_aux ? aux : nullptr), "aca join");
             check(launch_np_t(B + b0, nbk, rank + b0, cu + b0, cv + b0, P.hcu[k], P.hcv[k], Ucap.p,
-                              Vcap.p, h->vecpool.p, kmax, h->sym, tb.p, h->sym ? t2b.p : nullptr,
+                              vcap, h->vecpool.p, kmax, h->sym, tb.p, h->sym ? t2b.p : nullptr,
                               f64, st),
                   "far field t");
             check(launch_np_apply(P.seg_start.as<int64_t>(), P.seg_tile.as<int32_t>(), P.cseg[k],
                                   P.cseg[k + 1] - P.cseg[k], P.spcs.as<int2>(), B, rank, cu, cv,
-                                  P.hcu[k], P.hcv[k], b0, Ucap.p, Vcap.p, tb.p,
+                                  P.hcu[k], P.hcv[k], b0, Ucap.p, vcap, tb.p,
                                   h->sym ? t2b.p : nullptr, kmax, h->tile_lo.as<int32_t>(),
                                   h->perm.as<int32_t>(), alpha, z, h->max_tile, f64, st),
                   "far field apply");
