@@ -69,6 +69,11 @@ def lib():
         L.hmxo_hmvp_ex.argtypes = [P, i64, i32, i32, f64, i32, f64, i32, f64, f64, f64, i32, i32,
                                    f64, f64, f64, P, P, i64, P, P]
         L.hmxo_dense_matvec.argtypes = [P, i64, i32, i32, f64, f64, P, P, i64, P]
+        L.hmxo_dense_matvec_rect.argtypes = [P, i64, P, i64, i32, i32, f64, P, P]
+        L.hmxo_partition_rect.argtypes = [P, i64, P, i64, i32, i32, f64, i64, P, P, i64, P, P,
+                                          P, P]
+        L.hmxo_hmvp_rect.argtypes = [P, i64, P, i64, i32, i32, f64, i32, f64, i32, f64, f64, f64,
+                                     i32, f64, f64, P, P, i64, P, P]
         L.hmxo_dense_block.argtypes = [P, i64, i32, i32, f64, i64, i64, i64, i64, P]
         L.hmxo_hmvp_rows.argtypes = [P, i64, i32, i32, f64, i32, f64, i32, f64, f64, f64, i32,
                                      i64, i64, P, P, P, P]
@@ -286,6 +291,63 @@ def dense_matvec(pts, x, kind, p0, sigma2=0.0, rows=None):
         lib().hmxo_dense_matvec(_p(pts), n, d, kind_of(kind), float(p0), float(sigma2), _p(x),
                                 _p(rows), rows.shape[0], _p(z))
     return z
+
+
+def dense_matvec_rect(pts1, pts2, x, kind, p0):
+    """z = A_{Y1 x Y2} x, the plain dense product (x: n2 entries, z: n1)."""
+    pts1, pts2, x = _f64(pts1), _f64(pts2), _f64(x)
+    n1, d = pts1.shape
+    n2 = pts2.shape[0]
+    z = np.empty(n1)
+    lib().hmxo_dense_matvec_rect(_p(pts1), n1, _p(pts2), n2, d, kind_of(kind), float(p0), _p(x),
+                                 _p(z))
+    return z
+
+
+def partition_rect(soa1, soa2, leaf, eta):
+    """Leaves of A(Y1 x Y2) from the two sets' ordered coordinates: (adm,
+    dense, level_sizes), rows in Y1's Morton order, columns in Y2's."""
+    soa1, soa2 = _f64(soa1), _f64(soa2)
+    d, n1 = soa1.shape
+    n2 = soa2.shape[1]
+    na, nd = C.c_int64(0), C.c_int64(0)
+    ls = np.zeros(64, np.int64)
+    nl = C.c_int32(0)
+    cap_a = cap_d = 1024
+    while True:
+        adm = np.empty((cap_a, 5), np.int32)
+        den = np.empty((cap_d, 5), np.int32)
+        rc = lib().hmxo_partition_rect(_p(soa1), n1, _p(soa2), n2, d, int(leaf), float(eta),
+                                       cap_a, _p(adm), C.byref(na), cap_d, _p(den), C.byref(nd),
+                                       _p(ls), C.byref(nl))
+        if rc < 0:
+            raise ValueError("hmxo_partition_rect failed: %d" % rc)
+        if rc == 0:
+            return adm[: na.value].copy(), den[: nd.value].copy(), ls[: nl.value].copy()
+        cap_a, cap_d = max(cap_a, na.value), max(cap_d, nd.value)
+
+
+def hmvp_rect(pts1, pts2, x, kind, p0, leaf, eta, kmax, eps, aca_eta=0.0, eps0=1e-14,
+              fixed=False, alpha=1.0, beta=0.0, z=None, want_ranks=False):
+    """z = alpha H x + beta z for A(Y1 x Y2); returns (z, ranks or None, stats)."""
+    pts1, pts2, x = _f64(pts1), _f64(pts2), _f64(x)
+    n1, d = pts1.shape
+    n2 = pts2.shape[0]
+    zz = _f64(z).copy() if z is not None else np.zeros(n1)
+    stats = np.zeros(8)
+    cap = (1 << 22) if want_ranks else 0
+    ranks = np.zeros(cap, np.int32) if want_ranks else None
+    rc = lib().hmxo_hmvp_rect(_p(pts1), n1, _p(pts2), n2, d, kind_of(kind), float(p0), int(leaf),
+                              float(eta), int(kmax), float(eps), float(aca_eta), float(eps0),
+                              int(bool(fixed)), float(alpha), float(beta), _p(x), _p(zz), cap,
+                              _p(ranks), _p(stats))
+    if rc != 0:
+        raise ValueError("hmxo_hmvp_rect failed: %d" % rc)
+    st = dict(n_adm=int(stats[0]), n_dense=int(stats[1]), sum_rank=int(stats[2]),
+              dense_entries=int(stats[3]), factor_entries=int(stats[4]), levels=int(stats[5]))
+    if ranks is not None:
+        ranks = ranks[: st["n_adm"]].copy()
+    return zz, ranks, st
 
 
 def hmvp_rows(pts, x, kind, p0, leaf, eta, kmax, eps, row_lo, row_hi, aca_eta=0.0, eps0=1e-14,

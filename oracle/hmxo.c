@@ -385,7 +385,10 @@ static void part_free(partition* P)
     free(P->dense_level);
 }
 
-static int part_make(partition* P, const ctree* T, int32_t d, int32_t leaf, double eta)
+/* T1: the row tree (tau), T2: the column tree (sigma); a square matrix
+ * passes one tree twice */
+static int part_make2(partition* P, const ctree* T1, const ctree* T2, int32_t d, int32_t leaf,
+                      double eta)
 {
     memset(P, 0, sizeof(*P));
     pairlist cur = {0, 0, NULL}, nxt = {0, 0, NULL};
@@ -398,9 +401,9 @@ static int part_make(partition* P, const ctree* T, int32_t d, int32_t leaf, doub
         nxt.n = 0;
         for (int64_t q = 0; q < cur.n; ++q) {
             int64_t t = cur.a[2 * q], s = cur.a[2 * q + 1];
-            int64_t mt = T->hi[t] - T->lo[t], ms = T->hi[s] - T->lo[s];
-            if (hmxo_admissible(T->bmin + t * d, T->bmax + t * d, T->bmin + s * d,
-                                T->bmax + s * d, d, eta)) {
+            int64_t mt = T1->hi[t] - T1->lo[t], ms = T2->hi[s] - T2->lo[s];
+            if (hmxo_admissible(T1->bmin + t * d, T1->bmax + t * d, T2->bmin + s * d,
+                                T2->bmax + s * d, d, eta)) {
                 pl_push(&P->adm, t, s);
                 if (P->adm.n > acap) {
                     acap = P->adm.cap;
@@ -410,7 +413,7 @@ static int part_make(partition* P, const ctree* T, int32_t d, int32_t leaf, doub
             } else if (mt > leaf && ms > leaf) {
                 /* children in the loop order of Algorithm 1: tau' outer, sigma' inner */
                 for (int a = 0; a < 2; ++a)
-                    for (int b = 0; b < 2; ++b) pl_push(&nxt, T->child0[t] + a, T->child0[s] + b);
+                    for (int b = 0; b < 2; ++b) pl_push(&nxt, T1->child0[t] + a, T2->child0[s] + b);
             } else {
                 pl_push(&P->dense, t, s);
                 if (P->dense.n > dcap) {
@@ -430,6 +433,11 @@ static int part_make(partition* P, const ctree* T, int32_t d, int32_t leaf, doub
     free(cur.a);
     free(nxt.a);
     return 0;
+}
+
+static int part_make(partition* P, const ctree* T, int32_t d, int32_t leaf, double eta)
+{
+    return part_make2(P, T, T, d, leaf, eta);
 }
 
 int hmxo_partition(const double* soa, int64_t n, int32_t d, int32_t leaf, double eta,
@@ -869,6 +877,181 @@ int hmxo_dense_matmat(const double* pts, int64_t n, int32_t d, int32_t kind, dou
         }
         for (int c = 0; c < m; ++c) Z[q * m + c] = acc[c] + sigma2 * X[i * m + c];
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rectangular A_{phi, Y1 x Y2} (the kernel matrix between two point sets,  */
+/* Section 6): each set ordered by its own Morton codes (Algorithm 6 in its */
+/* own bounding box) and clustered in its own tree; Algorithm 1 from the    */
+/* single block Y1 x Y2 with eq. (3).  Leaves report rows in Y1's Morton    */
+/* order and columns in Y2's.                                               */
+/* ------------------------------------------------------------------------ */
+
+/* z = A_{Y1 x Y2} x, the plain dense product (x: n2 entries, z: n1) */
+int hmxo_dense_matvec_rect(const double* pts1, int64_t n1, const double* pts2, int64_t n2,
+                           int32_t d, int32_t kind, double p0, const double* x, double* z)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n1; ++i) {
+        double acc = 0.0;
+        for (int64_t j = 0; j < n2; ++j)
+            acc += hmxo_kernel(kind, p0, pts1 + i * d, pts2 + j * d, d) * x[j];
+        z[i] = acc;
+    }
+    return 0;
+}
+
+int hmxo_partition_rect(const double* soa1, int64_t n1, const double* soa2, int64_t n2,
+                        int32_t d, int32_t leaf, double eta, int64_t cap_adm, int32_t* adm,
+                        int64_t* n_adm, int64_t cap_dense, int32_t* dense, int64_t* n_dense,
+                        int64_t* level_sizes, int32_t* n_levels)
+{
+    if (n1 < 1 || n2 < 1 || d < 1 || d > 3 || leaf < 1 || !(eta >= 0.0)) return -1;
+    ctree T1, T2;
+    if (ctree_make(&T1, soa1, n1, d, leaf) || ctree_make(&T2, soa2, n2, d, leaf)) return -2;
+    partition P;
+    if (part_make2(&P, &T1, &T2, d, leaf, eta)) return -3;
+    *n_adm = P.adm.n;
+    *n_dense = P.dense.n;
+    *n_levels = P.nlev;
+    for (int l = 0; l < P.nlev; ++l) level_sizes[l] = P.level_sizes[l];
+    int rc = (P.adm.n > cap_adm || P.dense.n > cap_dense) ? 1 : 0;
+    for (int k = 0; rc == 0 && k < 2; ++k) {
+        const pairlist* L = k ? &P.dense : &P.adm;
+        const int64_t* lev = k ? P.dense_level : P.adm_level;
+        int32_t* out = k ? dense : adm;
+        for (int64_t q = 0; q < L->n; ++q) {
+            int64_t t = L->a[2 * q], s = L->a[2 * q + 1];
+            int32_t* o = out + 5 * q;
+            o[0] = T1.lo[t];
+            o[1] = T1.hi[t];
+            o[2] = T2.lo[s];
+            o[3] = T2.hi[s];
+            o[4] = (int32_t)lev[q];
+        }
+    }
+    part_free(&P);
+    ctree_free(&T1);
+    ctree_free(&T2);
+    return rc;
+}
+
+/* z = alpha H x + beta z for the H-matrix of A_{Y1 x Y2} (x: n2 entries in
+ * Y2's original order, z: n1 in Y1's); the ACA runs on the union of the two
+ * ordered sets (rows first, columns after them), each block as in
+ * hmxo_hmvp_ex */
+int hmxo_hmvp_rect(const double* pts1, int64_t n1, const double* pts2, int64_t n2, int32_t d,
+                   int32_t kind, double p0, int32_t leaf, double eta, int32_t kmax, double eps,
+                   double aca_eta, double eps0, int32_t fixed, double alpha, double beta,
+                   const double* x, double* z, int64_t ranks_cap, int32_t* ranks, double* stats)
+{
+    if (n1 < 1 || n2 < 1 || d < 1 || d > 3 || leaf < 1 || !(eta >= 0.0) || kmax < 1) return -1;
+    const int64_t nu = n1 + n2;
+    double lo1[3], hi1[3], lo2[3], hi2[3];
+    hmxo_global_box(pts1, n1, d, lo1, hi1);
+    hmxo_global_box(pts2, n2, d, lo2, hi2);
+    uint64_t* c1 = (uint64_t*)malloc(sizeof(uint64_t) * n1);
+    uint64_t* c2 = (uint64_t*)malloc(sizeof(uint64_t) * n2);
+    int32_t* perm1 = (int32_t*)malloc(sizeof(int32_t) * n1);
+    int32_t* perm2 = (int32_t*)malloc(sizeof(int32_t) * n2);
+    double* soa1 = (double*)malloc(sizeof(double) * n1 * d);
+    double* soa2 = (double*)malloc(sizeof(double) * n2 * d);
+    double* soa = (double*)malloc(sizeof(double) * nu * d);
+    double* xm = (double*)malloc(sizeof(double) * n2);
+    double* zm = (double*)calloc((size_t)n1, sizeof(double));
+    if (!c1 || !c2 || !perm1 || !perm2 || !soa1 || !soa2 || !soa || !xm || !zm) return -2;
+    hmxo_morton(pts1, n1, d, lo1, hi1, c1);
+    hmxo_morton(pts2, n2, d, lo2, hi2, c2);
+    hmxo_sort(c1, n1, perm1);
+    hmxo_sort(c2, n2, perm2);
+    hmxo_ordered_coords(pts1, n1, d, perm1, soa1);
+    hmxo_ordered_coords(pts2, n2, d, perm2, soa2);
+    for (int k = 0; k < d; ++k) {
+        memcpy(soa + (int64_t)k * nu, soa1 + (int64_t)k * n1, sizeof(double) * n1);
+        memcpy(soa + (int64_t)k * nu + n1, soa2 + (int64_t)k * n2, sizeof(double) * n2);
+    }
+    for (int64_t j = 0; j < n2; ++j) xm[j] = x[perm2[j]];
+
+    ctree T1, T2;
+    if (ctree_make(&T1, soa1, n1, d, leaf) || ctree_make(&T2, soa2, n2, d, leaf)) return -2;
+    partition P;
+    if (part_make2(&P, &T1, &T2, d, leaf, eta)) return -3;
+
+    double sum_rank = 0.0, dense_entries = 0.0, factor_entries = 0.0;
+    int nthr = hmxo_num_threads();
+    double* zpriv = (double*)calloc((size_t)nthr * (size_t)n1, sizeof(double));
+    if (!zpriv) return -2;
+#pragma omp parallel reduction(+ : sum_rank, dense_entries, factor_entries)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double* zt = zpriv + (int64_t)tid * n1;
+#pragma omp for schedule(dynamic, 1) nowait
+        for (int64_t q = 0; q < P.adm.n; ++q) {
+            int64_t t = P.adm.a[2 * q], s = P.adm.a[2 * q + 1];
+            int64_t tlo = T1.lo[t], thi = T1.hi[t], slo = T2.lo[s], shi = T2.hi[s];
+            int64_t m = thi - tlo, nc = shi - slo;
+            double* U = (double*)malloc(sizeof(double) * m * kmax);
+            double* V = (double*)malloc(sizeof(double) * nc * kmax);
+            int32_t rk = 0;
+            hmxo_aca(soa, nu, d, kind, p0, tlo, thi, n1 + slo, n1 + shi, kmax, eps, aca_eta,
+                     eps0, fixed, 0, U, V, &rk, NULL);
+            if (ranks && q < ranks_cap) ranks[q] = rk;
+            for (int64_t l = 0; l < rk; ++l) {
+                double tl = 0.0;
+                for (int64_t jj = 0; jj < nc; ++jj) tl += V[l * nc + jj] * xm[slo + jj];
+                for (int64_t i = 0; i < m; ++i) zt[tlo + i] += U[l * m + i] * tl;
+            }
+            sum_rank += rk;
+            factor_entries += (double)rk * (double)(m + nc);
+            free(U);
+            free(V);
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t q = 0; q < P.dense.n; ++q) {
+            int64_t t = P.dense.a[2 * q], s = P.dense.a[2 * q + 1];
+            int64_t tlo = T1.lo[t], thi = T1.hi[t], slo = T2.lo[s], shi = T2.hi[s];
+            for (int64_t i = tlo; i < thi; ++i) {
+                double acc = 0.0;
+                for (int64_t jj = slo; jj < shi; ++jj)
+                    acc += entry(soa, nu, d, kind, p0, i, n1 + jj) * xm[jj];
+                zt[i] += acc;
+            }
+            dense_entries += (double)(thi - tlo) * (double)(shi - slo);
+        }
+    }
+    for (int th = 0; th < nthr; ++th)
+        for (int64_t k = 0; k < n1; ++k) zm[k] += zpriv[(int64_t)th * n1 + k];
+    for (int64_t k = 0; k < n1; ++k) {
+        int64_t p = perm1[k];
+        z[p] = alpha * zm[k] + (beta != 0.0 ? beta * z[p] : 0.0);
+    }
+    if (stats) {
+        stats[0] = (double)P.adm.n;
+        stats[1] = (double)P.dense.n;
+        stats[2] = sum_rank;
+        stats[3] = dense_entries;
+        stats[4] = factor_entries;
+        stats[5] = (double)P.nlev;
+        stats[6] = 0.0;
+        stats[7] = 0.0;
+    }
+    free(zpriv);
+    part_free(&P);
+    ctree_free(&T1);
+    ctree_free(&T2);
+    free(c1);
+    free(c2);
+    free(perm1);
+    free(perm2);
+    free(soa1);
+    free(soa2);
+    free(soa);
+    free(xm);
+    free(zm);
     return 0;
 }
 

@@ -111,6 +111,24 @@ int hmxo_hmvp_ex(const double* pts, int64_t n, int32_t d, int32_t kind, double p
                  double beta, const double* x, double* z, int64_t ranks_cap, int32_t* ranks,
                  double* stats);
 
+/* Rectangular A_{phi, Y1 x Y2} (two point sets, Section 6): each set ordered
+ * by its own Morton codes and clustered in its own tree, Algorithm 1 from the
+ * block Y1 x Y2.  hmxo_partition_rect: leaves (tlo, thi, slo, shi, level)
+ * with rows in Y1's Morton order and columns in Y2's (soa1, soa2: the sets'
+ * ordered coordinates), return codes as hmxo_partition.  hmxo_hmvp_rect:
+ * z = alpha H x + beta z, x (n2) in Y2's original order, z (n1) in Y1's.
+ * hmxo_dense_matvec_rect: z = A x, the plain dense product. */
+int hmxo_dense_matvec_rect(const double* pts1, int64_t n1, const double* pts2, int64_t n2,
+                           int32_t d, int32_t kind, double p0, const double* x, double* z);
+int hmxo_partition_rect(const double* soa1, int64_t n1, const double* soa2, int64_t n2,
+                        int32_t d, int32_t leaf, double eta, int64_t cap_adm, int32_t* adm,
+                        int64_t* n_adm, int64_t cap_dense, int32_t* dense, int64_t* n_dense,
+                        int64_t* level_sizes, int32_t* n_levels);
+int hmxo_hmvp_rect(const double* pts1, int64_t n1, const double* pts2, int64_t n2, int32_t d,
+                   int32_t kind, double p0, int32_t leaf, double eta, int32_t kmax, double eps,
+                   double aca_eta, double eps0, int32_t fixed, double alpha, double beta,
+                   const double* x, double* z, int64_t ranks_cap, int32_t* ranks, double* stats);
+
 /* Stored-mode product restricted to the Morton-order rows [row_lo, row_hi):
  * the leaves whose tau meets the range are built (ACA / dense entries),
  * stored and applied; z gets (H x) for those rows in Morton order (no shift).
