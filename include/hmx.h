@@ -257,6 +257,8 @@ typedef struct {
     double aca_flops;         /* ACA multiply-add flops: sum of
                                  2 rank (rank - 1) (m + n) (residual updates
                                  and the norm recursion's inner products) */
+    int64_t rows, cols;       /* the matrix's shape: n x n, or n1 x n2 for
+                                 hmx_build_rect */
 } hmx_stats;
 
 /* Fill *p with the defaults: leaf 256, eta 1.5, eps 1e-5, aca_eta 0,
@@ -303,15 +305,41 @@ hmx_status hmx_build_batched(int32_t nprob, const void* const* points, hmx_dtype
                              const int64_t* n, const int32_t* d, const hmx_kernel* kernels,
                              const hmx_params* params, void* stream, hmx_hmatrix* out);
 
-/* Problems of a handle: *nprob (1 for hmx_build) and, if offsets != NULL
- * (host, nprob + 1 entries), each problem's first index and the total. */
+/* Rectangular H-matrix of A_{phi, Y1 x Y2} = [phi(y_i, y'_j)] for two point
+ * sets (Section 6: the library's problem is the kernel matrix between sets
+ * Y1 and Y2): rows Y1 (n1 points), columns Y2 (n2 points), both
+ * d-dimensional (n x d row-major device arrays in pts_dtype).  Each set is
+ * ordered by its own Morton codes (Algorithm 6 relative to its own bounding
+ * box) and clustered in its own tree (Section 2.1); the block cluster tree
+ * starts from the single block Y1 x Y2 and follows Algorithm 1 with eq. (3)
+ * (a block splits into 4 when it is not admissible and both clusters hold
+ * more than leaf_size points).  ACA, near field, matvec, NP mode and the
+ * autotuner work as for hmx_build; the matvec maps x (n2 entries, Y2's
+ * order) to z (n1 entries, Y1's order).  Internally the two sets are one
+ * union of n1 + n2 points (Y2 after Y1), their coordinates divided by the
+ * kernel length and padded to 3 dimensions, so entries may differ from a
+ * direct evaluation in the last bits.  hmx_get_partition reports union
+ * indices (columns offset by n1) and hmx_get_batch the two sets as two
+ * problems.  Kernels: Gaussian, Matern-3/2, Matern nu = 1.  params.sigma2
+ * must be 0 and symmetric_far 0 (INVALID_ARG); hmx_cg_solve and
+ * hmx_cg_solve_noalloc return UNSUPPORTED; hmx_get_boxes, hmx_block_features
+ * and hmx_rank_predict return UNSUPPORTED.  Limits: n1 + n2 < 2^31.
+ * Host-blocking like hmx_build. */
+hmx_status hmx_build_rect(const void* rows, int64_t n1, const void* cols, int64_t n2,
+                          hmx_dtype pts_dtype, int32_t d, const hmx_kernel* kernel,
+                          const hmx_params* params, void* stream, hmx_hmatrix* out);
+
+/* Problems of a handle: *nprob (1 for hmx_build, 2 for hmx_build_rect) and,
+ * if offsets != NULL (host, nprob + 1 entries), each problem's first index
+ * and the total. */
 hmx_status hmx_get_batch(hmx_hmatrix h, int32_t* nprob, int64_t* offsets);
 
 /* z := alpha (H + sigma2 I) x + beta z in the ORIGINAL point order
  * (Algorithm 3; x is permuted to Morton order and z back, Section 5.1).
- *   x, z : device vectors of n entries in vec_dtype, which must equal the
- *          handle's compute dtype (F32 for BF16 storage).  x and z must not
- *          overlap.
+ *   x, z : device vectors in vec_dtype, which must equal the handle's
+ *          compute dtype (F32 for BF16 storage): x of stats.cols and z of
+ *          stats.rows entries (both n, except for hmx_build_rect).  x and z
+ *          must not overlap.
  * Fully asynchronous on `stream`; allocates nothing. */
 hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype, double alpha,
                       double beta, void* stream);

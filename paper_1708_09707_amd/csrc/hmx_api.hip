@@ -368,6 +368,12 @@ struct hmx_hmatrix_s {
     DevBuf partner, vpieces, vtpool, vt_meta, p1rec, pfc, partial;
     int far_np = 0;  // factors recomputed by every matvec
     NpPlan np;
+    // rectangular A(Y1 x Y2): the union holds Y1 (rows, [0, nrows)) then Y2
+    // (columns, [col0, col0 + ncols)); the row tiles are Y1's leaf clusters,
+    // the first ntiles_rows tiles.  Square handles: rows = columns = [0, n).
+    bool rect = false;
+    int64_t nrows = 0, ncols = 0, col0 = 0, ntiles_rows = 0;
+    int kd = 0;  // the points' dimension for the kernel's normalisation
     hmx_stats stats{};
     // matvec phase tracing (hmx_profile_begin / end)
     std::vector<hipEvent_t> prof_events;
@@ -413,6 +419,8 @@ void finish_stats(hmx_hmatrix_s* h, std::chrono::steady_clock::time_point t_all)
     S.entry_bytes = (int32_t)ssz;
     S.near_entry_bytes = (int32_t)h->nsz;
     S.tile_config = h->rt_config;
+    S.rows = h->nrows;
+    S.cols = h->ncols;
     S.phase_ms[7] = ms_since(t_all);
     // algorithmic bytes of one matvec with beta = 0: the near field once,
     // U_b and V_b of every admissible leaf once (with the symmetric far
@@ -486,6 +494,8 @@ void init_handle(hmx_hmatrix_s* h, int64_t n, int d, const hmx_kernel& k, const 
     }
     h->sym = p.symmetric_far;
     h->far_np = p.far_recompute;
+    h->nrows = h->ncols = n;
+    h->kd = d;
 }
 
 // validation shared by the single and the batched build
@@ -649,6 +659,7 @@ void stage_partition(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t
                                      cnt.as<int64_t>(), scratch.p, st),
               "tile scan");
         h->ntiles = read_scalar(cnt.as<int64_t>(), st);
+        h->ntiles_rows = h->ntiles;
     }
     {
         // largest leaf cluster = largest tile
@@ -959,7 +970,7 @@ AcaArgs aca_args_base(const hmx_hmatrix_s* h, const AcaPlan& plan) {
     a.soa64 = h->soa64.as<double>();
     a.n = h->n;
     a.d = h->d;
-    a.kern = kernel_fn(h->kern, h->d);
+    a.kern = kernel_fn(h->kern, h->kd);
     a.kmax = h->prm.max_rank;
     a.eps = h->prm.aca_eps;
     a.aca_eta = h->prm.aca_eta;
@@ -1673,7 +1684,7 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
         check(launch_piece_data(h->pieces.as<Piece>(), h->npieces, h->tile_lo.as<int32_t>(),
                                 h->adm.as<int4>(), h->dense.as<int4>(), rfo.as<int64_t>(), F.p,
                                 f64 ? h->soa64.p : h->soa32.p, n, d,
-                                kernel_fn(h->kern, h->d), h->upool.p, nullptr, smode, h->nmode, 1,
+                                kernel_fn(h->kern, h->kd), h->upool.p, nullptr, smode, h->nmode, 1,
                                 st),
               "piece data (factors)");
         h->Ru = R;
@@ -1774,7 +1785,7 @@ void stage_factors(hmx_hmatrix_s* h, const AcaPlan& plan, hipStream_t st,
             check(launch_piece_data(h->pieces.as<Piece>(), h->npieces, h->tile_lo.as<int32_t>(),
                                     h->adm.as<int4>(), h->dense.as<int4>(), nullptr, nullptr,
                                     f64 ? h->soa64.p : h->soa32.p, n, d,
-                                    kernel_fn(h->kern, h->d), h->upool.p, h->npool.p, smode,
+                                    kernel_fn(h->kern, h->kd), h->upool.p, h->npool.p, smode,
                                     h->nmode, 2, st),
                   "piece data (near field)");
         check(hipStreamSynchronize(st), "near-field sync");
@@ -1826,7 +1837,8 @@ void build_impl(hmx_hmatrix_s* h, const void* pts, int pts_f64, hipStream_t st) 
 // union leaf lists hold them level by level, problem by problem within a
 // level, so each problem's leaves keep its canonical order.
 void stage_forest(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
-                  const int64_t* n, const int32_t* d, const hmx_kernel* kern, hipStream_t st) {
+                  const int64_t* n, const int32_t* d, const hmx_kernel* kern, hipStream_t st,
+                  bool cross = false) {
     using clk = std::chrono::steady_clock;
     const int64_t N = u->n;
     const int leaf = u->prm.leaf_size;
@@ -1967,6 +1979,12 @@ void stage_forest(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
                                      cnt.as<int64_t>(), scratch.p, st),
               "tile scan");
         u->ntiles = read_scalar(cnt.as<int64_t>(), st);
+        u->ntiles_rows = u->ntiles;
+        if (cross) {  // the row tiles: the leaf clusters of the first point set
+            std::vector<int32_t> tl(u->ntiles + 1);
+            d2h(tl.data(), u->tile_lo.p, tl.size() * 4, st);
+            u->ntiles_rows = std::lower_bound(tl.begin(), tl.end() - 1, (int32_t)n[0]) - tl.begin();
+        }
     }
     u->max_tile = 0;
     for (int p = 0; p < np; ++p) {
@@ -1982,14 +2000,19 @@ void stage_forest(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
         DevBuf sbase, cur, nxt, scratch, totals;
         alloc(sbase, nslots * 4, "slot bases");
         check(launch_forest_slot_base(NB, np, nslots, sbase.as<int32_t>(), st), "slot bases");
-        std::vector<int2> roots(np);
-        for (int p = 0; p < np; ++p) roots[p] = make_int2((int)nb[p], (int)nb[p]);
-        alloc(cur, (size_t)np * sizeof(int2), "level 0");
-        check(hipMemcpyAsync(cur.p, roots.data(), (size_t)np * sizeof(int2), hipMemcpyHostToDevice,
-                             st),
+        // one root block per problem, or (two point sets) the one block of
+        // the first set's root by the second set's root
+        std::vector<int2> roots;
+        if (cross)
+            roots.push_back(make_int2((int)nb[0], (int)nb[1]));
+        else
+            for (int p = 0; p < np; ++p) roots.push_back(make_int2((int)nb[p], (int)nb[p]));
+        alloc(cur, roots.size() * sizeof(int2), "level 0");
+        check(hipMemcpyAsync(cur.p, roots.data(), roots.size() * sizeof(int2),
+                             hipMemcpyHostToDevice, st),
               "roots");
         alloc(totals, 8 * sizeof(int64_t), "totals");
-        int64_t ncur = np;
+        int64_t ncur = (int64_t)roots.size();
         int level = 0;
         int64_t cap_adm = 0, cap_dense = 0;
         while (ncur > 0) {
@@ -2053,10 +2076,11 @@ void stage_forest(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
 }
 
 void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
-                  const int64_t* n, const int32_t* d, const hmx_kernel* kern, hipStream_t st) {
+                  const int64_t* n, const int32_t* d, const hmx_kernel* kern, hipStream_t st,
+                  bool cross = false) {
     const auto t_all = std::chrono::steady_clock::now();
     const bool learned = u->prm.rank_mode == HMX_RANK_LEARNED;
-    stage_forest(u, np, pts, pts_f64, n, d, kern, st);
+    stage_forest(u, np, pts, pts_f64, n, d, kern, st, cross);
     const int64_t nadm = u->n_adm;
     AcaPlan plan;
     DevBuf cls, rt;
@@ -2064,7 +2088,11 @@ void batched_impl(hmx_hmatrix_s* u, int np, const void* const* pts, int pts_f64,
         // size classes: each leaf's from its problem's level cuts; the leaves
         // stably grouped by class (each problem's leaves keep their order)
         std::vector<int4> cuts(np);
-        for (int p = 0; p < np; ++p) cuts[p] = level_cuts(n[p], split_rows(u), nullptr, nullptr, nullptr);
+        // (two point sets: a block's clusters at level l hold at most
+        // ceil(max(n_1, n_2) / 2^l) points on either side)
+        const int64_t nmax = cross ? std::max(n[0], n[1]) : 0;
+        for (int p = 0; p < np; ++p)
+            cuts[p] = level_cuts(cross ? nmax : n[p], split_rows(u), nullptr, nullptr, nullptr);
         std::vector<int64_t> pb(u->offsets);
         DevBuf dcuts, dpb, keys, vals, sscr, big;
         alloc(dcuts, np * sizeof(int4), "class cuts");
@@ -2221,7 +2249,9 @@ hipError_t matvec_launch(hmx_hmatrix_s* h, const void* x, void* z, double alpha,
                          hipStream_t st, hipEvent_t* ev, int config) {
     const int f64 = h->f64;
     hipError_t e = ev ? hipEventRecord(ev[0], st) : hipSuccess;
-    if (e == hipSuccess) e = launch_gather_x(x, h->perm.as<int32_t>(), h->n, h->vecpool.p, f64, st);
+    if (e == hipSuccess)
+        e = launch_gather_x(x, h->perm.as<int32_t>() + h->col0, h->ncols,
+                            (char*)h->vecpool.p + (size_t)h->col0 * h->esz, f64, st, h->col0);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
     // phase 1 by row tiles: partial sums of every source column, then the t
     // entries; the sources are the factor pool (symmetric far field) and the V pool
@@ -2231,11 +2261,11 @@ hipError_t matvec_launch(hmx_hmatrix_s* h, const void* x, void* z, double alpha,
                              h->partial.p, h->vecpool.p, h->n, f64, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
     if (e == hipSuccess)
-        e = launch_rowtile(h->ntiles, h->tile_lo.as<int32_t>(), h->tile_meta.as<int64_t>(),
+        e = launch_rowtile(h->ntiles_rows, h->tile_lo.as<int32_t>(), h->tile_meta.as<int64_t>(),
                            h->widx.as<int64_t>(), h->upool.p, h->npool.p, h->vecpool.p,
                            h->perm.as<int32_t>(), alpha, beta, h->prm.sigma2, z, h->max_tile,
                            h->smode, h->nmode, config, f64 ? h->soa64.p : h->soa32.p, h->n, h->d,
-                           kernel_fn(h->kern, h->d), st);
+                           kernel_fn(h->kern, h->kd), st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
     return e;
 }
@@ -2354,6 +2384,10 @@ hmx_status cg_args(hmx_hmatrix_s* h, const void* b, const void* x, double rel_to
     }
     if (h->prm.aca_only) {
         set_err("handle was built with aca_only: no matrix to apply");
+        return HMX_ERR_UNSUPPORTED;
+    }
+    if (h->rect) {
+        set_err("a rectangular handle has no linear system to solve");
         return HMX_ERR_UNSUPPORTED;
     }
     return HMX_OK;
@@ -2619,6 +2653,80 @@ hmx_status hmx_build_batched(int32_t nprob, const void* const* points, hmx_dtype
     return HMX_OK;
 }
 
+hmx_status hmx_build_rect(const void* rows, int64_t n1, const void* cols, int64_t n2,
+                          hmx_dtype pts_dtype, int32_t d, const hmx_kernel* kernel,
+                          const hmx_params* params, void* stream, hmx_hmatrix* out) {
+    if (out) *out = nullptr;
+    if (!out || !rows || !cols || !kernel || !params || n1 < 1 || n2 < 1 || d < 1 || d > 3) {
+        set_err("NULL argument, n1 < 1, n2 < 1 or d not in {1,2,3}");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (pts_dtype != HMX_F64 && pts_dtype != HMX_F32) {
+        set_err("points must be F64 or F32");
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (n1 + n2 >= (1ll << 31)) {
+        set_err("n1 + n2 = %lld exceeds 2^31 - 1", (long long)(n1 + n2));
+        return HMX_ERR_INVALID_ARG;
+    }
+    const hmx_params& p = *params;
+    {
+        const hmx_status ps = check_params(p);
+        if (ps != HMX_OK) return ps;
+    }
+    if (p.sigma2 != 0.0 || p.symmetric_far) {
+        set_err("a rectangular matrix takes no diagonal shift and has no mirror blocks "
+                "(sigma2 = 0, symmetric_far = 0)");
+        return HMX_ERR_INVALID_ARG;
+    }
+    const hmx_kernel_kind kind = kernel->kind;
+    if (kind != HMX_GAUSSIAN && kind != HMX_MATERN32 && kind != HMX_MATERN_NU1) {
+        set_err("rectangular build supports the Gaussian and Matern kernels");
+        return HMX_ERR_UNSUPPORTED;
+    }
+    if (!(kernel->p0 > 0 && std::isfinite(kernel->p0))) {
+        set_err("kernel parameter p0 must be positive and finite");
+        return HMX_ERR_INVALID_ARG;
+    }
+    hmx_hmatrix_s* h = new (std::nothrow) hmx_hmatrix_s();
+    if (!h) {
+        set_err("host allocation failed");
+        return HMX_ERR_OOM;
+    }
+    // the two sets as a forest of two trees (each ordered in its own box,
+    // coordinates divided by the kernel length), traversed from the one root
+    // block Y1 x Y2
+    init_handle(h, n1 + n2, 3, hmx_kernel{kind, 1.0, 0.0}, p);
+    h->kd = d;
+    h->nprob = 2;
+    h->batched = true;
+    h->rect = true;
+    h->nrows = n1;
+    h->ncols = n2;
+    h->col0 = n1;
+    const void* pts[2] = {rows, cols};
+    const int64_t nn[2] = {n1, n2};
+    const int32_t dd[2] = {d, d};
+    const hmx_kernel kk[2] = {*kernel, *kernel};
+    const Allocator ua{p.dev_alloc, p.dev_free, p.alloc_ctx};
+    AllocScope scope(&ua);
+    try {
+        batched_impl(h, 2, pts, pts_dtype == HMX_F64, nn, dd, kk, (hipStream_t)stream, true);
+    } catch (const Fail& f) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        (void)hipGetLastError();
+        delete h;
+        return f.s;
+    } catch (const std::bad_alloc&) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        delete h;
+        set_err("host allocation failed");
+        return HMX_ERR_OOM;
+    }
+    *out = h;
+    return HMX_OK;
+}
+
 hmx_status hmx_get_batch(hmx_hmatrix h, int32_t* nprob, int64_t* offsets) {
     if (!h || !nprob) {
         set_err("NULL argument");
@@ -2766,13 +2874,13 @@ hmx_status hmx_autotune(hmx_hmatrix h, int32_t reps, void* stream, int32_t* choi
         int bc = -1;
         for (int c = 0; c < kRowtileConfigs; ++c) {
             auto rt = [&] {
-                return launch_rowtile(h->ntiles, h->tile_lo.as<int32_t>(),
+                return launch_rowtile(h->ntiles_rows, h->tile_lo.as<int32_t>(),
                                       h->tile_meta.as<int64_t>(), h->widx.as<int64_t>(),
                                       h->upool.p, h->npool.p, h->vecpool.p,
                                       h->perm.as<int32_t>(), 1.0, 0.0, h->prm.sigma2, z.p,
                                       h->max_tile, h->smode, h->nmode, c,
                                       h->f64 ? h->soa64.p : h->soa32.p, h->n, h->d,
-                                      kernel_fn(h->kern, h->d), st);
+                                      kernel_fn(h->kern, h->kd), st);
             };
             check(rt(), "tuning warm-up");
             check(hipEventRecord(e0, st), "event");

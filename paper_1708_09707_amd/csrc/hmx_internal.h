@@ -425,8 +425,10 @@ hipError_t launch_piece_data(const Piece* pieces, int64_t np, const int32_t* til
 hipError_t launch_compact_v(const int4* blocks, int64_t nblocks, const int32_t* rank,
                             const int64_t* cap_voff, int64_t cap_base, const int64_t* voff,
                             const void* Vcap, void* V, int smode, hipStream_t st);
+// xm[i] = x[perm[i] - base] for i < n (base: the first column's index in
+// the union of a rectangular handle's two point sets, else 0)
 hipError_t launch_gather_x(const void* x, const int32_t* perm, int64_t n, void* xm, int f64,
-                           hipStream_t st);
+                           hipStream_t st, int64_t base = 0);
 // data[i] += c for i < n
 hipError_t launch_add_const(int64_t* data, int64_t n, int64_t c, hipStream_t st);
 // U compaction into the exact per-block pool (compute type)

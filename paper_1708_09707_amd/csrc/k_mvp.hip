@@ -406,9 +406,9 @@ __global__ __launch_bounds__(256) void piece_data_kernel(
 
 template <typename T>
 __global__ void gather_x_kernel(const T* __restrict__ x, const int32_t* __restrict__ perm,
-                                int64_t n, T* __restrict__ xm) {
+                                int64_t n, T* __restrict__ xm, int64_t base) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) xm[i] = x[perm[i]];
+    if (i < n) xm[i] = x[perm[i] - base];
 }
 
 // out[0] = max, out[1] = sum of n int32 values (integer atomics: order-free)
@@ -948,13 +948,14 @@ hipError_t launch_chunk_bounds(const int64_t* cap_off, int64_t nb, int64_t step,
 }
 
 hipError_t launch_gather_x(const void* x, const int32_t* perm, int64_t n, void* xm, int f64,
-                           hipStream_t st) {
+                           hipStream_t st, int64_t base) {
+    if (n <= 0) return hipSuccess;
     if (f64)
         hipLaunchKernelGGL(gather_x_kernel<double>, dim3((unsigned)((n + 255) / 256)), dim3(256),
-                           0, st, (const double*)x, perm, n, (double*)xm);
+                           0, st, (const double*)x, perm, n, (double*)xm, base);
     else
         hipLaunchKernelGGL(gather_x_kernel<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                           st, (const float*)x, perm, n, (float*)xm);
+                           st, (const float*)x, perm, n, (float*)xm, base);
     return hipGetLastError();
 }
 

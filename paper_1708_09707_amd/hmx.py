@@ -38,7 +38,7 @@ EXPORTS = ["hmx_params_default", "hmx_build", "hmx_matvec", "hmx_cg_solve", "hmx
            "hmx_block_features", "hmx_build_batched", "hmx_get_batch", "hmx_matvec_graph",
            "hmx_graph_launch", "hmx_graph_destroy", "hmx_autotune", "hmx_set_tile_config",
            "hmx_rank_predict", "hmx_cg_solve_noalloc", "hmx_matvec_batched", "hmx_mlp_save",
-           "hmx_mlp_load"]
+           "hmx_mlp_load", "hmx_build_rect"]
 HMX_CG_NOALLOC_MAX_BYTES = 50397184
 HMX_TILE_CONFIGS = 15
 
@@ -78,7 +78,8 @@ class hmx_stats(C.Structure):
                 ("device_bytes", C.c_int64), ("level_sizes", C.c_int64 * 64),
                 ("aca_fallback", C.c_int64), ("aca_capacity", C.c_int64),
                 ("predict_ms", C.c_double), ("aca_overflow", C.c_int64),
-                ("aca_kernel_evals", C.c_int64), ("aca_flops", C.c_double)]
+                ("aca_kernel_evals", C.c_int64), ("aca_flops", C.c_double),
+                ("rows", C.c_int64), ("cols", C.c_int64)]
 
 
 class HmxError(RuntimeError):
@@ -219,24 +220,33 @@ def hmx_build(points, kernel: hmx_kernel, params: hmx_params, stream=None):
     return h
 
 
-def _check_vectors(h, *vecs):
+def _check_vectors(h, *vecs, lengths=None):
     """The C ABI takes bare device pointers: every vector must be a
-    contiguous device tensor of exactly the handle's n entries, all of one
-    dtype and on one device (a short vector would be read and written past
-    its end by the gather and scatter kernels)."""
+    contiguous device tensor of exactly the length the handle expects (its n,
+    or per vector `lengths`), all of one dtype and on one device (a short
+    vector would be read and written past its end by the gather and scatter
+    kernels)."""
     n = hmx_get_stats(h).n
+    lengths = lengths or [n] * len(vecs)
     t0 = vecs[0]
-    for t in vecs:
+    for t, m in zip(vecs, lengths):
         if not (t.is_cuda and t.is_contiguous()):
             raise ValueError("vectors must be contiguous device tensors")
-        if t.dim() != 1 or t.numel() != n:
-            raise ValueError("vectors must have shape (%d,), got %s" % (n, tuple(t.shape)))
+        if t.dim() != 1 or t.numel() != m:
+            raise ValueError("vectors must have shape (%d,), got %s" % (m, tuple(t.shape)))
         if t.dtype != t0.dtype or t.device != t0.device:
             raise ValueError("vectors must share one dtype and device")
 
 
+def _shape(h):
+    """(rows, cols) of the handle's matrix."""
+    st = hmx_get_stats(h)
+    return int(st.rows), int(st.cols)
+
+
 def hmx_matvec(h, x, z, alpha=1.0, beta=0.0, stream=None):
-    _check_vectors(h, x, z)
+    rows, cols = _shape(h)
+    _check_vectors(h, x, z, lengths=(cols, rows))
     _check(lib().hmx_matvec(h, C.c_void_p(x.data_ptr()), C.c_void_p(z.data_ptr()), _dtype_of(x),
                             float(alpha), float(beta), _stream(stream)))
 
@@ -246,7 +256,8 @@ def hmx_matvec_batched(handles, xs, zs, alpha=1.0, beta=0.0, stream=None):
     if not (len(handles) == len(xs) == len(zs)):
         raise ValueError("handles, xs and zs must have one entry per problem")
     for h, x, z in zip(handles, xs, zs):
-        _check_vectors(h, x, z)
+        rows, cols = _shape(h)
+        _check_vectors(h, x, z, lengths=(cols, rows))
     k = len(handles)
     hs = (C.c_void_p * k)(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
     xp = (C.c_void_p * k)(*[x.data_ptr() for x in xs])
@@ -473,7 +484,8 @@ def hmx_rank_predict(h, mlp, stream=None):
 
 def hmx_matvec_graph(h, x, z, alpha=1.0, beta=0.0, reps=1):
     """Capture reps matvecs into a HIP graph; returns the graph handle."""
-    _check_vectors(h, x, z)
+    rows, cols = _shape(h)
+    _check_vectors(h, x, z, lengths=(cols, rows))
     g = C.c_void_p()
     _check(lib().hmx_matvec_graph(h, C.c_void_p(x.data_ptr()), C.c_void_p(z.data_ptr()),
                                   _dtype_of(x), float(alpha), float(beta), int(reps),
@@ -521,6 +533,22 @@ def hmx_build_batched(points_list, kernels, params: hmx_params, stream=None):
     _check(lib().hmx_build_batched(np_, ptrs, dt, ns, ds, ks, C.byref(params), _stream(stream),
                                    C.byref(h)))
     return h, hmx_get_batch(h)
+
+
+def hmx_build_rect(rows_pts, cols_pts, kernel: hmx_kernel, params: hmx_params, stream=None):
+    """Rectangular H-matrix of A(Y1 x Y2): rows_pts (n1, d) and cols_pts (n2, d)
+    contiguous device tensors of one float dtype."""
+    dt = _dtype_of(rows_pts)
+    for t in (rows_pts, cols_pts):
+        if not t.is_cuda or not t.is_contiguous() or t.dim() != 2 or _dtype_of(t) != dt:
+            raise ValueError("points must be contiguous (n, d) device tensors of one dtype")
+    if rows_pts.shape[1] != cols_pts.shape[1]:
+        raise ValueError("both point sets need the same dimension")
+    h = C.c_void_p()
+    _check(lib().hmx_build_rect(_ptr(rows_pts), int(rows_pts.shape[0]), _ptr(cols_pts),
+                                int(cols_pts.shape[0]), dt, int(rows_pts.shape[1]),
+                                C.byref(kernel), C.byref(params), _stream(stream), C.byref(h)))
+    return h
 
 
 def hmx_get_batch(h):
@@ -646,10 +674,23 @@ class HMatrix:
         self.n, self.d = int(self.offsets[-1]), 3
         return self
 
+    @classmethod
+    def rect(cls, rows_pts, cols_pts, kernel="gaussian", p0=1.0, stream=None, **params):
+        """The rectangular matrix A(Y1 x Y2) (hmx_build_rect)."""
+        self = cls.__new__(cls)
+        self.params = hmx_params_default(**params)
+        self.allocator = params.get("allocator")
+        self.kernel = make_kernel(kernel, p0)
+        self.h = hmx_build_rect(rows_pts, cols_pts, self.kernel, self.params, stream)
+        self.offsets = hmx_get_batch(self.h)
+        self.n, self.d = int(self.offsets[-1]), int(rows_pts.shape[1])
+        return self
+
     def matvec(self, x, z=None, alpha=1.0, beta=0.0, stream=None):
         import torch
         if z is None:
-            z = torch.empty_like(x)
+            rows, _ = _shape(self.h)
+            z = torch.empty(rows, dtype=x.dtype, device=x.device)
         hmx_matvec(self.h, x, z, alpha, beta, stream)
         return z
 

@@ -148,7 +148,7 @@ def test_binding_rejects_vectors_of_the_wrong_size(monkeypatch):
     from paper_1708_09707_amd import hmx
 
     class _St:
-        n = 1000
+        n = rows = cols = 1000
 
     monkeypatch.setattr(hmx, "hmx_get_stats", lambda h: _St())
     h = C.c_void_p(1)
@@ -161,6 +161,15 @@ def test_binding_rejects_vectors_of_the_wrong_size(monkeypatch):
                   lambda: hmx.hmx_matvec_graph(h, b, good)):
             with pytest.raises(ValueError):
                 f()
+
+    class _Rect:  # a 700 x 300 rectangular handle: x has 300 entries, z 700
+        n, rows, cols = 1000, 700, 300
+
+    monkeypatch.setattr(hmx, "hmx_get_stats", lambda h: _Rect())
+    for x, z in [(_Vec(700), _Vec(300)), (_Vec(300), _Vec(300)), (_Vec(700), _Vec(700)),
+                 (_Vec(1000), _Vec(1000))]:
+        with pytest.raises(ValueError):
+            hmx.hmx_matvec(h, x, z)
 
 
 def test_mlp_load_rejects_bad_files(tmp_path):
