@@ -344,6 +344,23 @@ hmx_status hmx_get_batch(hmx_hmatrix h, int32_t* nprob, int64_t* offsets);
 hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype, double alpha,
                       double beta, void* stream);
 
+/* Z := alpha (H + sigma2 I) X + beta Z for m right-hand sides (the product
+ * of Algorithm 3 for a block of vectors; for many vectors V^T X and the row
+ * tiles become products with m columns).  Every stored entry is read once
+ * per group of up to 16 right-hand sides.
+ *   X : device, column-major stats.cols x m, leading dimension ldx >= cols
+ *       (right-hand side c at X + c ldx, original point order);
+ *   Z : device, column-major stats.rows x m, leading dimension ldz >= rows;
+ *       vec_dtype as for hmx_matvec; X and Z must not overlap.
+ * Column c of Z sums the same terms as hmx_matvec of X's column c, in
+ * another order (results agree to rounding).  The first call on a handle
+ * allocates work vectors of 16 (n + sum_rank) compute-type values and the
+ * partial sums, kept by the handle (hmx_destroy returns them); later calls
+ * allocate nothing.  Asynchronous on `stream`.  far_recompute handles:
+ * UNSUPPORTED. */
+hmx_status hmx_matmat(hmx_hmatrix h, const void* X, int64_t ldx, void* Z, int64_t ldz,
+                      int32_t m, hmx_dtype vec_dtype, double alpha, double beta, void* stream);
+
 /* Matvecs of nprob separately built handles on one stream:
  * z[q] := alpha (H_q + sigma2_q I) x[q] + beta z[q] for q = 0..nprob-1 (host
  * arrays of nprob handles and device pointers; each pair of vectors as for

@@ -26,7 +26,7 @@ COMMON = [
 # exact IEEE sequences required (ordering and partition are compared bit for bit)
 NO_CONTRACT = {"k_order.hip", "k_tree.hip"}
 SOURCES = ["k_order.hip", "k_tree.hip", "k_aca.hip", "k_aca_split.hip", "k_mvp.hip",
-           "k_blas.hip", "k_mlp.hip", "k_batch.hip", "k_phase1.hip", "k_np.hip", "hmx_api.hip"]
+           "k_blas.hip", "k_mlp.hip", "k_batch.hip", "k_phase1.hip", "k_np.hip", "k_mm.hip", "hmx_api.hip"]
 
 
 def hipcc() -> str:

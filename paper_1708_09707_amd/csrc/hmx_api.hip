@@ -373,6 +373,8 @@ struct hmx_hmatrix_s {
     // the first ntiles_rows tiles.  Square handles: rows = columns = [0, n).
     bool rect = false;
     int64_t nrows = 0, ncols = 0, col0 = 0, ntiles_rows = 0;
+    // work vectors of hmx_matmat (16 right-hand sides, point-major), grown on use
+    DevBuf mm_vec, mm_partial;
     int kd = 0;  // the points' dimension for the kernel's normalisation
     hmx_stats stats{};
     // matvec phase tracing (hmx_profile_begin / end)
@@ -394,7 +396,8 @@ struct hmx_hmatrix_s {
                                &npool,   &widx,    &tile_meta, &vecpool,       &partner,
                                &vpieces, &vtpool,  &vt_meta,   &p1rec,         &pfc,
                                &partial, &np.blocks, &np.lmap, &np.cu,  &np.cv,
-                               &np.rank, &np.steps, &np.spcs,  &np.seg_start, &np.seg_tile};
+                               &np.rank, &np.steps, &np.spcs,  &np.seg_start, &np.seg_tile,
+                               &mm_vec,  &mm_partial};
         int64_t s = 0;
         for (auto* b : all) s += (int64_t)b->bytes;
         return s;
@@ -2761,6 +2764,62 @@ hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype
         return HMX_ERR_DEVICE;
     }
     return HMX_OK;
+}
+
+hmx_status hmx_matmat(hmx_hmatrix h, const void* X, int64_t ldx, void* Z, int64_t ldz,
+                      int32_t m, hmx_dtype vec_dtype, double alpha, double beta, void* stream) {
+    const hmx_status cs = matvec_args(h, X, Z, vec_dtype);
+    if (cs != HMX_OK) return cs;
+    if (m < 1 || ldx < h->ncols || ldz < h->nrows) {
+        set_err("m < 1, ldx < %lld or ldz < %lld", (long long)h->ncols, (long long)h->nrows);
+        return HMX_ERR_INVALID_ARG;
+    }
+    if (h->far_np) {
+        set_err("hmx_matmat: a far_recompute handle multiplies one vector at a time");
+        return HMX_ERR_UNSUPPORTED;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const Allocator ua{h->prm.dev_alloc, h->prm.dev_free, h->prm.alloc_ctx};
+    AllocScope scope(&ua);
+    return guarded([&] {
+        constexpr int kMaxM = 16;
+        const size_t esz = h->esz;
+        const int f64 = h->f64;
+        ensure(h->mm_vec, (size_t)(h->n + h->sum_rank) * kMaxM * esz, st, "multi-RHS vectors");
+        const int64_t np1 = (h->sym ? h->ncols_u : 0) + h->ncols_v;
+        ensure(h->mm_partial, (size_t)std::max<int64_t>(np1, 1) * kMaxM * esz, st,
+               "multi-RHS partial sums");
+        for (int32_t c0 = 0; c0 < m;) {
+            int M = kMaxM;
+            while (M > m - c0) M >>= 1;
+            const void* Xc = (const char*)X + (size_t)c0 * ldx * esz;
+            void* Zc = (char*)Z + (size_t)c0 * ldz * esz;
+            check(launch_mm_gather(Xc, ldx, h->perm.as<int32_t>(), h->ncols, h->col0, h->mm_vec.p,
+                                   M, f64, st),
+                  "multi-RHS gather");
+            if (h->sym && h->ncols_u > 0)
+                check(launch_mm_p1(M, h->ntiles, h->tile_lo.as<int32_t>(),
+                                   h->tile_meta.as<int64_t>(), 4, h->Ru, h->upool.p, h->mm_vec.p,
+                                   h->mm_partial.p, 0, h->smode, st),
+                      "multi-RHS phase 1");
+            if (h->ncols_v > 0)
+                check(launch_mm_p1(M, h->ntiles, h->tile_lo.as<int32_t>(),
+                                   h->vt_meta.as<int64_t>(), 4, h->Rv, h->vtpool.p, h->mm_vec.p,
+                                   h->mm_partial.p, h->sym ? h->ncols_u : 0, h->smode, st),
+                      "multi-RHS phase 1");
+            check(launch_mm_p1_reduce(M, h->p1rec.as<int4>(), h->sum_rank, h->pfc.as<int64_t>(),
+                                      h->mm_partial.p, h->mm_vec.p, h->n, f64, st),
+                  "multi-RHS phase 1 sums");
+            check(launch_mm_rowtile(M, h->ntiles_rows, h->tile_lo.as<int32_t>(),
+                                    h->tile_meta.as<int64_t>(), h->widx.as<int64_t>(),
+                                    h->upool.p, h->npool.p, h->mm_vec.p, h->perm.as<int32_t>(),
+                                    alpha, beta, h->prm.sigma2, Zc, ldz, h->Ru, h->max_tile,
+                                    h->smode, h->nmode, f64 ? h->soa64.p : h->soa32.p, h->n, h->d,
+                                    kernel_fn(h->kern, h->kd), st),
+                  "multi-RHS row tiles");
+            c0 += M;
+        }
+    });
 }
 
 hmx_status hmx_matvec_batched(int32_t nprob, const hmx_hmatrix* hs, const void* const* x,

@@ -38,7 +38,7 @@ EXPORTS = ["hmx_params_default", "hmx_build", "hmx_matvec", "hmx_cg_solve", "hmx
            "hmx_block_features", "hmx_build_batched", "hmx_get_batch", "hmx_matvec_graph",
            "hmx_graph_launch", "hmx_graph_destroy", "hmx_autotune", "hmx_set_tile_config",
            "hmx_rank_predict", "hmx_cg_solve_noalloc", "hmx_matvec_batched", "hmx_mlp_save",
-           "hmx_mlp_load", "hmx_build_rect"]
+           "hmx_mlp_load", "hmx_build_rect", "hmx_matmat"]
 HMX_CG_NOALLOC_MAX_BYTES = 50397184
 HMX_TILE_CONFIGS = 15
 
@@ -118,6 +118,9 @@ def lib():
         L.hmx_cg_solve_noalloc.argtypes = [P, P, P, f64, i32, P, C.POINTER(i32), C.POINTER(f64),
                                            C.POINTER(f64)]
         L.hmx_matvec_batched.argtypes = [i32, P, P, P, C.c_int, f64, f64, P]
+        L.hmx_matmat.argtypes = [P, P, i64, P, i64, i32, C.c_int, f64, f64, P]
+        L.hmx_build_rect.argtypes = [P, i64, P, i64, C.c_int, i32, C.POINTER(hmx_kernel),
+                                     C.POINTER(hmx_params), P, C.POINTER(P)]
         L.hmx_mlp_save.argtypes = [P, C.c_char_p]
         L.hmx_mlp_load.argtypes = [C.c_char_p, C.POINTER(P)]
         L.hmx_get_partition.argtypes = [P, P, P, P, C.POINTER(i64), P, C.POINTER(i64), P]
@@ -249,6 +252,23 @@ def hmx_matvec(h, x, z, alpha=1.0, beta=0.0, stream=None):
     _check_vectors(h, x, z, lengths=(cols, rows))
     _check(lib().hmx_matvec(h, C.c_void_p(x.data_ptr()), C.c_void_p(z.data_ptr()), _dtype_of(x),
                             float(alpha), float(beta), _stream(stream)))
+
+
+def hmx_matmat(h, X, Z, alpha=1.0, beta=0.0, stream=None):
+    """Z = alpha (H + sigma2 I) X + beta Z for several right-hand sides.  X:
+    contiguous (m, ldx) device tensor with ldx >= cols (right-hand side c in
+    X[c, :cols]), Z: (m, ldz) with ldz >= rows; the C ABI sees them as
+    column-major cols x m and rows x m with leading dimensions ldx, ldz."""
+    rows, cols = _shape(h)
+    for t, w in ((X, cols), (Z, rows)):
+        if not (t.is_cuda and t.is_contiguous()) or t.dim() != 2 or t.shape[1] < w:
+            raise ValueError("X must be a contiguous (m, >= %d) and Z a (m, >= %d) device tensor"
+                             % (cols, rows))
+    if X.shape[0] != Z.shape[0] or X.dtype != Z.dtype or X.device != Z.device:
+        raise ValueError("X and Z need the same number of rows, dtype and device")
+    _check(lib().hmx_matmat(h, C.c_void_p(X.data_ptr()), int(X.shape[1]),
+                            C.c_void_p(Z.data_ptr()), int(Z.shape[1]), int(X.shape[0]),
+                            _dtype_of(X), float(alpha), float(beta), _stream(stream)))
 
 
 def hmx_matvec_batched(handles, xs, zs, alpha=1.0, beta=0.0, stream=None):
@@ -693,6 +713,15 @@ class HMatrix:
             z = torch.empty(rows, dtype=x.dtype, device=x.device)
         hmx_matvec(self.h, x, z, alpha, beta, stream)
         return z
+
+    def matmat(self, X, Z=None, alpha=1.0, beta=0.0, stream=None):
+        """Several right-hand sides, one per row of X."""
+        import torch
+        if Z is None:
+            rows, _ = _shape(self.h)
+            Z = torch.empty((X.shape[0], rows), dtype=X.dtype, device=X.device)
+        hmx_matmat(self.h, X, Z, alpha, beta, stream)
+        return Z
 
     def stats(self):
         return hmx_get_stats(self.h)
