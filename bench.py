@@ -432,6 +432,52 @@ def batched_problems(torch, lo, hi, nprob=64):
     return ns, ds, p0s, pts
 
 
+def multi_rhs_leg(torch, H, log, wl, pts_d, reps=5):
+    """Several right-hand sides on the bench workload: m single-vector
+    products against one hmx_matmat, for the plain FP32 and the BF16 forms
+    (stored entries read once per 16 vectors instead of once per vector)."""
+    n = wl["n"]
+    out = {}
+    for form, kw in (("plain_f32", dict(compute_dtype="f32")),
+                     ("bf16", dict(compute_dtype="f32", storage_dtype="bf16"))):
+        hm = H.HMatrix(pts_d, wl["kernel"], wl["p0"], leaf_size=wl["leaf"], eta=wl["eta"],
+                       aca_eps=wl["eps"], max_rank=wl["kmax"], **kw)
+        st = hm.stats()
+        res = {}
+        for m in (4, 16, 64):
+            X = torch.from_numpy(synth.rng(7300 + m).standard_normal((m, n)).astype(np.float32)).cuda()
+            Z = torch.empty_like(X)
+            hm.matmat(X[:1], Z[:1])  # work vectors allocated outside the timing
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                H.hmx_matmat(hm.h, X, Z)
+            e1.record()
+            torch.cuda.synchronize()
+            mm_ms = e0.elapsed_time(e1) / reps
+            z = torch.empty(n, dtype=torch.float32, device=X.device)
+            e0.record()
+            for _ in range(reps):
+                for c in range(m):
+                    H.hmx_matvec(hm.h, X[c], z)
+            e1.record()
+            torch.cuda.synchronize()
+            mv_ms = e0.elapsed_time(e1) / reps
+            ref = torch.empty(n, dtype=torch.float32, device=X.device)
+            H.hmx_matvec(hm.h, X[m - 1], ref)
+            err = (torch.linalg.norm(Z[m - 1].double() - ref.double()) /
+                   torch.linalg.norm(ref.double())).item()
+            res["m%d" % m] = {"matmat_ms": mm_ms, "matvecs_ms": mv_ms, "speedup": mv_ms / mm_ms,
+                              "matrix_gbs_per_rhs": st.matvec_bytes * m / (mm_ms * 1e-3) / 1e9,
+                              "rel_diff_last_column": err}
+            log("bench: %s m=%d: matmat %.2f ms vs %d matvecs %.2f ms (%.2fx)"
+                % (form, m, mm_ms, m, mv_ms, mv_ms / mm_ms))
+        out[form] = res
+        hm.close()
+    return out
+
+
 def batched_leg(torch, H, log, M=20):
     """64 independent problems as one block-diagonal handle against the same
     problems built (and multiplied) one by one, all on one stream.  The full
@@ -833,6 +879,7 @@ def main():
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = nel * 4
         del src, dst
+    out["multi_rhs"] = multi_rhs_leg(torch, H, log, wl, pts_d)
     if not args.no_batched:
         H.hmx_trim()
         out["batched_64"] = batched_leg(torch, H, log)

@@ -9,10 +9,12 @@
 // contiguous run.
 //
 //   * gather:    vec[(col0 + i) M + c] = X[perm[col0 + i] - col0 + c ldx];
-//   * phase 1:   T_b = V_b^T X|sigma_b by row tiles: one wave per tile, the
-//                tile's X rows staged in LDS, groups of 8 lanes per source
-//                column, each lane summing its rows for all M sides, then a
-//                butterfly over the 8 lanes; partials per (column, tile);
+//   * phase 1:   T_b = V_b^T X|sigma_b by row tiles: one workgroup of four
+//                waves per tile, the tile's X rows staged in LDS, groups of 8
+//                lanes taking two source columns at a time (eight row vectors
+//                per lane in flight), each lane summing its rows for all M
+//                sides, then a butterfly over the 8 lanes; partials per
+//                (column, tile);
 //   * reduce:    the partials of each t entry summed over its tiles in tile
 //                order (as for one vector);
 //   * row tiles: one wave per (tile, pass of 64 x VR rows): each lane owns VR
@@ -36,8 +38,8 @@ struct MmUnit;
 template <>
 struct MmUnit<double> {
     static constexpr int VR = 2;
-    static __device__ __forceinline__ void load(const double* p, double* o) {
-        const double2 v = *(const double2*)p;
+    typedef double2 Raw;
+    static __device__ __forceinline__ void get(const Raw& v, double* o) {
         o[0] = v.x;
         o[1] = v.y;
     }
@@ -45,8 +47,8 @@ struct MmUnit<double> {
 template <>
 struct MmUnit<float> {
     static constexpr int VR = 4;
-    static __device__ __forceinline__ void load(const float* p, float* o) {
-        const float4 v = *(const float4*)p;
+    typedef float4 Raw;
+    static __device__ __forceinline__ void get(const Raw& v, float* o) {
         o[0] = v.x;
         o[1] = v.y;
         o[2] = v.z;
@@ -56,14 +58,33 @@ struct MmUnit<float> {
 template <>
 struct MmUnit<uint16_t> {
     static constexpr int VR = 4;
-    static __device__ __forceinline__ void load(const uint16_t* p, float* o) {
-        const uint2 v = *(const uint2*)p;
+    typedef uint2 Raw;
+    static __device__ __forceinline__ void get(const Raw& v, float* o) {
         o[0] = __uint_as_float(v.x << 16);
         o[1] = __uint_as_float(v.x & 0xffff0000u);
         o[2] = __uint_as_float(v.y << 16);
         o[3] = __uint_as_float(v.y & 0xffff0000u);
     }
 };
+
+template <typename S>
+__device__ __forceinline__ typename MmUnit<S>::Raw mm_raw(const S* p) {
+    return *(const typename MmUnit<S>::Raw*)p;
+}
+
+// M weights of one column, 16 bytes at a time when M allows
+template <typename T, int M>
+__device__ __forceinline__ void mm_copy_weights(T* __restrict__ dst, const T* __restrict__ src) {
+    constexpr int W = 16 / (int)sizeof(T);  // values per 16-byte move
+    if constexpr (M % W == 0) {
+        typedef T V __attribute__((ext_vector_type(W)));
+#pragma unroll
+        for (int c = 0; c < M; c += W) *(V*)(dst + c) = *(const V*)(src + c);
+    } else {
+#pragma unroll
+        for (int c = 0; c < M; ++c) dst[c] = src[c];
+    }
+}
 
 __device__ __host__ __forceinline__ int mm_ld(int rows, int R) { return (rows + R - 1) / R * R; }
 
@@ -83,20 +104,68 @@ __global__ void mm_gather_kernel(const T* __restrict__ X, int64_t ldx,
     }
 }
 
-template <typename S, typename T, int M>
-__global__ __launch_bounds__(64) void mm_p1_kernel(int64_t ntiles,
-                                                   const int32_t* __restrict__ tile_lo,
-                                                   const int64_t* __restrict__ meta, int ms,
-                                                   int R, const S* __restrict__ pool,
-                                                   const T* __restrict__ vec,
-                                                   T* __restrict__ partial, int64_t pbase) {
+// one lane's share of U source columns (col, col + ld, ...; nu of them
+// real, the others repeat the first and count zero) against M right-hand
+// sides: row vectors q, q + L, ... of each column, B row vectors of every
+// column loaded before any is used, each X row read once (from LDS with row
+// stride XS, or from the point-major vector xt) for all U columns
+template <typename S, typename T, int M, int B, int L, int U, bool STAGED>
+__device__ __forceinline__ void mm_p1_rows(const S* __restrict__ col, int ld, int nu, int mt,
+                                           int q, const T* __restrict__ xs, int xstride,
+                                           T (&acc)[U][M]) {
     constexpr int VR = MmUnit<S>::VR;
-    constexpr int L = 8;                 // lanes per column
-    constexpr int G = 64 / L;            // columns per wave at a time
-    constexpr int SROWS = 16384 / (M * (int)sizeof(T));  // rows of X staged in LDS
-    __shared__ T sx[SROWS * M];
-    const int lane = threadIdx.x;
-    const int g = lane / L, q = lane % L;
+    for (int u0 = q * VR; u0 < ld; u0 += B * L * VR) {
+        typename MmUnit<S>::Raw raw[U][B];
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int u = u0 + b * L * VR;
+                raw[k][b] = mm_raw(col + (int64_t)(k < nu ? k : 0) * ld + (u < ld ? u : u0));
+            }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int u = u0 + b * L * VR;
+            const bool in = u < ld;
+            const int uu = in ? u : u0;
+            T a[U][VR];
+#pragma unroll
+            for (int k = 0; k < U; ++k) MmUnit<S>::get(raw[k][b], a[k]);
+#pragma unroll
+            for (int e = 0; e < VR; ++e) {
+                const int row = uu + e;
+                // rows past the tile (or past a column group's end) count zero
+                const bool live = in && (STAGED || row < mt);
+                const T* __restrict__ xr = xs + (int64_t)(STAGED || row < mt ? row : 0) * xstride;
+                T xv[M];
+#pragma unroll
+                for (int c = 0; c < M; ++c) xv[c] = xr[c];
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const T ae = (live && k < nu) ? a[k][e] : (T)0;
+#pragma unroll
+                    for (int c = 0; c < M; ++c) acc[k][c] += ae * xv[c];
+                }
+            }
+        }
+    }
+}
+
+template <typename S, typename T, int M>
+__global__ __launch_bounds__(256) void mm_p1_kernel(int64_t ntiles,
+                                                    const int32_t* __restrict__ tile_lo,
+                                                    const int64_t* __restrict__ meta, int ms,
+                                                    int R, const S* __restrict__ pool,
+                                                    const T* __restrict__ vec,
+                                                    T* __restrict__ partial, int64_t pbase) {
+    constexpr int L = 8;         // lanes per column group
+    constexpr int G = 256 / L;   // column groups per workgroup
+    constexpr int U = 2;         // columns a group takes at a time
+    constexpr int B = 8 / U;     // row vectors of each column loaded ahead
+    constexpr int XS = M + 1;    // padded LDS row stride: a group's 8 lanes read 8 banks
+    constexpr int SROWS = 16384 / (XS * (int)sizeof(T));  // rows of X staged in LDS
+    __shared__ __align__(16) T sx[SROWS * XS];
+    const int g = threadIdx.x / L, q = threadIdx.x % L;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t c0 = meta[ms * t + 1];
         const int nc = (int)(meta[ms * (t + 1) + 1] - c0);
@@ -107,37 +176,38 @@ __global__ __launch_bounds__(64) void mm_p1_kernel(int64_t ntiles,
         const S* __restrict__ base = pool + meta[ms * t + 2];
         const bool staged = ld <= SROWS;
         if (staged) {
-            for (int i = lane; i < ld * M; i += 64)
-                sx[i] = i / M < mt ? vec[(int64_t)(r0 + i / M) * M + i % M] : (T)0;
+            for (int i = threadIdx.x; i < ld * M; i += 256)
+                sx[(i / M) * XS + i % M] =
+                    i / M < mt ? vec[(int64_t)(r0 + i / M) * M + i % M] : (T)0;
             __syncthreads();
         }
-        for (int cb = g; cb < nc; cb += G) {
-            T acc[M];
+        for (int cb = g * U; cb < nc; cb += G * U) {
+            const int nu = nc - cb < U ? nc - cb : U;
+            T acc[U][M];
 #pragma unroll
-            for (int c = 0; c < M; ++c) acc[c] = 0;
+            for (int k = 0; k < U; ++k)
+#pragma unroll
+                for (int c = 0; c < M; ++c) acc[k][c] = 0;
             const S* __restrict__ col = base + (int64_t)cb * ld;
-            for (int u = q * VR; u < ld; u += L * VR) {
-                T a[VR];
-                MmUnit<S>::load(col + u, a);
-#pragma unroll
-                for (int e = 0; e < VR; ++e) {
-                    const int row = u + e;
-#pragma unroll
-                    for (int c = 0; c < M; ++c) {
-                        const T xv = staged ? sx[row * M + c]
-                                            : (row < mt ? vec[(int64_t)(r0 + row) * M + c] : (T)0);
-                        acc[c] += a[e] * xv;
-                    }
-                }
-            }
+            // X rows from LDS (staged tiles) or from the vector itself: the
+            // choice is made once per tile, not per value
+            if (staged)
+                mm_p1_rows<S, T, M, B, L, U, true>(col, ld, nu, mt, q, sx, XS, acc);
+            else
+                mm_p1_rows<S, T, M, B, L, U, false>(col, ld, nu, mt, q, vec + (int64_t)r0 * M,
+                                                    M, acc);
 #pragma unroll
             for (int m = L / 2; m >= 1; m >>= 1)
 #pragma unroll
-                for (int c = 0; c < M; ++c) acc[c] += __shfl_xor(acc[c], m, 64);
+                for (int k = 0; k < U; ++k)
+#pragma unroll
+                    for (int c = 0; c < M; ++c) acc[k][c] += __shfl_xor(acc[k][c], m, 64);
             // every lane of the group holds the totals; lane q writes sides q, q + 8
 #pragma unroll
-            for (int c = 0; c < M; ++c)
-                if (c % L == q) partial[(pbase + c0 + cb) * M + c] = acc[c];
+            for (int k = 0; k < U; ++k)
+#pragma unroll
+                for (int c = 0; c < M; ++c)
+                    if (c % L == q && k < nu) partial[(pbase + c0 + cb + k) * M + c] = acc[k][c];
         }
         if (staged) __syncthreads();  // sx is refilled by the next tile
     }
@@ -174,8 +244,9 @@ __global__ __launch_bounds__(64) void mm_rowtile_kernel(
     KernelEval<T> K) {
     constexpr int VR = MmUnit<SU>::VR;
     static_assert(NR || MmUnit<SN>::VR == VR, "one row unit for both pools");
-    constexpr int KC = 128;  // columns whose weights are staged at a time
-    __shared__ T sw[KC * M];
+    constexpr int KC = 256;  // columns whose weights are staged at a time
+    constexpr int B = 8;     // columns each lane loads before using them
+    __shared__ __align__(16) T sw[KC * M];
     const int lane = threadIdx.x;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int32_t r0 = tile_lo[t];
@@ -206,35 +277,84 @@ __global__ __launch_bounds__(64) void mm_rowtile_kernel(
         for (int64_t kc = k0; kc < k1; kc += KC) {
             const int nk = (int)min((int64_t)KC, k1 - kc);
             __syncthreads();  // the previous chunk's weights are used up
-            for (int i = lane; i < nk * M; i += 64) sw[i] = vec[widx[kc + i / M] * M + i % M];
+            {
+                // each lane moves the M weights of columns lane, lane + 64, ...
+                // (all their index loads first, then the weights)
+                int64_t w[KC / 64];
+#pragma unroll
+                for (int u = 0; u < KC / 64; ++u) {
+                    const int col = lane + 64 * u;
+                    w[u] = col < nk ? widx[kc + col] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < KC / 64; ++u) {
+                    const int col = lane + 64 * u;
+                    if (col < nk) mm_copy_weights<T, M>(sw + col * M, vec + w[u] * M);
+                }
+            }
             __syncthreads();
             const int ju = (int)max((int64_t)0, min((int64_t)nk, k0 + ku - kc));
-#pragma unroll 4
-            for (int j = 0; j < ju; ++j) {
-                T a[VR];
-                MmUnit<SU>::load(ubase + (kc + j - k0) * ld + lrow, a);
+            for (int j0 = 0; j0 < ju; j0 += B) {
+                typename MmUnit<SU>::Raw raw[B];
 #pragma unroll
-                for (int e = 0; e < VR; ++e)
+                for (int b = 0; b < B; ++b) {
+                    const int j = j0 + b < ju ? j0 + b : ju - 1;
+                    raw[b] = mm_raw(ubase + (kc + j - k0) * ld + lrow);
+                }
+                // straight-line use of all B loads (columns past the part
+                // repeat its last one and count zero), so they stay in flight
 #pragma unroll
-                    for (int c = 0; c < M; ++c) acc[e][c] += a[e] * sw[j * M + c];
+                for (int b = 0; b < B; ++b) {
+                    const int j = j0 + b < ju ? j0 + b : ju - 1;
+                    const T msk = j0 + b < ju ? (T)1 : (T)0;
+                    T a[VR];
+                    MmUnit<SU>::get(raw[b], a);
+                    const T* __restrict__ wj = sw + j * M;
+#pragma unroll
+                    for (int e = 0; e < VR; ++e) {
+                        const T ae = a[e] * msk;
+#pragma unroll
+                        for (int c = 0; c < M; ++c) acc[e][c] += ae * wj[c];
+                    }
+                }
             }
-#pragma unroll 4
-            for (int j = ju; j < nk; ++j) {
-                T a[VR];
-                if constexpr (NR) {
+            if constexpr (NR) {
+                for (int j = ju; j < nk; ++j) {
                     const int64_t pj = widx[kc + j];
                     T y[3];
 #pragma unroll
                     for (int k = 0; k < 3; ++k) y[k] = k < d ? soa[(int64_t)k * n + pj] : (T)0;
+                    T a[VR];
 #pragma unroll
                     for (int e = 0; e < VR; ++e) a[e] = phi(K, py[e], y, d);
-                } else {
-                    MmUnit<SN>::load(nbase + (kc + j - k0 - ku) * ld + lrow, a);
+#pragma unroll
+                    for (int e = 0; e < VR; ++e)
+#pragma unroll
+                        for (int c = 0; c < M; ++c) acc[e][c] += a[e] * sw[j * M + c];
                 }
+            } else {
+                for (int j0 = ju; j0 < nk; j0 += B) {
+                    typename MmUnit<SN>::Raw raw[B];
 #pragma unroll
-                for (int e = 0; e < VR; ++e)
+                    for (int b = 0; b < B; ++b) {
+                        const int j = j0 + b < nk ? j0 + b : nk - 1;
+                        raw[b] = mm_raw(nbase + (kc + j - k0 - ku) * ld + lrow);
+                    }
 #pragma unroll
-                    for (int c = 0; c < M; ++c) acc[e][c] += a[e] * sw[j * M + c];
+                    for (int b = 0; b < B; ++b) {
+                        const int j = j0 + b < nk ? j0 + b : nk - 1;
+                        const T msk = j0 + b < nk ? (T)1 : (T)0;
+                        T a[VR];
+                        MmUnit<SN>::get(raw[b], a);
+                        const T* __restrict__ wj = sw + j * M;
+#pragma unroll
+                        for (int e = 0; e < VR; ++e) {
+                            const T ae = a[e] * msk;
+#pragma unroll
+                            for (int c = 0; c < M; ++c) acc[e][c] += ae * wj[c];
+                        }
+                    }
+                }
             }
         }
         if (row == lrow) {
@@ -272,7 +392,7 @@ hipError_t mm_p1_dispatch(int M, int64_t ntiles, const int32_t* tile_lo, const i
                           int64_t pbase, hipStream_t st) {
     const unsigned g = (unsigned)std::min<int64_t>(ntiles, 1 << 20);
 #define HMX_P1(MM)                                                                             \
-    hipLaunchKernelGGL((mm_p1_kernel<S, T, MM>), dim3(g), dim3(64), 0, st, ntiles, tile_lo,  \
+    hipLaunchKernelGGL((mm_p1_kernel<S, T, MM>), dim3(g), dim3(256), 0, st, ntiles, tile_lo, \
                        meta, ms, R, (const S*)pool, (const T*)vec, (T*)partial, pbase)
     HMX_MM_SWITCH(M, HMX_P1)
 #undef HMX_P1
