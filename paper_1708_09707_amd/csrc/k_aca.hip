@@ -559,16 +559,20 @@ __device__ __noinline__ long long aca_overflow_move(const Overflow& ovf, int m, 
 }
 
 // waves per SIMD the compiler must leave room for: four for the multi-wave
-// classes (their latency-bound steps gain from the occupancy more than the
-// few spilled registers cost), the register-limited default for the
-// single-wave class (whose blocks are many and short)
-template <int NT>
+// classes in FP32 (their latency-bound steps gain from the occupancy more
+// than the 112-128 spilled bytes per lane cost: at two waves, without
+// spills, the N = 2^20 ACA took 46 ms instead of 38), two in FP64 (whose
+// values take twice the registers: at four waves it spilled 480 bytes per
+// lane, and the N = 2^20 FP64 ACA took 137 ms instead of 84), the
+// register-limited default for the single-wave class (whose blocks are many
+// and short)
+template <typename T, int NT>
 constexpr int aca_min_waves() {
-    return NT > kWave ? 4 : 1;
+    return NT > kWave ? (sizeof(T) == 8 ? 2 : 4) : 1;
 }
 
 template <typename T, int NT>
-__global__ __launch_bounds__(NT, aca_min_waves<NT>()) void aca_kernel(
+__global__ __launch_bounds__(NT, (aca_min_waves<T, NT>())) void aca_kernel(
     const T* __restrict__ soa, const double* __restrict__ soa64, int64_t n, int d, KernelEval<T> K,
     const int4* __restrict__ blocks, int64_t nblocks, const int64_t* __restrict__ uoff,
     const int64_t* __restrict__ voff, int64_t ubase, int64_t vbase, int kmax, double eps, double aca_eta, T eps0, int fixed,
