@@ -9,22 +9,24 @@
 // contiguous run.
 //
 //   * gather:    vec[(col0 + i) M + c] = X[perm[col0 + i] - col0 + c ldx];
-//   * phase 1:   T_b = V_b^T X|sigma_b by row tiles: one workgroup of four
-//                waves per tile, the tile's X rows staged in LDS, groups of 8
-//                lanes taking two source columns at a time (eight row vectors
-//                per lane in flight), each lane summing its rows for all M
-//                sides, then a butterfly over the 8 lanes; partials per
+//   * phase 1:   T_b = V_b^T X|sigma_b by row tiles, partial sums per
 //                (column, tile);
 //   * reduce:    the partials of each t entry summed over its tiles in tile
 //                order (as for one vector);
-//   * row tiles: one wave per (tile, pass of 64 x VR rows): each lane owns VR
-//                consecutive rows and accumulates VR x M sums; the column
-//                weights (M per column) are staged in LDS 128 columns at a
-//                time; near-field columns are read from the pool or
-//                evaluated from the coordinates.
+//   * row tiles: Z rows = sum over the tile's columns of column x weights
+//                (factor columns with the t entries, near-field columns with
+//                x), near-field columns read from the pool or evaluated from
+//                the coordinates.
+// With 8 or 16 sides (stored near field) both contractions run on the
+// matrix cores (the mfma kernels below): a stored entry then carries 32
+// flops, more than the vector units sustain at HBM speed.  With 1, 2 or 4
+// sides, or a near field evaluated in the product, they run on the vector
+// units: phase 1 with groups of 8 lanes taking two source columns at a time
+// and a butterfly over the group; row tiles with one wave per pass of 64 VR
+// rows, each lane owning VR consecutive rows, weights staged in LDS.
 // All sums run in a fixed order, so the product is deterministic; column c
 // of the result sums the same terms as the single-vector product of X's
-// column c, in another order (per lane instead of per lane group).
+// column c, in another order.
 #include "hmx_internal.h"
 
 namespace hmx {
@@ -376,6 +378,314 @@ __global__ __launch_bounds__(64) void mm_rowtile_kernel(
     }
 }
 
+// ---- matrix-core forms (8 or 16 right-hand sides) ----
+//
+// Both phases are contractions with 16 right-hand sides on one side, so they
+// run on the 16 x 16 x 4 matrix instructions (FP32 for FP32 and BF16
+// storage, BF16 decoded exactly to FP32; FP64 for FP64).  With 16 sides a
+// stored entry carries 32 flops, which the vector units (FP32 fused
+// multiply-add without packing: half the matrix rate) cannot keep up with at
+// HBM speed.  Lane l = i + 16 k supplies A[i][k] and B[k][j = i]; its four
+// results are D[drow(k, v)][i], v = 0..3, with drow(k, v) = 4 k + v for the
+// FP32 instruction and k + 4 v for the FP64 one.  A lane's 16-byte load holds VR
+// consecutive rows of one column, and element e of it feeds the e-th of VR
+// instructions, so instruction e sums the rows congruent to e mod VR.
+
+typedef float mm_f4 __attribute__((ext_vector_type(4)));
+typedef double mm_d4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MfmaOp;
+template <>
+struct MfmaOp<float> {
+    typedef mm_f4 Acc;
+    static __device__ __forceinline__ Acc mac(float a, float b, Acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int drow(int k, int v) { return 4 * k + v; }
+};
+template <>
+struct MfmaOp<double> {
+    typedef mm_d4 Acc;
+    static __device__ __forceinline__ Acc mac(double a, double b, Acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int drow(int k, int v) { return k + 4 * v; }
+};
+
+// VR consecutive rows of one column in one load (raw 32-bit words, so the
+// load can be marked non-temporal: every entry is read once per product),
+// decoded to the arithmetic type
+typedef uint32_t mm_u4 __attribute__((ext_vector_type(4)));
+typedef uint32_t mm_u2 __attribute__((ext_vector_type(2)));
+template <typename S, int VR>
+struct MfUnit;
+template <>
+struct MfUnit<double, 2> {
+    typedef mm_u4 Raw;
+    static __device__ __forceinline__ void get(const Raw& v, double* o) {
+        o[0] = __builtin_bit_cast(double, ((uint64_t)v.y << 32) | v.x);
+        o[1] = __builtin_bit_cast(double, ((uint64_t)v.w << 32) | v.z);
+    }
+};
+template <>
+struct MfUnit<float, 4> {
+    typedef mm_u4 Raw;
+    static __device__ __forceinline__ void get(const Raw& v, float* o) {
+        o[0] = __uint_as_float(v.x);
+        o[1] = __uint_as_float(v.y);
+        o[2] = __uint_as_float(v.z);
+        o[3] = __uint_as_float(v.w);
+    }
+};
+template <>
+struct MfUnit<uint16_t, 4> {
+    typedef mm_u2 Raw;
+    static __device__ __forceinline__ void get(const Raw& v, float* o) {
+        o[0] = __uint_as_float(v.x << 16);
+        o[1] = __uint_as_float(v.x & 0xffff0000u);
+        o[2] = __uint_as_float(v.y << 16);
+        o[3] = __uint_as_float(v.y & 0xffff0000u);
+    }
+};
+template <>
+struct MfUnit<uint16_t, 8> {
+    typedef mm_u4 Raw;
+    static __device__ __forceinline__ void get(const Raw& v, float* o) {
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            o[2 * i] = __uint_as_float(w[i] << 16);
+            o[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+        }
+    }
+};
+
+// columns [ja, jb) of a staged chunk against their weights: column j's rows
+// for this lane start at base + j ld, its weights at sw[j M].  PB K-steps of
+// four columns are loaded (non-temporal: every entry is read once per
+// product) and only then used; past jb a load repeats column jb - 1 and its
+// weight is zero
+template <typename S, typename T, int M, int VR, int PB>
+__device__ __forceinline__ void mf_rows_part(const S* __restrict__ base, int ld, int ja, int jb,
+                                             const T* __restrict__ sw, int li, int lk,
+                                             typename MfmaOp<T>::Acc (&acc)[VR]) {
+    typedef MfUnit<S, VR> Un;
+    for (int j0 = ja; j0 < jb; j0 += 4 * PB) {
+        typename Un::Raw raw[PB];
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            const int j = j0 + 4 * b + lk;
+            raw[b] = __builtin_nontemporal_load(
+                (const typename Un::Raw*)(base + (int64_t)(j < jb ? j : jb - 1) * ld));
+        }
+        // all PB loads issued before the first use: keeps the scheduler from
+        // sinking them next to their instructions (two in flight otherwise)
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            const int j = j0 + 4 * b + lk;
+            const bool live = j < jb && li < M;
+            const T wv = sw[(live ? j : ja) * M + (li < M ? li : 0)];
+            const T w = live ? wv : (T)0;
+            T a[VR];
+            Un::get(raw[b], a);
+#pragma unroll
+            for (int e = 0; e < VR; ++e) acc[e] = MfmaOp<T>::mac(a[e], w, acc[e]);
+        }
+    }
+}
+
+// row tiles on the matrix cores: a workgroup of nw waves (blockDim.x / 64)
+// per (tile, group of nw slabs); wave w owns the 16 VR rows of its slab and
+// all M <= 16 right-hand sides.  The column weights pass through LDS, one
+// column per staging thread per chunk (KC columns, 16 KB of weights),
+// double-buffered: while a chunk is multiplied, the weights of the next one
+// are loaded into registers and the column indices of the one after are
+// read, so one barrier per chunk remains and no load waits on another.
+// Factor columns first, then the stored near field
+template <typename SU, typename SN, typename T, int M, int VR, int PB>
+__global__ __launch_bounds__(256) void mm_rowtile_mfma_kernel(
+    int64_t ntiles, const int32_t* __restrict__ tile_lo, const int64_t* __restrict__ meta,
+    const int64_t* __restrict__ widx, const SU* __restrict__ upool, const SN* __restrict__ npool,
+    const T* __restrict__ vec, const int32_t* __restrict__ perm, T alpha, T beta, T sigma2,
+    T* __restrict__ Z, int64_t ldz, int R) {
+    typedef MfmaOp<T> Op;
+    constexpr int RS = 16 * VR;              // rows of a wave's slab
+    constexpr int WV = 16 / (int)sizeof(T);  // weights per 16-byte move
+    static_assert(M % WV == 0, "whole 16-byte moves of weights");
+    typedef T WVec __attribute__((ext_vector_type(WV)));
+    constexpr int KCM = 16384 / (M * (int)sizeof(T));  // 16 KB of weights per buffer
+    __shared__ __align__(16) T sw[2][KCM * M];
+    const int nw = (int)(blockDim.x >> 6);
+    const int KC = min((int)blockDim.x, KCM);  // columns per chunk: one per staging thread
+    const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int li = lane & 15, lk = lane >> 4;
+    const int me = (int)threadIdx.x;
+    const bool stager = me < KC;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int32_t r0 = tile_lo[t];
+        const int mt = tile_lo[t + 1] - r0;
+        const int ld = mm_ld(mt, R);
+        const int slab0 = (int)blockIdx.y * nw * RS;
+        if (slab0 >= ld) continue;  // the same for the whole workgroup
+        const int slab = slab0 + wv * RS;
+        const bool active = slab < ld;
+        // loads stay inside the column (a clamped lane's rows are past ld and discarded)
+        const int lrow = min(slab + li * VR, ld - VR);
+        const int64_t k0 = meta[4 * t], k1 = meta[4 * t + 4];
+        const int64_t ku = meta[4 * t + 5] - meta[4 * t + 1];
+        const SU* __restrict__ ubase = upool + meta[4 * t + 2] + lrow;
+        const SN* __restrict__ nbase = npool + meta[4 * t + 3] + lrow;
+        typename Op::Acc acc[VR];
+#pragma unroll
+        for (int e = 0; e < VR; ++e)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[e][v] = 0;
+        // this thread's column of chunk c is k0 + c KC + me
+        const int nch = (int)((k1 - k0 + KC - 1) / KC);
+        int64_t idx_next = stager && k0 + KC + me < k1 ? widx[k0 + KC + me] : 0;  // chunk 1
+        {
+            const bool own = stager && k0 + me < k1;
+            const int64_t i0 = own ? widx[k0 + me] : 0;
+            if (own)
+#pragma unroll
+                for (int c = 0; c < M; c += WV)
+                    *(WVec*)(&sw[0][me * M + c]) = *(const WVec*)(vec + i0 * M + c);
+        }
+        __syncthreads();
+        for (int ch = 0; ch < nch; ++ch) {
+            const int64_t kc = k0 + (int64_t)ch * KC;
+            const int nk = (int)min((int64_t)KC, k1 - kc);
+            // the next chunk's weights into registers, the indices of the one after
+            WVec wr[M / WV];
+            const bool has_next = stager && kc + KC + me < k1;
+            if (has_next)
+#pragma unroll
+                for (int c = 0; c < M / WV; ++c) wr[c] = *(const WVec*)(vec + idx_next * M + c * WV);
+            idx_next = stager && kc + 2 * KC + me < k1 ? widx[kc + 2 * KC + me] : 0;
+            if (active) {
+                const T* __restrict__ swc = sw[ch & 1];
+                const int ju = (int)max((int64_t)0, min((int64_t)nk, k0 + ku - kc));
+                if (ju > 0)
+                    mf_rows_part<SU, T, M, VR, PB>(ubase + (kc - k0) * ld, ld, 0, ju, swc, li, lk,
+                                                   acc);
+                if (ju < nk)
+                    mf_rows_part<SN, T, M, VR, PB>(nbase + (kc - k0 - ku) * ld, ld, ju, nk, swc,
+                                                   li, lk, acc);
+            }
+            if (has_next)
+#pragma unroll
+                for (int c = 0; c < M / WV; ++c) *(WVec*)(&sw[(ch + 1) & 1][me * M + c * WV]) = wr[c];
+            __syncthreads();
+        }
+        if (active && li < M) {
+#pragma unroll
+            for (int e = 0; e < VR; ++e)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = slab + VR * Op::drow(lk, v) + e;
+                    if (row >= mt) continue;
+                    const int64_t gi = r0 + row;
+                    const int64_t zi = perm[gi] + li * ldz;
+                    T s = acc[e][v];
+                    if (sigma2 != (T)0) s += sigma2 * vec[gi * M + li];
+                    T out = alpha * s;
+                    if (beta != (T)0) out += beta * Z[zi];
+                    Z[zi] = out;
+                }
+        }
+    }
+}
+
+// phase 1 on the matrix cores: T = V^T X per row tile, the contraction over
+// the tile's rows.  A wave takes 16 source columns (lane i's column cb + i)
+// and runs down all rows, 4 VR per K-step; the tile's X rows are staged in
+// LDS transposed (side-major, row stride XT), so a lane's VR rows of one side
+// are one contiguous read; wider tiles read X from the vector itself
+template <typename S, typename T, int M, int VR>
+__global__ __launch_bounds__(256) void mm_p1_mfma_kernel(int64_t ntiles,
+                                                         const int32_t* __restrict__ tile_lo,
+                                                         const int64_t* __restrict__ meta,
+                                                         int ms, int R,
+                                                         const S* __restrict__ pool,
+                                                         const T* __restrict__ vec,
+                                                         T* __restrict__ partial, int64_t pbase) {
+    typedef MfmaOp<T> Op;
+    typedef MfUnit<S, VR> Un;
+    constexpr int KS = 4 * VR;                       // rows per K-step
+    constexpr int PB = 8;                            // K-steps in flight
+    constexpr int SROWS = 256;                       // rows of X staged in LDS
+    constexpr int XT = SROWS + 16 / (int)sizeof(T);  // padded: 8 lanes' reads on distinct banks
+    __shared__ __align__(16) T sx[M * XT];
+    const int nw = (int)(blockDim.x >> 6);
+    const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int li = lane & 15, lk = lane >> 4;
+    const int lj = li < M ? li : 0;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t c0 = meta[ms * t + 1];
+        const int nc = (int)(meta[ms * (t + 1) + 1] - c0);
+        if (nc <= 0) continue;
+        const int32_t r0 = tile_lo[t];
+        const int mt = tile_lo[t + 1] - r0;
+        const int ld = mm_ld(mt, R);
+        const int kr = (ld + KS - 1) / KS * KS;  // rows padded to whole K-steps
+        const S* __restrict__ base = pool + meta[ms * t + 2];
+        const bool staged = kr <= SROWS;
+        if (staged) {
+            for (int i = (int)threadIdx.x; i < kr * M; i += (int)blockDim.x) {
+                const int row = i / M, j = i % M;
+                sx[j * XT + row] = row < mt ? vec[(int64_t)(r0 + row) * M + j] : (T)0;
+            }
+            __syncthreads();
+        }
+        for (int cb = wv * 16; cb < nc; cb += nw * 16) {
+            // columns past nc repeat the last one; their sums are not stored
+            const S* __restrict__ cp = base + (int64_t)min(cb + li, nc - 1) * ld;
+            typename Op::Acc acc;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] = 0;
+            for (int k0 = 0; k0 < kr; k0 += KS * PB) {
+                typename Un::Raw raw[PB];
+#pragma unroll
+                for (int b = 0; b < PB; ++b) {
+                    const int r = k0 + KS * b + VR * lk;
+                    raw[b] = __builtin_nontemporal_load(
+                        (const typename Un::Raw*)(cp + (r < ld ? r : ld - VR)));
+                }
+                __builtin_amdgcn_sched_barrier(0);  // every load in flight before the first use
+#pragma unroll
+                for (int b = 0; b < PB; ++b) {
+                    const int r = k0 + KS * b + VR * lk;
+                    T a[VR], xb[VR];
+                    Un::get(raw[b], a);
+                    if (staged) {
+                        const T* xp = sx + lj * XT + (r < kr ? r : 0);
+#pragma unroll
+                        for (int e = 0; e < VR; ++e) xb[e] = (r < kr && li < M) ? xp[e] : (T)0;
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VR; ++e)
+                            xb[e] = (r + e < mt && li < M)
+                                        ? vec[(int64_t)(r0 + (r + e < mt ? r + e : 0)) * M + lj]
+                                        : (T)0;
+                    }
+#pragma unroll
+                    for (int e = 0; e < VR; ++e) acc = Op::mac(a[e], xb[e], acc);
+                }
+            }
+            if (li < M) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int c = cb + Op::drow(lk, v);
+                    if (c < nc) partial[(pbase + c0 + c) * M + li] = acc[v];
+                }
+            }
+        }
+        if (staged) __syncthreads();  // sx is refilled by the next tile
+    }
+}
+
 #define HMX_MM_SWITCH(M, CALL) \
     switch (M) {               \
         case 1: CALL(1); break; \
@@ -421,6 +731,31 @@ hipError_t launch_mm_p1(int M, int64_t ntiles, const int32_t* tile_lo, const int
                         int ms, int R, const void* pool, const void* vec, void* partial,
                         int64_t pbase, int smode, hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
+    if (M == 8 || M == 16) {
+        // matrix cores; R (entries per 16 bytes) is a multiple of the load's rows
+        const unsigned g = (unsigned)std::min<int64_t>(ntiles, 1 << 20);
+#define HMX_P1M(S, T, VR)                                                                       \
+    if (M == 8)                                                                                 \
+        hipLaunchKernelGGL((mm_p1_mfma_kernel<S, T, 8, VR>), dim3(g), dim3(256), 0, st, ntiles,  \
+                           tile_lo, meta, ms, R, (const S*)pool, (const T*)vec, (T*)partial,     \
+                           pbase);                                                              \
+    else                                                                                        \
+        hipLaunchKernelGGL((mm_p1_mfma_kernel<S, T, 16, VR>), dim3(g), dim3(256), 0, st, ntiles, \
+                           tile_lo, meta, ms, R, (const S*)pool, (const T*)vec, (T*)partial,     \
+                           pbase)
+        if (smode == 0) {
+            if (R % 2) return hipErrorInvalidValue;
+            HMX_P1M(double, double, 2);
+        } else if (smode == 1) {
+            if (R % 4) return hipErrorInvalidValue;
+            HMX_P1M(float, float, 4);
+        } else {
+            if (R % 8) return hipErrorInvalidValue;
+            HMX_P1M(uint16_t, float, 8);
+        }
+#undef HMX_P1M
+        return hipGetLastError();
+    }
     if (smode == 0)
         return mm_p1_dispatch<double, double>(M, ntiles, tile_lo, meta, ms, R, pool, vec, partial,
                                               pbase, st);
@@ -448,6 +783,13 @@ hipError_t launch_mm_p1_reduce(int M, const int4* rec, int64_t ncols, const int6
     return hipGetLastError();
 }
 
+#ifndef HMX_MM_PB
+#define HMX_MM_PB 16
+#endif
+#ifndef HMX_MM_BF16_VR
+#define HMX_MM_BF16_VR 8
+#endif
+
 hipError_t launch_mm_rowtile(int M, int64_t ntiles, const int32_t* tile_lo, const int64_t* meta,
                              const int64_t* widx, const void* upool, const void* npool,
                              const void* vec, const int32_t* perm, double alpha, double beta,
@@ -455,6 +797,37 @@ hipError_t launch_mm_rowtile(int M, int64_t ntiles, const int32_t* tile_lo, cons
                              int fmode, int nmode, const void* soa, int64_t n, int d,
                              KernelFn kern, hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
+    if ((M == 8 || M == 16) && nmode != 3) {
+        // matrix cores: a wave per slab of 16 VR rows, up to four slabs per workgroup
+        const int vr = fmode == 0 ? 2 : (fmode == 2 && nmode == 2 ? HMX_MM_BF16_VR : 4);
+        if (R % vr) return hipErrorInvalidValue;
+        const int ldmax = mm_ld(max_tile, R), rs = 16 * vr;
+        const int nw = std::max(1, std::min(4, (ldmax + rs - 1) / rs));
+        const unsigned passes = (unsigned)((ldmax + nw * rs - 1) / (nw * rs));
+        const dim3 grid((unsigned)std::min<int64_t>(ntiles, 1 << 20), passes);
+#define HMX_RTM(SU, SN, T, VR)                                                                   \
+    if (M == 8)                                                                                  \
+        hipLaunchKernelGGL((mm_rowtile_mfma_kernel<SU, SN, T, 8, VR, HMX_MM_PB>), grid, dim3(64 * nw), 0, st, \
+                           ntiles, tile_lo, meta, widx, (const SU*)upool, (const SN*)npool,      \
+                           (const T*)vec, perm, (T)alpha, (T)beta, (T)sigma2, (T*)Z, ldz, R);     \
+    else                                                                                         \
+        hipLaunchKernelGGL((mm_rowtile_mfma_kernel<SU, SN, T, 16, VR, HMX_MM_PB>), grid, dim3(64 * nw), 0,   \
+                           st, ntiles, tile_lo, meta, widx, (const SU*)upool, (const SN*)npool,  \
+                           (const T*)vec, perm, (T)alpha, (T)beta, (T)sigma2, (T*)Z, ldz, R)
+        if (fmode == 0 && nmode == 0) {
+            HMX_RTM(double, double, double, 2);
+        } else if (fmode == 1 && nmode == 1) {
+            HMX_RTM(float, float, float, 4);
+        } else if (fmode == 2 && nmode == 2) {
+            HMX_RTM(uint16_t, uint16_t, float, HMX_MM_BF16_VR);
+        } else if (fmode == 2 && nmode == 1) {
+            HMX_RTM(uint16_t, float, float, 4);
+        } else {
+            return hipErrorInvalidValue;
+        }
+#undef HMX_RTM
+        return hipGetLastError();
+    }
     const int vr = fmode == 0 ? 2 : 4;
     const unsigned passes = (unsigned)((mm_ld(max_tile, R) + 64 * vr - 1) / (64 * vr));
     const dim3 grid((unsigned)std::min<int64_t>(ntiles, 1 << 20), passes);

@@ -136,3 +136,43 @@ def test_matmat_refusals(H):
     with pytest.raises(H.HmxError):  # dtype must be the compute dtype
         H.hmx_matmat(hs.h, X.float(), X.float().clone())
     hs.close()
+
+
+# Two summation orders of K terms differ by about sqrt(K) u relative to the
+# result (random signs); a 600-point tile sums about 10^4 columns per row,
+# so FP32 (u = 2^-24) allows 8 sqrt(10^4) u = 5e-6 there, 2e-6 on 256-point
+# tiles (about 3 10^3 columns).
+WIDE = [  # compute, storage, near, leaf: 256-row tiles (four waves per workgroup), 600-row
+    # tiles (row passes, phase 1 reading X from the vector), ragged tile sizes
+    ("f64", "f64", "f64", 256, 1e-13),
+    ("f32", "f32", "f32", 256, 2e-6),
+    ("f32", "bf16", "bf16", 256, 2e-6),
+    ("f32", "bf16", "f32", 256, 2e-6),
+    ("f64", "f64", "f64", 600, 1e-13),
+    ("f32", "bf16", "bf16", 600, 5e-6),
+]
+
+
+@pytest.mark.parametrize("mode", WIDE)
+def test_matmat_wide_tiles_matrix_cores(H, mode):
+    """The matrix-core forms (8 and 16 sides) on tiles of 150-256 and 300-600
+    rows: every column equals the single-vector product to rounding."""
+    cd, sd, nd, leaf, tol = mode
+    n, m = 45000, 24  # 16 + 8 sides; N not a power of two: tile sizes differ
+    dt = np.float64 if cd == "f64" else np.float32
+    pts = synth.uniform_points(n, 2, 740, dtype=dt)
+    print("build: N=%d d=2 %s/%s/%s leaf %d, %d right-hand sides" % (n, cd, sd, nd, leaf, m),
+          flush=True)
+    hm = H.HMatrix(_dev(pts), "gaussian", 0.02, compute_dtype=cd, storage_dtype=sd,
+                   near_dtype=nd, leaf_size=leaf, eta=1.5, aca_eps=1e-6, max_rank=32, sigma2=0.1)
+    g = synth.rng(741)
+    X = _dev(g.standard_normal((m, n)).astype(dt))
+    Z0 = _dev(g.standard_normal((m, n)).astype(dt))
+    Z = Z0.clone()
+    H.hmx_matmat(hm.h, X, Z, 1.25, 0.5)
+    ref = _columns(H, hm, X, Z0, 1.25, 0.5)
+    worst = max(_rel(Z[c].double().cpu().numpy(), ref[c].double().cpu().numpy())
+                for c in range(m))
+    print("  worst column vs matvec: %.2e" % worst, flush=True)
+    assert worst <= tol
+    hm.close()
