@@ -439,13 +439,15 @@ def multi_rhs_leg(torch, H, log, wl, pts_d, reps=5):
     n = wl["n"]
     out = {}
     for form, kw in (("plain_f32", dict(compute_dtype="f32")),
-                     ("bf16", dict(compute_dtype="f32", storage_dtype="bf16"))):
+                     ("bf16", dict(compute_dtype="f32", storage_dtype="bf16")),
+                     ("plain_f64", dict(compute_dtype="f64"))):
         hm = H.HMatrix(pts_d, wl["kernel"], wl["p0"], leaf_size=wl["leaf"], eta=wl["eta"],
                        aca_eps=wl["eps"], max_rank=wl["kmax"], **kw)
         st = hm.stats()
+        dt = np.float64 if form == "plain_f64" else np.float32
         res = {}
         for m in (4, 16, 64):
-            X = torch.from_numpy(synth.rng(7300 + m).standard_normal((m, n)).astype(np.float32)).cuda()
+            X = torch.from_numpy(synth.rng(7300 + m).standard_normal((m, n)).astype(dt)).cuda()
             Z = torch.empty_like(X)
             hm.matmat(X[:1], Z[:1])  # work vectors allocated outside the timing
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -456,7 +458,7 @@ def multi_rhs_leg(torch, H, log, wl, pts_d, reps=5):
             e1.record()
             torch.cuda.synchronize()
             mm_ms = e0.elapsed_time(e1) / reps
-            z = torch.empty(n, dtype=torch.float32, device=X.device)
+            z = torch.empty(n, dtype=X.dtype, device=X.device)
             e0.record()
             for _ in range(reps):
                 for c in range(m):
@@ -464,7 +466,7 @@ def multi_rhs_leg(torch, H, log, wl, pts_d, reps=5):
             e1.record()
             torch.cuda.synchronize()
             mv_ms = e0.elapsed_time(e1) / reps
-            ref = torch.empty(n, dtype=torch.float32, device=X.device)
+            ref = torch.empty(n, dtype=X.dtype, device=X.device)
             H.hmx_matvec(hm.h, X[m - 1], ref)
             err = (torch.linalg.norm(Z[m - 1].double() - ref.double()) /
                    torch.linalg.norm(ref.double())).item()
@@ -639,6 +641,11 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the measured FP64 form (no predictor training, no other forms "
                          "or legs): the run the hardware counters are taken on")
+    ap.add_argument("--leg", choices=("multi_rhs", "n22_aca", "aca_n20"), default=None,
+                    help="run one leg only and print its JSON (the runs the kernel-time and "
+                         "counter summaries are taken on): several right-hand sides on the bench "
+                         "workload, the N = 2^22 builds up to the ACA, or plain FP32 builds up to "
+                         "the ACA on the bench workload")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -672,6 +679,24 @@ def main():
     kern = H.make_kernel(wl["kernel"], wl["p0"])
     stream = torch.cuda.current_stream()
 
+    if args.leg is not None:
+        if args.leg == "multi_rhs":
+            res = multi_rhs_leg(torch, H, log, wl, pts_d)
+        elif args.leg == "n22_aca":
+            res = n22_aca_builds(torch, H, log, full=False)
+        else:
+            res = {}
+            for rep in range(3):
+                hm = H.HMatrix(pts_d, wl["kernel"], wl["p0"], compute_dtype="f32",
+                               leaf_size=wl["leaf"], eta=wl["eta"], aca_eps=wl["eps"],
+                               max_rank=wl["kmax"], aca_only=1)
+                st = hm.stats()
+                res = {"aca_ms": st.phase_ms[3], "aca_kernel_evals": st.aca_kernel_evals,
+                       "n_adm": st.n_adm, "sum_rank": st.sum_rank}
+                log("bench: ACA-only build #%d: ACA %.1f ms" % (rep, st.phase_ms[3]))
+                hm.close()
+        print(json.dumps({"leg": args.leg, "workload": args.workload, args.leg: res}), flush=True)
+        return
     mixed_eps = wl.get("mixed_eps", wl["eps"])
     mlp, train_info = (None, None) if args.headline_only else train_predictor(
         torch, H, wl, mixed_eps, log)

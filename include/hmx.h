@@ -347,7 +347,10 @@ hmx_status hmx_matvec(hmx_hmatrix h, const void* x, void* z, hmx_dtype vec_dtype
 /* Z := alpha (H + sigma2 I) X + beta Z for m right-hand sides (the product
  * of Algorithm 3 for a block of vectors; for many vectors V^T X and the row
  * tiles become products with m columns).  Every stored entry is read once
- * per group of up to 16 right-hand sides.
+ * per group of up to 16 right-hand sides: groups of 16, the rest as one
+ * group (on the matrix cores, padded to 8 or 16 with zero sides, when the
+ * near field is stored; in power-of-two groups when it is evaluated in the
+ * product), a last single side as hmx_matvec.
  *   X : device, column-major stats.cols x m, leading dimension ldx >= cols
  *       (right-hand side c at X + c ldx, original point order);
  *   Z : device, column-major stats.rows x m, leading dimension ldz >= rows;
@@ -409,11 +412,9 @@ hmx_status hmx_graph_destroy(hmx_graph g);
  * launch.  Host-blocking. */
 hmx_status hmx_autotune(hmx_hmatrix h, int32_t reps, void* stream, int32_t* choice,
                         double* times_ms);
-/* Select a row-tile configuration directly (-1: the default, which is the
- * narrowest shape covering the handle's largest tile in one pass on the
- * one-workgroup-per-tile grid, or configuration 10 when the handle has fewer
- * than 2048 tiles or evaluates its near field in the product; and the
- * default phase-1 lanes too, so a handle returns to its untuned products). */
+/* Select a row-tile configuration directly (-1: the default, configuration
+ * 10, one workgroup per 16-lane row pass of a tile; and the default phase-1
+ * lanes too, so a handle returns to its untuned products). */
 hmx_status hmx_set_tile_config(hmx_hmatrix h, int32_t config);
 
 /* Conjugate gradients for (H + sigma2 I) c = b, the kernel ridge regression

@@ -760,8 +760,11 @@ struct AcaPlan {
 // default keeps the many-workgroup path for blocks whose bitmasks would not
 // fit a workgroup's LDS
 constexpr int64_t kDefaultSplitRows = (int64_t)1 << 18;
+// (one-wave class up to 512 points rather than 256: N = 2^22 3-d ACA
+// 3.36 -> 3.16 s, N = 2^20 2-d 38 -> 34.5 ms, the same ranks; the 512-thread
+// cut at 4096 or 8192 points makes no measurable difference)
 constexpr int64_t kBigRows = 4096;
-constexpr int64_t kTinyRows = 256;
+constexpr int64_t kTinyRows = 512;
 
 // size classes of a single problem by tree level: clusters at level l hold at
 // most s_l points (s_0 = n, s_{l+1} = ceil(s_l / 2)); levels whose clusters
@@ -2789,13 +2792,33 @@ hmx_status hmx_matmat(hmx_hmatrix h, const void* X, int64_t ldx, void* Z, int64_
         const int64_t np1 = (h->sym ? h->ncols_u : 0) + h->ncols_v;
         ensure(h->mm_partial, (size_t)std::max<int64_t>(np1, 1) * kMaxM * esz, st,
                "multi-RHS partial sums");
+        // groups: 16 sides at a time; the rest in one group padded to 8 or 16
+        // zero sides when the row tiles run on the matrix cores (stored near
+        // field: a padded group costs the same stream of stored entries),
+        // else in power-of-two groups; a single remaining side is an
+        // ordinary matvec
+        const bool cores = h->nmode != 3;
         for (int32_t c0 = 0; c0 < m;) {
-            int M = kMaxM;
-            while (M > m - c0) M >>= 1;
+            const int32_t left = m - c0;
             const void* Xc = (const char*)X + (size_t)c0 * ldx * esz;
             void* Zc = (char*)Z + (size_t)c0 * ldz * esz;
+            if (left == 1) {
+                check(matvec_launch(h, Xc, Zc, alpha, beta, st, nullptr, h->rt_config),
+                      "multi-RHS (one side)");
+                break;
+            }
+            int M = kMaxM, mr = kMaxM;
+            if (left < kMaxM) {
+                if (cores) {
+                    M = left > 8 ? 16 : 8;
+                    mr = left;
+                } else {
+                    while (M > left) M >>= 1;
+                    mr = M;
+                }
+            }
             check(launch_mm_gather(Xc, ldx, h->perm.as<int32_t>(), h->ncols, h->col0, h->mm_vec.p,
-                                   M, f64, st),
+                                   M, mr, f64, st),
                   "multi-RHS gather");
             if (h->sym && h->ncols_u > 0)
                 check(launch_mm_p1(M, h->ntiles, h->tile_lo.as<int32_t>(),
@@ -2815,9 +2838,9 @@ hmx_status hmx_matmat(hmx_hmatrix h, const void* X, int64_t ldx, void* Z, int64_
                                     h->upool.p, h->npool.p, h->mm_vec.p, h->perm.as<int32_t>(),
                                     alpha, beta, h->prm.sigma2, Zc, ldz, h->Ru, h->max_tile,
                                     h->smode, h->nmode, f64 ? h->soa64.p : h->soa32.p, h->n, h->d,
-                                    kernel_fn(h->kern, h->kd), st),
+                                    kernel_fn(h->kern, h->kd), mr, st),
                   "multi-RHS row tiles");
-            c0 += M;
+            c0 += mr;
         }
     });
 }

@@ -610,9 +610,10 @@ hipError_t launch_np_apply(const int64_t* seg_start, const int32_t* seg_tile, in
                            hipStream_t st);
 
 // several right-hand sides (k_mm.hip), M in {1, 2, 4, 8, 16} per launch:
-// vectors point-major (vec[i * M + c])
+// vectors point-major (vec[i * M + c]); mr <= M real sides (the matrix-core
+// forms pad a group to M = 8 or 16 with zero sides, the others take mr = M)
 hipError_t launch_mm_gather(const void* X, int64_t ldx, const int32_t* perm, int64_t ncols,
-                            int64_t col0, void* vec, int M, int f64, hipStream_t st);
+                            int64_t col0, void* vec, int M, int mr, int f64, hipStream_t st);
 hipError_t launch_mm_p1(int M, int64_t ntiles, const int32_t* tile_lo, const int64_t* meta,
                         int ms, int R, const void* pool, const void* vec, void* partial,
                         int64_t pbase, int smode, hipStream_t st);
@@ -624,6 +625,6 @@ hipError_t launch_mm_rowtile(int M, int64_t ntiles, const int32_t* tile_lo, cons
                              const void* vec, const int32_t* perm, double alpha, double beta,
                              double sigma2, void* Z, int64_t ldz, int R, int max_tile,
                              int fmode, int nmode, const void* soa, int64_t n, int d,
-                             KernelFn kern, hipStream_t st);
+                             KernelFn kern, int mr, hipStream_t st);
 
 }  // namespace hmx

@@ -3,7 +3,7 @@
 // One workgroup per admissible block, each running its own rank loop, so
 // blocks stop independently (no global "voting" bounded by the slowest
 // block).  Blocks of the upper tree levels (many rows) get 512-thread
-// workgroups, those of the leaf levels (at most 256 rows) one wave, the rest
+// workgroups, those of the lowest levels (at most 512 rows) one wave, the rest
 // 256 threads (the very largest run on many workgroups each, k_aca_split.hip);
 // every chunk of blocks handed to the ACA is level-sorted (the canonical leaf
 // order is level order; a list cut into several chunks is first reordered so

@@ -94,15 +94,16 @@ inline unsigned mm_grid(int64_t n, int b = 256) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + b - 1) / b, 1 << 20));
 }
 
+// sides c >= mr (a group padded to the matrix cores' width) are zero
 template <typename T, int M>
 __global__ void mm_gather_kernel(const T* __restrict__ X, int64_t ldx,
                                  const int32_t* __restrict__ perm, int64_t ncols, int64_t col0,
-                                 T* __restrict__ vec) {
+                                 int mr, T* __restrict__ vec) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ncols * M;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = e / M;
         const int c = (int)(e % M);
-        vec[(col0 + i) * M + c] = X[(perm[col0 + i] - col0) + c * ldx];
+        vec[(col0 + i) * M + c] = c < mr ? X[(perm[col0 + i] - col0) + c * ldx] : (T)0;
     }
 }
 
@@ -509,7 +510,7 @@ __global__ __launch_bounds__(256) void mm_rowtile_mfma_kernel(
     int64_t ntiles, const int32_t* __restrict__ tile_lo, const int64_t* __restrict__ meta,
     const int64_t* __restrict__ widx, const SU* __restrict__ upool, const SN* __restrict__ npool,
     const T* __restrict__ vec, const int32_t* __restrict__ perm, T alpha, T beta, T sigma2,
-    T* __restrict__ Z, int64_t ldz, int R) {
+    T* __restrict__ Z, int64_t ldz, int R, int mr) {
     typedef MfmaOp<T> Op;
     constexpr int RS = 16 * VR;              // rows of a wave's slab
     constexpr int WV = 16 / (int)sizeof(T);  // weights per 16-byte move
@@ -579,7 +580,7 @@ __global__ __launch_bounds__(256) void mm_rowtile_mfma_kernel(
                 for (int c = 0; c < M / WV; ++c) *(WVec*)(&sw[(ch + 1) & 1][me * M + c * WV]) = wr[c];
             __syncthreads();
         }
-        if (active && li < M) {
+        if (active && li < mr) {  // the group's real sides (mr <= M)
 #pragma unroll
             for (int e = 0; e < VR; ++e)
 #pragma unroll
@@ -712,16 +713,17 @@ hipError_t mm_p1_dispatch(int M, int64_t ntiles, const int32_t* tile_lo, const i
 }  // namespace
 
 hipError_t launch_mm_gather(const void* X, int64_t ldx, const int32_t* perm, int64_t ncols,
-                            int64_t col0, void* vec, int M, int f64, hipStream_t st) {
+                            int64_t col0, void* vec, int M, int mr, int f64, hipStream_t st) {
     if (ncols <= 0) return hipSuccess;
+    if (mr < 1 || mr > M) return hipErrorInvalidValue;
     const unsigned g = mm_grid(ncols * M);
 #define HMX_G(MM)                                                                               \
     if (f64)                                                                                    \
         hipLaunchKernelGGL((mm_gather_kernel<double, MM>), dim3(g), dim3(256), 0, st,          \
-                           (const double*)X, ldx, perm, ncols, col0, (double*)vec);            \
+                           (const double*)X, ldx, perm, ncols, col0, mr, (double*)vec);        \
     else                                                                                        \
         hipLaunchKernelGGL((mm_gather_kernel<float, MM>), dim3(g), dim3(256), 0, st,           \
-                           (const float*)X, ldx, perm, ncols, col0, (float*)vec)
+                           (const float*)X, ldx, perm, ncols, col0, mr, (float*)vec)
     HMX_MM_SWITCH(M, HMX_G)
 #undef HMX_G
     return hipGetLastError();
@@ -795,8 +797,9 @@ hipError_t launch_mm_rowtile(int M, int64_t ntiles, const int32_t* tile_lo, cons
                              const void* vec, const int32_t* perm, double alpha, double beta,
                              double sigma2, void* Z, int64_t ldz, int R, int max_tile,
                              int fmode, int nmode, const void* soa, int64_t n, int d,
-                             KernelFn kern, hipStream_t st) {
+                             KernelFn kern, int mr, hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
+    if (mr < 1 || mr > M) return hipErrorInvalidValue;
     if ((M == 8 || M == 16) && nmode != 3) {
         // matrix cores: a wave per slab of 16 VR rows, up to four slabs per workgroup
         const int vr = fmode == 0 ? 2 : (fmode == 2 && nmode == 2 ? HMX_MM_BF16_VR : 4);
@@ -809,11 +812,11 @@ hipError_t launch_mm_rowtile(int M, int64_t ntiles, const int32_t* tile_lo, cons
     if (M == 8)                                                                                  \
         hipLaunchKernelGGL((mm_rowtile_mfma_kernel<SU, SN, T, 8, VR, HMX_MM_PB>), grid, dim3(64 * nw), 0, st, \
                            ntiles, tile_lo, meta, widx, (const SU*)upool, (const SN*)npool,      \
-                           (const T*)vec, perm, (T)alpha, (T)beta, (T)sigma2, (T*)Z, ldz, R);     \
+                           (const T*)vec, perm, (T)alpha, (T)beta, (T)sigma2, (T*)Z, ldz, R, mr); \
     else                                                                                         \
         hipLaunchKernelGGL((mm_rowtile_mfma_kernel<SU, SN, T, 16, VR, HMX_MM_PB>), grid, dim3(64 * nw), 0,   \
                            st, ntiles, tile_lo, meta, widx, (const SU*)upool, (const SN*)npool,  \
-                           (const T*)vec, perm, (T)alpha, (T)beta, (T)sigma2, (T*)Z, ldz, R)
+                           (const T*)vec, perm, (T)alpha, (T)beta, (T)sigma2, (T*)Z, ldz, R, mr)
         if (fmode == 0 && nmode == 0) {
             HMX_RTM(double, double, double, 2);
         } else if (fmode == 1 && nmode == 1) {
@@ -828,6 +831,7 @@ hipError_t launch_mm_rowtile(int M, int64_t ntiles, const int32_t* tile_lo, cons
 #undef HMX_RTM
         return hipGetLastError();
     }
+    if (mr != M) return hipErrorInvalidValue;  // the vector-unit forms take whole groups
     const int vr = fmode == 0 ? 2 : 4;
     const unsigned passes = (unsigned)((mm_ld(max_tile, R) + 64 * vr - 1) / (64 * vr));
     const dim3 grid((unsigned)std::min<int64_t>(ntiles, 1 << 20), passes);

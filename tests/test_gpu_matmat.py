@@ -176,3 +176,32 @@ def test_matmat_wide_tiles_matrix_cores(H, mode):
     print("  worst column vs matvec: %.2e" % worst, flush=True)
     assert worst <= tol
     hm.close()
+
+
+@pytest.mark.parametrize("sd", ["f32", "bf16", "f64"])
+def test_matmat_padded_groups(H, sd):
+    """Groups of 3, 5, 13 and 17 sides (the rest of 16 padded with zero sides on
+    the matrix cores, a last single side as a matvec): every column equals the
+    single-vector product to rounding, and memory past Z's m columns is never
+    written."""
+    cd = "f64" if sd == "f64" else "f32"
+    dt = np.float64 if cd == "f64" else np.float32
+    tol = 1e-13 if cd == "f64" else 2e-6
+    n = 20000
+    pts = synth.uniform_points(n, 2, 750, dtype=dt)
+    hm = H.HMatrix(_dev(pts), "gaussian", 0.02, compute_dtype=cd, storage_dtype=sd,
+                   leaf_size=256, eta=1.5, aca_eps=1e-6, max_rank=32, sigma2=0.2)
+    g = synth.rng(751)
+    for m in (3, 5, 13, 17):
+        print("storage %s, %d sides" % (sd, m), flush=True)
+        X = _dev(g.standard_normal((m, n)).astype(dt))
+        Zall = _dev(g.standard_normal((m + 2, n)).astype(dt))
+        before = Zall.clone()
+        Z = Zall[:m]
+        H.hmx_matmat(hm.h, X, Z, 0.5, 2.0)
+        assert torch.equal(Zall[m:], before[m:]), "rows past the m sides were written"
+        ref = _columns(H, hm, X, before[:m], 0.5, 2.0)
+        worst = max(_rel(Z[c].double().cpu().numpy(), ref[c].double().cpu().numpy())
+                    for c in range(m))
+        assert worst <= tol, (m, worst)
+    hm.close()
