@@ -420,6 +420,53 @@ def krr_leg(torch, H, log, cg_iters=400, nrows=1024):
     return res_out
 
 
+def krr_sizes_leg(torch, H, log, sizes=(1 << 14, 1 << 16, 1 << 18), max_iter=6000):
+    """The kernel ridge regression system of the N = 2^22 configuration
+    (32-component Gaussian mixture in [0,1]^3, Matern-3/2 l = 0.1,
+    (A + 1e-2 I) c = y, CG to relative residual 1e-6, FP64 inner products) at
+    sizes where the solve is affordable, in three arithmetics, each with the
+    symmetric far field (H exactly symmetric), leaf 64, eta 1.5: FP64 (ACA eps
+    1e-8), FP32 (eps 1e-6) and the configuration's own BF16 factors and near
+    field (eps 1e-4).  Iterations, seconds, the recurrence and the true
+    residual, or the breakdown (p.Ap <= 0: the operator is not definite)."""
+    ell, sigma2 = 0.1, 1e-2
+    forms = (("f64", dict(compute_dtype="f64", aca_eps=1e-8, max_rank=128)),
+             ("f32", dict(compute_dtype="f32", aca_eps=1e-6, max_rank=96)),
+             ("bf16", dict(compute_dtype="f32", storage_dtype="bf16", aca_eps=1e-4, max_rank=64)))
+    out = {}
+    for n in sizes:
+        pts = synth.gmm_points(n, 3, 31)
+        y = synth.krr_target(pts, 32)
+        res_n = {}
+        for form, kw in forms:
+            dt = torch.float64 if form == "f64" else torch.float32
+            pts_d = torch.from_numpy(pts).to(dt).cuda()
+            y_d = torch.from_numpy(y).to(dt).cuda()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hm = H.HMatrix(pts_d, "matern32", ell, leaf_size=64, eta=1.5, sigma2=sigma2,
+                           symmetric_far=1, **kw)
+            torch.cuda.synchronize()
+            build_s = time.perf_counter() - t0
+            H.hmx_autotune(hm.h, 2)
+            c = torch.zeros_like(y_d)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, it, rres, tres = H.hmx_cg_solve(hm.h, y_d, c, rel_tol=1e-6, max_iter=max_iter,
+                                                raise_on_fail=False)
+            cg_s = time.perf_counter() - t0
+            msg = H.lib().hmx_last_error().decode() if st != H.HMX_OK else ""
+            res_n[form] = {"build_s": build_s, "status": int(st), "iters": it, "rel_res": rres,
+                           "true_rel_res": tres, "cg_s": cg_s,
+                           "ms_per_iter": 1e3 * cg_s / max(it, 1), "message": msg}
+            log("bench: KRR N=%d %s: build %.2f s, CG status %d after %d iterations (%.2f s), "
+                "res %.2e, true res %.2e %s" % (n, form, build_s, st, it, cg_s, rres, tres, msg))
+            hm.close()
+        out["n%d" % n] = res_n
+    H.hmx_trim()
+    return out
+
+
 def batched_problems(torch, lo, hi, nprob=64):
     """nprob problems: N_p = round(2^U(lo, hi)), d_p in {2, 3}, points uniform,
     Gaussian p0 log-uniform in [0.005, 0.05] (seeds 41, 42, 4100 + p)."""
@@ -641,11 +688,12 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the measured FP64 form (no predictor training, no other forms "
                          "or legs): the run the hardware counters are taken on")
-    ap.add_argument("--leg", choices=("multi_rhs", "n22_aca", "aca_n20"), default=None,
+    ap.add_argument("--leg", choices=("multi_rhs", "n22_aca", "aca_n20", "krr_sizes"),
+                    default=None,
                     help="run one leg only and print its JSON (the runs the kernel-time and "
                          "counter summaries are taken on): several right-hand sides on the bench "
-                         "workload, the N = 2^22 builds up to the ACA, or plain FP32 builds up to "
-                         "the ACA on the bench workload")
+                         "workload, the N = 2^22 builds up to the ACA, plain FP32 builds up to "
+                         "the ACA on the bench workload, or the KRR system at N = 2^14 .. 2^18")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -684,6 +732,8 @@ def main():
             res = multi_rhs_leg(torch, H, log, wl, pts_d)
         elif args.leg == "n22_aca":
             res = n22_aca_builds(torch, H, log, full=False)
+        elif args.leg == "krr_sizes":
+            res = krr_sizes_leg(torch, H, log)
         else:
             res = {}
             for rep in range(3):
