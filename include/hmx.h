@@ -412,9 +412,11 @@ hmx_status hmx_graph_destroy(hmx_graph g);
  * launch.  Host-blocking. */
 hmx_status hmx_autotune(hmx_hmatrix h, int32_t reps, void* stream, int32_t* choice,
                         double* times_ms);
-/* Select a row-tile configuration directly (-1: the default, configuration
- * 10, one workgroup per 16-lane row pass of a tile; and the default phase-1
- * lanes too, so a handle returns to its untuned products). */
+/* Select a row-tile configuration directly (-1: the default, one workgroup
+ * per row pass of 128 rows (configuration 10, 11 or 12: 16, 32 or 64 lanes
+ * per row group for 8, 4 or 2 rows per 16-byte vector), narrower when the
+ * handle's largest tile is shorter; and the default phase-1 lanes too, so a
+ * handle returns to its untuned products). */
 hmx_status hmx_set_tile_config(hmx_hmatrix h, int32_t config);
 
 /* Conjugate gradients for (H + sigma2 I) c = b, the kernel ridge regression

@@ -510,7 +510,7 @@ __global__ __launch_bounds__(256) void mm_rowtile_mfma_kernel(
     int64_t ntiles, const int32_t* __restrict__ tile_lo, const int64_t* __restrict__ meta,
     const int64_t* __restrict__ widx, const SU* __restrict__ upool, const SN* __restrict__ npool,
     const T* __restrict__ vec, const int32_t* __restrict__ perm, T alpha, T beta, T sigma2,
-    T* __restrict__ Z, int64_t ldz, int R, int mr) {
+    T* __restrict__ Z, int64_t ldz, int R, int mr, int npass) {
     typedef MfmaOp<T> Op;
     constexpr int RS = 16 * VR;              // rows of a wave's slab
     constexpr int WV = 16 / (int)sizeof(T);  // weights per 16-byte move
@@ -524,11 +524,14 @@ __global__ __launch_bounds__(256) void mm_rowtile_mfma_kernel(
     const int li = lane & 15, lk = lane >> 4;
     const int me = (int)threadIdx.x;
     const bool stager = me < KC;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    // one workgroup per (tile, group of nw slabs), the groups of a tile
+    // consecutive in the grid (workgroups running together read whole columns)
+    for (int64_t w = blockIdx.x; w < ntiles * npass; w += gridDim.x) {
+        const int64_t t = w / npass;
         const int32_t r0 = tile_lo[t];
         const int mt = tile_lo[t + 1] - r0;
         const int ld = mm_ld(mt, R);
-        const int slab0 = (int)blockIdx.y * nw * RS;
+        const int slab0 = (int)(w - t * npass) * nw * RS;
         if (slab0 >= ld) continue;  // the same for the whole workgroup
         const int slab = slab0 + wv * RS;
         const bool active = slab < ld;
@@ -806,17 +809,19 @@ hipError_t launch_mm_rowtile(int M, int64_t ntiles, const int32_t* tile_lo, cons
         if (R % vr) return hipErrorInvalidValue;
         const int ldmax = mm_ld(max_tile, R), rs = 16 * vr;
         const int nw = std::max(1, std::min(4, (ldmax + rs - 1) / rs));
-        const unsigned passes = (unsigned)((ldmax + nw * rs - 1) / (nw * rs));
-        const dim3 grid((unsigned)std::min<int64_t>(ntiles, 1 << 20), passes);
+        const int passes = (ldmax + nw * rs - 1) / (nw * rs);
+        const dim3 grid((unsigned)std::min<int64_t>(ntiles * passes, 1 << 20));
 #define HMX_RTM(SU, SN, T, VR)                                                                   \
     if (M == 8)                                                                                  \
         hipLaunchKernelGGL((mm_rowtile_mfma_kernel<SU, SN, T, 8, VR, HMX_MM_PB>), grid, dim3(64 * nw), 0, st, \
                            ntiles, tile_lo, meta, widx, (const SU*)upool, (const SN*)npool,      \
-                           (const T*)vec, perm, (T)alpha, (T)beta, (T)sigma2, (T*)Z, ldz, R, mr); \
+                           (const T*)vec, perm, (T)alpha, (T)beta, (T)sigma2, (T*)Z, ldz, R, mr, \
+                           passes);                                                              \
     else                                                                                         \
         hipLaunchKernelGGL((mm_rowtile_mfma_kernel<SU, SN, T, 16, VR, HMX_MM_PB>), grid, dim3(64 * nw), 0,   \
                            st, ntiles, tile_lo, meta, widx, (const SU*)upool, (const SN*)npool,  \
-                           (const T*)vec, perm, (T)alpha, (T)beta, (T)sigma2, (T*)Z, ldz, R, mr)
+                           (const T*)vec, perm, (T)alpha, (T)beta, (T)sigma2, (T*)Z, ldz, R, mr, \
+                           passes)
         if (fmode == 0 && nmode == 0) {
             HMX_RTM(double, double, double, 2);
         } else if (fmode == 1 && nmode == 1) {

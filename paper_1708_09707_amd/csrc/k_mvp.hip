@@ -694,7 +694,13 @@ __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
     // the group index is wave-uniform when a group is a whole wave
     const int g = (SUB == 1) ? __builtin_amdgcn_readfirstlane(tid >> 6) : (tid >> 6) * SUB + lane / L;
     const int q = lane % L;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    // split > 0: one workgroup per (tile, row pass), the passes of a tile
+    // consecutive in the grid, so the workgroups running together read whole
+    // columns of a few tiles rather than one pass of every tile
+    const int64_t nwork = split ? ntiles * split : ntiles;
+    for (int64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const int64_t t = split ? w / split : w;
+        const int pass = split ? (int)(w - t * split) : 0;
         const int32_t r0 = tile_lo[t];
         const int mt = tile_lo[t + 1] - r0;
         const int ld = tile_ld(mt, R);
@@ -702,8 +708,8 @@ __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
         const int64_t ku = meta[4 * t + 5] - meta[4 * t + 1];  // factor columns of the tile
         const SU* __restrict__ ubase = upool + meta[4 * t + 2];
         const SN* __restrict__ nbase = NR ? npool : npool + meta[4 * t + 3];
-        // split: this workgroup's row pass only (blockIdx.y), else all of them
-        for (int rb = split ? (int)blockIdx.y * RPG : 0; rb < ld; rb += split ? ld : RPG) {
+        // split: this workgroup's row pass only, else all of them
+        for (int rb = split ? pass * RPG : 0; rb < ld; rb += split ? ld : RPG) {
             const int nvec = ((ld - rb) < RPG ? (ld - rb) : RPG) / R;  // lane units in this pass
             T acc[RV][R];
 #pragma unroll
@@ -755,13 +761,17 @@ hipError_t rowtile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_
     constexpr int R = VU > VN ? VU : VN;
     int shape, mode = 0;
     if (config < 0) {
-        // default: one workgroup per 16-lane row pass of a tile (configuration
-        // 10).  Timed on the N = 2^20 workload (256-point tiles) it is the
-        // fastest or within 1.5% of the fastest of all 15 configurations in
-        // FP64, FP32 and BF16, while the shapes with two or four row vectors
-        // per lane take 3.5x as long in FP64; on tiles of at most 16 R rows it
-        // is the one-workgroup-per-tile grid
-        shape = 0;
+        // default: one workgroup per row pass of 128 rows (L = 128 / R lanes
+        // per row group, one row vector per lane: 64 lanes in FP64, 32 in
+        // FP32, 16 in BF16), narrower when the largest tile is shorter.
+        // Timed on the N = 2^20 workload (256-point tiles) this is the
+        // fastest of the 15 configurations in each of FP64, FP32 and BF16
+        // (configurations 12, 11 and 10), while the shapes with two or four
+        // row vectors per lane take 3.5x as long in FP64
+        const int need = (max_tile + R - 1) / R;  // lane units per tile column
+        int L = 16;
+        while (L < need && L * R < 128 && L < 64) L *= 2;
+        shape = L == 16 ? 0 : (L == 32 ? 1 : 2);
         mode = 2;
     } else {
         shape = config % kRowtileShapes;
@@ -773,9 +783,8 @@ hipError_t rowtile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_
     const unsigned passes =
         mode == 2 ? (unsigned)((tile_ld(max_tile, R) + rpg - 1) / rpg) : 1u;
     const dim3 grid(mode == 1 ? (unsigned)(ntiles < kPersistentGrid ? ntiles : kPersistentGrid)
-                              : grid_cap(ntiles, 1 << 20),
-                    passes);
-    const int split = mode == 2 ? 1 : 0;
+                              : grid_cap(mode == 2 ? ntiles * passes : ntiles, 1 << 20));
+    const int split = mode == 2 ? (int)passes : 0;
 #define HMX_RT(LL, RR)                                                                       \
     hipLaunchKernelGGL((rowtile_kernel<SU, SN, T, LL, RR>), grid, dim3(kTileThreads), 0, st,  \
                        ntiles, tile_lo, meta, widx, (const SU*)upool, (const SN*)npool,      \
