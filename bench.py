@@ -86,18 +86,25 @@ def rowtile_bytes(st, esz=4) -> float:
             + st.sum_rank * esz + st.n * (esz + 4))
 
 
-def measured_traffic(workload: str, form: str):
-    """HBM bytes per row-tile launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source and this form."""
+# row-tile shapes (lanes per row group, row vectors per lane) of configurations
+# c = mode * 5 + shape
+ROWTILE_SHAPES = ((16, 1), (32, 1), (64, 1), (64, 2), (64, 4))
+
+
+def measured_traffic(workload: str, form: str, config: int):
+    """HBM bytes per row-tile launch of the chosen configuration's kernel
+    shape, from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel source and this form."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
     if (rec.get("kernel_source") != kernel_source_hash() or rec.get("workload") != workload
-            or rec.get("form") != form):
+            or rec.get("form") != form or config is None or config < 0):
         return None
-    return rec.get("bytes_per_launch")
+    L, RV = ROWTILE_SHAPES[config % len(ROWTILE_SHAPES)]
+    return rec.get("bytes_per_launch_by_shape", {}).get("%d,%d" % (L, RV))
 
 
 # ACA tolerances tried for the plain form at equal error (errors grow with
@@ -927,7 +934,7 @@ def main():
     pe["aca_eps"] = eq_eps
 
     rt_gbs = pd["rowtile_bytes"] / (pd["rowtile_ms"] * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, "plain_f64")
+    traffic = measured_traffic(args.workload, "plain_f64", pd["tile_config"])
     out = {
         "metric": METRIC, "value": pd["matvec_gbs"], "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": pd["step_ms"],

@@ -42,8 +42,7 @@ struct Fail {
 // pools); returning them to the driver and mapping them anew each time costs
 // seconds on a busy device, so released blocks are kept per device and
 // reused best-fit (a block is reused for requests of 3/4 of its size or
-// more).  A failed device allocation releases cached blocks one at a time
-// (the smallest that covers the shortfall) until it succeeds.
+// more).  A failed device allocation flushes the cache and retries once.
 // Blocks enter the cache only after the work using them has completed (the
 // build synchronises its stream before releasing scratch, destroy
 // synchronises the device).
@@ -84,34 +83,16 @@ hipError_t cache_alloc(void** p, size_t* bytes) {
     }
     hipError_t e = hipMalloc(p, *bytes);
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
-        // release cached blocks of this device one at a time until the
-        // request fits: the rest stay for the requests after it
-        // (flushing every block would hand the whole next build to the
-        // driver, which clears recycled memory at about 35 GB/s)
         (void)hipGetLastError();
         std::lock_guard<std::mutex> lk(c.mu);
         (void)hipDeviceSynchronize();
-        while (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
-            (void)hipGetLastError();
-            // the smallest block of this device that covers the shortfall
-            // (with 256 MiB to spare), else the largest
-            size_t fr = 0, tot = 0;
-            (void)hipMemGetInfo(&fr, &tot);
-            const size_t need = *bytes > fr ? *bytes - fr + ((size_t)256 << 20) : 0;
-            auto it = c.blocks.end(), big = c.blocks.end();
-            for (auto jt = c.blocks.begin(); jt != c.blocks.end(); ++jt) {
-                if (jt->second.first != dev) continue;
-                big = jt;
-                if (it == c.blocks.end() && jt->first >= need) it = jt;
-            }
-            if (it == c.blocks.end()) it = big;
-            if (it == c.blocks.end()) break;
-            c.owned.erase(it->second.second);
-            (void)hipFree(it->second.second);
-            c.cached -= it->first;
-            c.blocks.erase(it);
-            e = hipMalloc(p, *bytes);
+        for (auto& b : c.blocks) {
+            c.owned.erase(b.second.second);
+            (void)hipFree(b.second.second);
         }
+        c.blocks.clear();
+        c.cached = 0;
+        e = hipMalloc(p, *bytes);
     }
     if (e == hipSuccess) {
         std::lock_guard<std::mutex> lk(c.mu);
