@@ -226,6 +226,7 @@ def n22_aca_builds(torch, H, log, full=True, one_shot=False):
         res["one_shot_sum_rank_ratio"] = (float(np.sum(ranks["learned_one_shot"]))
                                           / max(float(np.sum(ranks["plain"])), 1.0))
     H.hmx_trim()
+    torch.cuda.empty_cache()
     if full:
         res["learned_mixed_full"] = n22_full_path(torch, H, log, wl, pts_d, p0, mlp)
     mlp.close()
@@ -241,7 +242,7 @@ def n22_full_path(torch, H, log, wl, pts_d, p0, mlp, eps=3e-3, M=10, nrows=1024)
     n = wl["n"]
     kw = dict(compute_dtype="f32", storage_dtype="bf16", leaf_size=wl["leaf"], eta=wl["eta"],
               aca_eps=eps, max_rank=wl["kmax"], rank_mode="learned", mlp=mlp, symmetric_far=1)
-    times = []
+    times, fresh = [], []
     for rep in range(2):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -249,6 +250,7 @@ def n22_full_path(torch, H, log, wl, pts_d, p0, mlp, eps=3e-3, M=10, nrows=1024)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         st = hm.stats()
+        fresh.append(st.alloc_fresh_bytes)
         if rep == 0:
             hm.close()
     stream = torch.cuda.current_stream()
@@ -275,6 +277,7 @@ def n22_full_path(torch, H, log, wl, pts_d, p0, mlp, eps=3e-3, M=10, nrows=1024)
     err = (torch.linalg.norm(z.double()[rows_d] - ref) / torch.linalg.norm(ref)).item()
     fb = (st.u_entries + st.v_entries) * st.entry_bytes
     out = {"eps": eps, "build_s_each": times, "build_s": min(times),
+           "build_fresh_bytes_each": fresh,
            "matvec_bytes": st.matvec_bytes, "matvec_gbs": st.matvec_bytes / (mv_ms * 1e-3) / 1e9,
            "build_phase_ms": list(st.phase_ms), "sum_rank": st.sum_rank,
            "factor_entries": st.factor_entries, "near_entries": st.near_entries,
@@ -977,7 +980,10 @@ def main():
         H.hmx_trim()
         out["batched_64"] = batched_leg(torch, H, log)
     if not args.no_n22:
+        # the N = 2^22 builds use nearly the whole device: return the library's
+        # cached blocks and torch's reserve from the earlier legs to the driver
         H.hmx_trim()
+        torch.cuda.empty_cache()
         out["n22_build"] = n22_aca_builds(torch, H, log)
     if args.krr:
         H.hmx_trim()

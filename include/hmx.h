@@ -259,6 +259,12 @@ typedef struct {
                                  and the norm recursion's inner products) */
     int64_t rows, cols;       /* the matrix's shape: n x n, or n1 x n2 for
                                  hmx_build_rect */
+    int64_t alloc_fresh_bytes; /* device bytes the build obtained from the
+                                  driver instead of the library's block cache
+                                  (memory the process released before is
+                                  cleared by the driver on allocation) */
+    int64_t alloc_flushes;    /* cache flushes during the build (an allocation
+                                 failed and every cached block was freed) */
 } hmx_stats;
 
 /* Fill *p with the defaults: leaf 256, eta 1.5, eps 1e-5, aca_eta 0,

@@ -3,6 +3,7 @@
 // sizes buffers, launches, and reads back the few counters that size the
 // next step (one per block-tree level, as in Algorithm 4, and one per pool).
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -59,6 +60,11 @@ DeviceCache& cache() {
     return *c;
 }
 
+// bytes the library obtained from the driver (cache misses) and cache
+// flushes, over the process: a handle's stats report their growth during
+// its build
+std::atomic<int64_t> g_fresh_bytes{0}, g_flushes{0};
+
 size_t cache_round(size_t bytes) {
     const size_t g = bytes >= ((size_t)64 << 20) ? ((size_t)2 << 20) : 256;
     return (bytes + g - 1) / g * g;
@@ -92,11 +98,13 @@ hipError_t cache_alloc(void** p, size_t* bytes) {
         }
         c.blocks.clear();
         c.cached = 0;
+        g_flushes.fetch_add(1);
         e = hipMalloc(p, *bytes);
     }
     if (e == hipSuccess) {
         std::lock_guard<std::mutex> lk(c.mu);
         c.owned.insert(*p);
+        g_fresh_bytes.fetch_add((int64_t)*bytes);
     }
     return e;
 }
@@ -368,6 +376,8 @@ struct hmx_hmatrix_s {
     DevBuf partner, vpieces, vtpool, vt_meta, p1rec, pfc, partial;
     int far_np = 0;  // factors recomputed by every matvec
     NpPlan np;
+    // the process-wide allocation counters when the handle was created
+    int64_t fresh0 = g_fresh_bytes.load(), flush0 = g_flushes.load();
     // rectangular A(Y1 x Y2): the union holds Y1 (rows, [0, nrows)) then Y2
     // (columns, [col0, col0 + ncols)); the row tiles are Y1's leaf clusters,
     // the first ntiles_rows tiles.  Square handles: rows = columns = [0, n).
@@ -424,6 +434,8 @@ void finish_stats(hmx_hmatrix_s* h, std::chrono::steady_clock::time_point t_all)
     S.tile_config = h->rt_config;
     S.rows = h->nrows;
     S.cols = h->ncols;
+    S.alloc_fresh_bytes = g_fresh_bytes.load() - h->fresh0;
+    S.alloc_flushes = g_flushes.load() - h->flush0;
     S.phase_ms[7] = ms_since(t_all);
     // algorithmic bytes of one matvec with beta = 0: the near field once,
     // U_b and V_b of every admissible leaf once (with the symmetric far

@@ -79,7 +79,8 @@ class hmx_stats(C.Structure):
                 ("aca_fallback", C.c_int64), ("aca_capacity", C.c_int64),
                 ("predict_ms", C.c_double), ("aca_overflow", C.c_int64),
                 ("aca_kernel_evals", C.c_int64), ("aca_flops", C.c_double),
-                ("rows", C.c_int64), ("cols", C.c_int64)]
+                ("rows", C.c_int64), ("cols", C.c_int64),
+                ("alloc_fresh_bytes", C.c_int64), ("alloc_flushes", C.c_int64)]
 
 
 class HmxError(RuntimeError):
