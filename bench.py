@@ -253,6 +253,9 @@ def n22_full_path(torch, H, log, wl, pts_d, p0, mlp, eps=3e-3, M=10, nrows=1024)
         fresh.append(st.alloc_fresh_bytes)
         if rep == 0:
             hm.close()
+    # the first build's blocks the second did not take (its ACA scratch peak)
+    # go back to the driver, so torch has room for the reference rows
+    H.hmx_trim()
     stream = torch.cuda.current_stream()
     H.hmx_autotune(hm.h, 2, stream)
     x = torch.from_numpy(synth.normal_vector(n, 5400, dtype=np.float32)).cuda()
