@@ -436,8 +436,9 @@ hmx_status hmx_set_tile_config(hmx_hmatrix h, int32_t config);
  *   iters, rel_res (recurrence), true_rel_res (|b - (H + sigma2 I) x| / |b|,
  *   one extra product at the end): host, optional.
  * Returns HMX_ERR_NOT_CONVERGED when rel_tol was not reached (x holds the
- * last iterate).  Host-blocking (one readback per iteration); allocates
- * three work vectors. */
+ * last iterate; on breakdown the step that broke down is not taken, so x is
+ * the iterate before it, while iters counts that step too).  Host-blocking
+ * (one readback per iteration); allocates three work vectors. */
 hmx_status hmx_cg_solve(hmx_hmatrix h, const void* b, void* x, double rel_tol, int32_t max_iter,
                         void* stream, int32_t* iters, double* rel_res, double* true_rel_res);
 

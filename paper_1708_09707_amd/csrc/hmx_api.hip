@@ -2451,7 +2451,7 @@ hmx_status cg_run(hmx_hmatrix_s* h, const void* b, void* x, double rel_tol, int3
         ++it;
         if (!(two[0] > 0.0)) {
             set_err("CG breakdown at iteration %d: p.Ap = %g", it, two[0]);
-            break;  // x holds a damaged last update; report not converged
+            break;  // the step was not taken: x is the last iterate; not converged
         }
         rr = two[1];
         res = sqrt(rr / bb);

@@ -59,7 +59,11 @@ __global__ __launch_bounds__(kDotThreads) void cg_update_kernel(T* __restrict__ 
                                                                 int64_t n,
                                                                 double* __restrict__ partial) {
     __shared__ double sh[kDotThreads / 64];
-    const T alpha = (T)(scal[0] / scal[1]);  // (r.r) / (p.q)
+    // (r.r) / (p.q); a step with p.q <= 0 (the operator is not positive
+    // definite on p: CG breaks down) is not taken, so x and r keep the last
+    // iterate's values
+    const double pq = scal[1];
+    const T alpha = pq > 0.0 ? (T)(scal[0] / pq) : (T)0;
     double acc = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)kDotThreads + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kDotThreads) {

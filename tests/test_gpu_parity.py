@@ -510,3 +510,36 @@ def test_cg_edge_cases(H):
     s, it, res, tres = H.hmx_cg_solve(hm.h, torch.zeros_like(y), c, rel_tol=1e-8)
     assert s == H.HMX_OK and it == 0 and not c.abs().max().item()
     hm.close()
+
+
+def test_cg_breakdown_keeps_last_iterate(H):
+    """The KRR system with BF16 factors and near field (Matern-3/2 l = 0.1,
+    sigma2 = 1e-2, N = 2^14 Gaussian-mixture points) is not positive definite
+    to working precision, so CG breaks down on p.Ap <= 0.  The step that broke
+    down is not taken: the returned x equals, bit for bit, the x of a solve
+    stopped one iteration earlier, and the reported true residual is that of
+    the returned x."""
+    n = 1 << 14
+    pts = synth.gmm_points(n, 3, 31)
+    y = synth.krr_target(pts, 32)
+    hm = H.HMatrix(_dev(pts).float(), "matern32", 0.1, compute_dtype="f32", storage_dtype="bf16",
+                   leaf_size=64, eta=1.5, aca_eps=1e-4, max_rank=64, sigma2=1e-2,
+                   symmetric_far=1)
+    b = _dev(y).float()
+    x = torch.zeros_like(b)
+    s, it, res, tres = H.hmx_cg_solve(hm.h, b, x, rel_tol=1e-6, max_iter=2000, raise_on_fail=False)
+    msg = H.lib().hmx_last_error().decode()
+    print("bf16 KRR CG: status %d after %d iterations, res %.3e, true %.3e (%s)"
+          % (s, it, res, tres, msg))
+    assert s == H.HMX_ERR_NOT_CONVERGED and "breakdown" in msg and 1 < it < 2000
+    assert bool(torch.isfinite(x).all())
+    x_prev = torch.zeros_like(b)
+    s2, it2, _, _ = H.hmx_cg_solve(hm.h, b, x_prev, rel_tol=1e-6, max_iter=it - 1,
+                                   raise_on_fail=False)
+    assert s2 == H.HMX_ERR_NOT_CONVERGED and it2 == it - 1
+    assert torch.equal(x, x_prev)
+    z = torch.empty_like(b)
+    H.hmx_matvec(hm.h, x, z)
+    t = (torch.linalg.norm((b - z).double()) / torch.linalg.norm(b.double())).item()
+    assert abs(t - tres) <= 1e-6 * max(1.0, t)
+    hm.close()
