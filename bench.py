@@ -238,7 +238,10 @@ def n22_full_path(torch, H, log, wl, pts_d, p0, mlp, eps=3e-3, M=10, nrows=1024)
     """The whole path at N = 2^22 in 3-d for the learned / mixed-precision
     form: learned sizing, BF16 factors and near field, the symmetric far
     field (each factor pair stored once).  Build time, matvec time and bytes,
-    and the product's error on sampled rows against an FP64 dense product."""
+    and the product's error on sampled rows against an FP64 dense product.
+    (The plain FP32 form at this tolerance does not fit one GPU, even with its
+    near field evaluated in the product: its 153 GB of factors are held twice
+    while the build lays them out tile-major.)"""
     n = wl["n"]
     kw = dict(compute_dtype="f32", storage_dtype="bf16", leaf_size=wl["leaf"], eta=wl["eta"],
               aca_eps=eps, max_rank=wl["kmax"], rank_mode="learned", mlp=mlp, symmetric_far=1)
@@ -711,12 +714,13 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="only the measured FP64 form (no predictor training, no other forms "
                          "or legs): the run the hardware counters are taken on")
-    ap.add_argument("--leg", choices=("multi_rhs", "n22_aca", "aca_n20", "krr_sizes"),
+    ap.add_argument("--leg", choices=("multi_rhs", "n22_aca", "n22_full", "aca_n20", "krr_sizes"),
                     default=None,
                     help="run one leg only and print its JSON (the runs the kernel-time and "
                          "counter summaries are taken on): several right-hand sides on the bench "
                          "workload, the N = 2^22 builds up to the ACA (with the one-shot learned "
-                         "form), plain FP32 builds up to "
+                         "form), the N = 2^22 builds with the full learned/mixed and plain paths, "
+                         "plain FP32 builds up to "
                          "the ACA on the bench workload, or the KRR system at N = 2^14 .. 2^18")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (counter calibration)")
@@ -756,6 +760,8 @@ def main():
             res = multi_rhs_leg(torch, H, log, wl, pts_d)
         elif args.leg == "n22_aca":
             res = n22_aca_builds(torch, H, log, full=False, one_shot=True)
+        elif args.leg == "n22_full":
+            res = n22_aca_builds(torch, H, log, full=True)
         elif args.leg == "krr_sizes":
             res = krr_sizes_leg(torch, H, log)
         else:
