@@ -769,9 +769,10 @@ hipError_t rowtile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_
         // per row group, one row vector per lane: 64 lanes in FP64, 32 in
         // FP32, 16 in BF16), narrower when the largest tile is shorter.
         // Timed on the N = 2^20 workload (256-point tiles) this is the
-        // fastest of the 15 configurations in each of FP64, FP32 and BF16
-        // (configurations 12, 11 and 10), while the shapes with two or four
-        // row vectors per lane take 3.5x as long in FP64
+        // fastest of the 15 configurations in FP32 and BF16 (configurations
+        // 11 and 10) and within 1% of the fastest in FP64 (configuration 12
+        // against 32-lane 64-row passes); the shapes with two or four row
+        // vectors per lane take 4-10% longer in FP64 and FP32, 40% in BF16
         const int need = (max_tile + R - 1) / R;  // lane units per tile column
         int L = 16;
         while (L < need && L * R < 128 && L < 64) L *= 2;
