@@ -7,6 +7,11 @@
   gives the default configuration's product within FP32 summation-order
   rounding, and the product meets e_rel <= 10 eps + 4 u_BF16 against the
   oracle's FP64 dense product on 4096 sampled rows.
+* The same points in the plain FP64 form (adaptive ACA eps 1e-5, k_max 64,
+  stored near field and factors): the default and every row-tile
+  configuration agree with the oracle's stored-mode H-matrix product on
+  three Morton row ranges to FP64 summation-order rounding, and the default
+  meets e_rel <= 10 eps against the FP64 dense product on 4096 sampled rows.
 * N = 2^22 uniform points in [0,1]^3, leaf 64, eta 1.5: Morton codes,
   permutation and both leaf lists bit for bit against the oracle.
 """
@@ -81,6 +86,45 @@ def test_bench_config_every_tile_config(H, orc, n1m, n1m_ref, near):
         assert err <= tol, (c, err)
     hm.close()
     mlp.close()
+
+
+def test_plain_fp64_every_tile_config_vs_oracle_hmatrix(H, orc, n1m, n1m_ref):
+    """The FP64 product of the plain method (Alg. 3 over the stored blocks)
+    in every row-tile configuration against the oracle's H-matrix product
+    built from the same partition and ACA in FP64: the first rows, a range in
+    the middle that starts and ends inside leaves, and the last rows.  The two
+    sum the same terms in different orders, so they agree to FP64 rounding
+    (the ACA pivots are the same decisions on both sides for this input)."""
+    n, pts, x = n1m
+    rows, zd = n1m_ref
+    x64 = x.astype(np.float64)
+    p64 = pts.astype(np.float64)
+    print("build: N=%d plain FP64, eps 1e-5, leaf 256" % n, flush=True)
+    hm = H.HMatrix(_dev(pts), "gaussian", 0.01, compute_dtype="f64", storage_dtype="f64",
+                   near_dtype="f64", rank_mode="adaptive", leaf_size=256, eta=1.5,
+                   aca_eps=1e-5, max_rank=64)
+    perm_gpu = hm.partition()["perm"]
+    refs = []
+    for lo, hi in ((0, 1024), (n // 2 - 300, n // 2 + 700), (n - 1024, n)):
+        print("oracle: H-matrix product on Morton rows [%d, %d)" % (lo, hi), flush=True)
+        zr, perm, _ = orc.hmvp_rows(p64, x64, "gaussian", 0.01, 256, 1.5, 64, 1e-5, lo, hi,
+                                    eps0=1e-14)
+        assert np.array_equal(perm, perm_gpu)
+        refs.append((lo, hi, zr))
+    xd = _dev(x64)
+    for c in [-1] + list(range(H.HMX_TILE_CONFIGS)):
+        H.hmx_set_tile_config(hm.h, c)
+        z = hm.matvec(xd).cpu().numpy()
+        errs = [np.linalg.norm(z[perm_gpu[lo:hi]] - zr) / np.linalg.norm(zr)
+                for lo, hi, zr in refs]
+        print("config %2d: vs oracle H-matrix rows %s" % (c, " ".join("%.2e" % e for e in errs)),
+              flush=True)
+        assert max(errs) <= 1e-12, (c, errs)
+        if c == -1:
+            err = np.linalg.norm(z[rows] - zd) / np.linalg.norm(zd)
+            print("default: vs oracle dense rows %.3e" % err, flush=True)
+            assert err <= 10 * 1e-5, err
+    hm.close()
 
 
 def test_partition_bit_exact_n4m_3d(H, orc):
