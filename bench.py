@@ -88,7 +88,7 @@ def rowtile_bytes(st, esz=4) -> float:
 
 # row-tile shapes (lanes per row group, row vectors per lane) of configurations
 # c = mode * 5 + shape
-ROWTILE_SHAPES = ((16, 1), (32, 1), (64, 1), (64, 2), (64, 4))
+ROWTILE_SHAPES = ((16, 1), (32, 1), (64, 1), (64, 2), (64, 4), (8, 1))
 
 
 def measured_traffic(workload: str, form: str, config: int):
@@ -103,7 +103,7 @@ def measured_traffic(workload: str, form: str, config: int):
     if (rec.get("kernel_source") != kernel_source_hash() or rec.get("workload") != workload
             or rec.get("form") != form or config is None or config < 0):
         return None
-    L, RV = ROWTILE_SHAPES[config % len(ROWTILE_SHAPES)]
+    L, RV = ROWTILE_SHAPES[config % 5 if config < 15 else 5]
     return rec.get("bytes_per_launch_by_shape", {}).get("%d,%d" % (L, RV))
 
 

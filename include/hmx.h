@@ -399,14 +399,16 @@ hmx_status hmx_graph_launch(hmx_graph g, void* stream);
 hmx_status hmx_graph_destroy(hmx_graph g);
 
 /* ---- autotuner of the matvec's row-tile kernel ---- */
-/* Row-tile configurations: shape c % 5 of (lanes per row group, row vectors
- * per lane) = (16,1), (32,1), (64,1), (64,2), (64,4); grid c / 5: 0 one
+/* Row-tile configurations: for c < 15 shape c % 5 of (lanes per row group,
+ * row vectors per lane) = (16,1), (32,1), (64,1), (64,2), (64,4) and grid
+ * c / 5; c = 15, 16, 17: the shape (8,1), for tiles of at most 8 row vectors
+ * (16 rows in FP64, 32 in FP32, 64 in BF16), with grid c - 15.  Grids: 0 one
  * workgroup per tile, 1 a persistent grid of 2048 workgroups looping over the
  * tiles, 2 one workgroup per row pass of a tile (shapes whose pass covers
  * fewer rows than a tile split each tile's rows over several workgroups).
  * Configurations sum in different orders, so results may differ in the last
  * bits. */
-#define HMX_TILE_CONFIGS 15
+#define HMX_TILE_CONFIGS 18
 
 /* Time every configuration on this handle (reps row-tile launches each, HIP
  * events on `stream`, on scratch vectors it allocates) and keep the fastest

@@ -445,10 +445,11 @@ hipError_t launch_aca_work(const int4* blocks, const int32_t* rank, const int32_
                            int64_t nb, unsigned long long* out, hipStream_t st);
 hipError_t launch_int_stats(const int32_t* a, int64_t n, unsigned long long* out,
                             hipStream_t st);
-// config < 0: default tile shape; else shape config % kRowtileShapes, grid
-// config / kRowtileShapes: one workgroup per tile, a persistent grid of
+// config < 0: default tile shape; config < 15: shape config % 5 of the first
+// five, grid config / 5; config 15-17: shape 5 (8 lanes per row group), grid
+// config - 15.  Grids: one workgroup per tile, a persistent grid of
 // kPersistentGrid workgroups, or one workgroup per (tile, row pass)
-constexpr int kRowtileShapes = 5;
+constexpr int kRowtileShapes = 6;
 constexpr int kRowtileConfigs = 3 * kRowtileShapes;
 constexpr unsigned kPersistentGrid = 2048;
 // nmode 3: near field recomputed from soa (compute type, d x n) with kern

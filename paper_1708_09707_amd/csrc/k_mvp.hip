@@ -752,8 +752,10 @@ __global__ __launch_bounds__(kTileThreads) void rowtile_kernel(
 }
 
 // tile shapes of the row-tile kernel, (lanes per row group L, row vectors per
-// lane RV) = (16, 1), (32, 1), (64, 1), (64, 2), (64, 4); the grid is one
-// workgroup per tile or a fixed persistent grid looping over the tiles
+// lane RV) = (16, 1), (32, 1), (64, 1), (64, 2), (64, 4), (8, 1) (the last for
+// tiles of at most 8 row vectors, whose columns would leave lanes of wider
+// groups without rows); the grid is one workgroup per tile, a fixed
+// persistent grid looping over the tiles, or one workgroup per row pass
 
 template <typename SU, typename SN, typename T>
 hipError_t rowtile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_t* meta,
@@ -778,12 +780,15 @@ hipError_t rowtile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_
         while (L < need && L * R < 128 && L < 64) L *= 2;
         shape = L == 16 ? 0 : (L == 32 ? 1 : 2);
         mode = 2;
-    } else {
-        shape = config % kRowtileShapes;
-        mode = config / kRowtileShapes;
+    } else if (config < 15) {
+        shape = config % 5;
+        mode = config / 5;
+    } else {  // the 8-lane shape, for tiles of at most 8 row vectors
+        shape = 5;
+        mode = config - 15;
     }
-    static constexpr int kL[kRowtileShapes] = {16, 32, 64, 64, 64};
-    static constexpr int kRV[kRowtileShapes] = {1, 1, 1, 2, 4};
+    static constexpr int kL[kRowtileShapes] = {16, 32, 64, 64, 64, 8};
+    static constexpr int kRV[kRowtileShapes] = {1, 1, 1, 2, 4, 1};
     const int rpg = kL[shape] * kRV[shape] * R;  // rows per pass
     const unsigned passes =
         mode == 2 ? (unsigned)((tile_ld(max_tile, R) + rpg - 1) / rpg) : 1u;
@@ -800,7 +805,8 @@ hipError_t rowtile_dispatch(int64_t ntiles, const int32_t* tile_lo, const int64_
         case 1: HMX_RT(32, 1); break;
         case 2: HMX_RT(64, 1); break;
         case 3: HMX_RT(64, 2); break;
-        default: HMX_RT(64, 4); break;
+        case 4: HMX_RT(64, 4); break;
+        default: HMX_RT(8, 1); break;
     }
 #undef HMX_RT
     return hipGetLastError();

@@ -40,7 +40,7 @@ EXPORTS = ["hmx_params_default", "hmx_build", "hmx_matvec", "hmx_cg_solve", "hmx
            "hmx_rank_predict", "hmx_cg_solve_noalloc", "hmx_matvec_batched", "hmx_mlp_save",
            "hmx_mlp_load", "hmx_build_rect", "hmx_matmat"]
 HMX_CG_NOALLOC_MAX_BYTES = 50397184
-HMX_TILE_CONFIGS = 15
+HMX_TILE_CONFIGS = 18
 
 
 class hmx_kernel(C.Structure):
